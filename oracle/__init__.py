@@ -1,0 +1,21 @@
+"""FP64 CPU oracle for the overlapping-PML source-transfer FDFD solver.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and the
+benchmark's cpu_baseline leg may import it; the HIP library and its Python
+binding never do.  Written from the paper (arXiv 2509.20801) in plain
+NumPy/SciPy complex128; it shares no code with the GPU path.
+
+Parity status of each function (pins live in tests/test_oracle_*.py):
+  fdfd.axis_stretch / assemble   pinned: closed-form eigenpairs, reciprocity,
+                                 1D discrete Green's function, Mie series
+  fdfd.solve_direct / solve_dense pinned: against each other and residuals
+  ddm.partition / local_matrix / SourceTransfer   pinned: N=1 gives A^-1,
+                                 residual-support invariant, convergence of
+                                 the stationary iteration to the direct solve
+  krylov.fgmres                  pinned: identity preconditioner vs SciPy's
+                                 GMRES, Arnoldi relation, exact preconditioner
+                                 converges in one step
+  mie                            pinned: Jacobi-Anger series of the incident
+                                 wave, boundary continuity, eps = 1 gives zero
+"""
+from . import fdfd, ddm, krylov, mie  # noqa: F401

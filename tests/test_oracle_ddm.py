@@ -1,0 +1,117 @@
+"""Pins for the oracle's overlapping decomposition and source-transfer round
+(Sec. 2.3, Eqs. (14)-(21), Algorithm 1).  CPU only."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import ddm, fdfd, krylov
+
+
+def _setup(w):
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    return p, A
+
+
+def test_partition_covers_grid_once():
+    w = workloads.configs.metasurface_sheet(interior=256, pml=20, parts=4, n_pillars=8, slot=32,
+                                            substrate_rows=64, source_row=32)
+    subs = ddm.partition(w.params())
+    own = np.zeros((w.ny, w.nx), int)
+    for s in subs:
+        own[s.iy[0]:s.iy[1], s.ix[0]:s.ix[1]] += 1
+        e = 24
+        assert s.ox[0] == (s.ix[0] - e if s.kx > 0 else 0)
+        assert s.oy[1] == (s.iy[1] + e if s.ky < 3 else w.ny)
+    assert np.all(own == 1)
+    # Interior blocks of 64 cells; the edge blocks carry the 20-cell PML.
+    assert [s.ix for s in subs[:4]] == [(0, 84), (84, 148), (148, 212), (212, 296)]
+
+
+def test_config_local_shapes():
+    """The 8x8 split of a 1024 interior with a 20-cell PML gives local sides
+    of 172 (edge) and 176 (interior); the 2x2 split of the 100 interior with a
+    16-cell PML gives 90."""
+    p = workloads.configs.metasurface_sheet.__defaults__  # noqa: F841 (documentation)
+    params = dict(nx=1064, ny=1064, pml=(20,) * 4, px=8, py=8, overlap=8, local_pml=16)
+    sides = sorted({s.ox[1] - s.ox[0] for s in ddm.partition(params)})
+    assert sides == [172, 176]
+    params = dict(nx=132, ny=132, pml=(16,) * 4, px=2, py=2, overlap=8, local_pml=16)
+    assert {s.ox[1] - s.ox[0] for s in ddm.partition(params)} == {90}
+
+
+def test_local_stretch_follows_global_away_from_local_pml():
+    w = workloads.configs.small_random(nx=60, ny=50, pml=6, px=3, py=2, overlap=3, local_pml=5)
+    p = w.params()
+    sx, sxh, sy, syh = fdfd.global_axes(p)
+    for s in ddm.partition(p):
+        ls, lsh = ddm.local_axis(sx, sxh, s.ox, s.ix, s.ox[0] < s.ix[0], s.ox[1] > s.ix[1],
+                                 3, 5, 3, 1e-8, p["k0"], 1.0)
+        a = s.ox[0]
+        # I_k plus the physical overlap keep the global values exactly.
+        lo = s.ix[0] - (3 if s.ox[0] < s.ix[0] else 0)
+        hi = s.ix[1] + (3 if s.ox[1] > s.ix[1] else 0)
+        assert np.array_equal(ls[lo - a:hi - a], sx[lo:hi])
+        assert np.array_equal(lsh[lo - a:hi - a + 1], sxh[lo:hi + 1])
+        # The local PML has the same profile as a global PML of the same depth.
+        if s.ox[1] > s.ix[1]:
+            gs, gsh = fdfd.axis_stretch(5 + 5, 0, 5, 3, 1e-8, p["k0"], 1.0)
+            assert np.allclose(ls[-5:], gs[-5:]) and np.allclose(lsh[-6:], gsh[-6:])
+
+
+def test_single_subdomain_round_is_exact_inverse():
+    """N = 1: Omega_1 is the whole grid, so one round is A^{-1} b."""
+    w = workloads.configs.small_random(nx=40, ny=36, pml=6, px=1, py=1)
+    p, A = _setup(w)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    assert fdfd.relres(A, B.apply(b), b) < 1e-13
+
+
+@pytest.mark.parametrize("px,py", [(2, 2), (3, 2)])
+def test_residual_vanishes_away_from_transfer_bands(px, py):
+    """After the initial local solves (Eq. (14)) summed by Eq. (21), the global
+    residual on I_k is exactly the source transferred from neighbours, so it is
+    zero at every node whose stencil does not touch a neighbour's Omega_i."""
+    w = workloads.configs.small_random(nx=70, ny=64, pml=6, px=px, py=py, overlap=3, local_pml=6)
+    p, A = _setup(w)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    r = (b - A @ B.apply(b)).reshape(w.ny, w.nx)
+    touched = np.zeros((w.ny, w.nx), bool)
+    for s in B.subs:
+        cover = np.zeros((w.ny, w.nx), bool)
+        cover[s.oy[0]:s.oy[1], s.ox[0]:s.ox[1]] = True
+        grow = cover.copy()
+        grow[1:, :] |= cover[:-1, :]; grow[:-1, :] |= cover[1:, :]
+        grow[:, 1:] |= cover[:, :-1]; grow[:, :-1] |= cover[:, 1:]
+        own = np.zeros_like(cover)
+        own[s.iy[0]:s.iy[1], s.ix[0]:s.ix[1]] = True
+        # Nodes outside I_s whose stencil meets Omega_s receive s's field.
+        touched |= grow & ~own
+    scale = np.abs(b).max()
+    assert np.abs(r[~touched]).max() < 1e-12 * scale
+    assert np.abs(r[touched]).max() > 1e-6 * scale
+
+
+def test_stationary_algorithm1_converges_to_direct():
+    """Algorithm 1 (Jacobi rounds) converges to the full-domain solution (Fig. 5b)."""
+    w = workloads.configs.cylinder_tfsf()
+    p, A = _setup(w)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    x, hist = ddm.stationary(A, B, b, 14)
+    assert hist[-1] < 1e-13
+    assert all(h1 < h0 for h0, h1 in zip(hist[:8], hist[1:9]))
+    xd = fdfd.solve_direct(A, b)
+    assert fdfd.rel_l2(x, xd) < 1e-12
+
+
+def test_fgmres_with_round_matches_direct():
+    w = workloads.configs.cylinder_tfsf()
+    p, A = _setup(w)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    x, info = krylov.fgmres(lambda v: A @ v, b, B.apply, tol=1e-12, restart=30)
+    assert info["converged"] and info["iters"] <= 12
+    assert fdfd.rel_l2(x, fdfd.solve_direct(A, b)) < 1e-11

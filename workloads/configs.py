@@ -1,0 +1,94 @@
+"""Workload descriptions with their seeded inputs.
+
+All lengths are in grid cells (dx = dy = 1), so k0 = 2*pi/lambda_cells; only
+k0*dx enters the discrete problem.  Each config returns a plain dict holding
+the solver parameters and the input arrays (cell permittivity map and source).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import geometry, sources
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    k0: float
+    pml: tuple            # global PML cells (x-, x+, y-, y+)
+    pml_order: int
+    pml_R: float
+    px: int
+    py: int
+    overlap: int
+    local_pml: int
+    local_pml_order: int
+    local_pml_R: float
+    eps_cells: np.ndarray   # (ny+1, nx+1) complex128
+    b: np.ndarray           # (nrhs, ny, nx) complex128
+    dx: float = 1.0
+    dy: float = 1.0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ndof(self):
+        return self.nx * self.ny
+
+    def params(self, **over):
+        d = dict(nx=self.nx, ny=self.ny, dx=self.dx, dy=self.dy, k0=self.k0, pml=tuple(self.pml),
+                 pml_order=self.pml_order, pml_R=self.pml_R, px=self.px, py=self.py,
+                 overlap=self.overlap, local_pml=self.local_pml,
+                 local_pml_order=self.local_pml_order, local_pml_R=self.local_pml_R)
+        d.update(over)
+        return d
+
+
+def cylinder_tfsf(interior=100, pml=16, lam=20.0, radius_lam=0.5, eps_cyl=4.0, parts=2,
+                  overlap=8, local_pml=16, subcells=16):
+    """Dielectric cylinder at the grid centre lit by a +x plane wave through a
+    TF/SF line at interior column 2 (default: 100x100 interior, 16-cell PML,
+    lambda = 20 cells, r = lambda/2, eps = 4, 2x2 subdomains, overlap 8)."""
+    n = interior + 2 * pml
+    c = (n - 1) / 2.0
+    k0 = 2 * math.pi / lam
+    cells = geometry.cylinder(n, n, c, c, radius_lam * lam, eps_cyl, subcells=subcells)
+    col = pml + 2
+    b = sources.tfsf_plane_wave_x(n, n, 1.0, k0, col)[None]
+    return Workload("cylinder_tfsf_%d" % n, n, n, k0, (pml,) * 4, 3, 1e-8, parts, parts, overlap,
+                    local_pml, 3, 1e-8, cells, b,
+                    meta=dict(centre=(c, c), radius=radius_lam * lam, eps_cyl=eps_cyl, tfsf_col=col,
+                              lam=lam))
+
+
+def metasurface_sheet(interior=1024, pml=20, lam=30.0, parts=8, overlap=8, local_pml=16, seed=2,
+                      n_pillars=None, slot=16, substrate_rows=256, source_row=128, subcells=16):
+    """Random metasurface (pillars eps 12.25 on an eps 2.13 substrate) lit by a
+    current sheet inside the substrate (default 1024x1024 interior, 20-cell PML,
+    lambda = 30 cells, 8x8 subdomains, overlap 8, seed 2)."""
+    n = interior + 2 * pml
+    if n_pillars is None:
+        n_pillars = interior // slot
+    k0 = 2 * math.pi / lam
+    cells = geometry.metasurface(n, n, pml, lam, n_pillars, slot, substrate_rows, 12.25, 2.13, seed,
+                                 subcells=subcells)
+    b = sources.current_sheet(n, n, pml + source_row)[None]
+    return Workload("metasurface_%d" % n, n, n, k0, (pml,) * 4, 3, 1e-8, parts, parts, overlap,
+                    local_pml, 3, 1e-8, cells, b, meta=dict(seed=seed, lam=lam))
+
+
+def small_random(nx=48, ny=40, pml=6, lam=12.0, px=2, py=2, overlap=2, local_pml=6, seed=0,
+                 nrhs=1):
+    """Small random-medium problem for fast parity tests: smooth random
+    permittivity in [1, 4] with a small loss, random complex sources."""
+    rng = np.random.default_rng(seed)
+    base = rng.uniform(1.0, 4.0, size=(ny + 1, nx + 1))
+    cells = (base + 0.01j * rng.uniform(0, 1, size=base.shape)).astype(np.complex128)
+    b = np.stack([sources.random_field(nx, ny, seed * 1000 + r + 1) for r in range(nrhs)])
+    k0 = 2 * math.pi / lam
+    return Workload("random_%dx%d" % (nx, ny), nx, ny, k0, (pml,) * 4, 3, 1e-8, px, py, overlap,
+                    local_pml, 3, 1e-8, cells, b, meta=dict(seed=seed))
