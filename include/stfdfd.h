@@ -1,0 +1,184 @@
+/*
+ * stfdfd.h - C ABI of the MI355X (gfx950) overlapping-PML source-transfer FDFD solver.
+ *
+ * Method: arXiv 2509.20801, "Parallel overlapping-domain decomposition FDFD for
+ * large-scale complex nanostructures modeling".  The library solves the 2D TM
+ * FDFD system A e = b (Sec. 2.1, Eqs. (2)-(4)) with the stretched-coordinate PML
+ * of Sec. 2.2 (Eqs. (9)-(13)) by flexible GMRES in FP64, right-preconditioned by
+ * one source-transfer round over overlapping PML-terminated subdomains
+ * (Sec. 2.3, Eqs. (14)-(21), Algorithm 1) whose local systems are factored by a
+ * nested-dissection multifrontal LU (Sec. 2.4, Eqs. (22)-(23)).
+ *
+ * Conventions used by every call:
+ *   - Complex arrays are interleaved (re, im) doubles.
+ *   - Node arrays are row-major [ny][nx], x fastest: node (i, j) is element j*nx + i,
+ *     at position x = i*dx, y = j*dy.
+ *   - The cell permittivity map is row-major [ny+1][nx+1]; cell (c, d) is the dual
+ *     cell whose corners are nodes (c-1..c, d-1..d).  The node permittivity is the
+ *     mean of its four cells (Eq. (3)).
+ *   - Pointers marked "host or device" are read as device pointers when the call's
+ *     on_device argument is nonzero, else as host pointers.  Device pointers must
+ *     be accessible from the context's device; work on them is ordered on the
+ *     context's stream.  The caller owns every buffer it passes; the library
+ *     never retains a caller pointer after the call returns.
+ *   - Every call returns a status and never aborts, exits or throws; the message
+ *     of the last failing call on a context is returned by stf_last_error().
+ *   - One context per host thread.  Calls on one context are not thread safe.
+ */
+#ifndef STFDFD_H
+#define STFDFD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct stf_ctx_s*     stf_ctx;      /* device, stream, symbolic cache, timers */
+typedef struct stf_problem_s* stf_problem;  /* one assembled problem: operator, partition, factors */
+
+typedef enum {
+  STF_OK = 0,
+  STF_EINVAL = 1,   /* invalid argument (sizes, NaN/Inf input, partition too fine, ...) */
+  STF_ENOMEM = 2,   /* device or host allocation failed */
+  STF_EDEVICE = 3,  /* HIP runtime error */
+  STF_ESTATE = 4,   /* call out of order (e.g. solve before factor) */
+  STF_EPIVOT = 5,   /* a tiny pivot was perturbed during factorisation; results are valid
+                       (FGMRES absorbs the perturbation) */
+  STF_ENOCONV = 6,  /* max_iter reached above tol; x holds the last iterate */
+  STF_ENAN = 7      /* non-finite residual during the solve */
+} stf_status;
+
+/* Precision of the subdomain fronts and sweeps.  FGMRES, the global stencil,
+ * the Arnoldi process and the solution update are always FP64. */
+enum { STF_C128 = 0, STF_C64 = 1 };
+
+/* Initial guess. */
+enum { STF_X0_ZERO = 0, STF_X0_USER = 1 };
+
+/* Problem description (Sec. 2.1-2.3).  Global PML sides are ordered x-, x+, y-, y+.
+ * The interior [pml[0], nx-pml[1]) x [pml[2], ny-pml[3]) is split into px x py
+ * blocks as evenly as possible (earlier blocks take the remainder); edge blocks
+ * also own the global PML on their side.  Each block is extended on every side
+ * facing a neighbour by overlap + local_pml nodes: `overlap` unstretched cells
+ * then a local PML of `local_pml` cells (Eqs. (10)-(13) with local_pml_order and
+ * local_pml_R).  Requires every interior block side >= overlap + local_pml + 1. */
+typedef struct {
+  int32_t nx, ny;            /* nodes, global PML included (each >= 3) */
+  double  dx, dy;            /* grid steps (> 0) */
+  double  k0;                /* free-space wavenumber 2*pi/lambda in the same unit (> 0) */
+  int32_t pml[4];            /* global PML cells per side (>= 0) */
+  int32_t pml_order;         /* m of Eqs. (11)-(12) (>= 0) */
+  double  pml_R;             /* R(0) of Eq. (13), 0 < R < 1 */
+  int32_t px, py;            /* subdomain grid (>= 1 each) */
+  int32_t overlap;           /* unstretched overlap cells before the local PML (>= 0) */
+  int32_t local_pml;         /* local PML cells (>= 1 when px*py > 1) */
+  int32_t local_pml_order;
+  double  local_pml_R;
+  int32_t front_prec;        /* STF_C128 or STF_C64 */
+  int32_t leaf_size;         /* largest leaf box (nodes) of the nested dissection; 0 = 16 */
+} stf_params;
+
+typedef struct {
+  double  tol;        /* stop when |b - A x|_2 <= tol |b|_2 (FP64 true residual) */
+  int32_t restart;    /* FGMRES cycle length m (1..200) */
+  int32_t max_iter;   /* total inner iterations (>= 1) */
+  int32_t x0_mode;    /* STF_X0_ZERO or STF_X0_USER (x holds the guess on entry) */
+  int32_t reserved0;
+} stf_solve_opts;
+
+typedef struct {
+  int32_t iters;          /* inner FGMRES iterations performed */
+  int32_t restarts;       /* completed cycles */
+  int32_t status;         /* stf_status of this right-hand side */
+  int32_t history_len;    /* entries written to history */
+  double  relres_true;    /* FP64 |b - A x| / |b| at exit */
+  double  relres_x0;      /* FP64 |b - A x0| / |b| */
+  double* history;        /* caller-owned host buffer (may be NULL): relative residual
+                             estimate after every iteration, true residual at x0 first */
+  int32_t history_cap;    /* capacity of history */
+  int32_t reserved0;
+} stf_solve_info;
+
+/* Sizes and work counts of a plan. */
+typedef struct {
+  int64_t ndof;             /* nx*ny */
+  int32_t nsub;             /* px*py */
+  int32_t nshapes;          /* distinct subdomain shapes (symbolic plans) */
+  int64_t local_dof;        /* sum of subdomain node counts */
+  int64_t nfronts;          /* fronts over all subdomains */
+  int32_t max_front;        /* largest front order m = p + q */
+  int32_t max_depth;        /* deepest tree level (root = 0) */
+  int64_t factor_entries;   /* sum over fronts of p*p + 2*p*q (entries the sweeps read) */
+  int64_t front_entries;    /* sum over fronts of m*m (stored) */
+  double  lu_flops;         /* real flops of the partial LUs: 8 * sum_k (m-k)^2, k = 1..p */
+  int64_t device_bytes;     /* device memory held by the problem (0 from stf_plan_query) */
+} stf_plan_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Create a context on HIP device `device`.  hip_stream: a hipStream_t to order
+ * all work on (e.g. torch.cuda.current_stream().cuda_stream), or NULL for a
+ * stream of the library's own.  */
+stf_status  stf_ctx_create(int device, void* hip_stream, stf_ctx* out);
+void        stf_ctx_destroy(stf_ctx ctx);                 /* NULL-safe */
+const char* stf_last_error(stf_ctx ctx);                  /* never NULL */
+
+/* Per-kernel timing with HIP events on the context stream.  While enabled,
+ * every launch of the listed kernel classes is bracketed by two events. */
+enum {
+  STF_K_ASSEMBLE = 0, STF_K_STENCIL = 1, STF_K_FRONT_ASM = 2, STF_K_FRONT_LU = 3,
+  STF_K_SWEEP_FWD = 4, STF_K_SWEEP_BWD = 5, STF_K_SCATTER = 6, STF_K_ARNOLDI = 7,
+  STF_K_UPDATE = 8, STF_K_COUNT = 9
+};
+stf_status  stf_ctx_set_timing(stf_ctx ctx, int enable);  /* enabling resets the counters */
+/* Synchronises the stream, then reports the summed duration (ms) and launch count
+ * of kernel class `cls` since timing was enabled. */
+stf_status  stf_ctx_kernel_stats(stf_ctx ctx, int cls, double* total_ms, int64_t* launches);
+
+/* ---- problem ------------------------------------------------------------ */
+
+/* Host-only: validate `prm` and compute the partition and the nested-dissection
+ * plan statistics without touching a device. */
+stf_status  stf_plan_query(const stf_params* prm, stf_plan_info* out);
+
+/* Host-only test hook: the 1D coupling coefficients of subdomain k's local
+ * operator (Sec. 2.3 with the stretch of Eqs. (10)-(13)).  cw[t], ce[t] (t < local
+ * nx) couple local node column t to t-1 and t+1; cs[u], cn[u] (u < local ny) in y.
+ * Each is an interleaved complex array; dims receives {ox0, oy0, nxl, nyl,
+ * ix0, ix1, iy0, iy1} (global node ranges of Omega_k and I_k).  Any output
+ * pointer may be NULL; non-NULL arrays must hold the local size. */
+stf_status  stf_debug_local_axes(const stf_params* prm, int32_t k, int32_t* dims,
+                                 double* cw, double* ce, double* cs, double* cn);
+
+/* "Assemble from eps(x,y), omega, PML profile and subdomain partition" (Sec. 2.1-2.3,
+ * Algorithm 1 preprocessing): validates prm, builds the global and local stretch
+ * arrays, the partition and the symbolic plans (cached per subdomain shape in
+ * the context), allocates the device state and assembles the node permittivity.
+ * eps_cells: (ny+1)*(nx+1) complex, host or device.  */
+stf_status  stf_problem_create(stf_ctx ctx, const stf_params* prm, const double* eps_cells,
+                               int on_device, stf_problem* out);
+/* Re-assemble with a new permittivity map of the same shape (invalidates factors). */
+stf_status  stf_assemble(stf_problem pb, const double* eps_cells, int on_device);
+/* Numeric multifrontal LU of every subdomain operator (Eq. (22)); returns
+ * STF_EPIVOT if a pivot was perturbed. */
+stf_status  stf_factor(stf_problem pb);
+/* Solve A x = b for nrhs right-hand sides (FGMRES, FP64, right-preconditioned by
+ * one source-transfer round).  b, x: nrhs*ny*nx complex, host or device.
+ * info: array of nrhs (may be NULL).  Returns the worst per-RHS status. */
+stf_status  stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
+                      const stf_solve_opts* opts, stf_solve_info* info);
+/* y = A x with the global FP64 operator (Eqs. (2), (9)).  x, y: ny*nx complex. */
+stf_status  stf_apply(stf_problem pb, const double* x, double* y, int on_device);
+/* One source-transfer round z = sum_k P_k A_k^{-1} R_k^I v (Eqs. (14), (21)):
+ * restriction to each subdomain's own box, local multifrontal solve
+ * (Eq. (23)), and the sum of the full local fields.  v, z: ny*nx complex. */
+stf_status  stf_precond_apply(stf_problem pb, const double* v, double* z, int on_device);
+stf_status  stf_problem_info(stf_problem pb, stf_plan_info* out);
+void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STFDFD_H */

@@ -1,0 +1,258 @@
+"""stfdfd: MI355X (gfx950) overlapping-PML source-transfer FDFD solver.
+
+Thin Python binding over the C ABI declared in include/stfdfd.h.  It only
+marshals arguments (NumPy host arrays or torch device tensors -> pointers);
+every step of the solver runs in the HIP library.  If libstfdfd.so is not built
+the calls raise: there is no CPU fallback.
+
+Arrays: complex128, node arrays shaped (ny, nx) (x fastest), cell maps
+(ny+1, nx+1).  NumPy arrays are host buffers; torch CUDA tensors are device
+buffers used in place on the context's stream.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _abi
+from ._abi import (STF_C128, STF_C64, STF_X0_USER, STF_X0_ZERO, KERNEL_CLASSES,  # noqa: F401
+                   STATUS_NAMES)
+
+__all__ = ["Context", "Problem", "StfError", "plan_query", "debug_local_axes", "make_params",
+           "STF_C128", "STF_C64", "STF_X0_ZERO", "STF_X0_USER", "KERNEL_CLASSES"]
+
+
+class StfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS_NAMES.get(status, status), msg))
+        self.status = status
+
+
+def make_params(nx, ny, k0, dx=1.0, dy=1.0, pml=(0, 0, 0, 0), pml_order=3, pml_R=1e-8, px=1,
+                py=1, overlap=0, local_pml=0, local_pml_order=3, local_pml_R=1e-8,
+                front_prec=STF_C128, leaf_size=0):
+    p = _abi.Params()
+    p.nx, p.ny, p.dx, p.dy, p.k0 = int(nx), int(ny), float(dx), float(dy), float(k0)
+    for i in range(4):
+        p.pml[i] = int(pml[i])
+    p.pml_order, p.pml_R = int(pml_order), float(pml_R)
+    p.px, p.py, p.overlap, p.local_pml = int(px), int(py), int(overlap), int(local_pml)
+    p.local_pml_order, p.local_pml_R = int(local_pml_order), float(local_pml_R)
+    p.front_prec, p.leaf_size = int(front_prec), int(leaf_size)
+    return p
+
+
+def _params(prm):
+    if isinstance(prm, _abi.Params):
+        return prm
+    return make_params(**prm)
+
+
+def _is_torch(a):
+    return type(a).__module__.startswith("torch")
+
+
+def _ptr(a, n_complex, name):
+    """(pointer, on_device, keepalive) for a complex128 array of n_complex entries."""
+    if _is_torch(a):
+        import torch
+        if a.dtype != torch.complex128:
+            raise TypeError("%s must be torch.complex128" % name)
+        if not a.is_cuda or not a.is_contiguous():
+            raise TypeError("%s must be a contiguous CUDA tensor" % name)
+        if a.numel() != n_complex:
+            raise ValueError("%s has %d entries, expected %d" % (name, a.numel(), n_complex))
+        return C.c_void_p(a.data_ptr()), 1, a
+    arr = np.ascontiguousarray(a, dtype=np.complex128)
+    if arr.size != n_complex:
+        raise ValueError("%s has %d entries, expected %d" % (name, arr.size, n_complex))
+    return C.c_void_p(arr.ctypes.data), 0, arr
+
+
+def _check(ctx_handle, status, allow=()):
+    if status != 0 and status not in allow:
+        msg = _abi.load().stf_last_error(ctx_handle)
+        raise StfError(status, msg.decode() if msg else "")
+    return status
+
+
+def plan_query(prm):
+    """Host-only plan statistics (partition and nested-dissection fronts)."""
+    lib = _abi.load()
+    info = _abi.PlanInfo()
+    st = lib.stf_plan_query(C.byref(_params(prm)), C.byref(info))
+    if st != 0:
+        raise StfError(st, "invalid parameters")
+    return {f: getattr(info, f) for f, _ in _abi.PlanInfo._fields_}
+
+
+def debug_local_axes(prm, k):
+    """Host-only: local coupling coefficients (cw, ce, cs, cn) of subdomain k and its boxes."""
+    lib = _abi.load()
+    p = _params(prm)
+    dims = (C.c_int32 * 8)()
+    st = lib.stf_debug_local_axes(C.byref(p), int(k), dims, None, None, None, None)
+    if st != 0:
+        raise StfError(st, "invalid parameters or subdomain")
+    ox0, oy0, nxl, nyl, ix0, ix1, iy0, iy1 = list(dims)
+    cw = np.zeros(nxl, np.complex128); ce = np.zeros(nxl, np.complex128)
+    cs = np.zeros(nyl, np.complex128); cn = np.zeros(nyl, np.complex128)
+    st = lib.stf_debug_local_axes(C.byref(p), int(k), dims, cw.ctypes.data, ce.ctypes.data,
+                                  cs.ctypes.data, cn.ctypes.data)
+    if st != 0:
+        raise StfError(st, "invalid parameters or subdomain")
+    return dict(ox=(ox0, ox0 + nxl), oy=(oy0, oy0 + nyl), ix=(ix0, ix1), iy=(iy0, iy1),
+                cw=cw, ce=ce, cs=cs, cn=cn)
+
+
+class Context:
+    """Device context.  stream: a hipStream_t handle (int) or a torch stream; by
+    default the current torch stream of `device` (so torch and library work are
+    ordered), or the library's own stream when torch is unavailable."""
+
+    def __init__(self, device=0, stream=None):
+        self._lib = _abi.load()
+        if stream is None:
+            try:
+                import torch
+                stream = torch.cuda.current_stream(device).cuda_stream
+            except Exception:
+                stream = 0
+        elif hasattr(stream, "cuda_stream"):
+            stream = stream.cuda_stream
+        h = C.c_void_p()
+        st = self._lib.stf_ctx_create(int(device), C.c_void_p(int(stream) or None), C.byref(h))
+        if st != 0:
+            raise StfError(st, "stf_ctx_create failed")
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.stf_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, on):
+        _check(self.handle, self._lib.stf_ctx_set_timing(self.handle, int(bool(on))))
+
+    def kernel_stats(self, cls):
+        if isinstance(cls, str):
+            cls = KERNEL_CLASSES.index(cls)
+        ms, n = C.c_double(), C.c_int64()
+        _check(self.handle, self._lib.stf_ctx_kernel_stats(self.handle, int(cls), C.byref(ms),
+                                                           C.byref(n)))
+        return ms.value, n.value
+
+
+class Problem:
+    """An assembled problem: global operator, partition, symbolic plans, factors."""
+
+    def __init__(self, ctx, prm, eps_cells):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self.params = _params(prm)
+        self.nx, self.ny = self.params.nx, self.params.ny
+        ptr, dev, keep = _ptr(eps_cells, (self.nx + 1) * (self.ny + 1), "eps_cells")
+        h = C.c_void_p()
+        _check(ctx.handle, self._lib.stf_problem_create(ctx.handle, C.byref(self.params), ptr, dev,
+                                                        C.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self._lib.stf_problem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def ndof(self):
+        return self.nx * self.ny
+
+    def assemble(self, eps_cells):
+        ptr, dev, keep = _ptr(eps_cells, (self.nx + 1) * (self.ny + 1), "eps_cells")
+        _check(self.ctx.handle, self._lib.stf_assemble(self.handle, ptr, dev))
+
+    def factor(self):
+        """Returns True if a pivot was perturbed (STF_EPIVOT)."""
+        st = _check(self.ctx.handle, self._lib.stf_factor(self.handle), allow=(_abi.STF_EPIVOT,))
+        return st == _abi.STF_EPIVOT
+
+    def _out_like(self, a, shape):
+        if _is_torch(a):
+            import torch
+            return torch.empty(shape, dtype=torch.complex128, device=a.device)
+        return np.empty(shape, dtype=np.complex128)
+
+    def apply(self, x, y=None):
+        n = self.ndof
+        px, dev, kx = _ptr(x, n, "x")
+        y = self._out_like(x, (self.ny, self.nx)) if y is None else y
+        py_, dev2, ky = _ptr(y, n, "y")
+        if dev != dev2:
+            raise TypeError("x and y must both be host or both be device arrays")
+        _check(self.ctx.handle, self._lib.stf_apply(self.handle, px, py_, dev))
+        return y if dev else ky.reshape(self.ny, self.nx)
+
+    def precond(self, v, z=None):
+        n = self.ndof
+        pv, dev, kv = _ptr(v, n, "v")
+        z = self._out_like(v, (self.ny, self.nx)) if z is None else z
+        pz, dev2, kz = _ptr(z, n, "z")
+        if dev != dev2:
+            raise TypeError("v and z must both be host or both be device arrays")
+        _check(self.ctx.handle, self._lib.stf_precond_apply(self.handle, pv, pz, dev))
+        return z if dev else kz.reshape(self.ny, self.nx)
+
+    def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
+              raise_on_noconv=False):
+        """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos)."""
+        shape = tuple(b.shape)
+        nrhs = 1 if len(shape) == 2 else int(shape[0])
+        n = self.ndof
+        pb_, dev, kb = _ptr(b, nrhs * n, "b")
+        mode = _abi.STF_X0_ZERO
+        if x0 is not None:
+            mode = _abi.STF_X0_USER
+            if _is_torch(x0):
+                x = x0.clone()
+            else:
+                x = np.array(x0, dtype=np.complex128, copy=True)
+        elif x is None:
+            x = self._out_like(b, shape)
+        pxx, dev2, kx = _ptr(x, nrhs * n, "x")
+        if dev != dev2:
+            raise TypeError("b and x must both be host or both be device arrays")
+        opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, 0)
+        infos = (_abi.SolveInfo * nrhs)()
+        hist = [np.zeros(history_cap, dtype=np.float64) for _ in range(nrhs)]
+        for i in range(nrhs):
+            infos[i].history = hist[i].ctypes.data_as(C.POINTER(C.c_double))
+            infos[i].history_cap = history_cap
+        allow = () if raise_on_noconv else (_abi.STF_ENOCONV,)
+        _check(self.ctx.handle, self._lib.stf_solve(self.handle, nrhs, pb_, pxx, dev,
+                                                    C.byref(opts), infos), allow=allow)
+        out = []
+        for i in range(nrhs):
+            inf = infos[i]
+            out.append(dict(iters=inf.iters, restarts=inf.restarts, status=inf.status,
+                            relres_true=inf.relres_true, relres_x0=inf.relres_x0,
+                            history=hist[i][:inf.history_len].copy()))
+        xo = x if dev else kx.reshape(shape)
+        return xo, out
+
+    def info(self):
+        pi = _abi.PlanInfo()
+        _check(self.ctx.handle, self._lib.stf_problem_info(self.handle, C.byref(pi)))
+        return {f: getattr(pi, f) for f, _ in _abi.PlanInfo._fields_}

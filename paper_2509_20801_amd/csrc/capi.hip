@@ -1,0 +1,869 @@
+// C ABI of the stfdfd library: contexts, problems, factorisation and the FGMRES
+// solve preconditioned by one source-transfer round (Sec. 2.3, Algorithm 1;
+// Sec. 2.4, Eqs. (22)-(23)).  Host code only orchestrates: every arithmetic
+// step on problem data runs in the kernels of kernels_*.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+#include "cplx.h"
+#include "stf_internal.h"
+
+using namespace stf;
+
+namespace {
+
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void alloc(size_t b) {
+    if (b <= bytes && p) return;
+    release();
+    if (b == 0) b = 16;
+    HIP_CHECK(hipMalloc(&p, b));
+    bytes = b;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+void upload(DBuf& d, const std::vector<T>& h, hipStream_t st) {
+  d.alloc(std::max<size_t>(h.size() * sizeof(T), 16));
+  if (!h.empty()) HIP_CHECK(hipMemcpyAsync(d.p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, st));
+}
+
+struct Level {
+  int off = 0, n = 0, max_m = 0;
+};
+
+}  // namespace
+
+struct stf_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string last_error;
+  std::map<std::tuple<int, int, int>, std::shared_ptr<const SymShape>> shapes;
+  // Timing: pending event pairs per kernel class, folded totals.
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[STF_K_COUNT];
+  std::vector<hipEvent_t> pool;
+  double total_ms[STF_K_COUNT] = {};
+  int64_t launches[STF_K_COUNT] = {};
+  double* pinned = nullptr;     // small pinned host staging area
+
+  hipEvent_t get_event() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    HIP_CHECK(hipEventCreate(&e));
+    return e;
+  }
+  void fold() {
+    HIP_CHECK(hipStreamSynchronize(stream));
+    for (int c = 0; c < STF_K_COUNT; ++c) {
+      for (auto& pr : pending[c]) {
+        float ms = 0.f;
+        HIP_CHECK(hipEventElapsedTime(&ms, pr.first, pr.second));
+        total_ms[c] += ms;
+        launches[c] += 1;
+        pool.push_back(pr.first);
+        pool.push_back(pr.second);
+      }
+      pending[c].clear();
+    }
+  }
+  size_t npending() const {
+    size_t s = 0;
+    for (int c = 0; c < STF_K_COUNT; ++c) s += pending[c].size();
+    return s;
+  }
+};
+
+namespace {
+
+// Brackets one kernel launch with events when timing is on.
+struct Timed {
+  stf_ctx c;
+  int cls;
+  hipEvent_t b = nullptr;
+  Timed(stf_ctx c_, int cls_) : c(c_), cls(cls_) {
+    if (c->timing) {
+      if (c->npending() > 16384) c->fold();
+      b = c->get_event();
+      HIP_CHECK(hipEventRecord(b, c->stream));
+    }
+  }
+  ~Timed() {
+    if (!b) return;
+    hipEvent_t e = nullptr;
+    if (!c->pool.empty()) {
+      e = c->pool.back();
+      c->pool.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+      c->pool.push_back(b);
+      return;
+    }
+    if (hipEventRecord(e, c->stream) != hipSuccess) {
+      c->pool.push_back(b);
+      c->pool.push_back(e);
+      return;
+    }
+    c->pending[cls].push_back({b, e});
+  }
+};
+
+}  // namespace
+
+struct stf_problem_s {
+  stf_ctx ctx = nullptr;
+  Plan plan;
+  stf_params prm{};
+  long long N = 0;
+  int nsub = 0;
+  int max_depth = 0;
+  bool assembled = false, factored = false;
+  int prec = STF_C128;
+  int64_t n_fronts = 0;
+  int64_t fac_elems = 0, vec_elems = 0, piv_elems = 0, u_elems = 0;
+  std::vector<Level> levels;     // by depth
+
+  // Device state.
+  DBuf keps, gcoef, lcoef, subs, fronts, level_list, vars, cmap, ents, children;
+  DBuf fac, piv, vec, u, cover_x, cover_y, flag;
+  DBuf partial, scal;              // reduction scratch, device scalars
+  DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2;
+  DBuf hb, hx, cells;              // staging for host inputs
+  int krylov_m = 0;
+
+  const double2* cxw() const { return gcoef.as<double2>(); }
+  const double2* cxe() const { return gcoef.as<double2>() + prm.nx; }
+  const double2* cyw() const { return gcoef.as<double2>() + 2 * prm.nx; }
+  const double2* cye() const { return gcoef.as<double2>() + 2 * prm.nx + prm.ny; }
+
+  LevelArgs level_args(int d) const {
+    LevelArgs a{};
+    a.fronts = fronts.as<FrontDev>();
+    a.level_list = level_list.as<int>() + levels[d].off;
+    a.nlevel = levels[d].n;
+    a.subs = subs.as<SubDev>();
+    a.vars = vars.as<int>();
+    a.cmap = cmap.as<int>();
+    a.ents = ents.as<SymEntry>();
+    a.children = children.as<int>();
+    a.keps = keps.as<double2>();
+    a.lcoef = lcoef.as<double2>();
+    a.nx = prm.nx;
+    a.max_m = levels[d].max_m;
+    return a;
+  }
+  int64_t device_bytes() const {
+    const DBuf* all[] = {&keps, &gcoef, &lcoef, &subs, &fronts, &level_list, &vars, &cmap, &ents,
+                         &children, &fac, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
+                         &scal, &kV, &kZ, &kw, &kr, &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &hb,
+                         &hx, &cells};
+    int64_t s = 0;
+    for (const DBuf* b : all) s += (int64_t)b->bytes;
+    return s;
+  }
+};
+
+namespace {
+
+template <typename F>
+stf_status guard(stf_ctx c, F&& fn) {
+  try {
+    if (c) HIP_CHECK(hipSetDevice(c->device));
+    fn();
+    return STF_OK;
+  } catch (const Error& e) {
+    if (c) c->last_error = e.what();
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    if (c) c->last_error = "host allocation failed";
+    return STF_ENOMEM;
+  } catch (const std::exception& e) {
+    if (c) c->last_error = e.what();
+    return STF_EDEVICE;
+  }
+}
+
+bool host_finite(const double* a, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(a[i])) return false;
+  return true;
+}
+
+// Rejects non-finite values in a caller array (host or device).
+void require_finite(stf_problem pb, const double* a, size_t n, int on_device, const char* what) {
+  if (!on_device) {
+    STF_REQUIRE(host_finite(a, n), std::string(what) + " holds NaN or Inf");
+    return;
+  }
+  hipStream_t st = pb->ctx->stream;
+  HIP_CHECK(hipMemsetAsync(pb->flag.p, 0, sizeof(int), st));
+  launch_check_finite(st, a, (long long)n, pb->flag.as<int>());
+  int h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, pb->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  STF_REQUIRE(h == 0, std::string(what) + " holds NaN or Inf");
+}
+
+void build_device_state(stf_problem pb) {
+  const Plan& pl = pb->plan;
+  const stf_params& p = pb->prm;
+  hipStream_t st = pb->ctx->stream;
+  pb->N = (long long)p.nx * p.ny;
+  pb->nsub = (int)pl.subs.size();
+  pb->prec = p.front_prec;
+
+  // Global coupling arrays: cxw | cxe | cyw | cye.
+  std::vector<double2> gc;
+  for (auto& v : pl.g.cx.w) gc.push_back(make_double2(v.real(), v.imag()));
+  for (auto& v : pl.g.cx.e) gc.push_back(make_double2(v.real(), v.imag()));
+  for (auto& v : pl.g.cy.w) gc.push_back(make_double2(v.real(), v.imag()));
+  for (auto& v : pl.g.cy.e) gc.push_back(make_double2(v.real(), v.imag()));
+  upload(pb->gcoef, gc, st);
+
+  // Subdomains and local coefficient pairs.
+  std::vector<double2> lc;
+  std::vector<SubDev> sd;
+  long long uoff = 0;
+  for (const SubDesc& s : pl.subs) {
+    SubDev d{};
+    d.ox0 = s.ox0; d.oy0 = s.oy0; d.nxl = s.nxl; d.nyl = s.nyl;
+    d.ix0 = s.ix0; d.ix1 = s.ix1; d.iy0 = s.iy0; d.iy1 = s.iy1;
+    d.cx_off = (int)lc.size();
+    for (int t = 0; t < s.nxl; ++t) {
+      lc.push_back(make_double2(s.cx.w[t].real(), s.cx.w[t].imag()));
+      lc.push_back(make_double2(s.cx.e[t].real(), s.cx.e[t].imag()));
+    }
+    d.cy_off = (int)lc.size();
+    for (int t = 0; t < s.nyl; ++t) {
+      lc.push_back(make_double2(s.cy.w[t].real(), s.cy.w[t].imag()));
+      lc.push_back(make_double2(s.cy.e[t].real(), s.cy.e[t].imag()));
+    }
+    d.u_off = uoff;
+    uoff += (long long)s.nxl * s.nyl;
+    sd.push_back(d);
+  }
+  pb->u_elems = uoff;
+  upload(pb->lcoef, lc, st);
+  upload(pb->subs, sd, st);
+
+  // Concatenated symbolic arrays of the distinct shapes.
+  std::vector<int> vars, cmap, sh_var(pl.shapes.size()), sh_cmap(pl.shapes.size()),
+      sh_ent(pl.shapes.size());
+  std::vector<SymEntry> ents;
+  for (size_t k = 0; k < pl.shapes.size(); ++k) {
+    const SymShape& sh = *pl.shapes[k];
+    sh_var[k] = (int)vars.size();
+    sh_cmap[k] = (int)cmap.size();
+    sh_ent[k] = (int)ents.size();
+    vars.insert(vars.end(), sh.vars.begin(), sh.vars.end());
+    cmap.insert(cmap.end(), sh.cmap.begin(), sh.cmap.end());
+    ents.insert(ents.end(), sh.ents.begin(), sh.ents.end());
+  }
+  upload(pb->vars, vars, st);
+  upload(pb->cmap, cmap, st);
+  upload(pb->ents, ents, st);
+
+  // Front instances of every subdomain.
+  std::vector<FrontDev> fr;
+  std::vector<int> kids;
+  std::vector<std::vector<int>> bydepth;
+  long long fac_off = 0;
+  long long vec_off = 0, piv_off = 0;
+  for (int k = 0; k < pb->nsub; ++k) {
+    const SubDesc& s = pl.subs[k];
+    const SymShape& sh = *pl.shapes[s.shape];
+    int base = (int)fr.size();
+    for (size_t i = 0; i < sh.fronts.size(); ++i) {
+      const SymFront& f = sh.fronts[i];
+      FrontDev d{};
+      int m = f.p + f.q;
+      d.fac_off = fac_off;
+      d.vec_off = (int)vec_off;
+      d.piv_off = (int)piv_off;
+      d.p = f.p;
+      d.q = f.q;
+      d.sub = k;
+      d.var_off = sh_var[s.shape] + f.var_off;
+      d.cmap_off = sh_cmap[s.shape] + f.cmap_off;
+      d.ent_off = sh_ent[s.shape] + f.ent_off;
+      d.ent_cnt = f.ent_cnt;
+      d.parent = f.parent >= 0 ? base + f.parent : -1;
+      d.child_off = (int)kids.size();
+      d.nchild = f.nchild;
+      for (int c = 0; c < f.nchild; ++c) kids.push_back(base + sh.children[f.child_off + c]);
+      fac_off += (long long)m * m;
+      vec_off += m;
+      piv_off += f.p;
+      if ((int)bydepth.size() <= f.depth) bydepth.resize(f.depth + 1);
+      bydepth[f.depth].push_back((int)fr.size());
+      fr.push_back(d);
+    }
+  }
+  STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
+  pb->n_fronts = (int64_t)fr.size();
+  pb->fac_elems = fac_off;
+  pb->vec_elems = vec_off;
+  pb->piv_elems = piv_off;
+  // Level lists, largest fronts first.
+  std::vector<int> ll;
+  pb->levels.clear();
+  for (auto& lv : bydepth) {
+    std::stable_sort(lv.begin(), lv.end(), [&](int a, int b) {
+      return fr[a].p + fr[a].q > fr[b].p + fr[b].q;
+    });
+    Level L;
+    L.off = (int)ll.size();
+    L.n = (int)lv.size();
+    for (int i : lv) L.max_m = std::max(L.max_m, fr[i].p + fr[i].q);
+    ll.insert(ll.end(), lv.begin(), lv.end());
+    pb->levels.push_back(L);
+  }
+  pb->max_depth = (int)pb->levels.size() - 1;
+  upload(pb->fronts, fr, st);
+  upload(pb->children, kids, st);
+  upload(pb->level_list, ll, st);
+  upload(pb->cover_x, pl.cover_x, st);
+  upload(pb->cover_y, pl.cover_y, st);
+
+  size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
+  pb->fac.alloc((size_t)pb->fac_elems * es);
+  pb->piv.alloc((size_t)pb->piv_elems * sizeof(int));
+  pb->vec.alloc((size_t)pb->vec_elems * es);
+  pb->u.alloc((size_t)pb->u_elems * es);
+  pb->keps.alloc((size_t)pb->N * sizeof(double2));
+  pb->flag.alloc(sizeof(int) * 4);
+  pb->scal.alloc(sizeof(double) * 64);
+  int nblk = std::max(stencil_partial_blocks(p.nx, p.ny), krylov_blocks(pb->N));
+  pb->partial.alloc((size_t)nblk * sizeof(double2) * 4);
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void assemble_eps(stf_problem pb, const double* eps, int on_device) {
+  const stf_params& p = pb->prm;
+  size_t ncell = (size_t)(p.nx + 1) * (p.ny + 1);
+  require_finite(pb, eps, 2 * ncell, on_device, "eps_cells");
+  hipStream_t st = pb->ctx->stream;
+  const double2* src = reinterpret_cast<const double2*>(eps);
+  if (!on_device) {
+    pb->cells.alloc(ncell * sizeof(double2));
+    HIP_CHECK(hipMemcpyAsync(pb->cells.p, eps, ncell * sizeof(double2), hipMemcpyHostToDevice, st));
+    src = pb->cells.as<double2>();
+  }
+  {
+    Timed t(pb->ctx, K_ASSEMBLE);
+    launch_node_keps(st, src, pb->keps.as<double2>(), p.nx, p.ny, p.k0 * p.k0);
+  }
+  if (!on_device) HIP_CHECK(hipStreamSynchronize(st));   // staging buffer reuse
+  pb->assembled = true;
+  pb->factored = false;
+}
+
+template <typename T>
+int factor_t(stf_problem pb) {
+  hipStream_t st = pb->ctx->stream;
+  T* fac = pb->fac.as<T>();
+  HIP_CHECK(hipMemsetAsync(pb->flag.p, 0, sizeof(int), st));
+  double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
+  for (int d = pb->max_depth; d >= 0; --d) {
+    LevelArgs a = pb->level_args(d);
+    {
+      Timed t(pb->ctx, K_FRONT_ASM);
+      launch_front_assemble<T>(st, a, fac);
+    }
+    {
+      Timed t(pb->ctx, K_FRONT_LU);
+      launch_front_lu<T>(st, a, fac, pb->piv.as<int>(), pb->flag.as<int>(), tau);
+    }
+  }
+  HIP_CHECK(hipGetLastError());
+  int h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, pb->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return h;
+}
+
+// z = sum_k P_k A_k^{-1} R_k^I v  (one source-transfer round).
+template <typename T>
+void precond_t(stf_problem pb, const double2* v, double2* z) {
+  hipStream_t st = pb->ctx->stream;
+  const T* fac = pb->fac.as<T>();
+  T* vec = pb->vec.as<T>();
+  for (int d = pb->max_depth; d >= 0; --d) {
+    Timed t(pb->ctx, K_SWEEP_FWD);
+    launch_sweep_fwd<T>(st, pb->level_args(d), fac, pb->piv.as<int>(), vec, v);
+  }
+  for (int d = 0; d <= pb->max_depth; ++d) {
+    Timed t(pb->ctx, K_SWEEP_BWD);
+    launch_sweep_bwd<T>(st, pb->level_args(d), fac, vec, pb->u.as<T>());
+  }
+  Timed t(pb->ctx, K_SCATTER);
+  launch_scatter<T>(st, pb->u.as<T>(), pb->subs.as<SubDev>(), pb->cover_x.as<int4>(),
+                    pb->cover_y.as<int4>(), pb->prm.px, pb->prm.nx, pb->prm.ny, z);
+}
+
+void precond(stf_problem pb, const double2* v, double2* z) {
+  if (pb->prec == STF_C64)
+    precond_t<float2>(pb, v, z);
+  else
+    precond_t<double2>(pb, v, z);
+}
+
+void apply_A(stf_problem pb, const double2* x, double2* y) {
+  Timed t(pb->ctx, K_STENCIL);
+  launch_stencil(pb->ctx->stream, 0, x, nullptr, y, pb->keps.as<double2>(), pb->cxw(), pb->cxe(),
+                 pb->cyw(), pb->cye(), pb->prm.nx, pb->prm.ny, nullptr, nullptr);
+}
+
+// r = b - A x; dst receives |r|^2 on device.
+void residual(stf_problem pb, const double2* x, const double2* b, double2* r, double* dst) {
+  hipStream_t st = pb->ctx->stream;
+  int nb = 0;
+  {
+    Timed t(pb->ctx, K_STENCIL);
+    launch_stencil(st, 1, x, b, r, pb->keps.as<double2>(), pb->cxw(), pb->cxe(), pb->cyw(),
+                   pb->cye(), pb->prm.nx, pb->prm.ny, pb->partial.as<double>(), &nb);
+  }
+  launch_reduce_sum(st, pb->partial.as<double>(), nb, dst);
+}
+
+// |v|^2 on device (real part of v^H v).
+void norm2(stf_problem pb, const double2* v, double2* dst) {
+  hipStream_t st = pb->ctx->stream;
+  Timed t(pb->ctx, K_ARNOLDI);
+  launch_mdot(st, v, pb->N, 1, v, pb->N, pb->partial.as<double2>());
+  launch_mdot_reduce(st, pb->partial.as<double2>(), krylov_blocks(pb->N), 1, dst);
+}
+
+void ensure_krylov(stf_problem pb, int m) {
+  if (pb->krylov_m >= m) return;
+  size_t vb = (size_t)pb->N * sizeof(double2);
+  pb->kV.alloc(vb * (m + 1));
+  pb->kZ.alloc(vb * m);
+  pb->kw.alloc(vb);
+  pb->kr.alloc(vb);
+  pb->kH.alloc(sizeof(double2) * (m + 1) * m);
+  pb->kcs.alloc(sizeof(double) * m);
+  pb->ksn.alloc(sizeof(double2) * m);
+  pb->kg.alloc(sizeof(double2) * (m + 1));
+  pb->ky.alloc(sizeof(double2) * (m + 1));
+  pb->kh1.alloc(sizeof(double2) * (m + 1));
+  pb->kh2.alloc(sizeof(double2) * (m + 1));
+  int nblk = krylov_blocks(pb->N);
+  pb->partial.alloc(std::max<size_t>(pb->partial.bytes, (size_t)nblk * (m + 1) * sizeof(double2)));
+  pb->krylov_m = m;
+}
+
+// Scalars on device: [0] |b|^2 (double2 slot 0..1), [2] |r|^2, [3] |w|^2, [4] est.
+stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_solve_opts& o,
+                      stf_solve_info* info) {
+  stf_ctx c = pb->ctx;
+  hipStream_t st = c->stream;
+  const long long N = pb->N;
+  const int m = o.restart;
+  ensure_krylov(pb, m);
+  double* sc = pb->scal.as<double>();
+  double2* V = pb->kV.as<double2>();
+  double2* Z = pb->kZ.as<double2>();
+  double2* w = pb->kw.as<double2>();
+  double2* r = pb->kr.as<double2>();
+  double2* H = pb->kH.as<double2>();
+  double* hp = c->pinned;
+  const int nblk = krylov_blocks(N);
+
+  if (o.x0_mode == STF_X0_ZERO) HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
+  norm2(pb, b, reinterpret_cast<double2*>(sc));          // sc[0] = |b|^2
+  residual(pb, x, b, r, sc + 2);                         // sc[2] = |r|^2
+  HIP_CHECK(hipMemcpyAsync(hp, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  const double bnorm = std::sqrt(hp[0]);
+  double rnorm = std::sqrt(hp[2]);
+  int hlen = 0;
+  auto hist = [&](double v) {
+    if (info && info->history && hlen < info->history_cap) info->history[hlen] = v;
+    ++hlen;
+  };
+  stf_solve_info loc{};
+  loc.history_len = 0;
+  if (bnorm == 0.0) {
+    HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    loc.relres_true = 0.0;
+    loc.relres_x0 = 0.0;
+    if (info) {
+      loc.history = info->history;
+      loc.history_cap = info->history_cap;
+      *info = loc;
+    }
+    return STF_OK;
+  }
+  if (!std::isfinite(rnorm)) throw Error(STF_ENAN, "non-finite initial residual");
+  loc.relres_x0 = rnorm / bnorm;
+  hist(rnorm / bnorm);
+  int it = 0, restarts = 0;
+  stf_status status = STF_ENOCONV;
+  while (true) {
+    if (rnorm <= o.tol * bnorm) { status = STF_OK; break; }
+    if (it >= o.max_iter) { status = STF_ENOCONV; break; }
+    {
+      Timed t(c, K_UPDATE);
+      launch_scale(st, r, sc + 2, V, N);                    // v_0 = r / |r|
+    }
+    HIP_CHECK(hipMemsetAsync(pb->kg.p, 0, sizeof(double2) * (m + 1), st));
+    hp[8] = rnorm;
+    hp[9] = 0.0;
+    HIP_CHECK(hipMemcpyAsync(pb->kg.p, hp + 8, sizeof(double2), hipMemcpyHostToDevice, st));
+    int k = 0;
+    bool stop = false;
+    for (int j = 0; j < m && !stop; ++j) {
+      double2* vj = V + (long long)j * N;
+      double2* zj = Z + (long long)j * N;
+      precond(pb, vj, zj);
+      apply_A(pb, zj, w);
+      // Classical Gram-Schmidt, twice.
+      {
+        Timed t(c, K_ARNOLDI);
+        launch_mdot(st, V, N, j + 1, w, N, pb->partial.as<double2>());
+        launch_mdot_reduce(st, pb->partial.as<double2>(), nblk, j + 1, pb->kh1.as<double2>());
+        launch_mupdate(st, V, N, j + 1, pb->kh1.as<double2>(), w, N, nullptr);
+        launch_mdot(st, V, N, j + 1, w, N, pb->partial.as<double2>());
+        launch_mdot_reduce(st, pb->partial.as<double2>(), nblk, j + 1, pb->kh2.as<double2>());
+        launch_mupdate(st, V, N, j + 1, pb->kh2.as<double2>(), w, N, pb->partial.as<double>());
+        launch_reduce_sum(st, pb->partial.as<double>(), nblk, sc + 3);
+      }
+      {
+        Timed t(c, K_UPDATE);
+        launch_scale(st, w, sc + 3, V + (long long)(j + 1) * N, N);
+        launch_givens(st, H, pb->kh1.as<double2>(), pb->kh2.as<double2>(), sc + 3,
+                      pb->kcs.as<double>(), pb->ksn.as<double2>(), pb->kg.as<double2>(), j, m + 1,
+                      sc + 4);
+      }
+      HIP_CHECK(hipMemcpyAsync(hp + 4, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      ++it;
+      k = j + 1;
+      double est = hp[5];
+      hist(est / bnorm);
+      if (!std::isfinite(est)) throw Error(STF_ENAN, "non-finite residual estimate");
+      if (est <= o.tol * bnorm || hp[4] == 0.0 || it >= o.max_iter) stop = true;
+    }
+    {
+      Timed t(c, K_UPDATE);
+      launch_trisolve(st, H, pb->kg.as<double2>(), pb->ky.as<double2>(), k, m + 1);
+      launch_xupdate(st, Z, N, k, pb->ky.as<double2>(), x, N);
+    }
+    residual(pb, x, b, r, sc + 2);
+    HIP_CHECK(hipMemcpyAsync(hp + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    rnorm = std::sqrt(hp[2]);
+    ++restarts;
+    if (!std::isfinite(rnorm)) throw Error(STF_ENAN, "non-finite true residual");
+  }
+  loc.iters = it;
+  loc.restarts = restarts;
+  loc.relres_true = rnorm / bnorm;
+  loc.status = status;
+  loc.history_len = std::min(hlen, info ? info->history_cap : 0);
+  if (info) {
+    loc.history = info->history;
+    loc.history_cap = info->history_cap;
+    *info = loc;
+  }
+  return status;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Exported entry points
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
+  if (!out) return STF_EINVAL;
+  *out = nullptr;
+  stf_ctx c = nullptr;
+  try {
+    c = new stf_ctx_s();
+  } catch (...) {
+    return STF_ENOMEM;
+  }
+  stf_status s = guard(nullptr, [&] {
+    int n = 0;
+    HIP_CHECK(hipGetDeviceCount(&n));
+    STF_REQUIRE(device >= 0 && device < n, "device index out of range");
+    c->device = device;
+    HIP_CHECK(hipSetDevice(device));
+    if (hip_stream) {
+      c->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+      HIP_CHECK(hipStreamCreate(&c->stream));
+      c->own_stream = true;
+    }
+    HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault));
+  });
+  if (s != STF_OK) {
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+    return s;
+  }
+  *out = c;
+  return STF_OK;
+}
+
+void stf_ctx_destroy(stf_ctx c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (int k = 0; k < STF_K_COUNT; ++k)
+    for (auto& pr : c->pending[k]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* stf_last_error(stf_ctx c) {
+  if (!c) return "null context";
+  return c->last_error.c_str();
+}
+
+stf_status stf_ctx_set_timing(stf_ctx c, int enable) {
+  if (!c) return STF_EINVAL;
+  return guard(c, [&] {
+    c->fold();
+    for (int k = 0; k < STF_K_COUNT; ++k) {
+      c->total_ms[k] = 0.0;
+      c->launches[k] = 0;
+    }
+    c->timing = enable != 0;
+  });
+}
+
+stf_status stf_ctx_kernel_stats(stf_ctx c, int cls, double* total_ms, int64_t* launches) {
+  if (!c) return STF_EINVAL;
+  return guard(c, [&] {
+    STF_REQUIRE(cls >= 0 && cls < STF_K_COUNT, "kernel class out of range");
+    c->fold();
+    if (total_ms) *total_ms = c->total_ms[cls];
+    if (launches) *launches = c->launches[cls];
+  });
+}
+
+stf_status stf_plan_query(const stf_params* prm, stf_plan_info* out) {
+  if (!prm || !out) return STF_EINVAL;
+  try {
+    Plan pl = build_plan(*prm, nullptr);
+    *out = plan_info(pl);
+    return STF_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return STF_EINVAL;
+  }
+}
+
+stf_status stf_debug_local_axes(const stf_params* prm, int32_t k, int32_t* dims, double* cw,
+                                double* ce, double* cs, double* cn) {
+  if (!prm) return STF_EINVAL;
+  try {
+    stf_params p = normalized(*prm);
+    validate_params(p);
+    GlobalAxes g = build_global_axes(p);
+    std::vector<SubDesc> subs = build_partition(p, g);
+    if (k < 0 || k >= (int)subs.size()) return STF_EINVAL;
+    const SubDesc& s = subs[k];
+    if (dims) {
+      int32_t d[8] = {s.ox0, s.oy0, s.nxl, s.nyl, s.ix0, s.ix1, s.iy0, s.iy1};
+      std::memcpy(dims, d, sizeof(d));
+    }
+    auto put = [](double* dst, const std::vector<cd>& v) {
+      if (!dst) return;
+      for (size_t i = 0; i < v.size(); ++i) {
+        dst[2 * i] = v[i].real();
+        dst[2 * i + 1] = v[i].imag();
+      }
+    };
+    put(cw, s.cx.w);
+    put(ce, s.cx.e);
+    put(cs, s.cy.w);
+    put(cn, s.cy.e);
+    return STF_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return STF_EINVAL;
+  }
+}
+
+stf_status stf_problem_create(stf_ctx c, const stf_params* prm, const double* eps_cells,
+                              int on_device, stf_problem* out) {
+  if (!c) return STF_EINVAL;
+  if (!out || !prm || !eps_cells) {
+    c->last_error = "null argument";
+    return STF_EINVAL;
+  }
+  *out = nullptr;
+  stf_problem pb = nullptr;
+  stf_status s = guard(c, [&] {
+    pb = new stf_problem_s();
+    pb->ctx = c;
+    pb->plan = build_plan(*prm, &c->shapes);
+    pb->prm = pb->plan.prm;
+    build_device_state(pb);
+    assemble_eps(pb, eps_cells, on_device);
+  });
+  if (s != STF_OK) {
+    delete pb;
+    return s;
+  }
+  *out = pb;
+  return STF_OK;
+}
+
+stf_status stf_assemble(stf_problem pb, const double* eps_cells, int on_device) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(eps_cells != nullptr, "null eps_cells");
+    assemble_eps(pb, eps_cells, on_device);
+  });
+}
+
+stf_status stf_factor(stf_problem pb) {
+  if (!pb) return STF_EINVAL;
+  int flagged = 0;
+  stf_status s = guard(pb->ctx, [&] {
+    if (!pb->assembled) throw Error(STF_ESTATE, "factor before assemble");
+    flagged = pb->prec == STF_C64 ? factor_t<float2>(pb) : factor_t<double2>(pb);
+    pb->factored = true;
+  });
+  if (s == STF_OK && flagged) {
+    pb->ctx->last_error = "tiny pivot perturbed during factorisation";
+    return STF_EPIVOT;
+  }
+  return s;
+}
+
+stf_status stf_apply(stf_problem pb, const double* x, double* y, int on_device) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(x && y, "null argument");
+    hipStream_t st = pb->ctx->stream;
+    size_t vb = (size_t)pb->N * sizeof(double2);
+    if (on_device) {
+      apply_A(pb, reinterpret_cast<const double2*>(x), reinterpret_cast<double2*>(y));
+      HIP_CHECK(hipGetLastError());
+      return;
+    }
+    pb->hb.alloc(vb);
+    pb->hx.alloc(vb);
+    HIP_CHECK(hipMemcpyAsync(pb->hb.p, x, vb, hipMemcpyHostToDevice, st));
+    apply_A(pb, pb->hb.as<double2>(), pb->hx.as<double2>());
+    HIP_CHECK(hipMemcpyAsync(y, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+stf_status stf_precond_apply(stf_problem pb, const double* v, double* z, int on_device) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(v && z, "null argument");
+    if (!pb->factored) throw Error(STF_ESTATE, "precond before factor");
+    hipStream_t st = pb->ctx->stream;
+    size_t vb = (size_t)pb->N * sizeof(double2);
+    if (on_device) {
+      precond(pb, reinterpret_cast<const double2*>(v), reinterpret_cast<double2*>(z));
+      HIP_CHECK(hipGetLastError());
+      return;
+    }
+    pb->hb.alloc(vb);
+    pb->hx.alloc(vb);
+    HIP_CHECK(hipMemcpyAsync(pb->hb.p, v, vb, hipMemcpyHostToDevice, st));
+    precond(pb, pb->hb.as<double2>(), pb->hx.as<double2>());
+    HIP_CHECK(hipMemcpyAsync(z, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
+                     const stf_solve_opts* opts, stf_solve_info* info) {
+  if (!pb) return STF_EINVAL;
+  stf_status worst = STF_OK;
+  stf_status s = guard(pb->ctx, [&] {
+    STF_REQUIRE(b && x && opts, "null argument");
+    STF_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    STF_REQUIRE(opts->restart >= 1 && opts->restart <= 200, "restart out of range");
+    STF_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+    STF_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be finite and >= 0");
+    STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER, "x0_mode invalid");
+    if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
+    const size_t per = (size_t)pb->N * 2;
+    require_finite(pb, b, per * nrhs, on_device, "b");
+    if (opts->x0_mode == STF_X0_USER) require_finite(pb, x, per * nrhs, on_device, "x0");
+    hipStream_t st = pb->ctx->stream;
+    size_t vb = (size_t)pb->N * sizeof(double2);
+    for (int rr = 0; rr < nrhs; ++rr) {
+      const double2* bd;
+      double2* xd;
+      if (on_device) {
+        bd = reinterpret_cast<const double2*>(b) + (size_t)rr * pb->N;
+        xd = reinterpret_cast<double2*>(x) + (size_t)rr * pb->N;
+      } else {
+        pb->hb.alloc(vb);
+        pb->hx.alloc(vb);
+        HIP_CHECK(hipMemcpyAsync(pb->hb.p, b + rr * per, vb, hipMemcpyHostToDevice, st));
+        if (opts->x0_mode == STF_X0_USER)
+          HIP_CHECK(hipMemcpyAsync(pb->hx.p, x + rr * per, vb, hipMemcpyHostToDevice, st));
+        bd = pb->hb.as<double2>();
+        xd = pb->hx.as<double2>();
+      }
+      stf_status r = fgmres_one(pb, bd, xd, *opts, info ? info + rr : nullptr);
+      if (!on_device) {
+        HIP_CHECK(hipMemcpyAsync(x + rr * per, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+      }
+      if (r != STF_OK && worst == STF_OK) worst = r;
+    }
+    HIP_CHECK(hipGetLastError());
+  });
+  if (s != STF_OK) return s;
+  if (worst == STF_ENOCONV) pb->ctx->last_error = "FGMRES reached max_iter above tol";
+  return worst;
+}
+
+stf_status stf_problem_info(stf_problem pb, stf_plan_info* out) {
+  if (!pb || !out) return STF_EINVAL;
+  *out = plan_info(pb->plan);
+  out->device_bytes = pb->device_bytes();
+  return STF_OK;
+}
+
+void stf_problem_destroy(stf_problem pb) {
+  if (!pb) return;
+  (void)hipSetDevice(pb->ctx->device);
+  (void)hipStreamSynchronize(pb->ctx->stream);
+  delete pb;
+}
+
+}  // extern "C"

@@ -1,0 +1,264 @@
+// FP64 kernels of the flexible GMRES outer iteration: classical Gram-Schmidt
+// with one re-orthogonalisation (block dot products, then a block update),
+// norms, complex Givens rotations and the solution update x += Z y.
+//
+// Vectors are contiguous complex128 arrays of n entries; a basis V stores its
+// vectors with leading dimension ld.  Every thread owns up to EPT entries of a
+// chunk of EPT*256 consecutive entries (coalesced: entry = base + e*256 + tid),
+// keeps w in registers and walks the basis; partial sums per workgroup go to
+// a buffer reduced by a second kernel in a fixed order, so results do not
+// depend on scheduling.
+#include "cplx.h"
+#include "stf_internal.h"
+
+namespace stf {
+
+namespace {
+
+constexpr int KT = 256;
+constexpr int EPT = 8;
+constexpr int CHUNK = KT * EPT;
+constexpr int VB = 4;    // basis vectors per pass of the dot kernel
+
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int tid = threadIdx.x;
+  __syncthreads();
+  if ((tid & 63) == 0) red[tid >> 6] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(KT) void k_mdot(const double2* __restrict__ V, long long ld, int nv,
+                                             const double2* __restrict__ w, long long n,
+                                             double2* __restrict__ partial) {
+  __shared__ double red[4];
+  const long long base = (long long)blockIdx.x * CHUNK + threadIdx.x;
+  double2 wr[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    long long idx = base + (long long)e * KT;
+    wr[e] = idx < n ? w[idx] : make_double2(0.0, 0.0);
+  }
+  for (int i0 = 0; i0 < nv; i0 += VB) {
+    double2 acc[VB];
+#pragma unroll
+    for (int b = 0; b < VB; ++b) acc[b] = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < VB; ++b) {
+      if (i0 + b < nv) {
+        const double2* vi = V + (long long)(i0 + b) * ld;
+#pragma unroll
+        for (int e = 0; e < EPT; ++e) {
+          long long idx = base + (long long)e * KT;
+          if (idx < n) {
+            double2 a = vi[idx];
+            // conj(a) * w
+            acc[b].x = fma(a.x, wr[e].x, acc[b].x);
+            acc[b].x = fma(a.y, wr[e].y, acc[b].x);
+            acc[b].y = fma(a.x, wr[e].y, acc[b].y);
+            acc[b].y = fma(-a.y, wr[e].x, acc[b].y);
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < VB; ++b) {
+      double sr = block_sum(acc[b].x, red);
+      double si = block_sum(acc[b].y, red);
+      if (threadIdx.x == 0 && i0 + b < nv)
+        partial[(long long)blockIdx.x * nv + i0 + b] = make_double2(sr, si);
+    }
+  }
+}
+
+// h[i] = sum_b partial[b][i] in a fixed order.
+__global__ __launch_bounds__(KT) void k_mdot_reduce(const double2* __restrict__ partial, int nblk,
+                                                    int nv, double2* __restrict__ h) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  double sr = 0.0, si = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) {
+    double2 v = partial[(long long)b * nv + i];
+    sr += v.x;
+    si += v.y;
+  }
+  sr = block_sum(sr, red);
+  si = block_sum(si, red);
+  if (threadIdx.x == 0) h[i] = make_double2(sr, si);
+}
+
+// w -= V h; optional per-block |w|^2 partials.
+__global__ __launch_bounds__(KT) void k_mupdate(const double2* __restrict__ V, long long ld, int nv,
+                                                const double2* __restrict__ h,
+                                                double2* __restrict__ w, long long n,
+                                                double* __restrict__ norm_partial) {
+  __shared__ double red[4];
+  __shared__ double2 hs[256];
+  const long long base = (long long)blockIdx.x * CHUNK + threadIdx.x;
+  double2 wr[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    long long idx = base + (long long)e * KT;
+    wr[e] = idx < n ? w[idx] : make_double2(0.0, 0.0);
+  }
+  for (int i0 = 0; i0 < nv; i0 += 256) {
+    int cnt = nv - i0 < 256 ? nv - i0 : 256;
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) hs[threadIdx.x] = h[i0 + threadIdx.x];
+    __syncthreads();
+    for (int b = 0; b < cnt; ++b) {
+      const double2* vi = V + (long long)(i0 + b) * ld;
+      const double2 hb = hs[b];
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) {
+        long long idx = base + (long long)e * KT;
+        if (idx < n) wr[e] = cfms(vi[idx], hb, wr[e]);
+      }
+    }
+  }
+  double nr = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    long long idx = base + (long long)e * KT;
+    if (idx < n) {
+      w[idx] = wr[e];
+      nr += wr[e].x * wr[e].x + wr[e].y * wr[e].y;
+    }
+  }
+  if (norm_partial) {
+    double s = block_sum(nr, red);
+    if (threadIdx.x == 0) norm_partial[blockIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
+                                              const double* __restrict__ nrm2,
+                                              double2* __restrict__ v, long long n) {
+  const double s2 = nrm2[0];
+  const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  for (long long t = (long long)blockIdx.x * KT + threadIdx.x; t < n; t += (long long)gridDim.x * KT) {
+    double2 a = w[t];
+    v[t] = make_double2(a.x * inv, a.y * inv);
+  }
+}
+
+// One Givens step of FGMRES for column j (single thread).
+//   column j of the Hessenberg matrix: h[i] = h1[i] + h2[i] (i <= j), h[j+1] = |w|.
+//   Earlier rotations are applied, a new one zeroes h[j+1], g is rotated and
+//   est = |g[j+1]| is the residual norm of the least-squares iterate.
+__global__ void k_givens(double2* __restrict__ H, const double2* __restrict__ h1,
+                         const double2* __restrict__ h2, const double* __restrict__ wnorm2,
+                         double* __restrict__ cs, double2* __restrict__ sn,
+                         double2* __restrict__ g, int j, int ldh, double* __restrict__ est) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double2* col = H + (long long)j * ldh;
+  for (int i = 0; i <= j; ++i) col[i] = make_double2(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+  col[j + 1] = make_double2(sqrt(wnorm2[0]), 0.0);
+  for (int i = 0; i < j; ++i) {
+    double c = cs[i];
+    double2 s = sn[i];
+    double2 a = col[i], b = col[i + 1];
+    // [c, s; -conj(s), c] [a; b]
+    double2 t0 = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+    double2 t1 = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+    col[i] = t0;
+    col[i + 1] = t1;
+  }
+  double2 a = col[j], b = col[j + 1];
+  double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+  double c;
+  double2 s, r;
+  if (nb == 0.0) {
+    c = 1.0; s = make_double2(0.0, 0.0); r = a;
+  } else if (na == 0.0) {
+    c = 0.0; s = make_double2(b.x / nb, -b.y / nb); r = make_double2(nb, 0.0);
+  } else {
+    double nrm = hypot(na, nb);
+    double2 ph = make_double2(a.x / na, a.y / na);          // a / |a|
+    c = na / nrm;
+    // s = (a/|a|) conj(b) / nrm
+    s = make_double2((ph.x * b.x + ph.y * b.y) / nrm, (ph.y * b.x - ph.x * b.y) / nrm);
+    r = make_double2(ph.x * nrm, ph.y * nrm);
+  }
+  cs[j] = c;
+  sn[j] = s;
+  col[j] = r;
+  col[j + 1] = make_double2(0.0, 0.0);
+  double2 gj = g[j];
+  // g[j+1] = -conj(s) g[j]; g[j] = c g[j]
+  g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+  g[j] = make_double2(c * gj.x, c * gj.y);
+  est[0] = hypot(g[j + 1].x, g[j + 1].y);
+}
+
+__global__ void k_trisolve(const double2* __restrict__ H, const double2* __restrict__ g,
+                           double2* __restrict__ y, int k, int ldh) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  for (int i = k - 1; i >= 0; --i) {
+    double2 s = g[i];
+    for (int t = i + 1; t < k; ++t) s = cfms(H[(long long)t * ldh + i], y[t], s);
+    y[i] = cdiv(s, H[(long long)i * ldh + i]);
+  }
+}
+
+__global__ __launch_bounds__(KT) void k_xupdate(const double2* __restrict__ Z, long long ld, int k,
+                                                const double2* __restrict__ y,
+                                                double2* __restrict__ x, long long n) {
+  __shared__ double2 ys[256];
+  if ((int)threadIdx.x < k) ys[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  for (long long t = (long long)blockIdx.x * KT + threadIdx.x; t < n; t += (long long)gridDim.x * KT) {
+    double2 acc = x[t];
+    for (int i = 0; i < k; ++i) acc = cfma(Z[(long long)i * ld + t], ys[i], acc);
+    x[t] = acc;
+  }
+}
+
+int grid_for(long long n) {
+  long long g = (n + KT - 1) / KT;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+}  // namespace
+
+int krylov_blocks(long long n) { return (int)((n + CHUNK - 1) / CHUNK); }
+
+void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const double2* w,
+                 long long n, double2* partial) {
+  hipLaunchKernelGGL(k_mdot, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, w, n, partial);
+}
+
+void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk, nv, h);
+}
+
+void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
+                    double2* w, long long n, double* norm_partial) {
+  hipLaunchKernelGGL(k_mupdate, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, h, w, n,
+                     norm_partial);
+}
+
+void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n);
+}
+
+void launch_givens(hipStream_t st, double2* H, double2* h1, double2* h2, const double* wnorm2,
+                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out) {
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h1, h2, wnorm2, cs, sn, g, j, ldh,
+                     est_out);
+}
+
+void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
+                     int ldh) {
+  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, st, H, g, y, k, ldh);
+}
+
+void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
+                    double2* x, long long n) {
+  hipLaunchKernelGGL(k_xupdate, dim3(grid_for(n)), dim3(KT), 0, st, Z, ld, k, y, x, n);
+}
+
+}  // namespace stf

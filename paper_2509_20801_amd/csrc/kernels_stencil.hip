@@ -1,0 +1,132 @@
+// Global FP64 operator kernels: node permittivity (Eq. (3)) and the five-point
+// SC-PML stencil (Eqs. (2) and (9)), plus reductions.
+//
+// Layout: node arrays row-major [ny][nx] of double2 (complex128), x fastest.
+// The operator is stored implicitly: keps[n] = k0^2 eps_bar(n) per node and four
+// 1D coupling arrays (x: w, e per column; y: w, e per row), so one apply reads
+// x (16 B) + keps (16 B) and writes y (16 B) per node; the five x reads of a
+// node's stencil come from cache.  Blocks are 64 x 4 nodes so a wavefront reads
+// one contiguous 1 KiB row segment.
+#include "cplx.h"
+#include "stf_internal.h"
+
+namespace stf {
+
+namespace {
+
+constexpr int SBX = 64, SBY = 4;
+
+__global__ __launch_bounds__(256) void k_node_keps(const double2* __restrict__ cells,
+                                                   double2* __restrict__ keps, int nx, int ny,
+                                                   double k0sq) {
+  int i = blockIdx.x * SBX + threadIdx.x;
+  int j = blockIdx.y * SBY + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  long long w = nx + 1;
+  // Node (i, j) touches cells (i, j), (i+1, j), (i, j+1), (i+1, j+1).
+  double2 a = cells[(long long)j * w + i], b = cells[(long long)j * w + i + 1];
+  double2 c = cells[(long long)(j + 1) * w + i], d = cells[(long long)(j + 1) * w + i + 1];
+  double2 s = make_double2(0.25 * ((a.x + b.x) + (c.x + d.x)), 0.25 * ((a.y + b.y) + (c.y + d.y)));
+  keps[(long long)j * nx + i] = make_double2(k0sq * s.x, k0sq * s.y);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_stencil(const double2* __restrict__ x,
+                                                 const double2* __restrict__ b,
+                                                 double2* __restrict__ y,
+                                                 const double2* __restrict__ keps,
+                                                 const double2* __restrict__ cxw,
+                                                 const double2* __restrict__ cxe,
+                                                 const double2* __restrict__ cyw,
+                                                 const double2* __restrict__ cye, int nx, int ny,
+                                                 double* __restrict__ partial) {
+  int i = blockIdx.x * SBX + threadIdx.x;
+  int j = blockIdx.y * SBY + threadIdx.y;
+  double loc = 0.0;
+  if (i < nx && j < ny) {
+    long long n = (long long)j * nx + i;
+    double2 aw = cxw[i], ae = cxe[i], as = cyw[j], an = cye[j];
+    double2 ke = keps[n];
+    // Diagonal: k0^2 eps_bar minus all four couplings (Dirichlet neighbours included).
+    double2 dg = make_double2(ke.x - ((aw.x + ae.x) + (as.x + an.x)),
+                              ke.y - ((aw.y + ae.y) + (as.y + an.y)));
+    double2 acc = cmul(dg, x[n]);
+    if (i > 0) acc = cfma(aw, x[n - 1], acc);
+    if (i < nx - 1) acc = cfma(ae, x[n + 1], acc);
+    if (j > 0) acc = cfma(as, x[n - nx], acc);
+    if (j < ny - 1) acc = cfma(an, x[n + nx], acc);
+    if (MODE == 0) {
+      y[n] = acc;
+    } else {
+      double2 r = csub(b[n], acc);
+      y[n] = r;
+      loc = r.x * r.x + r.y * r.y;
+    }
+  }
+  if (MODE == 1) {
+    __shared__ double red[4];
+    int tid = threadIdx.y * SBX + threadIdx.x;
+    double s = wave_sum(loc);
+    if ((tid & 63) == 0) red[tid >> 6] = s;
+    __syncthreads();
+    if (tid == 0) partial[blockIdx.y * gridDim.x + blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ partial, int n,
+                                                    double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) s += partial[t];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ a, long long n,
+                                                      int* __restrict__ flag) {
+  long long t = (long long)blockIdx.x * 256 + threadIdx.x;
+  int bad = 0;
+  for (; t < n; t += (long long)gridDim.x * 256) bad |= !isfinite(a[t]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
+}
+
+}  // namespace
+
+void launch_node_keps(hipStream_t st, const double2* cells, double2* keps, int nx, int ny,
+                      double k0sq) {
+  dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
+  hipLaunchKernelGGL(k_node_keps, grd, blk, 0, st, cells, keps, nx, ny, k0sq);
+}
+
+int stencil_partial_blocks(int nx, int ny) {
+  return ((nx + SBX - 1) / SBX) * ((ny + SBY - 1) / SBY);
+}
+
+void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b, double2* y,
+                    const double2* keps, const double2* cxw, const double2* cxe,
+                    const double2* cyw, const double2* cye, int nx, int ny, double* partial,
+                    int* nblocks_out) {
+  dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
+  if (mode == 0)
+    hipLaunchKernelGGL(k_stencil<0>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
+                       partial);
+  else
+    hipLaunchKernelGGL(k_stencil<1>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
+                       partial);
+  if (nblocks_out) *nblocks_out = grd.x * grd.y;
+}
+
+void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out) {
+  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partial, n, out);
+}
+
+void launch_check_finite(hipStream_t st, const double* a, long long n, int* flag) {
+  long long g = (n + 255) / 256;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)g), dim3(256), 0, st, a, n, flag);
+}
+
+}  // namespace stf

@@ -1,0 +1,211 @@
+// Internal declarations of the stfdfd library (host plans, device layouts, launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <complex>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/stfdfd.h"
+
+namespace stf {
+
+using cd = std::complex<double>;
+
+struct Error : std::runtime_error {
+  stf_status code;
+  Error(stf_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define STF_REQUIRE(cond, msg)                                        \
+  do {                                                                \
+    if (!(cond)) throw ::stf::Error(STF_EINVAL, std::string(msg));    \
+  } while (0)
+
+#define HIP_CHECK(expr)                                                                    \
+  do {                                                                                     \
+    hipError_t e_ = (expr);                                                                \
+    if (e_ != hipSuccess)                                                                  \
+      throw ::stf::Error(e_ == hipErrorOutOfMemory ? STF_ENOMEM : STF_EDEVICE,             \
+                         std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Host plan: stretch arrays, partition, nested dissection (host_plan.cpp)
+// ---------------------------------------------------------------------------
+
+// 1D coupling coefficients of one axis of a domain: w[t] couples node t to t-1,
+// e[t] couples t to t+1 (Eq. (9) discretised: 1/(d^2 s[t] s[t -/+ 1/2])).
+struct AxisCoef {
+  std::vector<cd> w, e;
+};
+
+struct SubDesc {
+  int kx, ky;
+  int ox0, oy0, nxl, nyl;   // Omega_k: global node box [ox0, ox0+nxl) x [oy0, oy0+nyl)
+  int ix0, ix1, iy0, iy1;   // I_k (global node ranges, half-open)
+  AxisCoef cx, cy;          // local coupling coefficients
+  int shape;                // index of the symbolic plan
+};
+
+// One front of the nested-dissection elimination tree of a local grid.
+struct SymFront {
+  int p = 0, q = 0;         // separator (fully summed) size, update-set size
+  int parent = -1;          // index in the shape's front list
+  int depth = 0;            // root = 0
+  int var_off = 0;          // vars[var_off .. var_off+p+q): local node ids, separator first
+  int cmap_off = 0;         // cmap[cmap_off .. +q): position of each update var in the parent front
+  int ent_off = 0, ent_cnt = 0;   // original matrix entries assembled into this front
+  int child_off = 0, nchild = 0;  // children[child_off ..)
+};
+
+// Packed original entry: front row, front column, local node, stencil direction.
+// dir: 0 centre, 1 west (t-1), 2 east (t+1), 3 south (u-1), 4 north (u+1); the value
+// is row `node`'s coefficient towards its neighbour in that direction.
+struct SymEntry {
+  int32_t rc;      // row | (col << 16)
+  int32_t nd;      // node * 8 + dir
+};
+
+struct SymShape {
+  int nxl = 0, nyl = 0, leaf = 0;
+  std::vector<SymFront> fronts;    // preorder (parents before children)
+  std::vector<int> vars, cmap, children;
+  std::vector<SymEntry> ents;
+  int max_depth = 0, max_front = 0;
+  int64_t factor_entries = 0, front_entries = 0, vec_entries = 0;
+  double lu_flops = 0.0;
+};
+
+struct GlobalAxes {
+  std::vector<cd> sx, sxh, sy, syh;   // s at nodes, s at half points i-1/2 (n+1 entries)
+  AxisCoef cx, cy;
+};
+
+struct Plan {
+  stf_params prm;
+  GlobalAxes g;
+  std::vector<SubDesc> subs;
+  std::vector<std::shared_ptr<const SymShape>> shapes;
+  // Per-axis cover tables for the sum of local fields: for global index g, up to two
+  // (block, local coordinate) pairs; block -1 = none.
+  std::vector<int4> cover_x, cover_y;
+};
+
+void validate_params(const stf_params& p);
+stf_params normalized(const stf_params& p);
+GlobalAxes build_global_axes(const stf_params& p);
+std::vector<SubDesc> build_partition(const stf_params& p, const GlobalAxes& g);
+std::shared_ptr<SymShape> build_symbolic(int nxl, int nyl, int leaf);
+void build_cover(const stf_params& p, const std::vector<SubDesc>& subs, std::vector<int4>& cx,
+                 std::vector<int4>& cy);
+// Builds the whole host plan; shape_cache (may be null) memoises symbolic plans.
+Plan build_plan(const stf_params& p,
+                std::map<std::tuple<int, int, int>, std::shared_ptr<const SymShape>>* shape_cache);
+stf_plan_info plan_info(const Plan& pl);
+
+// ---------------------------------------------------------------------------
+// Device layouts (shared by host launch code and kernels)
+// ---------------------------------------------------------------------------
+
+struct SubDev {
+  int ox0, oy0, nxl, nyl;
+  int ix0, ix1, iy0, iy1;
+  int cx_off, cy_off;       // offsets of (w, e) pairs in the local coefficient arrays
+  long long u_off;          // offset of the local field (nxl*nyl elements)
+};
+
+struct FrontDev {
+  long long fac_off;        // element offset of the m x m front (row-major)
+  int vec_off;              // element offset of the front vector (m elements)
+  int piv_off;              // offset of the p pivot indices
+  int p, q;
+  int sub;                  // subdomain
+  int var_off, cmap_off;    // into the concatenated vars / cmap arrays
+  int ent_off, ent_cnt;     // into the concatenated entries
+  int parent;               // instance index or -1
+  int child_off, nchild;    // into the instance children array
+  int pad;
+};
+
+// Kernel classes for timing (match STF_K_* in stfdfd.h).
+enum KClass {
+  K_ASSEMBLE = STF_K_ASSEMBLE, K_STENCIL = STF_K_STENCIL, K_FRONT_ASM = STF_K_FRONT_ASM,
+  K_FRONT_LU = STF_K_FRONT_LU, K_SWEEP_FWD = STF_K_SWEEP_FWD, K_SWEEP_BWD = STF_K_SWEEP_BWD,
+  K_SCATTER = STF_K_SCATTER, K_ARNOLDI = STF_K_ARNOLDI, K_UPDATE = STF_K_UPDATE
+};
+
+// ---------------------------------------------------------------------------
+// Launchers (kernels_*.hip).  All are asynchronous on `st`.
+// ---------------------------------------------------------------------------
+
+// node k0^2 * eps_bar from the cell map (Eq. (3)).
+void launch_node_keps(hipStream_t st, const double2* cells, double2* keps, int nx, int ny,
+                      double k0sq);
+// y = A x  (mode 0) or r = b - A x with per-block partial |r|^2 (mode 1).
+void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b, double2* y,
+                    const double2* keps, const double2* cxw, const double2* cxe,
+                    const double2* cyw, const double2* cye, int nx, int ny, double* partial,
+                    int* nblocks_out);
+int stencil_partial_blocks(int nx, int ny);
+// out[0] = sum partial[0..n)  (single block, fixed order).
+void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out);
+// nonzero flag if any of n doubles is not finite (flag must be zeroed first).
+void launch_check_finite(hipStream_t st, const double* a, long long n, int* flag);
+
+// Multifrontal, per tree level; T = double2 (c128) or float2 (c64).
+struct LevelArgs {
+  const FrontDev* fronts;       // instance descriptors
+  const int* level_list;        // fronts of this level
+  int nlevel;                   // number of fronts in the level
+  const SubDev* subs;
+  const int* vars;
+  const int* cmap;
+  const SymEntry* ents;
+  const int* children;
+  const double2* keps;          // global k0^2 eps_bar
+  const double2* lcoef;         // local coupling coefficients
+  int nx;                       // global nx
+  int max_m;                    // largest front in the level
+};
+template <typename T>
+void launch_front_assemble(hipStream_t st, const LevelArgs& a, T* fac);
+template <typename T>
+void launch_front_lu(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag,
+                     double tau);
+template <typename T>
+void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
+                      const double2* v);
+template <typename T>
+void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* fac, T* vec, T* u);
+template <typename T>
+void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
+                    const int4* cover_y, int px, int nx, int ny, double2* z);
+
+// Krylov (kernels_krylov.hip).  Vectors of n complex doubles; V holds nv vectors
+// with leading dimension ld (elements).
+int krylov_blocks(long long n);
+void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const double2* w,
+                 long long n, double2* partial);
+void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h);
+void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
+                    double2* w, long long n, double* norm_partial);
+void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v,
+                  long long n);
+// Givens step j of FGMRES on device (single thread).  H column-major (ldh = m+1).
+void launch_givens(hipStream_t st, double2* H, double2* h1, double2* h2, const double* wnorm2,
+                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out);
+// y = R^{-1} g (k x k upper triangular, column-major ldh).
+void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
+                     int ldh);
+// x += Z y
+void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
+                    double2* x, long long n);
+
+}  // namespace stf

@@ -1,0 +1,181 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Tolerances:
+  * stencil y = A x (FP64, same formula, different summation order): 1e-14 rel;
+  * one source-transfer round with complex128 fronts: 1e-12 rel (direct solves of
+    the local systems, condition numbers ~1e4);
+  * the same with complex64 fronts: 2e-4 rel (FP32 rounding, 6e-8, times the
+    local condition number and growth);
+  * FGMRES solutions: 1e-10 rel-L2 (plain FP64 path at rel-res 1e-12) and 1e-8
+    (complex64 fronts, FP64 outer iteration at rel-res 1e-10).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import ddm, fdfd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stf():
+    import paper_2509_20801_amd as stf
+    return stf
+
+
+@pytest.fixture(scope="module")
+def ctx(stf):
+    return stf.Context(0)
+
+
+def _prm(w, **over):
+    p = w.params()
+    d = dict(nx=p["nx"], ny=p["ny"], k0=p["k0"], dx=p["dx"], dy=p["dy"], pml=p["pml"],
+             pml_order=p["pml_order"], pml_R=p["pml_R"], px=p["px"], py=p["py"],
+             overlap=p["overlap"], local_pml=p["local_pml"],
+             local_pml_order=p["local_pml_order"], local_pml_R=p["local_pml_R"])
+    d.update(over)
+    return d
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+CASES = {
+    "small": lambda: workloads.configs.small_random(nx=48, ny=40, pml=6, px=2, py=2, overlap=2,
+                                                    local_pml=6, seed=3),
+    "ragged": lambda: workloads.configs.small_random(nx=71, ny=53, pml=5, px=3, py=2, overlap=3,
+                                                     local_pml=5, seed=4),
+    "c1": lambda: workloads.configs.cylinder_tfsf(),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_stencil_matches_oracle(stf, ctx, case):
+    w = CASES[case]()
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    x = workloads.sources.random_field(w.nx, w.ny, 11)
+    y = pb.apply(x)
+    assert _rel(y, A @ x.ravel()) < 1e-14
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("leaf", [0, 4, 64])
+def test_round_c128_matches_oracle(stf, ctx, case, leaf):
+    w = CASES[case]()
+    pb = stf.Problem(ctx, _prm(w, leaf_size=leaf), w.eps_cells)
+    assert pb.factor() is False
+    B = ddm.SourceTransfer(w.params(), w.eps_cells)
+    v = workloads.sources.random_field(w.nx, w.ny, 12)
+    z = pb.precond(v)
+    assert _rel(z, B.apply(v.ravel())) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["small", "c1"])
+def test_round_c64_matches_oracle(stf, ctx, case):
+    w = CASES[case]()
+    pb = stf.Problem(ctx, _prm(w, front_prec=stf.STF_C64), w.eps_cells)
+    pb.factor()
+    B = ddm.SourceTransfer(w.params(), w.eps_cells)
+    v = workloads.sources.random_field(w.nx, w.ny, 13)
+    assert _rel(pb.precond(v), B.apply(v.ravel())) < 2e-4
+
+
+def test_single_subdomain_round_is_inverse(stf, ctx):
+    w = workloads.configs.small_random(nx=40, ny=36, pml=6, px=1, py=1, seed=5)
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    pb.factor()
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    b = w.b[0]
+    z = pb.precond(b)
+    assert fdfd.relres(A, z.ravel(), b.ravel()) < 1e-13
+    x, info = pb.solve(b, tol=1e-12)
+    assert info[0]["iters"] == 1 and info[0]["relres_true"] < 1e-12
+
+
+def test_c1_solve_plain_fp64(stf, ctx):
+    """Config 1 (plain method, complex128): FGMRES to rel-res 1e-12 equals the
+    global direct solve to 1e-10."""
+    w = workloads.configs.cylinder_tfsf()
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    pb.factor()
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    b = w.b[0]
+    xref = fdfd.solve_direct(A, b.ravel())
+    x, info = pb.solve(b, tol=1e-12, restart=30)
+    assert info[0]["status"] == 0 and info[0]["iters"] <= 15
+    assert _rel(x, xref) < 1e-10
+    assert fdfd.relres(A, x.ravel(), b.ravel()) < 1e-12
+    # The residual history starts at |b - A x0| / |b| = 1 and ends below tol.
+    h = info[0]["history"]
+    assert abs(h[0] - 1.0) < 1e-12 and h[-1] < 1e-12
+
+
+def test_c1_solve_mixed_c64(stf, ctx):
+    w = workloads.configs.cylinder_tfsf()
+    pb = stf.Problem(ctx, _prm(w, front_prec=stf.STF_C64), w.eps_cells)
+    pb.factor()
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    b = w.b[0]
+    xref = fdfd.solve_direct(A, b.ravel())
+    x, info = pb.solve(b, tol=1e-10, restart=30)
+    assert info[0]["status"] == 0
+    assert _rel(x, xref) < 1e-8
+
+
+def test_device_buffers_and_multiple_rhs(stf, ctx):
+    import torch
+    w = workloads.configs.small_random(nx=64, ny=48, pml=6, px=2, py=2, overlap=2, local_pml=6,
+                                       seed=6, nrhs=3)
+    eps = torch.from_numpy(w.eps_cells).cuda()
+    pb = stf.Problem(ctx, _prm(w), eps)
+    pb.factor()
+    bd = torch.from_numpy(w.b).cuda()
+    xd, info = pb.solve(bd, tol=1e-12)
+    torch.cuda.synchronize()
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    for r in range(3):
+        xref = fdfd.solve_direct(A, w.b[r].ravel())
+        assert _rel(xd[r].cpu().numpy(), xref) < 1e-10
+        assert info[r]["status"] == 0
+
+
+def test_user_initial_guess_resumes(stf, ctx):
+    """A solve stopped early and resumed from its iterate (x0 = USER) reaches the
+    same answer."""
+    w = workloads.configs.small_random(nx=60, ny=50, pml=6, px=2, py=2, overlap=2, local_pml=6,
+                                       seed=7)
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    pb.factor()
+    b = w.b[0]
+    x1, i1 = pb.solve(b, tol=1e-12, max_iter=2)
+    assert i1[0]["status"] == 6      # STF_ENOCONV
+    x2, i2 = pb.solve(b, tol=1e-12, x0=x1)
+    assert abs(i2[0]["relres_x0"] - i1[0]["relres_true"]) < 1e-12
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    assert _rel(x2, fdfd.solve_direct(A, b.ravel())) < 1e-10
+
+
+def test_errors(stf, ctx):
+    w = workloads.configs.small_random(nx=40, ny=36, pml=6, px=2, py=2, overlap=2, local_pml=6)
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    with pytest.raises(stf.StfError) as e:
+        pb.solve(w.b[0])
+    assert e.value.status == 4           # STF_ESTATE: solve before factor
+    pb.factor()
+    bad = w.b[0].copy()
+    bad[3, 4] = np.nan
+    with pytest.raises(stf.StfError) as e:
+        pb.solve(bad)
+    assert e.value.status == 1           # STF_EINVAL: non-finite source
+    cells = w.eps_cells.copy()
+    cells[0, 0] = np.inf
+    with pytest.raises(stf.StfError) as e:
+        stf.Problem(ctx, _prm(w), cells)
+    assert e.value.status == 1
+    # Zero source: zero field, no iterations.
+    x, info = pb.solve(np.zeros_like(w.b[0]))
+    assert np.all(x == 0) and info[0]["iters"] == 0
