@@ -1,0 +1,198 @@
+"""Throughput benchmark: DoF/s to FP64 true rel-res 1e-8 on one MI355X.
+
+Workload: random metasurface on a 1024 x 1024 interior with a 20-cell PML
+(1064 x 1064 = 1,132,096 DoF), lambda = 30 cells, 64 pillars (eps 12.25) on an
+eps 2.13 substrate, current-sheet source, 8 x 8 overlapping subdomains
+(overlap 8 + 16-cell local PML), seed 2.  Inputs are synthetic and resident in
+HBM before timing starts.
+
+One step = the whole hot path on one problem: node permittivity assembly,
+numeric multifrontal factorisation of all 64 subdomains, and the FGMRES solve
+(FP64 outer iteration, one source-transfer round per preconditioner
+application) until the FP64 true relative residual is <= 1e-8.  The timed
+form uses complex64 fronts ("mixed"); the plain complex128 form is timed too
+and reported beside it.
+
+Prints one JSON line (see the design doc for the roofline and baseline definitions).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoF/s to rel-res 1e-8: mixed+batched+learned vs plain FP64 DDM, 1 GPU"
+PEAK = {"hbm": 8000.0, "fp32_mfma": 157.3, "fp64": 78.6}   # GB/s, TFLOP/s
+
+
+def workload():
+    import workloads
+    return workloads.configs.metasurface_sheet()
+
+
+def params_of(w, prec, leaf=0):
+    p = w.params()
+    return dict(nx=p["nx"], ny=p["ny"], k0=p["k0"], pml=p["pml"], pml_order=p["pml_order"],
+                pml_R=p["pml_R"], px=p["px"], py=p["py"], overlap=p["overlap"],
+                local_pml=p["local_pml"], local_pml_order=p["local_pml_order"],
+                local_pml_R=p["local_pml_R"], front_prec=prec, leaf_size=leaf)
+
+
+def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, timing):
+    eps = torch.from_numpy(w.eps_cells).cuda()
+    b = torch.from_numpy(w.b[0]).cuda()
+    x = torch.empty_like(b)
+    pb = stf.Problem(ctx, params_of(w, prec), eps)
+    infos = []
+
+    def step():
+        pb.assemble(eps)
+        pb.factor()
+        _, inf = pb.solve(b, x=x, tol=tol, restart=restart, max_iter=max_iter)
+        infos.append(inf[0])
+
+    for _ in range(warmup):
+        step()
+    infos.clear()
+    ctx.set_timing(timing)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    stats = {}
+    if timing:
+        for k, name in enumerate(stf.KERNEL_CLASSES):
+            stats[name] = ctx.kernel_stats(k)
+        ctx.set_timing(False)
+    info = pb.info()
+    pb.close()
+    return (t1 - t0) / steps, infos, stats, info
+
+
+def roofline(stf, w, prec, infos, stats, steps):
+    """Roofline of the kernel class with the largest summed time."""
+    ref = stf.plan_query(params_of(w, prec, leaf=4))     # fine nested dissection reference
+    es = 8 if prec == stf.STF_C64 else 16
+    N = w.nx * w.ny
+    iters = sum(i["iters"] for i in infos)
+    cycles = sum(i["restarts"] for i in infos)
+    units = {
+        # algorithmic work per step summed over the timed steps
+        "front_lu": ("mfma", ref["lu_flops"] * steps / 1e12),                # TFLOP
+        "sweep_fwd": ("hbm", ref["factor_entries"] / 2 * es * iters / 1e9),  # GB
+        "sweep_bwd": ("hbm", ref["factor_entries"] / 2 * es * iters / 1e9),
+        "stencil": ("hbm", N * (48 * iters + 64 * (cycles + steps)) / 1e9),
+    }
+    dom = max(stats, key=lambda k: stats[k][0])
+    ms, launches = stats[dom]
+    if dom not in units:
+        return dom, None
+    bound, work = units[dom]
+    per_launch = work / launches
+    avg_s = ms / launches / 1e3
+    achieved = per_launch / avg_s
+    if bound == "mfma":
+        peak = PEAK["fp32_mfma"] if prec == stf.STF_C64 else PEAK["fp64"]
+        unit = "TFLOP/s"
+    else:
+        peak, unit = PEAK["hbm"], "GB/s"
+    return dom, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
+                 "avg_launch_ms": round(ms / launches, 4), "launches": launches}
+
+
+def cpu_baseline(w, gpu_iters, restart):
+    """Oracle (NumPy/SciPy, one thread) on a bounded sample of the same workload:
+    SuperLU factorisations of 16 of the 64 subdomains (all four shapes) and
+    3 full-size FGMRES iterations, extrapolated to 64 subdomains and to the GPU
+    run's iteration count."""
+    import numpy as np
+    import scipy.sparse.linalg as spla
+    from threadpoolctl import threadpool_limits
+    from oracle import ddm, fdfd, krylov
+    with threadpool_limits(limits=1):
+        p = w.params()
+        t0 = time.perf_counter()
+        A = fdfd.global_matrix(p, w.eps_cells)
+        subs = ddm.partition(p)
+        gax = fdfd.global_axes(p)
+        t_asm = time.perf_counter() - t0
+        pick = [s for s in subs if (s.kx in (0, 3, 4, 7) and s.ky in (0, 3, 4, 7))]
+        t0 = time.perf_counter()
+        for s in pick:
+            spla.splu(ddm.local_matrix(p, w.eps_cells, s, gax).tocsc())
+        t_fac = (time.perf_counter() - t0) * len(subs) / len(pick)
+        B = ddm.SourceTransfer(p, w.eps_cells)          # full factors for the iteration sample
+        b = w.b[0].ravel()
+        k = 3
+        t0 = time.perf_counter()
+        krylov.fgmres(lambda v: A @ v, b, B.apply, tol=0.0, restart=max(restart, k), max_iter=k)
+        t_it = (time.perf_counter() - t0) / k
+    total = t_asm + t_fac + gpu_iters * t_it
+    return {"value": round(w.nx * w.ny / total, 1), "unit": "DoF/s", "cores": 1, "kind": "oracle",
+            "sample": "SuperLU factors of 16/64 subdomains + 3 full-size FGMRES iterations, "
+                      "extrapolated to 64 subdomains and %d iterations (%.1f s est.)" % (gpu_iters, total)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--max-iter", type=int, default=400)
+    ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP event timing")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the complex128 reference form")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X "
+              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_2509_20801_amd as stf
+
+    w = workload()
+    ctx = stf.Context(0)
+    t_mixed, inf_mixed, stats, info = run_form(stf, torch, ctx, w, stf.STF_C64, args.steps,
+                                              args.warmup, args.tol, args.restart, args.max_iter,
+                                              not args.no_timing)
+    ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in inf_mixed)
+    N = w.nx * w.ny
+    out = {"metric": METRIC, "value": round(N / t_mixed, 1), "unit": "DoF/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t_mixed * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "c64 fronts + f64 Krylov", "data": "synthetic",
+           "config": {"workload": "metasurface 1064x1064 (1024^2 + 20-cell PML), 64 pillars, "
+                                  "current sheet, 8x8 subdomains, overlap 8 + local PML 16",
+                      "ndof": N, "form": "mixed (complex64 fronts, FP64 FGMRES)",
+                      "restart": args.restart, "tol": args.tol, "parallelism": "1 GPU"},
+           "iters": inf_mixed[0]["iters"], "relres_true": inf_mixed[0]["relres_true"],
+           "converged": ok}
+    if stats:
+        dom, rl = roofline(stf, w, stf.STF_C64, inf_mixed, stats, args.steps)
+        out["roofline"] = rl
+        out["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in stats.items()}
+    if not args.no_plain:
+        t_plain, inf_plain, _, _ = run_form(stf, torch, ctx, w, stf.STF_C128, 1, 1, args.tol,
+                                            args.restart, args.max_iter, False)
+        out["plain_fp64"] = {"value": round(N / t_plain, 1), "ms_per_step": round(t_plain * 1e3, 3),
+                             "iters": inf_plain[0]["iters"]}
+        out["speedup_vs_plain"] = round(t_plain / t_mixed, 3)
+    out["device_bytes"] = info["device_bytes"]
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, inf_mixed[0]["iters"], args.restart)
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -11,7 +11,9 @@ buffers used in place on the context's stream.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
+import weakref
 
 import numpy as np
 
@@ -106,6 +108,17 @@ def debug_local_axes(prm, k):
                 cw=cw, ce=ce, cs=cs, cn=cn)
 
 
+_live_contexts = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # Release device state while the HIP runtime is still alive (Python's own
+    # finalisation order of leftover objects is arbitrary).
+    for c in list(_live_contexts):
+        c.close()
+
+
 class Context:
     """Device context.  stream: a hipStream_t handle (int) or a torch stream; by
     default the current torch stream of `device` (so torch and library work are
@@ -124,12 +137,18 @@ class Context:
         h = C.c_void_p()
         st = self._lib.stf_ctx_create(int(device), C.c_void_p(int(stream) or None), C.byref(h))
         if st != 0:
-            raise StfError(st, "stf_ctx_create failed")
+            msg = self._lib.stf_last_error(None)
+            raise StfError(st, "stf_ctx_create: " + (msg.decode() if msg else ""))
         self.handle = h
         self.device = device
+        self._problems = weakref.WeakSet()
+        _live_contexts.add(self)
 
     def close(self):
+        """Destroy the context and every problem created on it (problems first)."""
         if getattr(self, "handle", None):
+            for pb in list(self._problems):
+                pb.close()
             self._lib.stf_ctx_destroy(self.handle)
             self.handle = None
 
@@ -164,11 +183,14 @@ class Problem:
         _check(ctx.handle, self._lib.stf_problem_create(ctx.handle, C.byref(self.params), ptr, dev,
                                                         C.byref(h)))
         self.handle = h
+        ctx._problems.add(self)
 
     def close(self):
-        if getattr(self, "handle", None):
+        # A problem must be destroyed before its context; closing the context
+        # closes its problems, so a problem whose context is gone is already freed.
+        if getattr(self, "handle", None) and getattr(self.ctx, "handle", None):
             self._lib.stf_problem_destroy(self.handle)
-            self.handle = None
+        self.handle = None
 
     def __del__(self):
         try:

@@ -71,9 +71,18 @@ _lib = None
 
 
 def load():
-    """Load the HIP library; raises if it has not been built (there is no fallback)."""
+    """Load the HIP library; raises if it has not been built (there is no fallback).
+
+    PyTorch (when installed) is imported first: its wheel carries its own HIP
+    runtime, and loading ours first would put two HIP runtimes in one process.
+    With torch loaded, the library binds to the runtime torch already holds.
+    """
     global _lib
     if _lib is None:
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libstfdfd.so is not built; run `python -m paper_2509_20801_amd.build`")
         lib = C.CDLL(LIB_PATH)

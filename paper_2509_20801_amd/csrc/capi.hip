@@ -95,6 +95,9 @@ struct stf_ctx_s {
 
 namespace {
 
+// Message of the last failure that happened without a context (stf_ctx_create).
+thread_local std::string g_noctx_error;
+
 // Brackets one kernel launch with events when timing is on.
 struct Timed {
   stf_ctx c;
@@ -606,7 +609,8 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
   } catch (...) {
     return STF_ENOMEM;
   }
-  stf_status s = guard(nullptr, [&] {
+  g_noctx_error.clear();
+  stf_status s = guard(c, [&] {
     int n = 0;
     HIP_CHECK(hipGetDeviceCount(&n));
     STF_REQUIRE(device >= 0 && device < n, "device index out of range");
@@ -621,6 +625,7 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
     HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault));
   });
   if (s != STF_OK) {
+    g_noctx_error = c->last_error;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
     return s;
@@ -645,7 +650,7 @@ void stf_ctx_destroy(stf_ctx c) {
 }
 
 const char* stf_last_error(stf_ctx c) {
-  if (!c) return "null context";
+  if (!c) return g_noctx_error.empty() ? "null context" : g_noctx_error.c_str();
   return c->last_error.c_str();
 }
 
