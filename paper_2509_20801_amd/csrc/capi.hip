@@ -386,15 +386,8 @@ int factor_t(stf_problem pb) {
   HIP_CHECK(hipMemsetAsync(pb->flag.p, 0, sizeof(int), st));
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
   for (int d = pb->max_depth; d >= 0; --d) {
-    LevelArgs a = pb->level_args(d);
-    {
-      Timed t(pb->ctx, K_FRONT_ASM);
-      launch_front_assemble<T>(st, a, fac);
-    }
-    {
-      Timed t(pb->ctx, K_FRONT_LU);
-      launch_front_lu<T>(st, a, fac, pb->piv.as<int>(), pb->flag.as<int>(), tau);
-    }
+    Timed t(pb->ctx, K_FRONT_LU);
+    launch_front_factor<T>(st, pb->level_args(d), fac, pb->piv.as<int>(), pb->flag.as<int>(), tau);
   }
   HIP_CHECK(hipGetLastError());
   int h = 0;

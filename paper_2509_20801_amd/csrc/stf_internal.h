@@ -174,11 +174,11 @@ struct LevelArgs {
   int nx;                       // global nx
   int max_m;                    // largest front in the level
 };
+// Assembly (original entries + extend-add of the children) and partial LU of
+// every front of one level.
 template <typename T>
-void launch_front_assemble(hipStream_t st, const LevelArgs& a, T* fac);
-template <typename T>
-void launch_front_lu(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag,
-                     double tau);
+void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag,
+                         double tau);
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
                       const double2* v);
