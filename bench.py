@@ -43,17 +43,18 @@ def params_of(w, prec, leaf=0):
                 local_pml_R=p["local_pml_R"], front_prec=prec, leaf_size=leaf)
 
 
-def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, timing):
+def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, timing, leaf=0,
+             rounds=1):
     eps = torch.from_numpy(w.eps_cells).cuda()
     b = torch.from_numpy(w.b[0]).cuda()
     x = torch.empty_like(b)
-    pb = stf.Problem(ctx, params_of(w, prec), eps)
+    pb = stf.Problem(ctx, params_of(w, prec, leaf), eps)
     infos = []
 
     def step():
         pb.assemble(eps)
         pb.factor()
-        _, inf = pb.solve(b, x=x, tol=tol, restart=restart, max_iter=max_iter)
+        _, inf = pb.solve(b, x=x, tol=tol, restart=restart, max_iter=max_iter, rounds=rounds)
         infos.append(inf[0])
 
     for _ in range(warmup):
@@ -147,7 +148,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--restart", type=int, default=60)
+    ap.add_argument("--restart", type=int, default=20)
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP event timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")

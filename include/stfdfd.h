@@ -77,7 +77,7 @@ typedef struct {
   int32_t local_pml_order;
   double  local_pml_R;
   int32_t front_prec;        /* STF_C128 or STF_C64 */
-  int32_t leaf_size;         /* largest leaf box (nodes) of the nested dissection; 0 = 16 */
+  int32_t leaf_size;         /* largest leaf box (nodes) of the nested dissection; 0 = 32 */
 } stf_params;
 
 typedef struct {
@@ -85,7 +85,9 @@ typedef struct {
   int32_t restart;    /* FGMRES cycle length m (1..200) */
   int32_t max_iter;   /* total inner iterations (>= 1) */
   int32_t x0_mode;    /* STF_X0_ZERO or STF_X0_USER (x holds the guess on entry) */
-  int32_t reserved0;
+  int32_t rounds;     /* source-transfer rounds per preconditioner application (0 or 1 = one
+                         round z = B v; r > 1 adds r-1 stationary corrections
+                         z += B (v - A z), i.e. r Jacobi rounds of Algorithm 1; <= 8) */
 } stf_solve_opts;
 
 typedef struct {

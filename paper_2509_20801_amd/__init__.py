@@ -238,7 +238,7 @@ class Problem:
         return z if dev else kz.reshape(self.ny, self.nx)
 
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
-              raise_on_noconv=False):
+              raise_on_noconv=False, rounds=1):
         """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos)."""
         shape = tuple(b.shape)
         nrhs = 1 if len(shape) == 2 else int(shape[0])
@@ -256,7 +256,7 @@ class Problem:
         pxx, dev2, kx = _ptr(x, nrhs * n, "x")
         if dev != dev2:
             raise TypeError("b and x must both be host or both be device arrays")
-        opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, 0)
+        opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, int(rounds))
         infos = (_abi.SolveInfo * nrhs)()
         hist = [np.zeros(history_cap, dtype=np.float64) for _ in range(nrhs)]
         for i in range(nrhs):

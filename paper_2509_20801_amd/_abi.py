@@ -27,7 +27,7 @@ class Params(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("x0_mode", C.c_int32), ("reserved0", C.c_int32)]
+                ("x0_mode", C.c_int32), ("rounds", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -43,7 +43,7 @@ void upload(DBuf& d, const std::vector<T>& h, hipStream_t st) {
 }
 
 struct Level {
-  int off = 0, n = 0, max_m = 0;
+  int off = 0, n = 0, max_m = 0, max_pm = 0;
 };
 
 }  // namespace
@@ -145,10 +145,10 @@ struct stf_problem_s {
   std::vector<Level> levels;     // by depth
 
   // Device state.
-  DBuf keps, gcoef, lcoef, subs, fronts, level_list, vars, cmap, ents, children;
+  DBuf keps, gcoef, lcoef, subs, fronts, vars, cmap, ents, children;
   DBuf fac, piv, vec, u, cover_x, cover_y, flag;
-  DBuf partial, scal;              // reduction scratch, device scalars
-  DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2;
+  DBuf partial, npartial, scal;    // reduction scratch, device scalars
+  DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
   DBuf hb, hx, cells;              // staging for host inputs
   int krylov_m = 0;
 
@@ -160,7 +160,7 @@ struct stf_problem_s {
   LevelArgs level_args(int d) const {
     LevelArgs a{};
     a.fronts = fronts.as<FrontDev>();
-    a.level_list = level_list.as<int>() + levels[d].off;
+    a.first = levels[d].off;
     a.nlevel = levels[d].n;
     a.subs = subs.as<SubDev>();
     a.vars = vars.as<int>();
@@ -171,12 +171,14 @@ struct stf_problem_s {
     a.lcoef = lcoef.as<double2>();
     a.nx = prm.nx;
     a.max_m = levels[d].max_m;
+    a.max_pm = levels[d].max_pm;
     return a;
   }
   int64_t device_bytes() const {
-    const DBuf* all[] = {&keps, &gcoef, &lcoef, &subs, &fronts, &level_list, &vars, &cmap, &ents,
+    const DBuf* all[] = {&keps, &gcoef, &lcoef, &subs, &fronts, &vars, &cmap, &ents,
                          &children, &fac, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
-                         &scal, &kV, &kZ, &kw, &kr, &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &hb,
+                         &npartial,
+                         &scal, &kV, &kZ, &kw, &kr, &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &hb,
                          &hx, &cells};
     int64_t s = 0;
     for (const DBuf* b : all) s += (int64_t)b->bytes;
@@ -284,65 +286,93 @@ void build_device_state(stf_problem pb) {
   upload(pb->cmap, cmap, st);
   upload(pb->ents, ents, st);
 
-  // Front instances of every subdomain.
-  std::vector<FrontDev> fr;
+  // Front instances of every subdomain, in level order (largest first within
+  // a level) so that each level is a contiguous range.
+  struct Rec { int sub, idx, depth, m; };
+  std::vector<Rec> recs;
+  std::vector<int> sub_base(pb->nsub);
+  for (int k = 0; k < pb->nsub; ++k) {
+    const SymShape& sh = *pl.shapes[pl.subs[k].shape];
+    sub_base[k] = (int)recs.size();
+    for (size_t i = 0; i < sh.fronts.size(); ++i)
+      recs.push_back({k, (int)i, sh.fronts[i].depth, sh.fronts[i].p + sh.fronts[i].q});
+  }
+  std::vector<int> order(recs.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (recs[x].depth != recs[y].depth) return recs[x].depth < recs[y].depth;
+    return recs[x].m > recs[y].m;
+  });
+  std::vector<int> inst(recs.size());      // record -> instance index
+  for (size_t t = 0; t < order.size(); ++t) inst[order[t]] = (int)t;
+  std::vector<FrontDev> fr(recs.size());
   std::vector<int> kids;
-  std::vector<std::vector<int>> bydepth;
   long long fac_off = 0;
   long long vec_off = 0, piv_off = 0;
-  for (int k = 0; k < pb->nsub; ++k) {
-    const SubDesc& s = pl.subs[k];
+  for (size_t t = 0; t < order.size(); ++t) {
+    const Rec& rc = recs[order[t]];
+    const SubDesc& s = pl.subs[rc.sub];
     const SymShape& sh = *pl.shapes[s.shape];
-    int base = (int)fr.size();
-    for (size_t i = 0; i < sh.fronts.size(); ++i) {
-      const SymFront& f = sh.fronts[i];
-      FrontDev d{};
-      int m = f.p + f.q;
-      d.fac_off = fac_off;
-      d.vec_off = (int)vec_off;
-      d.piv_off = (int)piv_off;
-      d.p = f.p;
-      d.q = f.q;
-      d.sub = k;
-      d.var_off = sh_var[s.shape] + f.var_off;
-      d.cmap_off = sh_cmap[s.shape] + f.cmap_off;
-      d.ent_off = sh_ent[s.shape] + f.ent_off;
-      d.ent_cnt = f.ent_cnt;
-      d.parent = f.parent >= 0 ? base + f.parent : -1;
-      d.child_off = (int)kids.size();
-      d.nchild = f.nchild;
-      for (int c = 0; c < f.nchild; ++c) kids.push_back(base + sh.children[f.child_off + c]);
-      fac_off += (long long)m * m;
-      vec_off += m;
-      piv_off += f.p;
-      if ((int)bydepth.size() <= f.depth) bydepth.resize(f.depth + 1);
-      bydepth[f.depth].push_back((int)fr.size());
-      fr.push_back(d);
-    }
+    const SymFront& f = sh.fronts[rc.idx];
+    FrontDev& d = fr[t];
+    int m = f.p + f.q;
+    d.fac_off = fac_off;
+    d.vec_off = (int)vec_off;
+    d.piv_off = (int)piv_off;
+    d.p = f.p;
+    d.q = f.q;
+    d.sub = rc.sub;
+    d.var_off = sh_var[s.shape] + f.var_off;
+    d.cmap_off = sh_cmap[s.shape] + f.cmap_off;
+    d.ent_off = sh_ent[s.shape] + f.ent_off;
+    d.ent_cnt = f.ent_cnt;
+    d.parent = f.parent >= 0 ? inst[sub_base[rc.sub] + f.parent] : -1;
+    STF_REQUIRE(f.nchild <= 2, "internal: more than two children");
+    d.child_off = (int)kids.size();
+    d.nchild = f.nchild;
+    for (int c = 0; c < f.nchild; ++c)
+      kids.push_back(inst[sub_base[rc.sub] + sh.children[f.child_off + c]]);
+    fac_off += (long long)m * m;
+    vec_off += m;
+    piv_off += f.p;
   }
   STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
+  // Embedded parent/children vector offsets (all offsets are known now).
+  for (size_t t = 0; t < fr.size(); ++t) {
+    FrontDev& d = fr[t];
+    d.pvec = d.parent >= 0 ? fr[d.parent].vec_off : -1;
+    for (int c = 0; c < 2; ++c) {
+      if (c < d.nchild) {
+        const FrontDev& cf = fr[kids[d.child_off + c]];
+        d.cvec[c] = cf.vec_off + cf.p;
+        d.ccmap[c] = cf.cmap_off;
+        d.cq[c] = cf.q;
+      } else {
+        d.cvec[c] = 0;
+        d.ccmap[c] = 0;
+        d.cq[c] = 0;
+      }
+    }
+  }
   pb->n_fronts = (int64_t)fr.size();
   pb->fac_elems = fac_off;
   pb->vec_elems = vec_off;
   pb->piv_elems = piv_off;
-  // Level lists, largest fronts first.
-  std::vector<int> ll;
   pb->levels.clear();
-  for (auto& lv : bydepth) {
-    std::stable_sort(lv.begin(), lv.end(), [&](int a, int b) {
-      return fr[a].p + fr[a].q > fr[b].p + fr[b].q;
-    });
-    Level L;
-    L.off = (int)ll.size();
-    L.n = (int)lv.size();
-    for (int i : lv) L.max_m = std::max(L.max_m, fr[i].p + fr[i].q);
-    ll.insert(ll.end(), lv.begin(), lv.end());
-    pb->levels.push_back(L);
+  for (size_t t = 0; t < order.size(); ++t) {
+    int dpt = recs[order[t]].depth;
+    if ((int)pb->levels.size() <= dpt) {
+      pb->levels.resize(dpt + 1);
+      pb->levels[dpt].off = (int)t;
+    }
+    Level& L = pb->levels[dpt];
+    L.n += 1;
+    L.max_m = std::max(L.max_m, fr[t].p + fr[t].q);
+    L.max_pm = std::max(L.max_pm, fr[t].p * (fr[t].p + fr[t].q));
   }
   pb->max_depth = (int)pb->levels.size() - 1;
   upload(pb->fronts, fr, st);
   upload(pb->children, kids, st);
-  upload(pb->level_list, ll, st);
   upload(pb->cover_x, pl.cover_x, st);
   upload(pb->cover_y, pl.cover_y, st);
 
@@ -356,6 +386,7 @@ void build_device_state(stf_problem pb) {
   pb->scal.alloc(sizeof(double) * 64);
   int nblk = std::max(stencil_partial_blocks(p.nx, p.ny), krylov_blocks(pb->N));
   pb->partial.alloc((size_t)nblk * sizeof(double2) * 4);
+  pb->npartial.alloc((size_t)krylov_blocks(pb->N) * sizeof(double));
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
@@ -422,6 +453,21 @@ void precond(stf_problem pb, const double2* v, double2* z) {
     precond_t<double2>(pb, v, z);
 }
 
+void residual(stf_problem pb, const double2* x, const double2* b, double2* r, double* dst);
+
+// `rounds` source-transfer rounds: z = B v, then z += B (v - A z).
+void precond_rounds(stf_problem pb, const double2* v, double2* z, int rounds) {
+  precond(pb, v, z);
+  for (int r = 1; r < rounds; ++r) {
+    double2* t = pb->kt.as<double2>();
+    double2* t2 = pb->kt2.as<double2>();
+    residual(pb, z, v, t, pb->scal.as<double>() + 7);
+    precond(pb, t, t2);
+    Timed tm(pb->ctx, K_UPDATE);
+    launch_axpy(pb->ctx->stream, z, t2, pb->N);
+  }
+}
+
 void apply_A(stf_problem pb, const double2* x, double2* y) {
   Timed t(pb->ctx, K_STENCIL);
   launch_stencil(pb->ctx->stream, 0, x, nullptr, y, pb->keps.as<double2>(), pb->cxw(), pb->cxe(),
@@ -444,8 +490,8 @@ void residual(stf_problem pb, const double2* x, const double2* b, double2* r, do
 void norm2(stf_problem pb, const double2* v, double2* dst) {
   hipStream_t st = pb->ctx->stream;
   Timed t(pb->ctx, K_ARNOLDI);
-  launch_mdot(st, v, pb->N, 1, v, pb->N, pb->partial.as<double2>());
-  launch_mdot_reduce(st, pb->partial.as<double2>(), krylov_blocks(pb->N), 1, dst);
+  launch_mdot(st, v, pb->N, 1, v, pb->N, pb->partial.as<double2>(), nullptr, nullptr);
+  launch_mdot_reduce(st, pb->partial.as<double2>(), krylov_blocks(pb->N), 1, dst, nullptr);
 }
 
 void ensure_krylov(stf_problem pb, int m) {
@@ -474,7 +520,12 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
   hipStream_t st = c->stream;
   const long long N = pb->N;
   const int m = o.restart;
+  const int rounds = o.rounds < 1 ? 1 : o.rounds;
   ensure_krylov(pb, m);
+  if (rounds > 1) {
+    pb->kt.alloc((size_t)N * sizeof(double2));
+    pb->kt2.alloc((size_t)N * sizeof(double2));
+  }
   double* sc = pb->scal.as<double>();
   double2* V = pb->kV.as<double2>();
   double2* Z = pb->kZ.as<double2>();
@@ -531,25 +582,34 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
     for (int j = 0; j < m && !stop; ++j) {
       double2* vj = V + (long long)j * N;
       double2* zj = Z + (long long)j * N;
-      precond(pb, vj, zj);
+      precond_rounds(pb, vj, zj, rounds);
       apply_A(pb, zj, w);
-      // Classical Gram-Schmidt, twice.
+      // Classical Gram-Schmidt with selective re-orthogonalisation:
+      // h1 = V^H w with |w|^2, w -= V h1 with the new |w|^2; a second pass
+      // (gated on the device) when more than half of |w|^2 cancelled.
       {
         Timed t(c, K_ARNOLDI);
-        launch_mdot(st, V, N, j + 1, w, N, pb->partial.as<double2>());
-        launch_mdot_reduce(st, pb->partial.as<double2>(), nblk, j + 1, pb->kh1.as<double2>());
-        launch_mupdate(st, V, N, j + 1, pb->kh1.as<double2>(), w, N, nullptr);
-        launch_mdot(st, V, N, j + 1, w, N, pb->partial.as<double2>());
-        launch_mdot_reduce(st, pb->partial.as<double2>(), nblk, j + 1, pb->kh2.as<double2>());
-        launch_mupdate(st, V, N, j + 1, pb->kh2.as<double2>(), w, N, pb->partial.as<double>());
-        launch_reduce_sum(st, pb->partial.as<double>(), nblk, sc + 3);
+        double2* part = pb->partial.as<double2>();
+        double* npart = pb->npartial.as<double>();
+        int* gate = pb->flag.as<int>() + 1;
+        double2* h1 = pb->kh1.as<double2>();
+        double2* h2 = pb->kh2.as<double2>();
+        launch_mdot(st, V, N, j + 1, w, N, part, npart, nullptr);
+        launch_mdot_reduce(st, part, nblk, j + 1, h1, nullptr);
+        launch_norm_reduce(st, npart, nblk, sc + 6, nullptr, nullptr, 0);
+        launch_mupdate(st, V, N, j + 1, h1, w, N, npart, nullptr);
+        launch_norm_reduce(st, npart, nblk, sc + 3, sc + 6, gate, 1);
+        launch_mdot(st, V, N, j + 1, w, N, part, nullptr, gate);
+        launch_mdot_reduce(st, part, nblk, j + 1, h2, gate);
+        launch_mupdate(st, V, N, j + 1, h2, w, N, npart, gate);
+        launch_norm_reduce(st, npart, nblk, sc + 3, nullptr, gate, 0);
+        launch_hacc(st, h1, h2, j + 1, gate);
       }
       {
         Timed t(c, K_UPDATE);
         launch_scale(st, w, sc + 3, V + (long long)(j + 1) * N, N);
-        launch_givens(st, H, pb->kh1.as<double2>(), pb->kh2.as<double2>(), sc + 3,
-                      pb->kcs.as<double>(), pb->ksn.as<double2>(), pb->kg.as<double2>(), j, m + 1,
-                      sc + 4);
+        launch_givens(st, H, pb->kh1.as<double2>(), sc + 3, pb->kcs.as<double>(),
+                      pb->ksn.as<double2>(), pb->kg.as<double2>(), j, m + 1, sc + 4);
       }
       HIP_CHECK(hipMemcpyAsync(hp + 4, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_CHECK(hipStreamSynchronize(st));
@@ -815,6 +875,7 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
     STF_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
     STF_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be finite and >= 0");
     STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER, "x0_mode invalid");
+    STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
     if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
     const size_t per = (size_t)pb->N * 2;
     require_finite(pb, b, per * nrhs, on_device, "b");

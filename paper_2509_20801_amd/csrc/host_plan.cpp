@@ -72,7 +72,7 @@ bool finite(double v) { return std::isfinite(v); }
 
 stf_params normalized(const stf_params& p) {
   stf_params q = p;
-  if (q.leaf_size == 0) q.leaf_size = 16;
+  if (q.leaf_size == 0) q.leaf_size = 32;
   return q;
 }
 

@@ -10,8 +10,12 @@
 // Schur complement that the parent gathers by extend-add.  Column-major makes
 // every step of the column-oriented triangular sweeps and every LU panel a
 // contiguous, coalesced read.  Pivoting is partial, restricted to the p fully
-// summed rows; swaps are applied to whole rows and recorded LAPACK-style
-// (piv[k] = row exchanged with row k at step k, front-relative).
+// summed rows; swaps are applied to whole rows.  After the partial LU the row
+// exchanges are stored as a gather permutation (piv[k] = source row of row k
+// of P b) and every diagonal block (DIB x DIB) of L11 and of U11 is replaced by
+// its inverse, so that each step of the triangular sweeps is a matrix-vector
+// product (Eq. (23) applied as products, as the paper describes the solve
+// phase) with no serial chain over the rows.
 //
 // Front vectors: each front owns m entries at vec_off.  The forward sweep
 // leaves [y_p ; update contribution] there, the backward sweep [x_p ; x_q],
@@ -31,9 +35,8 @@ namespace stf {
 namespace {
 
 constexpr int NT = 256;        // threads of a large-front workgroup
-constexpr int WB = 64;         // diagonal block (one wavefront) of the large sweeps
-constexpr int PF = 8;          // columns prefetched per chunk in the wave sweeps
 constexpr int UC = 32;         // columns of U staged in LDS per trailing-update chunk
+constexpr int DIB = 64;        // inverted diagonal blocks of L11 and U11
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -129,6 +132,56 @@ __device__ inline bool perturb(T& v, typename RealOf<T>::type best, typename Rea
   return true;
 }
 
+// Row exchanges ip[k] (LAPACK order) -> gather permutation stored back in ip:
+// (P b)[k] = b[ip[k]].  tmp: p ints.  One thread.
+__device__ inline void pivots_to_perm(int* ip, int* tmp, int p) {
+  for (int k = 0; k < p; ++k) tmp[k] = k;
+  for (int k = 0; k < p; ++k) {
+    int r2 = ip[k];
+    int t = tmp[k]; tmp[k] = tmp[r2]; tmp[r2] = t;
+  }
+  for (int k = 0; k < p; ++k) ip[k] = tmp[k];
+}
+
+// In-place inverse of the unit lower triangle of the n x n column-major block
+// G (ld): column j of the inverse is -(L[:, j] + X[:, j+1:] L[j+1:, j]) below
+// the diagonal, built from the right.  One wavefront (n <= 64); col: n entries.
+template <typename T>
+__device__ inline void invert_lower_unit(T* G, int ld, int n, T* col, int lane) {
+  for (int j = n - 2; j >= 0; --j) {
+    col[lane] = (lane > j && lane < n) ? G[j * ld + lane] : czero<T>();
+    wave_sync();
+    if (lane > j && lane < n) {
+      T x = col[lane];
+      for (int k = j + 1; k < lane; ++k) x = cfma(G[k * ld + lane], col[k], x);
+      G[j * ld + lane] = T{-x.x, -x.y};
+    }
+    wave_sync();
+  }
+}
+
+// In-place inverse of the upper triangle (diagonal included) of the n x n
+// column-major block G: X[j][j] = 1/U[j][j], X[0:j, j] = -X[0:j, 0:j] U[0:j, j] / U[j][j],
+// built from the left.  One wavefront (n <= 64); col: n entries.
+template <typename T>
+__device__ inline void invert_upper(T* G, int ld, int n, T* col, int lane) {
+  using R = typename RealOf<T>::type;
+  for (int j = 0; j < n; ++j) {
+    col[lane] = (lane <= j) ? G[j * ld + lane] : czero<T>();
+    wave_sync();
+    const T dinv = cdiv(T{(R)1, (R)0}, col[j]);
+    if (lane < j) {
+      T x = czero<T>();
+      for (int k = lane; k < j; ++k) x = cfma(G[k * ld + lane], col[k], x);
+      x = cmul(x, dinv);
+      G[j * ld + lane] = T{-x.x, -x.y};
+    } else if (lane == j) {
+      G[j * ld + j] = dinv;
+    }
+    wave_sync();
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Factorisation, small fronts: one wavefront per front, front in LDS.
 // ---------------------------------------------------------------------------
@@ -139,7 +192,7 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   using R = typename RealOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   T* G = reinterpret_cast<T*>(smem_raw);
-  const FrontDev f = a.fronts[a.level_list[blockIdx.x]];
+  const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p, lane = threadIdx.x;
   assemble_front<T>(a, fac, f, G, lane, 64, [] { wave_sync(); });
   int* ip = piv + f.piv_off;
@@ -172,6 +225,11 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
     }
     wave_sync();
   }
+  T* colbuf = G + (long long)m * m;
+  if (lane == 0) pivots_to_perm(ip, reinterpret_cast<int*>(colbuf + 64), p);
+  wave_sync();
+  invert_lower_unit(G, m, p, colbuf, lane);
+  invert_upper(G, m, p, colbuf, lane);
   T* F = fac + f.fac_off;
   const long long mm = (long long)m * m;
   for (long long t = lane; t < mm; t += 64) F[t] = G[t];
@@ -193,7 +251,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
   T* P = reinterpret_cast<T*>(smem_raw);           // panel, column-major, ld = ldp
   __shared__ T Us[UC][NB + 1];                      // staged U columns
   __shared__ int s_piv[NB];
-  const FrontDev f = a.fronts[a.level_list[blockIdx.x]];
+  const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p, ldp = a.max_m;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   T* F = fac + f.fac_off;
@@ -303,18 +361,47 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
     }
     __syncthreads();
   }
+  // Row exchanges -> gather permutation; inverses of the diagonal blocks of
+  // L11 (wavefront 0) and U11 (wavefront 1), one block at a time in LDS.
+  if (tid == 0) pivots_to_perm(ip, reinterpret_cast<int*>(P), p);
+  __syncthreads();
+  T* Db = P;                                    // DIB x DIB block, then two column buffers
+  for (int j0 = 0; j0 < p; j0 += DIB) {
+    const int nbk = min(DIB, p - j0);
+    for (int t = tid; t < nbk * nbk; t += NT) {
+      int c = t / nbk, r = t - c * nbk;
+      Db[c * DIB + r] = F[(long long)(j0 + c) * m + j0 + r];
+    }
+    __syncthreads();
+    if (wv == 0) invert_lower_unit(Db, DIB, nbk, Db + DIB * DIB, lane);
+    if (wv == 1) invert_upper(Db, DIB, nbk, Db + DIB * DIB + DIB, lane);
+    __syncthreads();
+    for (int t = tid; t < nbk * nbk; t += NT) {
+      int c = t / nbk, r = t - c * nbk;
+      F[(long long)(j0 + c) * m + j0 + r] = Db[c * DIB + r];
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
-// Sweeps, small fronts (m <= 64): one wavefront per front, lane = row.
+// Sweeps, small fronts (m <= 64): four fronts per workgroup, one wavefront per
+// front, lane = row.  With the inverted diagonal block each sweep is two
+// dependent matrix-vector products whose column reads are coalesced and all
+// independent of each other.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(64) void k_fwd_small(LevelArgs a, const T* __restrict__ fac,
+__global__ __launch_bounds__(NT) void k_fwd_small(LevelArgs a, const T* __restrict__ fac,
                                                   const int* __restrict__ piv, T* __restrict__ vec,
                                                   const double2* __restrict__ v) {
-  __shared__ T vl[64];
-  const FrontDev f = a.fronts[a.level_list[blockIdx.x]];
-  const int m = f.p + f.q, p = f.p, lane = threadIdx.x;
+  __shared__ T sh[4][2][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
+  if (fi >= a.nlevel) return;                          // whole wavefront; no block barriers below
+  T* vl = sh[wv][0];
+  T* yl = sh[wv][1];
+  const FrontDev f = a.fronts[a.first + fi];
+  const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
   T val = czero<T>();
   if (lane < p) {
@@ -324,89 +411,83 @@ __global__ __launch_bounds__(64) void k_fwd_small(LevelArgs a, const T* __restri
     if (gx >= s.ix0 && gx < s.ix1 && gy >= s.iy0 && gy < s.iy1)
       val = from_d2<T>(v[(long long)gy * a.nx + gx]);
   }
+  // Children's update vectors (both loaded before either is added).
+  int dst0 = -1, dst1 = -1;
+  T c0 = czero<T>(), c1 = czero<T>();
+  if (f.nchild > 0 && lane < f.cq[0]) {
+    dst0 = a.cmap[f.ccmap[0] + lane];
+    c0 = vec[f.cvec[0] + lane];
+  }
+  if (f.nchild > 1 && lane < f.cq[1]) {
+    dst1 = a.cmap[f.ccmap[1] + lane];
+    c1 = vec[f.cvec[1] + lane];
+  }
   vl[lane] = val;
   wave_sync();
-  for (int ci = 0; ci < f.nchild; ++ci) {
-    const FrontDev cf = a.fronts[a.children[f.child_off + ci]];
-    if (lane < cf.q) {
-      int dst = a.cmap[cf.cmap_off + lane];
-      vl[dst] = cadd(vl[dst], vec[cf.vec_off + cf.p + lane]);
-    }
-    wave_sync();
-  }
-  if (lane == 0) {
-    const int* ip = piv + f.piv_off;
-    for (int k = 0; k < p; ++k) {
-      int r2 = ip[k];
-      if (r2 != k) { T t0 = vl[k]; vl[k] = vl[r2]; vl[r2] = t0; }
-    }
-  }
+  if (dst0 >= 0) vl[dst0] = cadd(vl[dst0], c0);
   wave_sync();
-  val = vl[lane];
-  const bool row = lane < m;
-  for (int k0 = 0; k0 < p; k0 += PF) {
-    T col[PF];
-#pragma unroll
-    for (int t = 0; t < PF; ++t)
-      col[t] = (row && k0 + t < p) ? F[(long long)(k0 + t) * m + lane] : czero<T>();
-#pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      const int k = k0 + t;
-      if (k < p) {
-        T yk = shfl_c(val, k);
-        if (lane > k) val = cfms(col[t], yk, val);
-      }
-    }
+  if (dst1 >= 0) vl[dst1] = cadd(vl[dst1], c1);
+  wave_sync();
+  // (P b)_r = b[perm[r]] for the separator rows.
+  val = lane < p ? vl[piv[f.piv_off + lane]] : vl[lane];
+  wave_sync();
+  vl[lane] = val;
+  wave_sync();
+  // y = L11^{-1} P b_p (unit lower inverse stored below the diagonal).
+  if (lane < p) {
+    T acc = val;
+#pragma unroll 8
+    for (int k = 0; k < p; ++k)
+      if (k < lane) acc = cfma(F[(long long)k * m + lane], vl[k], acc);
+    val = acc;
   }
-  if (row) vec[f.vec_off + lane] = val;
+  yl[lane] = val;
+  wave_sync();
+  // b_q -= L21 y.
+  if (lane >= p && lane < m) {
+    T acc = czero<T>();
+#pragma unroll 8
+    for (int k = 0; k < p; ++k) acc = cfma(F[(long long)k * m + lane], yl[k], acc);
+    val = csub(val, acc);
+  }
+  if (lane < m) vec[f.vec_off + lane] = val;
 }
 
 template <typename T>
-__global__ __launch_bounds__(64) void k_bwd_small(LevelArgs a, const T* __restrict__ fac,
+__global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restrict__ fac,
                                                   T* __restrict__ vec, T* __restrict__ u) {
-  const FrontDev f = a.fronts[a.level_list[blockIdx.x]];
-  const int m = f.p + f.q, p = f.p, lane = threadIdx.x;
+  __shared__ T sh[4][2][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
+  if (fi >= a.nlevel) return;
+  T* vl = sh[wv][0];
+  T* tl = sh[wv][1];
+  const FrontDev f = a.fronts[a.first + fi];
+  const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
   T val = czero<T>();
   if (lane < p) {
     val = vec[f.vec_off + lane];
   } else if (lane < m) {
-    const FrontDev pf = a.fronts[f.parent];
-    val = vec[pf.vec_off + a.cmap[f.cmap_off + lane - p]];
+    val = vec[f.pvec + a.cmap[f.cmap_off + lane - p]];
   }
-  // y - U12 x_q
-  for (int j0 = p; j0 < m; j0 += PF) {
-    T col[PF];
-#pragma unroll
-    for (int t = 0; t < PF; ++t)
-      col[t] = (lane < p && j0 + t < m) ? F[(long long)(j0 + t) * m + lane] : czero<T>();
-#pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      const int j = j0 + t;
-      if (j < m) {
-        T xj = shfl_c(val, j);
-        if (lane < p) val = cfms(col[t], xj, val);
-      }
-    }
+  vl[lane] = val;
+  wave_sync();
+  T t = czero<T>();
+  if (lane < p) {                                        // t = y - U12 x_q
+    T acc = czero<T>();
+#pragma unroll 8
+    for (int j = p; j < m; ++j) acc = cfma(F[(long long)j * m + lane], vl[j], acc);
+    t = csub(val, acc);
   }
-  // U11 x = y'
-  for (int k1 = p; k1 > 0; k1 -= PF) {
-    T col[PF];
-#pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      const int k = k1 - 1 - t;
-      col[t] = (k >= 0 && lane <= k) ? F[(long long)k * m + lane] : czero<T>();
-    }
-#pragma unroll
-    for (int t = 0; t < PF; ++t) {
-      const int k = k1 - 1 - t;
-      if (k >= 0) {
-        T xk = (lane == k) ? cdiv(val, col[t]) : val;
-        xk = shfl_c(xk, k);
-        if (lane == k) val = xk;
-        else if (lane < k) val = cfms(col[t], xk, val);
-      }
-    }
+  tl[lane] = t;
+  wave_sync();
+  if (lane < p) {                                        // x_p = U11^{-1} t
+    T acc = czero<T>();
+#pragma unroll 8
+    for (int k = 0; k < p; ++k)
+      if (k >= lane) acc = cfma(F[(long long)k * m + lane], tl[k], acc);
+    val = acc;
   }
   if (lane < m) vec[f.vec_off + lane] = val;
   if (lane < p) {
@@ -415,21 +496,103 @@ __global__ __launch_bounds__(64) void k_bwd_small(LevelArgs a, const T* __restri
   }
 }
 
+// sum over c = c0, c0+step, ... < c1 of A[c*lda] * x[c], with the global
+// loads issued in batches of LB so that many are in flight at once.
+template <typename T>
+__device__ inline T strided_dot(const T* __restrict__ A, long long lda, int c0, int c1, int step,
+                                const T* x) {
+  constexpr int LB = 16;
+  T acc0 = czero<T>(), acc1 = czero<T>();
+  int c = c0;
+  for (; c + (LB - 1) * step < c1; c += LB * step) {
+    T av[LB];
+#pragma unroll
+    for (int t = 0; t < LB; ++t) av[t] = A[(long long)(c + t * step) * lda];
+#pragma unroll
+    for (int t = 0; t < LB; t += 2) {
+      acc0 = cfma(av[t], x[c + t * step], acc0);
+      acc1 = cfma(av[t + 1], x[c + (t + 1) * step], acc1);
+    }
+  }
+  for (; c < c1; c += step) acc0 = cfma(A[(long long)c * lda], x[c], acc0);
+  return cadd(acc0, acc1);
+}
+
+// y[r] -= sum_{c0 <= c < c1} A[c*lda + r] x[c] for r0 <= r < r1, with A
+// column-major in global memory and x, y in LDS, using all NT threads: a thread
+// per row when the rows fill the workgroup, otherwise (row, column-group)
+// pairs whose partial sums are reduced in a fixed order through `scr`
+// (NT entries).  Ends with a workgroup barrier.
+template <typename T>
+__device__ inline void block_gemv_sub(const T* __restrict__ A, int lda, int r0, int r1, int c0,
+                                      int c1, const T* x, T* y, T* scr, int tid) {
+  const int R = r1 - r0;
+  if (R <= 0 || c1 <= c0) return;
+  if (R >= NT / 2) {
+    for (int r = r0 + tid; r < r1; r += NT) {
+      const T acc = strided_dot(A + r, (long long)lda, c0, c1, 1, x);
+      y[r] = csub(y[r], acc);
+    }
+    __syncthreads();
+    return;
+  }
+  const int G = NT / R;
+  const int g = tid / R, rr = tid - g * R;
+  T acc = czero<T>();
+  if (g < G) acc = strided_dot(A + r0 + rr, (long long)lda, c0 + g, c1, G, x);
+  scr[tid] = acc;
+  __syncthreads();
+  if (tid < R) {
+    T sum = czero<T>();
+    for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * R + tid]);
+    y[r0 + tid] = csub(y[r0 + tid], sum);
+  }
+  __syncthreads();
+}
+
+// One inverted diagonal block applied in place to x[j0 .. j0+n) (n <= DIB):
+// LOWER: x <- (I + strict lower of A) x;  UPPER: x <- (upper of A) x, with A the
+// block at column-major offset j0*(lda+1).  Four column groups per row,
+// reduced in a fixed order.  Ends with a workgroup barrier.
+template <typename T, bool LOWER>
+__device__ inline void block_trmv(const T* __restrict__ A, int lda, int j0, int n, T* x, T* scr,
+                                  int tid) {
+  const int r = tid & 63, g = tid >> 6;
+  T acc = czero<T>();
+  if (r < n) {
+    const T* Ar = A + (long long)j0 * lda + j0 + r;
+    for (int c = g; c < n; c += 4) {
+      bool use = LOWER ? (c < r) : (c >= r);
+      if (use) acc = cfma(Ar[(long long)c * lda], x[j0 + c], acc);
+    }
+  }
+  scr[tid] = acc;
+  __syncthreads();
+  if (tid < n) {
+    T sum = LOWER ? x[j0 + tid] : czero<T>();
+    for (int gg = 0; gg < 4; ++gg) sum = cadd(sum, scr[gg * 64 + tid]);
+    x[j0 + tid] = sum;
+  }
+  __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
-// Sweeps, large fronts: one workgroup per front; diagonal blocks of 64 columns
-// solved by wavefront 0, the rest of each column block applied by all threads
-// (one row per thread, column-block GEMV with coalesced column reads).
+// Sweeps, large fronts: one workgroup per front, diagonal blocks of DIB
+// columns: inverted-block product, then the block GEMV below (forward) or
+// above (backward) it.
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restrict__ fac,
                                                   const int* __restrict__ piv, T* __restrict__ vec,
                                                   const double2* __restrict__ v) {
   extern __shared__ unsigned char smem_raw[];
-  T* vl = reinterpret_cast<T*>(smem_raw);
-  const FrontDev f = a.fronts[a.level_list[blockIdx.x]];
+  T* scr = reinterpret_cast<T*>(smem_raw);                 // NT
+  T* vl = scr + NT;                                        // max_m
+  T* tmp = vl + a.max_m;                                   // max_m
+  const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   const SubDev s = a.subs[f.sub];
   for (int i = tid; i < m; i += NT) {
     T val = czero<T>();
@@ -442,50 +605,27 @@ __global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restri
     vl[i] = val;
   }
   __syncthreads();
-  for (int ci = 0; ci < f.nchild; ++ci) {
-    const FrontDev cf = a.fronts[a.children[f.child_off + ci]];
-    const int* cm = a.cmap + cf.cmap_off;
-    const T* cv = vec + cf.vec_off + cf.p;
-    for (int i = tid; i < cf.q; i += NT) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
+  if (f.nchild > 0) {
+    const int* cm = a.cmap + f.ccmap[0];
+    const T* cv = vec + f.cvec[0];
+    for (int i = tid; i < f.cq[0]; i += NT) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
     __syncthreads();
   }
-  if (tid == 0) {
-    const int* ip = piv + f.piv_off;
-    for (int k = 0; k < p; ++k) {
-      int r2 = ip[k];
-      if (r2 != k) { T t0 = vl[k]; vl[k] = vl[r2]; vl[r2] = t0; }
-    }
+  if (f.nchild > 1) {
+    const int* cm = a.cmap + f.ccmap[1];
+    const T* cv = vec + f.cvec[1];
+    for (int i = tid; i < f.cq[1]; i += NT) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
+    __syncthreads();
   }
+  const int* perm = piv + f.piv_off;
+  for (int i = tid; i < m; i += NT) tmp[i] = i < p ? vl[perm[i]] : vl[i];
   __syncthreads();
-  for (int kb = 0; kb < p; kb += WB) {
-    const int nbk = min(WB, p - kb);
-    if (wv == 0) {
-      T val = lane < nbk ? vl[kb + lane] : czero<T>();
-      for (int k0 = 0; k0 < nbk; k0 += PF) {
-        T col[PF];
-#pragma unroll
-        for (int t = 0; t < PF; ++t)
-          col[t] = (lane < nbk && k0 + t < nbk) ? F[(long long)(kb + k0 + t) * m + kb + lane]
-                                                : czero<T>();
-#pragma unroll
-        for (int t = 0; t < PF; ++t) {
-          const int k = k0 + t;
-          if (k < nbk) {
-            T yk = shfl_c(val, k);
-            if (lane > k) val = cfms(col[t], yk, val);
-          }
-        }
-      }
-      if (lane < nbk) vl[kb + lane] = val;
-    }
-    __syncthreads();
-    for (int r = kb + nbk + tid; r < m; r += NT) {
-      T acc = czero<T>();
-      const T* Fr = F + (long long)kb * m + r;
-      for (int k = 0; k < nbk; ++k) acc = cfma(Fr[(long long)k * m], vl[kb + k], acc);
-      vl[r] = csub(vl[r], acc);
-    }
-    __syncthreads();
+  for (int i = tid; i < m; i += NT) vl[i] = tmp[i];
+  __syncthreads();
+  for (int j0 = 0; j0 < p; j0 += DIB) {
+    const int nbk = min(DIB, p - j0);
+    block_trmv<T, true>(F, m, j0, nbk, vl, scr, tid);
+    block_gemv_sub(F, m, j0 + nbk, m, j0, j0 + nbk, vl, vl, scr, tid);
   }
   T* out = vec + f.vec_off;
   for (int i = tid; i < m; i += NT) out[i] = vl[i];
@@ -495,60 +635,25 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restrict__ fac,
                                                   T* __restrict__ vec, T* __restrict__ u) {
   extern __shared__ unsigned char smem_raw[];
-  T* vl = reinterpret_cast<T*>(smem_raw);
-  const FrontDev f = a.fronts[a.level_list[blockIdx.x]];
+  T* scr = reinterpret_cast<T*>(smem_raw);
+  T* vl = scr + NT;
+  const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int tid = threadIdx.x;
   T* fv = vec + f.vec_off;
   for (int i = tid; i < p; i += NT) vl[i] = fv[i];
   if (f.parent >= 0) {
-    const FrontDev pf = a.fronts[f.parent];
     const int* cm = a.cmap + f.cmap_off;
-    const T* pv = vec + pf.vec_off;
+    const T* pv = vec + f.pvec;
     for (int i = tid; i < f.q; i += NT) vl[p + i] = pv[cm[i]];
   }
   __syncthreads();
-  // y - U12 x_q, one row per thread.
-  for (int r = tid; r < p; r += NT) {
-    T acc = czero<T>();
-    const T* Fr = F + r;
-    for (int j = p; j < m; ++j) acc = cfma(Fr[(long long)j * m], vl[j], acc);
-    vl[r] = csub(vl[r], acc);
-  }
-  __syncthreads();
-  for (int kb = ((p - 1) / WB) * WB; kb >= 0; kb -= WB) {
-    const int nbk = min(WB, p - kb);
-    if (wv == 0) {
-      T val = lane < nbk ? vl[kb + lane] : czero<T>();
-      for (int k1 = nbk; k1 > 0; k1 -= PF) {
-        T col[PF];
-#pragma unroll
-        for (int t = 0; t < PF; ++t) {
-          const int k = k1 - 1 - t;
-          col[t] = (k >= 0 && lane <= k) ? F[(long long)(kb + k) * m + kb + lane] : czero<T>();
-        }
-#pragma unroll
-        for (int t = 0; t < PF; ++t) {
-          const int k = k1 - 1 - t;
-          if (k >= 0) {
-            T xk = (lane == k) ? cdiv(val, col[t]) : val;
-            xk = shfl_c(xk, k);
-            if (lane == k) val = xk;
-            else if (lane < k) val = cfms(col[t], xk, val);
-          }
-        }
-      }
-      if (lane < nbk) vl[kb + lane] = val;
-    }
-    __syncthreads();
-    for (int r = tid; r < kb; r += NT) {
-      T acc = czero<T>();
-      const T* Fr = F + (long long)kb * m + r;
-      for (int k = 0; k < nbk; ++k) acc = cfma(Fr[(long long)k * m], vl[kb + k], acc);
-      vl[r] = csub(vl[r], acc);
-    }
-    __syncthreads();
+  block_gemv_sub(F, m, 0, p, p, m, vl, vl, scr, tid);     // y - U12 x_q
+  for (int j0 = ((p - 1) / DIB) * DIB; j0 >= 0; j0 -= DIB) {
+    const int nbk = min(DIB, p - j0);
+    block_trmv<T, false>(F, m, j0, nbk, vl, scr, tid);
+    block_gemv_sub(F, m, 0, j0, j0, j0 + nbk, vl, vl, scr, tid);
   }
   const int* vars = a.vars + f.var_off;
   const long long uo = a.subs[f.sub].u_off;
@@ -594,7 +699,7 @@ int max_lds() {
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
         v > 0)
-      g_max_lds = std::min(v, 65536);
+      g_max_lds = v;
     else
       g_max_lds = 65536;
   }
@@ -603,7 +708,7 @@ int max_lds() {
 
 template <typename T, int NB>
 void large_launch(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag, double tau) {
-  size_t lds = (size_t)a.max_m * NB * sizeof(T);
+  size_t lds = std::max((size_t)a.max_m * NB, (size_t)DIB * DIB + 2 * DIB) * sizeof(T);
   hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, piv, flag,
                      tau);
 }
@@ -611,9 +716,10 @@ void large_launch(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* fla
 }  // namespace
 
 int small_factor_limit(size_t elem) {
-  // Largest front order whose m x m block fits the LDS of one wavefront workgroup.
+  // Largest front order whose m x m block (plus two 64-entry buffers) fits
+  // 40 KiB of LDS, so that several one-wavefront workgroups share a CU.
   int lim = 1;
-  while ((size_t)(lim + 1) * (lim + 1) * elem <= 32768) ++lim;
+  while ((size_t)((lim + 1) * (lim + 1) + 128) * elem <= 40960) ++lim;
   return std::min(lim, 64);
 }
 
@@ -621,7 +727,7 @@ template <typename T>
 void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag,
                          double tau) {
   if (a.max_m <= small_factor_limit(sizeof(T))) {
-    size_t lds = (size_t)a.max_m * a.max_m * sizeof(T);
+    size_t lds = ((size_t)a.max_m * a.max_m + 128) * sizeof(T);
     hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, piv, flag, tau);
     return;
   }
@@ -647,9 +753,10 @@ template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
                       const double2* v) {
   if (a.max_m <= 64) {
-    hipLaunchKernelGGL(k_fwd_small<T>, dim3(a.nlevel), dim3(64), 0, st, a, fac, piv, vec, v);
+    hipLaunchKernelGGL(k_fwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, piv, vec,
+                       v);
   } else {
-    size_t lds = (size_t)a.max_m * sizeof(T);
+    size_t lds = ((size_t)NT + 2 * (size_t)a.max_m) * sizeof(T);
     hipLaunchKernelGGL(k_fwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, fac, piv, vec, v);
   }
 }
@@ -657,9 +764,9 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
 template <typename T>
 void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* fac, T* vec, T* u) {
   if (a.max_m <= 64) {
-    hipLaunchKernelGGL(k_bwd_small<T>, dim3(a.nlevel), dim3(64), 0, st, a, fac, vec, u);
+    hipLaunchKernelGGL(k_bwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, vec, u);
   } else {
-    size_t lds = (size_t)a.max_m * sizeof(T);
+    size_t lds = ((size_t)NT + (size_t)a.max_m) * sizeof(T);
     hipLaunchKernelGGL(k_bwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, fac, vec, u);
   }
 }

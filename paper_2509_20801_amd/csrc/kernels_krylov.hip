@@ -1,6 +1,8 @@
 // FP64 kernels of the flexible GMRES outer iteration: classical Gram-Schmidt
-// with one re-orthogonalisation (block dot products, then a block update),
-// norms, complex Givens rotations and the solution update x += Z y.
+// with selective re-orthogonalisation (a block dot pass that also yields |w|^2,
+// a block update pass that yields the new |w|^2, and a second pass only when
+// the norm dropped below |w|/sqrt(2), decided on the device), complex Givens
+// rotations and the solution update x += Z y.
 //
 // Vectors are contiguous complex128 arrays of n entries; a basis V stores its
 // vectors with leading dimension ld.  Every thread owns up to EPT entries of a
@@ -29,10 +31,15 @@ __device__ inline double block_sum(double v, double* red) {
   return (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// partial[blk][i] = V_i^H w over the block's chunk; with `gate`, skipped
+// (all threads return) unless *gate != 0; with `norm_partial`, also |w|^2.
 __global__ __launch_bounds__(KT) void k_mdot(const double2* __restrict__ V, long long ld, int nv,
                                              const double2* __restrict__ w, long long n,
-                                             double2* __restrict__ partial) {
+                                             double2* __restrict__ partial,
+                                             double* __restrict__ norm_partial,
+                                             const int* __restrict__ gate) {
   __shared__ double red[4];
+  if (gate && gate[0] == 0) return;
   const long long base = (long long)blockIdx.x * CHUNK + threadIdx.x;
   double2 wr[EPT];
 #pragma unroll
@@ -70,12 +77,21 @@ __global__ __launch_bounds__(KT) void k_mdot(const double2* __restrict__ V, long
         partial[(long long)blockIdx.x * nv + i0 + b] = make_double2(sr, si);
     }
   }
+  if (norm_partial) {
+    double nr = 0.0;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) nr += wr[e].x * wr[e].x + wr[e].y * wr[e].y;
+    double t = block_sum(nr, red);
+    if (threadIdx.x == 0) norm_partial[blockIdx.x] = t;
+  }
 }
 
-// h[i] = sum_b partial[b][i] in a fixed order.
+// h[i] = sum_b partial[b][i] in a fixed order (skipped unless *gate when gated).
 __global__ __launch_bounds__(KT) void k_mdot_reduce(const double2* __restrict__ partial, int nblk,
-                                                    int nv, double2* __restrict__ h) {
+                                                    int nv, double2* __restrict__ h,
+                                                    const int* __restrict__ gate) {
   __shared__ double red[4];
+  if (gate && gate[0] == 0) return;
   const int i = blockIdx.x;
   double sr = 0.0, si = 0.0;
   for (int b = threadIdx.x; b < nblk; b += KT) {
@@ -92,9 +108,11 @@ __global__ __launch_bounds__(KT) void k_mdot_reduce(const double2* __restrict__ 
 __global__ __launch_bounds__(KT) void k_mupdate(const double2* __restrict__ V, long long ld, int nv,
                                                 const double2* __restrict__ h,
                                                 double2* __restrict__ w, long long n,
-                                                double* __restrict__ norm_partial) {
+                                                double* __restrict__ norm_partial,
+                                                const int* __restrict__ gate) {
   __shared__ double red[4];
   __shared__ double2 hs[256];
+  if (gate && gate[0] == 0) return;
   const long long base = (long long)blockIdx.x * CHUNK + threadIdx.x;
   double2 wr[EPT];
 #pragma unroll
@@ -132,6 +150,33 @@ __global__ __launch_bounds__(KT) void k_mupdate(const double2* __restrict__ V, l
   }
 }
 
+// Fixed-order sum of n partials into out[0].  With `decide`: out holds the
+// new |w|^2 and ref[0] the |w|^2 before the update; gate[0] is set to 1 when
+// the update cancelled more than half of the norm squared (re-orthogonalise),
+// else 0.  With `gate` alone the kernel runs only when gate[0] != 0.
+__global__ __launch_bounds__(KT) void k_norm_reduce(const double* __restrict__ partial, int n,
+                                                    double* __restrict__ out,
+                                                    const double* __restrict__ ref,
+                                                    int* __restrict__ gate, int decide) {
+  __shared__ double red[4];
+  if (!decide && gate && gate[0] == 0) return;
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += KT) s += partial[t];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    out[0] = s;
+    if (decide) gate[0] = (s < 0.5 * ref[0]) ? 1 : 0;
+  }
+}
+
+// h1 += h2 when gate[0] != 0 (accumulates the re-orthogonalisation coefficients).
+__global__ void k_hacc(double2* __restrict__ h1, const double2* __restrict__ h2, int nv,
+                       const int* __restrict__ gate) {
+  if (gate[0] == 0) return;
+  for (int i = threadIdx.x; i < nv; i += blockDim.x)
+    h1[i] = make_double2(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+}
+
 __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
                                               const double* __restrict__ nrm2,
                                               double2* __restrict__ v, long long n) {
@@ -144,16 +189,16 @@ __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
 }
 
 // One Givens step of FGMRES for column j (single thread).
-//   column j of the Hessenberg matrix: h[i] = h1[i] + h2[i] (i <= j), h[j+1] = |w|.
+//   column j of the Hessenberg matrix: h[i] (i <= j), h[j+1] = |w|.
 //   Earlier rotations are applied, a new one zeroes h[j+1], g is rotated and
 //   est = |g[j+1]| is the residual norm of the least-squares iterate.
-__global__ void k_givens(double2* __restrict__ H, const double2* __restrict__ h1,
-                         const double2* __restrict__ h2, const double* __restrict__ wnorm2,
-                         double* __restrict__ cs, double2* __restrict__ sn,
-                         double2* __restrict__ g, int j, int ldh, double* __restrict__ est) {
+__global__ void k_givens(double2* __restrict__ H, const double2* __restrict__ h,
+                         const double* __restrict__ wnorm2, double* __restrict__ cs,
+                         double2* __restrict__ sn, double2* __restrict__ g, int j, int ldh,
+                         double* __restrict__ est) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   double2* col = H + (long long)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = make_double2(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
+  for (int i = 0; i <= j; ++i) col[i] = h[i];
   col[j + 1] = make_double2(sqrt(wnorm2[0]), 0.0);
   for (int i = 0; i < j; ++i) {
     double c = cs[i];
@@ -215,6 +260,14 @@ __global__ __launch_bounds__(KT) void k_xupdate(const double2* __restrict__ Z, l
   }
 }
 
+__global__ __launch_bounds__(KT) void k_axpy(double2* __restrict__ y, const double2* __restrict__ x,
+                                             long long n) {
+  for (long long t = (long long)blockIdx.x * KT + threadIdx.x; t < n; t += (long long)gridDim.x * KT) {
+    double2 a = y[t], b = x[t];
+    y[t] = make_double2(a.x + b.x, a.y + b.y);
+  }
+}
+
 int grid_for(long long n) {
   long long g = (n + KT - 1) / KT;
   if (g > 4096) g = 4096;
@@ -227,28 +280,42 @@ int grid_for(long long n) {
 int krylov_blocks(long long n) { return (int)((n + CHUNK - 1) / CHUNK); }
 
 void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const double2* w,
-                 long long n, double2* partial) {
-  hipLaunchKernelGGL(k_mdot, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, w, n, partial);
+                 long long n, double2* partial, double* norm_partial, const int* gate) {
+  hipLaunchKernelGGL(k_mdot, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, w, n, partial,
+                     norm_partial, gate);
 }
 
-void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk, nv, h);
+void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h,
+                        const int* gate) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk, nv, h, gate);
 }
 
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
-                    double2* w, long long n, double* norm_partial) {
+                    double2* w, long long n, double* norm_partial, const int* gate) {
   hipLaunchKernelGGL(k_mupdate, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, h, w, n,
-                     norm_partial);
+                     norm_partial, gate);
+}
+
+void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* out,
+                        const double* ref, int* gate, int decide) {
+  hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(KT), 0, st, partial, n, out, ref, gate, decide);
+}
+
+void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate) {
+  hipLaunchKernelGGL(k_hacc, dim3(1), dim3(256), 0, st, h1, h2, nv, gate);
 }
 
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n) {
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n);
 }
 
-void launch_givens(hipStream_t st, double2* H, double2* h1, double2* h2, const double* wnorm2,
+void launch_givens(hipStream_t st, double2* H, const double2* h, const double* wnorm2,
                    double* cs, double2* sn, double2* g, int j, int ldh, double* est_out) {
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h1, h2, wnorm2, cs, sn, g, j, ldh,
-                     est_out);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h, wnorm2, cs, sn, g, j, ldh, est_out);
+}
+
+void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(KT), 0, st, y, x, n);
 }
 
 void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,

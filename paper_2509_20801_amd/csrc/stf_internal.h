@@ -121,17 +121,24 @@ struct SubDev {
   long long u_off;          // offset of the local field (nxl*nyl elements)
 };
 
+// Front instances are stored in tree-level order (deepest level last within
+// the array's level ranges, largest fronts first within a level), so a level
+// is the contiguous range [first, first + n).  Children and parent vector
+// offsets are embedded so that the sweeps read one descriptor per front.
 struct FrontDev {
-  long long fac_off;        // element offset of the m x m front (row-major)
+  long long fac_off;        // element offset of the m x m front (column-major)
   int vec_off;              // element offset of the front vector (m elements)
-  int piv_off;              // offset of the p pivot indices
+  int piv_off;              // offset of the p pivot entries
   int p, q;
   int sub;                  // subdomain
   int var_off, cmap_off;    // into the concatenated vars / cmap arrays
   int ent_off, ent_cnt;     // into the concatenated entries
   int parent;               // instance index or -1
-  int child_off, nchild;    // into the instance children array
-  int pad;
+  int child_off, nchild;    // into the instance children array (nchild <= 2)
+  int pvec;                 // parent's vec_off (-1 for a root)
+  int cvec[2];              // children: vec_off + p (start of their update parts)
+  int ccmap[2];             // children: cmap_off
+  int cq[2];                // children: q
 };
 
 // Kernel classes for timing (match STF_K_* in stfdfd.h).
@@ -161,8 +168,8 @@ void launch_check_finite(hipStream_t st, const double* a, long long n, int* flag
 
 // Multifrontal, per tree level; T = double2 (c128) or float2 (c64).
 struct LevelArgs {
-  const FrontDev* fronts;       // instance descriptors
-  const int* level_list;        // fronts of this level
+  const FrontDev* fronts;       // instance descriptors (level order)
+  int first;                    // first front of this level
   int nlevel;                   // number of fronts in the level
   const SubDev* subs;
   const int* vars;
@@ -173,6 +180,7 @@ struct LevelArgs {
   const double2* lcoef;         // local coupling coefficients
   int nx;                       // global nx
   int max_m;                    // largest front in the level
+  int max_pm;                   // largest p*m in the level
 };
 // Assembly (original entries + extend-add of the children) and partial LU of
 // every front of one level.
@@ -191,19 +199,29 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
 // Krylov (kernels_krylov.hip).  Vectors of n complex doubles; V holds nv vectors
 // with leading dimension ld (elements).
 int krylov_blocks(long long n);
+// partial[blk][i] = V_i^H w per block (+ |w|^2 partials when norm_partial);
+// gated kernels run only when *gate != 0 (gate may be null).
 void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const double2* w,
-                 long long n, double2* partial);
-void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h);
+                 long long n, double2* partial, double* norm_partial, const int* gate);
+void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h,
+                        const int* gate);
+// w -= V h (+ |w|^2 partials).
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
-                    double2* w, long long n, double* norm_partial);
+                    double2* w, long long n, double* norm_partial, const int* gate);
+// out = sum of partials; decide: gate = (out < ref/2).
+void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* out,
+                        const double* ref, int* gate, int decide);
+void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate);
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v,
                   long long n);
 // Givens step j of FGMRES on device (single thread).  H column-major (ldh = m+1).
-void launch_givens(hipStream_t st, double2* H, double2* h1, double2* h2, const double* wnorm2,
+void launch_givens(hipStream_t st, double2* H, const double2* h, const double* wnorm2,
                    double* cs, double2* sn, double2* g, int j, int ldh, double* est_out);
 // y = R^{-1} g (k x k upper triangular, column-major ldh).
 void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
                      int ldh);
+// y += x
+void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n);
 // x += Z y
 void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
                     double2* x, long long n);
