@@ -76,6 +76,11 @@ template <typename T> __device__ inline T wave_csum(T v) {
   v.y = wave_sum(v.y);
   return v;
 }
+template <typename T> __device__ inline T shfl_xor_c(T v, int mask) {
+  v.x = __shfl_xor(v.x, mask, 64);
+  v.y = __shfl_xor(v.y, mask, 64);
+  return v;
+}
 template <typename T> __device__ inline T shfl_c(T v, int lane) {
   v.x = __shfl(v.x, lane, 64);
   v.y = __shfl(v.y, lane, 64);

@@ -230,6 +230,25 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   wave_sync();
   invert_lower_unit(G, m, p, colbuf, lane);
   invert_upper(G, m, p, colbuf, lane);
+  wave_sync();
+  // M' = -L21 L11^{-1} (rows p..m-1, one row per lane, columns ascending so
+  // each entry is rewritten after its last use) and V' = -U11^{-1} U12
+  // (columns p..m-1, one column per lane, rows ascending).
+  for (int r = p + lane; r < m; r += 64) {
+    for (int j = 0; j < p; ++j) {
+      T acc = G[(long long)j * m + r];
+      for (int k = j + 1; k < p; ++k) acc = cfma(G[(long long)k * m + r], G[(long long)j * m + k], acc);
+      G[(long long)j * m + r] = T{-acc.x, -acc.y};
+    }
+  }
+  for (int c = p + lane; c < m; c += 64) {
+    for (int r = 0; r < p; ++r) {
+      T acc = czero<T>();
+      for (int k = r; k < p; ++k) acc = cfma(G[(long long)k * m + r], G[(long long)c * m + k], acc);
+      G[(long long)c * m + r] = T{-acc.x, -acc.y};
+    }
+  }
+  wave_sync();
   T* F = fac + f.fac_off;
   const long long mm = (long long)m * m;
   for (long long t = lane; t < mm; t += 64) F[t] = G[t];
@@ -380,6 +399,58 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       int c = t / nbk, r = t - c * nbk;
       F[(long long)(j0 + c) * m + j0 + r] = Db[c * DIB + r];
     }
+    T* Cb = Db + DIB * DIB + 2 * DIB;           // 64 x DIB staging chunk
+    // M'_J = -L[j1:m, J] Linv_J, 64 rows at a time.
+    const int j1 = j0 + nbk;
+    for (int r0 = j1; r0 < m; r0 += 64) {
+      const int rows = min(64, m - r0);
+      __syncthreads();
+      for (int t = tid; t < rows * nbk; t += NT) {
+        int j = t / rows, rr = t - j * rows;
+        Cb[j * 64 + rr] = F[(long long)(j0 + j) * m + r0 + rr];
+      }
+      __syncthreads();
+      for (int t = tid; t < rows * nbk; t += NT) {
+        int j = t / rows, rr = t - j * rows;
+        T acc = Cb[j * 64 + rr];
+        for (int kk = j + 1; kk < nbk; ++kk) acc = cfma(Cb[kk * 64 + rr], Db[j * DIB + kk], acc);
+        F[(long long)(j0 + j) * m + r0 + rr] = T{-acc.x, -acc.y};
+      }
+    }
+    // N'_J = -U[0:j0, J] Uinv_J, 64 rows at a time.
+    for (int r0 = 0; r0 < j0; r0 += 64) {
+      const int rows = min(64, j0 - r0);
+      __syncthreads();
+      for (int t = tid; t < rows * nbk; t += NT) {
+        int j = t / rows, rr = t - j * rows;
+        Cb[j * 64 + rr] = F[(long long)(j0 + j) * m + r0 + rr];
+      }
+      __syncthreads();
+      for (int t = tid; t < rows * nbk; t += NT) {
+        int j = t / rows, rr = t - j * rows;
+        T acc = czero<T>();
+        for (int kk = 0; kk <= j; ++kk) acc = cfma(Cb[kk * 64 + rr], Db[j * DIB + kk], acc);
+        F[(long long)(j0 + j) * m + r0 + rr] = T{-acc.x, -acc.y};
+      }
+    }
+    // A single-block front also gets V' = -U11^{-1} U12 (64 columns at a time).
+    if (p <= DIB) {
+      for (int c0 = p; c0 < m; c0 += 64) {
+        const int cols = min(64, m - c0);
+        __syncthreads();
+        for (int t = tid; t < cols * p; t += NT) {
+          int c = t / p, r = t - c * p;
+          Cb[c * 64 + r] = F[(long long)(c0 + c) * m + r];
+        }
+        __syncthreads();
+        for (int t = tid; t < cols * p; t += NT) {
+          int c = t / p, r = t - c * p;
+          T acc = czero<T>();
+          for (int kk = r; kk < p; ++kk) acc = cfma(Db[kk * DIB + r], Cb[c * 64 + kk], acc);
+          F[(long long)(c0 + c) * m + r] = T{-acc.x, -acc.y};
+        }
+      }
+    }
     __syncthreads();
   }
 }
@@ -394,12 +465,11 @@ template <typename T>
 __global__ __launch_bounds__(NT) void k_fwd_small(LevelArgs a, const T* __restrict__ fac,
                                                   const int* __restrict__ piv, T* __restrict__ vec,
                                                   const double2* __restrict__ v) {
-  __shared__ T sh[4][2][64];
+  __shared__ T sh[4][1][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;                          // whole wavefront; no block barriers below
   T* vl = sh[wv][0];
-  T* yl = sh[wv][1];
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
@@ -433,35 +503,30 @@ __global__ __launch_bounds__(NT) void k_fwd_small(LevelArgs a, const T* __restri
   wave_sync();
   vl[lane] = val;
   wave_sync();
-  // y = L11^{-1} P b_p (unit lower inverse stored below the diagonal).
-  if (lane < p) {
-    T acc = val;
+  // One trapezoidal product: rows r < p get y_r = b_r + sum_{k<r} (L11^{-1})_{rk} b_k,
+  // rows r >= p get b_r + sum_{k<p} M'_{rk} b_k with M' = -L21 L11^{-1}.  When the
+  // rows fit in W = 64/G lanes, G lanes share a row (columns k = g, g+G, ...)
+  // and a fixed butterfly adds their partial sums.
+  const int W = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
+  const int G = 64 / W, g = lane / W, r = lane - g * W;
+  T acc = czero<T>();
+  if (r < m) {
+    const int kend = r < p ? r : p;
 #pragma unroll 8
-    for (int k = 0; k < p; ++k)
-      if (k < lane) acc = cfma(F[(long long)k * m + lane], vl[k], acc);
-    val = acc;
+    for (int k = g; k < kend; k += G) acc = cfma(F[(long long)k * m + r], vl[k], acc);
   }
-  yl[lane] = val;
-  wave_sync();
-  // b_q -= L21 y.
-  if (lane >= p && lane < m) {
-    T acc = czero<T>();
-#pragma unroll 8
-    for (int k = 0; k < p; ++k) acc = cfma(F[(long long)k * m + lane], yl[k], acc);
-    val = csub(val, acc);
-  }
-  if (lane < m) vec[f.vec_off + lane] = val;
+  for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
+  if (g == 0 && r < m) vec[f.vec_off + r] = cadd(vl[r], acc);
 }
 
 template <typename T>
 __global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restrict__ fac,
                                                   T* __restrict__ vec, T* __restrict__ u) {
-  __shared__ T sh[4][2][64];
+  __shared__ T sh[4][1][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;
   T* vl = sh[wv][0];
-  T* tl = sh[wv][1];
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
@@ -473,21 +538,18 @@ __global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restri
   }
   vl[lane] = val;
   wave_sync();
-  T t = czero<T>();
-  if (lane < p) {                                        // t = y - U12 x_q
+  // x_p = U11^{-1} y + V' x_q with V' = -U11^{-1} U12: one trapezoidal product,
+  // G lanes per row when p fits in W = 64/G lanes (fixed butterfly reduction).
+  {
+    const int W = p <= 16 ? 16 : (p <= 32 ? 32 : 64);
+    const int G = 64 / W, g = lane / W, r = lane - g * W;
     T acc = czero<T>();
+    if (r < p) {
 #pragma unroll 8
-    for (int j = p; j < m; ++j) acc = cfma(F[(long long)j * m + lane], vl[j], acc);
-    t = csub(val, acc);
-  }
-  tl[lane] = t;
-  wave_sync();
-  if (lane < p) {                                        // x_p = U11^{-1} t
-    T acc = czero<T>();
-#pragma unroll 8
-    for (int k = 0; k < p; ++k)
-      if (k >= lane) acc = cfma(F[(long long)k * m + lane], tl[k], acc);
-    val = acc;
+      for (int c = r + g; c < m; c += G) acc = cfma(F[(long long)c * m + r], vl[c], acc);
+    }
+    for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
+    if (lane < p) val = acc;                 // lane < p <= W: g = 0, r = lane
   }
   if (lane < m) vec[f.vec_off + lane] = val;
   if (lane < p) {
@@ -550,36 +612,48 @@ __device__ inline void block_gemv_sub(const T* __restrict__ A, int lda, int r0, 
   __syncthreads();
 }
 
-// One inverted diagonal block applied in place to x[j0 .. j0+n) (n <= DIB):
-// LOWER: x <- (I + strict lower of A) x;  UPPER: x <- (upper of A) x, with A the
-// block at column-major offset j0*(lda+1).  Four column groups per row,
-// reduced in a fixed order.  Ends with a workgroup barrier.
+// One block step of the sweeps over rows [r0, r1) and the block columns
+// [c0, c1), result written back into x (LDS) after all reads:
+//   LOWER:  x_r <- x_r + sum_{c0 <= c < min(c1, r)} A[c*lda + r] x_c
+//   !LOWER: x_r <- (r < keep ? x_r : 0) + sum_{max(c0, r) <= c < c1} A[c*lda + r] x_c
+// A thread per row when the rows fill the workgroup, else (row, column group)
+// pairs reduced in a fixed order through scr (NT).  ol: max_m scratch.
 template <typename T, bool LOWER>
-__device__ inline void block_trmv(const T* __restrict__ A, int lda, int j0, int n, T* x, T* scr,
-                                  int tid) {
-  const int r = tid & 63, g = tid >> 6;
-  T acc = czero<T>();
-  if (r < n) {
-    const T* Ar = A + (long long)j0 * lda + j0 + r;
-    for (int c = g; c < n; c += 4) {
-      bool use = LOWER ? (c < r) : (c >= r);
-      if (use) acc = cfma(Ar[(long long)c * lda], x[j0 + c], acc);
+__device__ inline void block_phase(const T* __restrict__ A, int lda, int r0, int r1, int c0, int c1,
+                                   int keep, T* x, T* ol, T* scr, int tid) {
+  const int R = r1 - r0;
+  if (R <= 0) return;
+  if (R >= NT / 2) {
+    for (int r = r0 + tid; r < r1; r += NT) {
+      const int lo = LOWER ? c0 : max(c0, r), hi = LOWER ? min(c1, r) : c1;
+      T acc = strided_dot(A + r, (long long)lda, lo, hi, 1, x);
+      ol[r] = (LOWER || r < keep) ? cadd(x[r], acc) : acc;
+    }
+  } else {
+    const int G = NT / R;
+    const int g = tid / R, rr = tid - g * R, r = r0 + rr;
+    T acc = czero<T>();
+    if (g < G) {
+      const int lo = LOWER ? c0 : max(c0, r), hi = LOWER ? min(c1, r) : c1;
+      acc = strided_dot(A + r, (long long)lda, lo + g, hi, G, x);
+    }
+    scr[tid] = acc;
+    __syncthreads();
+    if (tid < R) {
+      T sum = czero<T>();
+      for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * R + tid]);
+      const int rw = r0 + tid;
+      ol[rw] = (LOWER || rw < keep) ? cadd(x[rw], sum) : sum;
     }
   }
-  scr[tid] = acc;
   __syncthreads();
-  if (tid < n) {
-    T sum = LOWER ? x[j0 + tid] : czero<T>();
-    for (int gg = 0; gg < 4; ++gg) sum = cadd(sum, scr[gg * 64 + tid]);
-    x[j0 + tid] = sum;
-  }
+  for (int r = r0 + tid; r < r1; r += NT) x[r] = ol[r];
   __syncthreads();
 }
 
 // ---------------------------------------------------------------------------
-// Sweeps, large fronts: one workgroup per front, diagonal blocks of DIB
-// columns: inverted-block product, then the block GEMV below (forward) or
-// above (backward) it.
+// Sweeps, large fronts: one workgroup per front, one block_phase per DIB
+// columns of the separator (a single phase when p <= DIB).
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restrict__ fac,
@@ -618,14 +692,13 @@ __global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restri
     __syncthreads();
   }
   const int* perm = piv + f.piv_off;
-  for (int i = tid; i < m; i += NT) tmp[i] = i < p ? vl[perm[i]] : vl[i];
+  for (int i = tid; i < p; i += NT) tmp[i] = vl[perm[i]];
   __syncthreads();
-  for (int i = tid; i < m; i += NT) vl[i] = tmp[i];
+  for (int i = tid; i < p; i += NT) vl[i] = tmp[i];
   __syncthreads();
   for (int j0 = 0; j0 < p; j0 += DIB) {
-    const int nbk = min(DIB, p - j0);
-    block_trmv<T, true>(F, m, j0, nbk, vl, scr, tid);
-    block_gemv_sub(F, m, j0 + nbk, m, j0, j0 + nbk, vl, vl, scr, tid);
+    const int j1 = min(j0 + DIB, p);
+    block_phase<T, true>(F, m, j0, m, j0, j1, 0, vl, tmp, scr, tid);
   }
   T* out = vec + f.vec_off;
   for (int i = tid; i < m; i += NT) out[i] = vl[i];
@@ -637,6 +710,7 @@ __global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restri
   extern __shared__ unsigned char smem_raw[];
   T* scr = reinterpret_cast<T*>(smem_raw);
   T* vl = scr + NT;
+  T* tmp = vl + a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
@@ -649,11 +723,15 @@ __global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restri
     for (int i = tid; i < f.q; i += NT) vl[p + i] = pv[cm[i]];
   }
   __syncthreads();
-  block_gemv_sub(F, m, 0, p, p, m, vl, vl, scr, tid);     // y - U12 x_q
-  for (int j0 = ((p - 1) / DIB) * DIB; j0 >= 0; j0 -= DIB) {
-    const int nbk = min(DIB, p - j0);
-    block_trmv<T, false>(F, m, j0, nbk, vl, scr, tid);
-    block_gemv_sub(F, m, 0, j0, j0, j0 + nbk, vl, vl, scr, tid);
+  if (p <= DIB) {
+    // x_p = U11^{-1} y + V' x_q in one phase (V' = -U11^{-1} U12 stored).
+    block_phase<T, false>(F, m, 0, p, 0, m, 0, vl, tmp, scr, tid);
+  } else {
+    block_gemv_sub(F, m, 0, p, p, m, vl, vl, scr, tid);   // t = y - U12 x_q
+    for (int j0 = ((p - 1) / DIB) * DIB; j0 >= 0; j0 -= DIB) {
+      const int j1 = min(j0 + DIB, p);
+      block_phase<T, false>(F, m, 0, j1, j0, j1, j0, vl, tmp, scr, tid);
+    }
   }
   const int* vars = a.vars + f.var_off;
   const long long uo = a.subs[f.sub].u_off;
@@ -708,7 +786,7 @@ int max_lds() {
 
 template <typename T, int NB>
 void large_launch(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag, double tau) {
-  size_t lds = std::max((size_t)a.max_m * NB, (size_t)DIB * DIB + 2 * DIB) * sizeof(T);
+  size_t lds = std::max((size_t)a.max_m * NB, (size_t)2 * DIB * DIB + 2 * DIB) * sizeof(T);
   hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, piv, flag,
                      tau);
 }
@@ -766,7 +844,7 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* fac, T* vec, 
   if (a.max_m <= 64) {
     hipLaunchKernelGGL(k_bwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, vec, u);
   } else {
-    size_t lds = ((size_t)NT + (size_t)a.max_m) * sizeof(T);
+    size_t lds = ((size_t)NT + 2 * (size_t)a.max_m) * sizeof(T);
     hipLaunchKernelGGL(k_bwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, fac, vec, u);
   }
 }
