@@ -59,8 +59,19 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
 
     for _ in range(warmup):
         step()
+    profile, dom = {}, None
+    if timing:
+        # One extra step with every kernel class timed gives the per-class
+        # breakdown and the dominant class; the timed region then brackets only
+        # that class's launches with events, which perturbs it least.
+        ctx.set_timing(True)
+        step()
+        for k, name in enumerate(stf.KERNEL_CLASSES):
+            profile[name] = ctx.kernel_stats(k)
+        ctx.set_timing(False)
+        dom = max(profile, key=lambda k: profile[k][0])
+        ctx.set_timing(True, classes=[dom])
     infos.clear()
-    ctx.set_timing(timing)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -69,12 +80,11 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     t1 = time.perf_counter()
     stats = {}
     if timing:
-        for k, name in enumerate(stf.KERNEL_CLASSES):
-            stats[name] = ctx.kernel_stats(k)
+        stats[dom] = ctx.kernel_stats(dom)
         ctx.set_timing(False)
     info = pb.info()
     pb.close()
-    return (t1 - t0) / steps, infos, stats, info
+    return (t1 - t0) / steps, infos, stats, info, profile
 
 
 def roofline(stf, w, prec, infos, stats, steps):
@@ -91,7 +101,7 @@ def roofline(stf, w, prec, infos, stats, steps):
         "sweep_bwd": ("hbm", ref["factor_entries"] / 2 * es * iters / 1e9),
         "stencil": ("hbm", N * (48 * iters + 64 * (cycles + steps)) / 1e9),
     }
-    dom = max(stats, key=lambda k: stats[k][0])
+    dom = next(iter(stats))
     ms, launches = stats[dom]
     if dom not in units:
         return dom, None
@@ -163,9 +173,10 @@ def main():
 
     w = workload()
     ctx = stf.Context(0)
-    t_mixed, inf_mixed, stats, info = run_form(stf, torch, ctx, w, stf.STF_C64, args.steps,
-                                              args.warmup, args.tol, args.restart, args.max_iter,
-                                              not args.no_timing)
+    t_mixed, inf_mixed, stats, info, profile = run_form(stf, torch, ctx, w, stf.STF_C64,
+                                                       args.steps, args.warmup, args.tol,
+                                                       args.restart, args.max_iter,
+                                                       not args.no_timing)
     ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in inf_mixed)
     N = w.nx * w.ny
     out = {"metric": METRIC, "value": round(N / t_mixed, 1), "unit": "DoF/s", "n_gpus": 1,
@@ -181,10 +192,10 @@ def main():
     if stats:
         dom, rl = roofline(stf, w, stf.STF_C64, inf_mixed, stats, args.steps)
         out["roofline"] = rl
-        out["kernel_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in stats.items()}
+        out["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in profile.items()}
     if not args.no_plain:
-        t_plain, inf_plain, _, _ = run_form(stf, torch, ctx, w, stf.STF_C128, 1, 1, args.tol,
-                                            args.restart, args.max_iter, False)
+        t_plain, inf_plain, _, _, _ = run_form(stf, torch, ctx, w, stf.STF_C128, 1, 1, args.tol,
+                                               args.restart, args.max_iter, False)
         out["plain_fp64"] = {"value": round(N / t_plain, 1), "ms_per_step": round(t_plain * 1e3, 3),
                              "iters": inf_plain[0]["iters"]}
         out["speedup_vs_plain"] = round(t_plain / t_mixed, 3)

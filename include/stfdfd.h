@@ -134,7 +134,10 @@ enum {
   STF_K_SWEEP_FWD = 4, STF_K_SWEEP_BWD = 5, STF_K_SCATTER = 6, STF_K_ARNOLDI = 7,
   STF_K_UPDATE = 8, STF_K_COUNT = 9
 };
-stf_status  stf_ctx_set_timing(stf_ctx ctx, int enable);  /* enabling resets the counters */
+stf_status  stf_ctx_set_timing(stf_ctx ctx, int enable);  /* all classes; enabling resets the counters */
+/* Timing restricted to the classes whose bits (1 << STF_K_*) are set in mask (0 = off);
+ * resets the counters.  Fewer bracketed launches perturb the timed region less. */
+stf_status  stf_ctx_set_timing_mask(stf_ctx ctx, uint32_t mask);
 /* Synchronises the stream, then reports the summed duration (ms) and launch count
  * of kernel class `cls` since timing was enabled. */
 stf_status  stf_ctx_kernel_stats(stf_ctx ctx, int cls, double* total_ms, int64_t* launches);

@@ -158,8 +158,17 @@ class Context:
         except Exception:
             pass
 
-    def set_timing(self, on):
-        _check(self.handle, self._lib.stf_ctx_set_timing(self.handle, int(bool(on))))
+    def set_timing(self, on, classes=None):
+        """Per-launch HIP event timing: on/off for all classes, or only for the
+        named classes (KERNEL_CLASSES entries) when `classes` is given."""
+        if classes is None:
+            _check(self.handle, self._lib.stf_ctx_set_timing(self.handle, int(bool(on))))
+            return
+        mask = 0
+        if on:
+            for c in classes:
+                mask |= 1 << (KERNEL_CLASSES.index(c) if isinstance(c, str) else int(c))
+        _check(self.handle, self._lib.stf_ctx_set_timing_mask(self.handle, mask))
 
     def kernel_stats(self, cls):
         if isinstance(cls, str):

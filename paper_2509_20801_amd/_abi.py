@@ -50,6 +50,7 @@ EXPORTS = {
     "stf_ctx_destroy": (None, [C.c_void_p]),
     "stf_last_error": (C.c_char_p, [C.c_void_p]),
     "stf_ctx_set_timing": (C.c_int, [C.c_void_p, C.c_int]),
+    "stf_ctx_set_timing_mask": (C.c_int, [C.c_void_p, C.c_uint32]),
     "stf_ctx_kernel_stats": (C.c_int, [C.c_void_p, C.c_int, C.POINTER(C.c_double),
                                        C.POINTER(C.c_int64)]),
     "stf_plan_query": (C.c_int, [C.POINTER(Params), C.POINTER(PlanInfo)]),

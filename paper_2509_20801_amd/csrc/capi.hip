@@ -56,11 +56,13 @@ struct stf_ctx_s {
   std::map<std::tuple<int, int, int>, std::shared_ptr<const SymShape>> shapes;
   // Timing: pending event pairs per kernel class, folded totals.
   bool timing = false;
+  uint32_t timing_mask = 0;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[STF_K_COUNT];
   std::vector<hipEvent_t> pool;
   double total_ms[STF_K_COUNT] = {};
   int64_t launches[STF_K_COUNT] = {};
   double* pinned = nullptr;     // small pinned host staging area
+  hipEvent_t iter_ev[2] = {nullptr, nullptr};   // per-iteration estimate copies
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -104,7 +106,7 @@ struct Timed {
   int cls;
   hipEvent_t b = nullptr;
   Timed(stf_ctx c_, int cls_) : c(c_), cls(cls_) {
-    if (c->timing) {
+    if (c->timing && (c->timing_mask >> cls & 1u)) {
       if (c->npending() > 16384) c->fold();
       b = c->get_event();
       HIP_CHECK(hipEventRecord(b, c->stream));
@@ -141,12 +143,12 @@ struct stf_problem_s {
   bool assembled = false, factored = false;
   int prec = STF_C128;
   int64_t n_fronts = 0;
-  int64_t fac_elems = 0, vec_elems = 0, piv_elems = 0, u_elems = 0;
+  int64_t fac_elems = 0, upk_elems = 0, vec_elems = 0, piv_elems = 0, u_elems = 0;
   std::vector<Level> levels;     // by depth
 
   // Device state.
   DBuf keps, gcoef, lcoef, subs, fronts, vars, cmap, ents, children;
-  DBuf fac, piv, vec, u, cover_x, cover_y, flag;
+  DBuf fac, upk, piv, vec, u, cover_x, cover_y, flag;
   DBuf partial, npartial, scal;    // reduction scratch, device scalars
   DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
   DBuf hb, hx, cells;              // staging for host inputs
@@ -176,7 +178,7 @@ struct stf_problem_s {
   }
   int64_t device_bytes() const {
     const DBuf* all[] = {&keps, &gcoef, &lcoef, &subs, &fronts, &vars, &cmap, &ents,
-                         &children, &fac, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
+                         &children, &fac, &upk, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
                          &npartial,
                          &scal, &kV, &kZ, &kw, &kr, &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &hb,
                          &hx, &cells};
@@ -307,7 +309,7 @@ void build_device_state(stf_problem pb) {
   for (size_t t = 0; t < order.size(); ++t) inst[order[t]] = (int)t;
   std::vector<FrontDev> fr(recs.size());
   std::vector<int> kids;
-  long long fac_off = 0;
+  long long fac_off = 0, upk_off = 0;
   long long vec_off = 0, piv_off = 0;
   for (size_t t = 0; t < order.size(); ++t) {
     const Rec& rc = recs[order[t]];
@@ -317,6 +319,7 @@ void build_device_state(stf_problem pb) {
     FrontDev& d = fr[t];
     int m = f.p + f.q;
     d.fac_off = fac_off;
+    d.upk_off = upk_off;
     d.vec_off = (int)vec_off;
     d.piv_off = (int)piv_off;
     d.p = f.p;
@@ -333,9 +336,11 @@ void build_device_state(stf_problem pb) {
     for (int c = 0; c < f.nchild; ++c)
       kids.push_back(inst[sub_base[rc.sub] + sh.children[f.child_off + c]]);
     fac_off += (long long)m * m;
+    upk_off += (long long)f.p * m;
     vec_off += m;
     piv_off += f.p;
   }
+  pb->upk_elems = upk_off;
   STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
   // Embedded parent/children vector offsets (all offsets are known now).
   for (size_t t = 0; t < fr.size(); ++t) {
@@ -378,6 +383,7 @@ void build_device_state(stf_problem pb) {
 
   size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
   pb->fac.alloc((size_t)pb->fac_elems * es);
+  pb->upk.alloc((size_t)pb->upk_elems * es);
   pb->piv.alloc((size_t)pb->piv_elems * sizeof(int));
   pb->vec.alloc((size_t)pb->vec_elems * es);
   pb->u.alloc((size_t)pb->u_elems * es);
@@ -418,7 +424,8 @@ int factor_t(stf_problem pb) {
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
   for (int d = pb->max_depth; d >= 0; --d) {
     Timed t(pb->ctx, K_FRONT_LU);
-    launch_front_factor<T>(st, pb->level_args(d), fac, pb->piv.as<int>(), pb->flag.as<int>(), tau);
+    launch_front_factor<T>(st, pb->level_args(d), fac, pb->upk.as<T>(), pb->piv.as<int>(),
+                           pb->flag.as<int>(), tau);
   }
   HIP_CHECK(hipGetLastError());
   int h = 0;
@@ -439,7 +446,7 @@ void precond_t(stf_problem pb, const double2* v, double2* z) {
   }
   for (int d = 0; d <= pb->max_depth; ++d) {
     Timed t(pb->ctx, K_SWEEP_BWD);
-    launch_sweep_bwd<T>(st, pb->level_args(d), fac, vec, pb->u.as<T>());
+    launch_sweep_bwd<T>(st, pb->level_args(d), pb->upk.as<T>(), vec, pb->u.as<T>());
   }
   Timed t(pb->ctx, K_SCATTER);
   launch_scatter<T>(st, pb->u.as<T>(), pb->subs.as<SubDev>(), pb->cover_x.as<int4>(),
@@ -577,9 +584,10 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
     hp[8] = rnorm;
     hp[9] = 0.0;
     HIP_CHECK(hipMemcpyAsync(pb->kg.p, hp + 8, sizeof(double2), hipMemcpyHostToDevice, st));
-    int k = 0;
-    bool stop = false;
-    for (int j = 0; j < m && !stop; ++j) {
+    // Iteration j+1 is enqueued before the host waits for iteration j's
+    // residual estimate (copied to pinned memory behind an event), so the GPU
+    // queue does not drain between iterations.
+    auto launch_iter = [&](int j) {
       double2* vj = V + (long long)j * N;
       double2* zj = Z + (long long)j * N;
       precond_rounds(pb, vj, zj, rounds);
@@ -611,14 +619,37 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
         launch_givens(st, H, pb->kh1.as<double2>(), sc + 3, pb->kcs.as<double>(),
                       pb->ksn.as<double2>(), pb->kg.as<double2>(), j, m + 1, sc + 4);
       }
-      HIP_CHECK(hipMemcpyAsync(hp + 4, sc + 3, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipStreamSynchronize(st));
-      ++it;
-      k = j + 1;
-      double est = hp[5];
+      HIP_CHECK(hipMemcpyAsync(hp + 16 + 2 * (j & 1), sc + 3, 2 * sizeof(double),
+                               hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipEventRecord(c->iter_ev[j & 1], st));
+    };
+    // Waits for iteration j's estimate; returns true on convergence or breakdown.
+    auto check_iter = [&](int j) {
+      HIP_CHECK(hipEventSynchronize(c->iter_ev[j & 1]));
+      const double wn = hp[16 + 2 * (j & 1)], est = hp[17 + 2 * (j & 1)];
       hist(est / bnorm);
       if (!std::isfinite(est)) throw Error(STF_ENAN, "non-finite residual estimate");
-      if (est <= o.tol * bnorm || hp[4] == 0.0 || it >= o.max_iter) stop = true;
+      return est <= o.tol * bnorm || wn == 0.0;
+    };
+    int k = 0, launched = 0;
+    bool stop = false;
+    for (int j = 0; j < m && it < o.max_iter; ++j) {
+      launch_iter(j);
+      ++it;
+      launched = j + 1;
+      if (j >= 1 && check_iter(j - 1)) {
+        // Iteration j-1 met the tolerance (or broke down): the speculative
+        // iteration j is discarded, so the iterates equal those of the
+        // synchronous algorithm.
+        k = j;
+        --it;
+        stop = true;
+        break;
+      }
+    }
+    if (!stop && launched > 0) {
+      check_iter(launched - 1);
+      k = launched;
     }
     {
       Timed t(c, K_UPDATE);
@@ -676,6 +707,8 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
       c->own_stream = true;
     }
     HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault));
+    for (int e = 0; e < 2; ++e)
+      HIP_CHECK(hipEventCreateWithFlags(&c->iter_ev[e], hipEventDisableTiming));
   });
   if (s != STF_OK) {
     g_noctx_error = c->last_error;
@@ -697,6 +730,8 @@ void stf_ctx_destroy(stf_ctx c) {
       (void)hipEventDestroy(pr.second);
     }
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  for (int e = 0; e < 2; ++e)
+    if (c->iter_ev[e]) (void)hipEventDestroy(c->iter_ev[e]);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -707,7 +742,7 @@ const char* stf_last_error(stf_ctx c) {
   return c->last_error.c_str();
 }
 
-stf_status stf_ctx_set_timing(stf_ctx c, int enable) {
+stf_status stf_ctx_set_timing_mask(stf_ctx c, uint32_t mask) {
   if (!c) return STF_EINVAL;
   return guard(c, [&] {
     c->fold();
@@ -715,8 +750,13 @@ stf_status stf_ctx_set_timing(stf_ctx c, int enable) {
       c->total_ms[k] = 0.0;
       c->launches[k] = 0;
     }
-    c->timing = enable != 0;
+    c->timing_mask = mask & ((1u << STF_K_COUNT) - 1u);
+    c->timing = c->timing_mask != 0;
   });
+}
+
+stf_status stf_ctx_set_timing(stf_ctx c, int enable) {
+  return stf_ctx_set_timing_mask(c, enable ? (1u << STF_K_COUNT) - 1u : 0u);
 }
 
 stf_status stf_ctx_kernel_stats(stf_ctx c, int cls, double* total_ms, int64_t* launches) {

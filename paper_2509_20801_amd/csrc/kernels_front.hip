@@ -37,6 +37,7 @@ namespace {
 constexpr int NT = 256;        // threads of a large-front workgroup
 constexpr int UC = 32;         // columns of U staged in LDS per trailing-update chunk
 constexpr int DIB = 64;        // inverted diagonal blocks of L11 and U11
+constexpr int CR = 32;         // rows (or columns) staged per chunk by the inversion tail
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -187,8 +188,8 @@ __device__ inline void invert_upper(T* G, int ld, int n, T* col, int lane) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict__ fac,
-                                                     int* __restrict__ piv, int* __restrict__ flag,
-                                                     double tau) {
+                                                     T* __restrict__ upk, int* __restrict__ piv,
+                                                     int* __restrict__ flag, double tau) {
   using R = typename RealOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   T* G = reinterpret_cast<T*>(smem_raw);
@@ -252,6 +253,12 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   T* F = fac + f.fac_off;
   const long long mm = (long long)m * m;
   for (long long t = lane; t < mm; t += 64) F[t] = G[t];
+  // Backward operator rows 0..p-1, packed with leading dimension p.
+  T* U = upk + f.upk_off;
+  for (int t = lane; t < p * m; t += 64) {
+    int c = t / p, r = t - c * p;
+    U[t] = G[(long long)c * m + r];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -263,8 +270,8 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
 // ---------------------------------------------------------------------------
 template <typename T, int NB>
 __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict__ fac,
-                                                     int* __restrict__ piv, int* __restrict__ flag,
-                                                     double tau) {
+                                                     T* __restrict__ upk, int* __restrict__ piv,
+                                                     int* __restrict__ flag, double tau) {
   using R = typename RealOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
   T* P = reinterpret_cast<T*>(smem_raw);           // panel, column-major, ld = ldp
@@ -321,7 +328,8 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       int k = t / nr, r = t - k * nr;
       F[(long long)(kb + k) * m + kb + r] = P[k * ldp + r];
     }
-    // Row exchanges in the columns outside the panel, in pivot order.
+    // Row exchanges in the columns outside the panel, in pivot order, one
+    // column per thread.
     for (int c = tid; c < m; c += NT) {
       if (c >= kb && c < kb + nb) continue;
       T* Fc = F + (long long)c * m;
@@ -399,59 +407,65 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       int c = t / nbk, r = t - c * nbk;
       F[(long long)(j0 + c) * m + j0 + r] = Db[c * DIB + r];
     }
-    T* Cb = Db + DIB * DIB + 2 * DIB;           // 64 x DIB staging chunk
+    T* Cb = Db + DIB * DIB + 2 * DIB;           // CR x DIB staging chunk
     // M'_J = -L[j1:m, J] Linv_J, 64 rows at a time.
     const int j1 = j0 + nbk;
-    for (int r0 = j1; r0 < m; r0 += 64) {
-      const int rows = min(64, m - r0);
+    for (int r0 = j1; r0 < m; r0 += CR) {
+      const int rows = min(CR, m - r0);
       __syncthreads();
       for (int t = tid; t < rows * nbk; t += NT) {
         int j = t / rows, rr = t - j * rows;
-        Cb[j * 64 + rr] = F[(long long)(j0 + j) * m + r0 + rr];
+        Cb[j * CR + rr] = F[(long long)(j0 + j) * m + r0 + rr];
       }
       __syncthreads();
       for (int t = tid; t < rows * nbk; t += NT) {
         int j = t / rows, rr = t - j * rows;
-        T acc = Cb[j * 64 + rr];
-        for (int kk = j + 1; kk < nbk; ++kk) acc = cfma(Cb[kk * 64 + rr], Db[j * DIB + kk], acc);
+        T acc = Cb[j * CR + rr];
+        for (int kk = j + 1; kk < nbk; ++kk) acc = cfma(Cb[kk * CR + rr], Db[j * DIB + kk], acc);
         F[(long long)(j0 + j) * m + r0 + rr] = T{-acc.x, -acc.y};
       }
     }
     // N'_J = -U[0:j0, J] Uinv_J, 64 rows at a time.
-    for (int r0 = 0; r0 < j0; r0 += 64) {
-      const int rows = min(64, j0 - r0);
+    for (int r0 = 0; r0 < j0; r0 += CR) {
+      const int rows = min(CR, j0 - r0);
       __syncthreads();
       for (int t = tid; t < rows * nbk; t += NT) {
         int j = t / rows, rr = t - j * rows;
-        Cb[j * 64 + rr] = F[(long long)(j0 + j) * m + r0 + rr];
+        Cb[j * CR + rr] = F[(long long)(j0 + j) * m + r0 + rr];
       }
       __syncthreads();
       for (int t = tid; t < rows * nbk; t += NT) {
         int j = t / rows, rr = t - j * rows;
         T acc = czero<T>();
-        for (int kk = 0; kk <= j; ++kk) acc = cfma(Cb[kk * 64 + rr], Db[j * DIB + kk], acc);
+        for (int kk = 0; kk <= j; ++kk) acc = cfma(Cb[kk * CR + rr], Db[j * DIB + kk], acc);
         F[(long long)(j0 + j) * m + r0 + rr] = T{-acc.x, -acc.y};
       }
     }
     // A single-block front also gets V' = -U11^{-1} U12 (64 columns at a time).
     if (p <= DIB) {
-      for (int c0 = p; c0 < m; c0 += 64) {
-        const int cols = min(64, m - c0);
+      for (int c0 = p; c0 < m; c0 += CR) {
+        const int cols = min(CR, m - c0);
         __syncthreads();
         for (int t = tid; t < cols * p; t += NT) {
           int c = t / p, r = t - c * p;
-          Cb[c * 64 + r] = F[(long long)(c0 + c) * m + r];
+          Cb[c * DIB + r] = F[(long long)(c0 + c) * m + r];
         }
         __syncthreads();
         for (int t = tid; t < cols * p; t += NT) {
           int c = t / p, r = t - c * p;
           T acc = czero<T>();
-          for (int kk = r; kk < p; ++kk) acc = cfma(Db[kk * DIB + r], Cb[c * 64 + kk], acc);
+          for (int kk = r; kk < p; ++kk) acc = cfma(Db[kk * DIB + r], Cb[c * DIB + kk], acc);
           F[(long long)(c0 + c) * m + r] = T{-acc.x, -acc.y};
         }
       }
     }
     __syncthreads();
+  }
+  // Backward operator rows 0..p-1, packed with leading dimension p.
+  T* U = upk + f.upk_off;
+  for (int t = tid; t < p * m; t += NT) {
+    int c = t / p, r = t - c * p;
+    U[t] = F[(long long)c * m + r];
   }
 }
 
@@ -520,7 +534,7 @@ __global__ __launch_bounds__(NT) void k_fwd_small(LevelArgs a, const T* __restri
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restrict__ fac,
+__global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restrict__ upk,
                                                   T* __restrict__ vec, T* __restrict__ u) {
   __shared__ T sh[4][1][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -529,7 +543,7 @@ __global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restri
   T* vl = sh[wv][0];
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p;
-  const T* F = fac + f.fac_off;
+  const T* U = upk + f.upk_off;
   T val = czero<T>();
   if (lane < p) {
     val = vec[f.vec_off + lane];
@@ -546,7 +560,7 @@ __global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restri
     T acc = czero<T>();
     if (r < p) {
 #pragma unroll 8
-      for (int c = r + g; c < m; c += G) acc = cfma(F[(long long)c * m + r], vl[c], acc);
+      for (int c = r + g; c < m; c += G) acc = cfma(U[c * p + r], vl[c], acc);
     }
     for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
     if (lane < p) val = acc;                 // lane < p <= W: g = 0, r = lane
@@ -705,7 +719,7 @@ __global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restri
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restrict__ fac,
+__global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restrict__ upk,
                                                   T* __restrict__ vec, T* __restrict__ u) {
   extern __shared__ unsigned char smem_raw[];
   T* scr = reinterpret_cast<T*>(smem_raw);
@@ -713,7 +727,7 @@ __global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restri
   T* tmp = vl + a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
-  const T* F = fac + f.fac_off;
+  const T* U = upk + f.upk_off;                          // rows 0..p-1, leading dimension p
   const int tid = threadIdx.x;
   T* fv = vec + f.vec_off;
   for (int i = tid; i < p; i += NT) vl[i] = fv[i];
@@ -725,12 +739,12 @@ __global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restri
   __syncthreads();
   if (p <= DIB) {
     // x_p = U11^{-1} y + V' x_q in one phase (V' = -U11^{-1} U12 stored).
-    block_phase<T, false>(F, m, 0, p, 0, m, 0, vl, tmp, scr, tid);
+    block_phase<T, false>(U, p, 0, p, 0, m, 0, vl, tmp, scr, tid);
   } else {
-    block_gemv_sub(F, m, 0, p, p, m, vl, vl, scr, tid);   // t = y - U12 x_q
+    block_gemv_sub(U, p, 0, p, p, m, vl, vl, scr, tid);   // t = y - U12 x_q
     for (int j0 = ((p - 1) / DIB) * DIB; j0 >= 0; j0 -= DIB) {
       const int j1 = min(j0 + DIB, p);
-      block_phase<T, false>(F, m, 0, j1, j0, j1, j0, vl, tmp, scr, tid);
+      block_phase<T, false>(U, p, 0, j1, j0, j1, j0, vl, tmp, scr, tid);
     }
   }
   const int* vars = a.vars + f.var_off;
@@ -785,10 +799,11 @@ int max_lds() {
 }
 
 template <typename T, int NB>
-void large_launch(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag, double tau) {
-  size_t lds = std::max((size_t)a.max_m * NB, (size_t)2 * DIB * DIB + 2 * DIB) * sizeof(T);
-  hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, piv, flag,
-                     tau);
+void large_launch(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int* piv, int* flag,
+                  double tau) {
+  size_t lds = std::max((size_t)a.max_m * NB, (size_t)DIB * DIB + 2 * DIB + (size_t)CR * DIB) * sizeof(T);
+  hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, upk, piv,
+                     flag, tau);
 }
 
 }  // namespace
@@ -802,28 +817,33 @@ int small_factor_limit(size_t elem) {
 }
 
 template <typename T>
-void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag,
+void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int* piv, int* flag,
                          double tau) {
   if (a.max_m <= small_factor_limit(sizeof(T))) {
     size_t lds = ((size_t)a.max_m * a.max_m + 128) * sizeof(T);
-    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, piv, flag, tau);
+    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, upk, piv, flag,
+                       tau);
     return;
   }
   // Panel width: as wide as the LDS allows for the largest front of the level
   // (the staged U chunk and small arrays take the rest).
   const size_t budget = (size_t)max_lds() - (size_t)UC * 33 * sizeof(T) - 512;
   const size_t per_col = (size_t)a.max_m * sizeof(T);
-  const int nb_max = sizeof(T) == 16 ? 16 : 32;
+  // Narrower panels for smaller fronts: fewer registers per thread (higher
+  // occupancy) where the fronts are many and small.
+  int nb_max = sizeof(T) == 16 ? 16 : 32;
+  if (a.max_m <= 128) nb_max = 8;
+  else if (a.max_m <= 256) nb_max = std::min(nb_max, 16);
   int nb = 1;
   while (nb * 2 <= nb_max && per_col * nb * 2 <= budget) nb *= 2;
   if (per_col * nb > budget) throw Error(STF_EINVAL, "front too large for the LDS panel");
   switch (nb) {
-    case 32: large_launch<T, 32>(st, a, fac, piv, flag, tau); break;
-    case 16: large_launch<T, 16>(st, a, fac, piv, flag, tau); break;
-    case 8: large_launch<T, 8>(st, a, fac, piv, flag, tau); break;
-    case 4: large_launch<T, 4>(st, a, fac, piv, flag, tau); break;
-    case 2: large_launch<T, 2>(st, a, fac, piv, flag, tau); break;
-    default: large_launch<T, 1>(st, a, fac, piv, flag, tau); break;
+    case 32: large_launch<T, 32>(st, a, fac, upk, piv, flag, tau); break;
+    case 16: large_launch<T, 16>(st, a, fac, upk, piv, flag, tau); break;
+    case 8: large_launch<T, 8>(st, a, fac, upk, piv, flag, tau); break;
+    case 4: large_launch<T, 4>(st, a, fac, upk, piv, flag, tau); break;
+    case 2: large_launch<T, 2>(st, a, fac, upk, piv, flag, tau); break;
+    default: large_launch<T, 1>(st, a, fac, upk, piv, flag, tau); break;
   }
 }
 
@@ -840,12 +860,12 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
 }
 
 template <typename T>
-void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* fac, T* vec, T* u) {
+void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u) {
   if (a.max_m <= 64) {
-    hipLaunchKernelGGL(k_bwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, vec, u);
+    hipLaunchKernelGGL(k_bwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u);
   } else {
     size_t lds = ((size_t)NT + 2 * (size_t)a.max_m) * sizeof(T);
-    hipLaunchKernelGGL(k_bwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, fac, vec, u);
+    hipLaunchKernelGGL(k_bwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, upk, vec, u);
   }
 }
 
@@ -857,7 +877,7 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
 }
 
 #define STF_INST(T)                                                                             \
-  template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, int*, int*, double);  \
+  template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, int*, int*, double); \
   template void launch_sweep_fwd<T>(hipStream_t, const LevelArgs&, const T*, const int*, T*,    \
                                     const double2*);                                            \
   template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*);           \

@@ -127,6 +127,7 @@ struct SubDev {
 // offsets are embedded so that the sweeps read one descriptor per front.
 struct FrontDev {
   long long fac_off;        // element offset of the m x m front (column-major)
+  long long upk_off;        // element offset of the packed backward operator (p x m, ld p)
   int vec_off;              // element offset of the front vector (m elements)
   int piv_off;              // offset of the p pivot entries
   int p, q;
@@ -185,13 +186,14 @@ struct LevelArgs {
 // Assembly (original entries + extend-add of the children) and partial LU of
 // every front of one level.
 template <typename T>
-void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, int* piv, int* flag,
+void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int* piv, int* flag,
                          double tau);
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
                       const double2* v);
+// upk: packed backward operators (rows 0..p-1 of every front, leading dimension p).
 template <typename T>
-void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* fac, T* vec, T* u);
+void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u);
 template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
                     const int4* cover_y, int px, int nx, int ny, double2* z);
