@@ -43,7 +43,7 @@ void upload(DBuf& d, const std::vector<T>& h, hipStream_t st) {
 }
 
 struct Level {
-  int off = 0, n = 0, max_m = 0, max_pm = 0;
+  int off = 0, n = 0, max_m = 0, max_pm = 0, max_p = 0;
 };
 
 }  // namespace
@@ -174,6 +174,7 @@ struct stf_problem_s {
     a.nx = prm.nx;
     a.max_m = levels[d].max_m;
     a.max_pm = levels[d].max_pm;
+    a.max_p = levels[d].max_p;
     return a;
   }
   int64_t device_bytes() const {
@@ -374,6 +375,7 @@ void build_device_state(stf_problem pb) {
     L.n += 1;
     L.max_m = std::max(L.max_m, fr[t].p + fr[t].q);
     L.max_pm = std::max(L.max_pm, fr[t].p * (fr[t].p + fr[t].q));
+    L.max_p = std::max(L.max_p, fr[t].p);
   }
   pb->max_depth = (int)pb->levels.size() - 1;
   upload(pb->fronts, fr, st);

@@ -261,6 +261,46 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   }
 }
 
+// One step of folding the per-block sweep operators of a large separator into
+// full ones, on the columns [c0, c1) (at most DIB) of F, by the phase of the
+// diagonal block [k0, k1) (its inverse on the diagonal, M' below, N' above):
+//   LOWER: rows r >= k0:  X_r <- X_r + sum_{k0 <= k < min(k1, r)} F[r,k] X_k
+//   UPPER: rows r < k1:   X_r <- [r < k0] X_r + sum_{max(k0, r) <= k < k1} F[r,k] X_k
+// where X = F[:, c0:c1) and X_k (k in the block) is read from a copy staged in
+// LDS (Xs, DIB x DIB) before any write.  Begins with a workgroup barrier.
+template <typename T, bool LOWER>
+__device__ void fold_step(T* __restrict__ F, int m, int k0, int k1, int c0, int c1, T* Xs,
+                          int tid) {
+  constexpr int CC = 8;                       // columns per work item
+  const int w = c1 - c0, wk = k1 - k0;
+  __syncthreads();
+  for (int t = tid; t < wk * w; t += NT) {
+    int c = t / wk, k = t - c * wk;
+    Xs[k * DIB + c] = F[(long long)(c0 + c) * m + k0 + k];
+  }
+  __syncthreads();
+  const int rlo = LOWER ? k0 : 0, rhi = LOWER ? m : k1;
+  const int R = rhi - rlo, nch = (w + CC - 1) / CC;
+  for (int t = tid; t < R * nch; t += NT) {
+    const int ch = t / R, r = rlo + (t - ch * R), cb = ch * CC;
+    T acc[CC];
+#pragma unroll
+    for (int u = 0; u < CC; ++u)
+      acc[u] = (cb + u < w && (LOWER || r < k0)) ? F[(long long)(c0 + cb + u) * m + r] : czero<T>();
+    const int klo = LOWER ? k0 : max(k0, r), khi = LOWER ? min(k1, r) : k1;
+#pragma unroll 4
+    for (int k = klo; k < khi; ++k) {
+      const T av = F[(long long)k * m + r];
+      const T* xs = Xs + (k - k0) * DIB + cb;
+#pragma unroll
+      for (int u = 0; u < CC; ++u) acc[u] = cfma(av, xs[u], acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < CC; ++u)
+      if (cb + u < w) F[(long long)(c0 + cb + u) * m + r] = acc[u];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Factorisation, large fronts: one 256-thread workgroup per front.  Assembly in
 // global memory, then blocked right-looking LU: a panel of NB columns is
@@ -461,6 +501,33 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
     }
     __syncthreads();
   }
+  // A separator wider than one block: fold the per-block operators into the
+  // full ones, so that every sweep is a single product.  Forward: column block
+  // J of [L11^{-1}; -L21 L11^{-1}] collects the phases K > J.  Backward:
+  // V' = -U11^{-1} U12 runs through the phases K = last .. 0, then column block
+  // J of U11^{-1} collects the phases K < J.  Each pass reads only column
+  // blocks that it has not yet rewritten.
+  if (p > DIB) {
+    const int nJ = (p + DIB - 1) / DIB;
+    for (int J = 0; J + 1 < nJ; ++J)
+      for (int K = J + 1; K < nJ; ++K)
+        fold_step<T, true>(F, m, K * DIB, min(K * DIB + DIB, p), J * DIB, min(J * DIB + DIB, p), P,
+                           tid);
+    __syncthreads();
+    for (int t = tid; t < p * (m - p); t += NT) {
+      const int c = p + t / p, r = t % p;
+      const T x = F[(long long)c * m + r];
+      F[(long long)c * m + r] = T{-x.x, -x.y};
+    }
+    for (int c0 = p; c0 < m; c0 += DIB)
+      for (int K = nJ - 1; K >= 0; --K)
+        fold_step<T, false>(F, m, K * DIB, min(K * DIB + DIB, p), c0, min(c0 + DIB, m), P, tid);
+    for (int J = nJ - 1; J >= 1; --J)
+      for (int K = J - 1; K >= 0; --K)
+        fold_step<T, false>(F, m, K * DIB, min(K * DIB + DIB, p), J * DIB, min(J * DIB + DIB, p), P,
+                            tid);
+    __syncthreads();
+  }
   // Backward operator rows 0..p-1, packed with leading dimension p.
   T* U = upk + f.upk_off;
   for (int t = tid; t < p * m; t += NT) {
@@ -470,23 +537,99 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Sweeps, small fronts (m <= 64): four fronts per workgroup, one wavefront per
-// front, lane = row.  With the inverted diagonal block each sweep is two
-// dependent matrix-vector products whose column reads are coalesced and all
-// independent of each other.
+// Sweeps.  Per front the forward sweep computes
+//   y_p = L11^{-1} (P b)_p,   y_q = b_q + M' (P b)_p      (M' = -L21 L11^{-1})
+// and the backward sweep
+//   x_p = U11^{-1} y_p + V' x_q                          (V' = -U11^{-1} U12),
+// so that for p <= DIB each is ONE product with a lower- (forward) or upper-
+// (backward) trapezoidal operator.  The operator does not depend on the
+// right-hand side: every kernel loads its first operator columns into
+// registers before it gathers the vector, so that the chain of dependent loads
+// that assembles the right-hand side (descriptor, index maps, values) overlaps
+// the bulk of the front's traffic instead of preceding it.
 // ---------------------------------------------------------------------------
+
+// sum over c = c0, c0+step, ... < c1 of A[c*lda] * x[c], with the global
+// loads issued in predicated batches of LB, so that every batch (the last,
+// partial one included) costs one memory round trip.
 template <typename T>
-__global__ __launch_bounds__(NT) void k_fwd_small(LevelArgs a, const T* __restrict__ fac,
-                                                  const int* __restrict__ piv, T* __restrict__ vec,
-                                                  const double2* __restrict__ v) {
-  __shared__ T sh[4][1][64];
+__device__ inline T strided_dot(const T* __restrict__ A, long long lda, int c0, int c1, int step,
+                                const T* x) {
+  constexpr int LB = 8;
+  T acc0 = czero<T>(), acc1 = czero<T>();
+  for (int c = c0; c < c1; c += LB * step) {
+    T av[LB];
+#pragma unroll
+    for (int t = 0; t < LB; ++t) {
+      const int k = c + t * step;
+      av[t] = k < c1 ? A[(long long)k * lda] : czero<T>();
+    }
+#pragma unroll
+    for (int t = 0; t < LB; t += 2) {
+      const int k = c + t * step;
+      if (k < c1) acc0 = cfma(av[t], x[k], acc0);
+      if (k + step < c1) acc1 = cfma(av[t + 1], x[k + step], acc1);
+    }
+  }
+  return cadd(acc0, acc1);
+}
+
+// The first KP terms of a strided dot product, A[(k0 + G t) * lda] for t < KP
+// and k0 + G t < kend, held in registers; dot() adds the rest from memory.
+template <typename T, int KP>
+struct ColPrefetch {
+  T av[KP];
+  __device__ inline void load(const T* __restrict__ A, long long lda, int k0, int kend, int G) {
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
+      const int k = k0 + G * t;
+      av[t] = k < kend ? A[(long long)k * lda] : czero<T>();
+    }
+  }
+  // sum over k = k0, k0 + G, ... < kend of A[k*lda] x[k]
+  __device__ inline T dot(const T* __restrict__ A, long long lda, int k0, int kend, int G,
+                          const T* x) const {
+    T acc0 = czero<T>(), acc1 = czero<T>();
+#pragma unroll
+    for (int t = 0; t < KP; t += 2) {
+      const int k = k0 + G * t;
+      if (k < kend) acc0 = cfma(av[t], x[k], acc0);
+      if (k + G < kend) acc1 = cfma(av[t + 1], x[k + G], acc1);
+    }
+    const int kt = k0 + G * KP;
+    if (kt < kend) acc0 = cadd(acc0, strided_dot(A, lda, kt, kend, G, x));
+    return cadd(acc0, acc1);
+  }
+};
+
+// Forward sweep for levels with m <= 64 RPL and p <= 64: four fronts per
+// workgroup, one wavefront per front, no workgroup barriers.  Lane rows
+// r = lane + 64 i (i < RPL); with RPL = 1 and m <= 32, G = 64 / W lanes share a
+// row (columns k = g, g + G, ...) and a fixed butterfly adds their sums.
+template <typename T, int RPL, int KP>
+__global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restrict__ fac,
+                                                 const int* __restrict__ piv, T* __restrict__ vec,
+                                                 const double2* __restrict__ v) {
+  constexpr int MW = 64 * RPL;
+  __shared__ T sh[4][MW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
-  if (fi >= a.nlevel) return;                          // whole wavefront; no block barriers below
-  T* vl = sh[wv][0];
+  if (fi >= a.nlevel) return;                          // whole wavefront
+  T* vl = sh[wv];
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
+  const int W = RPL > 1 ? 64 : (m <= 16 ? 16 : (m <= 32 ? 32 : 64));
+  const int G = 64 / W, g = lane / W, rl = lane - g * W;
+  ColPrefetch<T, KP> pf[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = rl + 64 * i;
+    pf[i].load(F + r, m, g, r < m ? min(r, p) : 0, G);
+  }
+  const int pv = lane < p ? piv[f.piv_off + lane] : lane;
+  // b = R^I v on the separator rows plus the children's update vectors (all
+  // loaded before any is added).
   T val = czero<T>();
   if (lane < p) {
     const SubDev s = a.subs[f.sub];
@@ -495,194 +638,123 @@ __global__ __launch_bounds__(NT) void k_fwd_small(LevelArgs a, const T* __restri
     if (gx >= s.ix0 && gx < s.ix1 && gy >= s.iy0 && gy < s.iy1)
       val = from_d2<T>(v[(long long)gy * a.nx + gx]);
   }
-  // Children's update vectors (both loaded before either is added).
-  int dst0 = -1, dst1 = -1;
-  T c0 = czero<T>(), c1 = czero<T>();
-  if (f.nchild > 0 && lane < f.cq[0]) {
-    dst0 = a.cmap[f.ccmap[0] + lane];
-    c0 = vec[f.cvec[0] + lane];
-  }
-  if (f.nchild > 1 && lane < f.cq[1]) {
-    dst1 = a.cmap[f.ccmap[1] + lane];
-    c1 = vec[f.cvec[1] + lane];
+  int d0[RPL], d1[RPL];
+  T c0[RPL], c1[RPL];
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int idx = lane + 64 * i;
+    d0[i] = d1[i] = -1;
+    c0[i] = c1[i] = czero<T>();
+    if (f.nchild > 0 && idx < f.cq[0]) {
+      d0[i] = a.cmap[f.ccmap[0] + idx];
+      c0[i] = vec[f.cvec[0] + idx];
+    }
+    if (f.nchild > 1 && idx < f.cq[1]) {
+      d1[i] = a.cmap[f.ccmap[1] + idx];
+      c1[i] = vec[f.cvec[1] + idx];
+    }
   }
   vl[lane] = val;
+#pragma unroll
+  for (int i = 1; i < RPL; ++i) vl[lane + 64 * i] = czero<T>();
   wave_sync();
-  if (dst0 >= 0) vl[dst0] = cadd(vl[dst0], c0);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+    if (d0[i] >= 0) vl[d0[i]] = cadd(vl[d0[i]], c0[i]);
   wave_sync();
-  if (dst1 >= 0) vl[dst1] = cadd(vl[dst1], c1);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i)
+    if (d1[i] >= 0) vl[d1[i]] = cadd(vl[d1[i]], c1[i]);
   wave_sync();
-  // (P b)_r = b[perm[r]] for the separator rows.
-  val = lane < p ? vl[piv[f.piv_off + lane]] : vl[lane];
+  // (P b)_r = b[perm[r]] on the separator rows (p <= 64).
+  const T pb = vl[pv];
   wave_sync();
-  vl[lane] = val;
+  vl[lane] = pb;
   wave_sync();
-  // One trapezoidal product: rows r < p get y_r = b_r + sum_{k<r} (L11^{-1})_{rk} b_k,
-  // rows r >= p get b_r + sum_{k<p} M'_{rk} b_k with M' = -L21 L11^{-1}.  When the
-  // rows fit in W = 64/G lanes, G lanes share a row (columns k = g, g+G, ...)
-  // and a fixed butterfly adds their partial sums.
-  const int W = m <= 16 ? 16 : (m <= 32 ? 32 : 64);
-  const int G = 64 / W, g = lane / W, r = lane - g * W;
-  T acc = czero<T>();
-  if (r < m) {
-    const int kend = r < p ? r : p;
-#pragma unroll 8
-    for (int k = g; k < kend; k += G) acc = cfma(F[(long long)k * m + r], vl[k], acc);
+#pragma unroll
+  for (int i = 0; i < RPL; ++i) {
+    const int r = rl + 64 * i;
+    T acc = pf[i].dot(F + r, m, g, r < m ? min(r, p) : 0, G, vl);
+    if (RPL == 1)
+      for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
+    if (g == 0 && r < m) vec[f.vec_off + r] = cadd(vl[r], acc);
   }
-  for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-  if (g == 0 && r < m) vec[f.vec_off + r] = cadd(vl[r], acc);
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_small(LevelArgs a, const T* __restrict__ upk,
-                                                  T* __restrict__ vec, T* __restrict__ u) {
-  __shared__ T sh[4][1][64];
+// Backward sweep for levels with m <= 128 and p <= 64: four fronts per
+// workgroup, one wavefront per front.  Row r < p is shared by G = 64 / W lanes
+// (W >= p), which take columns c = r + g, r + g + G, ... of the packed operator
+// [U11^{-1} V'] (ld p); a fixed butterfly adds their sums.
+template <typename T, int KP>
+__global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restrict__ upk,
+                                                 T* __restrict__ vec, T* __restrict__ u) {
+  __shared__ T sh[4][128];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;
-  T* vl = sh[wv][0];
+  T* vl = sh[wv];
   const FrontDev f = a.fronts[a.first + fi];
-  const int m = f.p + f.q, p = f.p;
+  const int m = f.p + f.q, p = f.p, q = f.q;
   const T* U = upk + f.upk_off;
-  T val = czero<T>();
-  if (lane < p) {
-    val = vec[f.vec_off + lane];
-  } else if (lane < m) {
-    val = vec[f.pvec + a.cmap[f.cmap_off + lane - p]];
+  const int W = p <= 4 ? 4 : (p <= 8 ? 8 : (p <= 16 ? 16 : (p <= 32 ? 32 : 64)));
+  const int G = 64 / W, g = lane / W, r = lane - g * W;
+  ColPrefetch<T, KP> pf;
+  pf.load(U + r, p, r + g, r < p ? m : 0, G);
+  const int var = lane < p ? a.vars[f.var_off + lane] : 0;
+  // [y_p ; x_q]: y_p from the forward sweep, x_q from the parent's vector.
+  const T y = lane < p ? vec[f.vec_off + lane] : czero<T>();
+  T xq[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int idx = lane + 64 * i;
+    xq[i] = idx < q ? vec[f.pvec + a.cmap[f.cmap_off + idx]] : czero<T>();
   }
-  vl[lane] = val;
+  if (lane < p) vl[lane] = y;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+    if (lane + 64 * i < q) vl[p + lane + 64 * i] = xq[i];
   wave_sync();
-  // x_p = U11^{-1} y + V' x_q with V' = -U11^{-1} U12: one trapezoidal product,
-  // G lanes per row when p fits in W = 64/G lanes (fixed butterfly reduction).
-  {
-    const int W = p <= 16 ? 16 : (p <= 32 ? 32 : 64);
-    const int G = 64 / W, g = lane / W, r = lane - g * W;
-    T acc = czero<T>();
-    if (r < p) {
-#pragma unroll 8
-      for (int c = r + g; c < m; c += G) acc = cfma(U[c * p + r], vl[c], acc);
-    }
-    for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-    if (lane < p) val = acc;                 // lane < p <= W: g = 0, r = lane
+  T acc = pf.dot(U + r, p, r + g, r < p ? m : 0, G, vl);
+  for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
+  T* fv = vec + f.vec_off;
+  if (lane < p) {                          // lane < p <= W: g = 0, r = lane
+    fv[lane] = acc;
+    u[a.subs[f.sub].u_off + var] = acc;
   }
-  if (lane < m) vec[f.vec_off + lane] = val;
-  if (lane < p) {
-    const SubDev s = a.subs[f.sub];
-    u[s.u_off + a.vars[f.var_off + lane]] = val;
-  }
-}
-
-// sum over c = c0, c0+step, ... < c1 of A[c*lda] * x[c], with the global
-// loads issued in batches of LB so that many are in flight at once.
-template <typename T>
-__device__ inline T strided_dot(const T* __restrict__ A, long long lda, int c0, int c1, int step,
-                                const T* x) {
-  constexpr int LB = 16;
-  T acc0 = czero<T>(), acc1 = czero<T>();
-  int c = c0;
-  for (; c + (LB - 1) * step < c1; c += LB * step) {
-    T av[LB];
 #pragma unroll
-    for (int t = 0; t < LB; ++t) av[t] = A[(long long)(c + t * step) * lda];
-#pragma unroll
-    for (int t = 0; t < LB; t += 2) {
-      acc0 = cfma(av[t], x[c + t * step], acc0);
-      acc1 = cfma(av[t + 1], x[c + (t + 1) * step], acc1);
-    }
-  }
-  for (; c < c1; c += step) acc0 = cfma(A[(long long)c * lda], x[c], acc0);
-  return cadd(acc0, acc1);
-}
-
-// y[r] -= sum_{c0 <= c < c1} A[c*lda + r] x[c] for r0 <= r < r1, with A
-// column-major in global memory and x, y in LDS, using all NT threads: a thread
-// per row when the rows fill the workgroup, otherwise (row, column-group)
-// pairs whose partial sums are reduced in a fixed order through `scr`
-// (NT entries).  Ends with a workgroup barrier.
-template <typename T>
-__device__ inline void block_gemv_sub(const T* __restrict__ A, int lda, int r0, int r1, int c0,
-                                      int c1, const T* x, T* y, T* scr, int tid) {
-  const int R = r1 - r0;
-  if (R <= 0 || c1 <= c0) return;
-  if (R >= NT / 2) {
-    for (int r = r0 + tid; r < r1; r += NT) {
-      const T acc = strided_dot(A + r, (long long)lda, c0, c1, 1, x);
-      y[r] = csub(y[r], acc);
-    }
-    __syncthreads();
-    return;
-  }
-  const int G = NT / R;
-  const int g = tid / R, rr = tid - g * R;
-  T acc = czero<T>();
-  if (g < G) acc = strided_dot(A + r0 + rr, (long long)lda, c0 + g, c1, G, x);
-  scr[tid] = acc;
-  __syncthreads();
-  if (tid < R) {
-    T sum = czero<T>();
-    for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * R + tid]);
-    y[r0 + tid] = csub(y[r0 + tid], sum);
-  }
-  __syncthreads();
-}
-
-// One block step of the sweeps over rows [r0, r1) and the block columns
-// [c0, c1), result written back into x (LDS) after all reads:
-//   LOWER:  x_r <- x_r + sum_{c0 <= c < min(c1, r)} A[c*lda + r] x_c
-//   !LOWER: x_r <- (r < keep ? x_r : 0) + sum_{max(c0, r) <= c < c1} A[c*lda + r] x_c
-// A thread per row when the rows fill the workgroup, else (row, column group)
-// pairs reduced in a fixed order through scr (NT).  ol: max_m scratch.
-template <typename T, bool LOWER>
-__device__ inline void block_phase(const T* __restrict__ A, int lda, int r0, int r1, int c0, int c1,
-                                   int keep, T* x, T* ol, T* scr, int tid) {
-  const int R = r1 - r0;
-  if (R <= 0) return;
-  if (R >= NT / 2) {
-    for (int r = r0 + tid; r < r1; r += NT) {
-      const int lo = LOWER ? c0 : max(c0, r), hi = LOWER ? min(c1, r) : c1;
-      T acc = strided_dot(A + r, (long long)lda, lo, hi, 1, x);
-      ol[r] = (LOWER || r < keep) ? cadd(x[r], acc) : acc;
-    }
-  } else {
-    const int G = NT / R;
-    const int g = tid / R, rr = tid - g * R, r = r0 + rr;
-    T acc = czero<T>();
-    if (g < G) {
-      const int lo = LOWER ? c0 : max(c0, r), hi = LOWER ? min(c1, r) : c1;
-      acc = strided_dot(A + r, (long long)lda, lo + g, hi, G, x);
-    }
-    scr[tid] = acc;
-    __syncthreads();
-    if (tid < R) {
-      T sum = czero<T>();
-      for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * R + tid]);
-      const int rw = r0 + tid;
-      ol[rw] = (LOWER || rw < keep) ? cadd(x[rw], sum) : sum;
-    }
-  }
-  __syncthreads();
-  for (int r = r0 + tid; r < r1; r += NT) x[r] = ol[r];
-  __syncthreads();
+  for (int i = 0; i < 2; ++i)
+    if (lane + 64 * i < q) fv[p + lane + 64 * i] = xq[i];
 }
 
 // ---------------------------------------------------------------------------
-// Sweeps, large fronts: one workgroup per front, one block_phase per DIB
-// columns of the separator (a single phase when p <= DIB).
+// Sweeps, large fronts: one workgroup of NTL threads per front, the single
+// trapezoidal product with the first KP operator terms of each thread
+// prefetched into registers.  Rows are shared by G = NTL / rows threads
+// (column groups) whose partial sums are added in a fixed order through LDS.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restrict__ fac,
-                                                  const int* __restrict__ piv, T* __restrict__ vec,
-                                                  const double2* __restrict__ v) {
+template <typename T, int NTL, int KP>
+__global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restrict__ fac,
+                                                   const int* __restrict__ piv, T* __restrict__ vec,
+                                                   const double2* __restrict__ v) {
   extern __shared__ unsigned char smem_raw[];
-  T* scr = reinterpret_cast<T*>(smem_raw);                 // NT
-  T* vl = scr + NT;                                        // max_m
+  T* scr = reinterpret_cast<T*>(smem_raw);                 // NTL
+  T* vl = scr + NTL;                                       // max_m
   T* tmp = vl + a.max_m;                                   // max_m
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
   const int tid = threadIdx.x;
+  int G = 1, g = 0, rr = tid;
+  if (m < NTL) {
+    G = NTL / m;
+    g = tid / m;
+    rr = tid - g * m;
+  }
+  const bool act = g < G && rr < m;
+  ColPrefetch<T, KP> pf;
+  pf.load(F + rr, m, g, act ? min(rr, p) : 0, G);
   const SubDev s = a.subs[f.sub];
-  for (int i = tid; i < m; i += NT) {
+  for (int i = tid; i < m; i += NTL) {
     T val = czero<T>();
     if (i < p) {
       int node = a.vars[f.var_off + i];
@@ -696,63 +768,88 @@ __global__ __launch_bounds__(NT) void k_fwd_large(LevelArgs a, const T* __restri
   if (f.nchild > 0) {
     const int* cm = a.cmap + f.ccmap[0];
     const T* cv = vec + f.cvec[0];
-    for (int i = tid; i < f.cq[0]; i += NT) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
+    for (int i = tid; i < f.cq[0]; i += NTL) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
     __syncthreads();
   }
   if (f.nchild > 1) {
     const int* cm = a.cmap + f.ccmap[1];
     const T* cv = vec + f.cvec[1];
-    for (int i = tid; i < f.cq[1]; i += NT) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
+    for (int i = tid; i < f.cq[1]; i += NTL) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
     __syncthreads();
   }
   const int* perm = piv + f.piv_off;
-  for (int i = tid; i < p; i += NT) tmp[i] = vl[perm[i]];
+  for (int i = tid; i < p; i += NTL) tmp[i] = vl[perm[i]];
   __syncthreads();
-  for (int i = tid; i < p; i += NT) vl[i] = tmp[i];
+  for (int i = tid; i < p; i += NTL) vl[i] = tmp[i];
   __syncthreads();
-  for (int j0 = 0; j0 < p; j0 += DIB) {
-    const int j1 = min(j0 + DIB, p);
-    block_phase<T, true>(F, m, j0, m, j0, j1, 0, vl, tmp, scr, tid);
-  }
   T* out = vec + f.vec_off;
-  for (int i = tid; i < m; i += NT) out[i] = vl[i];
+  const T acc = act ? pf.dot(F + rr, m, g, min(rr, p), G, vl) : czero<T>();
+  if (G == 1) {
+    if (act) out[rr] = cadd(vl[rr], acc);
+    for (int r = tid + NTL; r < m; r += NTL)
+      out[r] = cadd(vl[r], strided_dot(F + r, (long long)m, 0, min(r, p), 1, vl));
+  } else {
+    scr[tid] = acc;
+    __syncthreads();
+    if (tid < m) {
+      T sum = czero<T>();
+      for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * m + tid]);
+      out[tid] = cadd(vl[tid], sum);
+    }
+  }
 }
 
-template <typename T>
-__global__ __launch_bounds__(NT) void k_bwd_large(LevelArgs a, const T* __restrict__ upk,
-                                                  T* __restrict__ vec, T* __restrict__ u) {
+template <typename T, int NTL, int KP>
+__global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restrict__ upk,
+                                                   T* __restrict__ vec, T* __restrict__ u) {
   extern __shared__ unsigned char smem_raw[];
-  T* scr = reinterpret_cast<T*>(smem_raw);
-  T* vl = scr + NT;
-  T* tmp = vl + a.max_m;
+  T* scr = reinterpret_cast<T*>(smem_raw);                 // NTL
+  T* vl = scr + NTL;                                       // max_m
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
-  const T* U = upk + f.upk_off;                          // rows 0..p-1, leading dimension p
+  const T* U = upk + f.upk_off;                            // rows 0..p-1, leading dimension p
   const int tid = threadIdx.x;
+  int G = 1, g = 0, rr = tid;
+  if (p < NTL) {
+    G = NTL / max(p, 1);
+    g = tid / max(p, 1);
+    rr = tid - g * max(p, 1);
+  }
+  const bool act = g < G && rr < p;
+  ColPrefetch<T, KP> pf;
+  pf.load(U + rr, p, rr + g, act ? m : 0, G);
   T* fv = vec + f.vec_off;
-  for (int i = tid; i < p; i += NT) vl[i] = fv[i];
+  for (int i = tid; i < p; i += NTL) vl[i] = fv[i];
   if (f.parent >= 0) {
     const int* cm = a.cmap + f.cmap_off;
     const T* pv = vec + f.pvec;
-    for (int i = tid; i < f.q; i += NT) vl[p + i] = pv[cm[i]];
+    for (int i = tid; i < f.q; i += NTL) vl[p + i] = pv[cm[i]];
   }
   __syncthreads();
-  if (p <= DIB) {
-    // x_p = U11^{-1} y + V' x_q in one phase (V' = -U11^{-1} U12 stored).
-    block_phase<T, false>(U, p, 0, p, 0, m, 0, vl, tmp, scr, tid);
-  } else {
-    block_gemv_sub(U, p, 0, p, p, m, vl, vl, scr, tid);   // t = y - U12 x_q
-    for (int j0 = ((p - 1) / DIB) * DIB; j0 >= 0; j0 -= DIB) {
-      const int j1 = min(j0 + DIB, p);
-      block_phase<T, false>(U, p, 0, j1, j0, j1, j0, vl, tmp, scr, tid);
-    }
-  }
   const int* vars = a.vars + f.var_off;
   const long long uo = a.subs[f.sub].u_off;
-  for (int i = tid; i < m; i += NT) {
-    fv[i] = vl[i];
-    if (i < p) u[uo + vars[i]] = vl[i];
+  const T acc = act ? pf.dot(U + rr, p, rr + g, m, G, vl) : czero<T>();
+  if (G == 1) {
+    if (act) {
+      fv[rr] = acc;
+      u[uo + vars[rr]] = acc;
+    }
+    for (int r = tid + NTL; r < p; r += NTL) {
+      const T x = strided_dot(U + r, (long long)p, r, m, 1, vl);
+      fv[r] = x;
+      u[uo + vars[r]] = x;
+    }
+  } else {
+    scr[tid] = acc;
+    __syncthreads();
+    if (tid < p) {
+      T sum = czero<T>();
+      for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * p + tid]);
+      fv[tid] = sum;
+      u[uo + vars[tid]] = sum;
+    }
   }
+  for (int i = p + tid; i < m; i += NTL) fv[i] = vl[i];
 }
 
 // z = sum_k P_k u_k: each global node adds the local fields of the (at most
@@ -847,26 +944,108 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int
   }
 }
 
+// Smallest prefetch depth in {8, 16, 32} that covers `need` columns, capped
+// at `cap` (the rest of a row is read by the dot product's tail batches).
+inline int prefetch_depth(int need, int cap) {
+  int kp = 8;
+  while (kp < need && kp < cap) kp *= 2;
+  return kp;
+}
+
+// Workgroup size for the large-front sweeps: the smallest of 256, 512, 1024
+// threads whose per-thread column count (rows shared by NTL / rows column
+// groups) fits the register prefetch.
+inline int large_threads(int rows, int cols, int cap) {
+  for (int ntl = 256; ntl < 1024; ntl *= 2) {
+    const int g = std::max(1, ntl / std::max(rows, 1));
+    if ((cols + g - 1) / g <= cap) return ntl;
+  }
+  return 1024;
+}
+
+template <typename T, int RPL, int KP>
+void fwd_wave_launch(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
+                     const double2* v) {
+  hipLaunchKernelGGL((k_fwd_wave<T, RPL, KP>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac,
+                     piv, vec, v);
+}
+
+template <typename T, int NTL>
+void fwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* fac, const int* piv,
+                      T* vec, const double2* v) {
+  const size_t lds = ((size_t)NTL + 2 * (size_t)a.max_m) * sizeof(T);
+  if (kp <= 16)
+    hipLaunchKernelGGL((k_fwd_large<T, NTL, 16>), dim3(a.nlevel), dim3(NTL), lds, st, a, fac, piv,
+                       vec, v);
+  else
+    hipLaunchKernelGGL((k_fwd_large<T, NTL, (sizeof(T) == 8 ? 32 : 16)>), dim3(a.nlevel), dim3(NTL),
+                       lds, st, a, fac, piv, vec, v);
+}
+
+template <typename T, int NTL>
+void bwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* upk, T* vec, T* u) {
+  const size_t lds = ((size_t)NTL + (size_t)a.max_m) * sizeof(T);
+  if (kp <= 16)
+    hipLaunchKernelGGL((k_bwd_large<T, NTL, 16>), dim3(a.nlevel), dim3(NTL), lds, st, a, upk, vec,
+                       u);
+  else
+    hipLaunchKernelGGL((k_bwd_large<T, NTL, (sizeof(T) == 8 ? 32 : 16)>), dim3(a.nlevel), dim3(NTL),
+                       lds, st, a, upk, vec, u);
+}
+
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
                       const double2* v) {
-  if (a.max_m <= 64) {
-    hipLaunchKernelGGL(k_fwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, piv, vec,
-                       v);
-  } else {
-    size_t lds = ((size_t)NT + 2 * (size_t)a.max_m) * sizeof(T);
-    hipLaunchKernelGGL(k_fwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, fac, piv, vec, v);
+  const int cap = sizeof(T) == 8 ? 32 : 16;      // registers per lane for the prefetch
+  if (a.max_m <= 128 && a.max_p <= 64) {
+    // A lane row takes at most min(r, p) <= max_p columns.
+    const int rpl = a.max_m <= 64 ? 1 : 2;
+    const int kp = prefetch_depth(a.max_p, cap / rpl);
+    if (rpl == 1) {
+      if (kp == 8) fwd_wave_launch<T, 1, 8>(st, a, fac, piv, vec, v);
+      else if (kp == 16) fwd_wave_launch<T, 1, 16>(st, a, fac, piv, vec, v);
+      else fwd_wave_launch<T, 1, (sizeof(T) == 8 ? 32 : 16)>(st, a, fac, piv, vec, v);
+    } else {
+      if (kp == 8) fwd_wave_launch<T, 2, 8>(st, a, fac, piv, vec, v);
+      else fwd_wave_launch<T, 2, (sizeof(T) == 8 ? 16 : 8)>(st, a, fac, piv, vec, v);
+    }
+    return;
   }
+  // Rows m share the workgroup; a row takes at most p columns.
+  const int ntl = large_threads(a.max_m, a.max_p, cap);
+  const int g = std::max(1, ntl / a.max_m);
+  const int kp = prefetch_depth((a.max_p + g - 1) / g, cap);
+  if (ntl == 256) fwd_large_launch<T, 256>(st, a, kp, fac, piv, vec, v);
+  else if (ntl == 512) fwd_large_launch<T, 512>(st, a, kp, fac, piv, vec, v);
+  else fwd_large_launch<T, 1024>(st, a, kp, fac, piv, vec, v);
 }
 
 template <typename T>
 void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u) {
-  if (a.max_m <= 64) {
-    hipLaunchKernelGGL(k_bwd_small<T>, dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u);
-  } else {
-    size_t lds = ((size_t)NT + 2 * (size_t)a.max_m) * sizeof(T);
-    hipLaunchKernelGGL(k_bwd_large<T>, dim3(a.nlevel), dim3(NT), lds, st, a, upk, vec, u);
+  const int cap = sizeof(T) == 8 ? 32 : 16;
+  if (a.max_m <= 128 && a.max_p <= 64) {
+    // Row groups: W >= max_p lanes, so G >= 64 / W groups share a row's columns.
+    int w = 4;
+    while (w < a.max_p) w *= 2;
+    const int g = 64 / w;
+    const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
+    if (kp == 8)
+      hipLaunchKernelGGL((k_bwd_wave<T, 8>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u);
+    else if (kp == 16)
+      hipLaunchKernelGGL((k_bwd_wave<T, 16>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec,
+                         u);
+    else
+      hipLaunchKernelGGL((k_bwd_wave<T, (sizeof(T) == 8 ? 32 : 16)>), dim3((a.nlevel + 3) / 4),
+                         dim3(NT), 0, st, a, upk, vec, u);
+    return;
   }
+  // Rows p share the workgroup; a row takes at most m columns.
+  const int ntl = large_threads(a.max_p, a.max_m, cap);
+  const int g = std::max(1, ntl / std::max(a.max_p, 1));
+  const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
+  if (ntl == 256) bwd_large_launch<T, 256>(st, a, kp, upk, vec, u);
+  else if (ntl == 512) bwd_large_launch<T, 512>(st, a, kp, upk, vec, u);
+  else bwd_large_launch<T, 1024>(st, a, kp, upk, vec, u);
 }
 
 template <typename T>

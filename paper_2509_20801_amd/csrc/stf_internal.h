@@ -182,6 +182,7 @@ struct LevelArgs {
   int nx;                       // global nx
   int max_m;                    // largest front in the level
   int max_pm;                   // largest p*m in the level
+  int max_p;                    // largest p in the level
 };
 // Assembly (original entries + extend-add of the children) and partial LU of
 // every front of one level.
