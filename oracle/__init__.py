@@ -17,5 +17,11 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
                                  converges in one step
   mie                            pinned: Jacobi-Anger series of the incident
                                  wave, boundary continuity, eps = 1 gives zero
+  nn (learned warm start)        pinned: truncated DFTs vs numpy.fft, every
+                                 gradient block vs central differences, GELU
+                                 identities, Adam first step, blending is a
+                                 partition of unity.  The quality of a trained
+                                 network's guess is parity unpinned (no reference
+                                 exists); the FP64 true residual judges it.
 """
-from . import fdfd, ddm, krylov, mie  # noqa: F401
+from . import fdfd, ddm, krylov, mie, nn  # noqa: F401
