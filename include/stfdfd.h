@@ -54,8 +54,11 @@ typedef enum {
  * the Arnoldi process and the solution update are always FP64. */
 enum { STF_C128 = 0, STF_C64 = 1 };
 
-/* Initial guess. */
-enum { STF_X0_ZERO = 0, STF_X0_USER = 1 };
+/* Initial guess.  STF_X0_LEARNED: the context's network (stf_ctx_set_nn)
+ * predicts the field on overlapping tiles of the physical interior and the
+ * blended prediction is the guess, unless its FP64 residual is not below |b|
+ * (then the zero guess is used instead; see stf_solve_info.used_learned). */
+enum { STF_X0_ZERO = 0, STF_X0_USER = 1, STF_X0_LEARNED = 2 };
 
 /* Problem description (Sec. 2.1-2.3).  Global PML sides are ordered x-, x+, y-, y+.
  * The interior [pml[0], nx-pml[1]) x [pml[2], ny-pml[3]) is split into px x py
@@ -84,7 +87,7 @@ typedef struct {
   double  tol;        /* stop when |b - A x|_2 <= tol |b|_2 (FP64 true residual) */
   int32_t restart;    /* FGMRES cycle length m (1..200) */
   int32_t max_iter;   /* total inner iterations (>= 1) */
-  int32_t x0_mode;    /* STF_X0_ZERO or STF_X0_USER (x holds the guess on entry) */
+  int32_t x0_mode;    /* STF_X0_ZERO, STF_X0_USER (x holds the guess on entry) or STF_X0_LEARNED */
   int32_t rounds;     /* source-transfer rounds per preconditioner application (0 or 1 = one
                          round z = B v; r > 1 adds r-1 stationary corrections
                          z += B (v - A z), i.e. r Jacobi rounds of Algorithm 1; <= 8) */
@@ -96,11 +99,12 @@ typedef struct {
   int32_t status;         /* stf_status of this right-hand side */
   int32_t history_len;    /* entries written to history */
   double  relres_true;    /* FP64 |b - A x| / |b| at exit */
-  double  relres_x0;      /* FP64 |b - A x0| / |b| */
+  double  relres_x0;      /* FP64 |b - A x0| / |b| (for STF_X0_LEARNED: of the network's
+                             guess, before the fallback) */
   double* history;        /* caller-owned host buffer (may be NULL): relative residual
                              estimate after every iteration, true residual at x0 first */
   int32_t history_cap;    /* capacity of history */
-  int32_t reserved0;
+  int32_t used_learned;   /* STF_X0_LEARNED: 1 if the network's guess was kept, 0 after fallback */
 } stf_solve_info;
 
 /* Sizes and work counts of a plan. */
@@ -132,7 +136,7 @@ const char* stf_last_error(stf_ctx ctx);                  /* never NULL */
 enum {
   STF_K_ASSEMBLE = 0, STF_K_STENCIL = 1, STF_K_FRONT_ASM = 2, STF_K_FRONT_LU = 3,
   STF_K_SWEEP_FWD = 4, STF_K_SWEEP_BWD = 5, STF_K_SCATTER = 6, STF_K_ARNOLDI = 7,
-  STF_K_UPDATE = 8, STF_K_COUNT = 9
+  STF_K_UPDATE = 8, STF_K_NN = 9, STF_K_COUNT = 10
 };
 stf_status  stf_ctx_set_timing(stf_ctx ctx, int enable);  /* all classes; enabling resets the counters */
 /* Timing restricted to the classes whose bits (1 << STF_K_*) are set in mask (0 = off);
@@ -182,6 +186,59 @@ stf_status  stf_apply(stf_problem pb, const double* x, double* y, int on_device)
 stf_status  stf_precond_apply(stf_problem pb, const double* v, double* z, int on_device);
 stf_status  stf_problem_info(stf_problem pb, stf_plan_info* out);
 void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
+
+/* ---- learned warm start -------------------------------------------------
+ * A spectral neural operator on n x n tiles (FP32): pointwise lift of the cin
+ * input features to W channels, L layers h <- act(K h + W_l h + c_l) with the
+ * spectral convolution K h = Finv(R . Ftrunc(h)) over the modes kx in [0, M),
+ * ky in [-M, M) (complex weights R per mode and channel pair), GELU (tanh
+ * form) after every layer but the last, and a pointwise projection to the
+ * real and imaginary part of the field.  Features of a tile:
+ * ((Re eps_node - 1) / 4, Re b, Im b).  Parameters form one flat FP32 vector:
+ * P_w (W, cin), P_b (W), per layer Re R (W, W, 2M, M), Im R, W_l (W, W),
+ * c_l (W), then Q_w (2, W), Q_b (2).  Training minimises the mean over tiles
+ * of |y - t|^2 / |t|^2 with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * Tensors are planar [tile][channel][y][x], x fastest. */
+typedef struct stf_nn_s* stf_nn;
+typedef struct {
+  int32_t n;          /* tile side in nodes (2M <= n) */
+  int32_t width;      /* W: 4, 8, 16 or 32 */
+  int32_t modes;      /* M */
+  int32_t layers;     /* L >= 1 */
+  int32_t cin;        /* input features: 3 */
+  int32_t max_batch;  /* largest number of tiles per call */
+} stf_nn_config;
+
+int64_t     stf_nn_param_count(const stf_nn_config* cfg);       /* -1 if cfg is invalid */
+/* params: host array of stf_nn_param_count floats (copied). */
+stf_status  stf_nn_create(stf_ctx ctx, const stf_nn_config* cfg, const float* params, stf_nn* out);
+void        stf_nn_destroy(stf_nn nn);                          /* NULL-safe */
+stf_status  stf_nn_get_params(stf_nn nn, float* params);        /* host, param_count floats */
+stf_status  stf_nn_set_params(stf_nn nn, const float* params);  /* host; resets the Adam moments */
+/* y (batch, 2, n, n) = network(f (batch, cin, n, n)); device pointers. */
+stf_status  stf_nn_forward(stf_nn nn, int32_t batch, const float* f, float* y);
+/* Loss and gradient of the loss for one batch (device f, t (batch, 2, n, n));
+ * grad: host array of param_count floats, or NULL. */
+stf_status  stf_nn_loss_grad(stf_nn nn, int32_t batch, const float* f, const float* t,
+                             double* loss, float* grad);
+/* loss_grad followed by one Adam step with learning rate lr; step counts from 1. */
+stf_status  stf_nn_train_step(stf_nn nn, int32_t batch, const float* f, const float* t, double lr,
+                              int32_t step, double* loss);
+/* Network used by STF_X0_LEARNED solves on this context (NULL detaches; not owned). */
+stf_status  stf_ctx_set_nn(stf_ctx ctx, stf_nn nn);
+/* The blended guess for source b on problem pb: tiles of side n at stride n/2
+ * over the physical interior (last tile flush with the far edge), weights
+ * sin^2(pi (i + 1/2) / n) per axis held at 1 on the outer half of edge tiles,
+ * divided by the summed weights; 0 in the global PML.  b, x0: ny*nx complex.
+ * Needs an assembled problem whose interior is at least n x n. */
+stf_status  stf_nn_initial_guess(stf_problem pb, stf_nn nn, const double* b, double* x0,
+                                 int on_device);
+/* Training data of problem pb on the same tiles (device pointers): features
+ * f (ntiles, cin, n, n) of source b, and the field x as t (ntiles, 2, n, n)
+ * (real, imaginary).  f or t may be NULL; *ntiles receives the tile count
+ * (call with f = t = NULL to size the buffers). */
+stf_status  stf_nn_tile_data(stf_problem pb, stf_nn nn, const double* b, const double* x, float* f,
+                             float* t, int32_t* ntiles);
 
 #ifdef __cplusplus
 }

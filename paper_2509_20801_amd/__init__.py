@@ -18,11 +18,12 @@ import weakref
 import numpy as np
 
 from . import _abi
-from ._abi import (STF_C128, STF_C64, STF_X0_USER, STF_X0_ZERO, KERNEL_CLASSES,  # noqa: F401
-                   STATUS_NAMES)
+from ._abi import (STF_C128, STF_C64, STF_X0_USER, STF_X0_ZERO, STF_X0_LEARNED,  # noqa: F401
+                   KERNEL_CLASSES, STATUS_NAMES)
 
-__all__ = ["Context", "Problem", "StfError", "plan_query", "debug_local_axes", "make_params",
-           "STF_C128", "STF_C64", "STF_X0_ZERO", "STF_X0_USER", "KERNEL_CLASSES"]
+__all__ = ["Context", "Problem", "Network", "StfError", "plan_query", "debug_local_axes",
+           "make_params", "nn_param_count", "STF_C128", "STF_C64", "STF_X0_ZERO", "STF_X0_USER",
+           "STF_X0_LEARNED", "KERNEL_CLASSES"]
 
 
 class StfError(RuntimeError):
@@ -142,15 +143,22 @@ class Context:
         self.handle = h
         self.device = device
         self._problems = weakref.WeakSet()
+        self._networks = weakref.WeakSet()
         _live_contexts.add(self)
 
     def close(self):
-        """Destroy the context and every problem created on it (problems first)."""
+        """Destroy the context and every problem and network created on it (those first)."""
         if getattr(self, "handle", None):
             for pb in list(self._problems):
                 pb.close()
+            for nn in list(self._networks):
+                nn.close()
             self._lib.stf_ctx_destroy(self.handle)
             self.handle = None
+
+    def set_nn(self, net):
+        """Network used by solves with x0="learned" (None detaches)."""
+        _check(self.handle, self._lib.stf_ctx_set_nn(self.handle, net.handle if net else None))
 
     def __del__(self):
         try:
@@ -248,13 +256,21 @@ class Problem:
 
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
               raise_on_noconv=False, rounds=1):
-        """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos)."""
+        """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos).
+        x0: None (zero guess), an array (user guess) or "learned" (the context's network)."""
         shape = tuple(b.shape)
         nrhs = 1 if len(shape) == 2 else int(shape[0])
         n = self.ndof
         pb_, dev, kb = _ptr(b, nrhs * n, "b")
         mode = _abi.STF_X0_ZERO
-        if x0 is not None:
+        if isinstance(x0, str):
+            if x0 != "learned":
+                raise ValueError("x0 must be None, an array or 'learned'")
+            mode = _abi.STF_X0_LEARNED
+            x0 = None
+            if x is None:
+                x = self._out_like(b, shape)
+        elif x0 is not None:
             mode = _abi.STF_X0_USER
             if _is_torch(x0):
                 x = x0.clone()
@@ -279,6 +295,7 @@ class Problem:
             inf = infos[i]
             out.append(dict(iters=inf.iters, restarts=inf.restarts, status=inf.status,
                             relres_true=inf.relres_true, relres_x0=inf.relres_x0,
+                            used_learned=inf.used_learned,
                             history=hist[i][:inf.history_len].copy()))
         xo = x if dev else kx.reshape(shape)
         return xo, out
@@ -287,3 +304,136 @@ class Problem:
         pi = _abi.PlanInfo()
         _check(self.ctx.handle, self._lib.stf_problem_info(self.handle, C.byref(pi)))
         return {f: getattr(pi, f) for f, _ in _abi.PlanInfo._fields_}
+
+    def tile_data(self, net, b=None, x=None):
+        """(features, fields) of this problem's tiles as float32 CUDA tensors
+        (device b and x, either may be None)."""
+        import torch
+        nt = C.c_int32()
+        _check(self.ctx.handle, self._lib.stf_nn_tile_data(self.handle, net.handle, None, None, None,
+                                                           None, C.byref(nt)))
+        n, N = net.cfg.n, self.ndof
+        dev = b.device if b is not None else x.device
+        f = torch.empty((nt.value, net.cfg.cin, n, n), dtype=torch.float32, device=dev) if b is not None else None
+        t = torch.empty((nt.value, 2, n, n), dtype=torch.float32, device=dev) if x is not None else None
+        _check(self.ctx.handle, self._lib.stf_nn_tile_data(
+            self.handle, net.handle, _cptr(b, N, "b") if b is not None else None,
+            _cptr(x, N, "x") if x is not None else None,
+            C.c_void_p(f.data_ptr()) if f is not None else None,
+            C.c_void_p(t.data_ptr()) if t is not None else None, C.byref(nt)))
+        return f, t
+
+    def initial_guess(self, net, b):
+        """The network's blended initial guess for source b (same kind of array as b)."""
+        n = self.ndof
+        pb_, dev, kb = _ptr(b, n, "b")
+        x = self._out_like(b, (self.ny, self.nx))
+        px, dev2, kx = _ptr(x, n, "x0")
+        _check(self.ctx.handle, self._lib.stf_nn_initial_guess(self.handle, net.handle, pb_, px, dev))
+        return x if dev else kx.reshape(self.ny, self.nx)
+
+
+def _cptr(a, count, name):
+    """Device pointer of a contiguous complex128 CUDA tensor with `count` entries."""
+    import torch
+    if not (_is_torch(a) and a.is_cuda and a.dtype == torch.complex128 and a.is_contiguous()):
+        raise TypeError("%s must be a contiguous complex128 CUDA tensor" % name)
+    if a.numel() != count:
+        raise ValueError("%s has %d entries, expected %d" % (name, a.numel(), count))
+    return C.c_void_p(a.data_ptr())
+
+
+def _nn_config(n, width, modes, layers, cin=3, max_batch=16):
+    c = _abi.NNConfig()
+    c.n, c.width, c.modes, c.layers, c.cin, c.max_batch = (int(n), int(width), int(modes),
+                                                            int(layers), int(cin), int(max_batch))
+    return c
+
+
+def nn_param_count(n, width, modes, layers, cin=3):
+    return int(_abi.load().stf_nn_param_count(C.byref(_nn_config(n, width, modes, layers, cin))))
+
+
+def _fptr(a, count, name):
+    """Device pointer of a contiguous float32 CUDA tensor with `count` entries."""
+    import torch
+    if not (_is_torch(a) and a.is_cuda and a.dtype == torch.float32 and a.is_contiguous()):
+        raise TypeError("%s must be a contiguous float32 CUDA tensor" % name)
+    if a.numel() != count:
+        raise ValueError("%s has %d entries, expected %d" % (name, a.numel(), count))
+    return C.c_void_p(a.data_ptr())
+
+
+class Network:
+    """The learned warm start's spectral neural operator (see include/stfdfd.h).
+    params: flat float64/float32 host array in the documented layout."""
+
+    def __init__(self, ctx, params, n=256, width=16, modes=16, layers=4, cin=3, max_batch=16):
+        self.ctx = ctx
+        self._lib = ctx._lib
+        self.cfg = _nn_config(n, width, modes, layers, cin, max_batch)
+        self.nparams = int(self._lib.stf_nn_param_count(C.byref(self.cfg)))
+        if self.nparams < 0:
+            raise StfError(_abi.STF_EINVAL, "invalid network configuration")
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.nparams:
+            raise ValueError("params has %d entries, expected %d" % (p.size, self.nparams))
+        h = C.c_void_p()
+        _check(ctx.handle, self._lib.stf_nn_create(ctx.handle, C.byref(self.cfg),
+                                                   C.c_void_p(p.ctypes.data), C.byref(h)))
+        self.handle = h
+        ctx._networks.add(self)
+
+    def close(self):
+        if getattr(self, "handle", None) and getattr(self.ctx, "handle", None):
+            self._lib.stf_nn_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _per(self, ch):
+        return ch * self.cfg.n * self.cfg.n
+
+    def get_params(self):
+        out = np.empty(self.nparams, dtype=np.float32)
+        _check(self.ctx.handle, self._lib.stf_nn_get_params(self.handle, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != self.nparams:
+            raise ValueError("params has %d entries, expected %d" % (p.size, self.nparams))
+        _check(self.ctx.handle, self._lib.stf_nn_set_params(self.handle, C.c_void_p(p.ctypes.data)))
+
+    def forward(self, f, y=None):
+        """f: float32 CUDA tensor (B, cin, n, n) -> y (B, 2, n, n)."""
+        import torch
+        B = int(f.shape[0])
+        if y is None:
+            y = torch.empty((B, 2, self.cfg.n, self.cfg.n), dtype=torch.float32, device=f.device)
+        _check(self.ctx.handle, self._lib.stf_nn_forward(self.handle, B,
+                                                         _fptr(f, B * self._per(self.cfg.cin), "f"),
+                                                         _fptr(y, B * self._per(2), "y")))
+        return y
+
+    def loss_grad(self, f, t):
+        """(loss, gradient as a host float32 array) for one batch."""
+        B = int(f.shape[0])
+        loss = C.c_double()
+        g = np.empty(self.nparams, dtype=np.float32)
+        _check(self.ctx.handle, self._lib.stf_nn_loss_grad(
+            self.handle, B, _fptr(f, B * self._per(self.cfg.cin), "f"),
+            _fptr(t, B * self._per(2), "t"), C.byref(loss), C.c_void_p(g.ctypes.data)))
+        return loss.value, g
+
+    def train_step(self, f, t, lr, step):
+        B = int(f.shape[0])
+        loss = C.c_double()
+        _check(self.ctx.handle, self._lib.stf_nn_train_step(
+            self.handle, B, _fptr(f, B * self._per(self.cfg.cin), "f"),
+            _fptr(t, B * self._per(2), "t"), float(lr), int(step), C.byref(loss)))
+        return loss.value

@@ -11,9 +11,9 @@ STF_OK, STF_EINVAL, STF_ENOMEM, STF_EDEVICE, STF_ESTATE, STF_EPIVOT, STF_ENOCONV
 STATUS_NAMES = {0: "STF_OK", 1: "STF_EINVAL", 2: "STF_ENOMEM", 3: "STF_EDEVICE", 4: "STF_ESTATE",
                 5: "STF_EPIVOT", 6: "STF_ENOCONV", 7: "STF_ENAN"}
 STF_C128, STF_C64 = 0, 1
-STF_X0_ZERO, STF_X0_USER = 0, 1
+STF_X0_ZERO, STF_X0_USER, STF_X0_LEARNED = 0, 1, 2
 KERNEL_CLASSES = ["assemble", "stencil", "front_asm", "front_lu", "sweep_fwd", "sweep_bwd",
-                  "scatter", "arnoldi", "update"]
+                  "scatter", "arnoldi", "update", "nn"]
 
 
 class Params(C.Structure):
@@ -34,7 +34,12 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
                 ("history_len", C.c_int32), ("relres_true", C.c_double),
                 ("relres_x0", C.c_double), ("history", C.POINTER(C.c_double)),
-                ("history_cap", C.c_int32), ("reserved0", C.c_int32)]
+                ("history_cap", C.c_int32), ("used_learned", C.c_int32)]
+
+
+class NNConfig(C.Structure):
+    _fields_ = [("n", C.c_int32), ("width", C.c_int32), ("modes", C.c_int32),
+                ("layers", C.c_int32), ("cin", C.c_int32), ("max_batch", C.c_int32)]
 
 
 class PlanInfo(C.Structure):
@@ -66,6 +71,21 @@ EXPORTS = {
     "stf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_problem_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
     "stf_problem_destroy": (None, [C.c_void_p]),
+    "stf_nn_param_count": (C.c_int64, [C.POINTER(NNConfig)]),
+    "stf_nn_create": (C.c_int, [C.c_void_p, C.POINTER(NNConfig), C.c_void_p,
+                                C.POINTER(C.c_void_p)]),
+    "stf_nn_destroy": (None, [C.c_void_p]),
+    "stf_nn_get_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "stf_nn_set_params": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "stf_nn_forward": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "stf_nn_loss_grad": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.POINTER(C.c_double), C.c_void_p]),
+    "stf_nn_train_step": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_double,
+                                    C.c_int32, C.POINTER(C.c_double)]),
+    "stf_ctx_set_nn": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "stf_nn_initial_guess": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "stf_nn_tile_data": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                                   C.c_void_p, C.POINTER(C.c_int32)]),
 }
 
 _lib = None

@@ -63,6 +63,7 @@ struct stf_ctx_s {
   int64_t launches[STF_K_COUNT] = {};
   double* pinned = nullptr;     // small pinned host staging area
   hipEvent_t iter_ev[2] = {nullptr, nullptr};   // per-iteration estimate copies
+  stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -187,6 +188,30 @@ struct stf_problem_s {
     for (const DBuf* b : all) s += (int64_t)b->bytes;
     return s;
   }
+};
+
+// Learned warm start: network parameters, Adam moments, twiddle tables and
+// the activations of one batch (kept for the backward pass).
+struct stf_nn_s {
+  stf_ctx ctx = nullptr;
+  stf_nn_config cfg{};
+  long long np = 0;
+  long long offP = 0, offQ = 0;
+  std::vector<long long> offR, offW;   // per layer: Re R (Im R follows), W_l (c_l follows)
+  DBuf par, grad, am, av;
+  DBuf exT;      // (n, 2M) floats: [cos | -sin](2 pi k x / n), the forward x transform
+  DBuf ey;       // (2M, n) float2: exp(-2 pi i ky(a) y / n)
+  DBuf exi;      // (M, n) float2: exp(+2 pi i k x / n)
+  DBuf ainv;     // (n, 4M) floats: [cos | -sin](2 pi ky(a) y / n), the inverse y transform
+  int cap = 0;   // batch capacity of the activation buffers
+  std::vector<DBuf> h, pre, H;
+  DBuf T, G, S, g, dh, dh2, dpre, dG, dH, y, dy, pwpart, lpart, den, loss;
+  // Tiling of the last problem passed to stf_nn_initial_guess.
+  DBuf org, oy, ox, tf, tpred;
+  std::vector<int> hoy, hox;
+
+  int NM() const { return 2 * cfg.modes * cfg.modes; }
+  long long npix() const { return (long long)cfg.n * cfg.n; }
 };
 
 namespace {
@@ -522,6 +547,248 @@ void ensure_krylov(stf_problem pb, int m) {
   pb->krylov_m = m;
 }
 
+// ---------------------------------------------------------------------------
+// Learned warm start
+// ---------------------------------------------------------------------------
+long long nn_param_count(const stf_nn_config& c) {
+  const long long W = c.width, M = c.modes;
+  return W * c.cin + W + (long long)c.layers * (2 * W * W * 2 * M * M + W * W + W) + 2 * W + 2;
+}
+
+void nn_validate(const stf_nn_config& c) {
+  STF_REQUIRE(c.n >= 4 && c.n <= 1024, "nn: tile side out of range");
+  STF_REQUIRE(c.modes >= 1 && 2 * c.modes <= c.n, "nn: modes out of range (2M <= n)");
+  STF_REQUIRE(c.layers >= 1 && c.layers <= 16, "nn: layers out of range");
+  STF_REQUIRE(c.cin == 3, "nn: three input features");
+  STF_REQUIRE(nn_width_supported(c.cin, c.width) && nn_width_supported(c.width, c.width) &&
+                  nn_width_supported(c.width, 2),
+              "nn: width must be 4, 8, 16 or 32");
+  STF_REQUIRE(c.max_batch >= 1 && c.max_batch <= 4096, "nn: max_batch out of range");
+}
+
+void nn_setup(stf_nn nn) {
+  const stf_nn_config& c = nn->cfg;
+  const long long W = c.width, NM = nn->NM();
+  nn->np = nn_param_count(c);
+  long long o = W * c.cin + W;
+  nn->offP = 0;
+  nn->offR.assign(c.layers, 0);
+  nn->offW.assign(c.layers, 0);
+  for (int l = 0; l < c.layers; ++l) {
+    nn->offR[l] = o;
+    o += 2 * W * W * NM;
+    nn->offW[l] = o;
+    o += W * W + W;
+  }
+  nn->offQ = o;
+  const size_t pb = (size_t)nn->np * sizeof(float);
+  nn->par.alloc(pb);
+  nn->grad.alloc(pb);
+  nn->am.alloc(pb);
+  nn->av.alloc(pb);
+  // Twiddle tables (double precision angles, rounded to float).
+  const int n = c.n, M = c.modes;
+  const double tw = 2.0 * M_PI / n;
+  std::vector<float> exT((size_t)n * 2 * M), ainv((size_t)n * 4 * M);
+  std::vector<float2> ey((size_t)2 * M * n), exi((size_t)M * n);
+  for (int x = 0; x < n; ++x)
+    for (int k = 0; k < M; ++k) {
+      const double ph = tw * (double)((long long)k * x % n);
+      exT[(size_t)x * 2 * M + k] = (float)std::cos(ph);
+      exT[(size_t)x * 2 * M + M + k] = (float)-std::sin(ph);
+      exi[(size_t)k * n + x] = make_float2((float)std::cos(ph), (float)std::sin(ph));
+    }
+  for (int a = 0; a < 2 * M; ++a) {
+    const long long ky = a < M ? a : n - 2 * M + a;
+    for (int y = 0; y < n; ++y) {
+      const double ph = tw * (double)(ky * y % n);
+      ey[(size_t)a * n + y] = make_float2((float)std::cos(ph), (float)-std::sin(ph));
+      ainv[(size_t)y * 4 * M + a] = (float)std::cos(ph);
+      ainv[(size_t)y * 4 * M + 2 * M + a] = (float)-std::sin(ph);
+    }
+  }
+  hipStream_t st = nn->ctx->stream;
+  upload(nn->exT, exT, st);
+  upload(nn->ainv, ainv, st);
+  upload(nn->ey, ey, st);
+  upload(nn->exi, exi, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+void nn_ensure(stf_nn nn, int B) {
+  STF_REQUIRE(B >= 1 && B <= nn->cfg.max_batch, "nn: batch out of range");
+  if (nn->cap >= B) return;
+  const stf_nn_config& c = nn->cfg;
+  const int L = c.layers, W = c.width, M = c.modes;
+  const size_t act = (size_t)B * W * nn->npix() * sizeof(float);
+  const size_t spec = (size_t)B * W * nn->NM() * sizeof(float2);
+  nn->h = std::vector<DBuf>(L + 1);
+  nn->pre = std::vector<DBuf>(L);
+  nn->H = std::vector<DBuf>(L);
+  for (auto& d : nn->h) d.alloc(act);
+  for (auto& d : nn->pre) d.alloc(act);
+  for (auto& d : nn->H) d.alloc(spec);
+  nn->T.alloc((size_t)B * W * c.n * 2 * M * sizeof(float));
+  nn->G.alloc(spec);
+  nn->dG.alloc(spec);
+  nn->dH.alloc(spec);
+  nn->S.alloc((size_t)B * W * 4 * M * c.n * sizeof(float));
+  nn->g.alloc(act);
+  nn->dh.alloc(act);
+  nn->dh2.alloc(act);
+  nn->dpre.alloc(act);
+  nn->y.alloc((size_t)B * 2 * nn->npix() * sizeof(float));
+  nn->dy.alloc((size_t)B * 2 * nn->npix() * sizeof(float));
+  nn->pwpart.alloc((size_t)nn_pw_bwd_blocks() * (W * W + W + 8) * sizeof(float));
+  nn->lpart.alloc((size_t)nn_loss_blocks() * B * 2 * sizeof(double));
+  nn->den.alloc((size_t)B * sizeof(double));
+  nn->loss.alloc(sizeof(double));
+  nn->cap = B;
+}
+
+// y = network(f); activations kept for nn_backward.
+void nn_forward(stf_nn nn, int B, const float* f, float* y) {
+  const stf_nn_config& c = nn->cfg;
+  hipStream_t st = nn->ctx->stream;
+  Timed t(nn->ctx, K_NN);
+  const int n = c.n, W = c.width, M = c.modes, L = c.layers, NM = nn->NM();
+  const long long npix = nn->npix();
+  const float* P = nn->par.as<float>();
+  float* h0 = nn->h[0].as<float>();
+  nn_pw_fwd(st, c.cin, W, false, f, P + nn->offP, P + nn->offP + W * c.cin, nullptr, npix, B,
+            nullptr, h0);
+  for (int l = 0; l < L; ++l) {
+    const float* hl = nn->h[l].as<float>();
+    float* T = nn->T.as<float>();
+    // T = h_l (B W n rows x n) [cos | -sin]: the x transform of every row.
+    nn_gemm(st, 1, B * W * n, 2 * M, n, hl, 0, n, 1, nn->exT.as<float>(), 0, 2 * M, 1, T, 0, 2 * M,
+            1, 1.0f, 0.0f);
+    float2* Hl = nn->H[l].as<float2>();
+    nn_dft_y(st, T, nn->ey.as<float2>(), B * W, n, M, false, Hl);
+    const float* Rre = P + nn->offR[l];
+    nn_mix_fwd(st, Hl, Rre, Rre + (long long)W * W * NM, B, W, NM, nn->G.as<float2>());
+    float* S = nn->S.as<float>();
+    nn_dft_x_inv(st, nn->G.as<float2>(), nn->exi.as<float2>(), B * W, n, M, true, S);
+    // g_plane = n^-2 [cos | -sin] (n x 4M) [Re S; Im S] (4M x n)
+    nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1,
+            nn->g.as<float>(), npix, n, 1, 1.0f / ((float)n * (float)n), 0.0f);
+    const float* Wl = P + nn->offW[l];
+    nn_pw_fwd(st, W, W, l < L - 1, hl, Wl, Wl + W * W, nn->g.as<float>(), npix, B,
+              nn->pre[l].as<float>(), nn->h[l + 1].as<float>());
+  }
+  nn_pw_fwd(st, W, 2, false, nn->h[L].as<float>(), P + nn->offQ, P + nn->offQ + 2 * W, nullptr,
+            npix, B, nullptr, y);
+}
+
+// Parameter gradient of the loss (dL/dy = dy) into nn->grad.
+void nn_backward(stf_nn nn, int B, const float* f, const float* dy) {
+  const stf_nn_config& c = nn->cfg;
+  hipStream_t st = nn->ctx->stream;
+  Timed t(nn->ctx, K_NN);
+  const int n = c.n, W = c.width, M = c.modes, L = c.layers, NM = nn->NM();
+  const long long npix = nn->npix();
+  const float* P = nn->par.as<float>();
+  float* Gd = nn->grad.as<float>();
+  float* part = nn->pwpart.as<float>();
+  float* dh = nn->dh.as<float>();
+  float* dh2 = nn->dh2.as<float>();
+  nn_pw_bwd(st, W, 2, false, dy, nullptr, nn->h[L].as<float>(), P + nn->offQ, npix, B, nullptr, dh,
+            part, Gd + nn->offQ);
+  for (int l = L - 1; l >= 0; --l) {
+    const float* Wl = P + nn->offW[l];
+    float* dpre = nn->dpre.as<float>();
+    nn_pw_bwd(st, W, W, l < L - 1, dh, nn->pre[l].as<float>(), nn->h[l].as<float>(), Wl, npix, B,
+              dpre, dh2, part, Gd + nn->offW[l]);
+    float* T = nn->T.as<float>();
+    nn_gemm(st, 1, B * W * n, 2 * M, n, dpre, 0, n, 1, nn->exT.as<float>(), 0, 2 * M, 1, T, 0, 2 * M,
+            1, 1.0f, 0.0f);
+    nn_dft_y(st, T, nn->ey.as<float2>(), B * W, n, M, true, nn->dG.as<float2>());
+    const float* Rre = P + nn->offR[l];
+    const long long rs = (long long)W * W * NM;
+    nn_mix_bwd(st, nn->H[l].as<float2>(), nn->dG.as<float2>(), Rre, Rre + rs, B, W, NM,
+               nn->dH.as<float2>(), Gd + nn->offR[l], Gd + nn->offR[l] + rs);
+    float* S = nn->S.as<float>();
+    nn_dft_x_inv(st, nn->dH.as<float2>(), nn->exi.as<float2>(), B * W, n, M, false, S);
+    nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1, dh2,
+            npix, n, 1, 1.0f, 1.0f);
+    std::swap(dh, dh2);
+  }
+  nn_pw_bwd(st, c.cin, W, false, dh, nullptr, f, P + nn->offP, npix, B, nullptr, nullptr, part,
+            Gd + nn->offP);
+}
+
+double nn_loss_grad(stf_nn nn, int B, const float* f, const float* t) {
+  nn_ensure(nn, B);
+  hipStream_t st = nn->ctx->stream;
+  nn_forward(nn, B, f, nn->y.as<float>());
+  {
+    Timed tm(nn->ctx, K_NN);
+    nn_loss(st, nn->y.as<float>(), t, 2 * nn->npix(), B, nn->lpart.as<double>(), nn->den.as<double>(),
+            nn->loss.as<double>(), nn->dy.as<float>());
+  }
+  nn_backward(nn, B, f, nn->dy.as<float>());
+  double L = 0.0;
+  HIP_CHECK(hipMemcpyAsync(&L, nn->loss.p, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  return L;
+}
+
+std::vector<int> nn_origins(int interior, int n) {
+  std::vector<int> o;
+  for (int v = 0; v + n <= interior; v += n / 2) o.push_back(v);
+  if (o.empty() || o.back() != interior - n) o.push_back(interior - n);
+  return o;
+}
+
+// Tile origins of problem pb for tiles of side n (interior coordinates),
+// uploaded to the network's buffers; returns the tile count.
+int nn_tiling(stf_problem pb, stf_nn nn, int n) {
+  STF_REQUIRE(pb->assembled, "nn: problem not assembled");
+  STF_REQUIRE(nn->ctx == pb->ctx, "nn: network and problem on different contexts");
+  const stf_params& p = pb->prm;
+  const int inx = p.nx - p.pml[0] - p.pml[1], iny = p.ny - p.pml[2] - p.pml[3];
+  STF_REQUIRE(inx >= n && iny >= n, "nn: physical interior smaller than one tile");
+  hipStream_t st = pb->ctx->stream;
+  nn->hoy = nn_origins(iny, n);
+  nn->hox = nn_origins(inx, n);
+  const int nty = (int)nn->hoy.size(), ntx = (int)nn->hox.size();
+  std::vector<int2> org;
+  for (int a = 0; a < nty; ++a)
+    for (int c2 = 0; c2 < ntx; ++c2) org.push_back(make_int2(nn->hox[c2], nn->hoy[a]));
+  upload(nn->org, org, st);
+  upload(nn->oy, nn->hoy, st);
+  upload(nn->ox, nn->hox, st);
+  return nty * ntx;
+}
+
+// x0 = blended tile predictions for source b (device).
+void nn_initial_guess(stf_problem pb, stf_nn nn, const double2* b, double2* x0) {
+  const stf_params& p = pb->prm;
+  const int n = nn->cfg.n;
+  const int inx = p.nx - p.pml[0] - p.pml[1], iny = p.ny - p.pml[2] - p.pml[3];
+  hipStream_t st = pb->ctx->stream;
+  const int nt = nn_tiling(pb, nn, n);
+  const int nty = (int)nn->hoy.size(), ntx = (int)nn->hox.size();
+  const long long per = nn->npix();
+  nn->tf.alloc((size_t)nt * 3 * per * sizeof(float));
+  nn->tpred.alloc((size_t)nt * 2 * per * sizeof(float));
+  {
+    Timed t(pb->ctx, K_NN);
+    nn_features(st, pb->keps.as<double2>(), b, p.k0 * p.k0, p.nx, p.pml[0], p.pml[2],
+                nn->org.as<int2>(), nt, n, nn->tf.as<float>());
+  }
+  const int bmax = nn->cfg.max_batch;
+  nn_ensure(nn, std::min(bmax, nt));
+  for (int t0 = 0; t0 < nt; t0 += bmax) {
+    const int B = std::min(bmax, nt - t0);
+    nn_forward(nn, B, nn->tf.as<float>() + (long long)t0 * 3 * per,
+               nn->tpred.as<float>() + (long long)t0 * 2 * per);
+  }
+  Timed t(pb->ctx, K_NN);
+  nn_blend(st, nn->tpred.as<float>(), nn->oy.as<int>(), nty, nn->ox.as<int>(), ntx, n, p.pml[0],
+           p.pml[2], inx, iny, p.nx, p.ny, x0);
+}
+
 // Scalars on device: [0] |b|^2 (double2 slot 0..1), [2] |r|^2, [3] |w|^2, [4] est.
 stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_solve_opts& o,
                       stf_solve_info* info) {
@@ -545,12 +812,30 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
   const int nblk = krylov_blocks(N);
 
   if (o.x0_mode == STF_X0_ZERO) HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
+  if (o.x0_mode == STF_X0_LEARNED) {
+    STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+    nn_initial_guess(pb, c->nn, b, x);
+  }
   norm2(pb, b, reinterpret_cast<double2*>(sc));          // sc[0] = |b|^2
   residual(pb, x, b, r, sc + 2);                         // sc[2] = |r|^2
   HIP_CHECK(hipMemcpyAsync(hp, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   const double bnorm = std::sqrt(hp[0]);
   double rnorm = std::sqrt(hp[2]);
+  double relres_guess = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+  int used_learned = 0;
+  if (o.x0_mode == STF_X0_LEARNED) {
+    // Fallback: the zero guess whenever the network's residual is not below |b|.
+    if (!(rnorm < bnorm)) {
+      HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
+      residual(pb, x, b, r, sc + 2);
+      HIP_CHECK(hipMemcpyAsync(hp + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      rnorm = std::sqrt(hp[2]);
+    } else {
+      used_learned = 1;
+    }
+  }
   int hlen = 0;
   auto hist = [&](double v) {
     if (info && info->history && hlen < info->history_cap) info->history[hlen] = v;
@@ -571,7 +856,8 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
     return STF_OK;
   }
   if (!std::isfinite(rnorm)) throw Error(STF_ENAN, "non-finite initial residual");
-  loc.relres_x0 = rnorm / bnorm;
+  loc.relres_x0 = o.x0_mode == STF_X0_LEARNED ? relres_guess : rnorm / bnorm;
+  loc.used_learned = used_learned;
   hist(rnorm / bnorm);
   int it = 0, restarts = 0;
   stf_status status = STF_ENOCONV;
@@ -916,7 +1202,9 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
     STF_REQUIRE(opts->restart >= 1 && opts->restart <= 200, "restart out of range");
     STF_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
     STF_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be finite and >= 0");
-    STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER, "x0_mode invalid");
+    STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER ||
+                    opts->x0_mode == STF_X0_LEARNED,
+                "x0_mode invalid");
     STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
     if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
     const size_t per = (size_t)pb->N * 2;
@@ -965,6 +1253,173 @@ void stf_problem_destroy(stf_problem pb) {
   (void)hipSetDevice(pb->ctx->device);
   (void)hipStreamSynchronize(pb->ctx->stream);
   delete pb;
+}
+
+// ---- learned warm start ------------------------------------------------
+
+int64_t stf_nn_param_count(const stf_nn_config* cfg) {
+  if (!cfg) return -1;
+  try {
+    nn_validate(*cfg);
+  } catch (...) {
+    return -1;
+  }
+  return nn_param_count(*cfg);
+}
+
+stf_status stf_nn_create(stf_ctx ctx, const stf_nn_config* cfg, const float* params, stf_nn* out) {
+  if (!ctx || !out) return STF_EINVAL;
+  *out = nullptr;
+  stf_nn nn = nullptr;
+  stf_status s = guard(ctx, [&] {
+    STF_REQUIRE(cfg && params, "null argument");
+    nn_validate(*cfg);
+    nn = new stf_nn_s();
+    nn->ctx = ctx;
+    nn->cfg = *cfg;
+    nn_setup(nn);
+    const size_t pb = (size_t)nn->np * sizeof(float);
+    for (long long i = 0; i < nn->np; ++i)
+      STF_REQUIRE(std::isfinite(params[i]), "nn: non-finite parameter");
+    HIP_CHECK(hipMemcpyAsync(nn->par.p, params, pb, hipMemcpyHostToDevice, ctx->stream));
+    HIP_CHECK(hipMemsetAsync(nn->am.p, 0, pb, ctx->stream));
+    HIP_CHECK(hipMemsetAsync(nn->av.p, 0, pb, ctx->stream));
+    HIP_CHECK(hipMemsetAsync(nn->grad.p, 0, pb, ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+  });
+  if (s != STF_OK) {
+    delete nn;
+    return s;
+  }
+  *out = nn;
+  return STF_OK;
+}
+
+void stf_nn_destroy(stf_nn nn) {
+  if (!nn) return;
+  (void)hipSetDevice(nn->ctx->device);
+  (void)hipStreamSynchronize(nn->ctx->stream);
+  if (nn->ctx->nn == nn) nn->ctx->nn = nullptr;
+  delete nn;
+}
+
+stf_status stf_nn_get_params(stf_nn nn, float* params) {
+  if (!nn) return STF_EINVAL;
+  return guard(nn->ctx, [&] {
+    STF_REQUIRE(params, "null argument");
+    HIP_CHECK(hipMemcpyAsync(params, nn->par.p, (size_t)nn->np * sizeof(float),
+                             hipMemcpyDeviceToHost, nn->ctx->stream));
+    HIP_CHECK(hipStreamSynchronize(nn->ctx->stream));
+  });
+}
+
+stf_status stf_nn_set_params(stf_nn nn, const float* params) {
+  if (!nn) return STF_EINVAL;
+  return guard(nn->ctx, [&] {
+    STF_REQUIRE(params, "null argument");
+    for (long long i = 0; i < nn->np; ++i)
+      STF_REQUIRE(std::isfinite(params[i]), "nn: non-finite parameter");
+    const size_t pb = (size_t)nn->np * sizeof(float);
+    hipStream_t st = nn->ctx->stream;
+    HIP_CHECK(hipMemcpyAsync(nn->par.p, params, pb, hipMemcpyHostToDevice, st));
+    HIP_CHECK(hipMemsetAsync(nn->am.p, 0, pb, st));
+    HIP_CHECK(hipMemsetAsync(nn->av.p, 0, pb, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+stf_status stf_nn_forward(stf_nn nn, int32_t batch, const float* f, float* y) {
+  if (!nn) return STF_EINVAL;
+  return guard(nn->ctx, [&] {
+    STF_REQUIRE(f && y, "null argument");
+    nn_ensure(nn, batch);
+    nn_forward(nn, batch, f, y);
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+stf_status stf_nn_loss_grad(stf_nn nn, int32_t batch, const float* f, const float* t, double* loss,
+                            float* grad) {
+  if (!nn) return STF_EINVAL;
+  return guard(nn->ctx, [&] {
+    STF_REQUIRE(f && t && loss, "null argument");
+    *loss = nn_loss_grad(nn, batch, f, t);
+    STF_REQUIRE(std::isfinite(*loss), "nn: non-finite loss");
+    if (grad) {
+      HIP_CHECK(hipMemcpyAsync(grad, nn->grad.p, (size_t)nn->np * sizeof(float),
+                               hipMemcpyDeviceToHost, nn->ctx->stream));
+      HIP_CHECK(hipStreamSynchronize(nn->ctx->stream));
+    }
+  });
+}
+
+stf_status stf_nn_train_step(stf_nn nn, int32_t batch, const float* f, const float* t, double lr,
+                             int32_t step, double* loss) {
+  if (!nn) return STF_EINVAL;
+  return guard(nn->ctx, [&] {
+    STF_REQUIRE(f && t && loss, "null argument");
+    STF_REQUIRE(step >= 1, "nn: step counts from 1");
+    STF_REQUIRE(std::isfinite(lr) && lr > 0, "nn: learning rate must be positive");
+    *loss = nn_loss_grad(nn, batch, f, t);
+    STF_REQUIRE(std::isfinite(*loss), "nn: non-finite loss");
+    Timed tm(nn->ctx, K_NN);
+    nn_adam(nn->ctx->stream, nn->par.as<float>(), nn->grad.as<float>(), nn->am.as<float>(),
+            nn->av.as<float>(), nn->np, lr, step, 0.9, 0.999, 1e-8);
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+stf_status stf_ctx_set_nn(stf_ctx ctx, stf_nn nn) {
+  if (!ctx) return STF_EINVAL;
+  return guard(ctx, [&] {
+    STF_REQUIRE(!nn || nn->ctx == ctx, "network created on another context");
+    ctx->nn = nn;
+  });
+}
+
+stf_status stf_nn_tile_data(stf_problem pb, stf_nn nn, const double* b, const double* x, float* f,
+                            float* t, int32_t* ntiles) {
+  if (!pb || !nn) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(ntiles, "null argument");
+    const stf_params& p = pb->prm;
+    const int n = nn->cfg.n;
+    const int nt = nn_tiling(pb, nn, n);
+    *ntiles = nt;
+    hipStream_t st = pb->ctx->stream;
+    if (f) {
+      STF_REQUIRE(b, "b is required with f");
+      nn_features(st, pb->keps.as<double2>(), reinterpret_cast<const double2*>(b), p.k0 * p.k0,
+                  p.nx, p.pml[0], p.pml[2], nn->org.as<int2>(), nt, n, f);
+    }
+    if (t) {
+      STF_REQUIRE(x, "x is required with t");
+      nn_fields(st, reinterpret_cast<const double2*>(x), p.nx, p.pml[0], p.pml[2],
+                nn->org.as<int2>(), nt, n, t);
+    }
+    HIP_CHECK(hipGetLastError());
+  });
+}
+
+stf_status stf_nn_initial_guess(stf_problem pb, stf_nn nn, const double* b, double* x0,
+                                int on_device) {
+  if (!pb || !nn) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(b && x0, "null argument");
+    const size_t vb = (size_t)pb->N * sizeof(double2);
+    hipStream_t st = pb->ctx->stream;
+    require_finite(pb, b, (size_t)pb->N * 2, on_device, "b");
+    if (on_device) {
+      nn_initial_guess(pb, nn, reinterpret_cast<const double2*>(b), reinterpret_cast<double2*>(x0));
+    } else {
+      pb->hb.alloc(vb);
+      pb->hx.alloc(vb);
+      HIP_CHECK(hipMemcpyAsync(pb->hb.p, b, vb, hipMemcpyHostToDevice, st));
+      nn_initial_guess(pb, nn, pb->hb.as<double2>(), pb->hx.as<double2>());
+      HIP_CHECK(hipMemcpyAsync(x0, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
+    }
+    HIP_CHECK(hipStreamSynchronize(st));
+  });
 }
 
 }  // extern "C"

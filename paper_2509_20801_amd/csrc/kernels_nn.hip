@@ -1,0 +1,623 @@
+// Learned warm start: FP32 kernels of the spectral neural operator (forward,
+// backward, loss, Adam) and of the tiled initial guess (features, blending).
+//
+// Tensors are planar, [sample][channel][y][x] with x fastest.  The spectral
+// convolution keeps the modes k = 0..M-1 along x and ky = -M..M-1 along y; the
+// truncated DFTs are evaluated as products with twiddle tables: the large ones
+// (along x forward, along y inverse) through a batched, strided, LDS-tiled
+// GEMM, the small ones (along y forward, along x inverse, the per-mode channel
+// mixing) by dedicated kernels.  Gradient reductions are per-block partial
+// sums added in a fixed order, so training is deterministic.
+#include <cmath>
+
+#include "stf_internal.h"
+
+namespace stf {
+
+namespace {
+
+constexpr int NNT = 256;
+
+__device__ inline float gelu_f(float x) {
+  const float c = 0.7978845608028654f;
+  return 0.5f * x * (1.0f + tanhf(c * (x + 0.044715f * x * x * x)));
+}
+
+__device__ inline float gelu_df(float x) {
+  const float c = 0.7978845608028654f;
+  const float t = tanhf(c * (x + 0.044715f * x * x * x));
+  return 0.5f * (1.0f + t) + 0.5f * x * (1.0f - t * t) * c * (1.0f + 3.0f * 0.044715f * x * x);
+}
+
+// ---------------------------------------------------------------------------
+// C[b] = alpha A[b] B[b] + beta C[b], A (M x K), B (K x N), arbitrary strides.
+// 64 x 64 output tile per 256-thread workgroup, 4 x 4 per thread, K staged in
+// LDS 16 at a time.
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  const float* A;
+  const float* B;
+  float* C;
+  int M, N, K;
+  long long sAb, sAm, sAk, sBb, sBk, sBn, sCb, sCm, sCn;
+  float alpha, beta;
+};
+
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  constexpr int TM = 64, TN = 64, TK = 16;
+  __shared__ float As[TK][TM + 4];
+  __shared__ float Bs[TK][TN + 4];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN, b = blockIdx.z;
+  const float* A = g.A + b * g.sAb;
+  const float* Bm = g.B + b * g.sBb;
+  float acc[4][4] = {};
+  for (int k0 = 0; k0 < g.K; k0 += TK) {
+    for (int t = tid; t < TM * TK; t += 256) {
+      const int mm = t % TM, kk = t / TM;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < g.K) ? A[m * g.sAm + k * g.sAk] : 0.0f;
+    }
+    for (int t = tid; t < TN * TK; t += 256) {
+      const int nn = t % TN, kk = t / TN;
+      const int n = n0 + nn, k = k0 + kk;
+      Bs[kk][nn] = (n < g.N && k < g.K) ? Bm[k * g.sBk + n * g.sBn] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < TK; ++kk) {
+      float a[4], bb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], bb[j], acc[i][j]);
+    }
+    __syncthreads();
+  }
+  float* C = g.C + b * g.sCb;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int m = m0 + ty + 16 * i;
+    if (m >= g.M) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int n = n0 + tx + 16 * j;
+      if (n >= g.N) continue;
+      float* c = C + m * g.sCm + n * g.sCn;
+      *c = g.alpha * acc[i][j] + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Truncated DFT along y of one plane: H[a, k] = s_k sum_y Ey[a, y] T[y, k],
+// T row y = [Re (M) | Im (M)] of the x transform, Ey = exp(-2 pi i ky(a) y / n).
+// s_k = 1 (forward) or w_k / n^2 (gradient through the inverse transform).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NNT) void k_dft_y(const float* __restrict__ T,
+                                               const float2* __restrict__ ey, int n, int M,
+                                               int grad_scale, float2* __restrict__ H) {
+  extern __shared__ float Ts[];                  // n x 2M
+  const int plane = blockIdx.x;
+  const float* Tp = T + (long long)plane * n * 2 * M;
+  for (int t = threadIdx.x; t < n * 2 * M; t += NNT) Ts[t] = Tp[t];
+  __syncthreads();
+  const float inv = 1.0f / ((float)n * (float)n);
+  for (int o = threadIdx.x; o < 2 * M * M; o += NNT) {
+    const int a = o / M, k = o - a * M;
+    const float2* e = ey + (long long)a * n;
+    float re = 0.0f, im = 0.0f;
+    for (int y = 0; y < n; ++y) {
+      const float2 w = e[y];
+      const float tr = Ts[y * 2 * M + k], ti = Ts[y * 2 * M + M + k];
+      re = fmaf(w.x, tr, fmaf(-w.y, ti, re));
+      im = fmaf(w.x, ti, fmaf(w.y, tr, im));
+    }
+    float s = 1.0f;
+    if (grad_scale) s = (k == 0 ? 1.0f : 2.0f) * inv;
+    H[(long long)plane * 2 * M * M + o] = make_float2(s * re, s * im);
+  }
+}
+
+// Inverse along x of one plane: S[a, x] = sum_k w_k G[a, k] exp(+2 pi i k x / n)
+// (w_k = 1, 2, 2, ... when weighted, else 1), stored planar: Re rows 0..2M-1,
+// Im rows 2M..4M-1, each of n entries.
+__global__ __launch_bounds__(NNT) void k_dft_x_inv(const float2* __restrict__ G,
+                                                   const float2* __restrict__ ex, int n, int M,
+                                                   int weighted, float* __restrict__ S) {
+  extern __shared__ float2 Gs[];                 // 2M x M
+  const int plane = blockIdx.y;
+  const float2* Gp = G + (long long)plane * 2 * M * M;
+  for (int t = threadIdx.x; t < 2 * M * M; t += NNT) Gs[t] = Gp[t];
+  __syncthreads();
+  const int o = blockIdx.x * NNT + threadIdx.x;
+  if (o >= 2 * M * n) return;
+  const int a = o / n, x = o - a * n;
+  float re = 0.0f, im = 0.0f;
+  for (int k = 0; k < M; ++k) {
+    const float2 w = ex[(long long)k * n + x];   // exp(+2 pi i k x / n)
+    float2 gv = Gs[a * M + k];
+    if (weighted && k > 0) gv = make_float2(2.0f * gv.x, 2.0f * gv.y);
+    re = fmaf(gv.x, w.x, fmaf(-gv.y, w.y, re));
+    im = fmaf(gv.x, w.y, fmaf(gv.y, w.x, im));
+  }
+  float* Sp = S + (long long)plane * 4 * M * n;
+  Sp[(long long)a * n + x] = re;
+  Sp[(long long)(2 * M + a) * n + x] = im;
+}
+
+// G[b, o, mode] = sum_i R[i, o, mode] H[b, i, mode].
+__global__ __launch_bounds__(NNT) void k_mix_fwd(const float2* __restrict__ H,
+                                                 const float* __restrict__ Rre,
+                                                 const float* __restrict__ Rim, int B, int W,
+                                                 int NM, float2* __restrict__ G) {
+  const long long t = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (t >= (long long)B * W * NM) return;
+  const int mode = (int)(t % NM);
+  const int o = (int)((t / NM) % W);
+  const int b = (int)(t / ((long long)NM * W));
+  float re = 0.0f, im = 0.0f;
+  for (int i = 0; i < W; ++i) {
+    const long long ri = ((long long)i * W + o) * NM + mode;
+    const float rr = Rre[ri], rim = Rim[ri];
+    const float2 h = H[((long long)b * W + i) * NM + mode];
+    re = fmaf(rr, h.x, fmaf(-rim, h.y, re));
+    im = fmaf(rr, h.y, fmaf(rim, h.x, im));
+  }
+  G[t] = make_float2(re, im);
+}
+
+// dH[b, i, mode] = sum_o conj(R[i, o, mode]) dG[b, o, mode].
+__global__ __launch_bounds__(NNT) void k_mix_bwd_h(const float2* __restrict__ dG,
+                                                   const float* __restrict__ Rre,
+                                                   const float* __restrict__ Rim, int B, int W,
+                                                   int NM, float2* __restrict__ dH) {
+  const long long t = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (t >= (long long)B * W * NM) return;
+  const int mode = (int)(t % NM);
+  const int i = (int)((t / NM) % W);
+  const int b = (int)(t / ((long long)NM * W));
+  float re = 0.0f, im = 0.0f;
+  for (int o = 0; o < W; ++o) {
+    const long long ri = ((long long)i * W + o) * NM + mode;
+    const float rr = Rre[ri], rim = Rim[ri];
+    const float2 d = dG[((long long)b * W + o) * NM + mode];
+    re = fmaf(rr, d.x, fmaf(rim, d.y, re));       // conj(R) d
+    im = fmaf(rr, d.y, fmaf(-rim, d.x, im));
+  }
+  dH[t] = make_float2(re, im);
+}
+
+// dR[i, o, mode] = sum_b conj(H[b, i, mode]) dG[b, o, mode] (Re and Im blocks).
+__global__ __launch_bounds__(NNT) void k_mix_bwd_r(const float2* __restrict__ H,
+                                                   const float2* __restrict__ dG, int B, int W,
+                                                   int NM, float* __restrict__ dRre,
+                                                   float* __restrict__ dRim) {
+  const long long t = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (t >= (long long)W * W * NM) return;
+  const int mode = (int)(t % NM);
+  const int o = (int)((t / NM) % W);
+  const int i = (int)(t / ((long long)NM * W));
+  float re = 0.0f, im = 0.0f;
+  for (int b = 0; b < B; ++b) {
+    const float2 h = H[((long long)b * W + i) * NM + mode];
+    const float2 d = dG[((long long)b * W + o) * NM + mode];
+    re = fmaf(h.x, d.x, fmaf(h.y, d.y, re));
+    im = fmaf(h.x, d.y, fmaf(-h.y, d.x, im));
+  }
+  dRre[t] = re;
+  dRim[t] = im;
+}
+
+// ---------------------------------------------------------------------------
+// Pointwise channel mixing, one thread per pixel:
+//   pre[o] = sum_i Wm[o, i] in[i] + bias[o] (+ add[o]);  out = ACT ? gelu(pre) : pre.
+// ---------------------------------------------------------------------------
+template <int CI, int CO, bool ACT>
+__global__ __launch_bounds__(NNT) void k_pw_fwd(const float* __restrict__ in,
+                                                const float* __restrict__ Wm,
+                                                const float* __restrict__ bias,
+                                                const float* __restrict__ add, long long npix,
+                                                int B, float* __restrict__ pre,
+                                                float* __restrict__ out) {
+  const long long t = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (t >= npix * B) return;
+  const long long b = t / npix, p = t - b * npix;
+  float x[CI];
+#pragma unroll
+  for (int i = 0; i < CI; ++i) x[i] = in[(b * CI + i) * npix + p];
+#pragma unroll
+  for (int o = 0; o < CO; ++o) {
+    float s = bias[o];
+#pragma unroll
+    for (int i = 0; i < CI; ++i) s = fmaf(Wm[o * CI + i], x[i], s);
+    const long long oi = (b * CO + o) * npix + p;
+    if (add) s += add[oi];
+    if (ACT) {
+      pre[oi] = s;
+      out[oi] = gelu_f(s);
+    } else {
+      out[oi] = s;
+    }
+  }
+}
+
+// Backward of k_pw_fwd over tiles of 64 pixels (one sample at a time):
+//   dpre = ACT ? dout * gelu'(pre) : dout   (stored when dpre_out is given)
+//   din[i] = sum_o Wm[o, i] dpre[o]          (when din is given)
+//   partial[blk] = [sum dpre[o] in[i] (CO x CI), sum dpre[o] (CO)] over the block's tiles.
+template <int CI, int CO, bool ACT>
+__global__ __launch_bounds__(NNT) void k_pw_bwd(const float* __restrict__ dout,
+                                                const float* __restrict__ pre,
+                                                const float* __restrict__ in,
+                                                const float* __restrict__ Wm, long long npix,
+                                                int B, float* __restrict__ dpre_out,
+                                                float* __restrict__ din,
+                                                float* __restrict__ partial) {
+  constexpr int P = 64;
+  __shared__ float sd[CO][P];
+  __shared__ float si[CI][P];
+  const int tid = threadIdx.x;
+  const long long ntile = (npix + P - 1) / P * B;
+  float accw[(CO * CI + NNT - 1) / NNT] = {};
+  float accb = 0.0f;
+  for (long long tile = blockIdx.x; tile < ntile; tile += gridDim.x) {
+    const long long b = tile / ((npix + P - 1) / P);
+    const long long p0 = (tile - b * ((npix + P - 1) / P)) * P;
+    __syncthreads();
+    for (int t = tid; t < CO * P; t += NNT) {
+      const int o = t / P, j = t % P;
+      const long long p = p0 + j;
+      float d = 0.0f;
+      if (p < npix) {
+        const long long oi = (b * CO + o) * npix + p;
+        d = dout[oi];
+        if (ACT) d *= gelu_df(pre[oi]);
+        if (dpre_out) dpre_out[oi] = d;
+      }
+      sd[o][j] = d;
+    }
+    for (int t = tid; t < CI * P; t += NNT) {
+      const int i = t / P, j = t % P;
+      const long long p = p0 + j;
+      si[i][j] = p < npix ? in[(b * CI + i) * npix + p] : 0.0f;
+    }
+    __syncthreads();
+    if (din) {
+      for (int t = tid; t < CI * P; t += NNT) {
+        const int i = t / P, j = t % P;
+        const long long p = p0 + j;
+        if (p >= npix) continue;
+        float s = 0.0f;
+#pragma unroll
+        for (int o = 0; o < CO; ++o) s = fmaf(Wm[o * CI + i], sd[o][j], s);
+        din[(b * CI + i) * npix + p] = s;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < (CO * CI + NNT - 1) / NNT; ++q) {
+      const int t = tid + q * NNT;
+      if (t < CO * CI) {
+        const int o = t / CI, i = t % CI;
+        float s = 0.0f;
+        for (int j = 0; j < P; ++j) s = fmaf(sd[o][j], si[i][j], s);
+        accw[q] += s;
+      }
+    }
+    if (tid < CO) {
+      float s = 0.0f;
+      for (int j = 0; j < P; ++j) s += sd[tid][j];
+      accb += s;
+    }
+  }
+  float* part = partial + (long long)blockIdx.x * (CO * CI + CO);
+#pragma unroll
+  for (int q = 0; q < (CO * CI + NNT - 1) / NNT; ++q) {
+    const int t = tid + q * NNT;
+    if (t < CO * CI) part[t] = accw[q];
+  }
+  if (tid < CO) part[CO * CI + tid] = accb;
+}
+
+// out[j] = sum over blocks of partial[blk * stride + j], blocks in order.
+__global__ __launch_bounds__(NNT) void k_sum_partials(const float* __restrict__ partial, int nblk,
+                                                      int stride, int count, float* __restrict__ out) {
+  const int j = blockIdx.x * NNT + threadIdx.x;
+  if (j >= count) return;
+  float s = 0.0f;
+  for (int b = 0; b < nblk; ++b) s += partial[(long long)b * stride + j];
+  out[j] = s;
+}
+
+// Per-sample sums of (y - t)^2 and t^2: partial[(b * nblk + blk) * 2 + {0, 1}].
+__global__ __launch_bounds__(NNT) void k_loss_partial(const float* __restrict__ y,
+                                                      const float* __restrict__ t, long long per,
+                                                      int nblk, double* __restrict__ partial) {
+  __shared__ double s0[NNT], s1[NNT];
+  const int b = blockIdx.y, blk = blockIdx.x;
+  double a0 = 0.0, a1 = 0.0;
+  for (long long i = (long long)blk * NNT + threadIdx.x; i < per; i += (long long)nblk * NNT) {
+    const double d = (double)y[b * per + i] - (double)t[b * per + i];
+    const double tv = t[b * per + i];
+    a0 += d * d;
+    a1 += tv * tv;
+  }
+  s0[threadIdx.x] = a0;
+  s1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int s = NNT / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) {
+      s0[threadIdx.x] += s0[threadIdx.x + s];
+      s1[threadIdx.x] += s1[threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[((long long)b * nblk + blk) * 2] = s0[0];
+    partial[((long long)b * nblk + blk) * 2 + 1] = s1[0];
+  }
+}
+
+// loss = mean_b num_b / den_b; den[b] = den_b (one thread).
+__global__ void k_loss_final(const double* __restrict__ partial, int B, int nblk,
+                             double* __restrict__ den, double* __restrict__ loss) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double L = 0.0;
+  for (int b = 0; b < B; ++b) {
+    double n0 = 0.0, d0 = 0.0;
+    for (int k = 0; k < nblk; ++k) {
+      n0 += partial[((long long)b * nblk + k) * 2];
+      d0 += partial[((long long)b * nblk + k) * 2 + 1];
+    }
+    den[b] = d0;
+    L += n0 / d0;
+  }
+  *loss = L / B;
+}
+
+// dy = 2 (y - t) / (B den_b).
+__global__ __launch_bounds__(NNT) void k_loss_grad(const float* __restrict__ y,
+                                                   const float* __restrict__ t,
+                                                   const double* __restrict__ den, long long per,
+                                                   int B, float* __restrict__ dy) {
+  const long long i = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (i >= per * B) return;
+  const long long b = i / per;
+  dy[i] = (float)(2.0 * ((double)y[i] - (double)t[i]) / ((double)B * den[b]));
+}
+
+// Adam (Kingma & Ba 2015): bc1 = 1 - beta1^step, bc2 = 1 - beta2^step.
+__global__ __launch_bounds__(NNT) void k_adam(float* __restrict__ p, const float* __restrict__ g,
+                                              float* __restrict__ m, float* __restrict__ v,
+                                              long long n, float lr, float beta1, float beta2,
+                                              float bc1, float bc2, float eps) {
+  const long long i = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+  const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Tiles of a problem: features and the blended initial guess.
+// ---------------------------------------------------------------------------
+// f[t] = [(Re keps / k0^2 - 1) / 4, Re b, Im b] on the n x n tile t whose
+// corner is (pml_y + oy[t], pml_x + ox[t]).
+__global__ __launch_bounds__(NNT) void k_nn_features(const double2* __restrict__ keps,
+                                                     const double2* __restrict__ b, double k0sq,
+                                                     int nx, int pml_x, int pml_y,
+                                                     const int2* __restrict__ org, int n,
+                                                     float* __restrict__ f) {
+  const int tile = blockIdx.y;
+  const long long p = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (p >= (long long)n * n) return;
+  const int y = (int)(p / n), x = (int)(p % n);
+  const int2 o = org[tile];
+  const long long g = (long long)(pml_y + o.y + y) * nx + (pml_x + o.x + x);
+  const long long per = (long long)n * n;
+  float* ft = f + (long long)tile * 3 * per;
+  ft[p] = (float)((keps[g].x / k0sq - 1.0) * 0.25);
+  ft[per + p] = (float)b[g].x;
+  ft[2 * per + p] = (float)b[g].y;
+}
+
+// t[tile] = [Re x, Im x] on the n x n tile (same placement as k_nn_features).
+__global__ __launch_bounds__(NNT) void k_nn_fields(const double2* __restrict__ x, int nx, int pml_x,
+                                                   int pml_y, const int2* __restrict__ org, int n,
+                                                   float* __restrict__ t) {
+  const int tile = blockIdx.y;
+  const long long p = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (p >= (long long)n * n) return;
+  const int y = (int)(p / n), xx = (int)(p % n);
+  const int2 o = org[tile];
+  const long long g = (long long)(pml_y + o.y + y) * nx + (pml_x + o.x + xx);
+  const long long per = (long long)n * n;
+  t[(long long)tile * 2 * per + p] = (float)x[g].x;
+  t[(long long)tile * 2 * per + per + p] = (float)x[g].y;
+}
+
+__device__ inline double tile_w(int i, int n, bool first, bool last) {
+  if ((first && i < n / 2) || (last && i >= n / 2)) return 1.0;
+  const double s = sinpi((i + 0.5) / n);
+  return s * s;
+}
+
+// x0 = sum_t w_t pred_t / sum_t w_t on the interior, 0 in the global PML.
+// Tile origins along each axis: oy[0..nty), ox[0..ntx) (interior coordinates);
+// pred[(ty * ntx + tx)] holds (2, n, n).
+__global__ __launch_bounds__(NNT) void k_nn_blend(const float* __restrict__ pred,
+                                                  const int* __restrict__ oy, int nty,
+                                                  const int* __restrict__ ox, int ntx, int n,
+                                                  int pml_x, int pml_y, int inx, int iny, int nx,
+                                                  int ny, double2* __restrict__ x0) {
+  const long long g = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (g >= (long long)nx * ny) return;
+  const int gy = (int)(g / nx), gx = (int)(g % nx);
+  const int iy = gy - pml_y, ix = gx - pml_x;
+  double2 out = make_double2(0.0, 0.0);
+  if (iy >= 0 && iy < iny && ix >= 0 && ix < inx) {
+    const long long per = (long long)n * n;
+    double re = 0.0, im = 0.0, ws = 0.0;
+    for (int a = 0; a < nty; ++a) {
+      const int ly = iy - oy[a];
+      if (ly < 0 || ly >= n) continue;
+      const double wy = tile_w(ly, n, a == 0, a == nty - 1);
+      for (int c = 0; c < ntx; ++c) {
+        const int lx = ix - ox[c];
+        if (lx < 0 || lx >= n) continue;
+        const double w = wy * tile_w(lx, n, c == 0, c == ntx - 1);
+        const float* pt = pred + (long long)(a * ntx + c) * 2 * per;
+        re += w * pt[(long long)ly * n + lx];
+        im += w * pt[per + (long long)ly * n + lx];
+        ws += w;
+      }
+    }
+    if (ws > 0.0) out = make_double2(re / ws, im / ws);
+  }
+  x0[g] = out;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, long long sAb,
+             long long sAm, long long sAk, const float* B, long long sBb, long long sBk,
+             long long sBn, float* C, long long sCb, long long sCm, long long sCn, float alpha,
+             float beta) {
+  GemmArgs g{A, B, C, M, N, K, sAb, sAm, sAk, sBb, sBk, sBn, sCb, sCm, sCn, alpha, beta};
+  dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+}
+
+void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int n, int M,
+              bool grad_scale, float2* H) {
+  hipLaunchKernelGGL(k_dft_y, dim3(planes), dim3(NNT), (size_t)n * 2 * M * sizeof(float), st, T, ey,
+                     n, M, grad_scale ? 1 : 0, H);
+}
+
+void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
+                  bool weighted, float* S) {
+  dim3 grid((2 * M * n + NNT - 1) / NNT, planes);
+  hipLaunchKernelGGL(k_dft_x_inv, grid, dim3(NNT), (size_t)2 * M * M * sizeof(float2), st, G, ex,
+                     n, M, weighted ? 1 : 0, S);
+}
+
+void nn_mix_fwd(hipStream_t st, const float2* H, const float* Rre, const float* Rim, int B, int W,
+                int NM, float2* G) {
+  long long tot = (long long)B * W * NM;
+  hipLaunchKernelGGL(k_mix_fwd, dim3((unsigned)((tot + NNT - 1) / NNT)), dim3(NNT), 0, st, H, Rre,
+                     Rim, B, W, NM, G);
+}
+
+void nn_mix_bwd(hipStream_t st, const float2* H, const float2* dG, const float* Rre,
+                const float* Rim, int B, int W, int NM, float2* dH, float* dRre, float* dRim) {
+  long long tot = (long long)B * W * NM;
+  hipLaunchKernelGGL(k_mix_bwd_h, dim3((unsigned)((tot + NNT - 1) / NNT)), dim3(NNT), 0, st, dG,
+                     Rre, Rim, B, W, NM, dH);
+  long long tr = (long long)W * W * NM;
+  hipLaunchKernelGGL(k_mix_bwd_r, dim3((unsigned)((tr + NNT - 1) / NNT)), dim3(NNT), 0, st, H, dG,
+                     B, W, NM, dRre, dRim);
+}
+
+#define NN_PW_CASES(X) X(3, 16) X(16, 16) X(16, 2) X(3, 4) X(4, 4) X(4, 2) X(3, 8) X(8, 8) X(8, 2) \
+  X(3, 32) X(32, 32) X(32, 2)
+
+bool nn_width_supported(int cin, int w) {
+#define NN_CASE(a, b) if (cin == a && w == b) return true;
+  NN_PW_CASES(NN_CASE)
+#undef NN_CASE
+  return false;
+}
+
+void nn_pw_fwd(hipStream_t st, int ci, int co, bool act, const float* in, const float* Wm,
+               const float* bias, const float* add, long long npix, int B, float* pre, float* out) {
+  const unsigned grid = (unsigned)((npix * B + NNT - 1) / NNT);
+#define NN_CASE(a, b)                                                                            \
+  if (ci == a && co == b) {                                                                      \
+    if (act)                                                                                     \
+      hipLaunchKernelGGL((k_pw_fwd<a, b, true>), dim3(grid), dim3(NNT), 0, st, in, Wm, bias, add, \
+                         npix, B, pre, out);                                                     \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_pw_fwd<a, b, false>), dim3(grid), dim3(NNT), 0, st, in, Wm, bias,    \
+                         add, npix, B, pre, out);                                                \
+    return;                                                                                      \
+  }
+  NN_PW_CASES(NN_CASE)
+#undef NN_CASE
+  throw Error(STF_EINVAL, "unsupported channel counts of a pointwise layer");
+}
+
+int nn_pw_bwd_blocks() { return 512; }
+
+void nn_pw_bwd(hipStream_t st, int ci, int co, bool act, const float* dout, const float* pre,
+               const float* in, const float* Wm, long long npix, int B, float* dpre, float* din,
+               float* partial, float* grad_w) {
+  const int nblk = nn_pw_bwd_blocks();
+#define NN_CASE(a, b)                                                                            \
+  if (ci == a && co == b) {                                                                      \
+    if (act)                                                                                     \
+      hipLaunchKernelGGL((k_pw_bwd<a, b, true>), dim3(nblk), dim3(NNT), 0, st, dout, pre, in, Wm, \
+                         npix, B, dpre, din, partial);                                           \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_pw_bwd<a, b, false>), dim3(nblk), dim3(NNT), 0, st, dout, pre, in,   \
+                         Wm, npix, B, dpre, din, partial);                                       \
+    const int cnt = a * b + b;                                                                   \
+    hipLaunchKernelGGL(k_sum_partials, dim3((cnt + NNT - 1) / NNT), dim3(NNT), 0, st, partial,   \
+                       nblk, cnt, cnt, grad_w);                                                  \
+    return;                                                                                      \
+  }
+  NN_PW_CASES(NN_CASE)
+#undef NN_CASE
+  throw Error(STF_EINVAL, "unsupported channel counts of a pointwise layer");
+}
+
+int nn_loss_blocks() { return 64; }
+
+void nn_loss(hipStream_t st, const float* y, const float* t, long long per, int B, double* partial,
+             double* den, double* loss, float* dy) {
+  const int nblk = nn_loss_blocks();
+  hipLaunchKernelGGL(k_loss_partial, dim3(nblk, B), dim3(NNT), 0, st, y, t, per, nblk, partial);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, partial, B, nblk, den, loss);
+  if (dy)
+    hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)((per * B + NNT - 1) / NNT)), dim3(NNT), 0, st, y,
+                       t, den, per, B, dy);
+}
+
+void nn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, long long n, double lr,
+             int step, double beta1, double beta2, double eps) {
+  const float bc1 = (float)(1.0 - std::pow(beta1, step));
+  const float bc2 = (float)(1.0 - std::pow(beta2, step));
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, g, m, v, n,
+                     (float)lr, (float)beta1, (float)beta2, bc1, bc2, (float)eps);
+}
+
+void nn_features(hipStream_t st, const double2* keps, const double2* b, double k0sq, int nx,
+                 int pml_x, int pml_y, const int2* org, int ntiles, int n, float* f) {
+  dim3 grid((unsigned)(((long long)n * n + NNT - 1) / NNT), ntiles);
+  hipLaunchKernelGGL(k_nn_features, grid, dim3(NNT), 0, st, keps, b, k0sq, nx, pml_x, pml_y, org, n,
+                     f);
+}
+
+void nn_fields(hipStream_t st, const double2* x, int nx, int pml_x, int pml_y, const int2* org,
+               int ntiles, int n, float* t) {
+  dim3 grid((unsigned)(((long long)n * n + NNT - 1) / NNT), ntiles);
+  hipLaunchKernelGGL(k_nn_fields, grid, dim3(NNT), 0, st, x, nx, pml_x, pml_y, org, n, t);
+}
+
+void nn_blend(hipStream_t st, const float* pred, const int* oy, int nty, const int* ox, int ntx,
+              int n, int pml_x, int pml_y, int inx, int iny, int nx, int ny, double2* x0) {
+  const long long N = (long long)nx * ny;
+  hipLaunchKernelGGL(k_nn_blend, dim3((unsigned)((N + NNT - 1) / NNT)), dim3(NNT), 0, st, pred, oy,
+                     nty, ox, ntx, n, pml_x, pml_y, inx, iny, nx, ny, x0);
+}
+
+}  // namespace stf

@@ -146,7 +146,8 @@ struct FrontDev {
 enum KClass {
   K_ASSEMBLE = STF_K_ASSEMBLE, K_STENCIL = STF_K_STENCIL, K_FRONT_ASM = STF_K_FRONT_ASM,
   K_FRONT_LU = STF_K_FRONT_LU, K_SWEEP_FWD = STF_K_SWEEP_FWD, K_SWEEP_BWD = STF_K_SWEEP_BWD,
-  K_SCATTER = STF_K_SCATTER, K_ARNOLDI = STF_K_ARNOLDI, K_UPDATE = STF_K_UPDATE
+  K_SCATTER = STF_K_SCATTER, K_ARNOLDI = STF_K_ARNOLDI, K_UPDATE = STF_K_UPDATE,
+  K_NN = STF_K_NN
 };
 
 // ---------------------------------------------------------------------------
@@ -228,5 +229,40 @@ void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n);
 // x += Z y
 void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
                     double2* x, long long n);
+
+// ---------------------------------------------------------------------------
+// Learned warm start (kernels_nn.hip).  FP32 tensors, all on `st`.
+// ---------------------------------------------------------------------------
+// C[b] = alpha A[b] B[b] + beta C[b] with element strides (A: b, m, k; B: b, k, n; C: b, m, n).
+void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, long long sAb,
+             long long sAm, long long sAk, const float* B, long long sBb, long long sBk,
+             long long sBn, float* C, long long sCb, long long sCm, long long sCn, float alpha,
+             float beta);
+void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int n, int M,
+              bool grad_scale, float2* H);
+void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
+                  bool weighted, float* S);
+void nn_mix_fwd(hipStream_t st, const float2* H, const float* Rre, const float* Rim, int B, int W,
+                int NM, float2* G);
+void nn_mix_bwd(hipStream_t st, const float2* H, const float2* dG, const float* Rre,
+                const float* Rim, int B, int W, int NM, float2* dH, float* dRre, float* dRim);
+bool nn_width_supported(int cin, int w);
+void nn_pw_fwd(hipStream_t st, int ci, int co, bool act, const float* in, const float* Wm,
+               const float* bias, const float* add, long long npix, int B, float* pre, float* out);
+int nn_pw_bwd_blocks();
+void nn_pw_bwd(hipStream_t st, int ci, int co, bool act, const float* dout, const float* pre,
+               const float* in, const float* Wm, long long npix, int B, float* dpre, float* din,
+               float* partial, float* grad_w);
+int nn_loss_blocks();
+void nn_loss(hipStream_t st, const float* y, const float* t, long long per, int B, double* partial,
+             double* den, double* loss, float* dy);
+void nn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, long long n, double lr,
+             int step, double beta1, double beta2, double eps);
+void nn_features(hipStream_t st, const double2* keps, const double2* b, double k0sq, int nx,
+                 int pml_x, int pml_y, const int2* org, int ntiles, int n, float* f);
+void nn_fields(hipStream_t st, const double2* x, int nx, int pml_x, int pml_y, const int2* org,
+               int ntiles, int n, float* t);
+void nn_blend(hipStream_t st, const float* pred, const int* oy, int nty, const int* ox, int ntx,
+              int n, int pml_x, int pml_y, int inx, int iny, int nx, int ny, double2* x0);
 
 }  // namespace stf

@@ -121,3 +121,13 @@ def test_invalid_parameters_rejected(stf, bad):
     with pytest.raises(stf.StfError) as e:
         stf.plan_query(prm)
     assert e.value.status == 1
+
+
+def test_network_parameter_count_matches_reference(stf):
+    """Host-only: the library's flat parameter layout has the reference's size."""
+    from oracle import nn
+    for c in [nn.NNConfig(), nn.NNConfig(n=32, width=8, modes=4, layers=3),
+              nn.NNConfig(n=64, width=32, modes=8, layers=2)]:
+        assert stf.nn_param_count(c.n, c.width, c.modes, c.layers, c.cin) == c.nparams()
+    assert stf.nn_param_count(16, 16, 9, 4) == -1          # 2M > n
+    assert stf.nn_param_count(256, 12, 16, 4) == -1        # unsupported width

@@ -121,4 +121,10 @@ def test_blend_is_a_partition_of_unity():
 def test_training_tile_shape():
     w = learned.tile_workload(50000, subcells=4)
     assert w.nx == w.ny == 296 and w.b.shape == (1, 296, 296)
-    assert w.b[0, 20 + 32].real.min() == 1.0 and np.count_nonzero(w.b) == 296
+    r = w.meta["source_row"]
+    assert 4 <= r <= w.meta["substrate_rows"] - 4
+    assert w.b[0, 20 + r].real.min() == 1.0 and np.count_nonzero(w.b) == 296
+    # the sheet sits in the substrate (eps 2.13) and is reproducible from the seed
+    assert abs(w.eps_cells[20 + r, 150].real - 2.13) < 1e-12
+    w2 = learned.tile_workload(50000, subcells=4)
+    assert np.array_equal(w.eps_cells, w2.eps_cells) and np.array_equal(w.b, w2.b)

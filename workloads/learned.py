@@ -33,18 +33,28 @@ def init_params(width, modes, layers, cin, seed):
     return np.concatenate(parts).astype(np.float64)
 
 
-def tile_workload(seed, interior=256, pml=20, lam=30.0, n_pillars=16, slot=16, substrate_rows=64,
-                  source_row=32, parts=2, overlap=8, local_pml=16, subcells=8):
+def tile_workload(seed, interior=256, pml=20, lam=30.0, n_pillars=16, slot=16, substrate_rows=None,
+                  source_row=None, parts=2, overlap=8, local_pml=16, subcells=8):
     """One training tile: a 256 x 256 random metasurface generated as the
     1024 x 1024 one (16 pillars on a substrate, current sheet inside it),
-    with its own 20-cell PML, split 2 x 2."""
+    with its own 20-cell PML, split 2 x 2.  Unless given, the substrate height
+    is drawn uniformly in [32, 248] rows and the sheet row uniformly in
+    [4, height - 4], so that the tiles of a larger grid that hold the sheet
+    (with or without the pillars in view) are in the training distribution."""
     n = interior + 2 * pml
     k0 = 2 * math.pi / lam
+    rng = np.random.default_rng([seed, 7919])
+    if substrate_rows is None:
+        substrate_rows = int(rng.integers(32, min(248, interior - 8) + 1))
+    if source_row is None:
+        source_row = int(rng.integers(4, substrate_rows - 4 + 1))
     cells = geometry.metasurface(n, n, pml, lam, n_pillars, slot, substrate_rows, 12.25, 2.13, seed,
                                  subcells=subcells)
     b = sources.current_sheet(n, n, pml + source_row)[None]
     return configs.Workload("tile_%d" % seed, n, n, k0, (pml,) * 4, 3, 1e-8, parts, parts, overlap,
-                            local_pml, 3, 1e-8, cells, b, meta=dict(seed=seed, lam=lam))
+                            local_pml, 3, 1e-8, cells, b,
+                            meta=dict(seed=seed, lam=lam, substrate_rows=substrate_rows,
+                                      source_row=source_row))
 
 
 def tile_origins(interior, tile=256, stride=128):
