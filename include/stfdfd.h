@@ -184,6 +184,11 @@ stf_status  stf_apply(stf_problem pb, const double* x, double* y, int on_device)
  * restriction to each subdomain's own box, local multifrontal solve
  * (Eq. (23)), and the sum of the full local fields.  v, z: ny*nx complex. */
 stf_status  stf_precond_apply(stf_problem pb, const double* v, double* z, int on_device);
+/* The same round for nrhs vectors (v, z: nrhs*ny*nx complex), swept up to four
+ * at a time with one read of the factors; each result equals that of
+ * stf_precond_apply on its own vector. */
+stf_status  stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v, double* z,
+                                    int on_device);
 stf_status  stf_problem_info(stf_problem pb, stf_plan_info* out);
 void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
 

@@ -245,14 +245,20 @@ class Problem:
         return y if dev else ky.reshape(self.ny, self.nx)
 
     def precond(self, v, z=None):
+        """One source-transfer round; v shaped (ny, nx) or (nrhs, ny, nx) (swept together)."""
+        shape = tuple(v.shape)
+        nrhs = 1 if len(shape) == 2 else int(shape[0])
         n = self.ndof
-        pv, dev, kv = _ptr(v, n, "v")
-        z = self._out_like(v, (self.ny, self.nx)) if z is None else z
-        pz, dev2, kz = _ptr(z, n, "z")
+        pv, dev, kv = _ptr(v, nrhs * n, "v")
+        z = self._out_like(v, shape) if z is None else z
+        pz, dev2, kz = _ptr(z, nrhs * n, "z")
         if dev != dev2:
             raise TypeError("v and z must both be host or both be device arrays")
-        _check(self.ctx.handle, self._lib.stf_precond_apply(self.handle, pv, pz, dev))
-        return z if dev else kz.reshape(self.ny, self.nx)
+        if len(shape) == 2:
+            _check(self.ctx.handle, self._lib.stf_precond_apply(self.handle, pv, pz, dev))
+        else:
+            _check(self.ctx.handle, self._lib.stf_precond_apply_batch(self.handle, nrhs, pv, pz, dev))
+        return z if dev else kz.reshape(shape)
 
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
               raise_on_noconv=False, rounds=1):

@@ -69,6 +69,7 @@ EXPORTS = {
                             C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "stf_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "stf_precond_apply_batch": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_problem_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
     "stf_problem_destroy": (None, [C.c_void_p]),
     "stf_nn_param_count": (C.c_int64, [C.POINTER(NNConfig)]),

@@ -61,7 +61,7 @@ struct stf_ctx_s {
   std::vector<hipEvent_t> pool;
   double total_ms[STF_K_COUNT] = {};
   int64_t launches[STF_K_COUNT] = {};
-  double* pinned = nullptr;     // small pinned host staging area
+  double* pinned = nullptr;     // pinned host staging: 64 doubles per right-hand side
   hipEvent_t iter_ev[2] = {nullptr, nullptr};   // per-iteration estimate copies
   stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
 
@@ -153,7 +153,7 @@ struct stf_problem_s {
   DBuf partial, npartial, scal;    // reduction scratch, device scalars
   DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
   DBuf hb, hx, cells;              // staging for host inputs
-  int krylov_m = 0;
+  int krylov_m = 0, krylov_nr = 0, ws_nr = 1;
 
   const double2* cxw() const { return gcoef.as<double2>(); }
   const double2* cxe() const { return gcoef.as<double2>() + prm.nx; }
@@ -461,30 +461,47 @@ int factor_t(stf_problem pb) {
   return h;
 }
 
-// z = sum_k P_k A_k^{-1} R_k^I v  (one source-transfer round).
+// z_s = sum_k P_k A_k^{-1} R_k^I v_s  (one source-transfer round) for the
+// right-hand sides of r, swept together.
 template <typename T>
-void precond_t(stf_problem pb, const double2* v, double2* z) {
+void precond_t(stf_problem pb, RhsSet r) {
   hipStream_t st = pb->ctx->stream;
+  if (pb->ws_nr < r.nr) {
+    const size_t es = sizeof(T);
+    pb->vec.alloc((size_t)pb->vec_elems * es * r.nr);
+    pb->u.alloc((size_t)pb->u_elems * es * r.nr);
+    pb->ws_nr = r.nr;
+  }
+  r.vec_stride = pb->vec_elems;
+  r.u_stride = pb->u_elems;
   const T* fac = pb->fac.as<T>();
   T* vec = pb->vec.as<T>();
   for (int d = pb->max_depth; d >= 0; --d) {
     Timed t(pb->ctx, K_SWEEP_FWD);
-    launch_sweep_fwd<T>(st, pb->level_args(d), fac, pb->piv.as<int>(), vec, v);
+    launch_sweep_fwd<T>(st, pb->level_args(d), fac, pb->piv.as<int>(), vec, r);
   }
   for (int d = 0; d <= pb->max_depth; ++d) {
     Timed t(pb->ctx, K_SWEEP_BWD);
-    launch_sweep_bwd<T>(st, pb->level_args(d), pb->upk.as<T>(), vec, pb->u.as<T>());
+    launch_sweep_bwd<T>(st, pb->level_args(d), pb->upk.as<T>(), vec, pb->u.as<T>(), r);
   }
   Timed t(pb->ctx, K_SCATTER);
   launch_scatter<T>(st, pb->u.as<T>(), pb->subs.as<SubDev>(), pb->cover_x.as<int4>(),
-                    pb->cover_y.as<int4>(), pb->prm.px, pb->prm.nx, pb->prm.ny, z);
+                    pb->cover_y.as<int4>(), pb->prm.px, pb->prm.nx, pb->prm.ny, r);
+}
+
+void precond_set(stf_problem pb, const RhsSet& r) {
+  if (pb->prec == STF_C64)
+    precond_t<float2>(pb, r);
+  else
+    precond_t<double2>(pb, r);
 }
 
 void precond(stf_problem pb, const double2* v, double2* z) {
-  if (pb->prec == STF_C64)
-    precond_t<float2>(pb, v, z);
-  else
-    precond_t<double2>(pb, v, z);
+  RhsSet r;
+  r.nr = 1;
+  r.v[0] = v;
+  r.z[0] = z;
+  precond_set(pb, r);
 }
 
 void residual(stf_problem pb, const double2* x, const double2* b, double2* r, double* dst);
@@ -528,23 +545,29 @@ void norm2(stf_problem pb, const double2* v, double2* dst) {
   launch_mdot_reduce(st, pb->partial.as<double2>(), krylov_blocks(pb->N), 1, dst, nullptr);
 }
 
-void ensure_krylov(stf_problem pb, int m) {
-  if (pb->krylov_m >= m) return;
+// Krylov storage for nr right-hand sides of cycle length m: per RHS V (m+1
+// vectors), Z (m), r, H ((m+1) x m), Givens and least-squares vectors.
+void ensure_krylov(stf_problem pb, int m, int nr) {
+  if (pb->krylov_m >= m && pb->krylov_nr >= nr) return;
+  m = std::max(m, pb->krylov_m);
+  nr = std::max(nr, pb->krylov_nr);
   size_t vb = (size_t)pb->N * sizeof(double2);
-  pb->kV.alloc(vb * (m + 1));
-  pb->kZ.alloc(vb * m);
+  pb->kV.alloc(vb * (m + 1) * nr);
+  pb->kZ.alloc(vb * m * nr);
   pb->kw.alloc(vb);
-  pb->kr.alloc(vb);
-  pb->kH.alloc(sizeof(double2) * (m + 1) * m);
-  pb->kcs.alloc(sizeof(double) * m);
-  pb->ksn.alloc(sizeof(double2) * m);
-  pb->kg.alloc(sizeof(double2) * (m + 1));
-  pb->ky.alloc(sizeof(double2) * (m + 1));
+  pb->kr.alloc(vb * nr);
+  pb->kH.alloc(sizeof(double2) * (m + 1) * m * nr);
+  pb->kcs.alloc(sizeof(double) * m * nr);
+  pb->ksn.alloc(sizeof(double2) * m * nr);
+  pb->kg.alloc(sizeof(double2) * (m + 1) * nr);
+  pb->ky.alloc(sizeof(double2) * (m + 1) * nr);
   pb->kh1.alloc(sizeof(double2) * (m + 1));
   pb->kh2.alloc(sizeof(double2) * (m + 1));
+  pb->scal.alloc(sizeof(double) * 16 * (nr + 1));
   int nblk = krylov_blocks(pb->N);
   pb->partial.alloc(std::max<size_t>(pb->partial.bytes, (size_t)nblk * (m + 1) * sizeof(double2)));
   pb->krylov_m = m;
+  pb->krylov_nr = nr;
 }
 
 // ---------------------------------------------------------------------------
@@ -789,100 +812,130 @@ void nn_initial_guess(stf_problem pb, stf_nn nn, const double2* b, double2* x0) 
            p.pml[2], inx, iny, p.nx, p.ny, x0);
 }
 
-// Scalars on device: [0] |b|^2 (double2 slot 0..1), [2] |r|^2, [3] |w|^2, [4] est.
-stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_solve_opts& o,
-                      stf_solve_info* info) {
+// Per right-hand side state of the lockstep FGMRES.  Device scalars sc:
+// [0] |b|^2, [2] |r|^2, [3] |w|^2, [4] residual estimate; pinned host hp:
+// [0..3] copies of sc, [8..9] g_0 staging, [16..19] estimates of the last two
+// iterations.
+struct RhsRun {
+  const double2* b = nullptr;
+  double2* x = nullptr;
+  double2 *V = nullptr, *Z = nullptr, *r = nullptr, *H = nullptr, *g = nullptr, *y = nullptr,
+          *sn = nullptr;
+  double *cs = nullptr, *sc = nullptr, *hp = nullptr;
+  stf_solve_info* info = nullptr;
+  double bnorm = 0.0, rnorm = 0.0, relres_guess = 0.0;
+  int used_learned = 0, it = 0, restarts = 0, hlen = 0, k = 0, launched = 0;
+  bool done = false, stop = false;
+  stf_status status = STF_ENOCONV;
+  void hist(double v) {
+    if (info && info->history && hlen < info->history_cap) info->history[hlen] = v;
+    ++hlen;
+  }
+};
+
+// Right-preconditioned FGMRES(m) for nr <= MAX_RHS right-hand sides in
+// lockstep: every iteration applies one source-transfer round to all active
+// right-hand sides together (the factors are read once), then runs the
+// stencil, the Arnoldi step and the Givens update of each.  Each right-hand
+// side keeps its own Krylov basis and stops on its own residual; the
+// arithmetic of each equals that of a solo solve.
+stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2* const* x,
+                        const stf_solve_opts& o, stf_solve_info* info) {
   stf_ctx c = pb->ctx;
   hipStream_t st = c->stream;
   const long long N = pb->N;
   const int m = o.restart;
   const int rounds = o.rounds < 1 ? 1 : o.rounds;
-  ensure_krylov(pb, m);
+  ensure_krylov(pb, m, nr);
   if (rounds > 1) {
     pb->kt.alloc((size_t)N * sizeof(double2));
     pb->kt2.alloc((size_t)N * sizeof(double2));
   }
-  double* sc = pb->scal.as<double>();
-  double2* V = pb->kV.as<double2>();
-  double2* Z = pb->kZ.as<double2>();
   double2* w = pb->kw.as<double2>();
-  double2* r = pb->kr.as<double2>();
-  double2* H = pb->kH.as<double2>();
-  double* hp = c->pinned;
   const int nblk = krylov_blocks(N);
-
-  if (o.x0_mode == STF_X0_ZERO) HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
-  if (o.x0_mode == STF_X0_LEARNED) {
-    STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
-    nn_initial_guess(pb, c->nn, b, x);
+  std::vector<RhsRun> R(nr);
+  for (int s = 0; s < nr; ++s) {
+    RhsRun& q = R[s];
+    q.b = b[s];
+    q.x = x[s];
+    q.V = pb->kV.as<double2>() + (long long)s * (m + 1) * N;
+    q.Z = pb->kZ.as<double2>() + (long long)s * m * N;
+    q.r = pb->kr.as<double2>() + (long long)s * N;
+    q.H = pb->kH.as<double2>() + (long long)s * (m + 1) * m;
+    q.g = pb->kg.as<double2>() + (long long)s * (m + 1);
+    q.y = pb->ky.as<double2>() + (long long)s * (m + 1);
+    q.sn = pb->ksn.as<double2>() + (long long)s * m;
+    q.cs = pb->kcs.as<double>() + (long long)s * m;
+    q.sc = pb->scal.as<double>() + 16 * (s + 1);
+    q.hp = c->pinned + 64 * s;
+    q.info = info ? info + s : nullptr;
   }
-  norm2(pb, b, reinterpret_cast<double2*>(sc));          // sc[0] = |b|^2
-  residual(pb, x, b, r, sc + 2);                         // sc[2] = |r|^2
-  HIP_CHECK(hipMemcpyAsync(hp, sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  // Initial guesses and residuals.
+  for (auto& q : R) {
+    if (o.x0_mode == STF_X0_ZERO) HIP_CHECK(hipMemsetAsync(q.x, 0, N * sizeof(double2), st));
+    if (o.x0_mode == STF_X0_LEARNED) {
+      STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+      nn_initial_guess(pb, c->nn, q.b, q.x);
+    }
+    norm2(pb, q.b, reinterpret_cast<double2*>(q.sc));     // sc[0] = |b|^2
+    residual(pb, q.x, q.b, q.r, q.sc + 2);                // sc[2] = |r|^2
+    HIP_CHECK(hipMemcpyAsync(q.hp, q.sc, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   HIP_CHECK(hipStreamSynchronize(st));
-  const double bnorm = std::sqrt(hp[0]);
-  double rnorm = std::sqrt(hp[2]);
-  double relres_guess = bnorm > 0.0 ? rnorm / bnorm : 0.0;
-  int used_learned = 0;
-  if (o.x0_mode == STF_X0_LEARNED) {
-    // Fallback: the zero guess whenever the network's residual is not below |b|.
-    if (!(rnorm < bnorm)) {
-      HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
-      residual(pb, x, b, r, sc + 2);
-      HIP_CHECK(hipMemcpyAsync(hp + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipStreamSynchronize(st));
-      rnorm = std::sqrt(hp[2]);
-    } else {
-      used_learned = 1;
+  bool refresh = false;
+  for (auto& q : R) {
+    q.bnorm = std::sqrt(q.hp[0]);
+    q.rnorm = std::sqrt(q.hp[2]);
+    q.relres_guess = q.bnorm > 0.0 ? q.rnorm / q.bnorm : 0.0;
+    if (o.x0_mode == STF_X0_LEARNED) {
+      // Fallback: the zero guess whenever the network's residual is not below |b|.
+      if (!(q.rnorm < q.bnorm)) {
+        HIP_CHECK(hipMemsetAsync(q.x, 0, N * sizeof(double2), st));
+        residual(pb, q.x, q.b, q.r, q.sc + 2);
+        HIP_CHECK(hipMemcpyAsync(q.hp + 2, q.sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        refresh = true;
+      } else {
+        q.used_learned = 1;
+      }
     }
   }
-  int hlen = 0;
-  auto hist = [&](double v) {
-    if (info && info->history && hlen < info->history_cap) info->history[hlen] = v;
-    ++hlen;
-  };
-  stf_solve_info loc{};
-  loc.history_len = 0;
-  if (bnorm == 0.0) {
-    HIP_CHECK(hipMemsetAsync(x, 0, N * sizeof(double2), st));
+  if (refresh) {
     HIP_CHECK(hipStreamSynchronize(st));
-    loc.relres_true = 0.0;
-    loc.relres_x0 = 0.0;
-    if (info) {
-      loc.history = info->history;
-      loc.history_cap = info->history_cap;
-      *info = loc;
-    }
-    return STF_OK;
+    for (auto& q : R) q.rnorm = std::sqrt(q.hp[2]);
   }
-  if (!std::isfinite(rnorm)) throw Error(STF_ENAN, "non-finite initial residual");
-  loc.relres_x0 = o.x0_mode == STF_X0_LEARNED ? relres_guess : rnorm / bnorm;
-  loc.used_learned = used_learned;
-  hist(rnorm / bnorm);
-  int it = 0, restarts = 0;
-  stf_status status = STF_ENOCONV;
-  while (true) {
-    if (rnorm <= o.tol * bnorm) { status = STF_OK; break; }
-    if (it >= o.max_iter) { status = STF_ENOCONV; break; }
-    {
-      Timed t(c, K_UPDATE);
-      launch_scale(st, r, sc + 2, V, N);                    // v_0 = r / |r|
+  for (auto& q : R) {
+    if (q.bnorm == 0.0) {
+      HIP_CHECK(hipMemsetAsync(q.x, 0, N * sizeof(double2), st));
+      q.done = true;
+      q.status = STF_OK;
+      q.rnorm = 0.0;
+      q.relres_guess = 0.0;
+      continue;
     }
-    HIP_CHECK(hipMemsetAsync(pb->kg.p, 0, sizeof(double2) * (m + 1), st));
-    hp[8] = rnorm;
-    hp[9] = 0.0;
-    HIP_CHECK(hipMemcpyAsync(pb->kg.p, hp + 8, sizeof(double2), hipMemcpyHostToDevice, st));
-    // Iteration j+1 is enqueued before the host waits for iteration j's
-    // residual estimate (copied to pinned memory behind an event), so the GPU
-    // queue does not drain between iterations.
-    auto launch_iter = [&](int j) {
-      double2* vj = V + (long long)j * N;
-      double2* zj = Z + (long long)j * N;
-      precond_rounds(pb, vj, zj, rounds);
-      apply_A(pb, zj, w);
-      // Classical Gram-Schmidt with selective re-orthogonalisation:
-      // h1 = V^H w with |w|^2, w -= V h1 with the new |w|^2; a second pass
-      // (gated on the device) when more than half of |w|^2 cancelled.
+    if (!std::isfinite(q.rnorm)) throw Error(STF_ENAN, "non-finite initial residual");
+    if (o.x0_mode != STF_X0_LEARNED) q.relres_guess = q.rnorm / q.bnorm;
+    q.hist(q.rnorm / q.bnorm);
+  }
+
+  auto launch_iter = [&](int j, const std::vector<int>& cur) {
+    if (rounds == 1) {
+      RhsSet rs;
+      rs.nr = (int)cur.size();
+      for (int i = 0; i < rs.nr; ++i) {
+        rs.v[i] = R[cur[i]].V + (long long)j * N;
+        rs.z[i] = R[cur[i]].Z + (long long)j * N;
+      }
+      precond_set(pb, rs);
+    } else {
+      for (int s : cur)
+        precond_rounds(pb, R[s].V + (long long)j * N, R[s].Z + (long long)j * N, rounds);
+    }
+    for (int s : cur) {
+      RhsRun& q = R[s];
+      apply_A(pb, q.Z + (long long)j * N, w);
+      // Classical Gram-Schmidt with re-orthogonalisation: h1 = V^H w with
+      // |w|^2, w -= V h1 with the new |w|^2; a second pass (gated on the
+      // device) when more than half of |w|^2 cancelled.
       {
         Timed t(c, K_ARNOLDI);
         double2* part = pb->partial.as<double2>();
@@ -890,78 +943,143 @@ stf_status fgmres_one(stf_problem pb, const double2* b, double2* x, const stf_so
         int* gate = pb->flag.as<int>() + 1;
         double2* h1 = pb->kh1.as<double2>();
         double2* h2 = pb->kh2.as<double2>();
-        launch_mdot(st, V, N, j + 1, w, N, part, npart, nullptr);
+        launch_mdot(st, q.V, N, j + 1, w, N, part, npart, nullptr);
         launch_mdot_reduce(st, part, nblk, j + 1, h1, nullptr);
-        launch_norm_reduce(st, npart, nblk, sc + 6, nullptr, nullptr, 0);
-        launch_mupdate(st, V, N, j + 1, h1, w, N, npart, nullptr);
-        launch_norm_reduce(st, npart, nblk, sc + 3, sc + 6, gate, 1);
-        launch_mdot(st, V, N, j + 1, w, N, part, nullptr, gate);
+        launch_norm_reduce(st, npart, nblk, q.sc + 6, nullptr, nullptr, 0);
+        launch_mupdate(st, q.V, N, j + 1, h1, w, N, npart, nullptr);
+        launch_norm_reduce(st, npart, nblk, q.sc + 3, q.sc + 6, gate, 1);
+        launch_mdot(st, q.V, N, j + 1, w, N, part, nullptr, gate);
         launch_mdot_reduce(st, part, nblk, j + 1, h2, gate);
-        launch_mupdate(st, V, N, j + 1, h2, w, N, npart, gate);
-        launch_norm_reduce(st, npart, nblk, sc + 3, nullptr, gate, 0);
+        launch_mupdate(st, q.V, N, j + 1, h2, w, N, npart, gate);
+        launch_norm_reduce(st, npart, nblk, q.sc + 3, nullptr, gate, 0);
         launch_hacc(st, h1, h2, j + 1, gate);
       }
       {
         Timed t(c, K_UPDATE);
-        launch_scale(st, w, sc + 3, V + (long long)(j + 1) * N, N);
-        launch_givens(st, H, pb->kh1.as<double2>(), sc + 3, pb->kcs.as<double>(),
-                      pb->ksn.as<double2>(), pb->kg.as<double2>(), j, m + 1, sc + 4);
+        launch_scale(st, w, q.sc + 3, q.V + (long long)(j + 1) * N, N);
+        launch_givens(st, q.H, pb->kh1.as<double2>(), q.sc + 3, q.cs, q.sn, q.g, j, m + 1, q.sc + 4);
       }
-      HIP_CHECK(hipMemcpyAsync(hp + 16 + 2 * (j & 1), sc + 3, 2 * sizeof(double),
+      HIP_CHECK(hipMemcpyAsync(q.hp + 16 + 2 * (j & 1), q.sc + 3, 2 * sizeof(double),
                                hipMemcpyDeviceToHost, st));
-      HIP_CHECK(hipEventRecord(c->iter_ev[j & 1], st));
-    };
-    // Waits for iteration j's estimate; returns true on convergence or breakdown.
-    auto check_iter = [&](int j) {
-      HIP_CHECK(hipEventSynchronize(c->iter_ev[j & 1]));
-      const double wn = hp[16 + 2 * (j & 1)], est = hp[17 + 2 * (j & 1)];
-      hist(est / bnorm);
-      if (!std::isfinite(est)) throw Error(STF_ENAN, "non-finite residual estimate");
-      return est <= o.tol * bnorm || wn == 0.0;
-    };
-    int k = 0, launched = 0;
-    bool stop = false;
-    for (int j = 0; j < m && it < o.max_iter; ++j) {
-      launch_iter(j);
-      ++it;
-      launched = j + 1;
-      if (j >= 1 && check_iter(j - 1)) {
-        // Iteration j-1 met the tolerance (or broke down): the speculative
-        // iteration j is discarded, so the iterates equal those of the
-        // synchronous algorithm.
-        k = j;
-        --it;
-        stop = true;
-        break;
+    }
+    HIP_CHECK(hipEventRecord(c->iter_ev[j & 1], st));
+  };
+  // Iteration j's estimate of right-hand side s (after its event); true on
+  // convergence or breakdown.
+  auto check = [&](RhsRun& q, int j) {
+    const double wn = q.hp[16 + 2 * (j & 1)], est = q.hp[17 + 2 * (j & 1)];
+    q.hist(est / q.bnorm);
+    if (!std::isfinite(est)) throw Error(STF_ENAN, "non-finite residual estimate");
+    return est <= o.tol * q.bnorm || wn == 0.0;
+  };
+
+  while (true) {
+    std::vector<int> active;
+    for (int s = 0; s < nr; ++s) {
+      RhsRun& q = R[s];
+      if (q.done) continue;
+      if (q.rnorm <= o.tol * q.bnorm) {
+        q.status = STF_OK;
+        q.done = true;
+      } else if (q.it >= o.max_iter) {
+        q.status = STF_ENOCONV;
+        q.done = true;
+      } else {
+        active.push_back(s);
       }
     }
-    if (!stop && launched > 0) {
-      check_iter(launched - 1);
-      k = launched;
+    if (active.empty()) break;
+    for (int s : active) {
+      RhsRun& q = R[s];
+      {
+        Timed t(c, K_UPDATE);
+        launch_scale(st, q.r, q.sc + 2, q.V, N);              // v_0 = r / |r|
+      }
+      HIP_CHECK(hipMemsetAsync(q.g, 0, sizeof(double2) * (m + 1), st));
+      q.hp[8] = q.rnorm;
+      q.hp[9] = 0.0;
+      HIP_CHECK(hipMemcpyAsync(q.g, q.hp + 8, sizeof(double2), hipMemcpyHostToDevice, st));
+      q.stop = false;
+      q.k = 0;
+      q.launched = 0;
     }
-    {
-      Timed t(c, K_UPDATE);
-      launch_trisolve(st, H, pb->kg.as<double2>(), pb->ky.as<double2>(), k, m + 1);
-      launch_xupdate(st, Z, N, k, pb->ky.as<double2>(), x, N);
+    // Iteration j+1 is enqueued before the host waits for iteration j's
+    // estimates, so the GPU queue does not drain between iterations.  A right-
+    // hand side whose iteration j met the tolerance has its speculative
+    // iteration j+1 discarded, so its iterates equal those of the synchronous
+    // algorithm.
+    std::vector<int> cur = active, prev;
+    int last = -1;
+    for (int j = 0; j < m && !cur.empty(); ++j) {
+      launch_iter(j, cur);
+      last = j;
+      for (int s : cur) {
+        ++R[s].it;
+        R[s].launched = j + 1;
+      }
+      if (!prev.empty()) {
+        HIP_CHECK(hipEventSynchronize(c->iter_ev[(j - 1) & 1]));
+        for (int s : prev) {
+          RhsRun& q = R[s];
+          if (q.stop) continue;                  // its iteration j-1 was a discarded one
+          if (check(q, j - 1)) {
+            q.stop = true;
+            q.k = j;
+            if (q.launched == j + 1) {
+              --q.it;
+              q.launched = j;
+            }
+          }
+        }
+      }
+      prev = cur;
+      std::vector<int> nxt;
+      for (int s : cur)
+        if (!R[s].stop && R[s].it < o.max_iter) nxt.push_back(s);
+      cur.swap(nxt);
     }
-    residual(pb, x, b, r, sc + 2);
-    HIP_CHECK(hipMemcpyAsync(hp + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (last >= 0) {
+      HIP_CHECK(hipEventSynchronize(c->iter_ev[last & 1]));
+      for (int s : prev)
+        if (!R[s].stop && R[s].launched == last + 1) check(R[s], last);
+    }
+    for (int s : active) {
+      RhsRun& q = R[s];
+      if (!q.stop) q.k = q.launched;
+      {
+        Timed t(c, K_UPDATE);
+        launch_trisolve(st, q.H, q.g, q.y, q.k, m + 1);
+        launch_xupdate(st, q.Z, N, q.k, q.y, q.x, N);
+      }
+      residual(pb, q.x, q.b, q.r, q.sc + 2);
+      HIP_CHECK(hipMemcpyAsync(q.hp + 2, q.sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     HIP_CHECK(hipStreamSynchronize(st));
-    rnorm = std::sqrt(hp[2]);
-    ++restarts;
-    if (!std::isfinite(rnorm)) throw Error(STF_ENAN, "non-finite true residual");
+    for (int s : active) {
+      RhsRun& q = R[s];
+      q.rnorm = std::sqrt(q.hp[2]);
+      ++q.restarts;
+      if (!std::isfinite(q.rnorm)) throw Error(STF_ENAN, "non-finite true residual");
+    }
   }
-  loc.iters = it;
-  loc.restarts = restarts;
-  loc.relres_true = rnorm / bnorm;
-  loc.status = status;
-  loc.history_len = std::min(hlen, info ? info->history_cap : 0);
-  if (info) {
-    loc.history = info->history;
-    loc.history_cap = info->history_cap;
-    *info = loc;
+  stf_status worst = STF_OK;
+  for (auto& q : R) {
+    if (q.info) {
+      stf_solve_info loc{};
+      loc.iters = q.it;
+      loc.restarts = q.restarts;
+      loc.relres_true = q.bnorm > 0.0 ? q.rnorm / q.bnorm : 0.0;
+      loc.relres_x0 = q.relres_guess;
+      loc.used_learned = q.used_learned;
+      loc.status = q.status;
+      loc.history = q.info->history;
+      loc.history_cap = q.info->history_cap;
+      loc.history_len = std::min(q.hlen, q.info->history_cap);
+      *q.info = loc;
+    }
+    if (q.status != STF_OK && worst == STF_OK) worst = q.status;
   }
-  return status;
+  return worst;
 }
 
 }  // namespace
@@ -994,7 +1112,7 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
       HIP_CHECK(hipStreamCreate(&c->stream));
       c->own_stream = true;
     }
-    HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * sizeof(double), hipHostMallocDefault));
+    HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * MAX_RHS * sizeof(double), hipHostMallocDefault));
     for (int e = 0; e < 2; ++e)
       HIP_CHECK(hipEventCreateWithFlags(&c->iter_ev[e], hipEventDisableTiming));
   });
@@ -1192,6 +1310,41 @@ stf_status stf_precond_apply(stf_problem pb, const double* v, double* z, int on_
   });
 }
 
+stf_status stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v, double* z,
+                                   int on_device) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(v && z, "null argument");
+    STF_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    if (!pb->factored) throw Error(STF_ESTATE, "precond before factor");
+    hipStream_t st = pb->ctx->stream;
+    const size_t vb = (size_t)pb->N * sizeof(double2);
+    const double2* vd = reinterpret_cast<const double2*>(v);
+    double2* zd = reinterpret_cast<double2*>(z);
+    if (!on_device) {
+      pb->hb.alloc(vb * nrhs);
+      pb->hx.alloc(vb * nrhs);
+      HIP_CHECK(hipMemcpyAsync(pb->hb.p, v, vb * nrhs, hipMemcpyHostToDevice, st));
+      vd = pb->hb.as<double2>();
+      zd = pb->hx.as<double2>();
+    }
+    for (int r0 = 0; r0 < nrhs; r0 += MAX_RHS) {
+      RhsSet rs;
+      rs.nr = std::min(MAX_RHS, nrhs - r0);
+      for (int i = 0; i < rs.nr; ++i) {
+        rs.v[i] = vd + (size_t)(r0 + i) * pb->N;
+        rs.z[i] = zd + (size_t)(r0 + i) * pb->N;
+      }
+      precond_set(pb, rs);
+    }
+    HIP_CHECK(hipGetLastError());
+    if (!on_device) {
+      HIP_CHECK(hipMemcpyAsync(z, pb->hx.p, vb * nrhs, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+  });
+}
+
 stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                      const stf_solve_opts* opts, stf_solve_info* info) {
   if (!pb) return STF_EINVAL;
@@ -1211,25 +1364,33 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
     require_finite(pb, b, per * nrhs, on_device, "b");
     if (opts->x0_mode == STF_X0_USER) require_finite(pb, x, per * nrhs, on_device, "x0");
     hipStream_t st = pb->ctx->stream;
-    size_t vb = (size_t)pb->N * sizeof(double2);
-    for (int rr = 0; rr < nrhs; ++rr) {
-      const double2* bd;
-      double2* xd;
-      if (on_device) {
-        bd = reinterpret_cast<const double2*>(b) + (size_t)rr * pb->N;
-        xd = reinterpret_cast<double2*>(x) + (size_t)rr * pb->N;
-      } else {
-        pb->hb.alloc(vb);
-        pb->hx.alloc(vb);
-        HIP_CHECK(hipMemcpyAsync(pb->hb.p, b + rr * per, vb, hipMemcpyHostToDevice, st));
-        if (opts->x0_mode == STF_X0_USER)
-          HIP_CHECK(hipMemcpyAsync(pb->hx.p, x + rr * per, vb, hipMemcpyHostToDevice, st));
-        bd = pb->hb.as<double2>();
-        xd = pb->hx.as<double2>();
-      }
-      stf_status r = fgmres_one(pb, bd, xd, *opts, info ? info + rr : nullptr);
+    const size_t vb = (size_t)pb->N * sizeof(double2);
+    // Right-hand sides go through in groups of up to MAX_RHS (one with
+    // several source-transfer rounds per application: those are not batched).
+    const int gmax = (opts->rounds > 1) ? 1 : MAX_RHS;
+    for (int r0 = 0; r0 < nrhs; r0 += gmax) {
+      const int g = std::min(gmax, nrhs - r0);
+      const double2* bd[MAX_RHS];
+      double2* xd[MAX_RHS];
       if (!on_device) {
-        HIP_CHECK(hipMemcpyAsync(x + rr * per, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
+        pb->hb.alloc(vb * g);
+        pb->hx.alloc(vb * g);
+        HIP_CHECK(hipMemcpyAsync(pb->hb.p, b + r0 * per, vb * g, hipMemcpyHostToDevice, st));
+        if (opts->x0_mode == STF_X0_USER)
+          HIP_CHECK(hipMemcpyAsync(pb->hx.p, x + r0 * per, vb * g, hipMemcpyHostToDevice, st));
+      }
+      for (int i = 0; i < g; ++i) {
+        if (on_device) {
+          bd[i] = reinterpret_cast<const double2*>(b) + (size_t)(r0 + i) * pb->N;
+          xd[i] = reinterpret_cast<double2*>(x) + (size_t)(r0 + i) * pb->N;
+        } else {
+          bd[i] = pb->hb.as<double2>() + (size_t)i * pb->N;
+          xd[i] = pb->hx.as<double2>() + (size_t)i * pb->N;
+        }
+      }
+      stf_status r = fgmres_multi(pb, g, bd, xd, *opts, info ? info + r0 : nullptr);
+      if (!on_device) {
+        HIP_CHECK(hipMemcpyAsync(x + r0 * per, pb->hx.p, vb * g, hipMemcpyDeviceToHost, st));
         HIP_CHECK(hipStreamSynchronize(st));
       }
       if (r != STF_OK && worst == STF_OK) worst = r;

@@ -605,17 +605,17 @@ struct ColPrefetch {
 // Forward sweep for levels with m <= 64 RPL and p <= 64: four fronts per
 // workgroup, one wavefront per front, no workgroup barriers.  Lane rows
 // r = lane + 64 i (i < RPL); with RPL = 1 and m <= 32, G = 64 / W lanes share a
-// row (columns k = g, g + G, ...) and a fixed butterfly adds their sums.
-template <typename T, int RPL, int KP>
+// row (columns k = g, g + G, ...) and a fixed butterfly adds their sums.  The
+// NR right-hand sides share the operator registers and the index loads.
+template <typename T, int RPL, int KP, int NR>
 __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restrict__ fac,
                                                  const int* __restrict__ piv, T* __restrict__ vec,
-                                                 const double2* __restrict__ v) {
+                                                 RhsSet rs) {
   constexpr int MW = 64 * RPL;
-  __shared__ T sh[4][MW];
+  __shared__ T sh[4][NR][MW];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;                          // whole wavefront
-  T* vl = sh[wv];
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
@@ -630,54 +630,70 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   const int pv = lane < p ? piv[f.piv_off + lane] : lane;
   // b = R^I v on the separator rows plus the children's update vectors (all
   // loaded before any is added).
-  T val = czero<T>();
+  long long gidx = -1;
   if (lane < p) {
     const SubDev s = a.subs[f.sub];
     int node = a.vars[f.var_off + lane];
     int gx = s.ox0 + node % s.nxl, gy = s.oy0 + node / s.nxl;
-    if (gx >= s.ix0 && gx < s.ix1 && gy >= s.iy0 && gy < s.iy1)
-      val = from_d2<T>(v[(long long)gy * a.nx + gx]);
+    if (gx >= s.ix0 && gx < s.ix1 && gy >= s.iy0 && gy < s.iy1) gidx = (long long)gy * a.nx + gx;
   }
   int d0[RPL], d1[RPL];
-  T c0[RPL], c1[RPL];
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int idx = lane + 64 * i;
-    d0[i] = d1[i] = -1;
-    c0[i] = c1[i] = czero<T>();
-    if (f.nchild > 0 && idx < f.cq[0]) {
-      d0[i] = a.cmap[f.ccmap[0] + idx];
-      c0[i] = vec[f.cvec[0] + idx];
-    }
-    if (f.nchild > 1 && idx < f.cq[1]) {
-      d1[i] = a.cmap[f.ccmap[1] + idx];
-      c1[i] = vec[f.cvec[1] + idx];
+    d0[i] = (f.nchild > 0 && idx < f.cq[0]) ? a.cmap[f.ccmap[0] + idx] : -1;
+    d1[i] = (f.nchild > 1 && idx < f.cq[1]) ? a.cmap[f.ccmap[1] + idx] : -1;
+  }
+  T val[NR], c0[NR][RPL], c1[NR][RPL];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const T* vs = vec + s * rs.vec_stride;
+    val[s] = gidx >= 0 ? from_d2<T>(rs.v[s][gidx]) : czero<T>();
+#pragma unroll
+    for (int i = 0; i < RPL; ++i) {
+      const int idx = lane + 64 * i;
+      c0[s][i] = d0[i] >= 0 ? vs[f.cvec[0] + idx] : czero<T>();
+      c1[s][i] = d1[i] >= 0 ? vs[f.cvec[1] + idx] : czero<T>();
     }
   }
-  vl[lane] = val;
 #pragma unroll
-  for (int i = 1; i < RPL; ++i) vl[lane + 64 * i] = czero<T>();
+  for (int s = 0; s < NR; ++s) {
+    sh[wv][s][lane] = val[s];
+#pragma unroll
+    for (int i = 1; i < RPL; ++i) sh[wv][s][lane + 64 * i] = czero<T>();
+  }
   wave_sync();
 #pragma unroll
-  for (int i = 0; i < RPL; ++i)
-    if (d0[i] >= 0) vl[d0[i]] = cadd(vl[d0[i]], c0[i]);
+  for (int s = 0; s < NR; ++s)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (d0[i] >= 0) sh[wv][s][d0[i]] = cadd(sh[wv][s][d0[i]], c0[s][i]);
   wave_sync();
 #pragma unroll
-  for (int i = 0; i < RPL; ++i)
-    if (d1[i] >= 0) vl[d1[i]] = cadd(vl[d1[i]], c1[i]);
+  for (int s = 0; s < NR; ++s)
+#pragma unroll
+    for (int i = 0; i < RPL; ++i)
+      if (d1[i] >= 0) sh[wv][s][d1[i]] = cadd(sh[wv][s][d1[i]], c1[s][i]);
   wave_sync();
   // (P b)_r = b[perm[r]] on the separator rows (p <= 64).
-  const T pb = vl[pv];
+  T pb[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) pb[s] = sh[wv][s][pv];
   wave_sync();
-  vl[lane] = pb;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) sh[wv][s][lane] = pb[s];
   wave_sync();
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int r = rl + 64 * i;
-    T acc = pf[i].dot(F + r, m, g, r < m ? min(r, p) : 0, G, vl);
-    if (RPL == 1)
-      for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-    if (g == 0 && r < m) vec[f.vec_off + r] = cadd(vl[r], acc);
+    const int kend = r < m ? min(r, p) : 0;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      T acc = pf[i].dot(F + r, m, g, kend, G, sh[wv][s]);
+      if (RPL == 1)
+        for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
+      if (g == 0 && r < m) vec[s * rs.vec_stride + f.vec_off + r] = cadd(sh[wv][s][r], acc);
+    }
   }
 }
 
@@ -685,14 +701,13 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
 // workgroup, one wavefront per front.  Row r < p is shared by G = 64 / W lanes
 // (W >= p), which take columns c = r + g, r + g + G, ... of the packed operator
 // [U11^{-1} V'] (ld p); a fixed butterfly adds their sums.
-template <typename T, int KP>
+template <typename T, int KP, int NR>
 __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restrict__ upk,
-                                                 T* __restrict__ vec, T* __restrict__ u) {
-  __shared__ T sh[4][128];
+                                                 T* __restrict__ vec, T* __restrict__ u, RhsSet rs) {
+  __shared__ T sh[4][NR][128];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;
-  T* vl = sh[wv];
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p, q = f.q;
   const T* U = upk + f.upk_off;
@@ -701,45 +716,61 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   ColPrefetch<T, KP> pf;
   pf.load(U + r, p, r + g, r < p ? m : 0, G);
   const int var = lane < p ? a.vars[f.var_off + lane] : 0;
-  // [y_p ; x_q]: y_p from the forward sweep, x_q from the parent's vector.
-  const T y = lane < p ? vec[f.vec_off + lane] : czero<T>();
-  T xq[2];
+  int ci[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
     const int idx = lane + 64 * i;
-    xq[i] = idx < q ? vec[f.pvec + a.cmap[f.cmap_off + idx]] : czero<T>();
+    ci[i] = idx < q ? a.cmap[f.cmap_off + idx] : -1;
   }
-  if (lane < p) vl[lane] = y;
+  // [y_p ; x_q]: y_p from the forward sweep, x_q from the parent's vector.
+  T y[NR], xq[NR][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-    if (lane + 64 * i < q) vl[p + lane + 64 * i] = xq[i];
+  for (int s = 0; s < NR; ++s) {
+    const T* vs = vec + s * rs.vec_stride;
+    y[s] = lane < p ? vs[f.vec_off + lane] : czero<T>();
+#pragma unroll
+    for (int i = 0; i < 2; ++i) xq[s][i] = ci[i] >= 0 ? vs[f.pvec + ci[i]] : czero<T>();
+  }
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    if (lane < p) sh[wv][s][lane] = y[s];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (lane + 64 * i < q) sh[wv][s][p + lane + 64 * i] = xq[s][i];
+  }
   wave_sync();
-  T acc = pf.dot(U + r, p, r + g, r < p ? m : 0, G, vl);
-  for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-  T* fv = vec + f.vec_off;
-  if (lane < p) {                          // lane < p <= W: g = 0, r = lane
-    fv[lane] = acc;
-    u[a.subs[f.sub].u_off + var] = acc;
-  }
+  const long long uo = a.subs[f.sub].u_off;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
-    if (lane + 64 * i < q) fv[p + lane + 64 * i] = xq[i];
+  for (int s = 0; s < NR; ++s) {
+    T acc = pf.dot(U + r, p, r + g, r < p ? m : 0, G, sh[wv][s]);
+    for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
+    T* fv = vec + s * rs.vec_stride + f.vec_off;
+    if (lane < p) {                        // lane < p <= W: g = 0, r = lane
+      fv[lane] = acc;
+      u[s * rs.u_stride + uo + var] = acc;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (lane + 64 * i < q) fv[p + lane + 64 * i] = xq[s][i];
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Sweeps, large fronts: one workgroup of NTL threads per front, the single
 // trapezoidal product with the first KP operator terms of each thread
-// prefetched into registers.  Rows are shared by G = NTL / rows threads
-// (column groups) whose partial sums are added in a fixed order through LDS.
+// prefetched into registers and shared by the NR right-hand sides.  Rows are
+// shared by G = NTL / rows threads (column groups) whose partial sums are
+// added in a fixed order through LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int NTL, int KP>
+template <typename T, int NTL, int KP, int NR>
 __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restrict__ fac,
                                                    const int* __restrict__ piv, T* __restrict__ vec,
-                                                   const double2* __restrict__ v) {
+                                                   RhsSet rs) {
   extern __shared__ unsigned char smem_raw[];
-  T* scr = reinterpret_cast<T*>(smem_raw);                 // NTL
-  T* vl = scr + NTL;                                       // max_m
-  T* tmp = vl + a.max_m;                                   // max_m
+  T* scr = reinterpret_cast<T*>(smem_raw);                 // NR x NTL
+  T* vl = scr + NR * NTL;                                  // NR x max_m
+  T* tmp = vl + NR * a.max_m;                              // NR x max_m
+  const int mm = a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
   const T* F = fac + f.fac_off;
@@ -753,58 +784,75 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   const bool act = g < G && rr < m;
   ColPrefetch<T, KP> pf;
   pf.load(F + rr, m, g, act ? min(rr, p) : 0, G);
-  const SubDev s = a.subs[f.sub];
+  const SubDev sd = a.subs[f.sub];
   for (int i = tid; i < m; i += NTL) {
-    T val = czero<T>();
+    long long gidx = -1;
     if (i < p) {
       int node = a.vars[f.var_off + i];
-      int gx = s.ox0 + node % s.nxl, gy = s.oy0 + node / s.nxl;
-      if (gx >= s.ix0 && gx < s.ix1 && gy >= s.iy0 && gy < s.iy1)
-        val = from_d2<T>(v[(long long)gy * a.nx + gx]);
+      int gx = sd.ox0 + node % sd.nxl, gy = sd.oy0 + node / sd.nxl;
+      if (gx >= sd.ix0 && gx < sd.ix1 && gy >= sd.iy0 && gy < sd.iy1) gidx = (long long)gy * a.nx + gx;
     }
-    vl[i] = val;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) vl[s * mm + i] = gidx >= 0 ? from_d2<T>(rs.v[s][gidx]) : czero<T>();
   }
   __syncthreads();
-  if (f.nchild > 0) {
-    const int* cm = a.cmap + f.ccmap[0];
-    const T* cv = vec + f.cvec[0];
-    for (int i = tid; i < f.cq[0]; i += NTL) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
-    __syncthreads();
-  }
-  if (f.nchild > 1) {
-    const int* cm = a.cmap + f.ccmap[1];
-    const T* cv = vec + f.cvec[1];
-    for (int i = tid; i < f.cq[1]; i += NTL) vl[cm[i]] = cadd(vl[cm[i]], cv[i]);
-    __syncthreads();
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    if (f.nchild > c) {
+      const int* cm = a.cmap + f.ccmap[c];
+      for (int i = tid; i < f.cq[c]; i += NTL) {
+        const int d = cm[i];
+#pragma unroll
+        for (int s = 0; s < NR; ++s)
+          vl[s * mm + d] = cadd(vl[s * mm + d], vec[s * rs.vec_stride + f.cvec[c] + i]);
+      }
+      __syncthreads();
+    }
   }
   const int* perm = piv + f.piv_off;
-  for (int i = tid; i < p; i += NTL) tmp[i] = vl[perm[i]];
+  for (int i = tid; i < p; i += NTL) {
+    const int src = perm[i];
+#pragma unroll
+    for (int s = 0; s < NR; ++s) tmp[s * mm + i] = vl[s * mm + src];
+  }
   __syncthreads();
-  for (int i = tid; i < p; i += NTL) vl[i] = tmp[i];
+  for (int i = tid; i < p; i += NTL)
+#pragma unroll
+    for (int s = 0; s < NR; ++s) vl[s * mm + i] = tmp[s * mm + i];
   __syncthreads();
-  T* out = vec + f.vec_off;
-  const T acc = act ? pf.dot(F + rr, m, g, min(rr, p), G, vl) : czero<T>();
+  T acc[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(F + rr, m, g, min(rr, p), G, vl + s * mm) : czero<T>();
   if (G == 1) {
-    if (act) out[rr] = cadd(vl[rr], acc);
-    for (int r = tid + NTL; r < m; r += NTL)
-      out[r] = cadd(vl[r], strided_dot(F + r, (long long)m, 0, min(r, p), 1, vl));
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      T* out = vec + s * rs.vec_stride + f.vec_off;
+      if (act) out[rr] = cadd(vl[s * mm + rr], acc[s]);
+      for (int r = tid + NTL; r < m; r += NTL)
+        out[r] = cadd(vl[s * mm + r], strided_dot(F + r, (long long)m, 0, min(r, p), 1, vl + s * mm));
+    }
   } else {
-    scr[tid] = acc;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) scr[s * NTL + tid] = acc[s];
     __syncthreads();
     if (tid < m) {
-      T sum = czero<T>();
-      for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * m + tid]);
-      out[tid] = cadd(vl[tid], sum);
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        T sum = czero<T>();
+        for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * m + tid]);
+        vec[s * rs.vec_stride + f.vec_off + tid] = cadd(vl[s * mm + tid], sum);
+      }
     }
   }
 }
 
-template <typename T, int NTL, int KP>
+template <typename T, int NTL, int KP, int NR>
 __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restrict__ upk,
-                                                   T* __restrict__ vec, T* __restrict__ u) {
+                                                   T* __restrict__ vec, T* __restrict__ u, RhsSet rs) {
   extern __shared__ unsigned char smem_raw[];
-  T* scr = reinterpret_cast<T*>(smem_raw);                 // NTL
-  T* vl = scr + NTL;                                       // max_m
+  T* scr = reinterpret_cast<T*>(smem_raw);                 // NR x NTL
+  T* vl = scr + NR * NTL;                                  // NR x max_m
+  const int mm = a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
   const T* U = upk + f.upk_off;                            // rows 0..p-1, leading dimension p
@@ -818,52 +866,71 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   const bool act = g < G && rr < p;
   ColPrefetch<T, KP> pf;
   pf.load(U + rr, p, rr + g, act ? m : 0, G);
-  T* fv = vec + f.vec_off;
-  for (int i = tid; i < p; i += NTL) vl[i] = fv[i];
+  for (int i = tid; i < p; i += NTL)
+#pragma unroll
+    for (int s = 0; s < NR; ++s) vl[s * mm + i] = vec[s * rs.vec_stride + f.vec_off + i];
   if (f.parent >= 0) {
     const int* cm = a.cmap + f.cmap_off;
-    const T* pv = vec + f.pvec;
-    for (int i = tid; i < f.q; i += NTL) vl[p + i] = pv[cm[i]];
+    for (int i = tid; i < f.q; i += NTL) {
+      const int c = cm[i];
+#pragma unroll
+      for (int s = 0; s < NR; ++s) vl[s * mm + p + i] = vec[s * rs.vec_stride + f.pvec + c];
+    }
   }
   __syncthreads();
   const int* vars = a.vars + f.var_off;
   const long long uo = a.subs[f.sub].u_off;
-  const T acc = act ? pf.dot(U + rr, p, rr + g, m, G, vl) : czero<T>();
+  T acc[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(U + rr, p, rr + g, m, G, vl + s * mm) : czero<T>();
   if (G == 1) {
-    if (act) {
-      fv[rr] = acc;
-      u[uo + vars[rr]] = acc;
-    }
-    for (int r = tid + NTL; r < p; r += NTL) {
-      const T x = strided_dot(U + r, (long long)p, r, m, 1, vl);
-      fv[r] = x;
-      u[uo + vars[r]] = x;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      T* fv = vec + s * rs.vec_stride + f.vec_off;
+      if (act) {
+        fv[rr] = acc[s];
+        u[s * rs.u_stride + uo + vars[rr]] = acc[s];
+      }
+      for (int r = tid + NTL; r < p; r += NTL) {
+        const T x = strided_dot(U + r, (long long)p, r, m, 1, vl + s * mm);
+        fv[r] = x;
+        u[s * rs.u_stride + uo + vars[r]] = x;
+      }
     }
   } else {
-    scr[tid] = acc;
+#pragma unroll
+    for (int s = 0; s < NR; ++s) scr[s * NTL + tid] = acc[s];
     __syncthreads();
     if (tid < p) {
-      T sum = czero<T>();
-      for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[gg * p + tid]);
-      fv[tid] = sum;
-      u[uo + vars[tid]] = sum;
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        T sum = czero<T>();
+        for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * p + tid]);
+        vec[s * rs.vec_stride + f.vec_off + tid] = sum;
+        u[s * rs.u_stride + uo + vars[tid]] = sum;
+      }
     }
   }
-  for (int i = p + tid; i < m; i += NTL) fv[i] = vl[i];
+  for (int i = p + tid; i < m; i += NTL)
+#pragma unroll
+    for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.vec_off + i] = vl[s * mm + i];
 }
 
-// z = sum_k P_k u_k: each global node adds the local fields of the (at most
-// four) subdomains whose Omega_k covers it, in a fixed order.
-template <typename T>
+// z_s = sum_k P_k u_k for each right-hand side s: each global node adds the
+// local fields of the (at most four) subdomains whose Omega_k covers it, in a
+// fixed order.
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_scatter(const T* __restrict__ u, const SubDev* __restrict__ subs,
                                                  const int4* __restrict__ cover_x,
                                                  const int4* __restrict__ cover_y, int px, int nx,
-                                                 int ny, double2* __restrict__ z) {
+                                                 int ny, RhsSet rs) {
   int i = blockIdx.x * 64 + threadIdx.x;
   int j = blockIdx.y * 4 + threadIdx.y;
   if (i >= nx || j >= ny) return;
   int4 cx = cover_x[i], cy = cover_y[j];
-  double2 acc = make_double2(0.0, 0.0);
+  double2 acc[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) acc[s] = make_double2(0.0, 0.0);
   int kys[2] = {cy.x, cy.z}, uys[2] = {cy.y, cy.w};
   int kxs[2] = {cx.x, cx.z}, txs[2] = {cx.y, cx.w};
 #pragma unroll
@@ -873,12 +940,17 @@ __global__ __launch_bounds__(256) void k_scatter(const T* __restrict__ u, const 
     for (int c = 0; c < 2; ++c) {
       if (kxs[c] < 0) continue;
       const SubDev& s = subs[kys[b] * px + kxs[c]];
-      double2 val = to_d2(u[s.u_off + (long long)uys[b] * s.nxl + txs[c]]);
-      acc.x += val.x;
-      acc.y += val.y;
+      const long long o = s.u_off + (long long)uys[b] * s.nxl + txs[c];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        double2 val = to_d2(u[r * rs.u_stride + o]);
+        acc[r].x += val.x;
+        acc[r].y += val.y;
+      }
     }
   }
-  z[(long long)j * nx + i] = acc;
+#pragma unroll
+  for (int r = 0; r < NR; ++r) rs.z[r][(long long)j * nx + i] = acc[r];
 }
 
 int g_max_lds = 0;
@@ -963,51 +1035,91 @@ inline int large_threads(int rows, int cols, int cap) {
   return 1024;
 }
 
+// Instantiation over the number of right-hand sides swept together.
+#define STF_NR_DISPATCH(nr, CALL) \
+  switch (nr) {                   \
+    case 1: CALL(1); break;       \
+    case 2: CALL(2); break;       \
+    case 3: CALL(3); break;       \
+    default: CALL(4); break;      \
+  }
+
 template <typename T, int RPL, int KP>
 void fwd_wave_launch(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
-                     const double2* v) {
-  hipLaunchKernelGGL((k_fwd_wave<T, RPL, KP>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac,
-                     piv, vec, v);
+                     const RhsSet& r) {
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_fwd_wave<T, RPL, KP, NR>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, piv, vec, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
+template <typename T, int KP>
+void bwd_wave_launch(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
+                     const RhsSet& r) {
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_bwd_wave<T, KP, NR>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
+template <typename T, int NTL, int KP>
+void fwd_large_nr(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
+                  const RhsSet& r) {
+  const size_t lds = ((size_t)r.nr * NTL + 2 * (size_t)r.nr * a.max_m) * sizeof(T);
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_fwd_large<T, NTL, KP, NR>), dim3(a.nlevel), dim3(NTL), lds, st, a, fac, piv, vec, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
+template <typename T, int NTL, int KP>
+void bwd_large_nr(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
+                  const RhsSet& r) {
+  const size_t lds = ((size_t)r.nr * NTL + (size_t)r.nr * a.max_m) * sizeof(T);
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_bwd_large<T, NTL, KP, NR>), dim3(a.nlevel), dim3(NTL), lds, st, a, upk, vec, u, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
 }
 
 template <typename T, int NTL>
 void fwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* fac, const int* piv,
-                      T* vec, const double2* v) {
-  const size_t lds = ((size_t)NTL + 2 * (size_t)a.max_m) * sizeof(T);
+                      T* vec, const RhsSet& r) {
   if (kp <= 16)
-    hipLaunchKernelGGL((k_fwd_large<T, NTL, 16>), dim3(a.nlevel), dim3(NTL), lds, st, a, fac, piv,
-                       vec, v);
+    fwd_large_nr<T, NTL, 16>(st, a, fac, piv, vec, r);
   else
-    hipLaunchKernelGGL((k_fwd_large<T, NTL, (sizeof(T) == 8 ? 32 : 16)>), dim3(a.nlevel), dim3(NTL),
-                       lds, st, a, fac, piv, vec, v);
+    fwd_large_nr<T, NTL, (sizeof(T) == 8 ? 32 : 16)>(st, a, fac, piv, vec, r);
 }
 
 template <typename T, int NTL>
-void bwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* upk, T* vec, T* u) {
-  const size_t lds = ((size_t)NTL + (size_t)a.max_m) * sizeof(T);
+void bwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* upk, T* vec, T* u,
+                      const RhsSet& r) {
   if (kp <= 16)
-    hipLaunchKernelGGL((k_bwd_large<T, NTL, 16>), dim3(a.nlevel), dim3(NTL), lds, st, a, upk, vec,
-                       u);
+    bwd_large_nr<T, NTL, 16>(st, a, upk, vec, u, r);
   else
-    hipLaunchKernelGGL((k_bwd_large<T, NTL, (sizeof(T) == 8 ? 32 : 16)>), dim3(a.nlevel), dim3(NTL),
-                       lds, st, a, upk, vec, u);
+    bwd_large_nr<T, NTL, (sizeof(T) == 8 ? 32 : 16)>(st, a, upk, vec, u, r);
+}
+
+void check_rhs(const RhsSet& r) {
+  if (r.nr < 1 || r.nr > MAX_RHS) throw Error(STF_EINVAL, "1 to 4 right-hand sides per sweep");
 }
 
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
-                      const double2* v) {
+                      const RhsSet& r) {
+  check_rhs(r);
   const int cap = sizeof(T) == 8 ? 32 : 16;      // registers per lane for the prefetch
   if (a.max_m <= 128 && a.max_p <= 64) {
     // A lane row takes at most min(r, p) <= max_p columns.
     const int rpl = a.max_m <= 64 ? 1 : 2;
     const int kp = prefetch_depth(a.max_p, cap / rpl);
     if (rpl == 1) {
-      if (kp == 8) fwd_wave_launch<T, 1, 8>(st, a, fac, piv, vec, v);
-      else if (kp == 16) fwd_wave_launch<T, 1, 16>(st, a, fac, piv, vec, v);
-      else fwd_wave_launch<T, 1, (sizeof(T) == 8 ? 32 : 16)>(st, a, fac, piv, vec, v);
+      if (kp == 8) fwd_wave_launch<T, 1, 8>(st, a, fac, piv, vec, r);
+      else if (kp == 16) fwd_wave_launch<T, 1, 16>(st, a, fac, piv, vec, r);
+      else fwd_wave_launch<T, 1, (sizeof(T) == 8 ? 32 : 16)>(st, a, fac, piv, vec, r);
     } else {
-      if (kp == 8) fwd_wave_launch<T, 2, 8>(st, a, fac, piv, vec, v);
-      else fwd_wave_launch<T, 2, (sizeof(T) == 8 ? 16 : 8)>(st, a, fac, piv, vec, v);
+      if (kp == 8) fwd_wave_launch<T, 2, 8>(st, a, fac, piv, vec, r);
+      else fwd_wave_launch<T, 2, (sizeof(T) == 8 ? 16 : 8)>(st, a, fac, piv, vec, r);
     }
     return;
   }
@@ -1015,13 +1127,15 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
   const int ntl = large_threads(a.max_m, a.max_p, cap);
   const int g = std::max(1, ntl / a.max_m);
   const int kp = prefetch_depth((a.max_p + g - 1) / g, cap);
-  if (ntl == 256) fwd_large_launch<T, 256>(st, a, kp, fac, piv, vec, v);
-  else if (ntl == 512) fwd_large_launch<T, 512>(st, a, kp, fac, piv, vec, v);
-  else fwd_large_launch<T, 1024>(st, a, kp, fac, piv, vec, v);
+  if (ntl == 256) fwd_large_launch<T, 256>(st, a, kp, fac, piv, vec, r);
+  else if (ntl == 512) fwd_large_launch<T, 512>(st, a, kp, fac, piv, vec, r);
+  else fwd_large_launch<T, 1024>(st, a, kp, fac, piv, vec, r);
 }
 
 template <typename T>
-void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u) {
+void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
+                      const RhsSet& r) {
+  check_rhs(r);
   const int cap = sizeof(T) == 8 ? 32 : 16;
   if (a.max_m <= 128 && a.max_p <= 64) {
     // Row groups: W >= max_p lanes, so G >= 64 / W groups share a row's columns.
@@ -1029,39 +1143,39 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, 
     while (w < a.max_p) w *= 2;
     const int g = 64 / w;
     const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
-    if (kp == 8)
-      hipLaunchKernelGGL((k_bwd_wave<T, 8>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u);
-    else if (kp == 16)
-      hipLaunchKernelGGL((k_bwd_wave<T, 16>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec,
-                         u);
-    else
-      hipLaunchKernelGGL((k_bwd_wave<T, (sizeof(T) == 8 ? 32 : 16)>), dim3((a.nlevel + 3) / 4),
-                         dim3(NT), 0, st, a, upk, vec, u);
+    if (kp == 8) bwd_wave_launch<T, 8>(st, a, upk, vec, u, r);
+    else if (kp == 16) bwd_wave_launch<T, 16>(st, a, upk, vec, u, r);
+    else bwd_wave_launch<T, (sizeof(T) == 8 ? 32 : 16)>(st, a, upk, vec, u, r);
     return;
   }
   // Rows p share the workgroup; a row takes at most m columns.
   const int ntl = large_threads(a.max_p, a.max_m, cap);
   const int g = std::max(1, ntl / std::max(a.max_p, 1));
   const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
-  if (ntl == 256) bwd_large_launch<T, 256>(st, a, kp, upk, vec, u);
-  else if (ntl == 512) bwd_large_launch<T, 512>(st, a, kp, upk, vec, u);
-  else bwd_large_launch<T, 1024>(st, a, kp, upk, vec, u);
+  if (ntl == 256) bwd_large_launch<T, 256>(st, a, kp, upk, vec, u, r);
+  else if (ntl == 512) bwd_large_launch<T, 512>(st, a, kp, upk, vec, u, r);
+  else bwd_large_launch<T, 1024>(st, a, kp, upk, vec, u, r);
 }
 
 template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
-                    const int4* cover_y, int px, int nx, int ny, double2* z) {
+                    const int4* cover_y, int px, int nx, int ny, const RhsSet& r) {
+  check_rhs(r);
   dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
-  hipLaunchKernelGGL(k_scatter<T>, grd, blk, 0, st, u, subs, cover_x, cover_y, px, nx, ny, z);
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_scatter<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, px, nx, ny, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
 }
 
 #define STF_INST(T)                                                                             \
   template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, int*, int*, double); \
   template void launch_sweep_fwd<T>(hipStream_t, const LevelArgs&, const T*, const int*, T*,    \
-                                    const double2*);                                            \
-  template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*);           \
+                                    const RhsSet&);                                             \
+  template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*,            \
+                                    const RhsSet&);                                             \
   template void launch_scatter<T>(hipStream_t, const T*, const SubDev*, const int4*,            \
-                                  const int4*, int, int, int, double2*);
+                                  const int4*, int, int, int, const RhsSet&);
 STF_INST(double2)
 STF_INST(float2)
 

@@ -142,6 +142,18 @@ struct FrontDev {
   int cq[2];                // children: q
 };
 
+// Right-hand sides swept together (1..MAX_RHS): each has its own global input
+// and output vector and its own copy of the front-vector and local-field
+// workspaces, at fixed strides; the factors are read once for all of them.
+constexpr int MAX_RHS = 4;
+struct RhsSet {
+  int nr = 1;
+  long long vec_stride = 0;            // elements between RHS copies of the front vectors
+  long long u_stride = 0;              // elements between RHS copies of the local fields
+  const double2* v[MAX_RHS] = {};      // restricted sources (global, FP64)
+  double2* z[MAX_RHS] = {};            // round outputs (global, FP64)
+};
+
 // Kernel classes for timing (match STF_K_* in stfdfd.h).
 enum KClass {
   K_ASSEMBLE = STF_K_ASSEMBLE, K_STENCIL = STF_K_STENCIL, K_FRONT_ASM = STF_K_FRONT_ASM,
@@ -192,13 +204,13 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int
                          double tau);
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
-                      const double2* v);
-// upk: packed backward operators (rows 0..p-1 of every front, leading dimension p).
+                      const RhsSet& r);
 template <typename T>
-void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u);
+void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
+                      const RhsSet& r);
 template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
-                    const int4* cover_y, int px, int nx, int ny, double2* z);
+                    const int4* cover_y, int px, int nx, int ny, const RhsSet& r);
 
 // Krylov (kernels_krylov.hip).  Vectors of n complex doubles; V holds nv vectors
 // with leading dimension ld (elements).

@@ -179,3 +179,47 @@ def test_errors(stf, ctx):
     # Zero source: zero field, no iterations.
     x, info = pb.solve(np.zeros_like(w.b[0]))
     assert np.all(x == 0) and info[0]["iters"] == 0
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_rhs_equal_solo_solves(stf, ctx, prec):
+    """Right-hand sides swept together (groups of up to four share every factor
+    read) give exactly the solo solves: the per-RHS arithmetic is the same.
+    Six RHS make a group of four and a group of two; one RHS is zero and one
+    converges much later than the others (a scaled copy stops at the same
+    iteration; a point source needs more), so RHS drop out of the lockstep at
+    different iterations."""
+    w = workloads.configs.small_random(nx=72, ny=60, pml=6, px=3, py=2, overlap=2, local_pml=6,
+                                       seed=9, nrhs=4)
+    b = np.concatenate([w.b, np.zeros((2,) + w.b.shape[1:], complex)])
+    b[4] = 1e3 * w.b[0]
+    b[5, 30, 36] = 1.0
+    b[2] = 0.0
+    pb = stf.Problem(ctx, _prm(w, front_prec=prec), w.eps_cells)
+    pb.factor()
+    tol = 1e-12 if prec == 0 else 1e-10
+    xb, ib = pb.solve(b, tol=tol, restart=8)
+    for r in range(6):
+        xs, is_ = pb.solve(b[r], tol=tol, restart=8)
+        assert ib[r]["iters"] == is_[0]["iters"] and ib[r]["restarts"] == is_[0]["restarts"]
+        assert np.array_equal(xb[r], xs), r
+        assert np.array_equal(ib[r]["history"], is_[0]["history"])
+    assert ib[2]["iters"] == 0 and np.all(xb[2] == 0)
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    assert _rel(xb[5], fdfd.solve_direct(A, b[5].ravel())) < (1e-10 if prec == 0 else 1e-8)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batched_round_equals_single_rounds(stf, ctx, prec):
+    """The round swept for 1..4 vectors together equals the round of each vector
+    alone, bit for bit (the sweeps share the factor reads, not the arithmetic)."""
+    w = workloads.configs.small_random(nx=72, ny=60, pml=6, px=3, py=2, overlap=2, local_pml=6,
+                                       seed=9, nrhs=4)
+    pb = stf.Problem(ctx, _prm(w, front_prec=prec), w.eps_cells)
+    pb.factor()
+    v = np.concatenate([w.b, 1e3 * w.b[:1]])
+    single = [pb.precond(v[r]) for r in range(5)]
+    for k in range(1, 6):
+        zb = pb.precond(v[:k])
+        for r in range(k):
+            assert np.array_equal(zb[r], single[r]), (k, r)

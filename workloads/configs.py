@@ -66,17 +66,22 @@ def cylinder_tfsf(interior=100, pml=16, lam=20.0, radius_lam=0.5, eps_cyl=4.0, p
 
 
 def metasurface_sheet(interior=1024, pml=20, lam=30.0, parts=8, overlap=8, local_pml=16, seed=2,
-                      n_pillars=None, slot=16, substrate_rows=256, source_row=128, subcells=16):
+                      n_pillars=None, slot=16, substrate_rows=256, source_row=128, subcells=16,
+                      nrhs=1):
     """Random metasurface (pillars eps 12.25 on an eps 2.13 substrate) lit by a
     current sheet inside the substrate (default 1024x1024 interior, 20-cell PML,
-    lambda = 30 cells, 8x8 subdomains, overlap 8, seed 2)."""
+    lambda = 30 cells, 8x8 subdomains, overlap 8, seed 2).  nrhs > 1 adds
+    sheets at further substrate rows (source_row - 64, + 64, + 96, ...)."""
     n = interior + 2 * pml
     if n_pillars is None:
         n_pillars = interior // slot
     k0 = 2 * math.pi / lam
     cells = geometry.metasurface(n, n, pml, lam, n_pillars, slot, substrate_rows, 12.25, 2.13, seed,
                                  subcells=subcells)
-    b = sources.current_sheet(n, n, pml + source_row)[None]
+    offs = [0, -64, 64, 96, -96, 32, -32, 112][:nrhs]
+    if nrhs > len(offs) or any(not 0 < source_row + o < substrate_rows for o in offs):
+        raise ValueError("sheet rows must lie inside the substrate")
+    b = np.stack([sources.current_sheet(n, n, pml + source_row + o) for o in offs])
     return Workload("metasurface_%d" % n, n, n, k0, (pml,) * 4, 3, 1e-8, parts, parts, overlap,
                     local_pml, 3, 1e-8, cells, b, meta=dict(seed=seed, lam=lam))
 
