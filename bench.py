@@ -92,6 +92,94 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     return (t1 - t0) / steps, infos, stats, info, profile
 
 
+# Kernel classes of the library's kernels (by kernel name) and the source file
+# that holds them (a PMC summary is valid only for the source it was taken on).
+CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "front_lu"),
+            ("k_stencil", "stencil"), ("k_scatter", "scatter"), ("k_mdot", "arnoldi"),
+            ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi")]
+SOURCE_OF = {"sweep_fwd": "kernels_front.hip", "sweep_bwd": "kernels_front.hip",
+             "front_lu": "kernels_front.hip", "scatter": "kernels_front.hip",
+             "stencil": "kernels_stencil.hip", "arnoldi": "kernels_krylov.hip"}
+PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_metasurface_1064.md")
+COPY_BYTES = 1 << 29          # the calibration copy: 512 MiB read and 512 MiB written
+
+
+def source_sha(cls):
+    import hashlib
+    path = os.path.join(ROOT, "paper_2509_20801_amd", "csrc", SOURCE_OF[cls])
+    return hashlib.sha256(open(path, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic(cls):
+    """HBM bytes per launch of class `cls` from the committed PMC summary, or
+    None when there is none or its kernels have changed since."""
+    if not os.path.exists(PMC_SUMMARY):
+        return None
+    for line in open(PMC_SUMMARY):
+        if line.startswith("traffic_json: "):
+            d = json.loads(line[len("traffic_json: "):])
+            c = d.get("classes", {}).get(cls)
+            if c and c.get("source_sha") == source_sha(cls):
+                return c["bytes_per_launch"]
+    return None
+
+
+def copy_probe():
+    """Calibration kernel for the PMC byte counters: a plain device copy of
+    COPY_BYTES (run under rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE)."""
+    import torch
+    a = torch.ones(COPY_BYTES // 8, dtype=torch.complex64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copied %d bytes per call" % COPY_BYTES)
+
+
+def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
+    """Markdown summary of two PMC passes (FETCH_SIZE, WRITE_SIZE; KiB per
+    dispatch) over a bench run, each scaled so that the calibration copy reads
+    COPY_BYTES; per kernel class: launches and HBM bytes per launch."""
+    import csv
+    import collections
+    import glob
+
+    def rows(d):
+        return list(csv.DictReader(open(glob.glob(os.path.join(d, "*counter_collection.csv"))[0])))
+
+    def copy_kib(d):
+        v = [float(r["Counter_Value"]) for r in rows(d) if "opy" in r["Kernel_Name"]]
+        return max(v)                            # the 512 MiB copy dispatches
+
+    scale = {"fetch": COPY_BYTES / (copy_kib(copy_fetch_dir) * 1024.0),
+             "write": COPY_BYTES / (copy_kib(copy_write_dir) * 1024.0)}
+    agg = collections.defaultdict(lambda: {"n": 0, "fetch": 0.0, "write": 0.0})
+    for key, d in (("fetch", fetch_dir), ("write", write_dir)):
+        for r in rows(d):
+            name = r["Kernel_Name"]
+            cls = next((c for pfx, c in CLASS_OF if pfx in name), None)
+            if cls is None:
+                continue
+            if key == "fetch":
+                agg[cls]["n"] += 1
+            agg[cls][key] += float(r["Counter_Value"]) * 1024.0 * scale[key]
+    out = {"calibration": {k: round(v, 4) for k, v in scale.items()}, "classes": {}}
+    lines = ["| class | launches | fetch MB/launch | write MB/launch | HBM bytes/launch |",
+             "|---|---|---|---|---|"]
+    for cls, a in sorted(agg.items(), key=lambda kv: -(kv[1]["fetch"] + kv[1]["write"])):
+        n = max(a["n"], 1)
+        per = (a["fetch"] + a["write"]) / n
+        out["classes"][cls] = {"launches": a["n"], "bytes_per_launch": round(per, 1),
+                               "fetch_per_launch": round(a["fetch"] / n, 1),
+                               "write_per_launch": round(a["write"] / n, 1),
+                               "source_sha": source_sha(cls)}
+        lines.append("| %s | %d | %.3f | %.3f | %.4g |" % (cls, a["n"], a["fetch"] / n / 1e6,
+                                                          a["write"] / n / 1e6, per))
+    print("\n".join(lines))
+    print()
+    print("traffic_json: " + json.dumps(out))
+
+
 def roofline(stf, w, prec, infos, stats, steps):
     """Roofline of the kernel class with the largest summed time."""
     ref = stf.plan_query(params_of(w, prec, leaf=4))     # fine nested dissection reference
@@ -119,9 +207,13 @@ def roofline(stf, w, prec, infos, stats, steps):
         unit = "TFLOP/s"
     else:
         peak, unit = PEAK["hbm"], "GB/s"
+    traffic = measured_traffic(dom)
     return dom, {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                 "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
-                 "avg_launch_ms": round(ms / launches, 4), "launches": launches}
+                 "frac": round(achieved / peak, 4),
+                 "traffic": None if traffic is None else round(traffic, 1),
+                 "traffic_unit": "HBM bytes per launch (PMC)",
+                 "algorithmic_per_launch": round(per_launch * (1e9 if bound == "hbm" else 1e12), 1),
+                 "kernel": dom, "avg_launch_ms": round(ms / launches, 4), "launches": launches}
 
 
 def cpu_baseline(w, gpu_iters, restart):
@@ -169,7 +261,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 reference form")
     ap.add_argument("--no-batched", action="store_true", help="skip the four-RHS batched form")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run only the PMC calibration copy (512 MiB)")
+    ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
+                    help="summarise rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
               "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
