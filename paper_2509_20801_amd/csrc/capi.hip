@@ -144,12 +144,12 @@ struct stf_problem_s {
   bool assembled = false, factored = false;
   int prec = STF_C128;
   int64_t n_fronts = 0;
-  int64_t fac_elems = 0, upk_elems = 0, vec_elems = 0, piv_elems = 0, u_elems = 0;
+  int64_t fac_elems = 0, lpk_elems = 0, upk_elems = 0, vec_elems = 0, piv_elems = 0, u_elems = 0;
   std::vector<Level> levels;     // by depth
 
   // Device state.
   DBuf keps, gcoef, lcoef, subs, fronts, vars, cmap, ents, children;
-  DBuf fac, upk, piv, vec, u, cover_x, cover_y, flag;
+  DBuf fac, lpk, upk, piv, vec, u, cover_x, cover_y, flag;
   DBuf partial, npartial, scal;    // reduction scratch, device scalars
   DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
   DBuf hb, hx, cells;              // staging for host inputs
@@ -180,7 +180,7 @@ struct stf_problem_s {
   }
   int64_t device_bytes() const {
     const DBuf* all[] = {&keps, &gcoef, &lcoef, &subs, &fronts, &vars, &cmap, &ents,
-                         &children, &fac, &upk, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
+                         &children, &fac, &lpk, &upk, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
                          &npartial,
                          &scal, &kV, &kZ, &kw, &kr, &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &hb,
                          &hx, &cells};
@@ -335,7 +335,7 @@ void build_device_state(stf_problem pb) {
   for (size_t t = 0; t < order.size(); ++t) inst[order[t]] = (int)t;
   std::vector<FrontDev> fr(recs.size());
   std::vector<int> kids;
-  long long fac_off = 0, upk_off = 0;
+  long long fac_off = 0, lpk_off = 0, upk_off = 0;
   long long vec_off = 0, piv_off = 0;
   for (size_t t = 0; t < order.size(); ++t) {
     const Rec& rc = recs[order[t]];
@@ -345,6 +345,7 @@ void build_device_state(stf_problem pb) {
     FrontDev& d = fr[t];
     int m = f.p + f.q;
     d.fac_off = fac_off;
+    d.lpk_off = lpk_off;
     d.upk_off = upk_off;
     d.vec_off = (int)vec_off;
     d.piv_off = (int)piv_off;
@@ -362,11 +363,15 @@ void build_device_state(stf_problem pb) {
     for (int c = 0; c < f.nchild; ++c)
       kids.push_back(inst[sub_base[rc.sub] + sh.children[f.child_off + c]]);
     fac_off += (long long)m * m;
-    upk_off += (long long)f.p * m;
+    // Packed sweep operators: the strictly lower trapezoid of the first p
+    // columns (forward) and the upper trapezoid of the first p rows (backward).
+    lpk_off += (long long)f.p * f.q + (long long)f.p * (f.p - 1) / 2;
+    upk_off += (long long)f.p * f.q + (long long)f.p * (f.p + 1) / 2;
     vec_off += m;
     piv_off += f.p;
   }
   pb->upk_elems = upk_off;
+  pb->lpk_elems = lpk_off;
   STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
   // Embedded parent/children vector offsets (all offsets are known now).
   for (size_t t = 0; t < fr.size(); ++t) {
@@ -411,6 +416,7 @@ void build_device_state(stf_problem pb) {
   size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
   pb->fac.alloc((size_t)pb->fac_elems * es);
   pb->upk.alloc((size_t)pb->upk_elems * es);
+  pb->lpk.alloc((size_t)pb->lpk_elems * es);
   pb->piv.alloc((size_t)pb->piv_elems * sizeof(int));
   pb->vec.alloc((size_t)pb->vec_elems * es);
   pb->u.alloc((size_t)pb->u_elems * es);
@@ -451,7 +457,7 @@ int factor_t(stf_problem pb) {
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
   for (int d = pb->max_depth; d >= 0; --d) {
     Timed t(pb->ctx, K_FRONT_LU);
-    launch_front_factor<T>(st, pb->level_args(d), fac, pb->upk.as<T>(), pb->piv.as<int>(),
+    launch_front_factor<T>(st, pb->level_args(d), fac, pb->lpk.as<T>(), pb->upk.as<T>(), pb->piv.as<int>(),
                            pb->flag.as<int>(), tau);
   }
   HIP_CHECK(hipGetLastError());
@@ -474,11 +480,11 @@ void precond_t(stf_problem pb, RhsSet r) {
   }
   r.vec_stride = pb->vec_elems;
   r.u_stride = pb->u_elems;
-  const T* fac = pb->fac.as<T>();
+  const T* lpk = pb->lpk.as<T>();
   T* vec = pb->vec.as<T>();
   for (int d = pb->max_depth; d >= 0; --d) {
     Timed t(pb->ctx, K_SWEEP_FWD);
-    launch_sweep_fwd<T>(st, pb->level_args(d), fac, pb->piv.as<int>(), vec, r);
+    launch_sweep_fwd<T>(st, pb->level_args(d), lpk, pb->piv.as<int>(), vec, r);
   }
   for (int d = 0; d <= pb->max_depth; ++d) {
     Timed t(pb->ctx, K_SWEEP_BWD);

@@ -45,6 +45,25 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Packed sweep operators of a front of order m with p separator variables:
+//   forward:  column k < p holds rows k+1 .. m-1 of [L11^{-1}; M'] (the unit
+//             diagonal is implicit), column after column;
+//   backward: column c holds rows 0 .. min(c, p-1) of [U11^{-1}  V'].
+// Only the entries the sweeps read are stored, each column contiguous.
+__host__ __device__ inline int lpk_col(int m, int k) { return k * (m - 1) - k * (k - 1) / 2; }
+__host__ __device__ inline int upk_col(int p, int c) {
+  return c < p ? c * (c + 1) / 2 : p * (p + 1) / 2 + (c - p) * p;
+}
+// Element offsets of row r, column k in the packed forms.
+struct LowerAt {
+  int m, r;
+  __device__ int operator()(int k) const { return lpk_col(m, k) + r - k - 1; }
+};
+struct UpperAt {
+  int p, r;
+  __device__ int operator()(int c) const { return upk_col(p, c) + r; }
+};
+
 // Coefficient of local row `node` towards direction `dir` (0 = diagonal).
 __device__ inline double2 local_coef(const LevelArgs& a, const SubDev& s, int node, int dir) {
   int tx = node % s.nxl, ty = node / s.nxl;
@@ -188,7 +207,8 @@ __device__ inline void invert_upper(T* G, int ld, int n, T* col, int lane) {
 // ---------------------------------------------------------------------------
 template <typename T>
 __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict__ fac,
-                                                     T* __restrict__ upk, int* __restrict__ piv,
+                                                     T* __restrict__ lpk, T* __restrict__ upk,
+                                                     int* __restrict__ piv,
                                                      int* __restrict__ flag, double tau) {
   using R = typename RealOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
@@ -253,11 +273,14 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   T* F = fac + f.fac_off;
   const long long mm = (long long)m * m;
   for (long long t = lane; t < mm; t += 64) F[t] = G[t];
-  // Backward operator rows 0..p-1, packed with leading dimension p.
-  T* U = upk + f.upk_off;
-  for (int t = lane; t < p * m; t += 64) {
-    int c = t / p, r = t - c * p;
-    U[t] = G[(long long)c * m + r];
+  // Packed sweep operators.
+  T* Lp = lpk + f.lpk_off;
+  for (int k = 0; k < p; ++k)
+    for (int r = k + 1 + lane; r < m; r += 64) Lp[lpk_col(m, k) + r - k - 1] = G[(long long)k * m + r];
+  T* Up = upk + f.upk_off;
+  for (int c = 0; c < m; ++c) {
+    const int rows = c < p ? c + 1 : p;
+    for (int r = lane; r < rows; r += 64) Up[upk_col(p, c) + r] = G[(long long)c * m + r];
   }
 }
 
@@ -310,7 +333,8 @@ __device__ void fold_step(T* __restrict__ F, int m, int k0, int k1, int c0, int 
 // ---------------------------------------------------------------------------
 template <typename T, int NB>
 __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict__ fac,
-                                                     T* __restrict__ upk, int* __restrict__ piv,
+                                                     T* __restrict__ lpk, T* __restrict__ upk,
+                                                     int* __restrict__ piv,
                                                      int* __restrict__ flag, double tau) {
   using R = typename RealOf<T>::type;
   extern __shared__ unsigned char smem_raw[];
@@ -528,11 +552,14 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
                             tid);
     __syncthreads();
   }
-  // Backward operator rows 0..p-1, packed with leading dimension p.
-  T* U = upk + f.upk_off;
-  for (int t = tid; t < p * m; t += NT) {
-    int c = t / p, r = t - c * p;
-    U[t] = F[(long long)c * m + r];
+  // Packed sweep operators, a wavefront per column.
+  T* Lp = lpk + f.lpk_off;
+  for (int k = wv; k < p; k += NT / 64)
+    for (int r = k + 1 + lane; r < m; r += 64) Lp[lpk_col(m, k) + r - k - 1] = F[(long long)k * m + r];
+  T* Up = upk + f.upk_off;
+  for (int c = wv; c < m; c += NT / 64) {
+    const int rows = c < p ? c + 1 : p;
+    for (int r = lane; r < rows; r += 64) Up[upk_col(p, c) + r] = F[(long long)c * m + r];
   }
 }
 
@@ -549,12 +576,14 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
 // the bulk of the front's traffic instead of preceding it.
 // ---------------------------------------------------------------------------
 
-// sum over c = c0, c0+step, ... < c1 of A[c*lda] * x[c], with the global
-// loads issued in predicated batches of LB, so that every batch (the last,
-// partial one included) costs one memory round trip.
-template <typename T>
-__device__ inline T strided_dot(const T* __restrict__ A, long long lda, int c0, int c1, int step,
-                                const T* x) {
+// sum over c = c0, c0+step, ... < c1 with c >= cmin of A[ad(c)] * x[c], with
+// the global loads issued in predicated batches of LB, so that every batch
+// (the last, partial one included) costs one memory round trip.  The column
+// sequence does not depend on the row, so the lanes of a wavefront read the
+// same column (contiguous rows) at every step.
+template <typename T, typename Addr>
+__device__ inline T gather_dot(const T* __restrict__ A, Addr ad, int c0, int cmin, int c1, int step,
+                               const T* x) {
   constexpr int LB = 8;
   T acc0 = czero<T>(), acc1 = czero<T>();
   for (int c = c0; c < c1; c += LB * step) {
@@ -562,42 +591,44 @@ __device__ inline T strided_dot(const T* __restrict__ A, long long lda, int c0, 
 #pragma unroll
     for (int t = 0; t < LB; ++t) {
       const int k = c + t * step;
-      av[t] = k < c1 ? A[(long long)k * lda] : czero<T>();
+      av[t] = (k >= cmin && k < c1) ? A[ad(k)] : czero<T>();
     }
 #pragma unroll
     for (int t = 0; t < LB; t += 2) {
       const int k = c + t * step;
-      if (k < c1) acc0 = cfma(av[t], x[k], acc0);
-      if (k + step < c1) acc1 = cfma(av[t + 1], x[k + step], acc1);
+      if (k >= cmin && k < c1) acc0 = cfma(av[t], x[k], acc0);
+      if (k + step >= cmin && k + step < c1) acc1 = cfma(av[t + 1], x[k + step], acc1);
     }
   }
   return cadd(acc0, acc1);
 }
 
-// The first KP terms of a strided dot product, A[(k0 + G t) * lda] for t < KP
-// and k0 + G t < kend, held in registers; dot() adds the rest from memory.
+// The first KP terms of a strided dot product, A[ad(k0 + G t)] for t < KP and
+// kmin <= k0 + G t < kend, held in registers; dot() adds the rest from memory.
 template <typename T, int KP>
 struct ColPrefetch {
   T av[KP];
-  __device__ inline void load(const T* __restrict__ A, long long lda, int k0, int kend, int G) {
+  template <typename Addr>
+  __device__ inline void load(const T* __restrict__ A, Addr ad, int k0, int kmin, int kend, int G) {
 #pragma unroll
     for (int t = 0; t < KP; ++t) {
       const int k = k0 + G * t;
-      av[t] = k < kend ? A[(long long)k * lda] : czero<T>();
+      av[t] = (k >= kmin && k < kend) ? A[ad(k)] : czero<T>();
     }
   }
-  // sum over k = k0, k0 + G, ... < kend of A[k*lda] x[k]
-  __device__ inline T dot(const T* __restrict__ A, long long lda, int k0, int kend, int G,
+  // sum over k = k0, k0 + G, ... < kend with k >= kmin of A[ad(k)] x[k]
+  template <typename Addr>
+  __device__ inline T dot(const T* __restrict__ A, Addr ad, int k0, int kmin, int kend, int G,
                           const T* x) const {
     T acc0 = czero<T>(), acc1 = czero<T>();
 #pragma unroll
     for (int t = 0; t < KP; t += 2) {
       const int k = k0 + G * t;
-      if (k < kend) acc0 = cfma(av[t], x[k], acc0);
-      if (k + G < kend) acc1 = cfma(av[t + 1], x[k + G], acc1);
+      if (k >= kmin && k < kend) acc0 = cfma(av[t], x[k], acc0);
+      if (k + G >= kmin && k + G < kend) acc1 = cfma(av[t + 1], x[k + G], acc1);
     }
     const int kt = k0 + G * KP;
-    if (kt < kend) acc0 = cadd(acc0, strided_dot(A, lda, kt, kend, G, x));
+    if (kt < kend) acc0 = cadd(acc0, gather_dot(A, ad, kt, kmin, kend, G, x));
     return cadd(acc0, acc1);
   }
 };
@@ -608,7 +639,7 @@ struct ColPrefetch {
 // row (columns k = g, g + G, ...) and a fixed butterfly adds their sums.  The
 // NR right-hand sides share the operator registers and the index loads.
 template <typename T, int RPL, int KP, int NR>
-__global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restrict__ fac,
+__global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restrict__ lpk,
                                                  const int* __restrict__ piv, T* __restrict__ vec,
                                                  RhsSet rs) {
   constexpr int MW = 64 * RPL;
@@ -618,14 +649,14 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   if (fi >= a.nlevel) return;                          // whole wavefront
   const FrontDev f = a.fronts[a.first + fi];
   const int m = f.p + f.q, p = f.p;
-  const T* F = fac + f.fac_off;
+  const T* L = lpk + f.lpk_off;
   const int W = RPL > 1 ? 64 : (m <= 16 ? 16 : (m <= 32 ? 32 : 64));
   const int G = 64 / W, g = lane / W, rl = lane - g * W;
   ColPrefetch<T, KP> pf[RPL];
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int r = rl + 64 * i;
-    pf[i].load(F + r, m, g, r < m ? min(r, p) : 0, G);
+    pf[i].load(L, LowerAt{m, r}, g, 0, r < m ? min(r, p) : 0, G);
   }
   const int pv = lane < p ? piv[f.piv_off + lane] : lane;
   // b = R^I v on the separator rows plus the children's update vectors (all
@@ -689,7 +720,7 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
     const int kend = r < m ? min(r, p) : 0;
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
-      T acc = pf[i].dot(F + r, m, g, kend, G, sh[wv][s]);
+      T acc = pf[i].dot(L, LowerAt{m, r}, g, 0, kend, G, sh[wv][s]);
       if (RPL == 1)
         for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
       if (g == 0 && r < m) vec[s * rs.vec_stride + f.vec_off + r] = cadd(sh[wv][s][r], acc);
@@ -714,7 +745,7 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   const int W = p <= 4 ? 4 : (p <= 8 ? 8 : (p <= 16 ? 16 : (p <= 32 ? 32 : 64)));
   const int G = 64 / W, g = lane / W, r = lane - g * W;
   ColPrefetch<T, KP> pf;
-  pf.load(U + r, p, r + g, r < p ? m : 0, G);
+  pf.load(U, UpperAt{p, r}, g, r, r < p ? m : 0, G);
   const int var = lane < p ? a.vars[f.var_off + lane] : 0;
   int ci[2];
 #pragma unroll
@@ -742,7 +773,7 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   const long long uo = a.subs[f.sub].u_off;
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
-    T acc = pf.dot(U + r, p, r + g, r < p ? m : 0, G, sh[wv][s]);
+    T acc = pf.dot(U, UpperAt{p, r}, g, r, r < p ? m : 0, G, sh[wv][s]);
     for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
     T* fv = vec + s * rs.vec_stride + f.vec_off;
     if (lane < p) {                        // lane < p <= W: g = 0, r = lane
@@ -763,7 +794,7 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
 // added in a fixed order through LDS.
 // ---------------------------------------------------------------------------
 template <typename T, int NTL, int KP, int NR>
-__global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restrict__ fac,
+__global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restrict__ lpk,
                                                    const int* __restrict__ piv, T* __restrict__ vec,
                                                    RhsSet rs) {
   extern __shared__ unsigned char smem_raw[];
@@ -773,7 +804,7 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   const int mm = a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
-  const T* F = fac + f.fac_off;
+  const T* L = lpk + f.lpk_off;
   const int tid = threadIdx.x;
   int G = 1, g = 0, rr = tid;
   if (m < NTL) {
@@ -783,7 +814,7 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   }
   const bool act = g < G && rr < m;
   ColPrefetch<T, KP> pf;
-  pf.load(F + rr, m, g, act ? min(rr, p) : 0, G);
+  pf.load(L, LowerAt{m, rr}, g, 0, act ? min(rr, p) : 0, G);
   const SubDev sd = a.subs[f.sub];
   for (int i = tid; i < m; i += NTL) {
     long long gidx = -1;
@@ -822,14 +853,14 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   __syncthreads();
   T acc[NR];
 #pragma unroll
-  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(F + rr, m, g, min(rr, p), G, vl + s * mm) : czero<T>();
+  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(L, LowerAt{m, rr}, g, 0, min(rr, p), G, vl + s * mm) : czero<T>();
   if (G == 1) {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       T* out = vec + s * rs.vec_stride + f.vec_off;
       if (act) out[rr] = cadd(vl[s * mm + rr], acc[s]);
       for (int r = tid + NTL; r < m; r += NTL)
-        out[r] = cadd(vl[s * mm + r], strided_dot(F + r, (long long)m, 0, min(r, p), 1, vl + s * mm));
+        out[r] = cadd(vl[s * mm + r], gather_dot(L, LowerAt{m, r}, 0, 0, min(r, p), 1, vl + s * mm));
     }
   } else {
 #pragma unroll
@@ -855,7 +886,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   const int mm = a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p;
-  const T* U = upk + f.upk_off;                            // rows 0..p-1, leading dimension p
+  const T* U = upk + f.upk_off;                            // packed [U11^{-1} V']
   const int tid = threadIdx.x;
   int G = 1, g = 0, rr = tid;
   if (p < NTL) {
@@ -865,7 +896,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   }
   const bool act = g < G && rr < p;
   ColPrefetch<T, KP> pf;
-  pf.load(U + rr, p, rr + g, act ? m : 0, G);
+  pf.load(U, UpperAt{p, rr}, g, rr, act ? m : 0, G);
   for (int i = tid; i < p; i += NTL)
 #pragma unroll
     for (int s = 0; s < NR; ++s) vl[s * mm + i] = vec[s * rs.vec_stride + f.vec_off + i];
@@ -882,7 +913,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   const long long uo = a.subs[f.sub].u_off;
   T acc[NR];
 #pragma unroll
-  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(U + rr, p, rr + g, m, G, vl + s * mm) : czero<T>();
+  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(U, UpperAt{p, rr}, g, rr, m, G, vl + s * mm) : czero<T>();
   if (G == 1) {
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
@@ -892,7 +923,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
         u[s * rs.u_stride + uo + vars[rr]] = acc[s];
       }
       for (int r = tid + NTL; r < p; r += NTL) {
-        const T x = strided_dot(U + r, (long long)p, r, m, 1, vl + s * mm);
+        const T x = gather_dot(U, UpperAt{p, r}, 0, r, m, 1, vl + s * mm);
         fv[r] = x;
         u[s * rs.u_stride + uo + vars[r]] = x;
       }
@@ -968,11 +999,11 @@ int max_lds() {
 }
 
 template <typename T, int NB>
-void large_launch(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int* piv, int* flag,
+void large_launch(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
                   double tau) {
   size_t lds = std::max((size_t)a.max_m * NB, (size_t)DIB * DIB + 2 * DIB + (size_t)CR * DIB) * sizeof(T);
-  hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, upk, piv,
-                     flag, tau);
+  hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, lpk, upk,
+                     piv, flag, tau);
 }
 
 }  // namespace
@@ -986,11 +1017,11 @@ int small_factor_limit(size_t elem) {
 }
 
 template <typename T>
-void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int* piv, int* flag,
+void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
                          double tau) {
   if (a.max_m <= small_factor_limit(sizeof(T))) {
     size_t lds = ((size_t)a.max_m * a.max_m + 128) * sizeof(T);
-    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, upk, piv, flag,
+    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, lpk, upk, piv, flag,
                        tau);
     return;
   }
@@ -1007,12 +1038,12 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int
   while (nb * 2 <= nb_max && per_col * nb * 2 <= budget) nb *= 2;
   if (per_col * nb > budget) throw Error(STF_EINVAL, "front too large for the LDS panel");
   switch (nb) {
-    case 32: large_launch<T, 32>(st, a, fac, upk, piv, flag, tau); break;
-    case 16: large_launch<T, 16>(st, a, fac, upk, piv, flag, tau); break;
-    case 8: large_launch<T, 8>(st, a, fac, upk, piv, flag, tau); break;
-    case 4: large_launch<T, 4>(st, a, fac, upk, piv, flag, tau); break;
-    case 2: large_launch<T, 2>(st, a, fac, upk, piv, flag, tau); break;
-    default: large_launch<T, 1>(st, a, fac, upk, piv, flag, tau); break;
+    case 32: large_launch<T, 32>(st, a, fac, lpk, upk, piv, flag, tau); break;
+    case 16: large_launch<T, 16>(st, a, fac, lpk, upk, piv, flag, tau); break;
+    case 8: large_launch<T, 8>(st, a, fac, lpk, upk, piv, flag, tau); break;
+    case 4: large_launch<T, 4>(st, a, fac, lpk, upk, piv, flag, tau); break;
+    case 2: large_launch<T, 2>(st, a, fac, lpk, upk, piv, flag, tau); break;
+    default: large_launch<T, 1>(st, a, fac, lpk, upk, piv, flag, tau); break;
   }
 }
 
@@ -1169,7 +1200,7 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
 }
 
 #define STF_INST(T)                                                                             \
-  template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, int*, int*, double); \
+  template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, T*, int*, int*, double); \
   template void launch_sweep_fwd<T>(hipStream_t, const LevelArgs&, const T*, const int*, T*,    \
                                     const RhsSet&);                                             \
   template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*,            \

@@ -127,7 +127,8 @@ struct SubDev {
 // offsets are embedded so that the sweeps read one descriptor per front.
 struct FrontDev {
   long long fac_off;        // element offset of the m x m front (column-major)
-  long long upk_off;        // element offset of the packed backward operator (p x m, ld p)
+  long long lpk_off;        // element offset of the packed forward operator
+  long long upk_off;        // element offset of the packed backward operator
   int vec_off;              // element offset of the front vector (m elements)
   int piv_off;              // offset of the p pivot entries
   int p, q;
@@ -200,7 +201,7 @@ struct LevelArgs {
 // Assembly (original entries + extend-add of the children) and partial LU of
 // every front of one level.
 template <typename T>
-void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* upk, int* piv, int* flag,
+void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
                          double tau);
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
