@@ -341,6 +341,8 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
   T* P = reinterpret_cast<T*>(smem_raw);           // panel, column-major, ld = ldp
   __shared__ T Us[UC][NB + 1];                      // staged U columns
   __shared__ int s_piv[NB];
+  __shared__ R s_best[NT / 64], s_amax[NT / 64];
+  __shared__ int s_bi[NT / 64];
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p, ldp = a.max_m;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -356,36 +358,68 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       P[k * ldp + r] = F[(long long)(kb + k) * m + kb + r];
     }
     __syncthreads();
-    if (wv == 0) {
-      for (int k = 0; k < nb; ++k) {
-        T* col = P + k * ldp;
-        int bi;
-        R best, amax;
-        wave_pivot(col, k, p - kb, nr, lane, bi, best, amax);
-        if (lane == 0) {
-          T v = col[bi];
-          if (perturb(v, best, amax, tau)) {
-            col[bi] = v;
-            atomicOr(flag, 1);
-          }
-          s_piv[k] = bi;
-          ip[kb + k] = kb + bi;
+    // Panel LU on all NT threads: rows split over the workgroup, the pivot
+    // search reduced per wavefront and combined in LDS (largest |.|^2, ties to
+    // the lower row, as a single wavefront would choose).
+    for (int k = 0; k < nb; ++k) {
+      T* col = P + k * ldp;
+      R best = (R)-1, amax = (R)0;
+      int bi = k;
+      for (int r = k + tid; r < nr; r += NT) {
+        const R v = cabs2(col[r]);
+        amax = v > amax ? v : amax;
+        if (r < p - kb && v > best) {
+          best = v;
+          bi = r;
         }
-        wave_sync();
-        if (bi != k && lane < nb) {
-          T t0 = P[lane * ldp + k];
-          P[lane * ldp + k] = P[lane * ldp + bi];
-          P[lane * ldp + bi] = t0;
-        }
-        wave_sync();
-        const T dinv = cdiv(T{(R)1, (R)0}, col[k]);
-        for (int r = k + 1 + lane; r < nr; r += 64) {
-          T l = cmul(col[r], dinv);
-          col[r] = l;
-          for (int c = k + 1; c < nb; ++c) P[c * ldp + r] = cfms(l, P[c * ldp + k], P[c * ldp + r]);
-        }
-        wave_sync();
       }
+      for (int o = 32; o > 0; o >>= 1) {
+        const R ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        const R oa = __shfl_xor(amax, o, 64);
+        if (ob > best || (ob == best && oi < bi)) {
+          best = ob;
+          bi = oi;
+        }
+        amax = oa > amax ? oa : amax;
+      }
+      if (lane == 0) {
+        s_best[wv] = best;
+        s_amax[wv] = amax;
+        s_bi[wv] = bi;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        for (int w = 1; w < NT / 64; ++w) {
+          if (s_best[w] > best || (s_best[w] == best && s_bi[w] < bi)) {
+            best = s_best[w];
+            bi = s_bi[w];
+          }
+          amax = s_amax[w] > amax ? s_amax[w] : amax;
+        }
+        T v = col[bi];
+        if (perturb(v, best, amax, tau)) {
+          col[bi] = v;
+          atomicOr(flag, 1);
+        }
+        s_piv[k] = bi;
+        ip[kb + k] = kb + bi;
+      }
+      __syncthreads();
+      bi = s_piv[k];
+      if (bi != k && tid < nb) {
+        T t0 = P[tid * ldp + k];
+        P[tid * ldp + k] = P[tid * ldp + bi];
+        P[tid * ldp + bi] = t0;
+      }
+      __syncthreads();
+      const T dinv = cdiv(T{(R)1, (R)0}, col[k]);
+      for (int r = k + 1 + tid; r < nr; r += NT) {
+        T l = cmul(col[r], dinv);
+        col[r] = l;
+        for (int c = k + 1; c < nb; ++c) P[c * ldp + r] = cfms(l, P[c * ldp + k], P[c * ldp + r]);
+      }
+      __syncthreads();
     }
     __syncthreads();
     for (int t = tid; t < nb * nr; t += NT) {
@@ -424,28 +458,47 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       }
     }
     __syncthreads();
-    // Trailing update over rows/cols n0 .. m-1.
+    // Trailing update over rows/cols n0 .. m-1: (row, column group) threads
+    // over the whole workgroup, each with its row's nb multipliers in
+    // registers; the read-modify-writes of a thread go in batches of TB
+    // columns, so that each batch costs one memory round trip.
     const int n0 = kb + nb;
-    for (int r0 = n0; r0 < m; r0 += NT) {
-      const int r = r0 + tid;
-      T lr[NB];
+    const int R = m - n0;
+    if (R > 0) {
+      constexpr int TB = 8;
+      const int RT = R < NT ? R : NT;            // rows per pass
+      const int G = NT / RT, g = tid / RT, rr = tid - g * RT;
+      for (int r0 = n0; r0 < m; r0 += RT) {
+        const int r = r0 + rr;
+        const bool act = g < G && r < m;
+        const T* Pr = P + (r - kb);                 // this row's multipliers, stride ldp
+        for (int c0 = n0; c0 < m; c0 += UC) {
+          const int cw = min(UC, m - c0);
+          __syncthreads();
+          for (int t = tid; t < cw * NB; t += NT) {
+            int c = t / NB, k = t - c * NB;
+            Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
+          }
+          __syncthreads();
+          if (act) {
+            for (int cb = g; cb < cw; cb += G * TB) {
+              T acc[TB];
 #pragma unroll
-      for (int t = 0; t < NB; ++t) lr[t] = (t < nb && r < m) ? P[t * ldp + (r - kb)] : czero<T>();
-      for (int c0 = n0; c0 < m; c0 += UC) {
-        const int cw = min(UC, m - c0);
-        __syncthreads();
-        for (int t = tid; t < cw * NB; t += NT) {
-          int c = t / NB, k = t - c * NB;
-          Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
-        }
-        __syncthreads();
-        if (r < m) {
-          for (int c = 0; c < cw; ++c) {
-            T* dst = F + (long long)(c0 + c) * m + r;
-            T acc = *dst;
+              for (int u = 0; u < TB; ++u) {
+                const int c = cb + G * u;
+                acc[u] = c < cw ? F[(long long)(c0 + c) * m + r] : czero<T>();
+              }
+              for (int t = 0; t < nb; ++t) {
+                const T l = Pr[t * ldp];
 #pragma unroll
-            for (int t = 0; t < NB; ++t) acc = cfms(lr[t], Us[c][t], acc);
-            *dst = acc;
+                for (int u = 0; u < TB; ++u) acc[u] = cfms(l, Us[min(cb + G * u, UC - 1)][t], acc[u]);
+              }
+#pragma unroll
+              for (int u = 0; u < TB; ++u) {
+                const int c = cb + G * u;
+                if (c < cw) F[(long long)(c0 + c) * m + r] = acc[u];
+              }
+            }
           }
         }
       }
