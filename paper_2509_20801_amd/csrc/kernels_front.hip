@@ -284,6 +284,28 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   }
 }
 
+// 16 x 16 x 4 matrix-core products (D = A B + C) in the precision of the front.
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; output element (i, j)
+// of the 16 x 16 tile sits in lane j + 16 (i / 4), register i % 4 for FP32 and in
+// lane j + 16 (i % 4), register i / 4 for FP64.
+template <typename T> struct Mma;
+template <> struct Mma<float2> {
+  typedef float R;
+  typedef float V __attribute__((ext_vector_type(4)));
+  static __device__ inline V mma(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int l, int v) { return 4 * (l >> 4) + v; }
+};
+template <> struct Mma<double2> {
+  typedef double R;
+  typedef double V __attribute__((ext_vector_type(4)));
+  static __device__ inline V mma(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ inline int row(int l, int v) { return (l >> 4) + 4 * v; }
+};
+
 // One step of folding the per-block sweep operators of a large separator into
 // full ones, on the columns [c0, c1) (at most DIB) of F, by the phase of the
 // diagonal block [k0, k1) (its inverse on the diagonal, M' below, N' above):
@@ -458,45 +480,85 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       }
     }
     __syncthreads();
-    // Trailing update over rows/cols n0 .. m-1: (row, column group) threads
-    // over the whole workgroup, each with its row's nb multipliers in
-    // registers; the read-modify-writes of a thread go in batches of TB
-    // columns, so that each batch costs one memory round trip.
+    // Trailing update F22 -= L21 U12 over rows/cols n0 .. m-1 on the matrix
+    // cores: 16 x 16 complex tiles of F22, one wavefront per tile, the
+    // multipliers from the LDS panel and U12 staged in LDS UC columns at a
+    // time; four real products per complex K-step of four.
     const int n0 = kb + nb;
     const int R = m - n0;
-    if (R > 0) {
+    if (R > 0 && R < 128) {
+      // Small trailing blocks: (row, column group) threads over the whole
+      // workgroup, read-modify-writes in batches of TB columns.
       constexpr int TB = 8;
-      const int RT = R < NT ? R : NT;            // rows per pass
-      const int G = NT / RT, g = tid / RT, rr = tid - g * RT;
-      for (int r0 = n0; r0 < m; r0 += RT) {
-        const int r = r0 + rr;
-        const bool act = g < G && r < m;
-        const T* Pr = P + (r - kb);                 // this row's multipliers, stride ldp
-        for (int c0 = n0; c0 < m; c0 += UC) {
-          const int cw = min(UC, m - c0);
-          __syncthreads();
-          for (int t = tid; t < cw * NB; t += NT) {
-            int c = t / NB, k = t - c * NB;
-            Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
+      const int G = NT / R, g = tid / R, rr = tid - g * R;
+      const int r = n0 + rr;
+      const T* Pr = P + (r - kb);
+      for (int c0 = n0; c0 < m; c0 += UC) {
+        const int cw = min(UC, m - c0);
+        __syncthreads();
+        for (int t = tid; t < cw * NB; t += NT) {
+          int c = t / NB, k = t - c * NB;
+          Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
+        }
+        __syncthreads();
+        if (g < G) {
+          for (int cb = g; cb < cw; cb += G * TB) {
+            T acc[TB];
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+              const int c = cb + G * u;
+              acc[u] = c < cw ? F[(long long)(c0 + c) * m + r] : czero<T>();
+            }
+            for (int t = 0; t < nb; ++t) {
+              const T l = Pr[t * ldp];
+#pragma unroll
+              for (int u = 0; u < TB; ++u) acc[u] = cfms(l, Us[min(cb + G * u, UC - 1)][t], acc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < TB; ++u) {
+              const int c = cb + G * u;
+              if (c < cw) F[(long long)(c0 + c) * m + r] = acc[u];
+            }
           }
-          __syncthreads();
-          if (act) {
-            for (int cb = g; cb < cw; cb += G * TB) {
-              T acc[TB];
+        }
+      }
+    } else if (R > 0) {
+      using M = Mma<T>;
+      using MR = typename M::R;
+      const int l16 = lane & 15, lk = lane >> 4;
+      const int ntr = (R + 15) / 16;
+      for (int c0 = n0; c0 < m; c0 += UC) {
+        const int cw = min(UC, m - c0);
+        __syncthreads();
+        for (int t = tid; t < cw * NB; t += NT) {
+          int c = t / NB, k = t - c * NB;
+          Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
+        }
+        __syncthreads();
+        const int ntc = (cw + 15) / 16;
+        for (int tt = wv; tt < ntr * ntc; tt += NT / 64) {
+          const int rb = n0 + 16 * (tt / ntc), cb = 16 * (tt % ntc);
+          typename M::V accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+          const int ra = rb + l16, cbb = cb + l16;
+          for (int k0 = 0; k0 < nb; k0 += 4) {
+            const int kk = k0 + lk;
+            const T av = (kk < nb && ra < m) ? P[kk * ldp + (ra - kb)] : czero<T>();
+            const T bv = (kk < nb && cbb < cw) ? Us[cbb][kk] : czero<T>();
+            accr = M::mma((MR)av.x, (MR)bv.x, accr);
+            accr = M::mma((MR)-av.y, (MR)bv.y, accr);
+            acci = M::mma((MR)av.x, (MR)bv.y, acci);
+            acci = M::mma((MR)av.y, (MR)bv.x, acci);
+          }
+          if (cbb < cw) {
+            T* Fc = F + (long long)(c0 + cbb) * m;
 #pragma unroll
-              for (int u = 0; u < TB; ++u) {
-                const int c = cb + G * u;
-                acc[u] = c < cw ? F[(long long)(c0 + c) * m + r] : czero<T>();
-              }
-              for (int t = 0; t < nb; ++t) {
-                const T l = Pr[t * ldp];
-#pragma unroll
-                for (int u = 0; u < TB; ++u) acc[u] = cfms(l, Us[min(cb + G * u, UC - 1)][t], acc[u]);
-              }
-#pragma unroll
-              for (int u = 0; u < TB; ++u) {
-                const int c = cb + G * u;
-                if (c < cw) F[(long long)(c0 + c) * m + r] = acc[u];
+            for (int v = 0; v < 4; ++v) {
+              const int r = rb + M::row(lane, v);
+              if (r < m) {
+                T x = Fc[r];
+                x.x -= accr[v];
+                x.y -= acci[v];
+                Fc[r] = x;
               }
             }
           }
