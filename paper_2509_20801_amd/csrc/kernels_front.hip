@@ -1256,6 +1256,9 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
   check_rhs(r);
   const int cap = sizeof(T) == 8 ? 32 : 16;      // registers per lane for the prefetch
   if (a.max_m <= 128 && a.max_p <= 64) {
+    // Wavefront kernels: at most 16 prefetched terms per lane (about 60
+    // registers), so that eight wavefronts per SIMD hide the gather latency.
+    const int cap = 16;
     // A lane row takes at most min(r, p) <= max_p columns.
     const int rpl = a.max_m <= 64 ? 1 : 2;
     const int kp = prefetch_depth(a.max_p, cap / rpl);
@@ -1284,6 +1287,7 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, 
   check_rhs(r);
   const int cap = sizeof(T) == 8 ? 32 : 16;
   if (a.max_m <= 128 && a.max_p <= 64) {
+    const int cap = 16;                          // as in the forward sweep
     // Row groups: W >= max_p lanes, so G >= 64 / W groups share a row's columns.
     int w = 4;
     while (w < a.max_p) w *= 2;
