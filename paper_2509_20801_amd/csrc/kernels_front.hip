@@ -270,9 +270,14 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
     }
   }
   wave_sync();
+  // Only the Schur complement F22 goes back to the front storage (the parent's
+  // extend-add reads it); the sweeps read the packed operators.
   T* F = fac + f.fac_off;
-  const long long mm = (long long)m * m;
-  for (long long t = lane; t < mm; t += 64) F[t] = G[t];
+  const int q = m - p;
+  for (int t = lane; t < q * q; t += 64) {
+    const int c = p + t / q, r = p + t % q;
+    F[(long long)c * m + r] = G[(long long)c * m + r];
+  }
   // Packed sweep operators.
   T* Lp = lpk + f.lpk_off;
   for (int k = 0; k < p; ++k)
