@@ -102,7 +102,8 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
 # that holds them (a PMC summary is valid only for the source it was taken on).
 CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "front_lu"),
             ("k_stencil", "stencil"), ("k_scatter", "scatter"), ("k_mdot", "arnoldi"),
-            ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi")]
+            ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi"),
+            ("k_gs", "arnoldi")]
 SOURCE_OF = {"sweep_fwd": "kernels_front.hip", "sweep_bwd": "kernels_front.hip",
              "front_lu": "kernels_front.hip", "scatter": "kernels_front.hip",
              "stencil": "kernels_stencil.hip", "arnoldi": "kernels_krylov.hip"}

@@ -425,7 +425,7 @@ void build_device_state(stf_problem pb) {
   pb->scal.alloc(sizeof(double) * 64);
   int nblk = std::max(stencil_partial_blocks(p.nx, p.ny), krylov_blocks(pb->N));
   pb->partial.alloc((size_t)nblk * sizeof(double2) * 4);
-  pb->npartial.alloc((size_t)krylov_blocks(pb->N) * sizeof(double));
+  pb->npartial.alloc((size_t)std::max(krylov_blocks(pb->N), gs_blocks(pb->N)) * sizeof(double));
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
@@ -571,7 +571,10 @@ void ensure_krylov(stf_problem pb, int m, int nr) {
   pb->kh2.alloc(sizeof(double2) * (m + 1));
   pb->scal.alloc(sizeof(double) * 16 * (nr + 1));
   int nblk = krylov_blocks(pb->N);
-  pb->partial.alloc(std::max<size_t>(pb->partial.bytes, (size_t)nblk * (m + 1) * sizeof(double2)));
+  size_t need = (size_t)nblk * (m + 1) * sizeof(double2);
+  const int stride = gs_stride(std::min(m + 1, 32));
+  need = std::max(need, (size_t)gs_blocks(pb->N) * stride * sizeof(double2));
+  pb->partial.alloc(std::max<size_t>(pb->partial.bytes, need));
   pb->krylov_m = m;
   pb->krylov_nr = nr;
 }
@@ -949,16 +952,30 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
         int* gate = pb->flag.as<int>() + 1;
         double2* h1 = pb->kh1.as<double2>();
         double2* h2 = pb->kh2.as<double2>();
-        launch_mdot(st, q.V, N, j + 1, w, N, part, npart, nullptr);
-        launch_mdot_reduce(st, part, nblk, j + 1, h1, nullptr);
-        launch_norm_reduce(st, npart, nblk, q.sc + 6, nullptr, nullptr, 0);
-        launch_mupdate(st, q.V, N, j + 1, h1, w, N, npart, nullptr);
-        launch_norm_reduce(st, npart, nblk, q.sc + 3, q.sc + 6, gate, 1);
-        launch_mdot(st, q.V, N, j + 1, w, N, part, nullptr, gate);
-        launch_mdot_reduce(st, part, nblk, j + 1, h2, gate);
-        launch_mupdate(st, q.V, N, j + 1, h2, w, N, npart, gate);
-        launch_norm_reduce(st, npart, nblk, q.sc + 3, nullptr, gate, 0);
-        launch_hacc(st, h1, h2, j + 1, gate);
+        const int nv = j + 1, stride = gs_stride(nv);
+        if (stride > 0) {
+          // The first pass's update and the second pass's products share one
+          // read of the basis (the products are discarded when the gate stays
+          // closed).
+          const int gb = gs_blocks(N);
+          launch_gs(st, GS_DOT, q.V, N, nv, nullptr, w, N, part, npart, nullptr);
+          launch_gs_reduce(st, part, gb, stride, nv, h1, npart, q.sc + 6, nullptr, nullptr);
+          launch_gs(st, GS_UPDATE_DOT, q.V, N, nv, h1, w, N, part, npart, nullptr);
+          launch_gs_reduce(st, part, gb, stride, nv, h2, npart, q.sc + 3, q.sc + 6, gate);
+          launch_gs(st, GS_UPDATE, q.V, N, nv, h2, w, N, part, npart, gate);
+          launch_gs_final(st, npart, gb, q.sc + 3, h1, h2, nv, gate);
+        } else {
+          launch_mdot(st, q.V, N, nv, w, N, part, npart, nullptr);
+          launch_mdot_reduce(st, part, nblk, nv, h1, nullptr);
+          launch_norm_reduce(st, npart, nblk, q.sc + 6, nullptr, nullptr, 0);
+          launch_mupdate(st, q.V, N, nv, h1, w, N, npart, nullptr);
+          launch_norm_reduce(st, npart, nblk, q.sc + 3, q.sc + 6, gate, 1);
+          launch_mdot(st, q.V, N, nv, w, N, part, nullptr, gate);
+          launch_mdot_reduce(st, part, nblk, nv, h2, gate);
+          launch_mupdate(st, q.V, N, nv, h2, w, N, npart, gate);
+          launch_norm_reduce(st, npart, nblk, q.sc + 3, nullptr, gate, 0);
+          launch_hacc(st, h1, h2, nv, gate);
+        }
       }
       {
         Timed t(c, K_UPDATE);

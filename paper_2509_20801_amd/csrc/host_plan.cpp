@@ -271,6 +271,9 @@ std::shared_ptr<SymShape> build_symbolic(int nxl, int nyl, int leaf) {
   }
   for (const SymFront& f : sh->fronts) {
     int64_t m = f.p + f.q;
+    // Front kernels index a front's entries (and a child's Schur complement)
+    // with 32-bit products m*m.
+    STF_REQUIRE(m <= 46340, "front order above 46340: subdomain too large");
     sh->max_depth = std::max(sh->max_depth, f.depth);
     sh->max_front = std::max<int>(sh->max_front, (int)m);
     sh->factor_entries += (int64_t)f.p * f.p + 2 * (int64_t)f.p * f.q;

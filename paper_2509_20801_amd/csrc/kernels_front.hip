@@ -100,17 +100,33 @@ __device__ inline void assemble_front(const LevelArgs& a, const T* __restrict__ 
     G[(long long)c * m + r] = from_d2<T>(local_coef(a, s, e.nd >> 3, e.nd & 7));
   }
   sync();
+  // Extend-add: the child map is injective, so the entries of one child go to
+  // distinct places and a thread takes UB of them per round trip (all loads of
+  // the batch, then all read-modify-writes).
+  constexpr int UB = 8;
   for (int ci = 0; ci < f.nchild; ++ci) {
     const FrontDev cf = a.fronts[a.children[f.child_off + ci]];
     const int mc = cf.p + cf.q, q = cf.q;
     const T* S = fac + cf.fac_off + (long long)cf.p * mc + cf.p;   // F22 of the child
     const int* cm = a.cmap + cf.cmap_off;
-    const long long qq = (long long)q * q;
-    for (long long t = tid; t < qq; t += nthr) {
-      int j = (int)(t / q), i = (int)(t - (long long)j * q);        // (i, j) of S, i fastest
-      T v = S[(long long)j * mc + i];
-      T* d = G + (long long)cm[j] * m + cm[i];
-      *d = cadd(*d, v);
+    const int qq = q * q;
+    for (int t0 = tid; t0 < qq; t0 += nthr * UB) {
+      T v[UB];
+      long long d[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) {
+        const int t = t0 + u * nthr;
+        const int j = t / q, i = t - j * q;                          // (i, j) of S, i fastest
+        const bool ok = t < qq;
+        v[u] = ok ? S[(long long)j * mc + i] : czero<T>();
+        d[u] = ok ? (long long)cm[j] * m + cm[i] : -1;
+      }
+      T g[UB];
+#pragma unroll
+      for (int u = 0; u < UB; ++u) g[u] = d[u] >= 0 ? G[d[u]] : czero<T>();
+#pragma unroll
+      for (int u = 0; u < UB; ++u)
+        if (d[u] >= 0) G[d[u]] = cadd(g[u], v[u]);
     }
     sync();
   }
@@ -310,6 +326,40 @@ template <> struct Mma<double2> {
   }
   static __device__ inline int row(int l, int v) { return (l >> 4) + 4 * v; }
 };
+
+// D = -A B over 16 x 16 complex tiles on the matrix cores, the tiles dealt to
+// the nw wavefronts of the workgroup: rows [0, R), columns [0, C), inner index
+// [0, K).  a(r, k) and b(k, c) return the operands (zero outside the triangle
+// they describe); st(r, c, v) stores one result.
+template <typename T, typename FA, typename FB, typename FS>
+__device__ inline void mma_neg_product(int R, int C, int K, FA a, FB b, FS st, int wv, int nw,
+                                       int lane) {
+  using M = Mma<T>;
+  using MR = typename M::R;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int ntr = (R + 15) / 16, ntc = (C + 15) / 16;
+  for (int tt = wv; tt < ntr * ntc; tt += nw) {
+    const int rb = 16 * (tt / ntc), cb = 16 * (tt % ntc);
+    typename M::V accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+    const int ra = rb + l16, cc = cb + l16;
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int kk = k0 + lk;
+      const T av = (ra < R && kk < K) ? a(ra, kk) : czero<T>();
+      const T bv = (cc < C && kk < K) ? b(kk, cc) : czero<T>();
+      accr = M::mma((MR)av.x, (MR)bv.x, accr);
+      accr = M::mma((MR)-av.y, (MR)bv.y, accr);
+      acci = M::mma((MR)av.x, (MR)bv.y, acci);
+      acci = M::mma((MR)av.y, (MR)bv.x, acci);
+    }
+    if (cc < C) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int r = rb + M::row(lane, v);
+        if (r < R) st(r, cc, T{-accr[v], -acci[v]});
+      }
+    }
+  }
+}
 
 // One step of folding the per-block sweep operators of a large separator into
 // full ones, on the columns [c0, c1) (at most DIB) of F, by the phase of the
@@ -602,12 +652,13 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
         Cb[j * CR + rr] = F[(long long)(j0 + j) * m + r0 + rr];
       }
       __syncthreads();
-      for (int t = tid; t < rows * nbk; t += NT) {
-        int j = t / rows, rr = t - j * rows;
-        T acc = Cb[j * CR + rr];
-        for (int kk = j + 1; kk < nbk; ++kk) acc = cfma(Cb[kk * CR + rr], Db[j * DIB + kk], acc);
-        F[(long long)(j0 + j) * m + r0 + rr] = T{-acc.x, -acc.y};
-      }
+      // [rows x nbk] = -C Linv_J (unit diagonal implicit)
+      mma_neg_product<T>(
+          rows, nbk, nbk, [&](int r, int k) { return Cb[k * CR + r]; },
+          [&](int k, int c) {
+            return k == c ? T{(R)1, (R)0} : (k > c ? Db[c * DIB + k] : czero<T>());
+          },
+          [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NT / 64, lane);
     }
     // N'_J = -U[0:j0, J] Uinv_J, 64 rows at a time.
     for (int r0 = 0; r0 < j0; r0 += CR) {
@@ -618,12 +669,11 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
         Cb[j * CR + rr] = F[(long long)(j0 + j) * m + r0 + rr];
       }
       __syncthreads();
-      for (int t = tid; t < rows * nbk; t += NT) {
-        int j = t / rows, rr = t - j * rows;
-        T acc = czero<T>();
-        for (int kk = 0; kk <= j; ++kk) acc = cfma(Cb[kk * CR + rr], Db[j * DIB + kk], acc);
-        F[(long long)(j0 + j) * m + r0 + rr] = T{-acc.x, -acc.y};
-      }
+      // [rows x nbk] = -C Uinv_J
+      mma_neg_product<T>(
+          rows, nbk, nbk, [&](int r, int k) { return Cb[k * CR + r]; },
+          [&](int k, int c) { return k <= c ? Db[c * DIB + k] : czero<T>(); },
+          [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NT / 64, lane);
     }
     // A single-block front also gets V' = -U11^{-1} U12 (64 columns at a time).
     if (p <= DIB) {
@@ -635,12 +685,11 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
           Cb[c * DIB + r] = F[(long long)(c0 + c) * m + r];
         }
         __syncthreads();
-        for (int t = tid; t < cols * p; t += NT) {
-          int c = t / p, r = t - c * p;
-          T acc = czero<T>();
-          for (int kk = r; kk < p; ++kk) acc = cfma(Db[kk * DIB + r], Cb[c * DIB + kk], acc);
-          F[(long long)(c0 + c) * m + r] = T{-acc.x, -acc.y};
-        }
+        // [p x cols] = -Uinv U12
+        mma_neg_product<T>(
+            p, cols, p, [&](int r, int k) { return k >= r ? Db[k * DIB + r] : czero<T>(); },
+            [&](int k, int c) { return Cb[c * DIB + k]; },
+            [&](int r, int c, T v) { F[(long long)(c0 + c) * m + r] = v; }, wv, NT / 64, lane);
       }
     }
     __syncthreads();

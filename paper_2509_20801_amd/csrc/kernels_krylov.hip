@@ -86,16 +86,16 @@ __global__ __launch_bounds__(KT) void k_mdot(const double2* __restrict__ V, long
   }
 }
 
-// h[i] = sum_b partial[b][i] in a fixed order (skipped unless *gate when gated).
+// h[i] = sum_b partial[b * stride + i] in a fixed order (skipped unless *gate when gated).
 __global__ __launch_bounds__(KT) void k_mdot_reduce(const double2* __restrict__ partial, int nblk,
-                                                    int nv, double2* __restrict__ h,
+                                                    int stride, double2* __restrict__ h,
                                                     const int* __restrict__ gate) {
   __shared__ double red[4];
   if (gate && gate[0] == 0) return;
   const int i = blockIdx.x;
   double sr = 0.0, si = 0.0;
   for (int b = threadIdx.x; b < nblk; b += KT) {
-    double2 v = partial[(long long)b * nv + i];
+    double2 v = partial[(long long)b * stride + i];
     sr += v.x;
     si += v.y;
   }
@@ -150,6 +150,90 @@ __global__ __launch_bounds__(KT) void k_mupdate(const double2* __restrict__ V, l
   }
 }
 
+// Register-resident Gram-Schmidt passes for bases of at most 32 vectors: one
+// entry per thread (coalesced, a fine grid that balances over the CUs), all
+// nv basis entries loaded at once into registers.  UPD: w -= V h; DOT: the
+// partial products V^H w of the (updated) entries, written as
+// partial[blk][NVM] (complex); always the partial |w|^2.  With UPD and DOT
+// together one read of the basis serves the update of the first pass and the
+// products of the second.
+//
+// The per-wave sums of the 2*NVM real values use a folding transpose: at each
+// exchange a lane keeps one half of its values and adds the partner's other
+// half, so after log2(2*NVM) exchanges lane l holds the sum of value
+// l >> (6 - log2(2*NVM)) over its lane group (63 exchanges for 64 values
+// instead of 384 for separate butterflies).
+// One exchange of the fold on the first K values (offset O), then the next.
+// Recursion on compile-time K keeps every index constant, so the values stay
+// in registers.
+template <int KT_, int K, int O> __device__ inline void fold_rec(double* a, int lane) {
+  if constexpr (K > 1) {
+    const bool up = (lane & O) != 0;
+#pragma unroll
+    for (int i = 0; i < K / 2; ++i) {
+      const double send = up ? a[i] : a[i + K / 2];
+      const double keep = up ? a[i + K / 2] : a[i];
+      a[i] = keep + __shfl_xor(send, O, 64);
+    }
+    fold_rec<KT_, K / 2, O / 2>(a, lane);
+  }
+}
+template <int K> __device__ inline double wave_fold(double (&a)[K], int lane) {
+  static_assert(K >= 2 && K <= 64 && (K & (K - 1)) == 0, "K must be a power of two <= 64");
+  fold_rec<K, K, 32>(a, lane);
+  double s = a[0];
+#pragma unroll
+  for (int o = 32 / K; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  return s;
+}
+
+template <int NVM, bool UPD, bool DOT>
+__global__ __launch_bounds__(KT) void k_gs(const double2* __restrict__ V, long long ld, int nv,
+                                           const double2* __restrict__ h,
+                                           double2* __restrict__ w, long long n,
+                                           double* __restrict__ partial,
+                                           double* __restrict__ norm_partial,
+                                           const int* __restrict__ gate) {
+  constexpr int K = 2 * NVM;
+  __shared__ double2 hs[NVM];
+  __shared__ double red[4][K];
+  __shared__ double nred[4];
+  if (gate && gate[0] == 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (UPD && tid < nv) hs[tid] = h[tid];
+  const long long idx = (long long)blockIdx.x * KT + tid;
+  const bool in = idx < n;
+  double2 v[NVM];
+#pragma unroll
+  for (int i = 0; i < NVM; ++i)
+    v[i] = (in && i < nv) ? V[(long long)i * ld + idx] : make_double2(0.0, 0.0);
+  double2 wr = in ? w[idx] : make_double2(0.0, 0.0);
+  if (UPD) {
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NVM; ++i)
+      if (i < nv) wr = cfms(v[i], hs[i], wr);
+    if (in) w[idx] = wr;
+  }
+  if (DOT) {
+    double a[K];
+#pragma unroll
+    for (int i = 0; i < NVM; ++i) {
+      a[2 * i] = fma(v[i].y, wr.y, v[i].x * wr.x);         // conj(v) * w
+      a[2 * i + 1] = fma(-v[i].y, wr.x, v[i].x * wr.y);
+    }
+    const double s = wave_fold<K>(a, lane);
+    constexpr int G = 64 / K;                              // lanes per value
+    if ((lane & (G - 1)) == 0) red[wv][lane / G] = s;
+  }
+  const double nr = wave_sum(wr.x * wr.x + wr.y * wr.y);
+  if (lane == 0) nred[wv] = nr;
+  __syncthreads();
+  if (DOT && tid < K)
+    partial[(long long)blockIdx.x * K + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  if (tid == 0) norm_partial[blockIdx.x] = (nred[0] + nred[1]) + (nred[2] + nred[3]);
+}
+
 // Fixed-order sum of n partials into out[0].  With `decide`: out holds the
 // new |w|^2 and ref[0] the |w|^2 before the update; gate[0] is set to 1 when
 // the update cancelled more than half of the norm squared (re-orthogonalise),
@@ -167,6 +251,55 @@ __global__ __launch_bounds__(KT) void k_norm_reduce(const double* __restrict__ p
     out[0] = s;
     if (decide) gate[0] = (s < 0.5 * ref[0]) ? 1 : 0;
   }
+}
+
+// The reductions between the register Gram-Schmidt passes, one launch each.
+// Blocks 0..nv-1: h[i] = sum_b partial[b * stride + i] in a fixed order;
+// block nv: out[0] = sum of the nblk norm partials and, with ref, the
+// re-orthogonalisation gate (out < ref/2).
+__global__ __launch_bounds__(KT) void k_gs_reduce(const double2* __restrict__ partial, int nblk,
+                                                  int stride, int nv, double2* __restrict__ h,
+                                                  const double* __restrict__ npart,
+                                                  double* __restrict__ out,
+                                                  const double* __restrict__ ref,
+                                                  int* __restrict__ gate) {
+  __shared__ double red[4];
+  const int i = blockIdx.x;
+  if (i < nv) {
+    double sr = 0.0, si = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += KT) {
+      const double2 v = partial[(long long)b * stride + i];
+      sr += v.x;
+      si += v.y;
+    }
+    sr = block_sum(sr, red);
+    si = block_sum(si, red);
+    if (threadIdx.x == 0) h[i] = make_double2(sr, si);
+  } else {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += KT) s += npart[b];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) {
+      out[0] = s;
+      if (ref) gate[0] = (s < 0.5 * ref[0]) ? 1 : 0;
+    }
+  }
+}
+
+// After a second pass (gate[0] != 0 only): out[0] = sum of the norm partials
+// and h1 += h2.
+__global__ __launch_bounds__(KT) void k_gs_final(const double* __restrict__ npart, int nblk,
+                                                 double* __restrict__ out, double2* __restrict__ h1,
+                                                 const double2* __restrict__ h2, int nv,
+                                                 const int* __restrict__ gate) {
+  __shared__ double red[4];
+  if (gate[0] == 0) return;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += KT) s += npart[b];
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) out[0] = s;
+  for (int i = threadIdx.x; i < nv; i += KT)
+    h1[i] = make_double2(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
 }
 
 // h1 += h2 when gate[0] != 0 (accumulates the re-orthogonalisation coefficients).
@@ -286,8 +419,50 @@ void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const d
 }
 
 void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h,
-                        const int* gate) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk, nv, h, gate);
+                        const int* gate, int stride) {
+  hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk,
+                     stride > 0 ? stride : nv, h, gate);
+}
+
+int gs_blocks(long long n) { return (int)((n + KT - 1) / KT); }
+
+int gs_stride(int nv) { return nv <= 8 ? 8 : nv <= 16 ? 16 : nv <= 32 ? 32 : 0; }
+
+void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
+                      double2* h, const double* npart, double* out, const double* ref, int* gate) {
+  hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(KT), 0, st, partial, nblk, stride, nv, h,
+                     npart, out, ref, gate);
+}
+
+void launch_gs_final(hipStream_t st, const double* npart, int nblk, double* out, double2* h1,
+                     const double2* h2, int nv, const int* gate) {
+  hipLaunchKernelGGL(k_gs_final, dim3(1), dim3(KT), 0, st, npart, nblk, out, h1, h2, nv, gate);
+}
+
+void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
+               double2* w, long long n, double2* partial, double* norm_partial, const int* gate) {
+  const int nvm = gs_stride(nv);
+  STF_REQUIRE(nvm > 0 && nv >= 1, "register Gram-Schmidt pass takes 1..32 basis vectors");
+  STF_REQUIRE(mode >= GS_DOT && mode <= GS_UPDATE, "unknown Gram-Schmidt pass");
+  double* pd = reinterpret_cast<double*>(partial);
+  const dim3 g(gs_blocks(n)), b(KT);
+#define STF_GS_CASE(M)                                                                         \
+  if (nvm == M) {                                                                              \
+    if (mode == GS_DOT)                                                                        \
+      hipLaunchKernelGGL((k_gs<M, false, true>), g, b, 0, st, V, ld, nv, h, w, n, pd,          \
+                         norm_partial, gate);                                                  \
+    else if (mode == GS_UPDATE_DOT)                                                            \
+      hipLaunchKernelGGL((k_gs<M, true, true>), g, b, 0, st, V, ld, nv, h, w, n, pd,           \
+                         norm_partial, gate);                                                  \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_gs<M, true, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,          \
+                         norm_partial, gate);                                                  \
+    return;                                                                                    \
+  }
+  STF_GS_CASE(8)
+  STF_GS_CASE(16)
+  STF_GS_CASE(32)
+#undef STF_GS_CASE
 }
 
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,

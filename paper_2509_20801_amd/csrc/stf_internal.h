@@ -220,8 +220,26 @@ int krylov_blocks(long long n);
 // gated kernels run only when *gate != 0 (gate may be null).
 void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const double2* w,
                  long long n, double2* partial, double* norm_partial, const int* gate);
+// h[i] = sum_b partial[b * stride + i] for i < nv (stride 0 means nv).
 void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h,
-                        const int* gate);
+                        const int* gate, int stride = 0);
+// Register-resident Gram-Schmidt passes over bases of 1..32 vectors (one entry
+// per thread, gs_blocks(n) workgroups; partials [blk][gs_stride(nv)]).
+//   GS_DOT:        partial = V^H w, |w|^2 partials
+//   GS_UPDATE_DOT: w -= V h, then partial = V^H w and |w|^2 of the new w
+//   GS_UPDATE:     w -= V h, |w|^2 partials
+enum { GS_DOT = 0, GS_UPDATE_DOT = 1, GS_UPDATE = 2 };
+int gs_blocks(long long n);
+int gs_stride(int nv);    // 8, 16 or 32; 0 when nv > 32 (use launch_mdot / launch_mupdate)
+void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
+               double2* w, long long n, double2* partial, double* norm_partial, const int* gate);
+// Between the passes: h[i] = sum_b partial[b * stride + i] (i < nv) and
+// out = sum of the nblk norm partials, with ref also gate = (out < ref/2).
+void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
+                      double2* h, const double* npart, double* out, const double* ref, int* gate);
+// After the gated second pass: out = sum of norm partials, h1 += h2.
+void launch_gs_final(hipStream_t st, const double* npart, int nblk, double* out, double2* h1,
+                     const double2* h2, int nv, const int* gate);
 // w -= V h (+ |w|^2 partials).
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
                     double2* w, long long n, double* norm_partial, const int* gate);
