@@ -985,35 +985,89 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   ColPrefetch<T, KP> pf;
   pf.load(L, LowerAt{m, rr}, g, 0, act ? min(rr, p) : 0, G);
   const SubDev sd = a.subs[f.sub];
-  for (int i = tid; i < m; i += NTL) {
-    long long gidx = -1;
-    if (i < p) {
-      int node = a.vars[f.var_off + i];
-      int gx = sd.ox0 + node % sd.nxl, gy = sd.oy0 + node / sd.nxl;
-      if (gx >= sd.ix0 && gx < sd.ix1 && gy >= sd.iy0 && gy < sd.iy1) gidx = (long long)gy * a.nx + gx;
-    }
-#pragma unroll
-    for (int s = 0; s < NR; ++s) vl[s * mm + i] = gidx >= 0 ? from_d2<T>(rs.v[s][gidx]) : czero<T>();
-  }
-  __syncthreads();
-#pragma unroll
-  for (int c = 0; c < 2; ++c) {
-    if (f.nchild > c) {
-      const int* cm = a.cmap + f.ccmap[c];
-      for (int i = tid; i < f.cq[c]; i += NTL) {
-        const int d = cm[i];
-#pragma unroll
-        for (int s = 0; s < NR; ++s)
-          vl[s * mm + d] = cadd(vl[s * mm + d], vec[s * rs.vec_stride + f.cvec[c] + i]);
-      }
-      __syncthreads();
-    }
-  }
   const int* perm = piv + f.piv_off;
-  for (int i = tid; i < p; i += NTL) {
-    const int src = perm[i];
+  auto global_row = [&](int i) -> long long {
+    const int node = a.vars[f.var_off + i];
+    const int gx = sd.ox0 + node % sd.nxl, gy = sd.oy0 + node / sd.nxl;
+    return (gx >= sd.ix0 && gx < sd.ix1 && gy >= sd.iy0 && gy < sd.iy1) ? (long long)gy * a.nx + gx
+                                                                         : -1;
+  };
+  if (m <= 2 * NTL) {
+    // Every global load of the right-hand side first (two rows per thread),
+    // so that the chains (index -> value) of R^I v, of both children's update
+    // vectors and of the pivots overlap; then the extend-add in LDS.
+    long long gidx[2];
+    int d0[2], d1[2], pv[2];
 #pragma unroll
-    for (int s = 0; s < NR; ++s) tmp[s * mm + i] = vl[s * mm + src];
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + u * NTL;
+      gidx[u] = i < p ? global_row(i) : -1;
+      d0[u] = (f.nchild > 0 && i < f.cq[0]) ? a.cmap[f.ccmap[0] + i] : -1;
+      d1[u] = (f.nchild > 1 && i < f.cq[1]) ? a.cmap[f.ccmap[1] + i] : -1;
+      pv[u] = i < p ? perm[i] : -1;
+    }
+    T bv[2][NR], c0[2][NR], c1[2][NR];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + u * NTL;
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        const T* vs = vec + s * rs.vec_stride;
+        bv[u][s] = gidx[u] >= 0 ? from_d2<T>(rs.v[s][gidx[u]]) : czero<T>();
+        c0[u][s] = d0[u] >= 0 ? vs[f.cvec[0] + i] : czero<T>();
+        c1[u][s] = d1[u] >= 0 ? vs[f.cvec[1] + i] : czero<T>();
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + u * NTL;
+      if (i < m)
+#pragma unroll
+        for (int s = 0; s < NR; ++s) vl[s * mm + i] = bv[u][s];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (d0[u] >= 0)
+#pragma unroll
+        for (int s = 0; s < NR; ++s) vl[s * mm + d0[u]] = cadd(vl[s * mm + d0[u]], c0[u][s]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (d1[u] >= 0)
+#pragma unroll
+        for (int s = 0; s < NR; ++s) vl[s * mm + d1[u]] = cadd(vl[s * mm + d1[u]], c1[u][s]);
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+      if (pv[u] >= 0)
+#pragma unroll
+        for (int s = 0; s < NR; ++s) tmp[s * mm + tid + u * NTL] = vl[s * mm + pv[u]];
+  } else {
+    for (int i = tid; i < m; i += NTL) {
+      const long long gi = i < p ? global_row(i) : -1;
+#pragma unroll
+      for (int s = 0; s < NR; ++s) vl[s * mm + i] = gi >= 0 ? from_d2<T>(rs.v[s][gi]) : czero<T>();
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (f.nchild > c) {
+        const int* cm = a.cmap + f.ccmap[c];
+        for (int i = tid; i < f.cq[c]; i += NTL) {
+          const int d = cm[i];
+#pragma unroll
+          for (int s = 0; s < NR; ++s)
+            vl[s * mm + d] = cadd(vl[s * mm + d], vec[s * rs.vec_stride + f.cvec[c] + i]);
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = tid; i < p; i += NTL) {
+      const int src = perm[i];
+#pragma unroll
+      for (int s = 0; s < NR; ++s) tmp[s * mm + i] = vl[s * mm + src];
+    }
   }
   __syncthreads();
   for (int i = tid; i < p; i += NTL)
@@ -1066,6 +1120,8 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   const bool act = g < G && rr < p;
   ColPrefetch<T, KP> pf;
   pf.load(U, UpperAt{p, rr}, g, rr, act ? m : 0, G);
+  const int* vars = a.vars + f.var_off;
+  const int var = tid < p ? vars[tid] : 0;       // the row this thread stores (issued early)
   for (int i = tid; i < p; i += NTL)
 #pragma unroll
     for (int s = 0; s < NR; ++s) vl[s * mm + i] = vec[s * rs.vec_stride + f.vec_off + i];
@@ -1078,7 +1134,6 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
     }
   }
   __syncthreads();
-  const int* vars = a.vars + f.var_off;
   const long long uo = a.subs[f.sub].u_off;
   T acc[NR];
 #pragma unroll
@@ -1089,7 +1144,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
       T* fv = vec + s * rs.vec_stride + f.vec_off;
       if (act) {
         fv[rr] = acc[s];
-        u[s * rs.u_stride + uo + vars[rr]] = acc[s];
+        u[s * rs.u_stride + uo + var] = acc[s];
       }
       for (int r = tid + NTL; r < p; r += NTL) {
         const T x = gather_dot(U, UpperAt{p, r}, 0, r, m, 1, vl + s * mm);
@@ -1107,7 +1162,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
         T sum = czero<T>();
         for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * p + tid]);
         vec[s * rs.vec_stride + f.vec_off + tid] = sum;
-        u[s * rs.u_stride + uo + vars[tid]] = sum;
+        u[s * rs.u_stride + uo + var] = sum;
       }
     }
   }

@@ -56,17 +56,23 @@ def metasurface():
     return w, A, ref
 
 
-@pytest.mark.parametrize("prec,tol,bar", [(1, 1e-10, 1e-8), (0, 1e-12, 1e-10)])
-def test_metasurface_full_size_matches_direct_solve(stf, ctx, metasurface, prec, tol, bar):
+# restart 100: one Arnoldi cycle runs past 32 basis vectors, so both the
+# register Gram-Schmidt passes (bases of up to 32 vectors) and the general ones
+# take part in the same solve.
+@pytest.mark.parametrize("prec,tol,bar,restart", [(1, 1e-10, 1e-8, 20), (0, 1e-12, 1e-10, 20),
+                                                  (1, 1e-10, 1e-8, 100)])
+def test_metasurface_full_size_matches_direct_solve(stf, ctx, metasurface, prec, tol, bar, restart):
     import torch
     w, A, ref = metasurface
     eps = torch.from_numpy(w.eps_cells).cuda()
     pb = stf.Problem(ctx, _prm(w, front_prec=prec), eps)
     pb.factor()
     b = torch.from_numpy(w.b[0]).cuda()
-    x, info = pb.solve(b, tol=tol, restart=20, max_iter=600)
+    x, info = pb.solve(b, tol=tol, restart=restart, max_iter=600)
     xh = x.cpu().numpy().ravel()
     assert info[0]["status"] == 0 and info[0]["relres_true"] <= tol
+    if restart > 32:
+        assert 33 < info[0]["iters"] <= restart, info[0]["iters"]
     # Property that holds at any size: the FP64 residual recomputed by the oracle.
     assert fdfd.relres(A, xh, w.b[0].ravel()) <= 1.5 * tol
     idx = np.array(ref["index"])
