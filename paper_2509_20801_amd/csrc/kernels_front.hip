@@ -368,20 +368,20 @@ __device__ inline void mma_neg_product(int R, int C, int K, FA a, FB b, FS st, i
 //   UPPER: rows r < k1:   X_r <- [r < k0] X_r + sum_{max(k0, r) <= k < k1} F[r,k] X_k
 // where X = F[:, c0:c1) and X_k (k in the block) is read from a copy staged in
 // LDS (Xs, DIB x DIB) before any write.  Begins with a workgroup barrier.
-template <typename T, bool LOWER>
+template <typename T, bool LOWER, int NTF>
 __device__ void fold_step(T* __restrict__ F, int m, int k0, int k1, int c0, int c1, T* Xs,
                           int tid) {
   constexpr int CC = 8;                       // columns per work item
   const int w = c1 - c0, wk = k1 - k0;
   __syncthreads();
-  for (int t = tid; t < wk * w; t += NT) {
+  for (int t = tid; t < wk * w; t += NTF) {
     int c = t / wk, k = t - c * wk;
     Xs[k * DIB + c] = F[(long long)(c0 + c) * m + k0 + k];
   }
   __syncthreads();
   const int rlo = LOWER ? k0 : 0, rhi = LOWER ? m : k1;
   const int R = rhi - rlo, nch = (w + CC - 1) / CC;
-  for (int t = tid; t < R * nch; t += NT) {
+  for (int t = tid; t < R * nch; t += NTF) {
     const int ch = t / R, r = rlo + (t - ch * R), cb = ch * CC;
     T acc[CC];
 #pragma unroll
@@ -402,14 +402,15 @@ __device__ void fold_step(T* __restrict__ F, int m, int k0, int k1, int c0, int 
 }
 
 // ---------------------------------------------------------------------------
-// Factorisation, large fronts: one 256-thread workgroup per front.  Assembly in
+// Factorisation, large fronts: one workgroup of NTF threads per front (256, or
+// 1024 for levels with at most one front per CU).  Assembly in
 // global memory, then blocked right-looking LU: a panel of NB columns is
 // factored in LDS by one wavefront, U12 is solved one column per thread and
 // the trailing matrix is updated with each thread owning one row (its NB
 // multipliers in registers) against U columns staged in LDS.
 // ---------------------------------------------------------------------------
-template <typename T, int NB>
-__global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict__ fac,
+template <typename T, int NB, int NTF>
+__global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict__ fac,
                                                      T* __restrict__ lpk, T* __restrict__ upk,
                                                      int* __restrict__ piv,
                                                      int* __restrict__ flag, double tau) {
@@ -418,31 +419,31 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
   T* P = reinterpret_cast<T*>(smem_raw);           // panel, column-major, ld = ldp
   __shared__ T Us[UC][NB + 1];                      // staged U columns
   __shared__ int s_piv[NB];
-  __shared__ R s_best[NT / 64], s_amax[NT / 64];
-  __shared__ int s_bi[NT / 64];
+  __shared__ R s_best[NTF / 64], s_amax[NTF / 64];
+  __shared__ int s_bi[NTF / 64];
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p, ldp = a.max_m;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   T* F = fac + f.fac_off;
-  assemble_front<T>(a, fac, f, F, tid, NT, [] { __syncthreads(); });
+  assemble_front<T>(a, fac, f, F, tid, NTF, [] { __syncthreads(); });
   int* ip = piv + f.piv_off;
 
   for (int kb = 0; kb < p; kb += NB) {
     const int nb = min(NB, p - kb);
     const int nr = m - kb;
-    for (int t = tid; t < nb * nr; t += NT) {
+    for (int t = tid; t < nb * nr; t += NTF) {
       int k = t / nr, r = t - k * nr;
       P[k * ldp + r] = F[(long long)(kb + k) * m + kb + r];
     }
     __syncthreads();
-    // Panel LU on all NT threads: rows split over the workgroup, the pivot
+    // Panel LU on all NTF threads: rows split over the workgroup, the pivot
     // search reduced per wavefront and combined in LDS (largest |.|^2, ties to
     // the lower row, as a single wavefront would choose).
     for (int k = 0; k < nb; ++k) {
       T* col = P + k * ldp;
       R best = (R)-1, amax = (R)0;
       int bi = k;
-      for (int r = k + tid; r < nr; r += NT) {
+      for (int r = k + tid; r < nr; r += NTF) {
         const R v = cabs2(col[r]);
         amax = v > amax ? v : amax;
         if (r < p - kb && v > best) {
@@ -467,7 +468,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       }
       __syncthreads();
       if (tid == 0) {
-        for (int w = 1; w < NT / 64; ++w) {
+        for (int w = 1; w < NTF / 64; ++w) {
           if (s_best[w] > best || (s_best[w] == best && s_bi[w] < bi)) {
             best = s_best[w];
             bi = s_bi[w];
@@ -491,7 +492,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       }
       __syncthreads();
       const T dinv = cdiv(T{(R)1, (R)0}, col[k]);
-      for (int r = k + 1 + tid; r < nr; r += NT) {
+      for (int r = k + 1 + tid; r < nr; r += NTF) {
         T l = cmul(col[r], dinv);
         col[r] = l;
         for (int c = k + 1; c < nb; ++c) P[c * ldp + r] = cfms(l, P[c * ldp + k], P[c * ldp + r]);
@@ -499,13 +500,13 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       __syncthreads();
     }
     __syncthreads();
-    for (int t = tid; t < nb * nr; t += NT) {
+    for (int t = tid; t < nb * nr; t += NTF) {
       int k = t / nr, r = t - k * nr;
       F[(long long)(kb + k) * m + kb + r] = P[k * ldp + r];
     }
     // Row exchanges in the columns outside the panel, in pivot order, one
     // column per thread.
-    for (int c = tid; c < m; c += NT) {
+    for (int c = tid; c < m; c += NTF) {
       if (c >= kb && c < kb + nb) continue;
       T* Fc = F + (long long)c * m;
       for (int k = 0; k < nb; ++k) {
@@ -519,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
     }
     __syncthreads();
     // U12 block row: L_d^{-1} F[kb:kb+nb, c] for every column c >= kb+nb.
-    for (int c = kb + nb + tid; c < m; c += NT) {
+    for (int c = kb + nb + tid; c < m; c += NTF) {
       T* Fc = F + (long long)c * m + kb;
       T x[NB];
 #pragma unroll
@@ -545,13 +546,13 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       // Small trailing blocks: (row, column group) threads over the whole
       // workgroup, read-modify-writes in batches of TB columns.
       constexpr int TB = 8;
-      const int G = NT / R, g = tid / R, rr = tid - g * R;
+      const int G = NTF / R, g = tid / R, rr = tid - g * R;
       const int r = n0 + rr;
       const T* Pr = P + (r - kb);
       for (int c0 = n0; c0 < m; c0 += UC) {
         const int cw = min(UC, m - c0);
         __syncthreads();
-        for (int t = tid; t < cw * NB; t += NT) {
+        for (int t = tid; t < cw * NB; t += NTF) {
           int c = t / NB, k = t - c * NB;
           Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
         }
@@ -585,13 +586,13 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       for (int c0 = n0; c0 < m; c0 += UC) {
         const int cw = min(UC, m - c0);
         __syncthreads();
-        for (int t = tid; t < cw * NB; t += NT) {
+        for (int t = tid; t < cw * NB; t += NTF) {
           int c = t / NB, k = t - c * NB;
           Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
         }
         __syncthreads();
         const int ntc = (cw + 15) / 16;
-        for (int tt = wv; tt < ntr * ntc; tt += NT / 64) {
+        for (int tt = wv; tt < ntr * ntc; tt += NTF / 64) {
           const int rb = n0 + 16 * (tt / ntc), cb = 16 * (tt % ntc);
           typename M::V accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
           const int ra = rb + l16, cbb = cb + l16;
@@ -629,7 +630,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
   T* Db = P;                                    // DIB x DIB block, then two column buffers
   for (int j0 = 0; j0 < p; j0 += DIB) {
     const int nbk = min(DIB, p - j0);
-    for (int t = tid; t < nbk * nbk; t += NT) {
+    for (int t = tid; t < nbk * nbk; t += NTF) {
       int c = t / nbk, r = t - c * nbk;
       Db[c * DIB + r] = F[(long long)(j0 + c) * m + j0 + r];
     }
@@ -637,7 +638,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
     if (wv == 0) invert_lower_unit(Db, DIB, nbk, Db + DIB * DIB, lane);
     if (wv == 1) invert_upper(Db, DIB, nbk, Db + DIB * DIB + DIB, lane);
     __syncthreads();
-    for (int t = tid; t < nbk * nbk; t += NT) {
+    for (int t = tid; t < nbk * nbk; t += NTF) {
       int c = t / nbk, r = t - c * nbk;
       F[(long long)(j0 + c) * m + j0 + r] = Db[c * DIB + r];
     }
@@ -647,7 +648,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
     for (int r0 = j1; r0 < m; r0 += CR) {
       const int rows = min(CR, m - r0);
       __syncthreads();
-      for (int t = tid; t < rows * nbk; t += NT) {
+      for (int t = tid; t < rows * nbk; t += NTF) {
         int j = t / rows, rr = t - j * rows;
         Cb[j * CR + rr] = F[(long long)(j0 + j) * m + r0 + rr];
       }
@@ -658,13 +659,13 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
           [&](int k, int c) {
             return k == c ? T{(R)1, (R)0} : (k > c ? Db[c * DIB + k] : czero<T>());
           },
-          [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NT / 64, lane);
+          [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NTF / 64, lane);
     }
     // N'_J = -U[0:j0, J] Uinv_J, 64 rows at a time.
     for (int r0 = 0; r0 < j0; r0 += CR) {
       const int rows = min(CR, j0 - r0);
       __syncthreads();
-      for (int t = tid; t < rows * nbk; t += NT) {
+      for (int t = tid; t < rows * nbk; t += NTF) {
         int j = t / rows, rr = t - j * rows;
         Cb[j * CR + rr] = F[(long long)(j0 + j) * m + r0 + rr];
       }
@@ -673,14 +674,14 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
       mma_neg_product<T>(
           rows, nbk, nbk, [&](int r, int k) { return Cb[k * CR + r]; },
           [&](int k, int c) { return k <= c ? Db[c * DIB + k] : czero<T>(); },
-          [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NT / 64, lane);
+          [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NTF / 64, lane);
     }
     // A single-block front also gets V' = -U11^{-1} U12 (64 columns at a time).
     if (p <= DIB) {
       for (int c0 = p; c0 < m; c0 += CR) {
         const int cols = min(CR, m - c0);
         __syncthreads();
-        for (int t = tid; t < cols * p; t += NT) {
+        for (int t = tid; t < cols * p; t += NTF) {
           int c = t / p, r = t - c * p;
           Cb[c * DIB + r] = F[(long long)(c0 + c) * m + r];
         }
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
         mma_neg_product<T>(
             p, cols, p, [&](int r, int k) { return k >= r ? Db[k * DIB + r] : czero<T>(); },
             [&](int k, int c) { return Cb[c * DIB + k]; },
-            [&](int r, int c, T v) { F[(long long)(c0 + c) * m + r] = v; }, wv, NT / 64, lane);
+            [&](int r, int c, T v) { F[(long long)(c0 + c) * m + r] = v; }, wv, NTF / 64, lane);
       }
     }
     __syncthreads();
@@ -704,29 +705,29 @@ __global__ __launch_bounds__(NT) void k_factor_large(LevelArgs a, T* __restrict_
     const int nJ = (p + DIB - 1) / DIB;
     for (int J = 0; J + 1 < nJ; ++J)
       for (int K = J + 1; K < nJ; ++K)
-        fold_step<T, true>(F, m, K * DIB, min(K * DIB + DIB, p), J * DIB, min(J * DIB + DIB, p), P,
+        fold_step<T, true, NTF>(F, m, K * DIB, min(K * DIB + DIB, p), J * DIB, min(J * DIB + DIB, p), P,
                            tid);
     __syncthreads();
-    for (int t = tid; t < p * (m - p); t += NT) {
+    for (int t = tid; t < p * (m - p); t += NTF) {
       const int c = p + t / p, r = t % p;
       const T x = F[(long long)c * m + r];
       F[(long long)c * m + r] = T{-x.x, -x.y};
     }
     for (int c0 = p; c0 < m; c0 += DIB)
       for (int K = nJ - 1; K >= 0; --K)
-        fold_step<T, false>(F, m, K * DIB, min(K * DIB + DIB, p), c0, min(c0 + DIB, m), P, tid);
+        fold_step<T, false, NTF>(F, m, K * DIB, min(K * DIB + DIB, p), c0, min(c0 + DIB, m), P, tid);
     for (int J = nJ - 1; J >= 1; --J)
       for (int K = J - 1; K >= 0; --K)
-        fold_step<T, false>(F, m, K * DIB, min(K * DIB + DIB, p), J * DIB, min(J * DIB + DIB, p), P,
+        fold_step<T, false, NTF>(F, m, K * DIB, min(K * DIB + DIB, p), J * DIB, min(J * DIB + DIB, p), P,
                             tid);
     __syncthreads();
   }
   // Packed sweep operators, a wavefront per column.
   T* Lp = lpk + f.lpk_off;
-  for (int k = wv; k < p; k += NT / 64)
+  for (int k = wv; k < p; k += NTF / 64)
     for (int r = k + 1 + lane; r < m; r += 64) Lp[lpk_col(m, k) + r - k - 1] = F[(long long)k * m + r];
   T* Up = upk + f.upk_off;
-  for (int c = wv; c < m; c += NT / 64) {
+  for (int c = wv; c < m; c += NTF / 64) {
     const int rows = c < p ? c + 1 : p;
     for (int r = lane; r < rows; r += 64) Up[upk_col(p, c) + r] = F[(long long)c * m + r];
   }
@@ -1222,12 +1223,12 @@ int max_lds() {
   return g_max_lds;
 }
 
-template <typename T, int NB>
+template <typename T, int NB, int NTF = NT>
 void large_launch(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
                   double tau) {
   size_t lds = std::max((size_t)a.max_m * NB, (size_t)DIB * DIB + 2 * DIB + (size_t)CR * DIB) * sizeof(T);
-  hipLaunchKernelGGL((k_factor_large<T, NB>), dim3(a.nlevel), dim3(NT), lds, st, a, fac, lpk, upk,
-                     piv, flag, tau);
+  hipLaunchKernelGGL((k_factor_large<T, NB, NTF>), dim3(a.nlevel), dim3(NTF), lds, st, a, fac, lpk,
+                     upk, piv, flag, tau);
 }
 
 }  // namespace
@@ -1261,6 +1262,15 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* 
   int nb = 1;
   while (nb * 2 <= nb_max && per_col * nb * 2 <= budget) nb *= 2;
   if (per_col * nb > budget) throw Error(STF_EINVAL, "front too large for the LDS panel");
+  // Levels with at most one front per CU: four times the threads per front
+  // (the serial chain of a front is the level's time), with 16-column panels
+  // (8 in FP64) so that a thread fits in 128 registers.  Not for root fronts
+  // (no Schur complement), where the serial panel and block inverses dominate.
+  constexpr int NB1K = sizeof(T) == 8 ? 16 : 8;
+  if (a.nlevel <= 256 && a.max_m > a.max_p && nb >= NB1K) {
+    large_launch<T, NB1K, 1024>(st, a, fac, lpk, upk, piv, flag, tau);
+    return;
+  }
   switch (nb) {
     case 32: large_launch<T, 32>(st, a, fac, lpk, upk, piv, flag, tau); break;
     case 16: large_launch<T, 16>(st, a, fac, lpk, upk, piv, flag, tau); break;
