@@ -253,6 +253,31 @@ __global__ __launch_bounds__(KT) void k_norm_reduce(const double* __restrict__ p
   }
 }
 
+// sum_{b = t, t + KT, ... < n} x[b * stride] in that order, the loads issued
+// eight at a time (one memory round trip per eight terms).
+template <typename V, typename F>
+__device__ inline void strided_sum(int t, int n, F load, V& acc) {
+  constexpr int LB = 8;
+  for (int b0 = t; b0 < n; b0 += LB * KT) {
+    V v[LB];
+#pragma unroll
+    for (int u = 0; u < LB; ++u) {
+      const int b = b0 + u * KT;
+      v[u] = b < n ? load(b) : V{};
+    }
+#pragma unroll
+    for (int u = 0; u < LB; ++u) acc += v[u];
+  }
+}
+struct Cd {
+  double x = 0.0, y = 0.0;
+  __device__ Cd& operator+=(const Cd& o) {
+    x += o.x;
+    y += o.y;
+    return *this;
+  }
+};
+
 // The reductions between the register Gram-Schmidt passes, one launch each.
 // Blocks 0..nv-1: h[i] = sum_b partial[b * stride + i] in a fixed order;
 // block nv: out[0] = sum of the nblk norm partials and, with ref, the
@@ -266,18 +291,20 @@ __global__ __launch_bounds__(KT) void k_gs_reduce(const double2* __restrict__ pa
   __shared__ double red[4];
   const int i = blockIdx.x;
   if (i < nv) {
-    double sr = 0.0, si = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += KT) {
+    Cd acc;
+    strided_sum(threadIdx.x, nblk, [&](int b) {
       const double2 v = partial[(long long)b * stride + i];
-      sr += v.x;
-      si += v.y;
-    }
-    sr = block_sum(sr, red);
-    si = block_sum(si, red);
+      Cd c;
+      c.x = v.x;
+      c.y = v.y;
+      return c;
+    }, acc);
+    const double sr = block_sum(acc.x, red);
+    const double si = block_sum(acc.y, red);
     if (threadIdx.x == 0) h[i] = make_double2(sr, si);
   } else {
     double s = 0.0;
-    for (int b = threadIdx.x; b < nblk; b += KT) s += npart[b];
+    strided_sum(threadIdx.x, nblk, [&](int b) { return npart[b]; }, s);
     s = block_sum(s, red);
     if (threadIdx.x == 0) {
       out[0] = s;
@@ -295,7 +322,7 @@ __global__ __launch_bounds__(KT) void k_gs_final(const double* __restrict__ npar
   __shared__ double red[4];
   if (gate[0] == 0) return;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblk; b += KT) s += npart[b];
+  strided_sum(threadIdx.x, nblk, [&](int b) { return npart[b]; }, s);
   s = block_sum(s, red);
   if (threadIdx.x == 0) out[0] = s;
   for (int i = threadIdx.x; i < nv; i += KT)
@@ -321,53 +348,68 @@ __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
   }
 }
 
-// One Givens step of FGMRES for column j (single thread).
+// One Givens step of FGMRES for column j.
 //   column j of the Hessenberg matrix: h[i] (i <= j), h[j+1] = |w|.
 //   Earlier rotations are applied, a new one zeroes h[j+1], g is rotated and
 //   est = |g[j+1]| is the residual norm of the least-squares iterate.
-__global__ void k_givens(double2* __restrict__ H, const double2* __restrict__ h,
-                         const double* __restrict__ wnorm2, double* __restrict__ cs,
-                         double2* __restrict__ sn, double2* __restrict__ g, int j, int ldh,
-                         double* __restrict__ est) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double2* col = H + (long long)j * ldh;
-  for (int i = 0; i <= j; ++i) col[i] = h[i];
-  col[j + 1] = make_double2(sqrt(wnorm2[0]), 0.0);
-  for (int i = 0; i < j; ++i) {
-    double c = cs[i];
-    double2 s = sn[i];
-    double2 a = col[i], b = col[i + 1];
-    // [c, s; -conj(s), c] [a; b]
-    double2 t0 = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
-    double2 t1 = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
-    col[i] = t0;
-    col[i + 1] = t1;
+// The operands are staged in LDS by the whole block (j < GV), so that the
+// sequential rotations by thread 0 wait on no memory round trips.
+constexpr int GV = 256;
+__global__ __launch_bounds__(64) void k_givens(double2* __restrict__ H, const double2* __restrict__ h,
+                                               const double* __restrict__ wnorm2,
+                                               double* __restrict__ cs, double2* __restrict__ sn,
+                                               double2* __restrict__ g, int j, int ldh,
+                                               double* __restrict__ est) {
+  __shared__ double2 col[GV + 1];
+  __shared__ double scs[GV];
+  __shared__ double2 ssn[GV];
+  const int t = threadIdx.x;
+  for (int i = t; i <= j; i += blockDim.x) col[i] = h[i];
+  for (int i = t; i < j; i += blockDim.x) {
+    scs[i] = cs[i];
+    ssn[i] = sn[i];
   }
-  double2 a = col[j], b = col[j + 1];
-  double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
-  double c;
-  double2 s, r;
-  if (nb == 0.0) {
-    c = 1.0; s = make_double2(0.0, 0.0); r = a;
-  } else if (na == 0.0) {
-    c = 0.0; s = make_double2(b.x / nb, -b.y / nb); r = make_double2(nb, 0.0);
-  } else {
-    double nrm = hypot(na, nb);
-    double2 ph = make_double2(a.x / na, a.y / na);          // a / |a|
-    c = na / nrm;
-    // s = (a/|a|) conj(b) / nrm
-    s = make_double2((ph.x * b.x + ph.y * b.y) / nrm, (ph.y * b.x - ph.x * b.y) / nrm);
-    r = make_double2(ph.x * nrm, ph.y * nrm);
+  if (t == 0) col[j + 1] = make_double2(sqrt(wnorm2[0]), 0.0);
+  __syncthreads();
+  if (t == 0) {
+    for (int i = 0; i < j; ++i) {
+      const double c = scs[i];
+      const double2 s = ssn[i];
+      const double2 a = col[i], b = col[i + 1];
+      // [c, s; -conj(s), c] [a; b]
+      col[i] = make_double2(c * a.x + (s.x * b.x - s.y * b.y), c * a.y + (s.x * b.y + s.y * b.x));
+      col[i + 1] = make_double2(-(s.x * a.x + s.y * a.y) + c * b.x, -(s.x * a.y - s.y * a.x) + c * b.y);
+    }
+    const double2 a = col[j], b = col[j + 1];
+    const double na = hypot(a.x, a.y), nb = hypot(b.x, b.y);
+    double c;
+    double2 s, r;
+    if (nb == 0.0) {
+      c = 1.0; s = make_double2(0.0, 0.0); r = a;
+    } else if (na == 0.0) {
+      c = 0.0; s = make_double2(b.x / nb, -b.y / nb); r = make_double2(nb, 0.0);
+    } else {
+      const double nrm = hypot(na, nb);
+      const double2 ph = make_double2(a.x / na, a.y / na);          // a / |a|
+      c = na / nrm;
+      // s = (a/|a|) conj(b) / nrm
+      s = make_double2((ph.x * b.x + ph.y * b.y) / nrm, (ph.y * b.x - ph.x * b.y) / nrm);
+      r = make_double2(ph.x * nrm, ph.y * nrm);
+    }
+    cs[j] = c;
+    sn[j] = s;
+    col[j] = r;
+    col[j + 1] = make_double2(0.0, 0.0);
+    const double2 gj = g[j];
+    // g[j+1] = -conj(s) g[j]; g[j] = c g[j]
+    const double2 g1 = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
+    g[j + 1] = g1;
+    g[j] = make_double2(c * gj.x, c * gj.y);
+    est[0] = hypot(g1.x, g1.y);
   }
-  cs[j] = c;
-  sn[j] = s;
-  col[j] = r;
-  col[j + 1] = make_double2(0.0, 0.0);
-  double2 gj = g[j];
-  // g[j+1] = -conj(s) g[j]; g[j] = c g[j]
-  g[j + 1] = make_double2(-(s.x * gj.x + s.y * gj.y), -(s.x * gj.y - s.y * gj.x));
-  g[j] = make_double2(c * gj.x, c * gj.y);
-  est[0] = hypot(g[j + 1].x, g[j + 1].y);
+  __syncthreads();
+  double2* Hc = H + (long long)j * ldh;
+  for (int i = t; i <= j + 1; i += blockDim.x) Hc[i] = col[i];
 }
 
 __global__ void k_trisolve(const double2* __restrict__ H, const double2* __restrict__ g,
@@ -486,6 +528,7 @@ void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2*
 
 void launch_givens(hipStream_t st, double2* H, const double2* h, const double* wnorm2,
                    double* cs, double2* sn, double2* g, int j, int ldh, double* est_out) {
+  STF_REQUIRE(j >= 0 && j < GV, "Givens step beyond the staged column");
   hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h, wnorm2, cs, sn, g, j, ldh, est_out);
 }
 
