@@ -1289,15 +1289,28 @@ inline int prefetch_depth(int need, int cap) {
   return kp;
 }
 
-// Workgroup size for the large-front sweeps: the smallest of 256, 512, 1024
-// threads whose per-thread column count (rows shared by NTL / rows column
-// groups) fits the register prefetch.
-inline int large_threads(int rows, int cols, int cap) {
-  for (int ntl = 256; ntl < 1024; ntl *= 2) {
-    const int g = std::max(1, ntl / std::max(rows, 1));
-    if ((cols + g - 1) / g <= cap) return ntl;
+// Workgroup size for the large-front sweeps: the largest of 256, 512, 1024
+// threads with which the level's fronts all fit in one round of workgroups at
+// sixteen wavefronts per CU (the latency of one front is the level's time, so a
+// second round costs more than narrower workgroups do); at least 256.
+int g_num_cus = 0;
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        v > 0)
+      g_num_cus = v;
+    else
+      g_num_cus = 256;
   }
-  return 1024;
+  return g_num_cus;
+}
+inline int large_threads(int nfronts) {
+  const long long budget = 16LL * num_cus();             // resident wavefronts
+  int ntl = 256;
+  while (ntl < 1024 && (long long)nfronts * (2 * ntl / 64) <= budget) ntl *= 2;
+  return ntl;
 }
 
 // Instantiation over the number of right-hand sides swept together.
@@ -1392,7 +1405,7 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
     return;
   }
   // Rows m share the workgroup; a row takes at most p columns.
-  const int ntl = large_threads(a.max_m, a.max_p, cap);
+  const int ntl = large_threads(a.nlevel);
   const int g = std::max(1, ntl / a.max_m);
   const int kp = prefetch_depth((a.max_p + g - 1) / g, cap);
   if (ntl == 256) fwd_large_launch<T, 256>(st, a, kp, fac, piv, vec, r);
@@ -1418,7 +1431,7 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, 
     return;
   }
   // Rows p share the workgroup; a row takes at most m columns.
-  const int ntl = large_threads(a.max_p, a.max_m, cap);
+  const int ntl = large_threads(a.nlevel);
   const int g = std::max(1, ntl / std::max(a.max_p, 1));
   const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
   if (ntl == 256) bwd_large_launch<T, 256>(st, a, kp, upk, vec, u, r);
