@@ -425,7 +425,7 @@ void build_device_state(stf_problem pb) {
   pb->scal.alloc(sizeof(double) * 64);
   int nblk = std::max(stencil_partial_blocks(p.nx, p.ny), krylov_blocks(pb->N));
   pb->partial.alloc((size_t)nblk * sizeof(double2) * 4);
-  pb->npartial.alloc((size_t)std::max(krylov_blocks(pb->N), gs_blocks(pb->N)) * sizeof(double));
+  pb->npartial.alloc((size_t)std::max(krylov_blocks(pb->N), gs_blocks(pb->N, 32)) * sizeof(double));
   HIP_CHECK(hipStreamSynchronize(st));
 }
 
@@ -573,7 +573,7 @@ void ensure_krylov(stf_problem pb, int m, int nr) {
   int nblk = krylov_blocks(pb->N);
   size_t need = (size_t)nblk * (m + 1) * sizeof(double2);
   const int stride = gs_stride(std::min(m + 1, 32));
-  need = std::max(need, (size_t)gs_blocks(pb->N) * stride * sizeof(double2));
+  need = std::max(need, (size_t)gs_blocks(pb->N, 32) * stride * sizeof(double2));
   pb->partial.alloc(std::max<size_t>(pb->partial.bytes, need));
   pb->krylov_m = m;
   pb->krylov_nr = nr;
@@ -957,7 +957,7 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
           // The first pass's update and the second pass's products share one
           // read of the basis (the products are discarded when the gate stays
           // closed).
-          const int gb = gs_blocks(N);
+          const int gb = gs_blocks(N, nv);
           launch_gs(st, GS_DOT, q.V, N, nv, nullptr, w, N, part, npart, nullptr);
           launch_gs_reduce(st, part, gb, stride, nv, h1, npart, q.sc + 6, nullptr, nullptr);
           launch_gs(st, GS_UPDATE_DOT, q.V, N, nv, h1, w, N, part, npart, nullptr);

@@ -436,14 +436,15 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
       P[k * ldp + r] = F[(long long)(kb + k) * m + kb + r];
     }
     __syncthreads();
-    // Panel LU on all NTF threads: rows split over the workgroup, the pivot
-    // search reduced per wavefront and combined in LDS (largest |.|^2, ties to
-    // the lower row, as a single wavefront would choose).
+    // Panel LU: the pivot search on the first NPV threads (reduced per
+    // wavefront and combined in LDS: largest |.|^2, ties to the lower row, as a
+    // single wavefront would choose), the row updates on all NTF threads.
+    constexpr int NPV = NTF < 256 ? NTF : 256;
     for (int k = 0; k < nb; ++k) {
       T* col = P + k * ldp;
       R best = (R)-1, amax = (R)0;
       int bi = k;
-      for (int r = k + tid; r < nr; r += NTF) {
+      for (int r = k + tid; tid < NPV && r < nr; r += NPV) {
         const R v = cabs2(col[r]);
         amax = v > amax ? v : amax;
         if (r < p - kb && v > best) {
@@ -461,14 +462,14 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
         }
         amax = oa > amax ? oa : amax;
       }
-      if (lane == 0) {
+      if (lane == 0 && tid < NPV) {
         s_best[wv] = best;
         s_amax[wv] = amax;
         s_bi[wv] = bi;
       }
       __syncthreads();
       if (tid == 0) {
-        for (int w = 1; w < NTF / 64; ++w) {
+        for (int w = 1; w < NPV / 64; ++w) {
           if (s_best[w] > best || (s_best[w] == best && s_bi[w] < bi)) {
             best = s_best[w];
             bi = s_bi[w];

@@ -150,9 +150,9 @@ __global__ __launch_bounds__(KT) void k_mupdate(const double2* __restrict__ V, l
   }
 }
 
-// Register-resident Gram-Schmidt passes for bases of at most 32 vectors: one
-// entry per thread (coalesced, a fine grid that balances over the CUs), all
-// nv basis entries loaded at once into registers.  UPD: w -= V h; DOT: the
+// Register-resident Gram-Schmidt passes for bases of at most 32 vectors: each
+// thread holds 32 basis values in registers, EPT = 32 / NVM entries of each of
+// the NVM vectors (coalesced: entry = base + e * 256 + tid), all loaded at once.  UPD: w -= V h; DOT: the
 // partial products V^H w of the (updated) entries, written as
 // partial[blk][NVM] (complex); always the partial |w|^2.  With UPD and DOT
 // together one read of the basis serves the update of the first pass and the
@@ -195,38 +195,60 @@ __global__ __launch_bounds__(KT) void k_gs(const double2* __restrict__ V, long l
                                            double* __restrict__ norm_partial,
                                            const int* __restrict__ gate) {
   constexpr int K = 2 * NVM;
+  constexpr int EPT = 32 / NVM;                          // entries per thread
   __shared__ double2 hs[NVM];
   __shared__ double red[4][K];
   __shared__ double nred[4];
   if (gate && gate[0] == 0) return;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (UPD && tid < nv) hs[tid] = h[tid];
-  const long long idx = (long long)blockIdx.x * KT + tid;
-  const bool in = idx < n;
-  double2 v[NVM];
+  const long long base = (long long)blockIdx.x * (KT * EPT) + tid;
+  double2 v[NVM][EPT], wr[EPT];
 #pragma unroll
   for (int i = 0; i < NVM; ++i)
-    v[i] = (in && i < nv) ? V[(long long)i * ld + idx] : make_double2(0.0, 0.0);
-  double2 wr = in ? w[idx] : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const long long idx = base + (long long)e * KT;
+      v[i][e] = (idx < n && i < nv) ? V[(long long)i * ld + idx] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const long long idx = base + (long long)e * KT;
+    wr[e] = idx < n ? w[idx] : make_double2(0.0, 0.0);
+  }
   if (UPD) {
     __syncthreads();
 #pragma unroll
-    for (int i = 0; i < NVM; ++i)
-      if (i < nv) wr = cfms(v[i], hs[i], wr);
-    if (in) w[idx] = wr;
+    for (int e = 0; e < EPT; ++e) {
+#pragma unroll
+      for (int i = 0; i < NVM; ++i)
+        if (i < nv) wr[e] = cfms(v[i][e], hs[i], wr[e]);
+      const long long idx = base + (long long)e * KT;
+      if (idx < n) w[idx] = wr[e];
+    }
   }
   if (DOT) {
     double a[K];
 #pragma unroll
     for (int i = 0; i < NVM; ++i) {
-      a[2 * i] = fma(v[i].y, wr.y, v[i].x * wr.x);         // conj(v) * w
-      a[2 * i + 1] = fma(-v[i].y, wr.x, v[i].x * wr.y);
+      a[2 * i] = fma(v[i][0].y, wr[0].y, v[i][0].x * wr[0].x);         // conj(v) * w
+      a[2 * i + 1] = fma(-v[i][0].y, wr[0].x, v[i][0].x * wr[0].y);
+#pragma unroll
+      for (int e = 1; e < EPT; ++e) {
+        a[2 * i] = fma(v[i][e].x, wr[e].x, a[2 * i]);
+        a[2 * i] = fma(v[i][e].y, wr[e].y, a[2 * i]);
+        a[2 * i + 1] = fma(v[i][e].x, wr[e].y, a[2 * i + 1]);
+        a[2 * i + 1] = fma(-v[i][e].y, wr[e].x, a[2 * i + 1]);
+      }
     }
     const double s = wave_fold<K>(a, lane);
     constexpr int G = 64 / K;                              // lanes per value
     if ((lane & (G - 1)) == 0) red[wv][lane / G] = s;
   }
-  const double nr = wave_sum(wr.x * wr.x + wr.y * wr.y);
+  double nr = 0.0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) nr += wr[e].x * wr[e].x + wr[e].y * wr[e].y;
+  nr = wave_sum(nr);
   if (lane == 0) nred[wv] = nr;
   __syncthreads();
   if (DOT && tid < K)
@@ -466,9 +488,14 @@ void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv
                      stride > 0 ? stride : nv, h, gate);
 }
 
-int gs_blocks(long long n) { return (int)((n + KT - 1) / KT); }
-
 int gs_stride(int nv) { return nv <= 8 ? 8 : nv <= 16 ? 16 : nv <= 32 ? 32 : 0; }
+
+int gs_blocks(long long n, int nv) {
+  const int nvm = gs_stride(nv);
+  const int ept = nvm > 0 ? 32 / nvm : 1;
+  return (int)((n + (long long)KT * ept - 1) / ((long long)KT * ept));
+}
+
 
 void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
                       double2* h, const double* npart, double* out, const double* ref, int* gate) {
@@ -487,7 +514,7 @@ void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv,
   STF_REQUIRE(nvm > 0 && nv >= 1, "register Gram-Schmidt pass takes 1..32 basis vectors");
   STF_REQUIRE(mode >= GS_DOT && mode <= GS_UPDATE, "unknown Gram-Schmidt pass");
   double* pd = reinterpret_cast<double*>(partial);
-  const dim3 g(gs_blocks(n)), b(KT);
+  const dim3 g(gs_blocks(n, nv)), b(KT);
 #define STF_GS_CASE(M)                                                                         \
   if (nvm == M) {                                                                              \
     if (mode == GS_DOT)                                                                        \

@@ -229,7 +229,7 @@ void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv
 //   GS_UPDATE_DOT: w -= V h, then partial = V^H w and |w|^2 of the new w
 //   GS_UPDATE:     w -= V h, |w|^2 partials
 enum { GS_DOT = 0, GS_UPDATE_DOT = 1, GS_UPDATE = 2 };
-int gs_blocks(long long n);
+int gs_blocks(long long n, int nv);   // workgroups of a pass over a basis of nv vectors
 int gs_stride(int nv);    // 8, 16 or 32; 0 when nv > 32 (use launch_mdot / launch_mupdate)
 void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
                double2* w, long long n, double2* partial, double* norm_partial, const int* gate);
