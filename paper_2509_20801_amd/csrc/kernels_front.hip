@@ -854,8 +854,10 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const int idx = lane + 64 * i;
-      c0[s][i] = d0[i] >= 0 ? vs[f.cvec[0] + idx] : czero<T>();
-      c1[s][i] = d1[i] >= 0 ? vs[f.cvec[1] + idx] : czero<T>();
+      // predicated on the position, not on the loaded index: the value load
+      // does not wait for the child map
+      c0[s][i] = (f.nchild > 0 && idx < f.cq[0]) ? vs[f.cvec[0] + idx] : czero<T>();
+      c1[s][i] = (f.nchild > 1 && idx < f.cq[1]) ? vs[f.cvec[1] + idx] : czero<T>();
     }
   }
 #pragma unroll
@@ -1016,8 +1018,9 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
       for (int s = 0; s < NR; ++s) {
         const T* vs = vec + s * rs.vec_stride;
         bv[u][s] = gidx[u] >= 0 ? from_d2<T>(rs.v[s][gidx[u]]) : czero<T>();
-        c0[u][s] = d0[u] >= 0 ? vs[f.cvec[0] + i] : czero<T>();
-        c1[u][s] = d1[u] >= 0 ? vs[f.cvec[1] + i] : czero<T>();
+        // predicated on the position, not on the loaded index (no chain)
+        c0[u][s] = (f.nchild > 0 && i < f.cq[0]) ? vs[f.cvec[0] + i] : czero<T>();
+        c1[u][s] = (f.nchild > 1 && i < f.cq[1]) ? vs[f.cvec[1] + i] : czero<T>();
       }
     }
 #pragma unroll
