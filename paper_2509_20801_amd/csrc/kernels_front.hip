@@ -1268,10 +1268,9 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* 
   if (per_col * nb > budget) throw Error(STF_EINVAL, "front too large for the LDS panel");
   // Levels with at most one front per CU: four times the threads per front
   // (the serial chain of a front is the level's time), with 16-column panels
-  // (8 in FP64) so that a thread fits in 128 registers.  Not for root fronts
-  // (no Schur complement), where the serial panel and block inverses dominate.
+  // (8 in FP64) so that a thread fits in 128 registers.
   constexpr int NB1K = sizeof(T) == 8 ? 16 : 8;
-  if (a.nlevel <= 256 && a.max_m > a.max_p && nb >= NB1K) {
+  if (a.nlevel <= 256 && nb >= NB1K) {
     large_launch<T, NB1K, 1024>(st, a, fac, lpk, upk, piv, flag, tau);
     return;
   }
