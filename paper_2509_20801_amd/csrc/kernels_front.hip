@@ -233,14 +233,16 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   const int m = f.p + f.q, p = f.p, lane = threadIdx.x;
   assemble_front<T>(a, fac, f, G, lane, 64, [] { wave_sync(); });
   int* ip = piv + f.piv_off;
-  for (int k = 0; k < p; ++k) {
+  // Pivot choice, perturbation and row exchange of step k (column k as it
+  // stands), then the multipliers of column k.
+  auto pivot_step = [&](int k) {
     int bi;
     R best, amax;
-    wave_pivot(G + (long long)k * m, k, p, m, lane, bi, best, amax);
+    wave_pivot(G + k * m, k, p, m, lane, bi, best, amax);
     if (lane == 0) {
-      T v = G[(long long)k * m + bi];
+      T v = G[k * m + bi];
       if (perturb(v, best, amax, tau)) {
-        G[(long long)k * m + bi] = v;
+        G[k * m + bi] = v;
         atomicOr(flag, 1);
       }
       ip[k] = bi;
@@ -248,17 +250,44 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
     wave_sync();
     if (bi != k)
       for (int c = lane; c < m; c += 64) {
-        T t0 = G[(long long)c * m + k];
-        G[(long long)c * m + k] = G[(long long)c * m + bi];
-        G[(long long)c * m + bi] = t0;
+        T t0 = G[c * m + k];
+        G[c * m + k] = G[c * m + bi];
+        G[c * m + bi] = t0;
       }
     wave_sync();
-    const T dinv = cdiv(T{(R)1, (R)0}, G[(long long)k * m + k]);
+    const T dinv = cdiv(T{(R)1, (R)0}, G[k * m + k]);
+    for (int r = k + 1 + lane; r < m; r += 64) G[k * m + r] = cmul(G[k * m + r], dinv);
+    wave_sync();
+  };
+  // Steps are taken in pairs (k, k+1): after step k only column k+1 is
+  // updated, so that step k+1 can choose its pivot; the rest of the trailing
+  // block then takes one rank-2 update, read and written once per pair.
+  int k = 0;
+  for (; k + 1 < p; k += 2) {
+    pivot_step(k);
+    for (int r = k + 1 + lane; r < m; r += 64)
+      G[(k + 1) * m + r] = cfms(G[k * m + r], G[(k + 1) * m + k], G[(k + 1) * m + r]);
+    wave_sync();
+    pivot_step(k + 1);
+    // Row k+1 past column k+1 still lacks step k's update: u2 = row k+1 - l u1.
+    const T lk1 = G[k * m + k + 1];
+    for (int r = k + 2 + lane; r < m; r += 64) {
+      const T l1 = G[k * m + r], l2 = G[(k + 1) * m + r];
+      for (int c = k + 2; c < m; ++c) {
+        const T u1 = G[c * m + k];
+        const T u2 = cfms(lk1, u1, G[c * m + k + 1]);
+        G[c * m + r] = cfms(l2, u2, cfms(l1, u1, G[c * m + r]));
+      }
+    }
+    wave_sync();
+    for (int c = k + 2 + lane; c < m; c += 64) G[c * m + k + 1] = cfms(lk1, G[c * m + k], G[c * m + k + 1]);
+    wave_sync();
+  }
+  if (k < p) {                      // odd p: a last single step
+    pivot_step(k);
     for (int r = k + 1 + lane; r < m; r += 64) {
-      T l = cmul(G[(long long)k * m + r], dinv);
-      G[(long long)k * m + r] = l;
-      for (int c = k + 1; c < m; ++c)
-        G[(long long)c * m + r] = cfms(l, G[(long long)c * m + k], G[(long long)c * m + r]);
+      const T l = G[k * m + r];
+      for (int c = k + 1; c < m; ++c) G[c * m + r] = cfms(l, G[c * m + k], G[c * m + r]);
     }
     wave_sync();
   }
