@@ -294,44 +294,74 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   T* colbuf = G + (long long)m * m;
   if (lane == 0) pivots_to_perm(ip, reinterpret_cast<int*>(colbuf + 64), p);
   wave_sync();
-  invert_lower_unit(G, m, p, colbuf, lane);
-  invert_upper(G, m, p, colbuf, lane);
-  wave_sync();
-  // M' = -L21 L11^{-1} (rows p..m-1, one row per lane, columns ascending so
-  // each entry is rewritten after its last use) and V' = -U11^{-1} U12
-  // (columns p..m-1, one column per lane, rows ascending).
-  for (int r = p + lane; r < m; r += 64) {
-    for (int j = 0; j < p; ++j) {
-      T acc = G[(long long)j * m + r];
-      for (int k = j + 1; k < p; ++k) acc = cfma(G[(long long)k * m + r], G[(long long)j * m + k], acc);
-      G[(long long)j * m + r] = T{-acc.x, -acc.y};
+  if (p <= 32) {
+    // Both triangles in one loop of p steps: lanes 0..31 build L11^{-1} by
+    // columns from the right (lane = row), lanes 32..63 build U11^{-1} by rows
+    // from the bottom (lane - 32 = column):
+    //   X_L[r][j] = -(L[r][j] + sum_{j<k<r} X_L[r][k] L[k][j]),
+    //   X_U[i][i] = 1/U[i][i],  X_U[i][c] = -X_U[i][i] sum_{i<k<=c} U[i][k] X_U[k][c].
+    // The column of L (resp. row of U) a step needs is staged in colbuf first.
+    const bool lo = lane < 32;
+    const int cl = lo ? lane : lane - 32;
+    for (int t = 0; t < p; ++t) {
+      const int j = p - 2 - t, ii = p - 1 - t;
+      if (lo) colbuf[cl] = (j >= 0 && cl > j && cl < p) ? G[j * m + cl] : czero<T>();
+      else colbuf[32 + cl] = (cl >= ii && cl < p) ? G[cl * m + ii] : czero<T>();
+      wave_sync();
+      if (lo) {
+        if (j >= 0 && cl > j && cl < p) {
+          T x = colbuf[cl];
+          for (int k = j + 1; k < cl; ++k) x = cfma(G[k * m + cl], colbuf[k], x);
+          G[j * m + cl] = T{-x.x, -x.y};
+        }
+      } else if (cl >= ii && cl < p) {
+        const T dinv = cdiv(T{(R)1, (R)0}, colbuf[32 + ii]);
+        if (cl == ii) {
+          G[ii * m + ii] = dinv;
+        } else {
+          T x = czero<T>();
+          for (int k = ii + 1; k <= cl; ++k) x = cfma(colbuf[32 + k], G[cl * m + k], x);
+          x = cmul(x, dinv);
+          G[cl * m + ii] = T{-x.x, -x.y};
+        }
+      }
+      wave_sync();
     }
+  } else {
+    invert_lower_unit(G, m, p, colbuf, lane);
+    invert_upper(G, m, p, colbuf, lane);
+    wave_sync();
   }
-  for (int c = p + lane; c < m; c += 64) {
-    for (int r = 0; r < p; ++r) {
-      T acc = czero<T>();
-      for (int k = r; k < p; ++k) acc = cfma(G[(long long)k * m + r], G[(long long)c * m + k], acc);
-      G[(long long)c * m + r] = T{-acc.x, -acc.y};
-    }
-  }
-  wave_sync();
-  // Only the Schur complement F22 goes back to the front storage (the parent's
-  // extend-add reads it); the sweeps read the packed operators.
-  T* F = fac + f.fac_off;
+  // M' = -L21 L11^{-1} and V' = -U11^{-1} U12, one entry per lane at a time over
+  // the whole wavefront, written straight into the packed operators (G keeps
+  // L21 and U12, which the products read).
   const int q = m - p;
+  T* Lp = lpk + f.lpk_off;
+  T* Up = upk + f.upk_off;
+  for (int t = lane; t < q * p; t += 64) {
+    const int j = t / q, r = p + (t - j * q);
+    T acc = G[j * m + r];
+    for (int k = j + 1; k < p; ++k) acc = cfma(G[k * m + r], G[j * m + k], acc);
+    Lp[lpk_col(m, j) + r - j - 1] = T{-acc.x, -acc.y};
+  }
+  for (int t = lane; t < q * p; t += 64) {
+    const int c = p + t / p, r = t - (c - p) * p;
+    T acc = czero<T>();
+    for (int k = r; k < p; ++k) acc = cfma(G[k * m + r], G[c * m + k], acc);
+    Up[upk_col(p, c) + r] = T{-acc.x, -acc.y};
+  }
+  // Only the Schur complement F22 goes back to the front storage (the parent's
+  // extend-add reads it).
+  T* F = fac + f.fac_off;
   for (int t = lane; t < q * q; t += 64) {
     const int c = p + t / q, r = p + t % q;
-    F[(long long)c * m + r] = G[(long long)c * m + r];
+    F[(long long)c * m + r] = G[c * m + r];
   }
-  // Packed sweep operators.
-  T* Lp = lpk + f.lpk_off;
+  // The L11^{-1} and U11^{-1} parts of the packed operators.
   for (int k = 0; k < p; ++k)
-    for (int r = k + 1 + lane; r < m; r += 64) Lp[lpk_col(m, k) + r - k - 1] = G[(long long)k * m + r];
-  T* Up = upk + f.upk_off;
-  for (int c = 0; c < m; ++c) {
-    const int rows = c < p ? c + 1 : p;
-    for (int r = lane; r < rows; r += 64) Up[upk_col(p, c) + r] = G[(long long)c * m + r];
-  }
+    for (int r = k + 1 + lane; r < p; r += 64) Lp[lpk_col(m, k) + r - k - 1] = G[k * m + r];
+  for (int c = 0; c < p; ++c)
+    for (int r = lane; r <= c; r += 64) Up[upk_col(p, c) + r] = G[c * m + r];
 }
 
 // 16 x 16 x 4 matrix-core products (D = A B + C) in the precision of the front.
