@@ -273,10 +273,23 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
     const T lk1 = G[k * m + k + 1];
     for (int r = k + 2 + lane; r < m; r += 64) {
       const T l1 = G[k * m + r], l2 = G[(k + 1) * m + r];
-      for (int c = k + 2; c < m; ++c) {
-        const T u1 = G[c * m + k];
-        const T u2 = cfms(lk1, u1, G[c * m + k + 1]);
-        G[c * m + r] = cfms(l2, u2, cfms(l1, u1, G[c * m + r]));
+      // four columns per round trip: all reads of a batch before its writes
+      constexpr int CB = 4;
+      for (int c0 = k + 2; c0 < m; c0 += CB) {
+        T u1[CB], a2[CB], x[CB];
+#pragma unroll
+        for (int e = 0; e < CB; ++e) {
+          const int c = min(c0 + e, m - 1);
+          u1[e] = G[c * m + k];
+          a2[e] = G[c * m + k + 1];
+          x[e] = G[c * m + r];
+        }
+#pragma unroll
+        for (int e = 0; e < CB; ++e)
+          if (c0 + e < m) {
+            const T u2 = cfms(lk1, u1[e], a2[e]);
+            G[(c0 + e) * m + r] = cfms(l2, u2, cfms(l1, u1[e], x[e]));
+          }
       }
     }
     wave_sync();
