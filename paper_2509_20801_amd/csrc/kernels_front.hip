@@ -314,30 +314,25 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
     //   X_L[r][j] = -(L[r][j] + sum_{j<k<r} X_L[r][k] L[k][j]),
     //   X_U[i][i] = 1/U[i][i],  X_U[i][c] = -X_U[i][i] sum_{i<k<=c} U[i][k] X_U[k][c].
     // The column of L (resp. row of U) a step needs is staged in colbuf first.
+    // Both halves run the same instructions: x = init + sum_k a[k sa] b[k],
+    // with per-lane pointers, strides and ranges (no divergent branches).
     const bool lo = lane < 32;
     const int cl = lo ? lane : lane - 32;
     for (int t = 0; t < p; ++t) {
       const int j = p - 2 - t, ii = p - 1 - t;
-      if (lo) colbuf[cl] = (j >= 0 && cl > j && cl < p) ? G[j * m + cl] : czero<T>();
-      else colbuf[32 + cl] = (cl >= ii && cl < p) ? G[cl * m + ii] : czero<T>();
+      const bool act = lo ? (j >= 0 && cl > j && cl < p) : (cl >= ii && cl < p);
+      colbuf[lane] = act ? (lo ? G[j * m + cl] : G[cl * m + ii]) : czero<T>();
       wave_sync();
-      if (lo) {
-        if (j >= 0 && cl > j && cl < p) {
-          T x = colbuf[cl];
-          for (int k = j + 1; k < cl; ++k) x = cfma(G[k * m + cl], colbuf[k], x);
-          G[j * m + cl] = T{-x.x, -x.y};
-        }
-      } else if (cl >= ii && cl < p) {
-        const T dinv = cdiv(T{(R)1, (R)0}, colbuf[32 + ii]);
-        if (cl == ii) {
-          G[ii * m + ii] = dinv;
-        } else {
-          T x = czero<T>();
-          for (int k = ii + 1; k <= cl; ++k) x = cfma(colbuf[32 + k], G[cl * m + k], x);
-          x = cmul(x, dinv);
-          G[cl * m + ii] = T{-x.x, -x.y};
-        }
-      }
+      const T dinv = cdiv(T{(R)1, (R)0}, colbuf[32 + ii]);
+      const T* a = lo ? G + cl : colbuf + 32;              // L: X_L[cl][k]; U: U[ii][k]
+      const T* b = lo ? colbuf : G + cl * m;               // L: L[k][j];    U: X_U[k][cl]
+      const int sa = lo ? m : 1;
+      const int k0 = lo ? j + 1 : ii + 1, k1 = lo ? cl : cl + 1;
+      T x = lo ? colbuf[cl] : czero<T>();
+      if (act)
+        for (int k = k0; k < k1; ++k) x = cfma(a[k * sa], b[k], x);
+      if (!lo) x = (cl == ii) ? T{-dinv.x, -dinv.y} : cmul(x, dinv);
+      if (act) G[lo ? j * m + cl : cl * m + ii] = T{-x.x, -x.y};
       wave_sync();
     }
   } else {
