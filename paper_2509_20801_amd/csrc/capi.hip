@@ -962,8 +962,11 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
           launch_gs_reduce(st, part, gb, stride, nv, h1, npart, q.sc + 6, nullptr, nullptr);
           launch_gs(st, GS_UPDATE_DOT, q.V, N, nv, h1, w, N, part, npart, nullptr);
           launch_gs_reduce(st, part, gb, stride, nv, h2, npart, q.sc + 3, q.sc + 6, gate);
-          launch_gs(st, GS_UPDATE, q.V, N, nv, h2, w, N, part, npart, gate);
-          launch_gs_final(st, npart, gb, q.sc + 3, h1, h2, nv, gate);
+          // The second update writes v_{j+1} itself, normalised by
+          // |w|^2 = |w1|^2 - |h2|^2 (kept in sc[8]); the Givens step adds h2 to
+          // the column.  With the gate closed, the scale below makes v_{j+1}.
+          launch_gs(st, GS_UPDATE_NORMALIZE, q.V, N, nv, h2, w, N, part, npart, gate,
+                    q.V + (long long)(j + 1) * N, q.sc + 3, q.sc + 8);
         } else {
           launch_mdot(st, q.V, N, nv, w, N, part, npart, nullptr);
           launch_mdot_reduce(st, part, nblk, nv, h1, nullptr);
@@ -979,8 +982,12 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
       }
       {
         Timed t(c, K_UPDATE);
-        launch_scale(st, w, q.sc + 3, q.V + (long long)(j + 1) * N, N);
-        launch_givens(st, q.H, pb->kh1.as<double2>(), q.sc + 3, q.cs, q.sn, q.g, j, m + 1, q.sc + 4);
+        const bool reg = gs_stride(j + 1) > 0;
+        int* gate = pb->flag.as<int>() + 1;
+        launch_scale(st, w, q.sc + 3, q.V + (long long)(j + 1) * N, N, reg ? gate : nullptr);
+        launch_givens(st, q.H, pb->kh1.as<double2>(), q.sc + 3, q.cs, q.sn, q.g, j, m + 1, q.sc + 4,
+                      reg ? pb->kh2.as<double2>() : nullptr, reg ? gate : nullptr,
+                      reg ? q.sc + 8 : nullptr);
       }
       HIP_CHECK(hipMemcpyAsync(q.hp + 16 + 2 * (j & 1), q.sc + 3, 2 * sizeof(double),
                                hipMemcpyDeviceToHost, st));

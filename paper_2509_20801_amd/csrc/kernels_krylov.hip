@@ -187,13 +187,20 @@ template <int K> __device__ inline double wave_fold(double (&a)[K], int lane) {
   return s;
 }
 
-template <int NVM, bool UPD, bool DOT>
+// NRM (with UPD, without DOT): the update of a second pass whose result is
+// final; instead of w it writes v = w / |w| to vout, with |w|^2 taken as
+// nrm_in[0] - |h|^2 (the new w is orthogonal to the basis, so the norm removed
+// is that of the coefficients), which block 0 also stores in nrm_out[0].
+template <int NVM, bool UPD, bool DOT, bool NRM>
 __global__ __launch_bounds__(KT) void k_gs(const double2* __restrict__ V, long long ld, int nv,
                                            const double2* __restrict__ h,
                                            double2* __restrict__ w, long long n,
                                            double* __restrict__ partial,
                                            double* __restrict__ norm_partial,
-                                           const int* __restrict__ gate) {
+                                           const int* __restrict__ gate,
+                                           double2* __restrict__ vout,
+                                           const double* __restrict__ nrm_in,
+                                           double* __restrict__ nrm_out) {
   constexpr int K = 2 * NVM;
   constexpr int EPT = 32 / NVM;                          // entries per thread
   __shared__ double2 hs[NVM];
@@ -218,14 +225,28 @@ __global__ __launch_bounds__(KT) void k_gs(const double2* __restrict__ V, long l
   }
   if (UPD) {
     __syncthreads();
+    double scale = 1.0;
+    if (NRM) {
+      double hh = 0.0;
+      for (int i = 0; i < nv; ++i) hh += hs[i].x * hs[i].x + hs[i].y * hs[i].y;
+      const double n2 = nrm_in[0] - hh;
+      scale = n2 > 0.0 ? 1.0 / sqrt(n2) : 0.0;
+      if (blockIdx.x == 0 && tid == 0) nrm_out[0] = n2 > 0.0 ? n2 : 0.0;
+    }
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
 #pragma unroll
       for (int i = 0; i < NVM; ++i)
         if (i < nv) wr[e] = cfms(v[i][e], hs[i], wr[e]);
       const long long idx = base + (long long)e * KT;
-      if (idx < n) w[idx] = wr[e];
+      if (idx < n) {
+        if (NRM)
+          vout[idx] = make_double2(wr[e].x * scale, wr[e].y * scale);
+        else
+          w[idx] = wr[e];
+      }
     }
+    if (NRM) return;                         // no partials needed
   }
   if (DOT) {
     double a[K];
@@ -335,22 +356,6 @@ __global__ __launch_bounds__(KT) void k_gs_reduce(const double2* __restrict__ pa
   }
 }
 
-// After a second pass (gate[0] != 0 only): out[0] = sum of the norm partials
-// and h1 += h2.
-__global__ __launch_bounds__(KT) void k_gs_final(const double* __restrict__ npart, int nblk,
-                                                 double* __restrict__ out, double2* __restrict__ h1,
-                                                 const double2* __restrict__ h2, int nv,
-                                                 const int* __restrict__ gate) {
-  __shared__ double red[4];
-  if (gate[0] == 0) return;
-  double s = 0.0;
-  strided_sum(threadIdx.x, nblk, [&](int b) { return npart[b]; }, s);
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) out[0] = s;
-  for (int i = threadIdx.x; i < nv; i += KT)
-    h1[i] = make_double2(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
-}
-
 // h1 += h2 when gate[0] != 0 (accumulates the re-orthogonalisation coefficients).
 __global__ void k_hacc(double2* __restrict__ h1, const double2* __restrict__ h2, int nv,
                        const int* __restrict__ gate) {
@@ -361,7 +366,9 @@ __global__ void k_hacc(double2* __restrict__ h1, const double2* __restrict__ h2,
 
 __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
                                               const double* __restrict__ nrm2,
-                                              double2* __restrict__ v, long long n) {
+                                              double2* __restrict__ v, long long n,
+                                              const int* __restrict__ skip) {
+  if (skip && skip[0] != 0) return;
   const double s2 = nrm2[0];
   const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
   for (long long t = (long long)blockIdx.x * KT + threadIdx.x; t < n; t += (long long)gridDim.x * KT) {
@@ -377,21 +384,32 @@ __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
 // The operands are staged in LDS by the whole block (j < GV), so that the
 // sequential rotations by thread 0 wait on no memory round trips.
 constexpr int GV = 256;
+// With gate (and gate[0] != 0): the column is h + h2 and |w|^2 is wnorm2_alt[0],
+// which is also stored to wnorm2[0].
 __global__ __launch_bounds__(64) void k_givens(double2* __restrict__ H, const double2* __restrict__ h,
-                                               const double* __restrict__ wnorm2,
+                                               double* __restrict__ wnorm2,
                                                double* __restrict__ cs, double2* __restrict__ sn,
                                                double2* __restrict__ g, int j, int ldh,
-                                               double* __restrict__ est) {
+                                               double* __restrict__ est,
+                                               const double2* __restrict__ h2,
+                                               const int* __restrict__ gate,
+                                               const double* __restrict__ wnorm2_alt) {
   __shared__ double2 col[GV + 1];
   __shared__ double scs[GV];
   __shared__ double2 ssn[GV];
   const int t = threadIdx.x;
-  for (int i = t; i <= j; i += blockDim.x) col[i] = h[i];
+  const bool second = gate && gate[0] != 0;
+  for (int i = t; i <= j; i += blockDim.x)
+    col[i] = second ? make_double2(h[i].x + h2[i].x, h[i].y + h2[i].y) : h[i];
   for (int i = t; i < j; i += blockDim.x) {
     scs[i] = cs[i];
     ssn[i] = sn[i];
   }
-  if (t == 0) col[j + 1] = make_double2(sqrt(wnorm2[0]), 0.0);
+  if (t == 0) {
+    const double n2 = second ? wnorm2_alt[0] : wnorm2[0];
+    if (second) wnorm2[0] = n2;
+    col[j + 1] = make_double2(sqrt(n2), 0.0);
+  }
   __syncthreads();
   if (t == 0) {
     for (int i = 0; i < j; ++i) {
@@ -503,29 +521,30 @@ void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stri
                      npart, out, ref, gate);
 }
 
-void launch_gs_final(hipStream_t st, const double* npart, int nblk, double* out, double2* h1,
-                     const double2* h2, int nv, const int* gate) {
-  hipLaunchKernelGGL(k_gs_final, dim3(1), dim3(KT), 0, st, npart, nblk, out, h1, h2, nv, gate);
-}
-
 void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
-               double2* w, long long n, double2* partial, double* norm_partial, const int* gate) {
+               double2* w, long long n, double2* partial, double* norm_partial, const int* gate,
+               double2* vout, const double* nrm_in, double* nrm_out) {
   const int nvm = gs_stride(nv);
   STF_REQUIRE(nvm > 0 && nv >= 1, "register Gram-Schmidt pass takes 1..32 basis vectors");
-  STF_REQUIRE(mode >= GS_DOT && mode <= GS_UPDATE, "unknown Gram-Schmidt pass");
+  STF_REQUIRE(mode >= GS_DOT && mode <= GS_UPDATE_NORMALIZE, "unknown Gram-Schmidt pass");
+  STF_REQUIRE(mode != GS_UPDATE_NORMALIZE || (vout && nrm_in && nrm_out),
+              "normalising pass needs its output vector and norms");
   double* pd = reinterpret_cast<double*>(partial);
   const dim3 g(gs_blocks(n, nv)), b(KT);
 #define STF_GS_CASE(M)                                                                         \
   if (nvm == M) {                                                                              \
     if (mode == GS_DOT)                                                                        \
-      hipLaunchKernelGGL((k_gs<M, false, true>), g, b, 0, st, V, ld, nv, h, w, n, pd,          \
-                         norm_partial, gate);                                                  \
+      hipLaunchKernelGGL((k_gs<M, false, true, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,   \
+                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
     else if (mode == GS_UPDATE_DOT)                                                            \
-      hipLaunchKernelGGL((k_gs<M, true, true>), g, b, 0, st, V, ld, nv, h, w, n, pd,           \
-                         norm_partial, gate);                                                  \
+      hipLaunchKernelGGL((k_gs<M, true, true, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,    \
+                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
+    else if (mode == GS_UPDATE)                                                                \
+      hipLaunchKernelGGL((k_gs<M, true, false, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,   \
+                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
     else                                                                                       \
-      hipLaunchKernelGGL((k_gs<M, true, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,          \
-                         norm_partial, gate);                                                  \
+      hipLaunchKernelGGL((k_gs<M, true, false, true>), g, b, 0, st, V, ld, nv, h, w, n, pd,    \
+                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
     return;                                                                                    \
   }
   STF_GS_CASE(8)
@@ -549,14 +568,17 @@ void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const i
   hipLaunchKernelGGL(k_hacc, dim3(1), dim3(256), 0, st, h1, h2, nv, gate);
 }
 
-void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n) {
-  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n);
+void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n,
+                  const int* skip) {
+  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n, skip);
 }
 
-void launch_givens(hipStream_t st, double2* H, const double2* h, const double* wnorm2,
-                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out) {
+void launch_givens(hipStream_t st, double2* H, const double2* h, double* wnorm2,
+                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out,
+                   const double2* h2, const int* gate, const double* wnorm2_alt) {
   STF_REQUIRE(j >= 0 && j < GV, "Givens step beyond the staged column");
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h, wnorm2, cs, sn, g, j, ldh, est_out);
+  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h, wnorm2, cs, sn, g, j, ldh, est_out,
+                     h2, gate, wnorm2_alt);
 }
 
 void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n) {

@@ -228,18 +228,18 @@ void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv
 //   GS_DOT:        partial = V^H w, |w|^2 partials
 //   GS_UPDATE_DOT: w -= V h, then partial = V^H w and |w|^2 of the new w
 //   GS_UPDATE:     w -= V h, |w|^2 partials
-enum { GS_DOT = 0, GS_UPDATE_DOT = 1, GS_UPDATE = 2 };
+//   GS_UPDATE_NORMALIZE: w -= V h, then vout = w / |w| with |w|^2 = nrm_in - |h|^2
+//                  (stored to nrm_out; the pass after which w is orthogonal to V)
+enum { GS_DOT = 0, GS_UPDATE_DOT = 1, GS_UPDATE = 2, GS_UPDATE_NORMALIZE = 3 };
 int gs_blocks(long long n, int nv);   // workgroups of a pass over a basis of nv vectors
 int gs_stride(int nv);    // 8, 16 or 32; 0 when nv > 32 (use launch_mdot / launch_mupdate)
 void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
-               double2* w, long long n, double2* partial, double* norm_partial, const int* gate);
+               double2* w, long long n, double2* partial, double* norm_partial, const int* gate,
+               double2* vout = nullptr, const double* nrm_in = nullptr, double* nrm_out = nullptr);
 // Between the passes: h[i] = sum_b partial[b * stride + i] (i < nv) and
 // out = sum of the nblk norm partials, with ref also gate = (out < ref/2).
 void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
                       double2* h, const double* npart, double* out, const double* ref, int* gate);
-// After the gated second pass: out = sum of norm partials, h1 += h2.
-void launch_gs_final(hipStream_t st, const double* npart, int nblk, double* out, double2* h1,
-                     const double2* h2, int nv, const int* gate);
 // w -= V h (+ |w|^2 partials).
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
                     double2* w, long long n, double* norm_partial, const int* gate);
@@ -247,11 +247,14 @@ void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, cons
 void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* out,
                         const double* ref, int* gate, int decide);
 void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate);
+// v = w / sqrt(nrm2) (skipped when skip and skip[0] != 0)
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v,
-                  long long n);
+                  long long n, const int* skip = nullptr);
 // Givens step j of FGMRES on device (single thread).  H column-major (ldh = m+1).
-void launch_givens(hipStream_t st, double2* H, const double2* h, const double* wnorm2,
-                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out);
+void launch_givens(hipStream_t st, double2* H, const double2* h, double* wnorm2,
+                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out,
+                   const double2* h2 = nullptr, const int* gate = nullptr,
+                   const double* wnorm2_alt = nullptr);
 // y = R^{-1} g (k x k upper triangular, column-major ldh).
 void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
                      int ldh);
