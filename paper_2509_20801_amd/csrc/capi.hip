@@ -352,6 +352,13 @@ void build_device_state(stf_problem pb) {
     d.p = f.p;
     d.q = f.q;
     d.sub = rc.sub;
+    d.gx0 = s.ox0 + f.sx0;
+    d.gy0 = s.oy0 + f.sy0;
+    d.sw = f.sw;
+    d.ix0 = s.ix0;
+    d.ix1 = s.ix1;
+    d.iy0 = s.iy0;
+    d.iy1 = s.iy1;
     d.var_off = sh_var[s.shape] + f.var_off;
     d.cmap_off = sh_cmap[s.shape] + f.cmap_off;
     d.ent_off = sh_ent[s.shape] + f.ent_off;

@@ -189,20 +189,27 @@ std::shared_ptr<SymShape> build_symbolic(int nxl, int nyl, int leaf) {
     int w = b.x1 - b.x0, h = b.y1 - b.y0;
     std::vector<int> sep;
     std::vector<Box> sub;
+    int sx0 = b.x0, sy0 = b.y0, sw = w;        // the separator's box (row by row)
     if (w * h <= leaf || (w <= 2 && h <= 2)) {
       for (int y = b.y0; y < b.y1; ++y)
         for (int x = b.x0; x < b.x1; ++x) sep.push_back(x + y * nxl);
     } else if (w >= h) {
       int xs = b.x0 + w / 2;
       for (int y = b.y0; y < b.y1; ++y) sep.push_back(xs + y * nxl);
+      sx0 = xs;
+      sw = 1;
       sub.push_back({b.x0, xs, b.y0, b.y1});
       sub.push_back({xs + 1, b.x1, b.y0, b.y1});
     } else {
       int ys = b.y0 + h / 2;
       for (int x = b.x0; x < b.x1; ++x) sep.push_back(x + ys * nxl);
+      sy0 = ys;
       sub.push_back({b.x0, b.x1, b.y0, ys});
       sub.push_back({b.x0, b.x1, ys + 1, b.y1});
     }
+    for (size_t i = 0; i < sep.size(); ++i)
+      STF_REQUIRE(sep[i] == sx0 + (int)i % sw + (sy0 + (int)i / sw) * nxl,
+                  "internal: separator not a row-by-row box");
     std::vector<int> halo;
     if (b.x0 > 0)
       for (int y = b.y0; y < b.y1; ++y) halo.push_back(b.x0 - 1 + y * nxl);
@@ -214,6 +221,9 @@ std::shared_ptr<SymShape> build_symbolic(int nxl, int nyl, int leaf) {
       for (int x = b.x0; x < b.x1; ++x) halo.push_back(x + b.y1 * nxl);
     {
       SymFront& f = sh->fronts[idx];
+      f.sx0 = sx0;
+      f.sy0 = sy0;
+      f.sw = sw;
       f.p = (int)sep.size();
       f.q = (int)halo.size();
       f.var_off = (int)sh->vars.size();

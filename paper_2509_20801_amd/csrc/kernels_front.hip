@@ -901,10 +901,8 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   // loaded before any is added).
   long long gidx = -1;
   if (lane < p) {
-    const SubDev s = a.subs[f.sub];
-    int node = a.vars[f.var_off + lane];
-    int gx = s.ox0 + node % s.nxl, gy = s.oy0 + node / s.nxl;
-    if (gx >= s.ix0 && gx < s.ix1 && gy >= s.iy0 && gy < s.iy1) gidx = (long long)gy * a.nx + gx;
+    const int gx = f.gx0 + lane % f.sw, gy = f.gy0 + lane / f.sw;
+    if (gx >= f.ix0 && gx < f.ix1 && gy >= f.iy0 && gy < f.iy1) gidx = (long long)gy * a.nx + gx;
   }
   int d0[RPL], d1[RPL];
 #pragma unroll
@@ -1055,13 +1053,11 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   const bool act = g < G && rr < m;
   ColPrefetch<T, KP> pf;
   pf.load(L, LowerAt{m, rr}, g, 0, act ? min(rr, p) : 0, G);
-  const SubDev sd = a.subs[f.sub];
   const int* perm = piv + f.piv_off;
   auto global_row = [&](int i) -> long long {
-    const int node = a.vars[f.var_off + i];
-    const int gx = sd.ox0 + node % sd.nxl, gy = sd.oy0 + node / sd.nxl;
-    return (gx >= sd.ix0 && gx < sd.ix1 && gy >= sd.iy0 && gy < sd.iy1) ? (long long)gy * a.nx + gx
-                                                                         : -1;
+    const int gx = f.gx0 + i % f.sw, gy = f.gy0 + i / f.sw;
+    return (gx >= f.ix0 && gx < f.ix1 && gy >= f.iy0 && gy < f.iy1) ? (long long)gy * a.nx + gx
+                                                                     : -1;
   };
   if (m <= 2 * NTL) {
     // Every global load of the right-hand side first (two rows per thread),

@@ -63,6 +63,9 @@ struct SymFront {
   int cmap_off = 0;         // cmap[cmap_off .. +q): position of each update var in the parent front
   int ent_off = 0, ent_cnt = 0;   // original matrix entries assembled into this front
   int child_off = 0, nchild = 0;  // children[child_off ..)
+  int sx0 = 0, sy0 = 0, sw = 1;   // the separator is the local box at (sx0, sy0) of width
+                                  // sw, its nodes listed row by row (vars[var_off + i] =
+                                  // sx0 + i % sw + (sy0 + i / sw) * nxl)
 };
 
 // Packed original entry: front row, front column, local node, stencil direction.
@@ -141,6 +144,12 @@ struct FrontDev {
   int cvec[2];              // children: vec_off + p (start of their update parts)
   int ccmap[2];             // children: cmap_off
   int cq[2];                // children: q
+  // The separator's global node box (origin gx0, gy0; width sw; row by row) and
+  // the subdomain's I_k: row i < p of the front is global node
+  // (gx0 + i % sw, gy0 + i / sw), restricted to I_k by the forward sweep
+  // without a load of its local index.
+  int gx0, gy0, sw;
+  int ix0, ix1, iy0, iy1;
 };
 
 // Right-hand sides swept together (1..MAX_RHS): each has its own global input
