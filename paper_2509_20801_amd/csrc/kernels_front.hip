@@ -18,9 +18,11 @@
 // phase) with no serial chain over the rows.
 //
 // Front vectors: each front owns m entries at vec_off.  The forward sweep
-// leaves [y_p ; update contribution] there, the backward sweep [x_p ; x_q],
-// from which the children gather their x_q.  Every write has one owner, so the
-// sweeps are deterministic without atomics.
+// leaves [y_p ; update contribution] there; in the backward sweep a front
+// reads y_p and the x_q that its parent put in place of the update
+// contribution, and puts its own [x_p ; x_q] into the update parts of its
+// children.  Every write has one owner, so the sweeps are deterministic
+// without atomics.
 //
 // Two team sizes: fronts of a level whose largest order fits a wavefront are
 // handled one per 64-lane workgroup with no workgroup barriers (lane = row);
@@ -985,20 +987,25 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   ColPrefetch<T, KP> pf;
   pf.load(U, UpperAt{p, r}, g, r, r < p ? m : 0, G);
   const int var = lane < p ? a.vars[f.var_off + lane] : 0;
-  int ci[2];
+  // The children's maps (a child's update rows are rows of this front, so
+  // q_child <= m <= 128), for the scatter of this front's vector at the end.
+  int cm[2][2];
 #pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int idx = lane + 64 * i;
-    ci[i] = idx < q ? a.cmap[f.cmap_off + idx] : -1;
-  }
-  // [y_p ; x_q]: y_p from the forward sweep, x_q from the parent's vector.
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = lane + 64 * i;
+      cm[c][i] = (c < f.nchild && idx < f.cq[c]) ? a.cmap[f.ccmap[c] + idx] : -1;
+    }
+  // [y_p ; x_q], both from this front's own vector: y_p from the forward sweep,
+  // x_q put there by the parent's backward sweep.
   T y[NR], xq[NR][2];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
-    const T* vs = vec + s * rs.vec_stride;
-    y[s] = lane < p ? vs[f.vec_off + lane] : czero<T>();
+    const T* vs = vec + s * rs.vec_stride + f.vec_off;
+    y[s] = lane < p ? vs[lane] : czero<T>();
 #pragma unroll
-    for (int i = 0; i < 2; ++i) xq[s][i] = ci[i] >= 0 ? vs[f.pvec + ci[i]] : czero<T>();
+    for (int i = 0; i < 2; ++i) xq[s][i] = lane + 64 * i < q ? vs[p + lane + 64 * i] : czero<T>();
   }
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
@@ -1009,19 +1016,29 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   }
   wave_sync();
   const long long uo = a.subs[f.sub].u_off;
+  T xp[NR];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     T acc = pf.dot(U, UpperAt{p, r}, g, r, r < p ? m : 0, G, sh[wv][s]);
     for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-    T* fv = vec + s * rs.vec_stride + f.vec_off;
-    if (lane < p) {                        // lane < p <= W: g = 0, r = lane
-      fv[lane] = acc;
-      u[s * rs.u_stride + uo + var] = acc;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-      if (lane + 64 * i < q) fv[p + lane + 64 * i] = xq[s][i];
+    xp[s] = acc;
   }
+  wave_sync();
+#pragma unroll
+  for (int s = 0; s < NR; ++s)
+    if (lane < p) {                        // lane < p <= W: g = 0, r = lane
+      sh[wv][s][lane] = xp[s];
+      u[s * rs.u_stride + uo + var] = xp[s];
+    }
+  wave_sync();
+  // This front's vector [x_p ; x_q] into the update slots of its children.
+#pragma unroll
+  for (int s = 0; s < NR; ++s)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+        if (cm[c][i] >= 0) vec[s * rs.vec_stride + f.cvec[c] + lane + 64 * i] = sh[wv][s][cm[c][i]];
 }
 
 // ---------------------------------------------------------------------------
@@ -1189,37 +1206,37 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   ColPrefetch<T, KP> pf;
   pf.load(U, UpperAt{p, rr}, g, rr, act ? m : 0, G);
   const int* vars = a.vars + f.var_off;
-  const int var = tid < p ? vars[tid] : 0;       // the row this thread stores (issued early)
-  for (int i = tid; i < p; i += NTL)
+  // the row this thread stores: rr (one column group) or tid (summed groups)
+  const int row = G == 1 ? rr : tid;
+  const bool has_row = G == 1 ? act : tid < p;
+  const int var = has_row ? vars[row] : 0;
+  // The children's maps (issued early; two entries per thread, the rest later).
+  int cm[2][2];
+#pragma unroll
+  for (int c = 0; c < 2; ++c)
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + NTL * i;
+      cm[c][i] = (c < f.nchild && idx < f.cq[c]) ? a.cmap[f.ccmap[c] + idx] : -1;
+    }
+  // [y_p ; x_q]: this front's own vector (x_q put there by the parent).
+  for (int i = tid; i < m; i += NTL)
 #pragma unroll
     for (int s = 0; s < NR; ++s) vl[s * mm + i] = vec[s * rs.vec_stride + f.vec_off + i];
-  if (f.parent >= 0) {
-    const int* cm = a.cmap + f.cmap_off;
-    for (int i = tid; i < f.q; i += NTL) {
-      const int c = cm[i];
-#pragma unroll
-      for (int s = 0; s < NR; ++s) vl[s * mm + p + i] = vec[s * rs.vec_stride + f.pvec + c];
-    }
-  }
   __syncthreads();
   const long long uo = a.subs[f.sub].u_off;
   T acc[NR];
 #pragma unroll
   for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(U, UpperAt{p, rr}, g, rr, m, G, vl + s * mm) : czero<T>();
   if (G == 1) {
+    // rows beyond NTL (p > NTL): written to the front vector now, read back below
+    for (int r = tid + NTL; r < p; r += NTL)
 #pragma unroll
-    for (int s = 0; s < NR; ++s) {
-      T* fv = vec + s * rs.vec_stride + f.vec_off;
-      if (act) {
-        fv[rr] = acc[s];
-        u[s * rs.u_stride + uo + var] = acc[s];
-      }
-      for (int r = tid + NTL; r < p; r += NTL) {
+      for (int s = 0; s < NR; ++s) {
         const T x = gather_dot(U, UpperAt{p, r}, 0, r, m, 1, vl + s * mm);
-        fv[r] = x;
+        vec[s * rs.vec_stride + f.vec_off + r] = x;
         u[s * rs.u_stride + uo + vars[r]] = x;
       }
-    }
   } else {
 #pragma unroll
     for (int s = 0; s < NR; ++s) scr[s * NTL + tid] = acc[s];
@@ -1229,14 +1246,37 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
       for (int s = 0; s < NR; ++s) {
         T sum = czero<T>();
         for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * p + tid]);
-        vec[s * rs.vec_stride + f.vec_off + tid] = sum;
-        u[s * rs.u_stride + uo + var] = sum;
+        acc[s] = sum;
       }
     }
   }
-  for (int i = p + tid; i < m; i += NTL)
+  __syncthreads();                        // every read of y_p by the products is done
+  if (has_row)
 #pragma unroll
-    for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.vec_off + i] = vl[s * mm + i];
+    for (int s = 0; s < NR; ++s) {
+      vl[s * mm + row] = acc[s];
+      u[s * rs.u_stride + uo + var] = acc[s];
+    }
+  for (int r = tid + NTL; G == 1 && r < p; r += NTL)
+#pragma unroll
+    for (int s = 0; s < NR; ++s) vl[s * mm + r] = vec[s * rs.vec_stride + f.vec_off + r];
+  __syncthreads();
+  // This front's vector [x_p ; x_q] into the update slots of its children.
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+      if (cm[c][i] >= 0)
+#pragma unroll
+        for (int s = 0; s < NR; ++s)
+          vec[s * rs.vec_stride + f.cvec[c] + tid + NTL * i] = vl[s * mm + cm[c][i]];
+    if (c < f.nchild)
+      for (int idx = tid + 2 * NTL; idx < f.cq[c]; idx += NTL) {
+        const int d = a.cmap[f.ccmap[c] + idx];
+#pragma unroll
+        for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.cvec[c] + idx] = vl[s * mm + d];
+      }
+  }
 }
 
 // z_s = sum_k P_k u_k for each right-hand side s: each global node adds the
