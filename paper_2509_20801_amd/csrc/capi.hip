@@ -380,10 +380,9 @@ void build_device_state(stf_problem pb) {
   pb->upk_elems = upk_off;
   pb->lpk_elems = lpk_off;
   STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
-  // Embedded parent/children vector offsets (all offsets are known now).
+  // Embedded children vector offsets and maps (all offsets are known now).
   for (size_t t = 0; t < fr.size(); ++t) {
     FrontDev& d = fr[t];
-    d.pvec = d.parent >= 0 ? fr[d.parent].vec_off : -1;
     for (int c = 0; c < 2; ++c) {
       if (c < d.nchild) {
         const FrontDev& cf = fr[kids[d.child_off + c]];

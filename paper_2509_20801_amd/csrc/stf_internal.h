@@ -126,8 +126,8 @@ struct SubDev {
 
 // Front instances are stored in tree-level order (deepest level last within
 // the array's level ranges, largest fronts first within a level), so a level
-// is the contiguous range [first, first + n).  Children and parent vector
-// offsets are embedded so that the sweeps read one descriptor per front.
+// is the contiguous range [first, first + n).  The children's vector offsets
+// and maps are embedded so that the sweeps read one descriptor per front.
 struct FrontDev {
   long long fac_off;        // element offset of the m x m front (column-major)
   long long lpk_off;        // element offset of the packed forward operator
@@ -140,7 +140,6 @@ struct FrontDev {
   int ent_off, ent_cnt;     // into the concatenated entries
   int parent;               // instance index or -1
   int child_off, nchild;    // into the instance children array (nchild <= 2)
-  int pvec;                 // parent's vec_off (-1 for a root)
   int cvec[2];              // children: vec_off + p (start of their update parts)
   int ccmap[2];             // children: cmap_off
   int cq[2];                // children: q
