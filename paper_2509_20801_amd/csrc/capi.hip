@@ -62,6 +62,7 @@ struct stf_ctx_s {
   double total_ms[STF_K_COUNT] = {};
   int64_t launches[STF_K_COUNT] = {};
   double* pinned = nullptr;     // pinned host staging: 64 doubles per right-hand side
+  double* pinned_dev = nullptr; // the same memory as the device addresses it
   hipEvent_t iter_ev[2] = {nullptr, nullptr};   // per-iteration estimate copies
   stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
 
@@ -829,14 +830,15 @@ void nn_initial_guess(stf_problem pb, stf_nn nn, const double2* b, double2* x0) 
 
 // Per right-hand side state of the lockstep FGMRES.  Device scalars sc:
 // [0] |b|^2, [2] |r|^2, [3] |w|^2, [4] residual estimate; pinned host hp:
-// [0..3] copies of sc, [8..9] g_0 staging, [16..19] estimates of the last two
-// iterations.
+// [0..3] copies of sc, [8..9] g_0 staging, [16..19] |w|^2 and the estimate of
+// the last two iterations (written by the Givens step itself through hpd, the
+// device address of hp).
 struct RhsRun {
   const double2* b = nullptr;
   double2* x = nullptr;
   double2 *V = nullptr, *Z = nullptr, *r = nullptr, *H = nullptr, *g = nullptr, *y = nullptr,
           *sn = nullptr;
-  double *cs = nullptr, *sc = nullptr, *hp = nullptr;
+  double *cs = nullptr, *sc = nullptr, *hp = nullptr, *hpd = nullptr;
   stf_solve_info* info = nullptr;
   double bnorm = 0.0, rnorm = 0.0, relres_guess = 0.0;
   int used_learned = 0, it = 0, restarts = 0, hlen = 0, k = 0, launched = 0;
@@ -883,6 +885,7 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
     q.cs = pb->kcs.as<double>() + (long long)s * m;
     q.sc = pb->scal.as<double>() + 16 * (s + 1);
     q.hp = c->pinned + 64 * s;
+    q.hpd = c->pinned_dev + 64 * s;
     q.info = info ? info + s : nullptr;
   }
   // Initial guesses and residuals.
@@ -990,13 +993,11 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
         Timed t(c, K_UPDATE);
         const bool reg = gs_stride(j + 1) > 0;
         int* gate = pb->flag.as<int>() + 1;
-        launch_scale(st, w, q.sc + 3, q.V + (long long)(j + 1) * N, N, reg ? gate : nullptr);
-        launch_givens(st, q.H, pb->kh1.as<double2>(), q.sc + 3, q.cs, q.sn, q.g, j, m + 1, q.sc + 4,
-                      reg ? pb->kh2.as<double2>() : nullptr, reg ? gate : nullptr,
-                      reg ? q.sc + 8 : nullptr);
+        launch_scale_givens(st, w, q.V + (long long)(j + 1) * N, N, q.H, pb->kh1.as<double2>(),
+                            q.sc + 3, q.cs, q.sn, q.g, j, m + 1, q.sc + 4,
+                            reg ? pb->kh2.as<double2>() : nullptr, reg ? gate : nullptr,
+                            reg ? q.sc + 8 : nullptr, q.hpd + 16 + 2 * (j & 1));
       }
-      HIP_CHECK(hipMemcpyAsync(q.hp + 16 + 2 * (j & 1), q.sc + 3, 2 * sizeof(double),
-                               hipMemcpyDeviceToHost, st));
     }
     HIP_CHECK(hipEventRecord(c->iter_ev[j & 1], st));
   };
@@ -1148,7 +1149,10 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
       HIP_CHECK(hipStreamCreate(&c->stream));
       c->own_stream = true;
     }
-    HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * MAX_RHS * sizeof(double), hipHostMallocDefault));
+    // Coherent: the Givens kernel writes its estimates here, and the host reads
+    // them once the iteration's event has completed.
+    HIP_CHECK(hipHostMalloc((void**)&c->pinned, 64 * MAX_RHS * sizeof(double), hipHostMallocCoherent));
+    HIP_CHECK(hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0));
     for (int e = 0; e < 2; ++e)
       HIP_CHECK(hipEventCreateWithFlags(&c->iter_ev[e], hipEventDisableTiming));
   });

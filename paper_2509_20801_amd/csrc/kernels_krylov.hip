@@ -364,17 +364,23 @@ __global__ void k_hacc(double2* __restrict__ h1, const double2* __restrict__ h2,
     h1[i] = make_double2(h1[i].x + h2[i].x, h1[i].y + h2[i].y);
 }
 
+__device__ inline void scale_body(const double2* __restrict__ w, const double* __restrict__ nrm2,
+                                  double2* __restrict__ v, long long n, const int* __restrict__ skip,
+                                  int blk, int nblk) {
+  if (skip && skip[0] != 0) return;
+  const double s2 = nrm2[0];
+  const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+  for (long long t = (long long)blk * KT + threadIdx.x; t < n; t += (long long)nblk * KT) {
+    double2 a = w[t];
+    v[t] = make_double2(a.x * inv, a.y * inv);
+  }
+}
+
 __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
                                               const double* __restrict__ nrm2,
                                               double2* __restrict__ v, long long n,
                                               const int* __restrict__ skip) {
-  if (skip && skip[0] != 0) return;
-  const double s2 = nrm2[0];
-  const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-  for (long long t = (long long)blockIdx.x * KT + threadIdx.x; t < n; t += (long long)gridDim.x * KT) {
-    double2 a = w[t];
-    v[t] = make_double2(a.x * inv, a.y * inv);
-  }
+  scale_body(w, nrm2, v, n, skip, blockIdx.x, gridDim.x);
 }
 
 // One Givens step of FGMRES for column j.
@@ -386,14 +392,15 @@ __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
 constexpr int GV = 256;
 // With gate (and gate[0] != 0): the column is h + h2 and |w|^2 is wnorm2_alt[0],
 // which is also stored to wnorm2[0].
-__global__ __launch_bounds__(64) void k_givens(double2* __restrict__ H, const double2* __restrict__ h,
+__device__ inline void givens_body(double2* __restrict__ H, const double2* __restrict__ h,
                                                double* __restrict__ wnorm2,
                                                double* __restrict__ cs, double2* __restrict__ sn,
                                                double2* __restrict__ g, int j, int ldh,
                                                double* __restrict__ est,
                                                const double2* __restrict__ h2,
                                                const int* __restrict__ gate,
-                                               const double* __restrict__ wnorm2_alt) {
+                                               const double* __restrict__ wnorm2_alt,
+                                               double* __restrict__ host_out) {
   __shared__ double2 col[GV + 1];
   __shared__ double scs[GV];
   __shared__ double2 ssn[GV];
@@ -446,10 +453,38 @@ __global__ __launch_bounds__(64) void k_givens(double2* __restrict__ H, const do
     g[j + 1] = g1;
     g[j] = make_double2(c * gj.x, c * gj.y);
     est[0] = hypot(g1.x, g1.y);
+    if (host_out) {                          // |w|^2 and the estimate, straight to the host
+      host_out[0] = second ? wnorm2_alt[0] : wnorm2[0];
+      host_out[1] = est[0];
+    }
   }
   __syncthreads();
   double2* Hc = H + (long long)j * ldh;
   for (int i = t; i <= j + 1; i += blockDim.x) Hc[i] = col[i];
+}
+
+// The end of an Arnoldi step in one launch: block 0 takes the Givens step,
+// the other blocks form v_{j+1} = w / |w| (skipped when the gate is set: the
+// second Gram-Schmidt update wrote it).  The Givens step writes |w| only when
+// the gate is set, the scale reads it only when it is not, so the blocks do
+// not race.
+__global__ __launch_bounds__(KT) void k_scale_givens(const double2* __restrict__ w,
+                                                     double2* __restrict__ v, long long n,
+                                                     double2* __restrict__ H,
+                                                     const double2* __restrict__ h,
+                                                     double* __restrict__ wnorm2,
+                                                     double* __restrict__ cs,
+                                                     double2* __restrict__ sn,
+                                                     double2* __restrict__ g, int j, int ldh,
+                                                     double* __restrict__ est,
+                                                     const double2* __restrict__ h2,
+                                                     const int* __restrict__ gate,
+                                                     const double* __restrict__ wnorm2_alt,
+                                                     double* __restrict__ host_out) {
+  if (blockIdx.x == 0)
+    givens_body(H, h, wnorm2, cs, sn, g, j, ldh, est, h2, gate, wnorm2_alt, host_out);
+  else
+    scale_body(w, wnorm2, v, n, gate, blockIdx.x - 1, gridDim.x - 1);
 }
 
 __global__ void k_trisolve(const double2* __restrict__ H, const double2* __restrict__ g,
@@ -573,12 +608,13 @@ void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2*
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n, skip);
 }
 
-void launch_givens(hipStream_t st, double2* H, const double2* h, double* wnorm2,
-                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out,
-                   const double2* h2, const int* gate, const double* wnorm2_alt) {
+void launch_scale_givens(hipStream_t st, const double2* w, double2* v, long long n, double2* H,
+                         const double2* h, double* wnorm2, double* cs, double2* sn, double2* g,
+                         int j, int ldh, double* est_out, const double2* h2, const int* gate,
+                         const double* wnorm2_alt, double* host_out) {
   STF_REQUIRE(j >= 0 && j < GV, "Givens step beyond the staged column");
-  hipLaunchKernelGGL(k_givens, dim3(1), dim3(64), 0, st, H, h, wnorm2, cs, sn, g, j, ldh, est_out,
-                     h2, gate, wnorm2_alt);
+  hipLaunchKernelGGL(k_scale_givens, dim3(grid_for(n) + 1), dim3(KT), 0, st, w, v, n, H, h, wnorm2,
+                     cs, sn, g, j, ldh, est_out, h2, gate, wnorm2_alt, host_out);
 }
 
 void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n) {

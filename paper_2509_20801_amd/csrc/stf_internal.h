@@ -258,11 +258,15 @@ void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const i
 // v = w / sqrt(nrm2) (skipped when skip and skip[0] != 0)
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v,
                   long long n, const int* skip = nullptr);
-// Givens step j of FGMRES on device (single thread).  H column-major (ldh = m+1).
-void launch_givens(hipStream_t st, double2* H, const double2* h, double* wnorm2,
-                   double* cs, double2* sn, double2* g, int j, int ldh, double* est_out,
-                   const double2* h2 = nullptr, const int* gate = nullptr,
-                   const double* wnorm2_alt = nullptr);
+// The end of Arnoldi step j in one launch: Givens step j of FGMRES on device
+// (H column-major, ldh = m+1; with gate[0] != 0 the column is h + h2 and |w|^2
+// is wnorm2_alt[0], stored to wnorm2[0]) and v = w / |w| (skipped when
+// gate[0] != 0).  |w|^2 and the residual estimate also go to host_out[0..1]
+// (device-visible pinned host memory) when it is given.
+void launch_scale_givens(hipStream_t st, const double2* w, double2* v, long long n, double2* H,
+                         const double2* h, double* wnorm2, double* cs, double2* sn, double2* g,
+                         int j, int ldh, double* est_out, const double2* h2, const int* gate,
+                         const double* wnorm2_alt, double* host_out);
 // y = R^{-1} g (k x k upper triangular, column-major ldh).
 void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
                      int ldh);
