@@ -917,7 +917,6 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     const T* vs = vec + s * rs.vec_stride;
-    val[s] = gidx >= 0 ? from_d2<T>(rs.v[s][gidx]) : czero<T>();
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
       const int idx = lane + 64 * i;
@@ -927,6 +926,9 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
       c1[s][i] = (f.nchild > 1 && idx < f.cq[1]) ? vs[f.cvec[1] + idx] : czero<T>();
     }
   }
+  // R^I v last: its conversion to T waits for every load issued before it.
+#pragma unroll
+  for (int s = 0; s < NR; ++s) val[s] = gidx >= 0 ? from_d2<T>(rs.v[s][gidx]) : czero<T>();
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     sh[wv][s][lane] = val[s];
@@ -1097,12 +1099,17 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
         const T* vs = vec + s * rs.vec_stride;
-        bv[u][s] = gidx[u] >= 0 ? from_d2<T>(rs.v[s][gidx[u]]) : czero<T>();
         // predicated on the position, not on the loaded index (no chain)
         c0[u][s] = (f.nchild > 0 && i < f.cq[0]) ? vs[f.cvec[0] + i] : czero<T>();
         c1[u][s] = (f.nchild > 1 && i < f.cq[1]) ? vs[f.cvec[1] + i] : czero<T>();
       }
     }
+    // R^I v last: its conversion to T waits for every load issued before it.
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int s = 0; s < NR; ++s)
+        bv[u][s] = gidx[u] >= 0 ? from_d2<T>(rs.v[s][gidx[u]]) : czero<T>();
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       const int i = tid + u * NTL;
