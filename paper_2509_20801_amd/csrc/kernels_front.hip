@@ -134,6 +134,64 @@ __device__ inline void assemble_front(const LevelArgs& a, const T* __restrict__ 
   }
 }
 
+// The same front assembled in one pass, for fronts in global memory: every
+// entry of G is written once, as the sum of the children's Schur complements
+// that map to it (through inverse child maps kept in LDS, icm: 2 m ints), and
+// the original entries are added after.  No zero fill and no read-modify-write
+// of G by the extend-add.  The sum is taken in the order child 0, child 1,
+// original entry.
+template <typename T>
+__device__ inline void assemble_front_gather(const LevelArgs& a, const T* __restrict__ fac,
+                                             const FrontDev& f, T* __restrict__ G, int tid,
+                                             int nthr, int* icm) {
+  const int m = f.p + f.q;
+  for (int t = tid; t < 2 * m; t += nthr) icm[t] = -1;
+  __syncthreads();
+  const T* S[2] = {fac, fac};                                        // F22 of the children
+  int ld[2] = {0, 0};
+#pragma unroll
+  for (int ci = 0; ci < 2; ++ci) {
+    if (ci < f.nchild) {
+      const FrontDev cf = a.fronts[a.children[f.child_off + ci]];
+      const int mc = cf.p + cf.q;
+      S[ci] = fac + cf.fac_off + (long long)cf.p * mc + cf.p;
+      ld[ci] = mc;
+      const int* cm = a.cmap + cf.cmap_off;
+      for (int i = tid; i < cf.q; i += nthr) icm[ci * m + cm[i]] = i;
+    }
+  }
+  __syncthreads();
+  constexpr int UB = 8;
+  const int mm = m * m;                                              // m <= 46340
+  for (int t0 = tid; t0 < mm; t0 += nthr * UB) {
+    T v0[UB], v1[UB];
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int t = t0 + u * nthr;
+      const int c = t / m, r = t - c * m;                            // r fastest
+      const bool ok = t < mm;
+      const int r0 = ok ? icm[r] : -1, c0 = ok ? icm[c] : -1;
+      const int r1 = ok ? icm[m + r] : -1, c1 = ok ? icm[m + c] : -1;
+      v0[u] = (r0 >= 0 && c0 >= 0) ? S[0][(long long)c0 * ld[0] + r0] : czero<T>();
+      v1[u] = (r1 >= 0 && c1 >= 0) ? S[1][(long long)c1 * ld[1] + r1] : czero<T>();
+    }
+#pragma unroll
+    for (int u = 0; u < UB; ++u) {
+      const int t = t0 + u * nthr;
+      if (t < mm) G[t] = cadd(v0[u], v1[u]);
+    }
+  }
+  __syncthreads();
+  const SubDev s = a.subs[f.sub];
+  for (int t = tid; t < f.ent_cnt; t += nthr) {
+    SymEntry e = a.ents[f.ent_off + t];
+    int r = e.rc & 0xffff, c = (e.rc >> 16) & 0xffff;
+    const long long idx = (long long)c * m + r;
+    G[idx] = cadd(G[idx], from_d2<T>(local_coef(a, s, e.nd >> 3, e.nd & 7)));
+  }
+  __syncthreads();
+}
+
 // Pivot choice for column k over rows [k, pend) with amax over [k, nrow) of a
 // column-major column `col`; one wavefront, result in every lane.
 template <typename T>
@@ -494,7 +552,8 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
   const int m = f.p + f.q, p = f.p, ldp = a.max_m;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   T* F = fac + f.fac_off;
-  assemble_front<T>(a, fac, f, F, tid, NTF, [] { __syncthreads(); });
+  // The inverse child maps use the panel's LDS (2 max_m ints <= max_m NB T).
+  assemble_front_gather<T>(a, fac, f, F, tid, NTF, reinterpret_cast<int*>(smem_raw));
   int* ip = piv + f.piv_off;
 
   for (int kb = 0; kb < p; kb += NB) {
