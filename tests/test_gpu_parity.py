@@ -84,6 +84,30 @@ def test_round_c64_matches_oracle(stf, ctx, case):
     assert _rel(pb.precond(v), B.apply(v.ravel())) < 2e-4
 
 
+# Degenerate shapes: the smallest grid (one front), strips four nodes wide,
+# blocks without overlap, blocks only just wider than overlap + local PML;
+# leaf_size 1 makes every separator a single node (the deepest trees).
+DEGENERATE = {
+    "3x3": dict(nx=3, ny=3, pml=0, px=1, py=1, overlap=0, local_pml=1),
+    "strip_4x29": dict(nx=4, ny=29, pml=0, px=1, py=3, overlap=1, local_pml=2),
+    "no_overlap_33x5": dict(nx=33, ny=5, pml=0, px=4, py=1, overlap=0, local_pml=1),
+    "tight_6x6": dict(nx=6, ny=6, pml=0, px=2, py=2, overlap=1, local_pml=1),
+}
+
+
+@pytest.mark.parametrize("shape", list(DEGENERATE))
+@pytest.mark.parametrize("leaf", [0, 1])
+@pytest.mark.parametrize("prec,bar", [(0, 1e-12), (1, 2e-4)])
+def test_round_degenerate_shapes_match_oracle(stf, ctx, shape, leaf, prec, bar):
+    w = workloads.configs.small_random(seed=7, **DEGENERATE[shape])
+    pb = stf.Problem(ctx, _prm(w, leaf_size=leaf, front_prec=prec), w.eps_cells)
+    pb.factor()
+    B = ddm.SourceTransfer(w.params(), w.eps_cells)
+    v = workloads.sources.random_field(w.nx, w.ny, 14)
+    assert _rel(pb.precond(v), B.apply(v.ravel())) < bar
+    pb.close()
+
+
 def test_single_subdomain_round_is_inverse(stf, ctx):
     w = workloads.configs.small_random(nx=40, ny=36, pml=6, px=1, py=1, seed=5)
     pb = stf.Problem(ctx, _prm(w), w.eps_cells)
