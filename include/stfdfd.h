@@ -66,7 +66,9 @@ enum { STF_X0_ZERO = 0, STF_X0_USER = 1, STF_X0_LEARNED = 2 };
  * also own the global PML on their side.  Each block is extended on every side
  * facing a neighbour by overlap + local_pml nodes: `overlap` unstretched cells
  * then a local PML of `local_pml` cells (Eqs. (10)-(13) with local_pml_order and
- * local_pml_R).  Requires every interior block side >= overlap + local_pml + 1. */
+ * local_pml_R).  Requires every interior block side >= overlap + local_pml + 1,
+ * and, with three or more blocks along an axis, >= 2 (overlap + local_pml), so
+ * that no node lies in more than two blocks' extended domains per axis. */
 typedef struct {
   int32_t nx, ny;            /* nodes, global PML included (each >= 3) */
   double  dx, dy;            /* grid steps (> 0) */

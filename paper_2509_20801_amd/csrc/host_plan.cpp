@@ -101,6 +101,12 @@ void validate_params(const stf_params& p) {
                 "x blocks narrower than overlap + local_pml + 1 (partition too fine)");
     STF_REQUIRE(p.py == 1 || wy / p.py >= e + 1,
                 "y blocks narrower than overlap + local_pml + 1 (partition too fine)");
+    // A middle block narrower than 2e would lie in the extensions of both of
+    // its neighbours as well as its own domain.
+    STF_REQUIRE(p.px <= 2 || wx / p.px >= 2 * e,
+                "x blocks narrower than 2 (overlap + local_pml) with three or more blocks");
+    STF_REQUIRE(p.py <= 2 || wy / p.py >= 2 * e,
+                "y blocks narrower than 2 (overlap + local_pml) with three or more blocks");
   }
 }
 

@@ -114,13 +114,21 @@ def test_plan_single_subdomain_counts_every_node_once(stf):
 
 
 @pytest.mark.parametrize("bad", [dict(nx=2), dict(pml_R=1.5), dict(px=20), dict(k0=-1.0),
-                                 dict(front_prec=5), dict(local_pml=0)])
+                                 dict(front_prec=5), dict(local_pml=0),
+                                 dict(px=3, overlap=5, local_pml=12)])
 def test_invalid_parameters_rejected(stf, bad):
     prm = dict(nx=132, ny=132, k0=0.3, pml=(16,) * 4, px=2, py=2, overlap=8, local_pml=16)
     prm.update(bad)
     with pytest.raises(stf.StfError) as e:
         stf.plan_query(prm)
     assert e.value.status == 1
+
+
+def test_three_blocks_at_the_narrowest_width_accepted(stf):
+    # 100 interior nodes in three blocks of >= 33 >= 2 (overlap + local_pml) = 32:
+    # every node lies in at most two extended domains per axis.
+    prm = dict(nx=132, ny=132, k0=0.3, pml=(16,) * 4, px=3, py=3, overlap=4, local_pml=12)
+    assert stf.plan_query(prm)["nsub"] == 9
 
 
 def test_network_parameter_count_matches_reference(stf):
