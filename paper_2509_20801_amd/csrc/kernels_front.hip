@@ -1122,13 +1122,18 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   const int m = f.p + f.q, p = f.p;
   const T* L = lpk + f.lpk_off;
   const int tid = threadIdx.x;
-  int G = 1, g = 0, rr = tid;
-  if (m < NTL) {
-    G = NTL / m;
-    g = tid / m;
-    rr = tid - g * m;
+  // Rows [r0, r1) of the product: part blockIdx.y of gridDim.y (every part
+  // stages the whole right-hand side).
+  const int chunk = (m + gridDim.y - 1) / gridDim.y;
+  const int r0 = blockIdx.y * chunk, r1 = min(m, r0 + chunk), R = r1 - r0;
+  if (R <= 0) return;                                      // whole workgroup
+  int G = 1, g = 0, rr = r0 + tid;
+  if (R < NTL) {
+    G = NTL / R;
+    g = tid / R;
+    rr = r0 + tid - g * R;
   }
-  const bool act = g < G && rr < m;
+  const bool act = g < G && rr < r1;
   ColPrefetch<T, KP> pf;
   pf.load(L, LowerAt{m, rr}, g, 0, act ? min(rr, p) : 0, G);
   const int* perm = piv + f.piv_off;
@@ -1233,19 +1238,19 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
     for (int s = 0; s < NR; ++s) {
       T* out = vec + s * rs.vec_stride + f.vec_off;
       if (act) out[rr] = cadd(vl[s * mm + rr], acc[s]);
-      for (int r = tid + NTL; r < m; r += NTL)
+      for (int r = rr + NTL; r < r1; r += NTL)
         out[r] = cadd(vl[s * mm + r], gather_dot(L, LowerAt{m, r}, 0, 0, min(r, p), 1, vl + s * mm));
     }
   } else {
 #pragma unroll
     for (int s = 0; s < NR; ++s) scr[s * NTL + tid] = acc[s];
     __syncthreads();
-    if (tid < m) {
+    if (tid < R) {
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
         T sum = czero<T>();
-        for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * m + tid]);
-        vec[s * rs.vec_stride + f.vec_off + tid] = cadd(vl[s * mm + tid], sum);
+        for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * R + tid]);
+        vec[s * rs.vec_stride + f.vec_off + r0 + tid] = cadd(vl[s * mm + r0 + tid], sum);
       }
     }
   }
@@ -1262,19 +1267,27 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   const int m = f.p + f.q, p = f.p;
   const T* U = upk + f.upk_off;                            // packed [U11^{-1} V']
   const int tid = threadIdx.x;
-  int G = 1, g = 0, rr = tid;
-  if (p < NTL) {
-    G = NTL / max(p, 1);
-    g = tid / max(p, 1);
-    rr = tid - g * max(p, 1);
+  // Rows [r0, r1) of x_p: part blockIdx.y of gridDim.y.  Every part stages the
+  // whole [y_p ; x_q]; part 0 also passes x_q on to the children.  A part never
+  // writes this front's own vector (the host keeps R <= NTL when there are
+  // several parts), which the other parts read.
+  const int sp = blockIdx.y;
+  const int chunk = (p + gridDim.y - 1) / gridDim.y;
+  const int r0 = sp * chunk, r1 = min(p, r0 + chunk), R = r1 - r0;
+  if (R <= 0) return;                                      // whole workgroup (never part 0)
+  int G = 1, g = 0, rr = r0 + tid;
+  if (R < NTL) {
+    G = NTL / R;
+    g = tid / R;
+    rr = r0 + tid - g * R;
   }
-  const bool act = g < G && rr < p;
+  const bool act = g < G && rr < r1;
   ColPrefetch<T, KP> pf;
   pf.load(U, UpperAt{p, rr}, g, rr, act ? m : 0, G);
   const int* vars = a.vars + f.var_off;
   // the row this thread stores: rr (one column group) or tid (summed groups)
-  const int row = G == 1 ? rr : tid;
-  const bool has_row = G == 1 ? act : tid < p;
+  const int row = G == 1 ? rr : r0 + tid;
+  const bool has_row = G == 1 ? act : tid < R;
   const int var = has_row ? vars[row] : 0;
   // The children's maps (issued early; two entries per thread, the rest later).
   int cm[2][2];
@@ -1296,7 +1309,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(U, UpperAt{p, rr}, g, rr, m, G, vl + s * mm) : czero<T>();
   if (G == 1) {
     // rows beyond NTL (p > NTL): written to the front vector now, read back below
-    for (int r = tid + NTL; r < p; r += NTL)
+    for (int r = rr + NTL; r < r1; r += NTL)
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
         const T x = gather_dot(U, UpperAt{p, r}, 0, r, m, 1, vl + s * mm);
@@ -1307,11 +1320,11 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
 #pragma unroll
     for (int s = 0; s < NR; ++s) scr[s * NTL + tid] = acc[s];
     __syncthreads();
-    if (tid < p) {
+    if (tid < R) {
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
         T sum = czero<T>();
-        for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * p + tid]);
+        for (int gg = 0; gg < G; ++gg) sum = cadd(sum, scr[s * NTL + gg * R + tid]);
         acc[s] = sum;
       }
     }
@@ -1323,24 +1336,27 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
       vl[s * mm + row] = acc[s];
       u[s * rs.u_stride + uo + var] = acc[s];
     }
-  for (int r = tid + NTL; G == 1 && r < p; r += NTL)
+  for (int r = rr + NTL; G == 1 && r < r1; r += NTL)
 #pragma unroll
     for (int s = 0; s < NR; ++s) vl[s * mm + r] = vec[s * rs.vec_stride + f.vec_off + r];
   __syncthreads();
-  // This front's vector [x_p ; x_q] into the update slots of its children.
+  // This front's vector [x_p ; x_q] into the update slots of its children:
+  // the rows of x_p this part computed, and x_q from part 0.
+  auto mine = [&](int d) { return d >= p ? sp == 0 : (d >= r0 && d < r1); };
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-      if (cm[c][i] >= 0)
+      if (cm[c][i] >= 0 && mine(cm[c][i]))
 #pragma unroll
         for (int s = 0; s < NR; ++s)
           vec[s * rs.vec_stride + f.cvec[c] + tid + NTL * i] = vl[s * mm + cm[c][i]];
     if (c < f.nchild)
       for (int idx = tid + 2 * NTL; idx < f.cq[c]; idx += NTL) {
         const int d = a.cmap[f.ccmap[c] + idx];
+        if (mine(d))
 #pragma unroll
-        for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.cvec[c] + idx] = vl[s * mm + d];
+          for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.cvec[c] + idx] = vl[s * mm + d];
       }
   }
 }
@@ -1462,7 +1478,7 @@ inline int prefetch_depth(int need, int cap) {
 }
 
 // Workgroup size for the large-front sweeps: the largest of 256, 512, 1024
-// threads with which the level's fronts all fit in one round of workgroups at
+// threads with which the level's nwg workgroups all fit in one round at
 // sixteen wavefronts per CU (the latency of one front is the level's time, so a
 // second round costs more than narrower workgroups do); at least 256.
 int g_num_cus = 0;
@@ -1478,11 +1494,26 @@ int num_cus() {
   }
   return g_num_cus;
 }
-inline int large_threads(int nfronts) {
+inline int large_threads(int nwg) {
   const long long budget = 16LL * num_cus();             // resident wavefronts
   int ntl = 256;
-  while (ntl < 1024 && (long long)nfronts * (2 * ntl / 64) <= budget) ntl *= 2;
+  while (ntl < 1024 && (long long)nwg * (2 * ntl / 64) <= budget) ntl *= 2;
   return ntl;
+}
+
+// Workgroups per front for the large-front sweeps: a level of fewer fronts
+// than CUs splits each front's rows over up to eight parts, until there is a
+// workgroup per CU (sixteen wavefronts each), keeping at least 32 rows per
+// part; a level that already fills the chip gains nothing from parts, which
+// each stage the whole right-hand side.  Several parts only when each takes at
+// most 256 rows (<= the workgroup's threads): a part then never writes its
+// front's own vector, which the other parts read.
+inline int sweep_parts(int nfronts, int rows) {
+  int parts = 1;
+  while (parts < 8 && (long long)nfronts * parts < num_cus() && rows / (2 * parts) >= 32)
+    parts *= 2;
+  if (parts > 1 && (rows + parts - 1) / parts > 256) parts = 1;
+  return parts;
 }
 
 // Instantiation over the number of right-hand sides swept together.
@@ -1513,41 +1544,43 @@ void bwd_wave_launch(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T
 }
 
 template <typename T, int NTL, int KP>
-void fwd_large_nr(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
-                  const RhsSet& r) {
+void fwd_large_nr(hipStream_t st, const LevelArgs& a, int parts, const T* fac, const int* piv,
+                  T* vec, const RhsSet& r) {
   const size_t lds = ((size_t)r.nr * NTL + 2 * (size_t)r.nr * a.max_m) * sizeof(T);
-#define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_fwd_large<T, NTL, KP, NR>), dim3(a.nlevel), dim3(NTL), lds, st, a, fac, piv, vec, r)
+#define STF_CALL(NR)                                                                         \
+  hipLaunchKernelGGL((k_fwd_large<T, NTL, KP, NR>), dim3(a.nlevel, parts), dim3(NTL), lds, st, a, \
+                     fac, piv, vec, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
 
 template <typename T, int NTL, int KP>
-void bwd_large_nr(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
+void bwd_large_nr(hipStream_t st, const LevelArgs& a, int parts, const T* upk, T* vec, T* u,
                   const RhsSet& r) {
   const size_t lds = ((size_t)r.nr * NTL + (size_t)r.nr * a.max_m) * sizeof(T);
-#define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_bwd_large<T, NTL, KP, NR>), dim3(a.nlevel), dim3(NTL), lds, st, a, upk, vec, u, r)
+#define STF_CALL(NR)                                                                         \
+  hipLaunchKernelGGL((k_bwd_large<T, NTL, KP, NR>), dim3(a.nlevel, parts), dim3(NTL), lds, st, a, \
+                     upk, vec, u, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
 
 template <typename T, int NTL>
-void fwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* fac, const int* piv,
-                      T* vec, const RhsSet& r) {
+void fwd_large_launch(hipStream_t st, const LevelArgs& a, int parts, int kp, const T* fac,
+                      const int* piv, T* vec, const RhsSet& r) {
   if (kp <= 16)
-    fwd_large_nr<T, NTL, 16>(st, a, fac, piv, vec, r);
+    fwd_large_nr<T, NTL, 16>(st, a, parts, fac, piv, vec, r);
   else
-    fwd_large_nr<T, NTL, (sizeof(T) == 8 ? 32 : 16)>(st, a, fac, piv, vec, r);
+    fwd_large_nr<T, NTL, (sizeof(T) == 8 ? 32 : 16)>(st, a, parts, fac, piv, vec, r);
 }
 
 template <typename T, int NTL>
-void bwd_large_launch(hipStream_t st, const LevelArgs& a, int kp, const T* upk, T* vec, T* u,
-                      const RhsSet& r) {
+void bwd_large_launch(hipStream_t st, const LevelArgs& a, int parts, int kp, const T* upk,
+                      T* vec, T* u, const RhsSet& r) {
   if (kp <= 16)
-    bwd_large_nr<T, NTL, 16>(st, a, upk, vec, u, r);
+    bwd_large_nr<T, NTL, 16>(st, a, parts, upk, vec, u, r);
   else
-    bwd_large_nr<T, NTL, (sizeof(T) == 8 ? 32 : 16)>(st, a, upk, vec, u, r);
+    bwd_large_nr<T, NTL, (sizeof(T) == 8 ? 32 : 16)>(st, a, parts, upk, vec, u, r);
 }
 
 void check_rhs(const RhsSet& r) {
@@ -1576,13 +1609,15 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
     }
     return;
   }
-  // Rows m share the workgroup; a row takes at most p columns.
-  const int ntl = large_threads(a.nlevel);
-  const int g = std::max(1, ntl / a.max_m);
+  // The rows of each front in `parts` workgroups; a row takes at most p columns.
+  const int parts = sweep_parts(a.nlevel, a.max_m);
+  const int ntl = large_threads(a.nlevel * parts);
+  const int rows = (a.max_m + parts - 1) / parts;
+  const int g = std::max(1, ntl / rows);
   const int kp = prefetch_depth((a.max_p + g - 1) / g, cap);
-  if (ntl == 256) fwd_large_launch<T, 256>(st, a, kp, fac, piv, vec, r);
-  else if (ntl == 512) fwd_large_launch<T, 512>(st, a, kp, fac, piv, vec, r);
-  else fwd_large_launch<T, 1024>(st, a, kp, fac, piv, vec, r);
+  if (ntl == 256) fwd_large_launch<T, 256>(st, a, parts, kp, fac, piv, vec, r);
+  else if (ntl == 512) fwd_large_launch<T, 512>(st, a, parts, kp, fac, piv, vec, r);
+  else fwd_large_launch<T, 1024>(st, a, parts, kp, fac, piv, vec, r);
 }
 
 template <typename T>
@@ -1602,13 +1637,15 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, 
     else bwd_wave_launch<T, (sizeof(T) == 8 ? 32 : 16)>(st, a, upk, vec, u, r);
     return;
   }
-  // Rows p share the workgroup; a row takes at most m columns.
-  const int ntl = large_threads(a.nlevel);
-  const int g = std::max(1, ntl / std::max(a.max_p, 1));
+  // The rows p of each front in `parts` workgroups; a row takes at most m columns.
+  const int parts = sweep_parts(a.nlevel, a.max_p);
+  const int ntl = large_threads(a.nlevel * parts);
+  const int rows = (std::max(a.max_p, 1) + parts - 1) / parts;
+  const int g = std::max(1, ntl / rows);
   const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
-  if (ntl == 256) bwd_large_launch<T, 256>(st, a, kp, upk, vec, u, r);
-  else if (ntl == 512) bwd_large_launch<T, 512>(st, a, kp, upk, vec, u, r);
-  else bwd_large_launch<T, 1024>(st, a, kp, upk, vec, u, r);
+  if (ntl == 256) bwd_large_launch<T, 256>(st, a, parts, kp, upk, vec, u, r);
+  else if (ntl == 512) bwd_large_launch<T, 512>(st, a, parts, kp, upk, vec, u, r);
+  else bwd_large_launch<T, 1024>(st, a, parts, kp, upk, vec, u, r);
 }
 
 template <typename T>
