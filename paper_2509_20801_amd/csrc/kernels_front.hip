@@ -1285,7 +1285,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   ColPrefetch<T, KP> pf;
   pf.load(U, UpperAt{p, rr}, g, rr, act ? m : 0, G);
   const int* vars = a.vars + f.var_off;
-  // the row this thread stores: rr (one column group) or tid (summed groups)
+  // the row this thread stores: rr (one column group) or r0 + tid (summed groups)
   const int row = G == 1 ? rr : r0 + tid;
   const bool has_row = G == 1 ? act : tid < R;
   const int var = has_row ? vars[row] : 0;
@@ -1614,7 +1614,10 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
   const int ntl = large_threads(a.nlevel * parts);
   const int rows = (a.max_m + parts - 1) / parts;
   const int g = std::max(1, ntl / rows);
-  const int kp = prefetch_depth((a.max_p + g - 1) / g, cap);
+  // A level of more workgroups than one round at four wavefronts per SIMD holds
+  // sixteen terms per lane (about 70 registers, seven wavefronts per SIMD).
+  const bool many = (long long)a.nlevel * parts * (ntl / 64) > 16LL * num_cus();
+  const int kp = prefetch_depth((a.max_p + g - 1) / g, many ? 16 : cap);
   if (ntl == 256) fwd_large_launch<T, 256>(st, a, parts, kp, fac, piv, vec, r);
   else if (ntl == 512) fwd_large_launch<T, 512>(st, a, parts, kp, fac, piv, vec, r);
   else fwd_large_launch<T, 1024>(st, a, parts, kp, fac, piv, vec, r);
