@@ -1443,11 +1443,15 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* 
   // (the staged U chunk and small arrays take the rest).
   const size_t budget = (size_t)max_lds() - (size_t)UC * 33 * sizeof(T) - 512;
   const size_t per_col = (size_t)a.max_m * sizeof(T);
-  // Narrower panels for smaller fronts: fewer registers per thread (higher
-  // occupancy) where the fronts are many and small.
+  // Fronts of order <= 256: panels as wide as the separator where that fits,
+  // so that the Schur complement is updated in fewer passes, except for
+  // complex64 fronts of order <= 128, whose levels hold thousands of fronts
+  // and keep 8-column panels (fewer registers, more workgroups per CU).
   int nb_max = sizeof(T) == 16 ? 16 : 32;
-  if (a.max_m <= 128) nb_max = 8;
-  else if (a.max_m <= 256) nb_max = std::min(nb_max, 16);
+  int one = 1;
+  while (one < a.max_p) one *= 2;
+  if (a.max_m <= 128 && sizeof(T) == 8) nb_max = 8;
+  else if (a.max_m <= 256) nb_max = std::min(nb_max, one);
   int nb = 1;
   while (nb * 2 <= nb_max && per_col * nb * 2 <= budget) nb *= 2;
   if (per_col * nb > budget) throw Error(STF_EINVAL, "front too large for the LDS panel");
