@@ -262,7 +262,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--restart", type=int, default=20)
+    ap.add_argument("--restart", type=int, default=10)
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP event timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
