@@ -13,7 +13,10 @@ application) until the FP64 true relative residual is <= 1e-8.  The timed
 form uses complex64 fronts ("mixed"); the plain complex128 form is timed too
 and reported beside it.
 
-Prints one JSON line (see the design doc for the roofline and baseline definitions).
+Prints one JSON line: the throughput, the roofline of the dominant kernel class
+(algorithmic bytes or flops per launch over its measured launch time, against the
+published MI355X peak, with the HBM bytes per launch from the committed PMC
+summary) and the oracle's throughput on a bounded sample.
 """
 from __future__ import annotations
 
@@ -188,7 +191,9 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
 
 
 def roofline(stf, w, prec, infos, stats, steps):
-    """Roofline of the kernel class with the largest summed time."""
+    """Roofline of the kernel class with the largest summed time: its algorithmic
+    work per launch (fine nested-dissection reference counts) over its measured
+    per-launch time, against the published peak of the bound it is priced on."""
     ref = stf.plan_query(params_of(w, prec, leaf=4))     # fine nested dissection reference
     es = 8 if prec == stf.STF_C64 else 16
     N = w.nx * w.ny
@@ -281,7 +286,7 @@ def main():
         return
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X "
-              "(multi-GPU sharding is described in DESIGN.md, not implemented)", file=sys.stderr)
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_2509_20801_amd as stf

@@ -2,8 +2,7 @@
 
 TEST INFRASTRUCTURE ONLY (see oracle/fdfd.py).
 
-Follows Sec. 2.3 (Figs. 2-3, Eqs. (14)-(21), Algorithm 1) with these readings
-(listed in DESIGN.md):
+Follows Sec. 2.3 (Figs. 2-3, Eqs. (14)-(21), Algorithm 1) with these readings:
   * Partition (Fig. 3): the node grid, global PML included, is cut into
     px x py non-overlapping boxes I_k; the physical interior is split as evenly
     as possible and each edge box also takes the global PML on its side.

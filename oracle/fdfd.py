@@ -10,7 +10,7 @@ Everything is plain NumPy/SciPy in complex128, written from the paper:
   * linear system A e = b, Eq. (4);
   * stretched-coordinate PML operator, Eq. (9), with the stretch factor of
     Eq. (10), the polynomial grading of Eqs. (11)-(12) and sigma_max of Eq. (13).
-Readings where the paper is silent or garbled (all listed in the design doc):
+Readings where the paper is silent or garbled:
   * time convention exp(+j w t): Eq. (10) and (13) taken literally give
     s = 1 - j|sigma|/(w eps0), which absorbs outgoing exp(-j k r) waves;
   * sigma/(w eps0) = (m+1)|ln R| / (2 k0 L dlt) * (rho / (L dlt))^m with the
