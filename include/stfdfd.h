@@ -180,6 +180,19 @@ stf_status  stf_factor(stf_problem pb);
  * info: array of nrhs (may be NULL).  Returns the worst per-RHS status. */
 stf_status  stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                       const stf_solve_opts* opts, stf_solve_info* info);
+/* Algorithm 1 as the paper runs it: a stationary iteration of source-transfer
+ * rounds (Sec. 2.3).  x_0 = B b (the initial local solves, Eq. (14)), then
+ * x <- x + B (b - A x) (the transferred sources of Eqs. (18)-(19) solved
+ * locally and summed as in Eq. (21)), until the FP64 true relative residual
+ * |b - A x| / |b| <= tol or max_rounds rounds after x_0 (0 <= max_rounds <=
+ * 100000).  b, x: ny*nx complex, host or device (on_device).  hist (host, may
+ * be NULL): max_rounds + 1 doubles, the relative residual of x_0 and of every
+ * round taken.  *rounds_out (may be NULL): rounds taken after x_0.  Returns
+ * STF_ENOCONV when tol was not reached (x, hist, *rounds_out still written),
+ * STF_ENAN on a non-finite residual, STF_ESTATE before stf_factor. */
+stf_status  stf_stationary_solve(stf_problem pb, const double* b, double* x, int on_device,
+                                 double tol, int32_t max_rounds, double* hist,
+                                 int32_t* rounds_out);
 /* y = A x with the global FP64 operator (Eqs. (2), (9)).  x, y: ny*nx complex. */
 stf_status  stf_apply(stf_problem pb, const double* x, double* y, int on_device);
 /* One source-transfer round z = sum_k P_k A_k^{-1} R_k^I v (Eqs. (14), (21)):

@@ -260,6 +260,27 @@ class Problem:
             _check(self.ctx.handle, self._lib.stf_precond_apply_batch(self.handle, nrhs, pv, pz, dev))
         return z if dev else kz.reshape(shape)
 
+    def stationary_solve(self, b, x=None, tol=1e-10, max_rounds=100):
+        """Algorithm 1 as a stationary iteration of source-transfer rounds:
+        x_0 = B b, then x <- x + B (b - A x) until the FP64 true relative residual
+        is <= tol or max_rounds rounds.  Returns (x, info) with info = dict(
+        rounds, status, relres_true, hist) (hist: relative residual of x_0 and of
+        every round)."""
+        n = self.ndof
+        pb_, dev, kb = _ptr(b, n, "b")
+        x = self._out_like(b, tuple(b.shape)) if x is None else x
+        px, dev2, kx = _ptr(x, n, "x")
+        if dev != dev2:
+            raise TypeError("b and x must both be host or both be device arrays")
+        hist = np.zeros(int(max_rounds) + 1, dtype=np.float64)
+        k = C.c_int32(0)
+        st = self._lib.stf_stationary_solve(self.handle, pb_, px, dev, float(tol), int(max_rounds),
+                                            hist.ctypes.data, C.byref(k))
+        _check(self.ctx.handle, st, allow=(_abi.STF_ENOCONV,))
+        h = hist[:k.value + 1].tolist()
+        info = dict(rounds=k.value, status=st, relres_true=h[-1], hist=h)
+        return (x if dev else kx.reshape(tuple(b.shape))), info
+
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
               raise_on_noconv=False, rounds=1):
         """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos).

@@ -1350,6 +1350,68 @@ stf_status stf_precond_apply(stf_problem pb, const double* v, double* z, int on_
   });
 }
 
+stf_status stf_stationary_solve(stf_problem pb, const double* b, double* x, int on_device,
+                                double tol, int32_t max_rounds, double* hist,
+                                int32_t* rounds_out) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(b && x, "null argument");
+    STF_REQUIRE(max_rounds >= 0 && max_rounds <= 100000, "max_rounds out of range");
+    STF_REQUIRE(std::isfinite(tol) && tol >= 0, "tol must be finite and >= 0");
+    if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
+    const long long N = pb->N;
+    require_finite(pb, b, 2 * (size_t)N, on_device, "b");
+    hipStream_t st = pb->ctx->stream;
+    const size_t vb = (size_t)N * sizeof(double2);
+    const double2* bd = reinterpret_cast<const double2*>(b);
+    double2* xd = reinterpret_cast<double2*>(x);
+    if (!on_device) {
+      pb->hb.alloc(vb);
+      pb->hx.alloc(vb);
+      HIP_CHECK(hipMemcpyAsync(pb->hb.p, b, vb, hipMemcpyHostToDevice, st));
+      bd = pb->hb.as<double2>();
+      xd = pb->hx.as<double2>();
+    }
+    pb->kt.alloc(vb);
+    pb->kt2.alloc(vb);
+    double2* r = pb->kt.as<double2>();
+    double2* z = pb->kt2.as<double2>();
+    double* sc = pb->scal.as<double>();          // [0..1] |b|^2 (real part), [2] |r|^2
+    double h[3] = {0.0, 0.0, 0.0};
+    norm2(pb, bd, reinterpret_cast<double2*>(sc));
+    precond(pb, bd, xd);                          // x_0 = B b
+    residual(pb, xd, bd, r, sc + 2);
+    HIP_CHECK(hipMemcpyAsync(h, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    const double bn = std::sqrt(h[0]);
+    auto rel = [&](double r2) { return bn > 0.0 ? std::sqrt(r2) / bn : std::sqrt(r2); };
+    double rr = rel(h[2]);
+    if (hist) hist[0] = rr;
+    int k = 0;
+    while (k < max_rounds && !(rr <= tol)) {
+      if (!std::isfinite(rr)) throw Error(STF_ENAN, "non-finite residual");
+      precond(pb, r, z);                          // B (b - A x): the transferred sources
+      {
+        Timed t(pb->ctx, K_UPDATE);
+        launch_axpy(st, xd, z, N);                // x <- x + B (b - A x)
+      }
+      residual(pb, xd, bd, r, sc + 2);
+      HIP_CHECK(hipMemcpyAsync(h + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+      rr = rel(h[2]);
+      ++k;
+      if (hist) hist[k] = rr;
+    }
+    if (!on_device) {
+      HIP_CHECK(hipMemcpyAsync(x, xd, vb, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+    if (rounds_out) *rounds_out = k;
+    if (!std::isfinite(rr)) throw Error(STF_ENAN, "non-finite residual");
+    if (!(rr <= tol)) throw Error(STF_ENOCONV, "tolerance not reached in max_rounds rounds");
+  });
+}
+
 stf_status stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v, double* z,
                                    int on_device) {
   if (!pb) return STF_EINVAL;

@@ -120,6 +120,47 @@ def test_single_subdomain_round_is_inverse(stf, ctx):
     assert info[0]["iters"] == 1 and info[0]["relres_true"] < 1e-12
 
 
+def test_stationary_algorithm1_matches_oracle(stf, ctx):
+    """Algorithm 1 as the paper iterates it (x_0 = B b, x <- x + B (b - A x)),
+    complex128 fronts on configuration 1: the relative residual of every round
+    equals the oracle's (up to rounding, 1e-6 relative + 1e-12) and the 14th
+    iterate equals the oracle's to 1e-10; tol 0 is never met (STF_ENOCONV)."""
+    w = CASES["c1"]()
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    pb.factor()
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    B = ddm.SourceTransfer(w.params(), w.eps_cells)
+    b = w.b[0]
+    xr, hr = ddm.stationary(A, B, b.ravel(), 14)
+    x, info = pb.stationary_solve(b, tol=0.0, max_rounds=14)
+    assert info["rounds"] == 14 and info["status"] == 6
+    h, hr = np.array(info["hist"]), np.array(hr)
+    assert h.shape == hr.shape
+    assert np.all(np.abs(h - hr) <= 1e-6 * hr + 1e-12)
+    assert _rel(x, xr) < 1e-10
+    pb.close()
+
+
+def test_stationary_mixed_converges_to_direct_on_device(stf, ctx):
+    """With complex64 fronts the rounds still drive the FP64 true residual down
+    (each round corrects with the FP64 residual): tol 1e-10 is met, the field
+    equals the direct solve to 1e-8; device tensors in and out."""
+    import torch
+    w = CASES["c1"]()
+    pb = stf.Problem(ctx, _prm(w, front_prec=stf.STF_C64), w.eps_cells)
+    pb.factor()
+    b = w.b[0]
+    bd = torch.from_numpy(b).cuda()
+    x, info = pb.stationary_solve(bd, tol=1e-10, max_rounds=60)
+    assert info["status"] == 0 and info["relres_true"] <= 1e-10
+    assert info["rounds"] == len(info["hist"]) - 1
+    h = info["hist"]
+    assert all(b1 < b0 for b0, b1 in zip(h[:6], h[1:7]))
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    assert _rel(x.cpu().numpy(), fdfd.solve_direct(A, b.ravel()).reshape(b.shape)) < 1e-8
+    pb.close()
+
+
 def test_c1_solve_plain_fp64(stf, ctx):
     """Config 1 (plain method, complex128): FGMRES to rel-res 1e-12 equals the
     global direct solve to 1e-10."""
