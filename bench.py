@@ -101,6 +101,27 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     return (t1 - t0) / steps, infos, stats, info, profile
 
 
+def stationary_form(stf, torch, ctx, w, prec, tol, max_rounds):
+    """Algorithm 1 as the paper runs it, a stationary iteration of
+    source-transfer rounds, on the same problem (factored once, not part of the
+    timed step): rounds to the FP64 true rel-res tol and their wall time."""
+    eps = torch.from_numpy(w.eps_cells).cuda()
+    b = torch.from_numpy(w.b[0]).cuda()
+    pb = stf.Problem(ctx, params_of(w, prec), eps)
+    pb.factor()
+    x = torch.empty_like(b)
+    pb.stationary_solve(b, x=x, tol=tol, max_rounds=max_rounds)          # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, inf = pb.stationary_solve(b, x=x, tol=tol, max_rounds=max_rounds)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    pb.close()
+    return {"rounds": inf["rounds"], "relres_true": inf["relres_true"],
+            "converged": inf["status"] == 0, "solve_ms": round(t * 1e3, 3),
+            "form": "complex64 fronts" if prec == stf.STF_C64 else "complex128 fronts"}
+
+
 # Kernel classes of the library's kernels (by kernel name) and the source file
 # that holds them (a PMC summary is valid only for the source it was taken on).
 CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "front_lu"),
@@ -273,6 +294,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 reference form")
     ap.add_argument("--no-batched", action="store_true", help="skip the four-RHS batched form")
+    ap.add_argument("--no-stationary", action="store_true",
+                    help="skip the stationary source-transfer iteration (the paper's own scheme)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only the PMC calibration copy (512 MiB)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -331,6 +354,8 @@ def main():
                                "iters": [i["iters"] for i in inf_b[0]],
                                "converged": all(i["status"] == 0 and i["relres_true"] <= args.tol
                                                 for i in inf_b[0])}
+    if not args.no_stationary:
+        out["stationary"] = stationary_form(stf, torch, ctx, w, stf.STF_C64, args.tol, 200)
     out["device_bytes"] = info["device_bytes"]
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, inf_mixed[0]["iters"], args.restart)
