@@ -165,3 +165,26 @@ def relres(A, x, b):
 
 def rel_l2(x, xref):
     return np.linalg.norm(np.ravel(x) - np.ravel(xref)) / np.linalg.norm(np.ravel(xref))
+
+
+def line_flux(E, nx, ny, axis, index, lo, hi, k0, dx, dy):
+    """Time-averaged power per unit length through a grid line: the line
+    integral U = 1/2 int_l Re(E x H*) of Sec. 3.2 for E = E_z z.  The line lies
+    between node rows index and index + 1 (axis 1: constant y, nodes x in
+    [lo, hi), power flowing towards +y) or node columns index and index + 1
+    (axis 0: constant x, nodes y in [lo, hi), towards +x).  H from Faraday's law
+    with exp(+j w t) and w mu = k0 (fields normalised so that eta0 = 1):
+    H_x = (j / k0) dE_z/dy and H_y = -(j / k0) dE_z/dx, so the y component of
+    the power flow is 1/2 Re(E_z conj(H_x)) and the x component
+    -1/2 Re(E_z conj(H_y)); on the line E_z is the mean of the two node rows and
+    the derivative their difference over the step.  Parity unpinned against the
+    paper (it prints no worked value); pinned by the discrete Poynting identity
+    and the discrete plane wave in tests/test_oracle_assembly.py."""
+    F = np.asarray(E, dtype=np.complex128).reshape(ny, nx)
+    if axis == 1:
+        a, b, d, dl = F[index, lo:hi], F[index + 1, lo:hi], dy, dx
+    else:
+        a, b, d, dl = F[lo:hi, index], F[lo:hi, index + 1], dx, dy
+    e_mid = 0.5 * (a + b)
+    h = 1j / k0 * (b - a) / d              # H_x (axis 1) or -H_y (axis 0) on the line
+    return 0.5 * float(np.sum(np.real(e_mid * np.conj(h)))) * dl

@@ -108,3 +108,44 @@ def test_tfsf_vacuum_leakage_small():
     err_tf = np.abs(x - inc)[phys][:, col - L + 1:col - L + 30].max()
     err_sf = np.abs(x)[phys][:, :col - L - 1].max()
     assert err_tf < 1e-3 and err_sf < 1e-4
+
+
+@pytest.mark.parametrize("dx,dy", [(1.0, 1.0), (0.6, 1.4)])
+def test_line_flux_discrete_poynting_identity(dx, dy):
+    """For any field E and a box of nodes, the sum over the box of
+    Im(conj(E) * Laplacian_h E) dx dy (the five-point Laplacian, written here
+    independently) equals -2 k0 times the net power flowing out through the
+    four grid lines around the box (the discrete Poynting theorem; a dropped
+    conjugate, a wrong sign or a transposed axis in line_flux fails it)."""
+    nx, ny, k0 = 23, 17, 0.7
+    rng = np.random.default_rng(5)
+    E = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    x0, x1, y0, y1 = 4, 19, 3, 12
+    s = 0.0
+    for j in range(y0, y1):
+        for i in range(x0, x1):
+            lap = ((E[j, i + 1] - 2 * E[j, i] + E[j, i - 1]) / dx ** 2
+                   + (E[j + 1, i] - 2 * E[j, i] + E[j - 1, i]) / dy ** 2)
+            s += (np.conj(E[j, i]) * lap).imag * dx * dy
+    f = lambda axis, index, lo, hi: fdfd.line_flux(E, nx, ny, axis, index, lo, hi, k0, dx, dy)
+    out = (f(0, x1 - 1, y0, y1) - f(0, x0 - 1, y0, y1)
+           + f(1, y1 - 1, x0, x1) - f(1, y0 - 1, x0, x1))
+    assert abs(s + 2 * k0 * out) <= 1e-12 * abs(s)
+
+
+@pytest.mark.parametrize("direction", [1, -1])
+def test_line_flux_of_a_plane_wave(direction):
+    """E = exp(-j beta y) (a wave towards +y for exp(+j w t)): the power through
+    any horizontal line of width W is W sin(beta dy) / (2 k0 dy), which tends
+    to W beta / (2 k0), the flux 1/2 |E|^2 / eta0 of a unit plane wave, as dy
+    -> 0; towards -y it is the negative."""
+    nx, ny, k0 = 12, 30, 0.5
+    for dy in (1.0, 0.1, 0.01):
+        beta = k0
+        y = np.arange(ny) * dy
+        E = np.tile(np.exp(-1j * direction * beta * y)[:, None], (1, nx))
+        for j in (0, 7, ny - 2):
+            u = fdfd.line_flux(E, nx, ny, 1, j, 2, 10, k0, 1.0, dy)
+            assert u == pytest.approx(direction * 8 * math.sin(beta * dy) / (2 * k0 * dy), rel=1e-12)
+    assert fdfd.line_flux(E, nx, ny, 1, 3, 2, 10, k0, 1.0, 0.01) == pytest.approx(direction * 8 / 2,
+                                                                                rel=1e-4)
