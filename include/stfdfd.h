@@ -193,6 +193,18 @@ stf_status  stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, 
 stf_status  stf_stationary_solve(stf_problem pb, const double* b, double* x, int on_device,
                                  double tol, int32_t max_rounds, double* hist,
                                  int32_t* rounds_out);
+/* Time-averaged power through a grid line, the line integral
+ * U = 1/2 int_l Re(E x H*) of Sec. 3.2 for E = E_z z, with H from Faraday's law
+ * (exp(+j w t), w mu = k0, fields normalised so that eta0 = 1):
+ * H_x = (j/k0) dE_z/dy, H_y = -(j/k0) dE_z/dx, E_z on the line the mean of the
+ * two node rows, the derivative their difference over the step.  axis 1: the
+ * line between node rows index and index + 1 (0 <= index < ny - 1), nodes x in
+ * [lo, hi) (0 <= lo <= hi <= nx), power towards +y; axis 0: between node
+ * columns index and index + 1, nodes y in [lo, hi), power towards +x.  The
+ * line should lie outside the PML (the step is the grid step there).  e: ny*nx
+ * complex field, host or device (on_device); *out (host): the power. */
+stf_status  stf_line_flux(stf_problem pb, const double* e, int on_device, int32_t axis,
+                          int32_t index, int32_t lo, int32_t hi, double* out);
 /* y = A x with the global FP64 operator (Eqs. (2), (9)).  x, y: ny*nx complex. */
 stf_status  stf_apply(stf_problem pb, const double* x, double* y, int on_device);
 /* One source-transfer round z = sum_k P_k A_k^{-1} R_k^I v (Eqs. (14), (21)):

@@ -260,6 +260,16 @@ class Problem:
             _check(self.ctx.handle, self._lib.stf_precond_apply_batch(self.handle, nrhs, pv, pz, dev))
         return z if dev else kz.reshape(shape)
 
+    def line_flux(self, e, axis, index, lo, hi):
+        """Power through the grid line between node rows (axis 1) or columns
+        (axis 0) index and index + 1, nodes [lo, hi) along it: the line integral
+        of Re(E x H*) / 2 (towards +y or +x)."""
+        pe, dev, ke = _ptr(e, self.ndof, "e")
+        out = C.c_double(0.0)
+        _check(self.ctx.handle, self._lib.stf_line_flux(self.handle, pe, dev, int(axis), int(index),
+                                                        int(lo), int(hi), C.byref(out)))
+        return out.value
+
     def stationary_solve(self, b, x=None, tol=1e-10, max_rounds=100):
         """Algorithm 1 as a stationary iteration of source-transfer rounds:
         x_0 = B b, then x <- x + B (b - A x) until the FP64 true relative residual

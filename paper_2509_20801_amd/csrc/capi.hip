@@ -1412,6 +1412,34 @@ stf_status stf_stationary_solve(stf_problem pb, const double* b, double* x, int 
   });
 }
 
+stf_status stf_line_flux(stf_problem pb, const double* e, int on_device, int32_t axis,
+                         int32_t index, int32_t lo, int32_t hi, double* out) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(e && out, "null argument");
+    const int nx = pb->prm.nx, ny = pb->prm.ny;
+    STF_REQUIRE(axis == 0 || axis == 1, "axis must be 0 or 1");
+    const int across = axis == 1 ? ny : nx, along = axis == 1 ? nx : ny;
+    STF_REQUIRE(index >= 0 && index + 1 < across, "line index out of range");
+    STF_REQUIRE(lo >= 0 && lo <= hi && hi <= along, "line range out of range");
+    hipStream_t st = pb->ctx->stream;
+    const double2* ed = reinterpret_cast<const double2*>(e);
+    if (!on_device) {
+      const size_t vb = (size_t)pb->N * sizeof(double2);
+      pb->hb.alloc(vb);
+      HIP_CHECK(hipMemcpyAsync(pb->hb.p, e, vb, hipMemcpyHostToDevice, st));
+      ed = pb->hb.as<double2>();
+    }
+    double* d = pb->scal.as<double>() + 3;
+    launch_line_flux(st, ed, nx, axis, index, lo, hi, pb->prm.k0, pb->prm.dx, pb->prm.dy, d);
+    HIP_CHECK(hipGetLastError());
+    double h = 0.0;
+    HIP_CHECK(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    *out = h;
+  });
+}
+
 stf_status stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v, double* z,
                                    int on_device) {
   if (!pb) return STF_EINVAL;

@@ -84,6 +84,32 @@ __global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ p
   if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
+// Power through a grid line (the line integral of Re(E x H*) / 2, Sec. 3.2):
+// the line lies between node rows j0 and j0 + 1 (constant y; nodes x in
+// [lo, hi): element t at (j0, lo + t) and (j0 + 1, lo + t), so stride_t = 1 and
+// stride_n = nx) or between node columns (stride_t = nx, stride_n = 1).  With
+// H_x = (j / k0) dE/dy (or -H_y = (j / k0) dE/dx) on the line, each element adds
+// Re(e_mid conj(j (b - a) / (k0 d))) = Im(e_mid conj(b - a)) / (k0 d); one
+// workgroup sums in a fixed order and scales by dl / 2.
+__global__ __launch_bounds__(256) void k_line_flux(const double2* __restrict__ e, long long base,
+                                                   long long stride_t, long long stride_n, int count,
+                                                   double inv_k0d, double half_dl,
+                                                   double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < count; t += 256) {
+    const long long n = base + (long long)t * stride_t;
+    const double2 a = e[n], b = e[n + stride_n];
+    const double mx = 0.5 * (a.x + b.x), my = 0.5 * (a.y + b.y);   // mean across the line
+    const double rx = b.x - a.x, ry = b.y - a.y;                    // difference across it
+    s += (my * rx - mx * ry) * inv_k0d;           // Im(mean conj(difference)) / (k0 d)
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[0] = ((red[0] + red[1]) + (red[2] + red[3])) * half_dl;
+}
+
 __global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ a, long long n,
                                                       int* __restrict__ flag) {
   long long t = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -116,6 +142,15 @@ void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b
     hipLaunchKernelGGL(k_stencil<1>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
                        partial);
   if (nblocks_out) *nblocks_out = grd.x * grd.y;
+}
+
+void launch_line_flux(hipStream_t st, const double2* e, int nx, int axis, int index, int lo, int hi,
+                      double k0, double dx, double dy, double* out) {
+  const long long base = axis == 1 ? (long long)index * nx + lo : (long long)lo * nx + index;
+  const long long st_t = axis == 1 ? 1 : nx, st_n = axis == 1 ? nx : 1;
+  const double d = axis == 1 ? dy : dx, dl = axis == 1 ? dx : dy;
+  hipLaunchKernelGGL(k_line_flux, dim3(1), dim3(256), 0, st, e, base, st_t, st_n, hi - lo,
+                     1.0 / (k0 * d), 0.5 * dl, out);
 }
 
 void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out) {

@@ -186,6 +186,11 @@ void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b
 int stencil_partial_blocks(int nx, int ny);
 // out[0] = sum partial[0..n)  (single block, fixed order).
 void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out);
+// Power through the grid line between node rows (axis 1) or columns (axis 0)
+// index and index + 1, nodes [lo, hi) along it; out: one device double.  The
+// caller checks 0 <= index, index + 1 < ny (nx), 0 <= lo <= hi <= nx (ny).
+void launch_line_flux(hipStream_t st, const double2* e, int nx, int axis, int index, int lo, int hi,
+                      double k0, double dx, double dy, double* out);
 // nonzero flag if any of n doubles is not finite (flag must be zeroed first).
 void launch_check_finite(hipStream_t st, const double* a, long long n, int* flag);
 

@@ -161,6 +161,39 @@ def test_stationary_mixed_converges_to_direct_on_device(stf, ctx):
     pb.close()
 
 
+def test_line_flux_matches_oracle(stf, ctx):
+    """Power through grid lines (both axes, full and partial ranges, the first
+    and last possible line) of a random field and of the configuration-1
+    solution, against oracle/fdfd.line_flux (FP64, another summation order:
+    1e-12 relative to the sum of the magnitudes); out-of-range lines are
+    rejected."""
+    w = CASES["ragged"]()
+    p = w.params()
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    e = workloads.sources.random_field(w.nx, w.ny, 21)
+    lines = [(1, 0, 0, w.nx), (1, w.ny - 2, 3, 40), (1, 20, 10, 10), (0, 0, 0, w.ny),
+             (0, w.nx - 2, 5, w.ny), (0, 33, 7, 29)]
+    for axis, index, lo, hi in lines:
+        ref = fdfd.line_flux(e, w.nx, w.ny, axis, index, lo, hi, p["k0"], p["dx"], p["dy"])
+        scale = fdfd.line_flux(np.abs(e), w.nx, w.ny, axis, index, lo, hi, p["k0"], p["dx"],
+                               p["dy"]) + np.abs(e).max() ** 2 * max(hi - lo, 1) / p["k0"]
+        got = pb.line_flux(e, axis, index, lo, hi)
+        assert abs(got - ref) <= 1e-12 * scale, (axis, index, lo, hi, got, ref)
+    for bad in [(2, 0, 0, 1), (1, w.ny - 1, 0, 1), (0, -1, 0, 1), (1, 0, 5, 4), (1, 0, 0, w.nx + 1)]:
+        with pytest.raises(stf.StfError):
+            pb.line_flux(e, *bad)
+    pb.close()
+    wc = CASES["c1"]()
+    pc = wc.params()
+    pb = stf.Problem(ctx, _prm(wc), wc.eps_cells)
+    pb.factor()
+    x, _ = pb.solve(wc.b[0], tol=1e-12)
+    j = wc.ny // 2
+    ref = fdfd.line_flux(x, wc.nx, wc.ny, 0, j, 20, wc.ny - 20, pc["k0"], pc["dx"], pc["dy"])
+    assert pb.line_flux(x, 0, j, 20, wc.ny - 20) == pytest.approx(ref, rel=1e-12)
+    pb.close()
+
+
 def test_c1_solve_plain_fp64(stf, ctx):
     """Config 1 (plain method, complex128): FGMRES to rel-res 1e-12 equals the
     global direct solve to 1e-10."""
