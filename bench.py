@@ -97,6 +97,15 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
         ctx.set_timing(False)
         infos[:] = timed_infos
     info = pb.info()
+    if nrhs == 1:
+        # Power of the last solution through two horizontal lines ten cells
+        # inside the global PML: towards +y near the top, towards -y near the
+        # bottom (the source sheet lies between them).
+        pml_lo, pml_hi = w.params()["pml"][2], w.params()["pml"][3]
+        lo, hi = w.params()["pml"][0], w.nx - w.params()["pml"][1]
+        up = pb.line_flux(x, 1, w.ny - pml_hi - 11, lo, hi)
+        down = -pb.line_flux(x, 1, pml_lo + 10, lo, hi)
+        info["power"] = {"up": up, "down": down}
     pb.close()
     return (t1 - t0) / steps, infos, stats, info, profile
 
@@ -331,7 +340,7 @@ def main():
                       "ndof": N, "form": "mixed (complex64 fronts, FP64 FGMRES)",
                       "restart": args.restart, "tol": args.tol, "parallelism": "1 GPU"},
            "iters": inf_mixed[0]["iters"], "relres_true": inf_mixed[0]["relres_true"],
-           "converged": ok}
+           "converged": ok, "power": {k: round(v, 6) for k, v in info["power"].items()}}
     if stats:
         dom, rl = roofline(stf, w, stf.STF_C64, inf_mixed, stats, args.steps)
         out["roofline"] = rl
