@@ -139,3 +139,19 @@ def test_network_parameter_count_matches_reference(stf):
         assert stf.nn_param_count(c.n, c.width, c.modes, c.layers, c.cin) == c.nparams()
     assert stf.nn_param_count(16, 16, 9, 4) == -1          # 2M > n
     assert stf.nn_param_count(256, 12, 16, 4) == -1        # unsupported width
+
+
+def test_public_header_is_plain_c(tmp_path):
+    """include/stfdfd.h compiles as C99 (the ABI has no C++ types) with warnings
+    as errors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    src = tmp_path / "use.c"
+    src.write_text('#include "stfdfd.h"\nint main(void) { return STF_OK; }\n')
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", inc,
+                        str(src)], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
