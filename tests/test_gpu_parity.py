@@ -191,6 +191,9 @@ def test_line_flux_matches_oracle(stf, ctx):
     j = wc.ny // 2
     ref = fdfd.line_flux(x, wc.nx, wc.ny, 0, j, 20, wc.ny - 20, pc["k0"], pc["dx"], pc["dy"])
     assert pb.line_flux(x, 0, j, 20, wc.ny - 20) == pytest.approx(ref, rel=1e-12)
+    import torch
+    xd = torch.from_numpy(x).cuda()                 # the same field from device memory
+    assert pb.line_flux(xd, 0, j, 20, wc.ny - 20) == pytest.approx(ref, rel=1e-12)
     pb.close()
 
 
