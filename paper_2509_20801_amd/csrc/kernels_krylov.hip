@@ -487,9 +487,31 @@ __global__ __launch_bounds__(KT) void k_scale_givens(const double2* __restrict__
     scale_body(w, wnorm2, v, n, gate, blockIdx.x - 1, gridDim.x - 1);
 }
 
+// y = R^{-1} g by back substitution on one thread.  For k <= TSL the upper
+// triangle of R and g are first staged in LDS by the whole block, so that the
+// serial chain waits on no memory round trips; larger k reads them directly.
+constexpr int TSL = 40;
 __global__ void k_trisolve(const double2* __restrict__ H, const double2* __restrict__ g,
                            double2* __restrict__ y, int k, int ldh) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  __shared__ double2 R[TSL * TSL];
+  __shared__ double2 gs[TSL], ys[TSL];
+  if (k <= TSL) {
+    for (int e = threadIdx.x; e < k * k; e += blockDim.x) {
+      const int c = e / k, r = e - c * k;
+      if (r <= c) R[c * TSL + r] = H[(long long)c * ldh + r];
+    }
+    for (int i = threadIdx.x; i < k; i += blockDim.x) gs[i] = g[i];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = k - 1; i >= 0; --i) {
+      double2 s = gs[i];
+      for (int t = i + 1; t < k; ++t) s = cfms(R[t * TSL + i], ys[t], s);
+      ys[i] = cdiv(s, R[i * TSL + i]);
+      y[i] = ys[i];
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
   for (int i = k - 1; i >= 0; --i) {
     double2 s = g[i];
     for (int t = i + 1; t < k; ++t) s = cfms(H[(long long)t * ldh + i], y[t], s);
