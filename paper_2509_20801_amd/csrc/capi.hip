@@ -1075,11 +1075,9 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
         if (!R[s].stop && R[s].it < o.max_iter) nxt.push_back(s);
       cur.swap(nxt);
     }
-    if (last >= 0) {
-      HIP_CHECK(hipEventSynchronize(c->iter_ev[last & 1]));
-      for (int s : prev)
-        if (!R[s].stop && R[s].launched == last + 1) check(R[s], last);
-    }
+    // The cycle's length k is fixed by the checks above (the last iteration's
+    // own estimate only adds to the history), so the update and the true
+    // residual are enqueued before the host waits for that estimate.
     for (int s : active) {
       RhsRun& q = R[s];
       if (!q.stop) q.k = q.launched;
@@ -1090,6 +1088,11 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
       }
       residual(pb, q.x, q.b, q.r, q.sc + 2);
       HIP_CHECK(hipMemcpyAsync(q.hp + 2, q.sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+    }
+    if (last >= 0) {
+      HIP_CHECK(hipEventSynchronize(c->iter_ev[last & 1]));
+      for (int s : prev)
+        if (!R[s].stop && R[s].launched == last + 1) check(R[s], last);
     }
     HIP_CHECK(hipStreamSynchronize(st));
     for (int s : active) {
