@@ -64,6 +64,7 @@ struct stf_ctx_s {
   double* pinned = nullptr;     // pinned host staging: 64 doubles per right-hand side
   double* pinned_dev = nullptr; // the same memory as the device addresses it
   hipEvent_t iter_ev[2] = {nullptr, nullptr};   // per-iteration estimate copies
+  hipEvent_t cycle_ev = nullptr;                // true residuals of a restart copied
   stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
 
   hipEvent_t get_event() {
@@ -830,7 +831,7 @@ void nn_initial_guess(stf_problem pb, stf_nn nn, const double2* b, double2* x0) 
 
 // Per right-hand side state of the lockstep FGMRES.  Device scalars sc:
 // [0] |b|^2, [2] |r|^2, [3] |w|^2, [4] residual estimate; pinned host hp:
-// [0..3] copies of sc, [8..9] g_0 staging, [16..19] |w|^2 and the estimate of
+// [0..3] copies of sc, [16..19] |w|^2 and the estimate of
 // the last two iterations (written by the Givens step itself through hpd, the
 // device address of hp).
 struct RhsRun {
@@ -842,6 +843,7 @@ struct RhsRun {
   stf_solve_info* info = nullptr;
   double bnorm = 0.0, rnorm = 0.0, relres_guess = 0.0;
   int used_learned = 0, it = 0, restarts = 0, hlen = 0, k = 0, launched = 0;
+  bool started = false;   // the next cycle's start is already enqueued
   bool done = false, stop = false;
   stf_status status = STF_ENOCONV;
   void hist(double v) {
@@ -1028,14 +1030,11 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
     if (active.empty()) break;
     for (int s : active) {
       RhsRun& q = R[s];
-      {
+      if (!q.started) {
         Timed t(c, K_UPDATE);
-        launch_scale(st, q.r, q.sc + 2, q.V, N);              // v_0 = r / |r|
+        launch_cycle_start(st, q.r, q.sc + 2, q.V, N, q.g, m + 1);   // v_0 = r / |r|, g = |r| e_1
       }
-      HIP_CHECK(hipMemsetAsync(q.g, 0, sizeof(double2) * (m + 1), st));
-      q.hp[8] = q.rnorm;
-      q.hp[9] = 0.0;
-      HIP_CHECK(hipMemcpyAsync(q.g, q.hp + 8, sizeof(double2), hipMemcpyHostToDevice, st));
+      q.started = false;
       q.stop = false;
       q.k = 0;
       q.launched = 0;
@@ -1089,12 +1088,22 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
       residual(pb, q.x, q.b, q.r, q.sc + 2);
       HIP_CHECK(hipMemcpyAsync(q.hp + 2, q.sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
     }
+    HIP_CHECK(hipEventRecord(c->cycle_ev, st));
+    // The next cycle's start needs only device values: enqueued now, it runs
+    // while the host reads the true residuals; a right-hand side that has
+    // converged or run out of iterations ignores it (it writes v_0 and g only).
+    for (int s : active) {
+      RhsRun& q = R[s];
+      Timed t(c, K_UPDATE);
+      launch_cycle_start(st, q.r, q.sc + 2, q.V, N, q.g, m + 1);
+      q.started = true;
+    }
     if (last >= 0) {
       HIP_CHECK(hipEventSynchronize(c->iter_ev[last & 1]));
       for (int s : prev)
         if (!R[s].stop && R[s].launched == last + 1) check(R[s], last);
     }
-    HIP_CHECK(hipStreamSynchronize(st));
+    HIP_CHECK(hipEventSynchronize(c->cycle_ev));
     for (int s : active) {
       RhsRun& q = R[s];
       q.rnorm = std::sqrt(q.hp[2]);
@@ -1158,6 +1167,7 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
     HIP_CHECK(hipHostGetDevicePointer((void**)&c->pinned_dev, c->pinned, 0));
     for (int e = 0; e < 2; ++e)
       HIP_CHECK(hipEventCreateWithFlags(&c->iter_ev[e], hipEventDisableTiming));
+    HIP_CHECK(hipEventCreateWithFlags(&c->cycle_ev, hipEventDisableTiming));
   });
   if (s != STF_OK) {
     g_noctx_error = c->last_error;
@@ -1181,6 +1191,7 @@ void stf_ctx_destroy(stf_ctx c) {
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   for (int e = 0; e < 2; ++e)
     if (c->iter_ev[e]) (void)hipEventDestroy(c->iter_ev[e]);
+  if (c->cycle_ev) (void)hipEventDestroy(c->cycle_ev);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;

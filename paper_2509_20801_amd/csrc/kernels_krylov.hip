@@ -383,6 +383,18 @@ __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
   scale_body(w, nrm2, v, n, skip, blockIdx.x, gridDim.x);
 }
 
+// The start of an FGMRES cycle: v_0 = r / |r| (|r|^2 in nrm2[0]), and block 0
+// also sets g = (|r|, 0, ..., 0) (glen entries), all from device values.
+__global__ __launch_bounds__(KT) void k_cycle_start(const double2* __restrict__ r,
+                                                    const double* __restrict__ nrm2,
+                                                    double2* __restrict__ v, long long n,
+                                                    double2* __restrict__ g, int glen) {
+  if (blockIdx.x == 0)
+    for (int i = threadIdx.x; i < glen; i += KT)
+      g[i] = make_double2(i == 0 ? sqrt(nrm2[0]) : 0.0, 0.0);
+  scale_body(r, nrm2, v, n, nullptr, blockIdx.x, gridDim.x);
+}
+
 // One Givens step of FGMRES for column j.
 //   column j of the Hessenberg matrix: h[i] (i <= j), h[j+1] = |w|.
 //   Earlier rotations are applied, a new one zeroes h[j+1], g is rotated and
@@ -623,6 +635,11 @@ void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* ou
 
 void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate) {
   hipLaunchKernelGGL(k_hacc, dim3(1), dim3(256), 0, st, h1, h2, nv, gate);
+}
+
+void launch_cycle_start(hipStream_t st, const double2* r, const double* nrm2, double2* v,
+                        long long n, double2* g, int glen) {
+  hipLaunchKernelGGL(k_cycle_start, dim3(grid_for(n)), dim3(KT), 0, st, r, nrm2, v, n, g, glen);
 }
 
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n,

@@ -260,6 +260,10 @@ void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, cons
 void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* out,
                         const double* ref, int* gate, int decide);
 void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate);
+// Start of an FGMRES cycle: v = r / sqrt(nrm2), g = (sqrt(nrm2), 0, ...) of glen
+// entries, from device values only.
+void launch_cycle_start(hipStream_t st, const double2* r, const double* nrm2, double2* v,
+                        long long n, double2* g, int glen);
 // v = w / sqrt(nrm2) (skipped when skip and skip[0] != 0)
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v,
                   long long n, const int* skip = nullptr);
