@@ -93,6 +93,12 @@ typedef struct {
   int32_t rounds;     /* source-transfer rounds per preconditioner application (0 or 1 = one
                          round z = B v; r > 1 adds r-1 stationary corrections
                          z += B (v - A z), i.e. r Jacobi rounds of Algorithm 1; <= 8) */
+  int32_t debug_fault; /* test hook of the tiny-pivot path (Eq. (22) with pivoting): 0 = off;
+                          1 = before iterating, factor the problem again with one planted
+                          fault, the first pivot column of one front of the deepest tree
+                          level zeroed on its fully summed rows, so that the pivot is
+                          replaced by its perturbation.  The solve then returns STF_EPIVOT
+                          when every right-hand side converged (info.status stays STF_OK). */
 } stf_solve_opts;
 
 typedef struct {
@@ -107,6 +113,11 @@ typedef struct {
                              estimate after every iteration, true residual at x0 first */
   int32_t history_cap;    /* capacity of history */
   int32_t used_learned;   /* STF_X0_LEARNED: 1 if the network's guess was kept, 0 after fallback */
+  /* Phase timers (device time, HIP events on the context stream, ms). */
+  double  t_factor_ms;    /* the problem's most recent factorisation */
+  double  t_solve_ms;     /* this call's solve of the group of right-hand sides swept with this
+                             one (initial residuals to the last true residual) */
+  double  t_nn_ms;        /* the network's guess for this right-hand side (STF_X0_LEARNED) */
 } stf_solve_info;
 
 /* Sizes and work counts of a plan. */

@@ -292,9 +292,11 @@ class Problem:
         return (x if dev else kx.reshape(tuple(b.shape))), info
 
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
-              raise_on_noconv=False, rounds=1):
+              raise_on_noconv=False, rounds=1, debug_fault=0):
         """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos).
-        x0: None (zero guess), an array (user guess) or "learned" (the context's network)."""
+        x0: None (zero guess), an array (user guess) or "learned" (the context's network).
+        debug_fault=1 re-factors with one planted zero pivot column first (test hook of the
+        tiny-pivot path); the call then reports STF_EPIVOT as info["epivot"]."""
         shape = tuple(b.shape)
         nrhs = 1 if len(shape) == 2 else int(shape[0])
         n = self.ndof
@@ -318,22 +320,24 @@ class Problem:
         pxx, dev2, kx = _ptr(x, nrhs * n, "x")
         if dev != dev2:
             raise TypeError("b and x must both be host or both be device arrays")
-        opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, int(rounds))
+        opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, int(rounds),
+                              int(debug_fault))
         infos = (_abi.SolveInfo * nrhs)()
         hist = [np.zeros(history_cap, dtype=np.float64) for _ in range(nrhs)]
         for i in range(nrhs):
             infos[i].history = hist[i].ctypes.data_as(C.POINTER(C.c_double))
             infos[i].history_cap = history_cap
-        allow = () if raise_on_noconv else (_abi.STF_ENOCONV,)
-        _check(self.ctx.handle, self._lib.stf_solve(self.handle, nrhs, pb_, pxx, dev,
-                                                    C.byref(opts), infos), allow=allow)
+        allow = (_abi.STF_EPIVOT,) if raise_on_noconv else (_abi.STF_ENOCONV, _abi.STF_EPIVOT)
+        st = _check(self.ctx.handle, self._lib.stf_solve(self.handle, nrhs, pb_, pxx, dev,
+                                                         C.byref(opts), infos), allow=allow)
         out = []
         for i in range(nrhs):
             inf = infos[i]
             out.append(dict(iters=inf.iters, restarts=inf.restarts, status=inf.status,
                             relres_true=inf.relres_true, relres_x0=inf.relres_x0,
-                            used_learned=inf.used_learned,
-                            history=hist[i][:inf.history_len].copy()))
+                            used_learned=inf.used_learned, epivot=st == _abi.STF_EPIVOT,
+                            t_factor_ms=inf.t_factor_ms, t_solve_ms=inf.t_solve_ms,
+                            t_nn_ms=inf.t_nn_ms, history=hist[i][:inf.history_len].copy()))
         xo = x if dev else kx.reshape(shape)
         return xo, out
 

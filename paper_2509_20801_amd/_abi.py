@@ -27,14 +27,15 @@ class Params(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("x0_mode", C.c_int32), ("rounds", C.c_int32)]
+                ("x0_mode", C.c_int32), ("rounds", C.c_int32), ("debug_fault", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32), ("restarts", C.c_int32), ("status", C.c_int32),
                 ("history_len", C.c_int32), ("relres_true", C.c_double),
                 ("relres_x0", C.c_double), ("history", C.POINTER(C.c_double)),
-                ("history_cap", C.c_int32), ("used_learned", C.c_int32)]
+                ("history_cap", C.c_int32), ("used_learned", C.c_int32),
+                ("t_factor_ms", C.c_double), ("t_solve_ms", C.c_double), ("t_nn_ms", C.c_double)]
 
 
 class NNConfig(C.Structure):

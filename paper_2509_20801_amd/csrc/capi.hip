@@ -156,6 +156,24 @@ struct stf_problem_s {
   DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
   DBuf hb, hx, cells;              // staging for host inputs
   int krylov_m = 0, krylov_nr = 0, ws_nr = 1;
+  // Phase timers: [0, 1] the last factorisation, [2, 3] a solve group, [4 + 2 s, 5 + 2 s]
+  // the network's guess of right-hand side s of the group.
+  hipEvent_t ev[4 + 2 * MAX_RHS] = {};
+  bool fac_timed = false;
+
+  ~stf_problem_s() {
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void make_events() {
+    for (hipEvent_t& e : ev)
+      if (!e) HIP_CHECK(hipEventCreate(&e));
+  }
+  // Elapsed ms between events a and b (both recorded and complete), else 0.
+  double elapsed(int a, int b) const {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, ev[a], ev[b]) == hipSuccess ? (double)ms : 0.0;
+  }
 
   const double2* cxw() const { return gcoef.as<double2>(); }
   const double2* cxe() const { return gcoef.as<double2>() + prm.nx; }
@@ -457,17 +475,24 @@ void assemble_eps(stf_problem pb, const double* eps, int on_device) {
   pb->factored = false;
 }
 
+// Numeric factorisation of every level; with `fault`, the first front of the
+// deepest level gets the planted zero pivot column (test hook).
 template <typename T>
-int factor_t(stf_problem pb) {
+int factor_t(stf_problem pb, bool fault = false) {
   hipStream_t st = pb->ctx->stream;
   T* fac = pb->fac.as<T>();
   HIP_CHECK(hipMemsetAsync(pb->flag.p, 0, sizeof(int), st));
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
+  HIP_CHECK(hipEventRecord(pb->ev[0], st));
   for (int d = pb->max_depth; d >= 0; --d) {
     Timed t(pb->ctx, K_FRONT_LU);
-    launch_front_factor<T>(st, pb->level_args(d), fac, pb->lpk.as<T>(), pb->upk.as<T>(), pb->piv.as<int>(),
+    LevelArgs la = pb->level_args(d);
+    if (fault && d == pb->max_depth) la.fault = la.first;
+    launch_front_factor<T>(st, la, fac, pb->lpk.as<T>(), pb->upk.as<T>(), pb->piv.as<int>(),
                            pb->flag.as<int>(), tau);
   }
+  HIP_CHECK(hipEventRecord(pb->ev[1], st));
+  pb->fac_timed = true;
   HIP_CHECK(hipGetLastError());
   int h = 0;
   HIP_CHECK(hipMemcpyAsync(&h, pb->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -891,11 +916,15 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
     q.info = info ? info + s : nullptr;
   }
   // Initial guesses and residuals.
-  for (auto& q : R) {
+  HIP_CHECK(hipEventRecord(pb->ev[2], st));
+  for (int s = 0; s < nr; ++s) {
+    RhsRun& q = R[s];
     if (o.x0_mode == STF_X0_ZERO) HIP_CHECK(hipMemsetAsync(q.x, 0, N * sizeof(double2), st));
     if (o.x0_mode == STF_X0_LEARNED) {
       STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+      HIP_CHECK(hipEventRecord(pb->ev[4 + 2 * s], st));
       nn_initial_guess(pb, c->nn, q.b, q.x);
+      HIP_CHECK(hipEventRecord(pb->ev[5 + 2 * s], st));
     }
     norm2(pb, q.b, reinterpret_cast<double2*>(q.sc));     // sc[0] = |b|^2
     residual(pb, q.x, q.b, q.r, q.sc + 2);                // sc[2] = |r|^2
@@ -1111,10 +1140,17 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
       if (!std::isfinite(q.rnorm)) throw Error(STF_ENAN, "non-finite true residual");
     }
   }
+  HIP_CHECK(hipEventRecord(pb->ev[3], st));
+  HIP_CHECK(hipEventSynchronize(pb->ev[3]));
+  const double t_solve = pb->elapsed(2, 3), t_fac = pb->fac_timed ? pb->elapsed(0, 1) : 0.0;
   stf_status worst = STF_OK;
-  for (auto& q : R) {
+  for (int s = 0; s < nr; ++s) {
+    RhsRun& q = R[s];
     if (q.info) {
       stf_solve_info loc{};
+      loc.t_factor_ms = t_fac;
+      loc.t_solve_ms = t_solve;
+      loc.t_nn_ms = o.x0_mode == STF_X0_LEARNED ? pb->elapsed(4 + 2 * s, 5 + 2 * s) : 0.0;
       loc.iters = q.it;
       loc.restarts = q.restarts;
       loc.relres_true = q.bnorm > 0.0 ? q.rnorm / q.bnorm : 0.0;
@@ -1289,6 +1325,7 @@ stf_status stf_problem_create(stf_ctx c, const stf_params* prm, const double* ep
     pb->ctx = c;
     pb->plan = build_plan(*prm, &c->shapes);
     pb->prm = pb->plan.prm;
+    pb->make_events();
     build_device_state(pb);
     assemble_eps(pb, eps_cells, on_device);
   });
@@ -1493,6 +1530,7 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
                      const stf_solve_opts* opts, stf_solve_info* info) {
   if (!pb) return STF_EINVAL;
   stf_status worst = STF_OK;
+  bool perturbed = false;
   stf_status s = guard(pb->ctx, [&] {
     STF_REQUIRE(b && x && opts, "null argument");
     STF_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
@@ -1503,7 +1541,12 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
                     opts->x0_mode == STF_X0_LEARNED,
                 "x0_mode invalid");
     STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
+    STF_REQUIRE(opts->debug_fault == 0 || opts->debug_fault == 1, "debug_fault must be 0 or 1");
     if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
+    if (opts->debug_fault == 1) {
+      perturbed = (pb->prec == STF_C64 ? factor_t<float2>(pb, true) : factor_t<double2>(pb, true)) != 0;
+      STF_REQUIRE(perturbed, "internal: the planted fault did not reach the pivot perturbation");
+    }
     const size_t per = (size_t)pb->N * 2;
     require_finite(pb, b, per * nrhs, on_device, "b");
     if (opts->x0_mode == STF_X0_USER) require_finite(pb, x, per * nrhs, on_device, "x0");
@@ -1543,6 +1586,10 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
   });
   if (s != STF_OK) return s;
   if (worst == STF_ENOCONV) pb->ctx->last_error = "FGMRES reached max_iter above tol";
+  if (worst == STF_OK && perturbed) {
+    pb->ctx->last_error = "tiny pivot perturbed during factorisation (planted fault)";
+    return STF_EPIVOT;
+  }
   return worst;
 }
 

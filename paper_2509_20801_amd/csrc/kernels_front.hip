@@ -292,6 +292,10 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
   const FrontDev f = a.fronts[a.first + blockIdx.x];
   const int m = f.p + f.q, p = f.p, lane = threadIdx.x;
   assemble_front<T>(a, fac, f, G, lane, 64, [] { wave_sync(); });
+  if (a.first + (int)blockIdx.x == a.fault) {         // planted fault (test hook)
+    for (int r = lane; r < p; r += 64) G[r] = czero<T>();
+    wave_sync();
+  }
   int* ip = piv + f.piv_off;
   // Pivot choice, perturbation and row exchange of step k (column k as it
   // stands), then the multipliers of column k.
@@ -554,6 +558,10 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
   T* F = fac + f.fac_off;
   // The inverse child maps use the panel's LDS (2 max_m ints <= max_m NB T).
   assemble_front_gather<T>(a, fac, f, F, tid, NTF, reinterpret_cast<int*>(smem_raw));
+  if (a.first + (int)blockIdx.x == a.fault) {         // planted fault (test hook)
+    for (int r = tid; r < p; r += NTF) F[r] = czero<T>();
+    __syncthreads();
+  }
   int* ip = piv + f.piv_off;
 
   for (int kb = 0; kb < p; kb += NB) {

@@ -210,6 +210,9 @@ struct LevelArgs {
   int max_m;                    // largest front in the level
   int max_pm;                   // largest p*m in the level
   int max_p;                    // largest p in the level
+  int fault = -1;               // factorisation test hook: front instance whose first
+                                // pivot column is zeroed on its fully summed rows after
+                                // assembly (-1 = none)
 };
 // Assembly (original entries + extend-add of the children) and partial LU of
 // every front of one level.

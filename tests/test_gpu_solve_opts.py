@@ -1,0 +1,109 @@
+"""GPU checks of the solve options through the C ABI: several source-transfer
+rounds per preconditioner application (rounds > 1), the planted tiny-pivot
+fault (debug_fault), and the phase timers of stf_solve_info.
+
+Tolerances as in test_gpu_parity.py: FGMRES solutions 1e-10 relative L2 at
+rel-res 1e-12 (complex128 fronts) and 1e-8 at rel-res 1e-10 (complex64 fronts).
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import ddm, fdfd, krylov
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def stf():
+    import paper_2509_20801_amd as stf
+    return stf
+
+
+@pytest.fixture(scope="module")
+def ctx(stf):
+    return stf.Context(0)
+
+
+def _prm(w, **over):
+    d = dict(w.params())
+    d.update(over)
+    return d
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+def _case():
+    return workloads.configs.small_random(nx=48, ny=40, pml=6, px=2, py=2, overlap=2, local_pml=6,
+                                          seed=3)
+
+
+@pytest.mark.parametrize("rounds", [2, 3])
+def test_several_rounds_per_application_match_oracle(stf, ctx, rounds):
+    """rounds = r: z = B v, then r - 1 corrections z += B (v - A z) (Algorithm 1's
+    Jacobi rounds inside one preconditioner application).  The FGMRES history
+    follows the oracle's FGMRES with the same r-round preconditioner, and the
+    solution matches the direct solve."""
+    w = _case()
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+
+    def M(v):
+        z = B.apply(v)
+        for _ in range(rounds - 1):
+            z = z + B.apply(v - A @ z)
+        return z
+
+    b = w.b[0]
+    xref = fdfd.solve_direct(A, b.ravel())
+    _, ref = krylov.fgmres(lambda v: A @ v, b.ravel(), M, tol=1e-12, restart=30)
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    pb.factor()
+    x1, i1 = pb.solve(b, tol=1e-12, restart=30, rounds=1)
+    xr, ir = pb.solve(b, tol=1e-12, restart=30, rounds=rounds)
+    assert ir[0]["status"] == 0 and ir[0]["relres_true"] <= 1e-12
+    assert _rel(xr, xref) < 1e-10 and _rel(x1, xref) < 1e-10
+    assert abs(ir[0]["iters"] - ref["iters"]) <= 1
+    assert ir[0]["iters"] < i1[0]["iters"]
+    h, hr = np.asarray(ir[0]["history"]), np.asarray(ref["history"])
+    keep = hr > 1e-9                                  # estimates well above rounding
+    assert np.all(np.abs(h[keep] - hr[keep]) <= 1e-6 * hr[keep])
+    pb.close()
+
+
+@pytest.mark.parametrize("prec,tol,bar", [(0, 1e-12, 1e-10), (1, 1e-10, 1e-8)])
+def test_planted_pivot_fault_is_perturbed_and_absorbed(stf, ctx, prec, tol, bar):
+    """debug_fault = 1 zeroes the fully summed part of one pivot column before its
+    LU: the tiny-pivot perturbation replaces the pivot (STF_EPIVOT), the round is
+    then an inexact preconditioner, and flexible GMRES still reaches tol."""
+    w = _case()
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0]
+    xref = fdfd.solve_direct(A, b.ravel())
+    pb = stf.Problem(ctx, _prm(w, front_prec=prec), w.eps_cells)
+    assert pb.factor() is False
+    v = workloads.sources.random_field(w.nx, w.ny, 21)
+    clean = _rel(pb.precond(v), B.apply(v.ravel()))
+    x, info = pb.solve(b, tol=tol, restart=30, debug_fault=1)
+    assert info[0]["epivot"] and info[0]["status"] == 0
+    assert info[0]["relres_true"] <= tol and _rel(x, xref) < bar
+    faulty = _rel(pb.precond(v), B.apply(v.ravel()))
+    assert faulty > 1e3 * clean and faulty > 1e-6   # the factors did change
+    assert pb.factor() is False                     # a clean factorisation restores them
+    assert _rel(pb.precond(v), B.apply(v.ravel())) <= 2 * clean
+    pb.close()
+
+
+def test_phase_timers(stf, ctx):
+    w = _case()
+    pb = stf.Problem(ctx, _prm(w, front_prec=1), w.eps_cells)
+    pb.factor()
+    _, info = pb.solve(w.b[0], tol=1e-10)
+    assert info[0]["t_factor_ms"] > 0.0 and info[0]["t_solve_ms"] > 0.0
+    assert info[0]["t_nn_ms"] == 0.0
+    pb.close()

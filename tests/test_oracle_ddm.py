@@ -115,3 +115,63 @@ def test_fgmres_with_round_matches_direct():
     x, info = krylov.fgmres(lambda v: A @ v, b, B.apply, tol=1e-12, restart=30)
     assert info["converged"] and info["iters"] <= 12
     assert fdfd.rel_l2(x, fdfd.solve_direct(A, b)) < 1e-11
+
+
+def _ras_round(B, v, ny, nx):
+    """Control for the pins below: the same local solves prolonged only on I_k
+    (a restricted-additive reading the paper's Eq. (21) rules out)."""
+    z = np.zeros((ny, nx), dtype=np.complex128)
+    for s in B.subs:
+        u = B.local_solve(s.k, B.restrict(v, s)).reshape(s.oy[1] - s.oy[0], s.ox[1] - s.ox[0])
+        z[s.iy[0]:s.iy[1], s.ix[0]:s.ix[1]] += u[s.iy[0] - s.oy[0]:s.iy[1] - s.oy[0],
+                                                 s.ix[0] - s.ox[0]:s.ix[1] - s.ox[0]]
+    return z.ravel()
+
+
+def _two_sub_vacuum(overlap=4, local_pml=10):
+    w = workloads.configs.small_random(nx=120, ny=60, pml=10, px=2, py=1, overlap=overlap,
+                                       local_pml=local_pml, seed=1)
+    p = w.params()
+    cells = np.ones_like(w.eps_cells)
+    A = fdfd.global_matrix(p, cells)
+    B = ddm.SourceTransfer(p, cells)
+    b = np.zeros((w.ny, w.nx), dtype=np.complex128)
+    b[w.ny // 2, 30] = 1.0                      # point source in I_1, far from the interface
+    return w, A, B, b.ravel()
+
+
+def test_round_residual_support_is_the_local_pml_band():
+    """Eq. (21) sums the FULL local fields.  Where the local operator equals the
+    global one (I_k and the `overlap` unstretched cells beyond it) the summed
+    field satisfies the global equations, so after the initial solves the
+    residual vanishes on the overlap cells next to the interface, including the
+    first node across it, and lives only in the neighbour's local PML band
+    (nodes c + o .. c + o + L).  A prolongation restricted to I_k leaves a
+    residual right at the interface instead."""
+    w, A, B, b = _two_sub_vacuum(overlap=4, local_pml=10)
+    c = B.subs[1].ix[0]                          # first column of I_2
+    o, L = w.overlap, w.local_pml
+    col = np.abs((b - A @ B.apply(b)).reshape(w.ny, w.nx)).max(axis=0)
+    assert col[c - o:c + o].max() < 1e-13        # both sides of the interface
+    assert col[:c - o].max() < 1e-13 and col[c + o + L + 1:].max() < 1e-13
+    band = col[c + o:c + o + L + 1]
+    assert band.min() > 1e-6 and band.max() > 1e-3
+    ras = np.abs((b - A @ _ras_round(B, b, w.ny, w.nx)).reshape(w.ny, w.nx)).max(axis=0)
+    assert ras[c - 1:c + 1].min() > 1e-3         # the control fails the pin
+
+
+def test_one_round_is_one_way_transfer_in_vacuum():
+    """Two subdomains, vacuum, a point source in Omega_1: the initial solve
+    (Eq. (14)) leaves the transferred source in Omega_2's band; one Jacobi round
+    (Eqs. (18)-(21)) carries the wave on, so the residual drops to the level of
+    the local PML's reflection (here ~7e-6 of |b| with 10 cubic cells, R = 1e-8),
+    and a second round removes the reflections as well."""
+    w, A, B, b = _two_sub_vacuum(overlap=4, local_pml=10)
+    x, hist = ddm.stationary(A, B, b, 2)
+    assert 1e-2 < hist[0] < 1.0
+    assert hist[1] < 1e-4
+    assert hist[2] < 1e-2 * hist[1]
+    # the I_k-restricted control does not transfer the wave
+    y = _ras_round(B, b, w.ny, w.nx)
+    y = y + _ras_round(B, b - A @ y, w.ny, w.nx)
+    assert fdfd.relres(A, y, b) > 0.1
