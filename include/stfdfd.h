@@ -95,10 +95,13 @@ typedef struct {
                          z += B (v - A z), i.e. r Jacobi rounds of Algorithm 1; <= 8) */
   int32_t debug_fault; /* test hook of the tiny-pivot path (Eq. (22) with pivoting): 0 = off;
                           1 = before iterating, factor the problem again with one planted
-                          fault, the first pivot column of one front of the deepest tree
-                          level zeroed on its fully summed rows, so that the pivot is
-                          replaced by its perturbation.  The solve then returns STF_EPIVOT
-                          when every right-hand side converged (info.status stays STF_OK). */
+                          fault, the first pivot column of one front of tree level 1
+                          zeroed on its fully summed rows, so that the pivot is replaced
+                          by its perturbation (multipliers then grow like 1/tau, which
+                          limits the attainable accuracy).  The solve then returns
+                          STF_EPIVOT when every right-hand side converged (info.status
+                          stays STF_OK).  The factors keep the fault until the next
+                          stf_factor. */
 } stf_solve_opts;
 
 typedef struct {

@@ -475,10 +475,13 @@ void assemble_eps(stf_problem pb, const double* eps, int on_device) {
   pb->factored = false;
 }
 
-// Numeric factorisation of every level; with `fault`, the first front of the
-// deepest level gets the planted zero pivot column (test hook).
+// Numeric factorisation of every level; with `fault`, the first front of
+// tree level 1 gets the planted zero pivot column (test hook): its first column
+// carries fill in the update rows after assembly, so the perturbation has a
+// nonzero column maximum to scale.
 template <typename T>
 int factor_t(stf_problem pb, bool fault = false) {
+  STF_REQUIRE(!fault || pb->max_depth >= 1, "the planted fault needs a tree of two levels or more");
   hipStream_t st = pb->ctx->stream;
   T* fac = pb->fac.as<T>();
   HIP_CHECK(hipMemsetAsync(pb->flag.p, 0, sizeof(int), st));
@@ -487,7 +490,7 @@ int factor_t(stf_problem pb, bool fault = false) {
   for (int d = pb->max_depth; d >= 0; --d) {
     Timed t(pb->ctx, K_FRONT_LU);
     LevelArgs la = pb->level_args(d);
-    if (fault && d == pb->max_depth) la.fault = la.first;
+    if (fault && d == 1) la.fault = la.first;
     launch_front_factor<T>(st, la, fac, pb->lpk.as<T>(), pb->upk.as<T>(), pb->piv.as<int>(),
                            pb->flag.as<int>(), tau);
   }

@@ -74,11 +74,16 @@ def test_several_rounds_per_application_match_oracle(stf, ctx, rounds):
     pb.close()
 
 
-@pytest.mark.parametrize("prec,tol,bar", [(0, 1e-12, 1e-10), (1, 1e-10, 1e-8)])
-def test_planted_pivot_fault_is_perturbed_and_absorbed(stf, ctx, prec, tol, bar):
+@pytest.mark.parametrize("prec", [0, 1])
+def test_planted_pivot_fault_is_perturbed_and_absorbed(stf, ctx, prec):
     """debug_fault = 1 zeroes the fully summed part of one pivot column before its
-    LU: the tiny-pivot perturbation replaces the pivot (STF_EPIVOT), the round is
-    then an inexact preconditioner, and flexible GMRES still reaches tol."""
+    LU: the tiny-pivot perturbation replaces the pivot by tau max|column| (tau =
+    1e-10 complex128, 1e-5 complex64; STF_EPIVOT), so that front's multipliers
+    grow like 1/tau and the round becomes the inverse of a nearly singular
+    neighbour of A_k.  Flexible GMRES still converges; its attainable accuracy is
+    about (unit roundoff) / tau of FP64 for complex128 fronts, so the check runs
+    at tol 1e-6 for both precisions (solution within 1e-5 of the direct solve)."""
+    tol, bar = 1e-6, 1e-5
     w = _case()
     p = w.params()
     A = fdfd.global_matrix(p, w.eps_cells)
@@ -90,7 +95,12 @@ def test_planted_pivot_fault_is_perturbed_and_absorbed(stf, ctx, prec, tol, bar)
     v = workloads.sources.random_field(w.nx, w.ny, 21)
     clean = _rel(pb.precond(v), B.apply(v.ravel()))
     x, info = pb.solve(b, tol=tol, restart=30, debug_fault=1)
-    assert info[0]["epivot"] and info[0]["status"] == 0
+    i0 = info[0]
+    msg = "status %d epivot %s iters %d relres %.3e hist %s" % (
+        i0["status"], i0["epivot"], i0["iters"], i0["relres_true"],
+        np.array2string(np.asarray(i0["history"])[:40], precision=2))
+    print(msg, flush=True)
+    assert i0["epivot"] and i0["status"] == 0, msg
     assert info[0]["relres_true"] <= tol and _rel(x, xref) < bar
     faulty = _rel(pb.precond(v), B.apply(v.ravel()))
     assert faulty > 1e3 * clean and faulty > 1e-6   # the factors did change
