@@ -230,6 +230,19 @@ stf_status  stf_precond_apply(stf_problem pb, const double* v, double* z, int on
  * stf_precond_apply on its own vector. */
 stf_status  stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v, double* z,
                                     int on_device);
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the round of
+ * stf_precond_apply on device buffers, allocating nothing.  v, z: ny*nx complex,
+ * DEVICE pointers (caller-owned, ordered on the context stream; the call returns
+ * after enqueueing, without synchronising).  The round's workspace (front
+ * vectors and local fields, fully written before they are read) lives in a
+ * static per-device array of 128 MiB that the library holds until the process
+ * ends: problems whose workspace exceeds it (about 1.2M DoF with complex128
+ * fronts, 2.3M with complex64 at 8 x 8 subdomains) are rejected with STF_EINVAL
+ * before anything is launched.  Every call on one device shares that array, so
+ * calls whose work overlaps on one device (several streams or host threads)
+ * race.  STF_ESTATE before stf_factor.  No event timing is recorded. */
+stf_status  stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z);
 stf_status  stf_problem_info(stf_problem pb, stf_plan_info* out);
 void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
 

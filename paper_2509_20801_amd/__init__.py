@@ -260,6 +260,15 @@ class Problem:
             _check(self.ctx.handle, self._lib.stf_precond_apply_batch(self.handle, nrhs, pv, pz, dev))
         return z if dev else kz.reshape(shape)
 
+    def precond_noalloc(self, v, z):
+        """One source-transfer round into the preallocated z with the library's
+        static workspace (no device allocation); v, z: complex128 CUDA tensors
+        shaped (ny, nx).  Enqueued on the context stream, not synchronised."""
+        n = self.ndof
+        _check(self.ctx.handle, self._lib.stf_precond_apply_noalloc(
+            self.handle, _cptr(v, n, "v"), _cptr(z, n, "z")))
+        return z
+
     def line_flux(self, e, axis, index, lo, hi):
         """Power through the grid line between node rows (axis 1) or columns
         (axis 0) index and index + 1, nodes [lo, hi) along it: the line integral

@@ -70,6 +70,7 @@ EXPORTS = {
                             C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "stf_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "stf_precond_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "stf_precond_apply_batch": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_stationary_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
                                        C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 
 #include "cplx.h"
@@ -48,6 +49,32 @@ struct Level {
 
 }  // namespace
 
+// Workspace of the allocation-free round (stf_precond_apply_noalloc): the front
+// vectors and the local fields of one right-hand side.  Each device holds its
+// own copy until the process ends; host code uses only the per-device address
+// that hipGetSymbolAddress returns (g_scratch), never the symbol itself.
+constexpr size_t SCRATCH_BYTES = size_t(128) << 20;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[MAX_DEVICES] = {};
+
+// Address of this device's scratch array (the device must be current).
+void* scratch_address(int device) {
+  STF_REQUIRE(device >= 0 && device < MAX_DEVICES, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[device]) {
+    void* ptr = nullptr;
+    HIP_CHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    STF_REQUIRE(ptr != nullptr, "hipGetSymbolAddress returned no address for the scratch array");
+    g_scratch[device] = ptr;
+  }
+  return g_scratch[device];
+}
+}  // namespace
+
 struct stf_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -66,6 +93,7 @@ struct stf_ctx_s {
   hipEvent_t iter_ev[2] = {nullptr, nullptr};   // per-iteration estimate copies
   hipEvent_t cycle_ev = nullptr;                // true residuals of a restart copied
   stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
+  void* scratch = nullptr;      // this device's scratch array (allocation-free round)
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -109,7 +137,7 @@ struct Timed {
   int cls;
   hipEvent_t b = nullptr;
   Timed(stf_ctx c_, int cls_) : c(c_), cls(cls_) {
-    if (c->timing && (c->timing_mask >> cls & 1u)) {
+    if (c && c->timing && (c->timing_mask >> cls & 1u)) {
       if (c->npending() > 16384) c->fold();
       b = c->get_event();
       HIP_CHECK(hipEventRecord(b, c->stream));
@@ -505,30 +533,45 @@ int factor_t(stf_problem pb, bool fault = false) {
 
 // z_s = sum_k P_k A_k^{-1} R_k^I v_s  (one source-transfer round) for the
 // right-hand sides of r, swept together.
+// The launches of one round with explicit workspaces: front vectors `vec` and
+// local fields `u` (vec_elems and u_elems entries per right-hand side).  With
+// timed = false no event is recorded (the allocation-free entry point).
+template <typename T>
+void precond_launch(stf_problem pb, RhsSet r, T* vec, T* u, bool timed) {
+  hipStream_t st = pb->ctx->stream;
+  stf_ctx tc = timed ? pb->ctx : nullptr;
+  r.vec_stride = pb->vec_elems;
+  r.u_stride = pb->u_elems;
+  const T* lpk = pb->lpk.as<T>();
+  for (int d = pb->max_depth; d >= 0; --d) {
+    Timed t(tc, K_SWEEP_FWD);
+    launch_sweep_fwd<T>(st, pb->level_args(d), lpk, pb->piv.as<int>(), vec, r);
+  }
+  for (int d = 0; d <= pb->max_depth; ++d) {
+    Timed t(tc, K_SWEEP_BWD);
+    launch_sweep_bwd<T>(st, pb->level_args(d), pb->upk.as<T>(), vec, u, r);
+  }
+  Timed t(tc, K_SCATTER);
+  launch_scatter<T>(st, u, pb->subs.as<SubDev>(), pb->cover_x.as<int4>(), pb->cover_y.as<int4>(),
+                    pb->prm.px, pb->prm.nx, pb->prm.ny, r);
+}
+
 template <typename T>
 void precond_t(stf_problem pb, RhsSet r) {
-  hipStream_t st = pb->ctx->stream;
   if (pb->ws_nr < r.nr) {
     const size_t es = sizeof(T);
     pb->vec.alloc((size_t)pb->vec_elems * es * r.nr);
     pb->u.alloc((size_t)pb->u_elems * es * r.nr);
     pb->ws_nr = r.nr;
   }
-  r.vec_stride = pb->vec_elems;
-  r.u_stride = pb->u_elems;
-  const T* lpk = pb->lpk.as<T>();
-  T* vec = pb->vec.as<T>();
-  for (int d = pb->max_depth; d >= 0; --d) {
-    Timed t(pb->ctx, K_SWEEP_FWD);
-    launch_sweep_fwd<T>(st, pb->level_args(d), lpk, pb->piv.as<int>(), vec, r);
-  }
-  for (int d = 0; d <= pb->max_depth; ++d) {
-    Timed t(pb->ctx, K_SWEEP_BWD);
-    launch_sweep_bwd<T>(st, pb->level_args(d), pb->upk.as<T>(), vec, pb->u.as<T>(), r);
-  }
-  Timed t(pb->ctx, K_SCATTER);
-  launch_scatter<T>(st, pb->u.as<T>(), pb->subs.as<SubDev>(), pb->cover_x.as<int4>(),
-                    pb->cover_y.as<int4>(), pb->prm.px, pb->prm.nx, pb->prm.ny, r);
+  precond_launch<T>(pb, r, pb->vec.as<T>(), pb->u.as<T>(), true);
+}
+
+// Bytes of the workspace of one right-hand side's round.
+size_t round_workspace_bytes(stf_problem pb) {
+  const size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
+  const size_t a = (size_t)pb->vec_elems * es;
+  return ((a + 255) & ~size_t(255)) + (size_t)pb->u_elems * es;
 }
 
 void precond_set(stf_problem pb, const RhsSet& r) {
@@ -1207,6 +1250,7 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
     for (int e = 0; e < 2; ++e)
       HIP_CHECK(hipEventCreateWithFlags(&c->iter_ev[e], hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&c->cycle_ev, hipEventDisableTiming));
+    c->scratch = scratch_address(device);
   });
   if (s != STF_OK) {
     g_noctx_error = c->last_error;
@@ -1401,6 +1445,33 @@ stf_status stf_precond_apply(stf_problem pb, const double* v, double* z, int on_
     precond(pb, pb->hb.as<double2>(), pb->hx.as<double2>());
     HIP_CHECK(hipMemcpyAsync(z, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+  });
+}
+
+stf_status stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(v && z, "null argument");
+    const size_t need = round_workspace_bytes(pb);
+    if (need > SCRATCH_BYTES)
+      throw Error(STF_EINVAL, "problem needs " + std::to_string(need) +
+                                  " bytes of round workspace; the allocation-free round holds at most " +
+                                  std::to_string(SCRATCH_BYTES));
+    if (!pb->factored) throw Error(STF_ESTATE, "precond before factor");
+    unsigned char* base = static_cast<unsigned char*>(pb->ctx->scratch);
+    const size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
+    const size_t voff = ((size_t)pb->vec_elems * es + 255) & ~size_t(255);
+    RhsSet r;
+    r.nr = 1;
+    r.v[0] = reinterpret_cast<const double2*>(v);
+    r.z[0] = reinterpret_cast<double2*>(z);
+    if (pb->prec == STF_C64)
+      precond_launch<float2>(pb, r, reinterpret_cast<float2*>(base),
+                             reinterpret_cast<float2*>(base + voff), false);
+    else
+      precond_launch<double2>(pb, r, reinterpret_cast<double2*>(base),
+                              reinterpret_cast<double2*>(base + voff), false);
+    HIP_CHECK(hipGetLastError());
   });
 }
 
