@@ -164,26 +164,267 @@ struct Timed {
 
 }  // namespace
 
+// Fronts, subdomains and round workspaces of one or more problems in one set of
+// device arrays.  Problem p's nodes are the segment [gbase[p], gbase[p] + nx*ny)
+// of concatenated global vectors; the fronts of all problems are ordered by tree
+// level (largest first within a level), so one launch per level serves them all.
+struct Mf {
+  int prec = STF_C128;
+  int nprob = 0, nsub = 0, max_depth = -1, max_nx = 0, max_ny = 0;
+  int64_t n_fronts = 0, fac_elems = 0, lpk_elems = 0, upk_elems = 0, vec_elems = 0,
+          piv_elems = 0, u_elems = 0;
+  std::vector<Level> levels;     // by depth
+  DBuf lcoef, subs, fronts, vars, cmap, ents, children, cover_x, cover_y, scat;
+  DBuf fac, lpk, upk, piv, vec, u;
+  int ws_nr = 0;                 // right-hand sides the vec / u workspaces hold
+
+  LevelArgs level_args(int d, const double2* keps, const int* pact = nullptr) const {
+    LevelArgs a{};
+    a.fronts = fronts.as<FrontDev>();
+    a.first = levels[d].off;
+    a.nlevel = levels[d].n;
+    a.subs = subs.as<SubDev>();
+    a.vars = vars.as<int>();
+    a.cmap = cmap.as<int>();
+    a.ents = ents.as<SymEntry>();
+    a.children = children.as<int>();
+    a.keps = keps;
+    a.lcoef = lcoef.as<double2>();
+    a.pact = pact;
+    a.max_m = levels[d].max_m;
+    a.max_pm = levels[d].max_pm;
+    a.max_p = levels[d].max_p;
+    return a;
+  }
+  int64_t device_bytes() const {
+    const DBuf* all[] = {&lcoef, &subs, &fronts, &vars, &cmap, &ents, &children, &cover_x,
+                         &cover_y, &scat, &fac, &lpk, &upk, &piv, &vec, &u};
+    int64_t t = 0;
+    for (const DBuf* d : all) t += (int64_t)d->bytes;
+    return t;
+  }
+};
+
+// Builds the set of problems `plans` (all with the front precision `prec`),
+// problem p at node offset gbase[p] of the global vectors; allocates the
+// factors and the workspaces of one right-hand side.
+void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<long long>& gbase,
+              int prec, hipStream_t st) {
+  mf.prec = prec;
+  mf.nprob = (int)plans.size();
+  // Subdomains of every problem (problem after problem) and their local coefficients.
+  std::vector<double2> lc;
+  std::vector<SubDev> sd;
+  std::vector<ScatDev> sc;
+  std::vector<int4> cvx, cvy;
+  std::vector<int> sub0(mf.nprob);
+  long long uoff = 0;
+  for (int pi = 0; pi < mf.nprob; ++pi) {
+    const Plan& pl = *plans[pi];
+    sub0[pi] = (int)sd.size();
+    ScatDev g{};
+    g.sub0 = (int)sd.size();
+    g.px = pl.prm.px;
+    g.nx = pl.prm.nx;
+    g.ny = pl.prm.ny;
+    g.cx_off = (int)cvx.size();
+    g.cy_off = (int)cvy.size();
+    g.gbase = gbase[pi];
+    sc.push_back(g);
+    cvx.insert(cvx.end(), pl.cover_x.begin(), pl.cover_x.end());
+    cvy.insert(cvy.end(), pl.cover_y.begin(), pl.cover_y.end());
+    mf.max_nx = std::max(mf.max_nx, pl.prm.nx);
+    mf.max_ny = std::max(mf.max_ny, pl.prm.ny);
+    for (const SubDesc& s : pl.subs) {
+      SubDev d{};
+      d.ox0 = s.ox0; d.oy0 = s.oy0; d.nxl = s.nxl; d.nyl = s.nyl;
+      d.ix0 = s.ix0; d.ix1 = s.ix1; d.iy0 = s.iy0; d.iy1 = s.iy1;
+      d.gbase = gbase[pi];
+      d.gnx = pl.prm.nx;
+      d.prob = pi;
+      d.cx_off = (int)lc.size();
+      for (int t = 0; t < s.nxl; ++t) {
+        lc.push_back(make_double2(s.cx.w[t].real(), s.cx.w[t].imag()));
+        lc.push_back(make_double2(s.cx.e[t].real(), s.cx.e[t].imag()));
+      }
+      d.cy_off = (int)lc.size();
+      for (int t = 0; t < s.nyl; ++t) {
+        lc.push_back(make_double2(s.cy.w[t].real(), s.cy.w[t].imag()));
+        lc.push_back(make_double2(s.cy.e[t].real(), s.cy.e[t].imag()));
+      }
+      d.u_off = uoff;
+      uoff += (long long)s.nxl * s.nyl;
+      sd.push_back(d);
+    }
+  }
+  mf.nsub = (int)sd.size();
+  mf.u_elems = uoff;
+  STF_REQUIRE(lc.size() < (1ULL << 31), "problem set too large for int32 coefficient offsets");
+  upload(mf.lcoef, lc, st);
+  upload(mf.subs, sd, st);
+  upload(mf.cover_x, cvx, st);
+  upload(mf.cover_y, cvy, st);
+  upload(mf.scat, sc, st);
+
+  // Concatenated symbolic arrays of the distinct shapes (shared between problems).
+  std::map<const SymShape*, int> shape_id;
+  std::vector<const SymShape*> shapes;
+  for (const Plan* pl : plans)
+    for (const auto& sh : pl->shapes)
+      if (shape_id.emplace(sh.get(), (int)shapes.size()).second) shapes.push_back(sh.get());
+  std::vector<int> vars, cmap, sh_var(shapes.size()), sh_cmap(shapes.size()), sh_ent(shapes.size());
+  std::vector<SymEntry> ents;
+  for (size_t k = 0; k < shapes.size(); ++k) {
+    const SymShape& sh = *shapes[k];
+    sh_var[k] = (int)vars.size();
+    sh_cmap[k] = (int)cmap.size();
+    sh_ent[k] = (int)ents.size();
+    vars.insert(vars.end(), sh.vars.begin(), sh.vars.end());
+    cmap.insert(cmap.end(), sh.cmap.begin(), sh.cmap.end());
+    ents.insert(ents.end(), sh.ents.begin(), sh.ents.end());
+  }
+  STF_REQUIRE(vars.size() < (1ULL << 31) && ents.size() < (1ULL << 31), "symbolic plans too large");
+  upload(mf.vars, vars, st);
+  upload(mf.cmap, cmap, st);
+  upload(mf.ents, ents, st);
+
+  // Front instances of every subdomain of every problem, in level order
+  // (largest first within a level) so that each level is a contiguous range.
+  struct Rec { int prob, sub, idx, depth, m; const SymShape* sh; };
+  std::vector<Rec> recs;
+  std::vector<int> sub_base(mf.nsub);
+  for (int pi = 0; pi < mf.nprob; ++pi) {
+    const Plan& pl = *plans[pi];
+    for (size_t k = 0; k < pl.subs.size(); ++k) {
+      const int gk = sub0[pi] + (int)k;
+      const SymShape* sh = pl.shapes[pl.subs[k].shape].get();
+      sub_base[gk] = (int)recs.size();
+      for (size_t i = 0; i < sh->fronts.size(); ++i)
+        recs.push_back({pi, gk, (int)i, sh->fronts[i].depth, sh->fronts[i].p + sh->fronts[i].q, sh});
+    }
+  }
+  std::vector<int> order(recs.size());
+  std::iota(order.begin(), order.end(), 0);
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    if (recs[x].depth != recs[y].depth) return recs[x].depth < recs[y].depth;
+    return recs[x].m > recs[y].m;
+  });
+  std::vector<int> inst(recs.size());      // record -> instance index
+  for (size_t t = 0; t < order.size(); ++t) inst[order[t]] = (int)t;
+  std::vector<FrontDev> fr(recs.size());
+  std::vector<int> kids;
+  long long fac_off = 0, lpk_off = 0, upk_off = 0;
+  long long vec_off = 0, piv_off = 0;
+  for (size_t t = 0; t < order.size(); ++t) {
+    const Rec& rc = recs[order[t]];
+    const SubDev& s = sd[rc.sub];
+    const SymShape& sh = *rc.sh;
+    const int sid = shape_id[rc.sh];
+    const SymFront& f = sh.fronts[rc.idx];
+    FrontDev& d = fr[t];
+    int m = f.p + f.q;
+    d.fac_off = fac_off;
+    d.lpk_off = lpk_off;
+    d.upk_off = upk_off;
+    d.vec_off = (int)vec_off;
+    d.piv_off = (int)piv_off;
+    d.p = f.p;
+    d.q = f.q;
+    d.sub = rc.sub;
+    d.gx0 = s.ox0 + f.sx0;
+    d.gy0 = s.oy0 + f.sy0;
+    d.sw = f.sw;
+    d.ix0 = s.ix0;
+    d.ix1 = s.ix1;
+    d.iy0 = s.iy0;
+    d.iy1 = s.iy1;
+    d.gbase = s.gbase;
+    d.gnx = s.gnx;
+    d.prob = rc.prob;
+    d.var_off = sh_var[sid] + f.var_off;
+    d.cmap_off = sh_cmap[sid] + f.cmap_off;
+    d.ent_off = sh_ent[sid] + f.ent_off;
+    d.ent_cnt = f.ent_cnt;
+    d.parent = f.parent >= 0 ? inst[sub_base[rc.sub] + f.parent] : -1;
+    STF_REQUIRE(f.nchild <= 2, "internal: more than two children");
+    d.child_off = (int)kids.size();
+    d.nchild = f.nchild;
+    for (int c = 0; c < f.nchild; ++c)
+      kids.push_back(inst[sub_base[rc.sub] + sh.children[f.child_off + c]]);
+    fac_off += (long long)m * m;
+    // Packed sweep operators: the strictly lower trapezoid of the first p
+    // columns (forward) and the upper trapezoid of the first p rows (backward).
+    lpk_off += (long long)f.p * f.q + (long long)f.p * (f.p - 1) / 2;
+    upk_off += (long long)f.p * f.q + (long long)f.p * (f.p + 1) / 2;
+    vec_off += m;
+    piv_off += f.p;
+  }
+  mf.upk_elems = upk_off;
+  mf.lpk_elems = lpk_off;
+  STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
+  // Embedded children vector offsets and maps (all offsets are known now).
+  for (size_t t = 0; t < fr.size(); ++t) {
+    FrontDev& d = fr[t];
+    for (int c = 0; c < 2; ++c) {
+      if (c < d.nchild) {
+        const FrontDev& cf = fr[kids[d.child_off + c]];
+        d.cvec[c] = cf.vec_off + cf.p;
+        d.ccmap[c] = cf.cmap_off;
+        d.cq[c] = cf.q;
+      } else {
+        d.cvec[c] = 0;
+        d.ccmap[c] = 0;
+        d.cq[c] = 0;
+      }
+    }
+  }
+  mf.n_fronts = (int64_t)fr.size();
+  mf.fac_elems = fac_off;
+  mf.vec_elems = vec_off;
+  mf.piv_elems = piv_off;
+  mf.levels.clear();
+  for (size_t t = 0; t < order.size(); ++t) {
+    int dpt = recs[order[t]].depth;
+    if ((int)mf.levels.size() <= dpt) {
+      mf.levels.resize(dpt + 1);
+      mf.levels[dpt].off = (int)t;
+    }
+    Level& L = mf.levels[dpt];
+    L.n += 1;
+    L.max_m = std::max(L.max_m, fr[t].p + fr[t].q);
+    L.max_pm = std::max(L.max_pm, fr[t].p * (fr[t].p + fr[t].q));
+    L.max_p = std::max(L.max_p, fr[t].p);
+  }
+  mf.max_depth = (int)mf.levels.size() - 1;
+  upload(mf.fronts, fr, st);
+  upload(mf.children, kids, st);
+
+  const size_t es = prec == STF_C64 ? sizeof(float2) : sizeof(double2);
+  mf.fac.alloc((size_t)mf.fac_elems * es);
+  mf.upk.alloc((size_t)mf.upk_elems * es);
+  mf.lpk.alloc((size_t)mf.lpk_elems * es);
+  mf.piv.alloc((size_t)mf.piv_elems * sizeof(int));
+  mf.vec.alloc((size_t)mf.vec_elems * es);
+  mf.u.alloc((size_t)mf.u_elems * es);
+  mf.ws_nr = 1;
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
 struct stf_problem_s {
   stf_ctx ctx = nullptr;
   Plan plan;
   stf_params prm{};
   long long N = 0;
-  int nsub = 0;
-  int max_depth = 0;
   bool assembled = false, factored = false;
   int prec = STF_C128;
-  int64_t n_fronts = 0;
-  int64_t fac_elems = 0, lpk_elems = 0, upk_elems = 0, vec_elems = 0, piv_elems = 0, u_elems = 0;
-  std::vector<Level> levels;     // by depth
+  std::unique_ptr<Mf> mf;          // fronts and workspaces (built at the first factorisation)
 
   // Device state.
-  DBuf keps, gcoef, lcoef, subs, fronts, vars, cmap, ents, children;
-  DBuf fac, lpk, upk, piv, vec, u, cover_x, cover_y, flag;
+  DBuf keps, gcoef, flag;
   DBuf partial, npartial, scal;    // reduction scratch, device scalars
   DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
   DBuf hb, hx, cells;              // staging for host inputs
-  int krylov_m = 0, krylov_nr = 0, ws_nr = 1;
+  int krylov_m = 0, krylov_nr = 0;
   // Phase timers: [0, 1] the last factorisation, [2, 3] a solve group, [4 + 2 s, 5 + 2 s]
   // the network's guess of right-hand side s of the group.
   hipEvent_t ev[4 + 2 * MAX_RHS] = {};
@@ -208,33 +449,21 @@ struct stf_problem_s {
   const double2* cyw() const { return gcoef.as<double2>() + 2 * prm.nx; }
   const double2* cye() const { return gcoef.as<double2>() + 2 * prm.nx + prm.ny; }
 
-  LevelArgs level_args(int d) const {
-    LevelArgs a{};
-    a.fronts = fronts.as<FrontDev>();
-    a.first = levels[d].off;
-    a.nlevel = levels[d].n;
-    a.subs = subs.as<SubDev>();
-    a.vars = vars.as<int>();
-    a.cmap = cmap.as<int>();
-    a.ents = ents.as<SymEntry>();
-    a.children = children.as<int>();
-    a.keps = keps.as<double2>();
-    a.lcoef = lcoef.as<double2>();
-    a.nx = prm.nx;
-    a.max_m = levels[d].max_m;
-    a.max_pm = levels[d].max_pm;
-    a.max_p = levels[d].max_p;
-    return a;
+  Mf& ensure_mf() {
+    if (!mf) {
+      std::unique_ptr<Mf> m(new Mf());
+      build_mf(*m, {&plan}, {0LL}, prm.front_prec, ctx->stream);
+      mf = std::move(m);
+    }
+    return *mf;
   }
+  int max_depth() const { return mf ? mf->max_depth : -1; }
   int64_t device_bytes() const {
-    const DBuf* all[] = {&keps, &gcoef, &lcoef, &subs, &fronts, &vars, &cmap, &ents,
-                         &children, &fac, &lpk, &upk, &piv, &vec, &u, &cover_x, &cover_y, &flag, &partial,
-                         &npartial,
-                         &scal, &kV, &kZ, &kw, &kr, &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &hb,
-                         &hx, &cells};
-    int64_t s = 0;
-    for (const DBuf* b : all) s += (int64_t)b->bytes;
-    return s;
+    const DBuf* all[] = {&keps, &gcoef, &flag, &partial, &npartial, &scal, &kV, &kZ, &kw, &kr,
+                         &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &hb, &hx, &cells};
+    int64_t t = 0;
+    for (const DBuf* d : all) t += (int64_t)d->bytes;
+    return t + (mf ? mf->device_bytes() : 0);
   }
 };
 
@@ -308,7 +537,6 @@ void build_device_state(stf_problem pb) {
   const stf_params& p = pb->prm;
   hipStream_t st = pb->ctx->stream;
   pb->N = (long long)p.nx * p.ny;
-  pb->nsub = (int)pl.subs.size();
   pb->prec = p.front_prec;
 
   // Global coupling arrays: cxw | cxe | cyw | cye.
@@ -318,162 +546,6 @@ void build_device_state(stf_problem pb) {
   for (auto& v : pl.g.cy.w) gc.push_back(make_double2(v.real(), v.imag()));
   for (auto& v : pl.g.cy.e) gc.push_back(make_double2(v.real(), v.imag()));
   upload(pb->gcoef, gc, st);
-
-  // Subdomains and local coefficient pairs.
-  std::vector<double2> lc;
-  std::vector<SubDev> sd;
-  long long uoff = 0;
-  for (const SubDesc& s : pl.subs) {
-    SubDev d{};
-    d.ox0 = s.ox0; d.oy0 = s.oy0; d.nxl = s.nxl; d.nyl = s.nyl;
-    d.ix0 = s.ix0; d.ix1 = s.ix1; d.iy0 = s.iy0; d.iy1 = s.iy1;
-    d.cx_off = (int)lc.size();
-    for (int t = 0; t < s.nxl; ++t) {
-      lc.push_back(make_double2(s.cx.w[t].real(), s.cx.w[t].imag()));
-      lc.push_back(make_double2(s.cx.e[t].real(), s.cx.e[t].imag()));
-    }
-    d.cy_off = (int)lc.size();
-    for (int t = 0; t < s.nyl; ++t) {
-      lc.push_back(make_double2(s.cy.w[t].real(), s.cy.w[t].imag()));
-      lc.push_back(make_double2(s.cy.e[t].real(), s.cy.e[t].imag()));
-    }
-    d.u_off = uoff;
-    uoff += (long long)s.nxl * s.nyl;
-    sd.push_back(d);
-  }
-  pb->u_elems = uoff;
-  upload(pb->lcoef, lc, st);
-  upload(pb->subs, sd, st);
-
-  // Concatenated symbolic arrays of the distinct shapes.
-  std::vector<int> vars, cmap, sh_var(pl.shapes.size()), sh_cmap(pl.shapes.size()),
-      sh_ent(pl.shapes.size());
-  std::vector<SymEntry> ents;
-  for (size_t k = 0; k < pl.shapes.size(); ++k) {
-    const SymShape& sh = *pl.shapes[k];
-    sh_var[k] = (int)vars.size();
-    sh_cmap[k] = (int)cmap.size();
-    sh_ent[k] = (int)ents.size();
-    vars.insert(vars.end(), sh.vars.begin(), sh.vars.end());
-    cmap.insert(cmap.end(), sh.cmap.begin(), sh.cmap.end());
-    ents.insert(ents.end(), sh.ents.begin(), sh.ents.end());
-  }
-  upload(pb->vars, vars, st);
-  upload(pb->cmap, cmap, st);
-  upload(pb->ents, ents, st);
-
-  // Front instances of every subdomain, in level order (largest first within
-  // a level) so that each level is a contiguous range.
-  struct Rec { int sub, idx, depth, m; };
-  std::vector<Rec> recs;
-  std::vector<int> sub_base(pb->nsub);
-  for (int k = 0; k < pb->nsub; ++k) {
-    const SymShape& sh = *pl.shapes[pl.subs[k].shape];
-    sub_base[k] = (int)recs.size();
-    for (size_t i = 0; i < sh.fronts.size(); ++i)
-      recs.push_back({k, (int)i, sh.fronts[i].depth, sh.fronts[i].p + sh.fronts[i].q});
-  }
-  std::vector<int> order(recs.size());
-  std::iota(order.begin(), order.end(), 0);
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
-    if (recs[x].depth != recs[y].depth) return recs[x].depth < recs[y].depth;
-    return recs[x].m > recs[y].m;
-  });
-  std::vector<int> inst(recs.size());      // record -> instance index
-  for (size_t t = 0; t < order.size(); ++t) inst[order[t]] = (int)t;
-  std::vector<FrontDev> fr(recs.size());
-  std::vector<int> kids;
-  long long fac_off = 0, lpk_off = 0, upk_off = 0;
-  long long vec_off = 0, piv_off = 0;
-  for (size_t t = 0; t < order.size(); ++t) {
-    const Rec& rc = recs[order[t]];
-    const SubDesc& s = pl.subs[rc.sub];
-    const SymShape& sh = *pl.shapes[s.shape];
-    const SymFront& f = sh.fronts[rc.idx];
-    FrontDev& d = fr[t];
-    int m = f.p + f.q;
-    d.fac_off = fac_off;
-    d.lpk_off = lpk_off;
-    d.upk_off = upk_off;
-    d.vec_off = (int)vec_off;
-    d.piv_off = (int)piv_off;
-    d.p = f.p;
-    d.q = f.q;
-    d.sub = rc.sub;
-    d.gx0 = s.ox0 + f.sx0;
-    d.gy0 = s.oy0 + f.sy0;
-    d.sw = f.sw;
-    d.ix0 = s.ix0;
-    d.ix1 = s.ix1;
-    d.iy0 = s.iy0;
-    d.iy1 = s.iy1;
-    d.var_off = sh_var[s.shape] + f.var_off;
-    d.cmap_off = sh_cmap[s.shape] + f.cmap_off;
-    d.ent_off = sh_ent[s.shape] + f.ent_off;
-    d.ent_cnt = f.ent_cnt;
-    d.parent = f.parent >= 0 ? inst[sub_base[rc.sub] + f.parent] : -1;
-    STF_REQUIRE(f.nchild <= 2, "internal: more than two children");
-    d.child_off = (int)kids.size();
-    d.nchild = f.nchild;
-    for (int c = 0; c < f.nchild; ++c)
-      kids.push_back(inst[sub_base[rc.sub] + sh.children[f.child_off + c]]);
-    fac_off += (long long)m * m;
-    // Packed sweep operators: the strictly lower trapezoid of the first p
-    // columns (forward) and the upper trapezoid of the first p rows (backward).
-    lpk_off += (long long)f.p * f.q + (long long)f.p * (f.p - 1) / 2;
-    upk_off += (long long)f.p * f.q + (long long)f.p * (f.p + 1) / 2;
-    vec_off += m;
-    piv_off += f.p;
-  }
-  pb->upk_elems = upk_off;
-  pb->lpk_elems = lpk_off;
-  STF_REQUIRE(vec_off < (1LL << 31) && piv_off < (1LL << 31), "problem too large for int32 offsets");
-  // Embedded children vector offsets and maps (all offsets are known now).
-  for (size_t t = 0; t < fr.size(); ++t) {
-    FrontDev& d = fr[t];
-    for (int c = 0; c < 2; ++c) {
-      if (c < d.nchild) {
-        const FrontDev& cf = fr[kids[d.child_off + c]];
-        d.cvec[c] = cf.vec_off + cf.p;
-        d.ccmap[c] = cf.cmap_off;
-        d.cq[c] = cf.q;
-      } else {
-        d.cvec[c] = 0;
-        d.ccmap[c] = 0;
-        d.cq[c] = 0;
-      }
-    }
-  }
-  pb->n_fronts = (int64_t)fr.size();
-  pb->fac_elems = fac_off;
-  pb->vec_elems = vec_off;
-  pb->piv_elems = piv_off;
-  pb->levels.clear();
-  for (size_t t = 0; t < order.size(); ++t) {
-    int dpt = recs[order[t]].depth;
-    if ((int)pb->levels.size() <= dpt) {
-      pb->levels.resize(dpt + 1);
-      pb->levels[dpt].off = (int)t;
-    }
-    Level& L = pb->levels[dpt];
-    L.n += 1;
-    L.max_m = std::max(L.max_m, fr[t].p + fr[t].q);
-    L.max_pm = std::max(L.max_pm, fr[t].p * (fr[t].p + fr[t].q));
-    L.max_p = std::max(L.max_p, fr[t].p);
-  }
-  pb->max_depth = (int)pb->levels.size() - 1;
-  upload(pb->fronts, fr, st);
-  upload(pb->children, kids, st);
-  upload(pb->cover_x, pl.cover_x, st);
-  upload(pb->cover_y, pl.cover_y, st);
-
-  size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
-  pb->fac.alloc((size_t)pb->fac_elems * es);
-  pb->upk.alloc((size_t)pb->upk_elems * es);
-  pb->lpk.alloc((size_t)pb->lpk_elems * es);
-  pb->piv.alloc((size_t)pb->piv_elems * sizeof(int));
-  pb->vec.alloc((size_t)pb->vec_elems * es);
-  pb->u.alloc((size_t)pb->u_elems * es);
   pb->keps.alloc((size_t)pb->N * sizeof(double2));
   pb->flag.alloc(sizeof(int) * 4);
   pb->scal.alloc(sizeof(double) * 64);
@@ -503,82 +575,108 @@ void assemble_eps(stf_problem pb, const double* eps, int on_device) {
   pb->factored = false;
 }
 
-// Numeric factorisation of every level; with `fault`, the first front of
-// tree level 1 gets the planted zero pivot column (test hook): its first column
-// carries fill in the update rows after assembly, so the perturbation has a
-// nonzero column maximum to scale.
+// Numeric factorisation of every level of a set; with `fault`, the first front
+// of tree level 1 gets the planted zero pivot column (test hook): its first
+// column carries fill in the update rows after assembly, so the perturbation
+// has a nonzero column maximum to scale.  e0 / e1 (may be null) bracket the
+// launches.  Returns the perturbation flag (synchronises the stream).
 template <typename T>
-int factor_t(stf_problem pb, bool fault = false) {
-  STF_REQUIRE(!fault || pb->max_depth >= 1, "the planted fault needs a tree of two levels or more");
-  hipStream_t st = pb->ctx->stream;
-  T* fac = pb->fac.as<T>();
-  HIP_CHECK(hipMemsetAsync(pb->flag.p, 0, sizeof(int), st));
+int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hipEvent_t e0,
+              hipEvent_t e1) {
+  STF_REQUIRE(!fault || mf.max_depth >= 1, "the planted fault needs a tree of two levels or more");
+  hipStream_t st = c->stream;
+  T* fac = mf.fac.as<T>();
+  HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
-  HIP_CHECK(hipEventRecord(pb->ev[0], st));
-  for (int d = pb->max_depth; d >= 0; --d) {
-    Timed t(pb->ctx, K_FRONT_LU);
-    LevelArgs la = pb->level_args(d);
+  if (e0) HIP_CHECK(hipEventRecord(e0, st));
+  for (int d = mf.max_depth; d >= 0; --d) {
+    Timed t(c, K_FRONT_LU);
+    LevelArgs la = mf.level_args(d, keps);
     if (fault && d == 1) la.fault = la.first;
-    launch_front_factor<T>(st, la, fac, pb->lpk.as<T>(), pb->upk.as<T>(), pb->piv.as<int>(),
-                           pb->flag.as<int>(), tau);
+    launch_front_factor<T>(st, la, fac, mf.lpk.as<T>(), mf.upk.as<T>(), mf.piv.as<int>(), flag, tau);
   }
-  HIP_CHECK(hipEventRecord(pb->ev[1], st));
-  pb->fac_timed = true;
+  if (e1) HIP_CHECK(hipEventRecord(e1, st));
   HIP_CHECK(hipGetLastError());
   int h = 0;
-  HIP_CHECK(hipMemcpyAsync(&h, pb->flag.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIP_CHECK(hipStreamSynchronize(st));
   return h;
 }
 
-// z_s = sum_k P_k A_k^{-1} R_k^I v_s  (one source-transfer round) for the
-// right-hand sides of r, swept together.
-// The launches of one round with explicit workspaces: front vectors `vec` and
-// local fields `u` (vec_elems and u_elems entries per right-hand side).  With
-// timed = false no event is recorded (the allocation-free entry point).
+int factor_problem(stf_problem pb, bool fault = false) {
+  Mf& mf = pb->ensure_mf();
+  const double2* keps = pb->keps.as<double2>();
+  int* flag = pb->flag.as<int>();
+  const int h = mf.prec == STF_C64
+                    ? factor_mf<float2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1])
+                    : factor_mf<double2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1]);
+  pb->fac_timed = true;
+  return h;
+}
+
+// z_s = sum_k P_k A_k^{-1} R_k^I v_s (one source-transfer round) for the
+// right-hand sides of r, swept together, over every problem of the set (those
+// with pact[p] == 0 skipped when pact is given).  Explicit workspaces: front
+// vectors `vec` and local fields `u` (vec_elems and u_elems entries per
+// right-hand side).  With timed = false no event is recorded (the
+// allocation-free entry point).
 template <typename T>
-void precond_launch(stf_problem pb, RhsSet r, T* vec, T* u, bool timed) {
-  hipStream_t st = pb->ctx->stream;
-  stf_ctx tc = timed ? pb->ctx : nullptr;
-  r.vec_stride = pb->vec_elems;
-  r.u_stride = pb->u_elems;
-  const T* lpk = pb->lpk.as<T>();
-  for (int d = pb->max_depth; d >= 0; --d) {
+void precond_launch(stf_ctx c, const Mf& mf, RhsSet r, T* vec, T* u, bool timed,
+                    const int* pact = nullptr) {
+  hipStream_t st = c->stream;
+  stf_ctx tc = timed ? c : nullptr;
+  r.vec_stride = mf.vec_elems;
+  r.u_stride = mf.u_elems;
+  const T* lpk = mf.lpk.as<T>();
+  for (int d = mf.max_depth; d >= 0; --d) {
     Timed t(tc, K_SWEEP_FWD);
-    launch_sweep_fwd<T>(st, pb->level_args(d), lpk, pb->piv.as<int>(), vec, r);
+    launch_sweep_fwd<T>(st, mf.level_args(d, nullptr, pact), lpk, mf.piv.as<int>(), vec, r);
   }
-  for (int d = 0; d <= pb->max_depth; ++d) {
+  for (int d = 0; d <= mf.max_depth; ++d) {
     Timed t(tc, K_SWEEP_BWD);
-    launch_sweep_bwd<T>(st, pb->level_args(d), pb->upk.as<T>(), vec, u, r);
+    launch_sweep_bwd<T>(st, mf.level_args(d, nullptr, pact), mf.upk.as<T>(), vec, u, r);
   }
   Timed t(tc, K_SCATTER);
-  launch_scatter<T>(st, u, pb->subs.as<SubDev>(), pb->cover_x.as<int4>(), pb->cover_y.as<int4>(),
-                    pb->prm.px, pb->prm.nx, pb->prm.ny, r);
+  launch_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.cover_x.as<int4>(), mf.cover_y.as<int4>(),
+                    mf.scat.as<ScatDev>(), mf.nprob, mf.max_nx, mf.max_ny, pact, r);
 }
 
+// The same with the set's own workspaces, grown to r.nr right-hand sides.
 template <typename T>
-void precond_t(stf_problem pb, RhsSet r) {
-  if (pb->ws_nr < r.nr) {
+void precond_mf(stf_ctx c, Mf& mf, const RhsSet& r, const int* pact = nullptr) {
+  if (mf.ws_nr < r.nr) {
     const size_t es = sizeof(T);
-    pb->vec.alloc((size_t)pb->vec_elems * es * r.nr);
-    pb->u.alloc((size_t)pb->u_elems * es * r.nr);
-    pb->ws_nr = r.nr;
+    mf.vec.alloc((size_t)mf.vec_elems * es * r.nr);
+    mf.u.alloc((size_t)mf.u_elems * es * r.nr);
+    mf.ws_nr = r.nr;
   }
-  precond_launch<T>(pb, r, pb->vec.as<T>(), pb->u.as<T>(), true);
+  precond_launch<T>(c, mf, r, mf.vec.as<T>(), mf.u.as<T>(), true, pact);
 }
 
-// Bytes of the workspace of one right-hand side's round.
-size_t round_workspace_bytes(stf_problem pb) {
-  const size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
-  const size_t a = (size_t)pb->vec_elems * es;
-  return ((a + 255) & ~size_t(255)) + (size_t)pb->u_elems * es;
+// Entries of the front vectors and of the local fields of one right-hand side
+// (from the host plan: a set's vec_elems and u_elems), and the bytes of that
+// workspace with the local fields at a 256-byte boundary.
+void round_workspace_elems(const Plan& pl, int64_t& vec, int64_t& u) {
+  vec = 0;
+  u = 0;
+  for (const SubDesc& s : pl.subs) {
+    vec += pl.shapes[s.shape]->vec_entries;
+    u += (int64_t)s.nxl * s.nyl;
+  }
+}
+size_t round_workspace_bytes(const Plan& pl, int prec) {
+  int64_t vec = 0, u = 0;
+  round_workspace_elems(pl, vec, u);
+  const size_t es = prec == STF_C64 ? sizeof(float2) : sizeof(double2);
+  const size_t a = (size_t)vec * es;
+  return ((a + 255) & ~size_t(255)) + (size_t)u * es;
 }
 
 void precond_set(stf_problem pb, const RhsSet& r) {
   if (pb->prec == STF_C64)
-    precond_t<float2>(pb, r);
+    precond_mf<float2>(pb->ctx, *pb->mf, r);
   else
-    precond_t<double2>(pb, r);
+    precond_mf<double2>(pb->ctx, *pb->mf, r);
 }
 
 void precond(stf_problem pb, const double2* v, double2* z) {
@@ -1397,7 +1495,7 @@ stf_status stf_factor(stf_problem pb) {
   int flagged = 0;
   stf_status s = guard(pb->ctx, [&] {
     if (!pb->assembled) throw Error(STF_ESTATE, "factor before assemble");
-    flagged = pb->prec == STF_C64 ? factor_t<float2>(pb) : factor_t<double2>(pb);
+    flagged = factor_problem(pb);
     pb->factored = true;
   });
   if (s == STF_OK && flagged) {
@@ -1452,24 +1550,28 @@ stf_status stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z)
   if (!pb) return STF_EINVAL;
   return guard(pb->ctx, [&] {
     STF_REQUIRE(v && z, "null argument");
-    const size_t need = round_workspace_bytes(pb);
+    const size_t need = round_workspace_bytes(pb->plan, pb->prec);
     if (need > SCRATCH_BYTES)
       throw Error(STF_EINVAL, "problem needs " + std::to_string(need) +
                                   " bytes of round workspace; the allocation-free round holds at most " +
                                   std::to_string(SCRATCH_BYTES));
-    if (!pb->factored) throw Error(STF_ESTATE, "precond before factor");
+    if (!pb->factored || !pb->mf) throw Error(STF_ESTATE, "precond before factor");
+    const Mf& mf = *pb->mf;
+    int64_t ve = 0, ue = 0;
+    round_workspace_elems(pb->plan, ve, ue);
+    STF_REQUIRE(ve == mf.vec_elems && ue == mf.u_elems, "internal: workspace size mismatch");
     unsigned char* base = static_cast<unsigned char*>(pb->ctx->scratch);
     const size_t es = pb->prec == STF_C64 ? sizeof(float2) : sizeof(double2);
-    const size_t voff = ((size_t)pb->vec_elems * es + 255) & ~size_t(255);
+    const size_t voff = ((size_t)mf.vec_elems * es + 255) & ~size_t(255);
     RhsSet r;
     r.nr = 1;
     r.v[0] = reinterpret_cast<const double2*>(v);
     r.z[0] = reinterpret_cast<double2*>(z);
     if (pb->prec == STF_C64)
-      precond_launch<float2>(pb, r, reinterpret_cast<float2*>(base),
+      precond_launch<float2>(pb->ctx, mf, r, reinterpret_cast<float2*>(base),
                              reinterpret_cast<float2*>(base + voff), false);
     else
-      precond_launch<double2>(pb, r, reinterpret_cast<double2*>(base),
+      precond_launch<double2>(pb->ctx, mf, r, reinterpret_cast<double2*>(base),
                               reinterpret_cast<double2*>(base + voff), false);
     HIP_CHECK(hipGetLastError());
   });
@@ -1618,7 +1720,7 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
     STF_REQUIRE(opts->debug_fault == 0 || opts->debug_fault == 1, "debug_fault must be 0 or 1");
     if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
     if (opts->debug_fault == 1) {
-      perturbed = (pb->prec == STF_C64 ? factor_t<float2>(pb, true) : factor_t<double2>(pb, true)) != 0;
+      perturbed = factor_problem(pb, true) != 0;
       STF_REQUIRE(perturbed, "internal: the planted fault did not reach the pivot perturbation");
     }
     const size_t per = (size_t)pb->N * 2;

@@ -78,7 +78,7 @@ __device__ inline double2 local_coef(const LevelArgs& a, const SubDev& s, int no
     case 3: return yw;
     case 4: return ye;
     default: {
-      double2 ke = a.keps[(long long)(s.oy0 + ty) * a.nx + (s.ox0 + tx)];
+      double2 ke = a.keps[s.gbase + (long long)(s.oy0 + ty) * s.gnx + (s.ox0 + tx)];
       return make_double2(ke.x - ((xw.x + xe.x) + (yw.x + ye.x)),
                           ke.y - ((xw.y + xe.y) + (yw.y + ye.y)));
     }
@@ -955,6 +955,7 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;                          // whole wavefront
   const FrontDev f = a.fronts[a.first + fi];
+  if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
   const int m = f.p + f.q, p = f.p;
   const T* L = lpk + f.lpk_off;
   const int W = RPL > 1 ? 64 : (m <= 16 ? 16 : (m <= 32 ? 32 : 64));
@@ -971,7 +972,8 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   long long gidx = -1;
   if (lane < p) {
     const int gx = f.gx0 + lane % f.sw, gy = f.gy0 + lane / f.sw;
-    if (gx >= f.ix0 && gx < f.ix1 && gy >= f.iy0 && gy < f.iy1) gidx = (long long)gy * a.nx + gx;
+    if (gx >= f.ix0 && gx < f.ix1 && gy >= f.iy0 && gy < f.iy1)
+      gidx = f.gbase + (long long)gy * f.gnx + gx;
   }
   int d0[RPL], d1[RPL];
 #pragma unroll
@@ -1049,6 +1051,7 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;
   const FrontDev f = a.fronts[a.first + fi];
+  if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
   const int m = f.p + f.q, p = f.p, q = f.q;
   const T* U = upk + f.upk_off;
   const int W = p <= 4 ? 4 : (p <= 8 ? 8 : (p <= 16 ? 16 : (p <= 32 ? 32 : 64)));
@@ -1127,6 +1130,7 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   T* tmp = vl + NR * a.max_m;                              // NR x max_m
   const int mm = a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
+  if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole workgroup)
   const int m = f.p + f.q, p = f.p;
   const T* L = lpk + f.lpk_off;
   const int tid = threadIdx.x;
@@ -1147,8 +1151,9 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   const int* perm = piv + f.piv_off;
   auto global_row = [&](int i) -> long long {
     const int gx = f.gx0 + i % f.sw, gy = f.gy0 + i / f.sw;
-    return (gx >= f.ix0 && gx < f.ix1 && gy >= f.iy0 && gy < f.iy1) ? (long long)gy * a.nx + gx
-                                                                     : -1;
+    return (gx >= f.ix0 && gx < f.ix1 && gy >= f.iy0 && gy < f.iy1)
+               ? f.gbase + (long long)gy * f.gnx + gx
+               : -1;
   };
   if (m <= 2 * NTL) {
     // Every global load of the right-hand side first (two rows per thread),
@@ -1272,6 +1277,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   T* vl = scr + NR * NTL;                                  // NR x max_m
   const int mm = a.max_m;
   const FrontDev f = a.fronts[a.first + blockIdx.x];
+  if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole workgroup)
   const int m = f.p + f.q, p = f.p;
   const T* U = upk + f.upk_off;                            // packed [U11^{-1} V']
   const int tid = threadIdx.x;
@@ -1375,12 +1381,17 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_scatter(const T* __restrict__ u, const SubDev* __restrict__ subs,
                                                  const int4* __restrict__ cover_x,
-                                                 const int4* __restrict__ cover_y, int px, int nx,
-                                                 int ny, RhsSet rs) {
+                                                 const int4* __restrict__ cover_y,
+                                                 const ScatDev* __restrict__ probs,
+                                                 const int* __restrict__ pact, RhsSet rs) {
+  const ScatDev P = probs[blockIdx.z];
+  if (pact && pact[blockIdx.z] == 0) return;
+  const int nx = P.nx, ny = P.ny, px = P.px;
   int i = blockIdx.x * 64 + threadIdx.x;
   int j = blockIdx.y * 4 + threadIdx.y;
   if (i >= nx || j >= ny) return;
-  int4 cx = cover_x[i], cy = cover_y[j];
+  subs += P.sub0;
+  int4 cx = cover_x[P.cx_off + i], cy = cover_y[P.cy_off + j];
   double2 acc[NR];
 #pragma unroll
   for (int s = 0; s < NR; ++s) acc[s] = make_double2(0.0, 0.0);
@@ -1403,7 +1414,7 @@ __global__ __launch_bounds__(256) void k_scatter(const T* __restrict__ u, const 
     }
   }
 #pragma unroll
-  for (int r = 0; r < NR; ++r) rs.z[r][(long long)j * nx + i] = acc[r];
+  for (int r = 0; r < NR; ++r) rs.z[r][P.gbase + (long long)j * nx + i] = acc[r];
 }
 
 int g_max_lds = 0;
@@ -1665,11 +1676,12 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, 
 
 template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
-                    const int4* cover_y, int px, int nx, int ny, const RhsSet& r) {
+                    const int4* cover_y, const ScatDev* probs, int nprob, int max_nx, int max_ny,
+                    const int* pact, const RhsSet& r) {
   check_rhs(r);
-  dim3 blk(64, 4), grd((nx + 63) / 64, (ny + 3) / 4);
+  dim3 blk(64, 4), grd((max_nx + 63) / 64, (max_ny + 3) / 4, nprob);
 #define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_scatter<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, px, nx, ny, r)
+  hipLaunchKernelGGL((k_scatter<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, probs, pact, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
@@ -1681,7 +1693,8 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
   template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*,            \
                                     const RhsSet&);                                             \
   template void launch_scatter<T>(hipStream_t, const T*, const SubDev*, const int4*,            \
-                                  const int4*, int, int, int, const RhsSet&);
+                                  const int4*, const ScatDev*, int, int, int, const int*,       \
+                                  const RhsSet&);
 STF_INST(double2)
 STF_INST(float2)
 

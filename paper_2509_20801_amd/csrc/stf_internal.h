@@ -117,11 +117,17 @@ stf_plan_info plan_info(const Plan& pl);
 // Device layouts (shared by host launch code and kernels)
 // ---------------------------------------------------------------------------
 
+// Several problems can share one set of device arrays (a batch): problem p's
+// nodes are then the segment [gbase, gbase + nx*ny) of concatenated global
+// vectors, so every node array is indexed gbase + y*gnx + x.
 struct SubDev {
   int ox0, oy0, nxl, nyl;
   int ix0, ix1, iy0, iy1;
   int cx_off, cy_off;       // offsets of (w, e) pairs in the local coefficient arrays
   long long u_off;          // offset of the local field (nxl*nyl elements)
+  long long gbase;          // first node of the subdomain's problem in global vectors
+  int gnx;                  // that problem's nx
+  int prob;                 // that problem's index in the set
 };
 
 // Front instances are stored in tree-level order (deepest level last within
@@ -149,6 +155,16 @@ struct FrontDev {
   // without a load of its local index.
   int gx0, gy0, sw;
   int ix0, ix1, iy0, iy1;
+  long long gbase;          // the problem's first node in global vectors
+  int gnx;                  // the problem's nx
+  int prob;                 // the problem's index in the set
+};
+
+// Per problem of a set, for the sum of local fields into global vectors.
+struct ScatDev {
+  int sub0, px, nx, ny;     // first subdomain, subdomain columns, grid
+  int cx_off, cy_off;       // offsets into the concatenated cover tables
+  long long gbase;          // first node in global vectors
 };
 
 // Right-hand sides swept together (1..MAX_RHS): each has its own global input
@@ -204,9 +220,10 @@ struct LevelArgs {
   const int* cmap;
   const SymEntry* ents;
   const int* children;
-  const double2* keps;          // global k0^2 eps_bar
+  const double2* keps;          // global k0^2 eps_bar (concatenated over the set's problems)
   const double2* lcoef;         // local coupling coefficients
-  int nx;                       // global nx
+  const int* pact;              // sweeps: per problem, nonzero while one of its right-hand
+                                // sides is active (null = all); fronts of others are skipped
   int max_m;                    // largest front in the level
   int max_pm;                   // largest p*m in the level
   int max_p;                    // largest p in the level
@@ -225,9 +242,12 @@ void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const in
 template <typename T>
 void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
                       const RhsSet& r);
+// z = sum_k P_k u_k for every problem of a set (ScatDev table of nprob entries,
+// grid sized by the largest nx, ny), skipping problems with pact[p] == 0.
 template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
-                    const int4* cover_y, int px, int nx, int ny, const RhsSet& r);
+                    const int4* cover_y, const ScatDev* probs, int nprob, int max_nx, int max_ny,
+                    const int* pact, const RhsSet& r);
 
 // Krylov (kernels_krylov.hip).  Vectors of n complex doubles; V holds nv vectors
 // with leading dimension ld (elements).
