@@ -243,6 +243,29 @@ stf_status  stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* 
  * calls whose work overlaps on one device (several streams or host threads)
  * race.  STF_ESTATE before stf_factor.  No event timing is recorded. */
 stf_status  stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z);
+/* Batched solve (Algorithm 1's parallel loop over subdomains, extended over
+ * problems): factor the nprob problems together, one launch per elimination-tree
+ * level over the fronts of all of them (Eq. (22)), then solve all their right-hand
+ * sides by FGMRES in lockstep, every kernel launch covering every (problem,
+ * right-hand side) system, one source-transfer round per preconditioner
+ * application (Eqs. (14)-(21)); each system keeps its own Krylov basis and stops
+ * on its own FP64 true residual (convergence is tracked on the device, the host
+ * looks once per FGMRES cycle, and a cycle is replayed as one HIP graph).
+ * probs: nprob distinct assembled problems of this context with the same
+ * front_prec; nrhs[p] >= 1; b[p], x[p]: nrhs[p]*ny_p*nx_p complex each, all host
+ * or all device (on_device); x[p] holds the guesses for STF_X0_USER.
+ * opts: as stf_solve with restart <= 32, rounds <= 1, debug_fault = 0.
+ * info: NULL, or nprob pointers (each NULL or an array of nrhs[p] infos).
+ * The factors live in a state cached on the context and reused while the same
+ * problems (and assemblies) are passed; every call factors again (a problem's
+ * own stf_factor state is neither needed nor touched).  Each system's result
+ * satisfies its tolerance like a solo solve; kernel variants are chosen per
+ * batched level, so results agree with solo solves to the tolerance, not bit
+ * for bit.  Returns the worst per-system status, or STF_EPIVOT when all
+ * converged after a perturbed pivot. */
+stf_status  stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,
+                            const int32_t* nrhs, const double* const* b, double* const* x,
+                            int on_device, const stf_solve_opts* opts, stf_solve_info* const* info);
 stf_status  stf_problem_info(stf_problem pb, stf_plan_info* out);
 void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
 

@@ -21,7 +21,7 @@ from . import _abi
 from ._abi import (STF_C128, STF_C64, STF_X0_USER, STF_X0_ZERO, STF_X0_LEARNED,  # noqa: F401
                    KERNEL_CLASSES, STATUS_NAMES)
 
-__all__ = ["Context", "Problem", "Network", "StfError", "plan_query", "debug_local_axes",
+__all__ = ["Context", "Problem", "Network", "StfError", "plan_query", "debug_local_axes", "batch_solve",
            "make_params", "nn_param_count", "STF_C128", "STF_C64", "STF_X0_ZERO", "STF_X0_USER",
            "STF_X0_LEARNED", "KERNEL_CLASSES"]
 
@@ -381,6 +381,68 @@ class Problem:
         px, dev2, kx = _ptr(x, n, "x0")
         _check(self.ctx.handle, self._lib.stf_nn_initial_guess(self.handle, net.handle, pb_, px, dev))
         return x if dev else kx.reshape(self.ny, self.nx)
+
+
+def batch_solve(ctx, problems, bs, xs=None, tol=1e-10, restart=10, max_iter=500, x0=None,
+                history_cap=1024, raise_on_noconv=False):
+    """Factor the problems together and solve all their right-hand sides in one
+    lockstep batched FGMRES (stf_batch_solve).  bs[p]: (nrhs_p, ny, nx) or (ny, nx),
+    all NumPy (host) or all complex128 CUDA tensors (device).  x0: None (zero),
+    "learned", or a list of guesses shaped like bs.  Returns (xs, infos) with
+    infos[p] a list of per-right-hand-side dicts as Problem.solve returns."""
+    lib = ctx._lib
+    n = len(problems)
+    if n == 0 or len(bs) != n:
+        raise ValueError("one right-hand side array per problem")
+    shapes = [tuple(b.shape) for b in bs]
+    nr = [1 if len(sh) == 2 else int(sh[0]) for sh in shapes]
+    mode = _abi.STF_X0_ZERO
+    if isinstance(x0, str):
+        if x0 != "learned":
+            raise ValueError("x0 must be None, a list of arrays or 'learned'")
+        mode = _abi.STF_X0_LEARNED
+    elif x0 is not None:
+        mode = _abi.STF_X0_USER
+        xs = [x.clone() if _is_torch(x) else np.array(x, dtype=np.complex128, copy=True) for x in x0]
+    if xs is None:
+        xs = [problems[p]._out_like(bs[p], shapes[p]) for p in range(n)]
+    keep, bptr, xptr, dev = [], (C.c_void_p * n)(), (C.c_void_p * n)(), None
+    for p in range(n):
+        cnt = nr[p] * problems[p].ndof
+        pb_, d1, kb = _ptr(bs[p], cnt, "b[%d]" % p)
+        px_, d2, kx = _ptr(xs[p], cnt, "x[%d]" % p)
+        if dev is None:
+            dev = d1
+        if d1 != dev or d2 != dev:
+            raise TypeError("all right-hand sides and solutions must be host, or all device, arrays")
+        keep += [kb, kx]
+        bptr[p], xptr[p] = pb_.value, px_.value
+    probs = (C.c_void_p * n)(*[pb.handle.value for pb in problems])
+    nrhs = (C.c_int32 * n)(*nr)
+    opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, 1, 0)
+    infos = [(_abi.SolveInfo * nr[p])() for p in range(n)]
+    hist = [[np.zeros(history_cap, dtype=np.float64) for _ in range(nr[p])] for p in range(n)]
+    for p in range(n):
+        for r in range(nr[p]):
+            infos[p][r].history = hist[p][r].ctypes.data_as(C.POINTER(C.c_double))
+            infos[p][r].history_cap = history_cap
+    iptr = (C.c_void_p * n)(*[C.cast(infos[p], C.c_void_p).value for p in range(n)])
+    allow = (_abi.STF_EPIVOT,) if raise_on_noconv else (_abi.STF_ENOCONV, _abi.STF_EPIVOT)
+    st = _check(ctx.handle, lib.stf_batch_solve(ctx.handle, n, probs, nrhs, bptr, xptr, dev,
+                                                C.byref(opts), iptr), allow=allow)
+    out = []
+    for p in range(n):
+        lst = []
+        for r in range(nr[p]):
+            inf = infos[p][r]
+            lst.append(dict(iters=inf.iters, restarts=inf.restarts, status=inf.status,
+                            relres_true=inf.relres_true, relres_x0=inf.relres_x0,
+                            used_learned=inf.used_learned, epivot=st == _abi.STF_EPIVOT,
+                            t_factor_ms=inf.t_factor_ms, t_solve_ms=inf.t_solve_ms,
+                            t_nn_ms=inf.t_nn_ms, history=hist[p][r][:inf.history_len].copy()))
+        out.append(lst)
+    res = [xs[p] if dev else keep[2 * p + 1].reshape(shapes[p]) for p in range(n)]
+    return res, out
 
 
 def _cptr(a, count, name):

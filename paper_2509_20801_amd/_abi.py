@@ -76,6 +76,8 @@ EXPORTS = {
                                        C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "stf_line_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_int32, C.POINTER(C.c_double)]),
+    "stf_batch_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                  C.c_void_p, C.c_int, C.POINTER(SolveOpts), C.c_void_p]),
     "stf_problem_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
     "stf_problem_destroy": (None, [C.c_void_p]),
     "stf_nn_param_count": (C.c_int64, [C.POINTER(NNConfig)]),

@@ -20,7 +20,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libstfdfd.so")
 
 SOURCES = ["host_plan.cpp", "kernels_stencil.hip", "kernels_front.hip", "kernels_krylov.hip",
-           "kernels_nn.hip", "capi.hip"]
+           "kernels_batch.hip", "kernels_nn.hip", "capi.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -3,8 +3,10 @@
 // Sec. 2.4, Eqs. (22)-(23)).  Host code only orchestrates: every arithmetic
 // step on problem data runs in the kernels of kernels_*.hip.
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
+#include <cstdlib>
 #include <mutex>
 #include <numeric>
 
@@ -75,6 +77,9 @@ void* scratch_address(int device) {
 }
 }  // namespace
 
+struct BatchState;
+void destroy_batch(BatchState* b);
+
 struct stf_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -94,6 +99,7 @@ struct stf_ctx_s {
   hipEvent_t cycle_ev = nullptr;                // true residuals of a restart copied
   stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
   void* scratch = nullptr;      // this device's scratch array (allocation-free round)
+  BatchState* batch = nullptr;  // state of the last stf_batch_solve (owned)
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -412,6 +418,8 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
 
 struct stf_problem_s {
   stf_ctx ctx = nullptr;
+  uint64_t uid = 0;                // unique per problem object
+  uint64_t generation = 0;         // incremented by every assembly
   Plan plan;
   stf_params prm{};
   long long N = 0;
@@ -573,6 +581,7 @@ void assemble_eps(stf_problem pb, const double* eps, int on_device) {
   if (!on_device) HIP_CHECK(hipStreamSynchronize(st));   // staging buffer reuse
   pb->assembled = true;
   pb->factored = false;
+  pb->generation += 1;
 }
 
 // Numeric factorisation of every level of a set; with `fault`, the first front
@@ -1311,6 +1320,483 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
   return worst;
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve: many problems, several right-hand sides each
+// ---------------------------------------------------------------------------
+//
+// All problems of a batch form one multifrontal set (one launch per tree level
+// over the fronts of every problem) and every (problem, right-hand side) pair is
+// a system of one lockstep FGMRES whose kernels cover all systems per launch.
+// Batch vectors hold nslot slots of ntot entries; problem p's nodes are at
+// gbase[p] inside each slot, so system s = slot * nprob + p is the segment
+// slot * ntot + gbase[p] .. + nx * ny.  One cycle (start, m iterations, update,
+// true residuals, status) is captured in a HIP graph and replayed.
+
+constexpr int BATCH_MAX_RESTART = 32;   // register Gram-Schmidt passes (nv <= 32)
+
+}  // namespace
+
+struct BatchState {
+  std::vector<uint64_t> key;      // (uid, generation) of every problem, in order
+  int prec = STF_C128, nprob = 0;
+  std::vector<long long> gbase;   // per problem
+  std::vector<long long> npts;    // per problem: nx * ny
+  long long ntot = 0;             // entries of one slot
+  Mf mf;
+  DBuf keps, gc;                  // concatenated k0^2 eps_bar and coupling arrays
+  std::vector<int> gc_off;        // per problem
+  DBuf flag;
+  // Systems of the current shape (nslot slots, cycle length m).
+  int nslot = 0, nsys = 0, m = 0, hcap = 0;
+  long long T = 0;                // batch vector length: nslot * ntot
+  std::vector<SysDev> hsys;
+  DBuf sysd, tsys, bsys[4];
+  int ntiles = 0, nblk[4] = {0, 0, 0, 0};
+  DBuf V, Z, W, R, X, B;
+  DBuf H, g, y, h1, h2, cs, sn, sc, act, cyc, kcol, it, rg, pact, hist;
+  DBuf part, npart, spart;
+  double* status = nullptr;       // pinned, device-visible: 4 doubles per system
+  double* status_dev = nullptr;
+  hipGraphExec_t graph = nullptr;
+  double graph_tol = -1.0;
+  int graph_max_iter = -1;
+  hipEvent_t ev[4] = {};          // [0, 1] factorisation, [2, 3] a slot group's solve
+  hipStream_t cap = nullptr;      // capture stream
+
+  ~BatchState() { release_graph(); if (status) (void)hipHostFree(status);
+    for (hipEvent_t& e : ev) if (e) (void)hipEventDestroy(e);
+    if (cap) (void)hipStreamDestroy(cap); }
+  void release_graph() {
+    if (graph) (void)hipGraphExecDestroy(graph);
+    graph = nullptr;
+  }
+};
+
+void destroy_batch(BatchState* b) { delete b; }
+
+namespace {
+
+// The batch state for `probs` on context c: reused while the problems and
+// their assemblies are the same, else rebuilt.
+BatchState& batch_state(stf_ctx c, int nprob, const stf_problem* probs) {
+  std::vector<uint64_t> key;
+  for (int p = 0; p < nprob; ++p) {
+    key.push_back(probs[p]->uid);
+    key.push_back(probs[p]->generation);
+  }
+  if (c->batch && c->batch->key == key) return *c->batch;
+  if (c->batch) {
+    HIP_CHECK(hipStreamSynchronize(c->stream));
+    destroy_batch(c->batch);
+    c->batch = nullptr;
+  }
+  std::unique_ptr<BatchState> b(new BatchState());
+  hipStream_t st = c->stream;
+  b->key = key;
+  b->nprob = nprob;
+  b->prec = probs[0]->prec;
+  std::vector<const Plan*> plans;
+  long long off = 0;
+  for (int p = 0; p < nprob; ++p) {
+    plans.push_back(&probs[p]->plan);
+    b->gbase.push_back(off);
+    b->npts.push_back(probs[p]->N);
+    off += (probs[p]->N + 63) / 64 * 64;          // segments start on 1 KiB boundaries
+  }
+  b->ntot = off;
+  build_mf(b->mf, plans, b->gbase, b->prec, st);
+  b->keps.alloc((size_t)b->ntot * sizeof(double2));
+  HIP_CHECK(hipMemsetAsync(b->keps.p, 0, (size_t)b->ntot * sizeof(double2), st));
+  long long gcn = 0;
+  for (int p = 0; p < nprob; ++p) {
+    b->gc_off.push_back((int)gcn);
+    gcn += 2LL * probs[p]->prm.nx + 2LL * probs[p]->prm.ny;
+  }
+  STF_REQUIRE(gcn < (1LL << 31), "batch too large for int32 coupling offsets");
+  b->gc.alloc((size_t)gcn * sizeof(double2));
+  for (int p = 0; p < nprob; ++p) {
+    HIP_CHECK(hipMemcpyAsync(b->keps.as<double2>() + b->gbase[p], probs[p]->keps.p,
+                             (size_t)probs[p]->N * sizeof(double2), hipMemcpyDeviceToDevice, st));
+    HIP_CHECK(hipMemcpyAsync(b->gc.as<double2>() + b->gc_off[p], probs[p]->gcoef.p,
+                             (size_t)(2 * probs[p]->prm.nx + 2 * probs[p]->prm.ny) * sizeof(double2),
+                             hipMemcpyDeviceToDevice, st));
+  }
+  b->flag.alloc(sizeof(int) * 4);
+  for (hipEvent_t& e : b->ev) HIP_CHECK(hipEventCreate(&e));
+  HIP_CHECK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  HIP_CHECK(hipStreamSynchronize(st));
+  c->batch = b.release();
+  return *c->batch;
+}
+
+// System tables, block maps and Krylov storage for nslot slots and cycle length m.
+void batch_systems(BatchState& b, const int32_t* nrhs, int slot0, int nslot, int m, int hcap,
+                   hipStream_t st) {
+  const bool same = b.nslot == nslot && b.m == m && b.hcap >= hcap;
+  // presence depends on the slot group: always rewrite the table
+  const int nsys = nslot * b.nprob;
+  std::vector<SysDev> sys(nsys);
+  std::vector<int> tsys, bsys[4];
+  int ntiles = 0, nblk[4] = {0, 0, 0, 0};
+  for (int k = 0; k < nslot; ++k)
+    for (int p = 0; p < b.nprob; ++p) {
+      const int s = k * b.nprob + p;
+      SysDev& d = sys[s];
+      d.off = (long long)k * b.ntot + b.gbase[p];
+      d.koff = b.gbase[p];
+      d.n = (int)b.npts[p];
+      d.gc = b.gc_off[p];
+      d.present = (slot0 + k) < nrhs[p] ? 1 : 0;
+      d.tile0 = ntiles;
+      sys[s] = d;
+    }
+  // grids come from the scatter table of the set (per problem nx, ny)
+  std::vector<ScatDev> scat(b.nprob);
+  HIP_CHECK(hipMemcpyAsync(scat.data(), b.mf.scat.p, sizeof(ScatDev) * b.nprob, hipMemcpyDeviceToHost, st));
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int s = 0; s < nsys; ++s) {
+    SysDev& d = sys[s];
+    const ScatDev& g = scat[s % b.nprob];
+    d.nx = g.nx;
+    d.ny = g.ny;
+    d.tile0 = ntiles;
+    const int nt = ((d.nx + 63) / 64) * ((d.ny + 3) / 4);
+    for (int t = 0; t < nt; ++t) tsys.push_back(s);
+    ntiles += nt;
+    for (int ci = 0; ci < 4; ++ci) {
+      const long long ch = 256LL << ci;
+      const int nb = (int)((d.n + ch - 1) / ch);
+      d.blk0[ci] = nblk[ci];
+      d.nblk[ci] = nb;
+      for (int t = 0; t < nb; ++t) bsys[ci].push_back(s);
+      nblk[ci] += nb;
+    }
+  }
+  b.hsys = sys;
+  b.nsys = nsys;
+  b.ntiles = ntiles;
+  upload(b.sysd, sys, st);
+  upload(b.tsys, tsys, st);
+  for (int ci = 0; ci < 4; ++ci) {
+    b.nblk[ci] = nblk[ci];
+    upload(b.bsys[ci], bsys[ci], st);
+  }
+  HIP_CHECK(hipStreamSynchronize(st));
+  if (same) return;
+  b.release_graph();
+  b.nslot = nslot;
+  b.m = m;
+  b.hcap = hcap;
+  b.T = (long long)nslot * b.ntot;
+  const size_t vb = (size_t)b.T * sizeof(double2);
+  b.V.alloc(vb * (m + 1));
+  b.Z.alloc(vb * m);
+  b.W.alloc(vb);
+  b.R.alloc(vb);
+  b.X.alloc(vb);
+  b.B.alloc(vb);
+  for (DBuf* d : {&b.V, &b.Z, &b.W, &b.R, &b.X, &b.B}) HIP_CHECK(hipMemsetAsync(d->p, 0, d->bytes, st));
+  const int hs = m + 1;
+  b.H.alloc(sizeof(double2) * hs * m * nsys);
+  b.g.alloc(sizeof(double2) * hs * nsys);
+  b.y.alloc(sizeof(double2) * hs * nsys);
+  b.h1.alloc(sizeof(double2) * hs * nsys);
+  b.h2.alloc(sizeof(double2) * hs * nsys);
+  b.cs.alloc(sizeof(double) * m * nsys);
+  b.sn.alloc(sizeof(double2) * m * nsys);
+  b.sc.alloc(sizeof(double) * 16 * nsys);
+  for (DBuf* d : {&b.act, &b.cyc, &b.kcol, &b.it, &b.rg}) d->alloc(sizeof(int) * nsys);
+  b.pact.alloc(sizeof(int) * b.nprob);
+  b.hist.alloc(sizeof(double) * (size_t)hcap * nsys);
+  const int maxblk = std::max({nblk[0], nblk[1], nblk[2], nblk[3], ntiles});
+  b.part.alloc(sizeof(double) * 64 * (size_t)std::max(1, maxblk));
+  b.npart.alloc(sizeof(double) * (size_t)std::max(1, maxblk));
+  b.spart.alloc(sizeof(double) * (size_t)std::max(1, ntiles));
+  if (b.status) (void)hipHostFree(b.status);
+  b.status = nullptr;
+  HIP_CHECK(hipHostMalloc((void**)&b.status, sizeof(double) * 4 * nsys, hipHostMallocCoherent));
+  HIP_CHECK(hipHostGetDevicePointer((void**)&b.status_dev, b.status, 0));
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
+// r = b - A x per system with |r|^2 into sc[s][dst] (gated).
+void batch_residual(stf_ctx c, BatchState& b, const int* gate, int dst) {
+  hipStream_t st = c->stream;
+  launch_bstencil(st, 1, b.X.as<double2>(), b.B.as<double2>(), b.R.as<double2>(),
+                  b.keps.as<double2>(), b.gc.as<double2>(), b.sysd.as<SysDev>(), b.tsys.as<int>(),
+                  b.ntiles, gate, b.spart.as<double>());
+  launch_bsum(st, b.spart.as<double>(), b.sysd.as<SysDev>(), b.nsys, -1, gate, b.sc.as<double>(), dst);
+}
+
+// One FGMRES cycle for every system, enqueued on c->stream: start (device
+// decision), m iterations gated by act, update and true residual of the
+// systems of the cycle, status to pinned host memory.
+template <typename T>
+void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter) {
+  hipStream_t st = c->stream;
+  const int m = b.m, hs = m + 1, nsys = b.nsys;
+  const SysDev* sys = b.sysd.as<SysDev>();
+  const int* bs3 = b.bsys[3].as<int>();
+  double2* V = b.V.as<double2>();
+  double2* Z = b.Z.as<double2>();
+  double2* W = b.W.as<double2>();
+  double* sc = b.sc.as<double>();
+  int* act = b.act.as<int>();
+  int* cyc = b.cyc.as<int>();
+  int* rg = b.rg.as<int>();
+  const long long Tn = b.T;
+  launch_bcycle_start(st, b.R.as<double2>(), V, sys, bs3, b.nblk[3], nsys, sc, b.g.as<double2>(), hs,
+                      act, cyc, b.kcol.as<int>(), b.it.as<int>(), tol, max_iter);
+  launch_bpact(st, act, b.nslot, b.nprob, b.pact.as<int>());
+  for (int j = 0; j < m; ++j) {
+    RhsSet rs;
+    rs.nr = b.nslot;
+    for (int k = 0; k < b.nslot; ++k) {
+      rs.v[k] = V + (long long)j * Tn + (long long)k * b.ntot;
+      rs.z[k] = Z + (long long)j * Tn + (long long)k * b.ntot;
+    }
+    precond_launch<T>(c, b.mf, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), false, b.pact.as<int>());
+    launch_bstencil(st, 0, Z + (long long)j * Tn, nullptr, W, b.keps.as<double2>(), b.gc.as<double2>(),
+                    sys, b.tsys.as<int>(), b.ntiles, act, nullptr);
+    // Classical Gram-Schmidt with the device-gated second pass, as in the solo solve.
+    const int nv = j + 1, ci = bgs_class(nv);
+    const int* bsg = b.bsys[ci].as<int>();
+    const int nbg = b.nblk[ci];
+    double2* h1 = b.h1.as<double2>();
+    double2* h2 = b.h2.as<double2>();
+    double* part = b.part.as<double>();
+    double* npart = b.npart.as<double>();
+    launch_bgs(st, GS_DOT, V, Tn, nv, nullptr, hs, W, sys, bsg, nbg, act, nullptr, part, npart,
+               nullptr, sc, 0, 0);
+    launch_bgs_reduce(st, part, nv, sys, nsys, act, nullptr, h1, hs, npart, sc, 6, -1, nullptr);
+    launch_bgs(st, GS_UPDATE_DOT, V, Tn, nv, h1, hs, W, sys, bsg, nbg, act, nullptr, part, npart,
+               nullptr, sc, 0, 0);
+    launch_bgs_reduce(st, part, nv, sys, nsys, act, nullptr, h2, hs, npart, sc, 3, 6, rg);
+    launch_bgs(st, GS_UPDATE_NORMALIZE, V, Tn, nv, h2, hs, W, sys, bsg, nbg, act, rg, part, npart,
+               V + (long long)(j + 1) * Tn, sc, 3, 8);
+    launch_bgivens_scale(st, W, V + (long long)(j + 1) * Tn, sys, bs3, b.nblk[3], nsys,
+                         b.H.as<double2>(), h1, h2, m, sc, b.cs.as<double>(), b.sn.as<double2>(),
+                         b.g.as<double2>(), j, act, rg, b.kcol.as<int>(), b.it.as<int>(),
+                         b.hist.as<double>(), b.hcap, tol, max_iter);
+    launch_bpact(st, act, b.nslot, b.nprob, b.pact.as<int>());
+  }
+  launch_btrisolve(st, b.H.as<double2>(), m, b.g.as<double2>(), b.y.as<double2>(), b.kcol.as<int>(),
+                   cyc, nsys);
+  launch_bxupdate(st, Z, Tn, b.y.as<double2>(), hs, b.X.as<double2>(), sys, bs3, b.nblk[3],
+                  b.kcol.as<int>(), cyc);
+  batch_residual(c, b, cyc, 2);
+  launch_bstatus(st, sc, b.it.as<int>(), cyc, nsys, b.status_dev);
+}
+
+// The cycle as a HIP graph (captured on the batch's own stream, replayed on the
+// context stream); rebuilt when the systems, m, tol or max_iter change.
+template <typename T>
+void batch_run_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, bool use_graph) {
+  if (!use_graph) {
+    batch_cycle<T>(c, b, tol, max_iter);
+    return;
+  }
+  if (!b.graph || b.graph_tol != tol || b.graph_max_iter != max_iter) {
+    b.release_graph();
+    hipStream_t keep = c->stream;
+    c->stream = b.cap;
+    hipGraph_t gr = nullptr;
+    HIP_CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeRelaxed));
+    try {
+      batch_cycle<T>(c, b, tol, max_iter);
+    } catch (...) {
+      (void)hipStreamEndCapture(b.cap, &gr);
+      if (gr) (void)hipGraphDestroy(gr);
+      c->stream = keep;
+      throw;
+    }
+    c->stream = keep;
+    HIP_CHECK(hipStreamEndCapture(b.cap, &gr));
+    const hipError_t e = hipGraphInstantiate(&b.graph, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIP_CHECK(e);
+    b.graph_tol = tol;
+    b.graph_max_iter = max_iter;
+  }
+  HIP_CHECK(hipGraphLaunch(b.graph, c->stream));
+}
+
+bool batch_use_graph() {
+  const char* e = std::getenv("STF_BATCH_EAGER");
+  return !(e && e[0] == '1');
+}
+
+template <typename T>
+stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const int32_t* nrhs,
+                         const double* const* b_in, double* const* x_out, int on_device,
+                         const stf_solve_opts& o, stf_solve_info* const* info, bool& perturbed) {
+  hipStream_t st = c->stream;
+  BatchState& bs = batch_state(c, nprob, probs);
+  // Factorisation of every problem, one launch per tree level over all fronts.
+  perturbed = factor_mf<T>(c, bs.mf, bs.keps.as<double2>(), bs.flag.as<int>(), false, bs.ev[0],
+                           bs.ev[1]) != 0;
+  const double t_fac = [&] {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, bs.ev[0], bs.ev[1]) == hipSuccess ? (double)ms : 0.0;
+  }();
+  int maxr = 0;
+  for (int p = 0; p < nprob; ++p) maxr = std::max(maxr, (int)nrhs[p]);
+  const int m = o.restart;
+  int hcap = 2;
+  for (int p = 0; p < nprob; ++p)
+    if (info && info[p])
+      for (int r = 0; r < nrhs[p]; ++r) hcap = std::max(hcap, info[p][r].history_cap);
+  hcap = std::min(hcap, o.max_iter + 1);
+  stf_status worst = STF_OK;
+  const bool graph = batch_use_graph();
+  for (int slot0 = 0; slot0 < maxr; slot0 += MAX_RHS) {
+    const int nslot = std::min(MAX_RHS, maxr - slot0);
+    batch_systems(bs, nrhs, slot0, nslot, m, hcap, st);
+    if (bs.mf.ws_nr < nslot) {
+      const size_t es = sizeof(T);
+      bs.mf.vec.alloc((size_t)bs.mf.vec_elems * es * nslot);
+      bs.mf.u.alloc((size_t)bs.mf.u_elems * es * nslot);
+      bs.mf.ws_nr = nslot;
+    }
+    const int nsys = bs.nsys;
+    const size_t vb = (size_t)bs.T * sizeof(double2);
+    HIP_CHECK(hipEventRecord(bs.ev[2], st));
+    // Right-hand sides and initial guesses into the batch vectors.
+    HIP_CHECK(hipMemsetAsync(bs.B.p, 0, vb, st));
+    HIP_CHECK(hipMemsetAsync(bs.X.p, 0, vb, st));
+    const hipMemcpyKind hk = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+    for (int k = 0; k < nslot; ++k)
+      for (int p = 0; p < nprob; ++p) {
+        const int r = slot0 + k;
+        if (r >= nrhs[p]) continue;
+        const size_t n = (size_t)bs.npts[p];
+        const long long off = (long long)k * bs.ntot + bs.gbase[p];
+        HIP_CHECK(hipMemcpyAsync(bs.B.as<double2>() + off, b_in[p] + 2 * n * r, n * sizeof(double2),
+                                 hk, st));
+        if (o.x0_mode == STF_X0_USER)
+          HIP_CHECK(hipMemcpyAsync(bs.X.as<double2>() + off, x_out[p] + 2 * n * r,
+                                   n * sizeof(double2), hk, st));
+      }
+    std::vector<double> t_nn(nsys, 0.0);
+    if (o.x0_mode == STF_X0_LEARNED) {
+      STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+      for (int s = 0; s < nsys; ++s) {
+        if (!bs.hsys[s].present) continue;
+        const int p = s % nprob;
+        hipEvent_t e0 = probs[p]->ev[4], e1 = probs[p]->ev[5];
+        HIP_CHECK(hipEventRecord(e0, st));
+        nn_initial_guess(probs[p], c->nn, bs.B.as<double2>() + bs.hsys[s].off,
+                         bs.X.as<double2>() + bs.hsys[s].off);
+        HIP_CHECK(hipEventRecord(e1, st));
+        HIP_CHECK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t_nn[s] = ms;
+      }
+    }
+    // |b|^2, initial residuals, cleared flags and counters.
+    HIP_CHECK(hipMemsetAsync(bs.sc.p, 0, bs.sc.bytes, st));
+    HIP_CHECK(hipMemsetAsync(bs.it.p, 0, bs.it.bytes, st));
+    launch_bnorm2(st, bs.B.as<double2>(), bs.sysd.as<SysDev>(), bs.bsys[3].as<int>(), bs.nblk[3],
+                  bs.npart.as<double>());
+    launch_bsum(st, bs.npart.as<double>(), bs.sysd.as<SysDev>(), nsys, 3, nullptr, bs.sc.as<double>(), 0);
+    batch_residual(c, bs, nullptr, 2);
+    std::vector<double> sch(16 * (size_t)nsys);
+    HIP_CHECK(hipMemcpyAsync(sch.data(), bs.sc.p, sizeof(double) * 16 * nsys, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<double> bnorm(nsys), rx0(nsys);
+    std::vector<int> used(nsys, 0);
+    bool refresh = false;
+    for (int s = 0; s < nsys; ++s) {
+      bnorm[s] = std::sqrt(sch[16 * s]);
+      const double rn = std::sqrt(sch[16 * s + 2]);
+      if (!std::isfinite(rn)) throw Error(STF_ENAN, "non-finite initial residual");
+      rx0[s] = bnorm[s] > 0.0 ? rn / bnorm[s] : 0.0;
+      if (o.x0_mode == STF_X0_LEARNED && bs.hsys[s].present) {
+        if (!(rn < bnorm[s])) {          // fallback: the zero guess
+          HIP_CHECK(hipMemsetAsync(bs.X.as<double2>() + bs.hsys[s].off, 0,
+                                   (size_t)bs.hsys[s].n * sizeof(double2), st));
+          refresh = true;
+        } else {
+          used[s] = 1;
+        }
+      }
+    }
+    if (refresh) {
+      batch_residual(c, bs, nullptr, 2);
+      HIP_CHECK(hipMemcpyAsync(sch.data(), bs.sc.p, sizeof(double) * 16 * nsys, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+    std::vector<double> rn2(nsys), itc(nsys, 0.0);
+    std::vector<int> restarts(nsys, 0);
+    for (int s = 0; s < nsys; ++s) rn2[s] = sch[16 * s + 2];
+    auto running = [&](int s) {
+      const double rn = std::sqrt(rn2[s]);
+      return bs.hsys[s].present && bnorm[s] > 0.0 && rn > o.tol * bnorm[s] && itc[s] < o.max_iter;
+    };
+    while (true) {
+      bool any = false;
+      for (int s = 0; s < nsys; ++s) any = any || running(s);
+      if (!any) break;
+      batch_run_cycle<T>(c, bs, o.tol, o.max_iter, graph);
+      HIP_CHECK(hipStreamSynchronize(st));
+      bool progress = false;
+      for (int s = 0; s < nsys; ++s) {
+        const double* q = bs.status + 4 * s;
+        if (q[1] != itc[s]) progress = true;
+        if (q[2] != 0.0) restarts[s] += 1;
+        rn2[s] = q[0];
+        itc[s] = q[1];
+        if (q[3] != 0.0 || !std::isfinite(q[0])) throw Error(STF_ENAN, "non-finite residual in a batched solve");
+      }
+      if (!progress) throw Error(STF_EDEVICE, "internal: a batched FGMRES cycle made no progress");
+    }
+    HIP_CHECK(hipEventRecord(bs.ev[3], st));
+    // Solutions back to the caller, histories and infos.
+    const hipMemcpyKind ok = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    for (int s = 0; s < nsys; ++s) {
+      if (!bs.hsys[s].present) continue;
+      const int p = s % nprob, r = slot0 + s / nprob;
+      const size_t n = (size_t)bs.npts[p];
+      HIP_CHECK(hipMemcpyAsync(x_out[p] + 2 * n * r, bs.X.as<double2>() + bs.hsys[s].off,
+                               n * sizeof(double2), ok, st));
+    }
+    std::vector<double> hh((size_t)bs.hcap * nsys);
+    HIP_CHECK(hipMemcpyAsync(hh.data(), bs.hist.p, sizeof(double) * hh.size(), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    float ms = 0.f;
+    const double t_solve = hipEventElapsedTime(&ms, bs.ev[2], bs.ev[3]) == hipSuccess ? (double)ms : 0.0;
+    for (int s = 0; s < nsys; ++s) {
+      if (!bs.hsys[s].present) continue;
+      const int p = s % nprob, r = slot0 + s / nprob;
+      const double rel = bnorm[s] > 0.0 ? std::sqrt(rn2[s]) / bnorm[s] : 0.0;
+      const stf_status sst = (bnorm[s] == 0.0 || rel <= o.tol) ? STF_OK : STF_ENOCONV;
+      if (sst != STF_OK && worst == STF_OK) worst = sst;
+      if (!info || !info[p]) continue;
+      stf_solve_info& inf = info[p][r];
+      stf_solve_info loc{};
+      loc.iters = (int)itc[s];
+      loc.restarts = restarts[s];
+      loc.status = sst;
+      loc.relres_true = rel;
+      loc.relres_x0 = rx0[s];
+      loc.used_learned = used[s];
+      loc.history = inf.history;
+      loc.history_cap = inf.history_cap;
+      loc.t_factor_ms = t_fac;
+      loc.t_solve_ms = t_solve;
+      loc.t_nn_ms = t_nn[s];
+      const int len = std::min((int)itc[s] + 1, std::min(inf.history_cap, bs.hcap));
+      if (inf.history && len > 0) {
+        inf.history[0] = bnorm[s] > 0.0 ? std::sqrt(sch[16 * s + 2]) / bnorm[s] : 0.0;
+        for (int i = 1; i < len; ++i) inf.history[i] = hh[(size_t)s * bs.hcap + i];
+      }
+      loc.history_len = inf.history ? std::max(0, len) : 0;
+      inf = loc;
+    }
+  }
+  return worst;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -1374,6 +1860,7 @@ void stf_ctx_destroy(stf_ctx c) {
     if (c->iter_ev[e]) (void)hipEventDestroy(c->iter_ev[e]);
   if (c->cycle_ev) (void)hipEventDestroy(c->cycle_ev);
   if (c->pinned) (void)hipHostFree(c->pinned);
+  destroy_batch(c->batch);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1468,6 +1955,8 @@ stf_status stf_problem_create(stf_ctx c, const stf_params* prm, const double* ep
   stf_status s = guard(c, [&] {
     pb = new stf_problem_s();
     pb->ctx = c;
+    static std::atomic<uint64_t> next_uid{1};
+    pb->uid = next_uid.fetch_add(1);
     pb->plan = build_plan(*prm, &c->shapes);
     pb->prm = pb->plan.prm;
     pb->make_events();
@@ -1764,6 +2253,48 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
   if (worst == STF_ENOCONV) pb->ctx->last_error = "FGMRES reached max_iter above tol";
   if (worst == STF_OK && perturbed) {
     pb->ctx->last_error = "tiny pivot perturbed during factorisation (planted fault)";
+    return STF_EPIVOT;
+  }
+  return worst;
+}
+
+stf_status stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,
+                           const int32_t* nrhs, const double* const* b, double* const* x,
+                           int on_device, const stf_solve_opts* opts, stf_solve_info* const* info) {
+  if (!ctx) return STF_EINVAL;
+  stf_status worst = STF_OK;
+  bool perturbed = false;
+  stf_status s = guard(ctx, [&] {
+    STF_REQUIRE(nprob >= 1 && probs && nrhs && b && x && opts, "null argument or empty batch");
+    STF_REQUIRE(opts->restart >= 1 && opts->restart <= BATCH_MAX_RESTART,
+                "batched restart out of range (1..32)");
+    STF_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+    STF_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be finite and >= 0");
+    STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER ||
+                    opts->x0_mode == STF_X0_LEARNED,
+                "x0_mode invalid");
+    STF_REQUIRE(opts->rounds <= 1, "a batched solve takes one source-transfer round per application");
+    STF_REQUIRE(opts->debug_fault == 0, "debug_fault is not available in a batched solve");
+    for (int p = 0; p < nprob; ++p) {
+      STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
+      STF_REQUIRE(probs[p]->assembled, "problem not assembled");
+      STF_REQUIRE(probs[p]->prec == probs[0]->prec, "all problems of a batch need one front precision");
+      STF_REQUIRE(nrhs[p] >= 1, "nrhs must be >= 1");
+      STF_REQUIRE(b[p] && x[p], "null right-hand side or solution pointer");
+      for (int q = 0; q < p; ++q) STF_REQUIRE(probs[q] != probs[p], "a problem appears twice in the batch");
+      const size_t per = (size_t)probs[p]->N * 2 * nrhs[p];
+      require_finite(probs[p], b[p], per, on_device, "b");
+      if (opts->x0_mode == STF_X0_USER) require_finite(probs[p], x[p], per, on_device, "x0");
+    }
+    worst = probs[0]->prec == STF_C64
+                ? batch_solve_t<float2>(ctx, nprob, probs, nrhs, b, x, on_device, *opts, info, perturbed)
+                : batch_solve_t<double2>(ctx, nprob, probs, nrhs, b, x, on_device, *opts, info, perturbed);
+    HIP_CHECK(hipGetLastError());
+  });
+  if (s != STF_OK) return s;
+  if (worst == STF_ENOCONV) ctx->last_error = "FGMRES reached max_iter above tol";
+  if (worst == STF_OK && perturbed) {
+    ctx->last_error = "tiny pivot perturbed during factorisation";
     return STF_EPIVOT;
   }
   return worst;

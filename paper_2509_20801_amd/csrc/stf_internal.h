@@ -179,6 +179,19 @@ struct RhsSet {
   double2* z[MAX_RHS] = {};            // round outputs (global, FP64)
 };
 
+// One system of a batched solve (a problem and one of its right-hand sides):
+// the segment [off, off + n) of every batch vector, systems slot-major
+// (s = slot * nprob + problem).
+struct SysDev {
+  long long off;            // first entry in the batch vectors
+  long long koff;           // first node of its problem in the concatenated node arrays
+  int n, nx, ny;            // entries (nx * ny) and grid
+  int gc;                   // offset of its problem's coupling arrays (cxw | cxe | cyw | cye)
+  int present;              // 0: a slot beyond its problem's right-hand sides
+  int tile0;                // first 64 x 4 stencil tile
+  int blk0[4], nblk[4];     // first block and block count for chunks of 256 << c entries
+};
+
 // Kernel classes for timing (match STF_K_* in stfdfd.h).
 enum KClass {
   K_ASSEMBLE = STF_K_ASSEMBLE, K_STENCIL = STF_K_STENCIL, K_FRONT_ASM = STF_K_FRONT_ASM,
@@ -307,6 +320,43 @@ void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n);
 // x += Z y
 void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
                     double2* x, long long n);
+
+// ---------------------------------------------------------------------------
+// Batched FGMRES (kernels_batch.hip): every launch covers all systems; sc holds
+// 16 doubles per system ([0] |b|^2, [2] |r|^2, [3] |w|^2, [4] estimate, [6] |w|^2
+// before the first update, [8] |w|^2 after the second, [10] non-finite flag).
+// ---------------------------------------------------------------------------
+int bgs_class(int nv);    // chunk class of the Gram-Schmidt pass over nv vectors (-1: > 32)
+void launch_bstencil(hipStream_t st, int mode, const double2* x, const double2* b, double2* y,
+                     const double2* keps, const double2* gc, const SysDev* sys, const int* tsys,
+                     int ntiles, const int* gate, double* partial);
+void launch_bnorm2(hipStream_t st, const double2* v, const SysDev* sys, const int* bsys, int nblk,
+                   double* npart);
+void launch_bsum(hipStream_t st, const double* partial, const SysDev* sys, int nsys, int ci,
+                 const int* gate, double* sc, int out);
+void launch_bgs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
+                int hs, double2* w, const SysDev* sys, const int* bsys, int nblk, const int* act,
+                const int* rgate, double* partial, double* npart, double2* vout, double* sc, int nin,
+                int nout);
+void launch_bgs_reduce(hipStream_t st, const double* partial, int nv, const SysDev* sys, int nsys,
+                       const int* act, const int* rgate_in, double2* h, int hs, const double* npart,
+                       double* sc, int out, int ref, int* rgate_out);
+void launch_bgivens_scale(hipStream_t st, const double2* w, double2* v, const SysDev* sys,
+                          const int* bsys, int nblk, int nsys, double2* H, const double2* h1,
+                          const double2* h2, int m, double* sc, double* cs, double2* sn, double2* g,
+                          int j, int* act, const int* rgate, int* kcol, int* it, double* hist,
+                          int hcap, double tol, int max_iter);
+void launch_bpact(hipStream_t st, const int* act, int nslot, int nprob, int* pact);
+void launch_bcycle_start(hipStream_t st, const double2* r, double2* v, const SysDev* sys,
+                         const int* bsys, int nblk, int nsys, const double* sc, double2* g, int glen,
+                         int* act, int* cyc, int* kcol, const int* it, double tol, int max_iter);
+void launch_btrisolve(hipStream_t st, const double2* H, int m, const double2* g, double2* y,
+                      const int* kcol, const int* cyc, int nsys);
+void launch_bxupdate(hipStream_t st, const double2* Z, long long ld, const double2* y, int hs,
+                     double2* x, const SysDev* sys, const int* bsys, int nblk, const int* kcol,
+                     const int* cyc);
+void launch_bstatus(hipStream_t st, const double* sc, const int* it, const int* cyc, int nsys,
+                    double* host_out);
 
 // ---------------------------------------------------------------------------
 // Learned warm start (kernels_nn.hip).  FP32 tensors, all on `st`.

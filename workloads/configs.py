@@ -97,3 +97,40 @@ def small_random(nx=48, ny=40, pml=6, lam=12.0, px=2, py=2, overlap=2, local_pml
     k0 = 2 * math.pi / lam
     return Workload("random_%dx%d" % (nx, ny), nx, ny, k0, (pml,) * 4, 3, 1e-8, px, py, overlap,
                     local_pml, 3, 1e-8, cells, b, meta=dict(seed=seed))
+
+
+def disks_problem(k, sides=(256, 384, 512, 768), pml=16, block=128, overlap=8, local_pml=16,
+                  nrhs=4, seed0=300, subcells=8):
+    """Problem k of the batched workload: a square interior of side drawn from
+    `sides` plus a 16-cell PML, vacuum with random dielectric disks (n in
+    [1.4, 3.5], radius [0.15, 0.5] lambda, 30% area fill), lambda uniform in
+    [16, 40] cells, side/128 subdomains per axis, and `nrhs` right-hand sides,
+    each with probability 1/2 a plane wave at a random angle (scattered-field
+    source) or a point dipole at a random interior node.  Seed seed0 + k."""
+    rng = np.random.default_rng(seed0 + k)
+    side = int(rng.choice(np.asarray(sides)))
+    lam = float(rng.uniform(16.0, 40.0))
+    n = side + 2 * pml
+    k0 = 2 * math.pi / lam
+    shapes = geometry.random_disk_shapes(n, n, pml, lam, 0.30, 1.4, 3.5, 0.15, 0.5, rng)
+    cells = geometry.subcell_raster(n, n, shapes, 1.0, 1.0, 1.0, subcells)
+    contrast = geometry.node_samples(n, n, shapes) - 1.0
+    bs, kinds = [], []
+    for _ in range(nrhs):
+        if rng.uniform() < 0.5:
+            th = float(rng.uniform(0.0, 2 * math.pi))
+            bs.append(sources.scattered_plane_wave(contrast, k0, th))
+            kinds.append(("plane", th))
+        else:
+            i, j = (int(v) for v in rng.integers(pml, pml + side, size=2))
+            bs.append(sources.point_dipole(n, n, i, j))
+            kinds.append(("dipole", (i, j)))
+    parts = max(1, side // block)
+    return Workload("disks_%d_%d" % (k, n), n, n, k0, (pml,) * 4, 3, 1e-8, parts, parts, overlap,
+                    local_pml, 3, 1e-8, cells, np.stack(bs), meta=dict(seed=seed0 + k, lam=lam,
+                                                                     side=side, rhs=kinds))
+
+
+def disks_batch(count=48, **kw):
+    """The batched workload: problems 0 .. count-1 of disks_problem."""
+    return [disks_problem(k, **kw) for k in range(count)]

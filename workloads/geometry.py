@@ -116,11 +116,10 @@ def metasurface(nx, ny, pml, lam_cells, n_pillars, slot, substrate_rows, eps_pil
     return subcell_raster(nx, ny, shapes, 1.0, 1.0, 1.0, subcells)
 
 
-def random_disks(nx, ny, pml, lam_cells, fill, nmin, nmax, rmin, rmax, seed, subcells=8):
-    """Vacuum plus random dielectric disks (refractive index U(nmin, nmax),
-    radius U(rmin, rmax)*lambda, uniform centres inside the physical region)
-    added until the summed disk area reaches `fill` of the physical area."""
-    rng = np.random.default_rng(seed)
+def random_disk_shapes(nx, ny, pml, lam_cells, fill, nmin, nmax, rmin, rmax, rng):
+    """Random dielectric disks (refractive index U(nmin, nmax), radius
+    U(rmin, rmax)*lambda, uniform centres inside the physical region) drawn from
+    `rng` until the summed disk area reaches `fill` of the physical area."""
     w = nx - 2 * pml
     h = ny - 2 * pml
     target = fill * w * h
@@ -133,4 +132,29 @@ def random_disks(nx, ny, pml, lam_cells, fill, nmin, nmax, rmin, rmax, seed, sub
         cy = pml + rng.uniform(0, h - 1)
         shapes.append(Circle(cx, cy, r, n * n))
         area += math.pi * r * r
+    return shapes
+
+
+def random_disks(nx, ny, pml, lam_cells, fill, nmin, nmax, rmin, rmax, seed, subcells=8):
+    """Vacuum plus random dielectric disks (random_disk_shapes with a PCG64 of
+    `seed`) rasterised on the cell grid."""
+    shapes = random_disk_shapes(nx, ny, pml, lam_cells, fill, nmin, nmax, rmin, rmax,
+                                np.random.default_rng(seed))
     return subcell_raster(nx, ny, shapes, 1.0, 1.0, 1.0, subcells)
+
+
+def node_samples(nx, ny, shapes, eps_bg=1.0, dx=1.0, dy=1.0):
+    """Permittivity sampled at the node positions (i dx, j dy): the medium that
+    contains the node itself (later shapes win).  Used to shape sources, not
+    the operator."""
+    out = np.full((ny, nx), complex(eps_bg), dtype=np.complex128)
+    for shp in shapes:
+        x0, x1, y0, y1 = shp.bbox()
+        i0, i1 = max(0, int(math.floor(x0 / dx))), min(nx, int(math.ceil(x1 / dx)) + 1)
+        j0, j1 = max(0, int(math.floor(y0 / dy))), min(ny, int(math.ceil(y1 / dy)) + 1)
+        if i0 >= i1 or j0 >= j1:
+            continue
+        X, Y = np.meshgrid(np.arange(i0, i1) * dx, np.arange(j0, j1) * dy)
+        blk = out[j0:j1, i0:i1]
+        blk[shp.inside(X, Y)] = shp.eps
+    return out

@@ -61,3 +61,15 @@ def random_field(nx, ny, seed):
     """Seeded complex field with independent standard-normal real and imaginary parts."""
     rng = np.random.default_rng(seed)
     return (rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))).astype(np.complex128)
+
+
+def scattered_plane_wave(contrast, k0, theta, dx=1.0, dy=1.0):
+    """Scattered-field source of a unit plane wave exp(-j k0 (x cos t + y sin t))
+    (the form of Eq. (7)): b = -k0^2 (eps - 1) e_inc, with the permittivity
+    contrast (eps - 1) given per node (ny, nx); the solution is the field
+    scattered by the contrast."""
+    ny, nx = contrast.shape
+    X = np.arange(nx)[None, :] * dx
+    Y = np.arange(ny)[:, None] * dy
+    e_inc = np.exp(-1j * k0 * (X * math.cos(theta) + Y * math.sin(theta)))
+    return (-(k0 ** 2) * contrast * e_inc).astype(np.complex128)
