@@ -152,3 +152,57 @@ def stationary(A, B, b, rounds):
         x = x + B.apply(b - A @ x)
         hist.append(fdfd.relres(A, x, b))
     return x, hist
+
+
+# ---------------------------------------------------------------------------
+# Multiplicative (sweeping) order of the source transfer.
+#
+# The paper runs the rounds in parallel over all subdomains (Jacobi).  The
+# sweeping source-transfer methods it builds on (Sec. 1: the multiplicative
+# and diagonal-sweep forms of Leng et al., Dai et al., Chen and Xiang) visit the
+# subdomains in stages instead: each stage solves its subdomains with the
+# residual that the stages before it left, so a wave crosses many subdomains in
+# one application.  With stages S_1, ..., S_T the application is
+#     z = 0;  for each stage t:  z <- z + sum_{k in S_t} P_k A_k^{-1} R_k^I (v - A z),
+# the local operators, restriction and full-field prolongation being those of
+# the Jacobi round above.  Orders: "rows" (subdomain rows up, then back down),
+# "rows_cols" (rows up and down, then columns right and back), "diagonal"
+# (anti-diagonals kx + ky rising and falling, then the diagonals
+# kx + (py - 1 - ky) rising and falling: four corner-to-corner directions).
+# ---------------------------------------------------------------------------
+
+ORDERS = ("additive", "rows", "rows_cols", "diagonal")
+
+
+def sweep_stages(subs, px, py, order):
+    """Stages (lists of subdomain indices) of a sweeping order."""
+    if order == "additive":
+        return [[s.k for s in subs]]
+    rows = [[s.k for s in subs if s.ky == j] for j in range(py)]
+    cols = [[s.k for s in subs if s.kx == i] for i in range(px)]
+    if order == "rows":
+        return rows + rows[-2::-1]
+    if order == "rows_cols":
+        return rows + rows[-2::-1] + cols + cols[-2::-1]
+    if order == "diagonal":
+        nd = px + py - 1
+        d1 = [[s.k for s in subs if s.kx + s.ky == d] for d in range(nd)]
+        d2 = [[s.k for s in subs if s.kx + (py - 1 - s.ky) == d] for d in range(nd)]
+        return d1 + d1[-2::-1] + d2 + d2[-2::-1]
+    raise ValueError("unknown order %r" % (order,))
+
+
+def sweep_apply(B, A, v, stages):
+    """One application of the staged (multiplicative) source transfer:
+    z = 0, then for every stage z += sum_k P_k A_k^{-1} R_k^I (v - A z)."""
+    v = np.asarray(v, dtype=np.complex128).ravel()
+    z = np.zeros(B.nx * B.ny, dtype=np.complex128)
+    for stage in stages:
+        r = v - A @ z
+        Z = z.reshape(B.ny, B.nx)
+        for k in stage:
+            s = B.subs[k]
+            u = B.local_solve(k, B.restrict(r, s))
+            Z[s.oy[0]:s.oy[1], s.ox[0]:s.ox[1]] += u.reshape(s.oy[1] - s.oy[0], s.ox[1] - s.ox[0])
+        z = Z.ravel()
+    return z

@@ -175,3 +175,69 @@ def test_one_round_is_one_way_transfer_in_vacuum():
     y = _ras_round(B, b, w.ny, w.nx)
     y = y + _ras_round(B, b - A @ y, w.ny, w.nx)
     assert fdfd.relres(A, y, b) > 0.1
+
+
+# --- sweeping (multiplicative) orders -----------------------------------------
+
+def test_sweep_stages_cover_every_subdomain():
+    w = workloads.configs.small_random(nx=70, ny=64, pml=6, px=3, py=2, overlap=3, local_pml=6)
+    subs = ddm.partition(w.params())
+    for order in ddm.ORDERS:
+        st = ddm.sweep_stages(subs, 3, 2, order)
+        seen = sorted({k for stg in st for k in stg})
+        assert seen == list(range(6))
+        for stg in st:                  # no two subdomains of a stage are the same
+            assert len(set(stg)) == len(stg)
+    assert len(ddm.sweep_stages(subs, 3, 2, "rows")) == 3
+    assert len(ddm.sweep_stages(subs, 3, 2, "rows_cols")) == 3 + 5
+    assert len(ddm.sweep_stages(subs, 3, 2, "diagonal")) == 4 * 4 - 2
+    # additive = the Jacobi round
+    B = ddm.SourceTransfer(w.params(), w.eps_cells)
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    v = w.b[0].ravel()
+    assert np.allclose(ddm.sweep_apply(B, A, v, ddm.sweep_stages(subs, 3, 2, "additive")), B.apply(v),
+                       rtol=0, atol=1e-13 * np.abs(B.apply(v)).max())
+
+
+def test_one_column_sweep_carries_a_wave_through_both_subdomains():
+    """Two subdomains side by side, vacuum, a point source in Omega_1: the
+    staged order visits Omega_1 then Omega_2 (the second stage solves with the
+    residual the first left, which is the transferred source), so ONE
+    application reaches the local PML's reflection level, where the Jacobi
+    round needs a second round (test_one_round_is_one_way_transfer_in_vacuum)."""
+    w, A, B, b = _two_sub_vacuum(overlap=4, local_pml=10)
+    stages = ddm.sweep_stages(B.subs, 2, 1, "rows_cols")      # [[0, 1], [0], [1], [0]]
+    z1 = ddm.sweep_apply(B, A, b, [[0], [1]])
+    assert fdfd.relres(A, z1, b) < 1e-4
+    assert fdfd.relres(A, B.apply(b), b) > 1e-2
+    # the full symmetric order only improves on that
+    assert fdfd.relres(A, ddm.sweep_apply(B, A, b, stages), b) < 1e-4
+
+
+@pytest.mark.parametrize("order", ["rows", "rows_cols", "diagonal"])
+def test_fgmres_with_sweeps_matches_direct_in_fewer_iterations(order):
+    """Any staged order is a fixed linear preconditioner: FGMRES converges to the
+    direct solve, in fewer iterations than with the Jacobi round here."""
+    w = workloads.configs.small_random(nx=96, ny=96, pml=8, px=3, py=3, overlap=3, local_pml=8,
+                                       seed=12)
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    stages = ddm.sweep_stages(B.subs, 3, 3, order)
+    x, info = krylov.fgmres(lambda v: A @ v, b, lambda v: ddm.sweep_apply(B, A, v, stages),
+                            tol=1e-11, restart=40)
+    _, add = krylov.fgmres(lambda v: A @ v, b, B.apply, tol=1e-11, restart=40)
+    assert info["converged"] and fdfd.rel_l2(x, fdfd.solve_direct(A, b)) < 1e-9
+    assert info["iters"] < add["iters"]
+
+
+def test_single_subdomain_sweep_is_exact_inverse():
+    w = workloads.configs.small_random(nx=40, ny=36, pml=6, px=1, py=1)
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    for order in ddm.ORDERS:
+        z = ddm.sweep_apply(B, A, b, ddm.sweep_stages(B.subs, 1, 1, order))
+        assert fdfd.relres(A, z, b) < 1e-13
