@@ -60,6 +60,23 @@ enum { STF_C128 = 0, STF_C64 = 1 };
  * (then the zero guess is used instead; see stf_solve_info.used_learned). */
 enum { STF_X0_ZERO = 0, STF_X0_USER = 1, STF_X0_LEARNED = 2 };
 
+/* Order of the source transfer inside one preconditioner application.
+ * STF_ORDER_ADDITIVE is the paper's Jacobi round (Algorithm 1: every subdomain
+ * solves with the previous round's data, Eq. (21) sums the local fields).  The
+ * others visit the subdomains in stages, as the sweeping source-transfer
+ * methods the paper builds on (Sec. 1) do: each stage solves its subdomains
+ * with the residual left by the stages before it and adds their full local
+ * fields,  z = 0;  for every stage: z += sum_{k in stage} P_k A_k^{-1} R_k^I (v - A z).
+ *   STF_ORDER_ROWS       subdomain rows ky = 0 .. py-1, then back down to 0;
+ *   STF_ORDER_ROWS_COLS  rows up and down, then columns kx = 0 .. px-1 and back;
+ *   STF_ORDER_DIAGONAL   the anti-diagonals kx + ky rising and falling, then the
+ *                        diagonals kx + (py-1-ky) rising and falling (four
+ *                        corner-to-corner directions).
+ * A staged application reads the factors once per stage a subdomain belongs
+ * to (2-4 times) but carries waves across many subdomains, so FGMRES needs far
+ * fewer iterations where waves cross many subdomains. */
+enum { STF_ORDER_ADDITIVE = 0, STF_ORDER_ROWS = 1, STF_ORDER_ROWS_COLS = 2, STF_ORDER_DIAGONAL = 3 };
+
 /* Problem description (Sec. 2.1-2.3).  Global PML sides are ordered x-, x+, y-, y+.
  * The interior [pml[0], nx-pml[1]) x [pml[2], ny-pml[3]) is split into px x py
  * blocks as evenly as possible (earlier blocks take the remainder); edge blocks
@@ -102,6 +119,8 @@ typedef struct {
                           STF_EPIVOT when every right-hand side converged (info.status
                           stays STF_OK).  The factors keep the fault until the next
                           stf_factor. */
+  int32_t order;      /* STF_ORDER_*: order of the source transfer in the preconditioner
+                         (rounds > 1 only with STF_ORDER_ADDITIVE) */
 } stf_solve_opts;
 
 typedef struct {
@@ -230,6 +249,10 @@ stf_status  stf_precond_apply(stf_problem pb, const double* v, double* z, int on
  * stf_precond_apply on its own vector. */
 stf_status  stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v, double* z,
                                     int on_device);
+/* One application of the preconditioner in a given order (STF_ORDER_*; the
+ * additive order is stf_precond_apply): v, z: ny*nx complex, host or device. */
+stf_status  stf_sweep_apply(stf_problem pb, int32_t order, const double* v, double* z,
+                            int on_device);
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): the round of
  * stf_precond_apply on device buffers, allocating nothing.  v, z: ny*nx complex,
@@ -254,7 +277,8 @@ stf_status  stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z
  * probs: nprob distinct assembled problems of this context with the same
  * front_prec; nrhs[p] >= 1; b[p], x[p]: nrhs[p]*ny_p*nx_p complex each, all host
  * or all device (on_device); x[p] holds the guesses for STF_X0_USER.
- * opts: as stf_solve with restart <= 32, rounds <= 1, debug_fault = 0.
+ * opts: as stf_solve with restart <= 32, rounds <= 1, debug_fault = 0 (any order;
+ * a staged order runs stage t of every problem in the same launches).
  * info: NULL, or nprob pointers (each NULL or an array of nrhs[p] infos).
  * The factors live in a state cached on the context and reused while the same
  * problems (and assemblies) are passed; every call factors again (a problem's

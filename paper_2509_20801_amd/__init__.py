@@ -260,6 +260,18 @@ class Problem:
             _check(self.ctx.handle, self._lib.stf_precond_apply_batch(self.handle, nrhs, pv, pz, dev))
         return z if dev else kz.reshape(shape)
 
+    def sweep(self, v, order, z=None):
+        """One preconditioner application in a staged order ("rows", "rows_cols",
+        "diagonal"; "additive" is the round of precond())."""
+        n = self.ndof
+        pv, dev, kv = _ptr(v, n, "v")
+        z = self._out_like(v, tuple(v.shape)) if z is None else z
+        pz, dev2, kz = _ptr(z, n, "z")
+        if dev != dev2:
+            raise TypeError("v and z must both be host or both be device arrays")
+        _check(self.ctx.handle, self._lib.stf_sweep_apply(self.handle, _order(order), pv, pz, dev))
+        return z if dev else kz.reshape(tuple(v.shape))
+
     def precond_noalloc(self, v, z):
         """One source-transfer round into the preallocated z with the library's
         static workspace (no device allocation); v, z: complex128 CUDA tensors
@@ -301,7 +313,7 @@ class Problem:
         return (x if dev else kx.reshape(tuple(b.shape))), info
 
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,
-              raise_on_noconv=False, rounds=1, debug_fault=0):
+              raise_on_noconv=False, rounds=1, debug_fault=0, order="additive"):
         """Solve A x = b; b shaped (ny, nx) or (nrhs, ny, nx).  Returns (x, infos).
         x0: None (zero guess), an array (user guess) or "learned" (the context's network).
         debug_fault=1 re-factors with one planted zero pivot column first (test hook of the
@@ -330,7 +342,7 @@ class Problem:
         if dev != dev2:
             raise TypeError("b and x must both be host or both be device arrays")
         opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, int(rounds),
-                              int(debug_fault))
+                              int(debug_fault), _order(order))
         infos = (_abi.SolveInfo * nrhs)()
         hist = [np.zeros(history_cap, dtype=np.float64) for _ in range(nrhs)]
         for i in range(nrhs):
@@ -383,8 +395,16 @@ class Problem:
         return x if dev else kx.reshape(self.ny, self.nx)
 
 
+def _order(order):
+    if isinstance(order, str):
+        if order not in _abi.ORDERS:
+            raise ValueError("order must be one of %s" % list(_abi.ORDERS))
+        return _abi.ORDERS[order]
+    return int(order)
+
+
 def batch_solve(ctx, problems, bs, xs=None, tol=1e-10, restart=10, max_iter=500, x0=None,
-                history_cap=1024, raise_on_noconv=False):
+                history_cap=1024, raise_on_noconv=False, order="additive"):
     """Factor the problems together and solve all their right-hand sides in one
     lockstep batched FGMRES (stf_batch_solve).  bs[p]: (nrhs_p, ny, nx) or (ny, nx),
     all NumPy (host) or all complex128 CUDA tensors (device).  x0: None (zero),
@@ -419,7 +439,7 @@ def batch_solve(ctx, problems, bs, xs=None, tol=1e-10, restart=10, max_iter=500,
         bptr[p], xptr[p] = pb_.value, px_.value
     probs = (C.c_void_p * n)(*[pb.handle.value for pb in problems])
     nrhs = (C.c_int32 * n)(*nr)
-    opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, 1, 0)
+    opts = _abi.SolveOpts(float(tol), int(restart), int(max_iter), mode, 1, 0, _order(order))
     infos = [(_abi.SolveInfo * nr[p])() for p in range(n)]
     hist = [[np.zeros(history_cap, dtype=np.float64) for _ in range(nr[p])] for p in range(n)]
     for p in range(n):

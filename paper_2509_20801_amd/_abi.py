@@ -12,6 +12,7 @@ STATUS_NAMES = {0: "STF_OK", 1: "STF_EINVAL", 2: "STF_ENOMEM", 3: "STF_EDEVICE",
                 5: "STF_EPIVOT", 6: "STF_ENOCONV", 7: "STF_ENAN"}
 STF_C128, STF_C64 = 0, 1
 STF_X0_ZERO, STF_X0_USER, STF_X0_LEARNED = 0, 1, 2
+ORDERS = {"additive": 0, "rows": 1, "rows_cols": 2, "diagonal": 3}
 KERNEL_CLASSES = ["assemble", "stencil", "front_asm", "front_lu", "sweep_fwd", "sweep_bwd",
                   "scatter", "arnoldi", "update", "nn"]
 
@@ -27,7 +28,8 @@ class Params(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
-                ("x0_mode", C.c_int32), ("rounds", C.c_int32), ("debug_fault", C.c_int32)]
+                ("x0_mode", C.c_int32), ("rounds", C.c_int32), ("debug_fault", C.c_int32),
+                ("order", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -76,6 +78,7 @@ EXPORTS = {
                                        C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
     "stf_line_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_int32, C.POINTER(C.c_double)]),
+    "stf_sweep_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_batch_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int, C.POINTER(SolveOpts), C.c_void_p]),
     "stf_problem_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),

@@ -174,9 +174,22 @@ struct Timed {
 // device arrays.  Problem p's nodes are the segment [gbase[p], gbase[p] + nx*ny)
 // of concatenated global vectors; the fronts of all problems are ordered by tree
 // level (largest first within a level), so one launch per level serves them all.
+// Stages of a sweeping order over a set: stage t holds, for every problem,
+// that problem's stage t (problems with fewer stages contribute nothing).
+struct SweepPlan {
+  int nstage = 0;
+  std::vector<int> s_first, s_count;          // per stage: its members in slist
+  std::vector<std::vector<Level>> lv;         // per stage and depth: range in flist
+  DBuf slist, flist, inst;                    // members, front instances, membership flags
+};
+
 struct Mf {
   int prec = STF_C128;
   int nprob = 0, nsub = 0, max_depth = -1, max_nx = 0, max_ny = 0;
+  int max_oxl = 0, max_oyl = 0, max_ixl = 0, max_iyl = 0;   // largest Omega_k and I_k boxes
+  std::vector<int> sub_prob, sub_kx, sub_ky, prob_px, prob_py;   // host copies for the stages
+  std::vector<int> front_sub, front_depth;                        // per front instance
+  std::map<int, std::unique_ptr<SweepPlan>> sweeps;              // by order
   int64_t n_fronts = 0, fac_elems = 0, lpk_elems = 0, upk_elems = 0, vec_elems = 0,
           piv_elems = 0, u_elems = 0;
   std::vector<Level> levels;     // by depth
@@ -215,7 +228,7 @@ struct Mf {
 // problem p at node offset gbase[p] of the global vectors; allocates the
 // factors and the workspaces of one right-hand side.
 void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<long long>& gbase,
-              int prec, hipStream_t st) {
+              int prec, hipStream_t st, const std::vector<int>& gc_off = {}) {
   mf.prec = prec;
   mf.nprob = (int)plans.size();
   // Subdomains of every problem (problem after problem) and their local coefficients.
@@ -236,7 +249,10 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
     g.cx_off = (int)cvx.size();
     g.cy_off = (int)cvy.size();
     g.gbase = gbase[pi];
+    g.gc_off = gc_off.empty() ? 0 : gc_off[pi];
     sc.push_back(g);
+    mf.prob_px.push_back(pl.prm.px);
+    mf.prob_py.push_back(pl.prm.py);
     cvx.insert(cvx.end(), pl.cover_x.begin(), pl.cover_x.end());
     cvy.insert(cvy.end(), pl.cover_y.begin(), pl.cover_y.end());
     mf.max_nx = std::max(mf.max_nx, pl.prm.nx);
@@ -261,6 +277,13 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
       d.u_off = uoff;
       uoff += (long long)s.nxl * s.nyl;
       sd.push_back(d);
+      mf.sub_prob.push_back(pi);
+      mf.sub_kx.push_back(s.kx);
+      mf.sub_ky.push_back(s.ky);
+      mf.max_oxl = std::max(mf.max_oxl, s.nxl);
+      mf.max_oyl = std::max(mf.max_oyl, s.nyl);
+      mf.max_ixl = std::max(mf.max_ixl, s.ix1 - s.ix0);
+      mf.max_iyl = std::max(mf.max_iyl, s.iy1 - s.iy0);
     }
   }
   mf.nsub = (int)sd.size();
@@ -385,6 +408,12 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
     }
   }
   mf.n_fronts = (int64_t)fr.size();
+  mf.front_sub.resize(fr.size());
+  mf.front_depth.resize(fr.size());
+  for (size_t t = 0; t < order.size(); ++t) {
+    mf.front_sub[t] = recs[order[t]].sub;
+    mf.front_depth[t] = recs[order[t]].depth;
+  }
   mf.fac_elems = fac_off;
   mf.vec_elems = vec_off;
   mf.piv_elems = piv_off;
@@ -431,6 +460,7 @@ struct stf_problem_s {
   DBuf keps, gcoef, flag;
   DBuf partial, npartial, scal;    // reduction scratch, device scalars
   DBuf kV, kZ, kw, kr, kH, kcs, ksn, kg, ky, kh1, kh2, kt, kt2;
+  DBuf ksr;                        // stage residuals of a staged order (one vector per slot)
   DBuf hb, hx, cells;              // staging for host inputs
   int krylov_m = 0, krylov_nr = 0;
   // Phase timers: [0, 1] the last factorisation, [2, 3] a solve group, [4 + 2 s, 5 + 2 s]
@@ -468,7 +498,8 @@ struct stf_problem_s {
   int max_depth() const { return mf ? mf->max_depth : -1; }
   int64_t device_bytes() const {
     const DBuf* all[] = {&keps, &gcoef, &flag, &partial, &npartial, &scal, &kV, &kZ, &kw, &kr,
-                         &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &hb, &hx, &cells};
+                         &kH, &kcs, &ksn, &kg, &ky, &kh1, &kh2, &kt, &kt2, &ksr, &hb, &hx,
+                         &cells};
     int64_t t = 0;
     for (const DBuf* d : all) t += (int64_t)d->bytes;
     return t + (mf ? mf->device_bytes() : 0);
@@ -662,6 +693,143 @@ void precond_mf(stf_ctx c, Mf& mf, const RhsSet& r, const int* pact = nullptr) {
   precond_launch<T>(c, mf, r, mf.vec.as<T>(), mf.u.as<T>(), true, pact);
 }
 
+// Stages of problem p (subdomain k = ky * px + kx of that problem) for a
+// sweeping order: 1 symmetric rows, 2 symmetric rows then symmetric columns,
+// 3 four diagonal sweeps (kx + ky rising and falling, then kx + (py-1-ky)
+// rising and falling).
+std::vector<std::vector<int>> order_stages(int order, int px, int py) {
+  std::vector<std::vector<int>> rows(py), cols(px), out;
+  for (int ky = 0; ky < py; ++ky)
+    for (int kx = 0; kx < px; ++kx) {
+      rows[ky].push_back(ky * px + kx);
+      cols[kx].push_back(ky * px + kx);
+    }
+  auto there_and_back = [&](const std::vector<std::vector<int>>& seq) {
+    for (size_t i = 0; i < seq.size(); ++i) out.push_back(seq[i]);
+    for (int i = (int)seq.size() - 2; i >= 0; --i) out.push_back(seq[i]);
+  };
+  if (order == STF_ORDER_ROWS) {
+    there_and_back(rows);
+  } else if (order == STF_ORDER_ROWS_COLS) {
+    there_and_back(rows);
+    there_and_back(cols);
+  } else if (order == STF_ORDER_DIAGONAL) {
+    const int nd = px + py - 1;
+    std::vector<std::vector<int>> d1(nd), d2(nd);
+    for (int ky = 0; ky < py; ++ky)
+      for (int kx = 0; kx < px; ++kx) {
+        d1[kx + ky].push_back(ky * px + kx);
+        d2[kx + (py - 1 - ky)].push_back(ky * px + kx);
+      }
+    there_and_back(d1);
+    there_and_back(d2);
+  } else {
+    throw Error(STF_EINVAL, "unknown sweeping order");
+  }
+  return out;
+}
+
+const SweepPlan& sweep_plan(Mf& mf, int order, hipStream_t st) {
+  auto it = mf.sweeps.find(order);
+  if (it != mf.sweeps.end()) return *it->second;
+  std::unique_ptr<SweepPlan> sp(new SweepPlan());
+  // first subdomain of every problem
+  std::vector<int> sub0(mf.nprob, -1);
+  for (int k = 0; k < mf.nsub; ++k)
+    if (sub0[mf.sub_prob[k]] < 0) sub0[mf.sub_prob[k]] = k;
+  std::vector<std::vector<std::vector<int>>> per(mf.nprob);
+  int nst = 0;
+  for (int p = 0; p < mf.nprob; ++p) {
+    per[p] = order_stages(order, mf.prob_px[p], mf.prob_py[p]);
+    nst = std::max(nst, (int)per[p].size());
+  }
+  // front instances of every subdomain by depth (level order, largest first)
+  const int nd = mf.max_depth + 1;
+  std::vector<std::vector<std::vector<int>>> fsd(mf.nsub, std::vector<std::vector<int>>(nd));
+  for (size_t t = 0; t < mf.front_sub.size(); ++t) fsd[mf.front_sub[t]][mf.front_depth[t]].push_back((int)t);
+  std::vector<int> slist, flist, inst((size_t)nst * mf.nsub, 0);
+  sp->nstage = nst;
+  sp->lv.assign(nst, std::vector<Level>(nd));
+  for (int t = 0; t < nst; ++t) {
+    std::vector<int> mem;
+    for (int p = 0; p < mf.nprob; ++p)
+      if (t < (int)per[p].size())
+        for (int k : per[p][t]) mem.push_back(sub0[p] + k);
+    sp->s_first.push_back((int)slist.size());
+    sp->s_count.push_back((int)mem.size());
+    slist.insert(slist.end(), mem.begin(), mem.end());
+    for (int k : mem) inst[(size_t)t * mf.nsub + k] = 1;
+    for (int d = 0; d < nd; ++d) {
+      std::vector<int> fl;
+      for (int k : mem) fl.insert(fl.end(), fsd[k][d].begin(), fsd[k][d].end());
+      // largest first: instance order within a level is by descending order m
+      std::sort(fl.begin(), fl.end());
+      Level L = mf.levels[d];
+      L.off = (int)flist.size();
+      L.n = (int)fl.size();
+      sp->lv[t][d] = L;
+      flist.insert(flist.end(), fl.begin(), fl.end());
+    }
+  }
+  upload(sp->slist, slist, st);
+  upload(sp->flist, flist, st);
+  upload(sp->inst, inst, st);
+  HIP_CHECK(hipStreamSynchronize(st));
+  const SweepPlan& ref = *sp;
+  mf.sweeps[order] = std::move(sp);
+  return ref;
+}
+
+// One application of the staged order for the right-hand sides of r:
+// z_s = 0, then for every stage r_s = v_s - A z_s on its own boxes (skipped for
+// the first stage, where z = 0), its sweeps, z_s += its full local fields.
+// keps / gc: the set's concatenated node permittivity and coupling arrays;
+// rbuf: one global vector per slot (rstride apart) for the stage residuals.
+template <typename T>
+void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u,
+                  const double2* keps, const double2* gc, double2* rbuf, long long rstride,
+                  long long zlen, bool timed, const int* pact = nullptr) {
+  hipStream_t st = c->stream;
+  stf_ctx tc = timed ? c : nullptr;
+  r.vec_stride = mf.vec_elems;
+  r.u_stride = mf.u_elems;
+  for (int s = 0; s < r.nr; ++s) launch_zero(st, r.z[s], zlen);
+  const T* lpk = mf.lpk.as<T>();
+  const int* sl = sp.slist.as<int>();
+  for (int t = 0; t < sp.nstage; ++t) {
+    const int sf = sp.s_first[t], sc = sp.s_count[t];
+    RhsSet rr = r;
+    if (t > 0) {
+      Timed tm(tc, K_STENCIL);
+      launch_stage_residual(st, keps, gc, mf.subs.as<SubDev>(), mf.scat.as<ScatDev>(), sl, sf, sc,
+                            mf.max_ixl, mf.max_iyl, pact, r, rbuf, rstride);
+      for (int s = 0; s < r.nr; ++s) rr.v[s] = rbuf + s * rstride;
+    }
+    for (int d = mf.max_depth; d >= 0; --d) {
+      if (sp.lv[t][d].n == 0) continue;
+      Timed tm(tc, K_SWEEP_FWD);
+      LevelArgs la = mf.level_args(d, nullptr, pact);
+      la.flist = sp.flist.as<int>();
+      la.first = sp.lv[t][d].off;
+      la.nlevel = sp.lv[t][d].n;
+      launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, rr);
+    }
+    for (int d = 0; d <= mf.max_depth; ++d) {
+      if (sp.lv[t][d].n == 0) continue;
+      Timed tm(tc, K_SWEEP_BWD);
+      LevelArgs la = mf.level_args(d, nullptr, pact);
+      la.flist = sp.flist.as<int>();
+      la.first = sp.lv[t][d].off;
+      la.nlevel = sp.lv[t][d].n;
+      launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, rr);
+    }
+    Timed tm(tc, K_SCATTER);
+    launch_stage_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.scat.as<ScatDev>(), mf.cover_x.as<int4>(),
+                            mf.cover_y.as<int4>(), sl, sf, sc, mf.max_oxl, mf.max_oyl,
+                            sp.inst.as<int>() + (size_t)t * mf.nsub, pact, r);
+  }
+}
+
 // Entries of the front vectors and of the local fields of one right-hand side
 // (from the host plan: a set's vec_elems and u_elems), and the bytes of that
 // workspace with the local fields at a 256-byte boundary.
@@ -681,7 +849,29 @@ size_t round_workspace_bytes(const Plan& pl, int prec) {
   return ((a + 255) & ~size_t(255)) + (size_t)u * es;
 }
 
-void precond_set(stf_problem pb, const RhsSet& r) {
+template <typename T>
+void sweep_problem(stf_problem pb, const RhsSet& r, int order) {
+  Mf& mf = *pb->mf;
+  const SweepPlan& sp = sweep_plan(mf, order, pb->ctx->stream);
+  if (mf.ws_nr < r.nr) {
+    mf.vec.alloc((size_t)mf.vec_elems * sizeof(T) * r.nr);
+    mf.u.alloc((size_t)mf.u_elems * sizeof(T) * r.nr);
+    mf.ws_nr = r.nr;
+  }
+  pb->ksr.alloc((size_t)pb->N * sizeof(double2) * r.nr);
+  sweep_launch<T>(pb->ctx, mf, sp, r, mf.vec.as<T>(), mf.u.as<T>(), pb->keps.as<double2>(),
+                  pb->gcoef.as<double2>(), pb->ksr.as<double2>(), pb->N, pb->N, true);
+}
+
+// One preconditioner application for the right-hand sides of r in `order`.
+void precond_set(stf_problem pb, const RhsSet& r, int order = STF_ORDER_ADDITIVE) {
+  if (order != STF_ORDER_ADDITIVE) {
+    if (pb->prec == STF_C64)
+      sweep_problem<float2>(pb, r, order);
+    else
+      sweep_problem<double2>(pb, r, order);
+    return;
+  }
   if (pb->prec == STF_C64)
     precond_mf<float2>(pb->ctx, *pb->mf, r);
   else
@@ -1127,7 +1317,7 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
         rs.v[i] = R[cur[i]].V + (long long)j * N;
         rs.z[i] = R[cur[i]].Z + (long long)j * N;
       }
-      precond_set(pb, rs);
+      precond_set(pb, rs, o.order);
     } else {
       for (int s : cur)
         precond_rounds(pb, R[s].V + (long long)j * N, R[s].Z + (long long)j * N, rounds);
@@ -1352,14 +1542,14 @@ struct BatchState {
   std::vector<SysDev> hsys;
   DBuf sysd, tsys, bsys[4];
   int ntiles = 0, nblk[4] = {0, 0, 0, 0};
-  DBuf V, Z, W, R, X, B;
+  DBuf V, Z, W, R, X, B, RS;      // RS: stage residuals of a staged order
   DBuf H, g, y, h1, h2, cs, sn, sc, act, cyc, kcol, it, rg, pact, hist;
   DBuf part, npart, spart;
   double* status = nullptr;       // pinned, device-visible: 4 doubles per system
   double* status_dev = nullptr;
   hipGraphExec_t graph = nullptr;
   double graph_tol = -1.0;
-  int graph_max_iter = -1;
+  int graph_max_iter = -1, graph_order = -1;
   hipEvent_t ev[4] = {};          // [0, 1] factorisation, [2, 3] a slot group's solve
   hipStream_t cap = nullptr;      // capture stream
 
@@ -1404,15 +1594,15 @@ BatchState& batch_state(stf_ctx c, int nprob, const stf_problem* probs) {
     off += (probs[p]->N + 63) / 64 * 64;          // segments start on 1 KiB boundaries
   }
   b->ntot = off;
-  build_mf(b->mf, plans, b->gbase, b->prec, st);
-  b->keps.alloc((size_t)b->ntot * sizeof(double2));
-  HIP_CHECK(hipMemsetAsync(b->keps.p, 0, (size_t)b->ntot * sizeof(double2), st));
   long long gcn = 0;
   for (int p = 0; p < nprob; ++p) {
     b->gc_off.push_back((int)gcn);
     gcn += 2LL * probs[p]->prm.nx + 2LL * probs[p]->prm.ny;
   }
   STF_REQUIRE(gcn < (1LL << 31), "batch too large for int32 coupling offsets");
+  build_mf(b->mf, plans, b->gbase, b->prec, st, b->gc_off);
+  b->keps.alloc((size_t)b->ntot * sizeof(double2));
+  HIP_CHECK(hipMemsetAsync(b->keps.p, 0, (size_t)b->ntot * sizeof(double2), st));
   b->gc.alloc((size_t)gcn * sizeof(double2));
   for (int p = 0; p < nprob; ++p) {
     HIP_CHECK(hipMemcpyAsync(b->keps.as<double2>() + b->gbase[p], probs[p]->keps.p,
@@ -1491,11 +1681,13 @@ void batch_systems(BatchState& b, const int32_t* nrhs, int slot0, int nslot, int
   const size_t vb = (size_t)b.T * sizeof(double2);
   b.V.alloc(vb * (m + 1));
   b.Z.alloc(vb * m);
+  b.RS.alloc(vb);
   b.W.alloc(vb);
   b.R.alloc(vb);
   b.X.alloc(vb);
   b.B.alloc(vb);
-  for (DBuf* d : {&b.V, &b.Z, &b.W, &b.R, &b.X, &b.B}) HIP_CHECK(hipMemsetAsync(d->p, 0, d->bytes, st));
+  for (DBuf* d : {&b.V, &b.Z, &b.W, &b.R, &b.X, &b.B, &b.RS})
+    HIP_CHECK(hipMemsetAsync(d->p, 0, d->bytes, st));
   const int hs = m + 1;
   b.H.alloc(sizeof(double2) * hs * m * nsys);
   b.g.alloc(sizeof(double2) * hs * nsys);
@@ -1532,7 +1724,7 @@ void batch_residual(stf_ctx c, BatchState& b, const int* gate, int dst) {
 // decision), m iterations gated by act, update and true residual of the
 // systems of the cycle, status to pinned host memory.
 template <typename T>
-void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter) {
+void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order) {
   hipStream_t st = c->stream;
   const int m = b.m, hs = m + 1, nsys = b.nsys;
   const SysDev* sys = b.sysd.as<SysDev>();
@@ -1555,7 +1747,13 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter) {
       rs.v[k] = V + (long long)j * Tn + (long long)k * b.ntot;
       rs.z[k] = Z + (long long)j * Tn + (long long)k * b.ntot;
     }
-    precond_launch<T>(c, b.mf, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), false, b.pact.as<int>());
+    if (order == STF_ORDER_ADDITIVE) {
+      precond_launch<T>(c, b.mf, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), false, b.pact.as<int>());
+    } else {
+      const SweepPlan& sp = sweep_plan(b.mf, order, st);
+      sweep_launch<T>(c, b.mf, sp, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), b.keps.as<double2>(),
+                      b.gc.as<double2>(), b.RS.as<double2>(), b.ntot, b.ntot, false, b.pact.as<int>());
+    }
     launch_bstencil(st, 0, Z + (long long)j * Tn, nullptr, W, b.keps.as<double2>(), b.gc.as<double2>(),
                     sys, b.tsys.as<int>(), b.ntiles, act, nullptr);
     // Classical Gram-Schmidt with the device-gated second pass, as in the solo solve.
@@ -1591,19 +1789,20 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter) {
 // The cycle as a HIP graph (captured on the batch's own stream, replayed on the
 // context stream); rebuilt when the systems, m, tol or max_iter change.
 template <typename T>
-void batch_run_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, bool use_graph) {
+void batch_run_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order, bool use_graph) {
+  if (order != STF_ORDER_ADDITIVE) sweep_plan(b.mf, order, c->stream);   // built outside a capture
   if (!use_graph) {
-    batch_cycle<T>(c, b, tol, max_iter);
+    batch_cycle<T>(c, b, tol, max_iter, order);
     return;
   }
-  if (!b.graph || b.graph_tol != tol || b.graph_max_iter != max_iter) {
+  if (!b.graph || b.graph_tol != tol || b.graph_max_iter != max_iter || b.graph_order != order) {
     b.release_graph();
     hipStream_t keep = c->stream;
     c->stream = b.cap;
     hipGraph_t gr = nullptr;
     HIP_CHECK(hipStreamBeginCapture(b.cap, hipStreamCaptureModeRelaxed));
     try {
-      batch_cycle<T>(c, b, tol, max_iter);
+      batch_cycle<T>(c, b, tol, max_iter, order);
     } catch (...) {
       (void)hipStreamEndCapture(b.cap, &gr);
       if (gr) (void)hipGraphDestroy(gr);
@@ -1617,6 +1816,7 @@ void batch_run_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, bool us
     HIP_CHECK(e);
     b.graph_tol = tol;
     b.graph_max_iter = max_iter;
+    b.graph_order = order;
   }
   HIP_CHECK(hipGraphLaunch(b.graph, c->stream));
 }
@@ -1737,7 +1937,7 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
       bool any = false;
       for (int s = 0; s < nsys; ++s) any = any || running(s);
       if (!any) break;
-      batch_run_cycle<T>(c, bs, o.tol, o.max_iter, graph);
+      batch_run_cycle<T>(c, bs, o.tol, o.max_iter, o.order, graph);
       HIP_CHECK(hipStreamSynchronize(st));
       bool progress = false;
       for (int s = 0; s < nsys; ++s) {
@@ -2191,6 +2391,37 @@ stf_status stf_precond_apply_batch(stf_problem pb, int32_t nrhs, const double* v
   });
 }
 
+stf_status stf_sweep_apply(stf_problem pb, int32_t order, const double* v, double* z,
+                           int on_device) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(v && z, "null argument");
+    STF_REQUIRE(order >= STF_ORDER_ADDITIVE && order <= STF_ORDER_DIAGONAL,
+                "unknown source-transfer order");
+    if (!pb->factored) throw Error(STF_ESTATE, "precond before factor");
+    hipStream_t st = pb->ctx->stream;
+    const size_t vb = (size_t)pb->N * sizeof(double2);
+    RhsSet r;
+    r.nr = 1;
+    if (on_device) {
+      r.v[0] = reinterpret_cast<const double2*>(v);
+      r.z[0] = reinterpret_cast<double2*>(z);
+    } else {
+      pb->hb.alloc(vb);
+      pb->hx.alloc(vb);
+      HIP_CHECK(hipMemcpyAsync(pb->hb.p, v, vb, hipMemcpyHostToDevice, st));
+      r.v[0] = pb->hb.as<double2>();
+      r.z[0] = pb->hx.as<double2>();
+    }
+    precond_set(pb, r, order);
+    HIP_CHECK(hipGetLastError());
+    if (!on_device) {
+      HIP_CHECK(hipMemcpyAsync(z, pb->hx.p, vb, hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipStreamSynchronize(st));
+    }
+  });
+}
+
 stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                      const stf_solve_opts* opts, stf_solve_info* info) {
   if (!pb) return STF_EINVAL;
@@ -2207,6 +2438,10 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
                 "x0_mode invalid");
     STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
     STF_REQUIRE(opts->debug_fault == 0 || opts->debug_fault == 1, "debug_fault must be 0 or 1");
+    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_DIAGONAL,
+                "unknown source-transfer order");
+    STF_REQUIRE(opts->rounds <= 1 || opts->order == STF_ORDER_ADDITIVE,
+                "several rounds per application need the additive order");
     if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
     if (opts->debug_fault == 1) {
       perturbed = factor_problem(pb, true) != 0;
@@ -2275,6 +2510,8 @@ stf_status stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,
                 "x0_mode invalid");
     STF_REQUIRE(opts->rounds <= 1, "a batched solve takes one source-transfer round per application");
     STF_REQUIRE(opts->debug_fault == 0, "debug_fault is not available in a batched solve");
+    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_DIAGONAL,
+                "unknown source-transfer order");
     for (int p = 0; p < nprob; ++p) {
       STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
       STF_REQUIRE(probs[p]->assembled, "problem not assembled");

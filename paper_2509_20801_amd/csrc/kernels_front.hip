@@ -954,7 +954,7 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;                          // whole wavefront
-  const FrontDev f = a.fronts[a.first + fi];
+  const FrontDev f = a.fronts[a.flist ? a.flist[a.first + fi] : a.first + fi];
   if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
   const int m = f.p + f.q, p = f.p;
   const T* L = lpk + f.lpk_off;
@@ -1050,7 +1050,7 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
   if (fi >= a.nlevel) return;
-  const FrontDev f = a.fronts[a.first + fi];
+  const FrontDev f = a.fronts[a.flist ? a.flist[a.first + fi] : a.first + fi];
   if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
   const int m = f.p + f.q, p = f.p, q = f.q;
   const T* U = upk + f.upk_off;
@@ -1129,7 +1129,7 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
   T* vl = scr + NR * NTL;                                  // NR x max_m
   T* tmp = vl + NR * a.max_m;                              // NR x max_m
   const int mm = a.max_m;
-  const FrontDev f = a.fronts[a.first + blockIdx.x];
+  const FrontDev f = a.fronts[a.flist ? a.flist[a.first + blockIdx.x] : a.first + blockIdx.x];
   if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole workgroup)
   const int m = f.p + f.q, p = f.p;
   const T* L = lpk + f.lpk_off;
@@ -1276,7 +1276,7 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   T* scr = reinterpret_cast<T*>(smem_raw);                 // NR x NTL
   T* vl = scr + NR * NTL;                                  // NR x max_m
   const int mm = a.max_m;
-  const FrontDev f = a.fronts[a.first + blockIdx.x];
+  const FrontDev f = a.fronts[a.flist ? a.flist[a.first + blockIdx.x] : a.first + blockIdx.x];
   if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole workgroup)
   const int m = f.p + f.q, p = f.p;
   const T* U = upk + f.upk_off;                            // packed [U11^{-1} V']
@@ -1415,6 +1415,102 @@ __global__ __launch_bounds__(256) void k_scatter(const T* __restrict__ u, const 
   }
 #pragma unroll
   for (int r = 0; r < NR; ++r) rs.z[r][P.gbase + (long long)j * nx + i] = acc[r];
+}
+
+// ---------------------------------------------------------------------------
+// Staged (multiplicative) order of the round.  A stage solves its subdomains
+// with the residual the earlier stages left: r = v - A z on their own boxes I_k
+// (disjoint), the usual sweeps on their fronts only, then z += sum of their
+// full local fields.  Blocks of 64 x 4 nodes, blockIdx.z = the stage member.
+// ---------------------------------------------------------------------------
+template <int NR>
+__global__ __launch_bounds__(256) void k_stage_residual(const double2* __restrict__ keps,
+                                                        const double2* __restrict__ gc,
+                                                        const SubDev* __restrict__ subs,
+                                                        const ScatDev* __restrict__ probs,
+                                                        const int* __restrict__ slist, int sfirst,
+                                                        const int* __restrict__ pact, RhsSet rs,
+                                                        double2* __restrict__ rbuf,
+                                                        long long rstride) {
+  const SubDev S = subs[slist[sfirst + blockIdx.z]];
+  if (pact && pact[S.prob] == 0) return;
+  const int gx = S.ix0 + blockIdx.x * 64 + threadIdx.x;
+  const int gy = S.iy0 + blockIdx.y * 4 + threadIdx.y;
+  if (gx >= S.ix1 || gy >= S.iy1) return;
+  const ScatDev P = probs[S.prob];
+  const int nx = P.nx, ny = P.ny;
+  const double2* cxw = gc + P.gc_off;
+  const double2* cxe = cxw + nx;
+  const double2* cyw = cxe + nx;
+  const double2* cye = cyw + ny;
+  const long long n = P.gbase + (long long)gy * nx + gx;
+  const double2 aw = cxw[gx], ae = cxe[gx], as = cyw[gy], an = cye[gy];
+  const double2 ke = keps[n];
+  const double2 dg = make_double2(ke.x - ((aw.x + ae.x) + (as.x + an.x)),
+                                  ke.y - ((aw.y + ae.y) + (as.y + an.y)));
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const double2* z = rs.z[s];
+    double2 acc = cmul(dg, z[n]);
+    if (gx > 0) acc = cfma(aw, z[n - 1], acc);
+    if (gx < nx - 1) acc = cfma(ae, z[n + 1], acc);
+    if (gy > 0) acc = cfma(as, z[n - nx], acc);
+    if (gy < ny - 1) acc = cfma(an, z[n + nx], acc);
+    rbuf[s * rstride + n] = csub(rs.v[s][n], acc);
+  }
+}
+
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_stage_scatter(const T* __restrict__ u,
+                                                       const SubDev* __restrict__ subs,
+                                                       const ScatDev* __restrict__ probs,
+                                                       const int4* __restrict__ cover_x,
+                                                       const int4* __restrict__ cover_y,
+                                                       const int* __restrict__ slist, int sfirst,
+                                                       const int* __restrict__ inst,
+                                                       const int* __restrict__ pact, RhsSet rs) {
+  const int k = slist[sfirst + blockIdx.z];
+  const SubDev S = subs[k];
+  if (pact && pact[S.prob] == 0) return;
+  const int gx = S.ox0 + blockIdx.x * 64 + threadIdx.x;
+  const int gy = S.oy0 + blockIdx.y * 4 + threadIdx.y;
+  if (gx >= S.ox0 + S.nxl || gy >= S.oy0 + S.nyl) return;
+  const ScatDev P = probs[S.prob];
+  const int4 cx = cover_x[P.cx_off + gx], cy = cover_y[P.cy_off + gy];
+  const int kys[2] = {cy.x, cy.z}, uys[2] = {cy.y, cy.w};
+  const int kxs[2] = {cx.x, cx.z}, txs[2] = {cx.y, cx.w};
+  // The stage members covering this node; the lowest one adds them all.
+  int mem[4], loc[4], cnt = 0, low = 1 << 30;
+#pragma unroll
+  for (int b = 0; b < 2; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (kys[b] < 0 || kxs[c] < 0) continue;
+      const int kk = P.sub0 + kys[b] * P.px + kxs[c];
+      if (inst[kk] == 0) continue;
+      const SubDev& Q = subs[kk];
+      mem[cnt] = kk;
+      loc[cnt] = uys[b] * Q.nxl + txs[c];
+      low = kk < low ? kk : low;
+      ++cnt;
+    }
+  if (low != k) return;
+  const long long n = P.gbase + (long long)gy * P.nx + gx;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    double2 acc = rs.z[s][n];
+    for (int i = 0; i < cnt; ++i) {
+      const double2 v = to_d2(u[s * rs.u_stride + subs[mem[i]].u_off + loc[i]]);
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    rs.z[s][n] = acc;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero(double2* __restrict__ p, long long n) {
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256)
+    p[t] = make_double2(0.0, 0.0);
 }
 
 int g_max_lds = 0;
@@ -1686,6 +1782,42 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
 #undef STF_CALL
 }
 
+void launch_stage_residual(hipStream_t st, const double2* keps, const double2* gc,
+                           const SubDev* subs, const ScatDev* probs, const int* slist, int sfirst,
+                           int scount, int maxw, int maxh, const int* pact, const RhsSet& r,
+                           double2* rbuf, long long rstride) {
+  check_rhs(r);
+  if (scount <= 0) return;
+  dim3 blk(64, 4), grd((maxw + 63) / 64, (maxh + 3) / 4, scount);
+#define STF_CALL(NR)                                                                            \
+  hipLaunchKernelGGL((k_stage_residual<NR>), grd, blk, 0, st, keps, gc, subs, probs, slist, sfirst, \
+                     pact, r, rbuf, rstride)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
+template <typename T>
+void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const ScatDev* probs,
+                          const int4* cover_x, const int4* cover_y, const int* slist, int sfirst,
+                          int scount, int maxw, int maxh, const int* inst, const int* pact,
+                          const RhsSet& r) {
+  check_rhs(r);
+  if (scount <= 0) return;
+  dim3 blk(64, 4), grd((maxw + 63) / 64, (maxh + 3) / 4, scount);
+#define STF_CALL(NR)                                                                            \
+  hipLaunchKernelGGL((k_stage_scatter<T, NR>), grd, blk, 0, st, u, subs, probs, cover_x, cover_y, \
+                     slist, sfirst, inst, pact, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
+void launch_zero(hipStream_t st, double2* p, long long n) {
+  long long g = (n + 255) / 256;
+  if (g > 8192) g = 8192;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, st, p, n);
+}
+
 #define STF_INST(T)                                                                             \
   template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, T*, int*, int*, double); \
   template void launch_sweep_fwd<T>(hipStream_t, const LevelArgs&, const T*, const int*, T*,    \
@@ -1694,7 +1826,10 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
                                     const RhsSet&);                                             \
   template void launch_scatter<T>(hipStream_t, const T*, const SubDev*, const int4*,            \
                                   const int4*, const ScatDev*, int, int, int, const int*,       \
-                                  const RhsSet&);
+                                  const RhsSet&);                                               \
+  template void launch_stage_scatter<T>(hipStream_t, const T*, const SubDev*, const ScatDev*,   \
+                                        const int4*, const int4*, const int*, int, int, int, int,\
+                                        const int*, const int*, const RhsSet&);
 STF_INST(double2)
 STF_INST(float2)
 

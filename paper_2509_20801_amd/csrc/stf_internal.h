@@ -165,6 +165,8 @@ struct ScatDev {
   int sub0, px, nx, ny;     // first subdomain, subdomain columns, grid
   int cx_off, cy_off;       // offsets into the concatenated cover tables
   long long gbase;          // first node in global vectors
+  int gc_off;               // offset of the problem's global coupling arrays (cxw|cxe|cyw|cye)
+  int pad;
 };
 
 // Right-hand sides swept together (1..MAX_RHS): each has its own global input
@@ -237,6 +239,8 @@ struct LevelArgs {
   const double2* lcoef;         // local coupling coefficients
   const int* pact;              // sweeps: per problem, nonzero while one of its right-hand
                                 // sides is active (null = all); fronts of others are skipped
+  const int* flist;             // sweeps: front instances [first, first + nlevel) of this
+                                // list (null: the instances first .. first + nlevel - 1)
   int max_m;                    // largest front in the level
   int max_pm;                   // largest p*m in the level
   int max_p;                    // largest p in the level
@@ -261,6 +265,22 @@ template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
                     const int4* cover_y, const ScatDev* probs, int nprob, int max_nx, int max_ny,
                     const int* pact, const RhsSet& r);
+
+// Staged (multiplicative) order of the round: r_s = v_s - A z_s on the own
+// boxes I_k of the scount subdomains slist[sfirst ..) (rbuf: slot s at
+// rbuf + s * rstride), and z_s += sum over the stage of P_k u_k on their
+// extended boxes (inst[k] != 0 marks the stage's subdomains; each node is
+// added once, by its lowest covering member).  maxw x maxh bounds the boxes.
+void launch_stage_residual(hipStream_t st, const double2* keps, const double2* gc,
+                           const SubDev* subs, const ScatDev* probs, const int* slist, int sfirst,
+                           int scount, int maxw, int maxh, const int* pact, const RhsSet& r,
+                           double2* rbuf, long long rstride);
+template <typename T>
+void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const ScatDev* probs,
+                          const int4* cover_x, const int4* cover_y, const int* slist, int sfirst,
+                          int scount, int maxw, int maxh, const int* inst, const int* pact,
+                          const RhsSet& r);
+void launch_zero(hipStream_t st, double2* p, long long n);
 
 // Krylov (kernels_krylov.hip).  Vectors of n complex doubles; V holds nv vectors
 // with leading dimension ld (elements).
