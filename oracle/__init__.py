@@ -12,9 +12,17 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
   ddm.partition / local_matrix / SourceTransfer   pinned: N=1 gives A^-1,
                                  residual-support invariant, convergence of
                                  the stationary iteration to the direct solve
+  pool.PooledSourceTransfer      the round of SourceTransfer with the factors in
+                                 worker processes; pinned: equals SourceTransfer
+                                 (complex128 factors) to roundoff
   krylov.fgmres                  pinned: identity preconditioner vs SciPy's
                                  GMRES, Arnoldi relation, exact preconditioner
                                  converges in one step
+  ntff.far_field / rcs           pinned: the sampled field of a line source gives
+                                 its closed-form far field (second order in h);
+                                 vacuum scatters nothing; FDFD cylinder RCS vs the
+                                 Mie series (ntff.mie_rcs) at 20 and 40 points per
+                                 wavelength, error falling at second order
   mie                            pinned: Jacobi-Anger series of the incident
                                  wave, boundary continuity, eps = 1 gives zero
   nn (learned warm start)        pinned: truncated DFTs vs numpy.fft, every
@@ -24,4 +32,4 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
                                  network's guess is parity unpinned (no reference
                                  exists); the FP64 true residual judges it.
 """
-from . import fdfd, ddm, krylov, mie, nn  # noqa: F401
+from . import fdfd, ddm, krylov, mie, nn, ntff, pool  # noqa: F401
