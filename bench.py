@@ -386,6 +386,44 @@ def cpu_baseline(w, sample, gpu_iters):
                                                              sample["t_it"], gpu_iters, total)}
 
 
+STUDY_PARTS = [(2, 1), (2, 2), (4, 2), (4, 4), (8, 4), (8, 8)]     # N = 2 ... 64 as in Table 1
+
+
+def subdomain_study(stf, torch, ctx, tol=1e-3, fgmres_tol=1e-8):
+    """Iterations against the number of subdomains (the paper's Table 1 and
+    Fig. 5b, on a synthetic stand-in for its cylinder): a dielectric cylinder of
+    radius 3 lambda (eps 4, lambda = 20 cells, 400^2 interior + 16-cell PML, TF/SF
+    plane wave), complex128 fronts, N = px * py from 2 to 64.  Per N: rounds of
+    Algorithm 1 to the Eq. (20) threshold (overlap energy below tol of the
+    first) and to FP64 true rel-res tol (tol = 1e-3, the discretisation-level
+    accuracy the paper iterates to), and FGMRES iterations to rel-res
+    fgmres_tol."""
+    import workloads
+    w = workloads.configs.cylinder_tfsf(interior=400, pml=16, lam=20.0, radius_lam=3.0,
+                                        subcells=8)
+    eps = torch.from_numpy(w.eps_cells).cuda()
+    b = torch.from_numpy(w.b[0]).cuda()
+    rows = []
+    for px, py in STUDY_PARTS:
+        pb = stf.Problem(ctx, dict(params_of(w, stf.STF_C128), px=px, py=py), eps)
+        pb.factor()
+        x = torch.empty_like(b)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, i20 = pb.stationary_solve(b, x=x, tol=tol, max_rounds=300, stop="overlap")
+        torch.cuda.synchronize()
+        t20 = time.perf_counter() - t0
+        _, ires = pb.stationary_solve(b, x=x, tol=tol, max_rounds=300)
+        _, ig = pb.solve(b, x=x, tol=fgmres_tol, restart=30, max_iter=400)
+        rows.append({"N": px * py, "px": px, "py": py, "rounds_eq20": i20["rounds"],
+                     "relres_at_eq20": round(i20["relres_true"], 12),
+                     "rounds_residual": ires["rounds"], "fgmres_iters": ig[0]["iters"],
+                     "eq20_solve_ms": round(t20 * 1e3, 2)})
+        pb.close()
+    return {"workload": "cylinder r = 3 lambda, eps 4, 432^2, lambda = 20 cells",
+            "stationary_tol": tol, "fgmres_tol": fgmres_tol, "rows": rows}
+
+
 def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagonal", count=48):
     """The batched workload: `count` disk problems, four right-hand sides each,
     factored and solved by stf_batch_solve (complex64 fronts)."""
@@ -507,6 +545,7 @@ def main():
                                      "ms_per_step": round(t_b * 1e3, 3),
                                      "iters": [i["iters"] for i in inf_b[-1]]}
         out["stationary"] = stationary_form(stf, torch, ctx, w, stf.STF_C64, args.tol, 200)
+        out["subdomain_study"] = subdomain_study(stf, torch, ctx)
     if not args.no_batched:
         out["batched_disks"] = batched_disks(stf, torch, ctx, 1, args.tol, 20, 1500)
     out["device_bytes"] = info["device_bytes"]

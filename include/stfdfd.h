@@ -213,19 +213,27 @@ stf_status  stf_factor(stf_problem pb);
  * info: array of nrhs (may be NULL).  Returns the worst per-RHS status. */
 stf_status  stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                       const stf_solve_opts* opts, stf_solve_info* info);
+/* Stop rules of the stationary iteration: the FP64 true relative residual
+ * |b - A x| / |b| <= tol, or Eq. (20): the summed 2-norms of the subdomains'
+ * local fields on their overlapping regions (Omega_k outside I_k, the fields
+ * E^F that the round transfers) fall below tol times the same sum after the
+ * initial local solves (Eq. (20) with its TOL taken relative to that scale). */
+enum { STF_STOP_RESIDUAL = 0, STF_STOP_OVERLAP = 1 };
+
 /* Algorithm 1 as the paper runs it: a stationary iteration of source-transfer
  * rounds (Sec. 2.3).  x_0 = B b (the initial local solves, Eq. (14)), then
  * x <- x + B (b - A x) (the transferred sources of Eqs. (18)-(19) solved
- * locally and summed as in Eq. (21)), until the FP64 true relative residual
- * |b - A x| / |b| <= tol or max_rounds rounds after x_0 (0 <= max_rounds <=
- * 100000).  b, x: ny*nx complex, host or device (on_device).  hist (host, may
- * be NULL): max_rounds + 1 doubles, the relative residual of x_0 and of every
- * round taken.  *rounds_out (may be NULL): rounds taken after x_0.  Returns
- * STF_ENOCONV when tol was not reached (x, hist, *rounds_out still written),
- * STF_ENAN on a non-finite residual, STF_ESTATE before stf_factor. */
+ * locally and summed as in Eq. (21)), until the stop rule `stop` (STF_STOP_*)
+ * holds or max_rounds rounds after x_0 (0 <= max_rounds <= 100000).  b, x:
+ * ny*nx complex, host or device (on_device).  hist, hist_energy (host, each
+ * may be NULL): max_rounds + 1 doubles, the relative residual, resp. the
+ * overlap energy of Eq. (20), of x_0 and of every round taken.  *rounds_out
+ * (may be NULL): rounds taken after x_0.  Returns STF_ENOCONV when the rule
+ * was not met (x, the histories, *rounds_out still written), STF_ENAN on a
+ * non-finite value, STF_ESTATE before stf_factor. */
 stf_status  stf_stationary_solve(stf_problem pb, const double* b, double* x, int on_device,
-                                 double tol, int32_t max_rounds, double* hist,
-                                 int32_t* rounds_out);
+                                 double tol, int32_t max_rounds, int32_t stop, double* hist,
+                                 double* hist_energy, int32_t* rounds_out);
 /* Time-averaged power through a grid line, the line integral
  * U = 1/2 int_l Re(E x H*) of Sec. 3.2 for E = E_z z, with H from Faraday's law
  * (exp(+j w t), w mu = k0, fields normalised so that eta0 = 1):
@@ -238,6 +246,21 @@ stf_status  stf_stationary_solve(stf_problem pb, const double* b, double* x, int
  * complex field, host or device (on_device); *out (host): the power. */
 stf_status  stf_line_flux(stf_problem pb, const double* e, int on_device, int32_t axis,
                           int32_t index, int32_t lo, int32_t hi, double* out);
+/* Radar cross section (2D scattering width) by the near-to-far-field transform,
+ * the quantity the paper compares with the Mie series (Sec. 3.1, Fig. 5a).  e:
+ * the SCATTERED field (ny*nx complex, host or device), e.g. the solution of the
+ * scattered-field source of Eq. (7), for a unit incident wave.  The contour is
+ * the rectangle through the half-node lines x = (box[0] + 1/2) dx,
+ * (box[1] + 1/2) dx, y = (box[2] + 1/2) dy, (box[3] + 1/2) dy (0 <= box[0] <
+ * box[1] < nx - 1, likewise y); it must enclose every scatterer and source and
+ * lie outside the PML.  With u the mean of the two node lines an edge
+ * separates and du/dn their difference over the step (outward), F(phi) =
+ * sum [du/dn - j k0 (rhat . n) u] exp(j k0 rhat . r) dl by the midpoint rule
+ * (Green's representation with the outgoing Hankel function, exp(+j w t)), and
+ * sigma(phi) = |F|^2 / (4 k0), phi measured from +x.  phis: nang angles (host);
+ * sigma: nang doubles (host); F: 2 nang doubles (host, interleaved, may be NULL). */
+stf_status  stf_rcs(stf_problem pb, const double* e, int on_device, const int32_t* box, int32_t nang,
+                    const double* phis, double* sigma, double* F);
 /* y = A x with the global FP64 operator (Eqs. (2), (9)).  x, y: ny*nx complex. */
 stf_status  stf_apply(stf_problem pb, const double* x, double* y, int on_device);
 /* One source-transfer round z = sum_k P_k A_k^{-1} R_k^I v (Eqs. (14), (21)):

@@ -142,6 +142,36 @@ class SourceTransfer:
         return z.ravel()
 
 
+def overlap_energy(B, v):
+    """The round z = B v together with the quantity of Eq. (20): the sum over the
+    subdomains of the 2-norm of their local field on the overlapping region,
+    i.e. on Omega_k outside I_k (the part E^F that is transferred)."""
+    z = np.zeros((B.ny, B.nx), dtype=np.complex128)
+    tot = 0.0
+    for s in B.subs:
+        u = B.local_solve(s.k, B.restrict(v, s)).reshape(s.oy[1] - s.oy[0], s.ox[1] - s.ox[0])
+        z[s.oy[0]:s.oy[1], s.ox[0]:s.ox[1]] += u
+        mask = np.ones(u.shape, dtype=bool)
+        mask[s.iy[0] - s.oy[0]:s.iy[1] - s.oy[0], s.ix[0] - s.ox[0]:s.ix[1] - s.ox[0]] = False
+        tot += float(np.linalg.norm(u[mask]))
+    return z.ravel(), tot
+
+
+def stationary_eq20(A, B, b, tol, max_rounds):
+    """Algorithm 1 with the stop rule of Eq. (20): rounds continue while the
+    overlap energy of the last round is at least tol times that of the initial
+    local solves (x_0 = B b).  Returns x, the energies and the relative residuals."""
+    x, e0 = overlap_energy(B, b)
+    energies = [e0]
+    hist = [fdfd.relres(A, x, b)]
+    while len(energies) <= max_rounds and not (energies[-1] < tol * e0):
+        z, e = overlap_energy(B, b - A @ x)
+        x = x + z
+        energies.append(e)
+        hist.append(fdfd.relres(A, x, b))
+    return x, energies, hist
+
+
 def stationary(A, B, b, rounds):
     """Algorithm 1 as a stationary iteration: x_0 = B b (initial local solves,
     Eq. (14)), then x <- x + B (b - A x) (transferred sources, Eqs. (18)-(19));

@@ -291,12 +291,26 @@ class Problem:
                                                         int(lo), int(hi), C.byref(out)))
         return out.value
 
-    def stationary_solve(self, b, x=None, tol=1e-10, max_rounds=100):
+    def rcs(self, e, box, phis):
+        """(sigma, F) of the scattered field e by the near-to-far-field transform
+        over the contour around node box (i0, i1, j0, j1) at angles phis."""
+        pe, dev, ke = _ptr(e, self.ndof, "e")
+        ph = np.ascontiguousarray(phis, dtype=np.float64)
+        bx = (C.c_int32 * 4)(*[int(v) for v in box])
+        sig = np.zeros(ph.size, dtype=np.float64)
+        F = np.zeros(ph.size, dtype=np.complex128)
+        _check(self.ctx.handle, self._lib.stf_rcs(self.handle, pe, dev, bx, ph.size, ph.ctypes.data,
+                                                  sig.ctypes.data, F.ctypes.data))
+        return sig, F
+
+    def stationary_solve(self, b, x=None, tol=1e-10, max_rounds=100, stop="residual"):
         """Algorithm 1 as a stationary iteration of source-transfer rounds:
-        x_0 = B b, then x <- x + B (b - A x) until the FP64 true relative residual
-        is <= tol or max_rounds rounds.  Returns (x, info) with info = dict(
-        rounds, status, relres_true, hist) (hist: relative residual of x_0 and of
-        every round)."""
+        x_0 = B b, then x <- x + B (b - A x) until the stop rule holds ("residual":
+        FP64 true relative residual <= tol; "overlap": Eq. (20), the summed
+        overlap-field norms below tol times the initial ones) or max_rounds
+        rounds.  Returns (x, info) with info = dict(rounds, status, relres_true,
+        hist, energy) (hist / energy: relative residual / overlap energy of x_0
+        and of every round)."""
         n = self.ndof
         pb_, dev, kb = _ptr(b, n, "b")
         x = self._out_like(b, tuple(b.shape)) if x is None else x
@@ -304,12 +318,15 @@ class Problem:
         if dev != dev2:
             raise TypeError("b and x must both be host or both be device arrays")
         hist = np.zeros(int(max_rounds) + 1, dtype=np.float64)
+        energy = np.zeros(int(max_rounds) + 1, dtype=np.float64)
         k = C.c_int32(0)
+        rule = {"residual": 0, "overlap": 1}[stop]
         st = self._lib.stf_stationary_solve(self.handle, pb_, px, dev, float(tol), int(max_rounds),
-                                            hist.ctypes.data, C.byref(k))
+                                            rule, hist.ctypes.data, energy.ctypes.data, C.byref(k))
         _check(self.ctx.handle, st, allow=(_abi.STF_ENOCONV,))
         h = hist[:k.value + 1].tolist()
-        info = dict(rounds=k.value, status=st, relres_true=h[-1], hist=h)
+        info = dict(rounds=k.value, status=st, relres_true=h[-1], hist=h,
+                    energy=energy[:k.value + 1].tolist())
         return (x if dev else kx.reshape(tuple(b.shape))), info
 
     def solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None, history_cap=4096,

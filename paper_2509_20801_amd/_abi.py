@@ -75,9 +75,12 @@ EXPORTS = {
     "stf_precond_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "stf_precond_apply_batch": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_stationary_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_double,
-                                       C.c_int32, C.c_void_p, C.POINTER(C.c_int32)]),
+                                       C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                       C.POINTER(C.c_int32)]),
     "stf_line_flux": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_int32, C.c_int32, C.c_int32,
                                 C.c_int32, C.POINTER(C.c_double)]),
+    "stf_rcs": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_int32, C.c_void_p,
+                          C.c_void_p, C.c_void_p]),
     "stf_sweep_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_batch_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int, C.POINTER(SolveOpts), C.c_void_p]),

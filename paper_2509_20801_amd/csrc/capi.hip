@@ -2267,11 +2267,12 @@ stf_status stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z)
 }
 
 stf_status stf_stationary_solve(stf_problem pb, const double* b, double* x, int on_device,
-                                double tol, int32_t max_rounds, double* hist,
-                                int32_t* rounds_out) {
+                                double tol, int32_t max_rounds, int32_t stop, double* hist,
+                                double* hist_energy, int32_t* rounds_out) {
   if (!pb) return STF_EINVAL;
   return guard(pb->ctx, [&] {
     STF_REQUIRE(b && x, "null argument");
+    STF_REQUIRE(stop == STF_STOP_RESIDUAL || stop == STF_STOP_OVERLAP, "unknown stop rule");
     STF_REQUIRE(max_rounds >= 0 && max_rounds <= 100000, "max_rounds out of range");
     STF_REQUIRE(std::isfinite(tol) && tol >= 0, "tol must be finite and >= 0");
     if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
@@ -2292,31 +2293,52 @@ stf_status stf_stationary_solve(stf_problem pb, const double* b, double* x, int 
     pb->kt2.alloc(vb);
     double2* r = pb->kt.as<double2>();
     double2* z = pb->kt2.as<double2>();
-    double* sc = pb->scal.as<double>();          // [0..1] |b|^2 (real part), [2] |r|^2
-    double h[3] = {0.0, 0.0, 0.0};
+    double* sc = pb->scal.as<double>();          // [0..1] |b|^2 (real part), [2] |r|^2, [4] energy
+    Mf& mf = *pb->mf;
+    DBuf per_sub;
+    per_sub.alloc(sizeof(double) * mf.nsub);
+    // Eq. (20): the summed norms of the local fields on the overlapping regions
+    // of the round just taken (before the next round overwrites them).
+    auto energy = [&] {
+      if (pb->prec == STF_C64)
+        launch_overlap_norm<float2>(st, mf.u.as<float2>(), mf.subs.as<SubDev>(), mf.nsub,
+                                    per_sub.as<double>(), sc + 4);
+      else
+        launch_overlap_norm<double2>(st, mf.u.as<double2>(), mf.subs.as<SubDev>(), mf.nsub,
+                                     per_sub.as<double>(), sc + 4);
+    };
+    double h[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     norm2(pb, bd, reinterpret_cast<double2*>(sc));
     precond(pb, bd, xd);                          // x_0 = B b
+    energy();
     residual(pb, xd, bd, r, sc + 2);
-    HIP_CHECK(hipMemcpyAsync(h, sc, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipMemcpyAsync(h, sc, 5 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     const double bn = std::sqrt(h[0]);
     auto rel = [&](double r2) { return bn > 0.0 ? std::sqrt(r2) / bn : std::sqrt(r2); };
     double rr = rel(h[2]);
+    const double e0 = h[4];
+    double en = e0;
     if (hist) hist[0] = rr;
+    if (hist_energy) hist_energy[0] = e0;
+    auto done = [&] { return stop == STF_STOP_RESIDUAL ? rr <= tol : en < tol * e0 || e0 == 0.0; };
     int k = 0;
-    while (k < max_rounds && !(rr <= tol)) {
-      if (!std::isfinite(rr)) throw Error(STF_ENAN, "non-finite residual");
+    while (k < max_rounds && !done()) {
+      if (!std::isfinite(rr) || !std::isfinite(en)) throw Error(STF_ENAN, "non-finite residual");
       precond(pb, r, z);                          // B (b - A x): the transferred sources
+      energy();
       {
         Timed t(pb->ctx, K_UPDATE);
         launch_axpy(st, xd, z, N);                // x <- x + B (b - A x)
       }
       residual(pb, xd, bd, r, sc + 2);
-      HIP_CHECK(hipMemcpyAsync(h + 2, sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_CHECK(hipMemcpyAsync(h + 2, sc + 2, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
       HIP_CHECK(hipStreamSynchronize(st));
       rr = rel(h[2]);
+      en = h[4];
       ++k;
       if (hist) hist[k] = rr;
+      if (hist_energy) hist_energy[k] = en;
     }
     if (!on_device) {
       HIP_CHECK(hipMemcpyAsync(x, xd, vb, hipMemcpyDeviceToHost, st));
@@ -2324,7 +2346,7 @@ stf_status stf_stationary_solve(stf_problem pb, const double* b, double* x, int 
     }
     if (rounds_out) *rounds_out = k;
     if (!std::isfinite(rr)) throw Error(STF_ENAN, "non-finite residual");
-    if (!(rr <= tol)) throw Error(STF_ENOCONV, "tolerance not reached in max_rounds rounds");
+    if (!done()) throw Error(STF_ENOCONV, "tolerance not reached in max_rounds rounds");
   });
 }
 
@@ -2353,6 +2375,45 @@ stf_status stf_line_flux(stf_problem pb, const double* e, int on_device, int32_t
     HIP_CHECK(hipMemcpyAsync(&h, d, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
     *out = h;
+  });
+}
+
+stf_status stf_rcs(stf_problem pb, const double* e, int on_device, const int32_t* box, int32_t nang,
+                   const double* phis, double* sigma, double* F) {
+  if (!pb) return STF_EINVAL;
+  return guard(pb->ctx, [&] {
+    STF_REQUIRE(e && box && phis && sigma, "null argument");
+    STF_REQUIRE(nang >= 1 && nang <= 1000000, "nang out of range");
+    const int nx = pb->prm.nx, ny = pb->prm.ny;
+    const int i0 = box[0], i1 = box[1], j0 = box[2], j1 = box[3];
+    STF_REQUIRE(i0 >= 0 && i1 > i0 && i1 + 1 < nx && j0 >= 0 && j1 > j0 && j1 + 1 < ny,
+                "contour box out of range");
+    for (int a = 0; a < nang; ++a) STF_REQUIRE(std::isfinite(phis[a]), "non-finite angle");
+    hipStream_t st = pb->ctx->stream;
+    const double2* ed = reinterpret_cast<const double2*>(e);
+    if (!on_device) {
+      const size_t vb = (size_t)pb->N * sizeof(double2);
+      pb->hb.alloc(vb);
+      HIP_CHECK(hipMemcpyAsync(pb->hb.p, e, vb, hipMemcpyHostToDevice, st));
+      ed = pb->hb.as<double2>();
+    }
+    DBuf dph, dF;
+    dph.alloc(sizeof(double) * nang);
+    dF.alloc(sizeof(double2) * nang);
+    HIP_CHECK(hipMemcpyAsync(dph.p, phis, sizeof(double) * nang, hipMemcpyHostToDevice, st));
+    launch_far_field(st, ed, nx, i0, i1, j0, j1, pb->prm.dx, pb->prm.dy, pb->prm.k0,
+                     dph.as<double>(), nang, dF.as<double2>());
+    HIP_CHECK(hipGetLastError());
+    std::vector<double2> hF(nang);
+    HIP_CHECK(hipMemcpyAsync(hF.data(), dF.p, sizeof(double2) * nang, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int a = 0; a < nang; ++a) {
+      sigma[a] = (hF[a].x * hF[a].x + hF[a].y * hF[a].y) / (4.0 * pb->prm.k0);
+      if (F) {
+        F[2 * a] = hF[a].x;
+        F[2 * a + 1] = hF[a].y;
+      }
+    }
   });
 }
 

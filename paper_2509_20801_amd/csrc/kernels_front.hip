@@ -1513,6 +1513,38 @@ __global__ __launch_bounds__(256) void k_zero(double2* __restrict__ p, long long
     p[t] = make_double2(0.0, 0.0);
 }
 
+// The quantity of Eq. (20): per subdomain (block), the 2-norm of its local
+// field on Omega_k outside I_k (the overlapping region), then (one block) the
+// sum of those norms over the subdomains in index order.
+template <typename T>
+__global__ __launch_bounds__(256) void k_overlap_norm(const T* __restrict__ u,
+                                                      const SubDev* __restrict__ subs,
+                                                      double* __restrict__ per_sub) {
+  __shared__ double red[4];
+  const SubDev S = subs[blockIdx.x];
+  const int n = S.nxl * S.nyl;
+  double a = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) {
+    const int gx = S.ox0 + t % S.nxl, gy = S.oy0 + t / S.nxl;
+    if (gx >= S.ix0 && gx < S.ix1 && gy >= S.iy0 && gy < S.iy1) continue;
+    const double2 v = to_d2(u[S.u_off + t]);
+    a += v.x * v.x + v.y * v.y;
+  }
+  a = wave_sum(a);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+  __syncthreads();
+  if (threadIdx.x == 0) per_sub[blockIdx.x] = sqrt((red[0] + red[1]) + (red[2] + red[3]));
+}
+
+__global__ __launch_bounds__(64) void k_sum_ordered(const double* __restrict__ a, int n,
+                                                    double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += a[i];
+    out[0] = s;
+  }
+}
+
 int g_max_lds = 0;
 int max_lds() {
   if (g_max_lds == 0) {
@@ -1818,6 +1850,13 @@ void launch_zero(hipStream_t st, double2* p, long long n) {
   hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, st, p, n);
 }
 
+template <typename T>
+void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsub, double* per_sub,
+                         double* out) {
+  hipLaunchKernelGGL((k_overlap_norm<T>), dim3(nsub), dim3(256), 0, st, u, subs, per_sub);
+  hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, st, per_sub, nsub, out);
+}
+
 #define STF_INST(T)                                                                             \
   template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, T*, int*, int*, double); \
   template void launch_sweep_fwd<T>(hipStream_t, const LevelArgs&, const T*, const int*, T*,    \
@@ -1827,6 +1866,8 @@ void launch_zero(hipStream_t st, double2* p, long long n) {
   template void launch_scatter<T>(hipStream_t, const T*, const SubDev*, const int4*,            \
                                   const int4*, const ScatDev*, int, int, int, const int*,       \
                                   const RhsSet&);                                               \
+  template void launch_overlap_norm<T>(hipStream_t, const T*, const SubDev*, int, double*,      \
+                                       double*);                                                \
   template void launch_stage_scatter<T>(hipStream_t, const T*, const SubDev*, const ScatDev*,   \
                                         const int4*, const int4*, const int*, int, int, int, int,\
                                         const int*, const int*, const RhsSet&);

@@ -110,6 +110,71 @@ __global__ __launch_bounds__(256) void k_line_flux(const double2* __restrict__ e
   if (threadIdx.x == 0) out[0] = ((red[0] + red[1]) + (red[2] + red[3])) * half_dl;
 }
 
+// Near-to-far-field transform (the RCS of Sec. 3.1): per angle (block),
+// F(phi) = sum over the contour elements of [du/dn - j k0 (rhat . n) u] exp(j k0 rhat . r) dl
+// on the rectangle through the half-node lines x = (i0 + 1/2) dx, (i1 + 1/2) dx,
+// y = (j0 + 1/2) dy, (j1 + 1/2) dy: u is the mean of the two node lines an edge
+// separates, du/dn their difference over the step times the outward sign; the
+// elements are the nodes strictly inside each edge's span.  A fixed-order
+// block reduction writes F[blockIdx.x].
+__global__ __launch_bounds__(256) void k_far_field(const double2* __restrict__ e, int nx, int i0,
+                                                   int i1, int j0, int j1, double dx, double dy,
+                                                   double k0, const double* __restrict__ phis,
+                                                   double2* __restrict__ F) {
+  __shared__ double red[2][4];
+  const double phi = phis[blockIdx.x];
+  const double c = cos(phi), s = sin(phi);
+  const int nh = i1 - i0, nv = j1 - j0;               // elements per horizontal / vertical edge
+  const int total = 2 * nh + 2 * nv;
+  double ar = 0.0, ai = 0.0;
+  for (int t = threadIdx.x; t < total; t += 256) {
+    long long na, nb;                                  // the two node lines' nodes
+    double xe, ye, nrm, dl, inv, rn;
+    if (t < 2 * nh) {                                  // bottom (t < nh) or top edge
+      const int top = t >= nh, i = i0 + 1 + (top ? t - nh : t);
+      const int row = top ? j1 : j0;
+      na = (long long)row * nx + i;
+      nb = na + nx;
+      xe = i * dx;
+      ye = (row + 0.5) * dy;
+      nrm = top ? 1.0 : -1.0;
+      dl = dx;
+      inv = 1.0 / dy;
+      rn = s * nrm;
+    } else {                                           // left or right edge
+      const int u = t - 2 * nh, right = u >= nv, j = j0 + 1 + (right ? u - nv : u);
+      const int col = right ? i1 : i0;
+      na = (long long)j * nx + col;
+      nb = na + 1;
+      xe = (col + 0.5) * dx;
+      ye = j * dy;
+      nrm = right ? 1.0 : -1.0;
+      dl = dy;
+      inv = 1.0 / dx;
+      rn = c * nrm;
+    }
+    const double2 a = e[na], b = e[nb];
+    const double2 um = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y + b.y));
+    const double2 dn = make_double2((b.x - a.x) * inv * nrm, (b.y - a.y) * inv * nrm);
+    // g = dn - j k0 rn um
+    const double2 g = make_double2(dn.x + k0 * rn * um.y, dn.y - k0 * rn * um.x);
+    double sp, cp;
+    sincos(k0 * (c * xe + s * ye), &sp, &cp);
+    ar += (g.x * cp - g.y * sp) * dl;
+    ai += (g.x * sp + g.y * cp) * dl;
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = ar;
+    red[1][threadIdx.x >> 6] = ai;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    F[blockIdx.x] = make_double2((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]),
+                                 (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+}
+
 __global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__ a, long long n,
                                                       int* __restrict__ flag) {
   long long t = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -151,6 +216,12 @@ void launch_line_flux(hipStream_t st, const double2* e, int nx, int axis, int in
   const double d = axis == 1 ? dy : dx, dl = axis == 1 ? dx : dy;
   hipLaunchKernelGGL(k_line_flux, dim3(1), dim3(256), 0, st, e, base, st_t, st_n, hi - lo,
                      1.0 / (k0 * d), 0.5 * dl, out);
+}
+
+void launch_far_field(hipStream_t st, const double2* e, int nx, int i0, int i1, int j0, int j1,
+                      double dx, double dy, double k0, const double* phis, int nang, double2* F) {
+  hipLaunchKernelGGL(k_far_field, dim3(nang), dim3(256), 0, st, e, nx, i0, i1, j0, j1, dx, dy, k0,
+                     phis, F);
 }
 
 void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out) {

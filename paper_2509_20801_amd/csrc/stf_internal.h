@@ -222,6 +222,11 @@ void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out
 // caller checks 0 <= index, index + 1 < ny (nx), 0 <= lo <= hi <= nx (ny).
 void launch_line_flux(hipStream_t st, const double2* e, int nx, int axis, int index, int lo, int hi,
                       double k0, double dx, double dy, double* out);
+// F[a] of the near-to-far-field transform at angle phis[a] (device) over the
+// rectangle through the half-node lines around node box [i0, i1] x [j0, j1]
+// (the caller checks 0 <= i0 < i1, i1 + 1 < nx, likewise j).
+void launch_far_field(hipStream_t st, const double2* e, int nx, int i0, int i1, int j0, int j1,
+                      double dx, double dy, double k0, const double* phis, int nang, double2* F);
 // nonzero flag if any of n doubles is not finite (flag must be zeroed first).
 void launch_check_finite(hipStream_t st, const double* a, long long n, int* flag);
 
@@ -281,6 +286,10 @@ void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const 
                           int scount, int maxw, int maxh, const int* inst, const int* pact,
                           const RhsSet& r);
 void launch_zero(hipStream_t st, double2* p, long long n);
+// Eq. (20): per_sub[k] = |u_k| on Omega_k outside I_k (nsub subdomains), out[0] = their sum.
+template <typename T>
+void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsub, double* per_sub,
+                         double* out);
 
 // Krylov (kernels_krylov.hip).  Vectors of n complex doubles; V holds nv vectors
 // with leading dimension ld (elements).

@@ -324,3 +324,62 @@ def test_batched_round_equals_single_rounds(stf, ctx, prec):
         zb = pb.precond(v[:k])
         for r in range(k):
             assert np.array_equal(zb[r], single[r]), (k, r)
+
+
+def test_stationary_eq20_stop_rule_matches_oracle(stf, ctx):
+    """Algorithm 1 with the stop rule of Eq. (20): the overlap energies of the
+    rounds follow the oracle's (1e-6 relative + 1e-12 of the first, complex128
+    fronts), the iteration stops at the same round and the solution matches."""
+    w = workloads.configs.cylinder_tfsf()
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0]
+    xr, er, hr = ddm.stationary_eq20(A, B, b.ravel(), 1e-8, 40)
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    pb.factor()
+    x, info = pb.stationary_solve(b, tol=1e-8, max_rounds=40, stop="overlap")
+    e = np.asarray(info["energy"])
+    assert info["status"] == 0 and info["rounds"] == len(er) - 1
+    assert np.all(np.abs(e - np.asarray(er)) <= 1e-6 * np.asarray(er) + 1e-12 * er[0])
+    assert _rel(x, xr) < 1e-10
+    # and the energies run down as Eq. (20) intends: below 1e-8 of the first
+    assert e[-1] < 1e-8 * e[0]
+
+
+def test_rcs_matches_oracle_and_mie(stf, ctx):
+    """The near-to-far-field transform on the GPU against oracle.ntff (1e-11
+    relative in F, same midpoint rule, another summation order), for the
+    scattered-field solve of a dielectric cylinder (r = lambda/2, eps 4, 20
+    points per wavelength, 2 x 2 subdomains): its RCS is within the
+    discretisation error of the Mie series (as the oracle's is, 26% at 20 ppw),
+    and a contour that does not enclose the scatterer sees (almost) nothing."""
+    import math
+    from oracle import ntff
+    h, a, eps = 1.0 / 20, 0.5, 4.0
+    L = 16
+    n = int(round(2.5 / h)) + 2 * L
+    c = (n - 1) / 2.0
+    k0 = 2 * math.pi
+    cells = workloads.geometry.cylinder(n, n, c * h, c * h, a, eps, dx=h, dy=h, subcells=16)
+    p = dict(nx=n, ny=n, dx=h, dy=h, k0=k0, pml=(L,) * 4, pml_order=3, pml_R=1e-8, px=2, py=2,
+             overlap=4, local_pml=12)
+    X, Y = np.meshgrid(np.arange(n) * h - c * h, np.arange(n) * h - c * h)
+    b = -k0 ** 2 * (fdfd.node_eps(cells) - 1) * np.exp(-1j * k0 * (X + c * h))
+    pb = stf.Problem(ctx, p, cells)
+    pb.factor()
+    u, info = pb.solve(b, tol=1e-12, restart=30)
+    m = L + 2
+    box = (m, n - 1 - m, m, n - 1 - m)
+    phis = np.linspace(0, 2 * math.pi, 72, endpoint=False)
+    sig, F = pb.rcs(u, box, phis)
+    Fr = ntff.far_field(u, h, h, box, k0, phis)
+    assert np.linalg.norm(F - Fr) < 1e-11 * np.linalg.norm(Fr)
+    ref = ntff.mie_rcs(k0, a, eps, phis)
+    assert np.linalg.norm(sig - ref) < 0.35 * np.linalg.norm(ref)
+    # a contour around empty space (left of the cylinder)
+    sig0, _ = pb.rcs(u, (m, m + 10, n // 2 - 5, n // 2 + 5), phis)
+    assert sig0.max() < 1e-3 * sig.max()
+    with pytest.raises(stf.StfError):
+        pb.rcs(u, (0, n - 1, 0, n - 1), phis)          # beyond the grid
+    pb.close()

@@ -241,3 +241,54 @@ def test_single_subdomain_sweep_is_exact_inverse():
     for order in ddm.ORDERS:
         z = ddm.sweep_apply(B, A, b, ddm.sweep_stages(B.subs, 1, 1, order))
         assert fdfd.relres(A, z, b) < 1e-13
+
+
+def test_pooled_round_equals_the_round():
+    """oracle.pool spreads the factors over worker processes; with complex128
+    factors its round is SourceTransfer's (same arithmetic up to roundoff), with
+    complex64 factors it is within single-precision rounding of it."""
+    from oracle import pool
+    w = workloads.configs.small_random(nx=70, ny=64, pml=6, px=3, py=2, overlap=3, local_pml=6)
+    p = w.params()
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    v = w.b[0].ravel()
+    ref = B.apply(v)
+    with pool.PooledSourceTransfer(p, w.eps_cells, 3) as P:
+        assert np.linalg.norm(P.apply(v) - ref) < 1e-13 * np.linalg.norm(ref)
+    with pool.PooledSourceTransfer(p, w.eps_cells, 2, np.complex64) as P:
+        err = np.linalg.norm(P.apply(v) - ref) / np.linalg.norm(ref)
+        assert 1e-9 < err < 1e-4
+
+
+# --- the stop rule of Eq. (20) -------------------------------------------------
+
+def test_overlap_energy_vanishes_without_overlap_and_in_one_way_transfer():
+    """One subdomain has no overlapping region, so the energy of Eq. (20) is 0
+    after the initial solve.  Two subdomains in vacuum with the source in
+    Omega_1 (the setting of the paper's Fig. 4): the initial solve leaves an
+    overlap field, and after one round the field in the overlapping regions is
+    at the level of the local PML's reflection."""
+    w = workloads.configs.small_random(nx=40, ny=36, pml=6, px=1, py=1)
+    p = w.params()
+    B1 = ddm.SourceTransfer(p, w.eps_cells)
+    _, e = ddm.overlap_energy(B1, w.b[0].ravel())
+    assert e == 0.0
+    w2, A, B, b = _two_sub_vacuum(overlap=4, local_pml=10)
+    x, en, hist = ddm.stationary_eq20(A, B, b, 1e-3, 3)
+    assert en[0] > 0 and en[1] < 1e-3 * en[0]
+    assert len(en) == 2 and hist[1] < 1e-4
+
+
+def test_eq20_stop_rule_tracks_the_residual():
+    """Run to the Eq. (20) threshold, the iterate is as close to the direct
+    solve as the residual says (the energies fall with the residual)."""
+    w = workloads.configs.cylinder_tfsf()
+    p, A = _setup(w)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    b = w.b[0].ravel()
+    x, en, hist = ddm.stationary_eq20(A, B, b, 1e-10, 30)
+    assert en[-1] < 1e-10 * en[0]
+    assert hist[-1] < 1e-9
+    assert fdfd.rel_l2(x, fdfd.solve_direct(A, b)) < 1e-8
+    # monotone decay over the first rounds, as the residual's
+    assert all(e1 < e0 for e0, e1 in zip(en[:6], en[1:7]))

@@ -134,3 +134,54 @@ def disks_problem(k, sides=(256, 384, 512, 768), pml=16, block=128, overlap=8, l
 def disks_batch(count=48, **kw):
     """The batched workload: problems 0 .. count-1 of disks_problem."""
     return [disks_problem(k, **kw) for k in range(count)]
+
+
+def waveguides(interior=4096, pml=16, h_nm=20.0, lam_um=1.55, parts=16, overlap=8, local_pml=16,
+               seed=4, n_routes=8, n_splits=4, width_um=0.45, eps_si=12.09, eps_sio2=2.085,
+               r_min_um=5.0, src_from_pml_um=2.0, subcols=16):
+    """Silicon photonic layout (default 4096^2 interior + 16-cell PML = 4128^2
+    nodes, h = 20 nm, lambda = 1.55 um = 77.5 cells, 16 x 16 subdomains):
+    `n_routes` seeded waveguides (0.45 um Si, eps 12.09, in SiO2, eps 2.085)
+    crossing from left to right, each in its own horizontal band, with random
+    raised-cosine S-bends of radius >= 5 um; `n_splits` of them split into two
+    branches (Y-splits).  Source: the fundamental mode of route 0's cross-section
+    (tridiagonal eigen-solve) on the node column 2 um right of the left PML."""
+    from . import photonics
+    rng = np.random.default_rng(seed)
+    n = interior + 2 * pml
+    cell_nm = h_nm
+    lam = lam_um * 1000.0 / cell_nm
+    width = width_um * 1000.0 / cell_nm
+    r_min = r_min_um * 1000.0 / cell_nm
+    k0 = 2 * math.pi / lam
+    band = interior / n_routes
+    split_ids = set(rng.choice(n_routes, size=min(n_splits, n_routes), replace=False).tolist())
+    paths, starts = [], []
+    for i in range(n_routes):
+        lo, hi = pml + i * band, pml + (i + 1) * band
+        y0 = 0.5 * (lo + hi) + rng.uniform(-0.1, 0.1) * band
+        margin = 0.5 * width + 0.1 * band
+        if i in split_ids:
+            # the trunk stays near the band centre; the branches leave it by +-dy
+            half_dy = 0.22 * band
+            trunk = photonics.route(-1.0, n, y0, y0 - 0.05 * band, y0 + 0.05 * band, r_min, rng,
+                                    n_bends=2, max_dy=0.05 * band)
+            xs = float(rng.uniform(0.35, 0.6) * n)
+            paths += photonics.y_split(trunk, xs, half_dy, r_min, n)
+        else:
+            paths.append(photonics.route(-1.0, n, y0, lo + margin, hi - margin, r_min, rng,
+                                         n_bends=3, max_dy=0.3 * band))
+        starts.append(y0)
+    cells = photonics.strip_cells(n, n, paths, width, eps_si, eps_sio2, subcols=subcols)
+    col = pml + int(round(src_from_pml_um * 1000.0 / cell_nm))
+    # route 0's cross-section window at the source column (its own band)
+    nodes = photonics.strip_nodes(n, n, paths[:2] if 0 in split_ids else paths[:1], width, eps_si,
+                                  eps_sio2)
+    lo, hi = pml, int(pml + band)
+    beta2, phi = photonics.fundamental_mode(nodes[lo:hi, col], k0)
+    b = np.zeros((n, n), dtype=np.complex128)
+    b[lo:hi, col] = phi
+    return Workload("waveguides_%d" % n, n, n, k0, (pml,) * 4, 3, 1e-8, parts, parts, overlap,
+                    local_pml, 3, 1e-8, cells, b[None],
+                    meta=dict(seed=seed, lam=lam, width=width, splits=sorted(split_ids),
+                              source_col=col, beta2=beta2, neff=math.sqrt(beta2) / k0))
