@@ -424,6 +424,39 @@ def subdomain_study(stf, torch, ctx, tol=1e-3, fgmres_tol=1e-8):
             "stationary_tol": tol, "fgmres_tol": fgmres_tol, "rows": rows}
 
 
+def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order="diagonal"):
+    """The large single problem: the 4128 x 4128 waveguide layout (17.0M DoF,
+    16 x 16 subdomains, complex64 fronts, fundamental-mode source) to FP64 true
+    rel-res 1e-10; one warm-up and one timed step (assembly, factorisation,
+    solve), in the four-diagonal order and in the additive one."""
+    import workloads
+    w = workloads.configs.waveguides()
+    eps = torch.from_numpy(w.eps_cells).cuda()
+    b = torch.from_numpy(w.b[0]).cuda()
+    pb = stf.Problem(ctx, params_of(w, stf.STF_C64), eps)
+    x = torch.empty_like(b)
+    out = {"workload": "waveguides 4128x4128 (4096^2 + 16-cell PML), h = 20 nm, lambda = 1.55 um, "
+                       "16x16 subdomains", "ndof": w.ndof, "tol": tol}
+    for od in (order, "additive"):
+        def step():
+            pb.assemble(eps)
+            pb.factor()
+            return pb.solve(b, x=x, tol=tol, restart=restart, max_iter=max_iter, order=od)
+        step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, inf = step()
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[od] = {"value": round(w.ndof / t, 1), "unit": "DoF/s", "ms_per_step": round(t * 1e3, 2),
+                   "iters": inf[0]["iters"], "relres_true": inf[0]["relres_true"],
+                   "t_factor_ms": round(inf[0]["t_factor_ms"], 3),
+                   "converged": inf[0]["status"] == 0}
+    out["device_bytes"] = pb.info()["device_bytes"]
+    pb.close()
+    return out
+
+
 def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagonal", count=48):
     """The batched workload: `count` disk problems, four right-hand sides each,
     factored and solved by stf_batch_solve (complex64 fronts)."""
@@ -470,7 +503,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 reference form")
     ap.add_argument("--no-side", action="store_true",
                     help="skip the side forms (mixed without the network, stationary)")
-    ap.add_argument("--no-batched", action="store_true", help="skip the 48-problem batch")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 48-problem batch and the 17M-DoF waveguide problem")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only the PMC calibration copy (512 MiB)")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
@@ -548,6 +582,7 @@ def main():
         out["subdomain_study"] = subdomain_study(stf, torch, ctx)
     if not args.no_batched:
         out["batched_disks"] = batched_disks(stf, torch, ctx, 1, args.tol, 20, 1500)
+        out["large_waveguides"] = large_waveguides(stf, torch, ctx)
     out["device_bytes"] = info["device_bytes"]
     if sample is not None:
         its = out.get("mixed_1rhs", {}).get("iters", out["iters"][0])

@@ -103,3 +103,36 @@ def test_cylinder_matches_oracle_and_mie(stf, ctx):
     mask &= np.abs(np.arange(n)[None, :] - col + 0.5) >= 2.5
     err = np.linalg.norm((x - ref)[mask]) / np.linalg.norm(ref[mask])
     assert err < 0.16, err
+
+
+WAVEGUIDE_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                "waveguides_4128_samples.json")
+
+
+@pytest.mark.parametrize("order", ["diagonal", "additive"])
+def test_waveguides_full_size_matches_oracle(stf, ctx, order):
+    """The 4128 x 4128 waveguide workload (17.0M DoF, 16 x 16 subdomains,
+    complex64 fronts) to FGMRES rel-res 1e-10, in the four-diagonal and the
+    additive order: the field at the oracle's sample nodes (the oracle's own
+    domain decomposition to rel-res 1e-13, tests/golden/waveguides_4128_samples.json
+    written by make_waveguide_reference.py) to 1e-8 relative L2, and the FP64
+    true residual recomputed on the CPU with the oracle's operator."""
+    import torch
+    ref = json.load(open(WAVEGUIDE_GOLDEN))
+    w = workloads.configs.waveguides()
+    print("waveguides %dx%d, %s order" % (w.nx, w.ny, order), flush=True)
+    pb = stf.Problem(ctx, dict(w.params(), front_prec=1), torch.from_numpy(w.eps_cells).cuda())
+    pb.factor()
+    b = torch.from_numpy(w.b[0]).cuda()
+    x, info = pb.solve(b, tol=1e-10, restart=20, max_iter=600, order=order)
+    assert info[0]["status"] == 0 and info[0]["relres_true"] <= 1e-10
+    xh = x.cpu().numpy().ravel()
+    pb.close()
+    idx = np.asarray(ref["index"])
+    xr = np.asarray(ref["re"]) + 1j * np.asarray(ref["im"])
+    err = np.linalg.norm(xh[idx] - xr) / np.linalg.norm(xr)
+    print("rel err at %d samples %.3e, iters %d" % (idx.size, err, info[0]["iters"]), flush=True)
+    assert err < 1e-8
+    assert abs(np.linalg.norm(xh) - ref["norm"]) < 1e-8 * ref["norm"]
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    assert fdfd.relres(A, xh, w.b[0].ravel()) < 1.05e-10
