@@ -59,12 +59,26 @@ def params_of(w, prec, leaf=0):
                 local_pml_R=p["local_pml_R"], front_prec=prec, leaf_size=leaf)
 
 
+def autotune(ctx, problems, nrhs, tune):
+    """The launch-shape autotuner for these problems' level signatures (a
+    one-time set-up per device and shape, like the symbolic plan: outside the
+    timed steps); its report and wall time, or None when tuning is off."""
+    if not tune or getattr(ctx, "_tune_loaded", False):
+        return None
+    t0 = time.perf_counter()
+    rep = ctx.autotune(problems, nrhs=nrhs, reps=3)
+    rep["wall_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+    rep["ms_default"], rep["ms_tuned"] = round(rep["ms_default"], 4), round(rep["ms_tuned"], 4)
+    return rep
+
+
 def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, timing, leaf=0,
-             rounds=1, nrhs=1, x0=None, order="additive"):
+             rounds=1, nrhs=1, x0=None, order="additive", tune=True):
     eps = torch.from_numpy(w.eps_cells).cuda()
     b = torch.from_numpy(w.b[0] if nrhs == 1 else w.b[:nrhs]).cuda()
     x = torch.empty_like(b)
     pb = stf.Problem(ctx, params_of(w, prec, leaf), eps)
+    tuned = autotune(ctx, pb, nrhs, tune)
     infos = []
 
     def step():
@@ -115,6 +129,7 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     up = pb.line_flux(x1, 1, w.ny - pml_hi - 11, lo, hi)
     down = -pb.line_flux(x1, 1, pml_lo + 10, lo, hi)
     info["power"] = {"up": up, "down": down}
+    info["autotune"] = tuned
     pb.close()
     return (t1 - t0) / steps, infos, stats, info, profile
 
@@ -457,9 +472,12 @@ def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order
     return out
 
 
-def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagonal", count=48):
+def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagonal", count=48,
+                  tune=True):
     """The batched workload: `count` disk problems, four right-hand sides each,
-    factored and solved by stf_batch_solve (complex64 fronts)."""
+    factored and solved by stf_batch_solve (complex64 fronts).  The autotuner
+    covers the batch's factorisation levels (and its sweeps for the additive
+    order; a staged order's levels keep the built-in shapes)."""
     import numpy as np
     import workloads
     ws = workloads.configs.disks_batch(count)
@@ -467,6 +485,13 @@ def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagona
            for x in ws]
     bs = [torch.from_numpy(x.b).cuda() for x in ws]
     nd = sum(x.ndof * x.b.shape[0] for x in ws)
+    tuned = None
+    if tune:
+        t0 = time.perf_counter()
+        tuned = None if getattr(ctx, "_tune_loaded", False) else \
+            ctx.autotune(pbs, nrhs=4, sweeps=order == "additive", reps=2)
+        if tuned is not None:
+            tuned["wall_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
 
     def step():
         return stf.batch_solve(ctx, pbs, bs, tol=tol, restart=restart, max_iter=max_iter,
@@ -484,7 +509,8 @@ def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagona
            "problems": count, "dof_rhs": nd, "order": order, "restart": restart,
            "iters_mean": round(float(np.mean(its)), 2), "iters_max": int(max(its)),
            "t_factor_ms": round(inf[0][0]["t_factor_ms"], 3),
-           "converged": all(i["status"] == 0 and i["relres_true"] <= tol for lst in inf for i in lst)}
+           "converged": all(i["status"] == 0 and i["relres_true"] <= tol for lst in inf for i in lst),
+           "autotune": tuned}
     for pb in pbs:
         pb.close()
     return out
@@ -499,6 +525,11 @@ def main():
     ap.add_argument("--restart", type=int, default=10)
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP event timing")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="built-in launch shapes (skip the autotuner before each form)")
+    ap.add_argument("--tune-file", default=None,
+                    help="load the tuned shapes from this file if it exists (no tuning), "
+                         "else tune and save them there at the end")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the complex128 reference form")
     ap.add_argument("--no-side", action="store_true",
@@ -531,6 +562,10 @@ def main():
     from paper_2509_20801_amd import learned
 
     ctx = stf.Context(0)
+    ctx._tune_loaded = False
+    if args.tune_file and os.path.exists(args.tune_file) and not args.no_tune:
+        ctx.tune_load(args.tune_file)
+        ctx._tune_loaded = True
     net = learned.load_network(stf, ctx)
     if net is None:
         raise RuntimeError("the trained network (paper_2509_20801_amd/data) is missing")
@@ -539,7 +574,8 @@ def main():
     # Headline: mixed + batched (four right-hand sides) + learned guess.
     t_h, inf_h, stats, info, profile = run_form(stf, torch, ctx, w4, stf.STF_C64, args.steps,
                                                 args.warmup, args.tol, args.restart, args.max_iter,
-                                                not args.no_timing, nrhs=4, x0="learned")
+                                                not args.no_timing, nrhs=4, x0="learned",
+                                                tune=not args.no_tune)
     last = inf_h[-1]
     ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in last)
     out = {"metric": METRIC, "value": round(4 * N / t_h, 1), "unit": "DoF*RHS/s", "n_gpus": 1,
@@ -556,21 +592,24 @@ def main():
            "learned_guess_kept": [i["used_learned"] for i in last],
            "relres_guess": [round(i["relres_x0"], 4) for i in last],
            "t_nn_ms": round(sum(i["t_nn_ms"] for i in last), 3),
-           "converged": ok, "power": {k: round(v, 6) for k, v in info["power"].items()}}
+           "converged": ok, "power": {k: round(v, 6) for k, v in info["power"].items()},
+           "autotune": info["autotune"]}
     if stats:
         dom, rl = roofline(stf, w, stf.STF_C64, stats, args.steps, info["max_depth"] + 1)
         out["roofline"] = rl
         out["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in profile.items()}
     if not args.no_plain:
         t_p, inf_p, _, _, _ = run_form(stf, torch, ctx, w, stf.STF_C128, args.steps, args.warmup,
-                                       args.tol, args.restart, args.max_iter, False)
+                                       args.tol, args.restart, args.max_iter, False,
+                                       tune=not args.no_tune)
         out["plain_fp64"] = {"value": round(N / t_p, 1), "unit": "DoF/s",
                              "ms_per_step": round(t_p * 1e3, 3), "iters": inf_p[-1]["iters"],
                              "form": "complex128 fronts, one right-hand side, zero guess"}
         out["speedup_vs_plain"] = round((4 * N / t_h) / (N / t_p), 3)
     if not args.no_side:
         t_m, inf_m, _, _, _ = run_form(stf, torch, ctx, w, stf.STF_C64, args.steps, args.warmup,
-                                       args.tol, args.restart, args.max_iter, False)
+                                       args.tol, args.restart, args.max_iter, False,
+                                       tune=not args.no_tune)
         out["mixed_1rhs"] = {"value": round(N / t_m, 1), "unit": "DoF/s",
                              "ms_per_step": round(t_m * 1e3, 3), "iters": inf_m[-1]["iters"]}
         t_b, inf_b, _, _, _ = run_form(stf, torch, ctx, w4, stf.STF_C64, args.steps, args.warmup,
@@ -581,9 +620,13 @@ def main():
         out["stationary"] = stationary_form(stf, torch, ctx, w, stf.STF_C64, args.tol, 200)
         out["subdomain_study"] = subdomain_study(stf, torch, ctx)
     if not args.no_batched:
-        out["batched_disks"] = batched_disks(stf, torch, ctx, 1, args.tol, 20, 1500)
+        out["batched_disks"] = batched_disks(stf, torch, ctx, 1, args.tol, 20, 1500,
+                                             tune=not args.no_tune)
         out["large_waveguides"] = large_waveguides(stf, torch, ctx)
     out["device_bytes"] = info["device_bytes"]
+    if args.tune_file and not args.no_tune and not ctx._tune_loaded:
+        ctx.tune_save(args.tune_file)
+    out["tune_file_loaded"] = bool(ctx._tune_loaded)
     if sample is not None:
         its = out.get("mixed_1rhs", {}).get("iters", out["iters"][0])
         out["cpu_baseline"] = cpu_baseline(w, sample, its)

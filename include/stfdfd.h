@@ -316,6 +316,68 @@ stf_status  stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs
 stf_status  stf_problem_info(stf_problem pb, stf_plan_info* out);
 void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
 
+/* ---- autotuner ------------------------------------------------------------
+ * Not part of the method: a search over the launch shapes of the per-level
+ * kernels of Eq. (22)'s multifrontal factorisation and of the source-transfer
+ * round's forward and backward sweeps (Eqs. (18)-(19)), which change how the
+ * work is spread over the GPU, not what is computed (results agree to rounding).
+ * A level's signature is (operation, front precision, right-hand sides per
+ * sweep, fronts in the level, largest front order m, largest separator p).
+ *
+ * stf_autotune times every candidate shape of every level (HIP events, `reps`
+ * passes of 1..100, the fastest pass counting) for the problems given: one
+ * problem (its own fronts), or nprob > 1 problems as the set that
+ * stf_batch_solve builds for the same problems in the same order.  what: 1 the
+ * factorisation, 2 the additive round's sweeps with nrhs (1..4) right-hand
+ * sides, 3 both.  The fastest shape per level signature is kept in the context
+ * and used by every later factorisation and round on it whose levels have
+ * that signature (solo, batched, staged or allocation-free); other levels keep
+ * the built-in rule.  Needs assembled problems of this context with one front
+ * precision (STF_ESTATE otherwise); leaves them factored (the factorisation
+ * is run again with the chosen shapes; a perturbed pivot is not reported
+ * here).  Contents of the round's workspaces are overwritten.  report: NULL or
+ * filled with the levels timed, how many changed from the built-in shape and
+ * the summed level times with the built-in and with the chosen shapes (ms). */
+typedef struct {
+  int32_t levels;
+  int32_t changed;
+  double  ms_default;
+  double  ms_tuned;
+} stf_tune_report;
+stf_status  stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
+                         int32_t what, int32_t reps, stf_tune_report* report);
+/* Test hook: sets, without timing, the entry of every level of the given
+ * problems (as stf_autotune selects them) to the level's candidate shape
+ * `index` (>= 0; the last candidate where a level has fewer; 0 is the
+ * built-in shape).  *max_candidates (may be NULL) receives the largest
+ * candidate count over the levels, so that index = 0 .. max - 1 visits every
+ * candidate; every one must give the same results to rounding. */
+stf_status  stf_tune_pick(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
+                          int32_t what, int32_t index, int32_t* max_candidates);
+/* Host-only check of the launch-shape rules on a problem's plan (no device):
+ * the levels of the plan (tree depths over all subdomains), the number of
+ * candidate shapes over all levels and operations, and how many built-in or
+ * candidate shapes fail the validity rules (0 expected).  The device limits
+ * are those of the current device when one is present, else gfx950's (160 KiB
+ * of LDS per workgroup, 256 compute units). */
+stf_status  stf_debug_level_shapes(const stf_params* prm, int32_t nrhs, int32_t* nlevels,
+                                   int32_t* ncandidates, int32_t* invalid);
+/* The context's tuned shapes as a text file for this device architecture
+ * (first line: "stfdfd-tune 1 <arch> <entries>", then one entry per line), and
+ * back: a file for another architecture, or malformed, is STF_EINVAL and
+ * changes nothing; loaded entries replace those of the same signature.  An
+ * entry whose shape cannot run its level is ignored at launch. */
+stf_status  stf_tune_save(stf_ctx ctx, const char* path);
+stf_status  stf_tune_load(stf_ctx ctx, const char* path);
+stf_status  stf_tune_clear(stf_ctx ctx);
+/* Number of entries (-1 for a NULL ctx), and entry i (0-based, in signature
+ * order): key = {op (0 factorisation, 1 forward sweep, 2 backward sweep),
+ * bytes per complex entry, nrhs (0 for the factorisation), fronts in the
+ * level, max m, max p}; shape = {kind, nb or kp, ntf or ntl, parts};
+ * ms = {chosen, built-in}.  Any output pointer may be NULL. */
+int32_t     stf_tune_count(stf_ctx ctx);
+stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms);
+
 /* ---- learned warm start -------------------------------------------------
  * A spectral neural operator on n x n tiles (FP32): pointwise lift of the cin
  * input features to W channels, L layers h <- act(K h + W_l h + c_l) with the

@@ -13,6 +13,7 @@ from __future__ import annotations
 
 import atexit
 import ctypes as C
+import os
 import weakref
 
 import numpy as np
@@ -21,7 +22,7 @@ from . import _abi
 from ._abi import (STF_C128, STF_C64, STF_X0_USER, STF_X0_ZERO, STF_X0_LEARNED,  # noqa: F401
                    KERNEL_CLASSES, STATUS_NAMES)
 
-__all__ = ["Context", "Problem", "Network", "StfError", "plan_query", "debug_local_axes", "batch_solve",
+__all__ = ["Context", "Problem", "Network", "StfError", "plan_query", "debug_local_axes", "debug_level_shapes", "batch_solve",
            "make_params", "nn_param_count", "STF_C128", "STF_C64", "STF_X0_ZERO", "STF_X0_USER",
            "STF_X0_LEARNED", "KERNEL_CLASSES"]
 
@@ -88,6 +89,17 @@ def plan_query(prm):
     if st != 0:
         raise StfError(st, "invalid parameters")
     return {f: getattr(info, f) for f, _ in _abi.PlanInfo._fields_}
+
+
+def debug_level_shapes(prm, nrhs=4):
+    """Host-only: (levels, candidate shapes, invalid shapes) of the launch-shape
+    rules on the plan of `prm`."""
+    lib = _abi.load()
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    st = lib.stf_debug_level_shapes(C.byref(_params(prm)), int(nrhs), C.byref(a), C.byref(b), C.byref(c))
+    if st != 0:
+        raise StfError(st, "invalid parameters")
+    return a.value, b.value, c.value
 
 
 def debug_local_axes(prm, k):
@@ -177,6 +189,52 @@ class Context:
             for c in classes:
                 mask |= 1 << (KERNEL_CLASSES.index(c) if isinstance(c, str) else int(c))
         _check(self.handle, self._lib.stf_ctx_set_timing_mask(self.handle, mask))
+
+    def autotune(self, problems, nrhs=4, factor=True, sweeps=True, reps=3):
+        """Time every candidate launch shape of each tree level (factorisation
+        and/or the round's sweeps with `nrhs` right-hand sides) of one problem, or
+        of the set a batched solve builds for `problems`, and keep the fastest per
+        level signature on this context.  Leaves the problems factored.  Returns
+        the report as a dict."""
+        if isinstance(problems, Problem):
+            problems = [problems]
+        what = (1 if factor else 0) | (2 if sweeps else 0)
+        arr = (C.c_void_p * len(problems))(*[p.handle.value for p in problems])
+        rep = _abi.TuneReport()
+        _check(self.handle, self._lib.stf_autotune(self.handle, len(problems), arr, int(nrhs), what,
+                                                   int(reps), C.byref(rep)))
+        return {f: getattr(rep, f) for f, _ in _abi.TuneReport._fields_}
+
+    def tune_pick(self, problems, index, nrhs=4, factor=True, sweeps=True):
+        """Test hook: every level's shape set to its candidate `index` (clamped);
+        returns the largest candidate count over the levels."""
+        if isinstance(problems, Problem):
+            problems = [problems]
+        what = (1 if factor else 0) | (2 if sweeps else 0)
+        arr = (C.c_void_p * len(problems))(*[p.handle.value for p in problems])
+        most = C.c_int32()
+        _check(self.handle, self._lib.stf_tune_pick(self.handle, len(problems), arr, int(nrhs), what,
+                                                    int(index), C.byref(most)))
+        return most.value
+
+    def tune_save(self, path):
+        _check(self.handle, self._lib.stf_tune_save(self.handle, os.fsencode(path)))
+
+    def tune_load(self, path):
+        _check(self.handle, self._lib.stf_tune_load(self.handle, os.fsencode(path)))
+
+    def tune_clear(self):
+        _check(self.handle, self._lib.stf_tune_clear(self.handle))
+
+    def tune_entries(self):
+        """The tuned shapes: list of (key, shape, (ms_chosen, ms_builtin)) with
+        key = (op, elem, nrhs, fronts, max_m, max_p), shape = (kind, a, b, c)."""
+        out = []
+        for i in range(self._lib.stf_tune_count(self.handle)):
+            key, shape, ms = (C.c_int32 * 6)(), (C.c_int32 * 4)(), (C.c_double * 2)()
+            _check(self.handle, self._lib.stf_tune_entry(self.handle, i, key, shape, ms))
+            out.append((tuple(key), tuple(shape), tuple(ms)))
+        return out
 
     def kernel_stats(self, cls):
         if isinstance(cls, str):

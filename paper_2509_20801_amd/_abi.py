@@ -45,6 +45,11 @@ class NNConfig(C.Structure):
                 ("layers", C.c_int32), ("cin", C.c_int32), ("max_batch", C.c_int32)]
 
 
+class TuneReport(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("changed", C.c_int32), ("ms_default", C.c_double),
+                ("ms_tuned", C.c_double)]
+
+
 class PlanInfo(C.Structure):
     _fields_ = [("ndof", C.c_int64), ("nsub", C.c_int32), ("nshapes", C.c_int32),
                 ("local_dof", C.c_int64), ("nfronts", C.c_int64), ("max_front", C.c_int32),
@@ -84,6 +89,17 @@ EXPORTS = {
     "stf_sweep_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_batch_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int, C.POINTER(SolveOpts), C.c_void_p]),
+    "stf_autotune": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                               C.POINTER(TuneReport)]),
+    "stf_debug_level_shapes": (C.c_int, [C.POINTER(Params), C.c_int32, C.POINTER(C.c_int32),
+                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
+    "stf_tune_pick": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_int32,
+                                C.POINTER(C.c_int32)]),
+    "stf_tune_save": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "stf_tune_load": (C.c_int, [C.c_void_p, C.c_char_p]),
+    "stf_tune_clear": (C.c_int, [C.c_void_p]),
+    "stf_tune_count": (C.c_int32, [C.c_void_p]),
+    "stf_tune_entry": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "stf_problem_info": (C.c_int, [C.c_void_p, C.POINTER(PlanInfo)]),
     "stf_problem_destroy": (None, [C.c_void_p]),
     "stf_nn_param_count": (C.c_int64, [C.POINTER(NNConfig)]),

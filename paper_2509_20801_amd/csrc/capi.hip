@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <cstdlib>
 #include <mutex>
@@ -80,6 +81,24 @@ void* scratch_address(int device) {
 struct BatchState;
 void destroy_batch(BatchState* b);
 
+// Level signature for the autotuner: operation (0 factorisation, 1 forward
+// sweep, 2 backward sweep), bytes per complex entry, right-hand sides per
+// sweep (0 for the factorisation), fronts in the level, largest m and p.  The
+// shapes that run a level and their speed depend on nothing else.
+struct TuneKey {
+  int op, elem, nr, nlevel, max_m, max_p;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(op, elem, nr, nlevel, max_m, max_p) <
+           std::tie(o.op, o.elem, o.nr, o.nlevel, o.max_m, o.max_p);
+  }
+};
+// The fastest shape measured for a signature (factorisation: kind, nb, ntf;
+// sweeps: kind, kp, ntl, parts), its time and that of the built-in shape.
+struct TuneEntry {
+  int kind = 0, a = 0, b = 0, c = 0;
+  double ms = 0.0, ms_default = 0.0;
+};
+
 struct stf_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -100,6 +119,8 @@ struct stf_ctx_s {
   stf_nn nn = nullptr;          // network for STF_X0_LEARNED (not owned)
   void* scratch = nullptr;      // this device's scratch array (allocation-free round)
   BatchState* batch = nullptr;  // state of the last stf_batch_solve (owned)
+  std::map<TuneKey, TuneEntry> tune;   // autotuned launch shapes (this device)
+  std::string arch;             // the device's architecture name (tune files)
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -615,6 +636,22 @@ void assemble_eps(stf_problem pb, const double* eps, int on_device) {
   pb->generation += 1;
 }
 
+// The autotuned shape of a level, or the built-in rule (kind 0) when the
+// context has none for its signature.
+FactorShape tuned_factor(stf_ctx c, const LevelArgs& a, size_t elem) {
+  auto it = c->tune.find(TuneKey{0, (int)elem, 0, a.nlevel, a.max_m, a.max_p});
+  if (it == c->tune.end()) return FactorShape{};
+  const FactorShape s{it->second.kind, it->second.a, it->second.b};
+  return factor_shape_ok(a, elem, s) ? s : FactorShape{};
+}
+
+SweepShape tuned_sweep(stf_ctx c, const LevelArgs& a, bool fwd, size_t elem, int nr) {
+  auto it = c->tune.find(TuneKey{fwd ? 1 : 2, (int)elem, nr, a.nlevel, a.max_m, a.max_p});
+  if (it == c->tune.end()) return SweepShape{};
+  const SweepShape s{it->second.kind, it->second.a, it->second.b, it->second.c};
+  return sweep_shape_ok(a, fwd, elem, nr, s) ? s : SweepShape{};
+}
+
 // Numeric factorisation of every level of a set; with `fault`, the first front
 // of tree level 1 gets the planted zero pivot column (test hook): its first
 // column carries fill in the update rows after assembly, so the perturbation
@@ -633,7 +670,8 @@ int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hip
     Timed t(c, K_FRONT_LU);
     LevelArgs la = mf.level_args(d, keps);
     if (fault && d == 1) la.fault = la.first;
-    launch_front_factor<T>(st, la, fac, mf.lpk.as<T>(), mf.upk.as<T>(), mf.piv.as<int>(), flag, tau);
+    launch_front_factor<T>(st, la, fac, mf.lpk.as<T>(), mf.upk.as<T>(), mf.piv.as<int>(), flag, tau,
+                           tuned_factor(c, la, sizeof(T)));
   }
   if (e1) HIP_CHECK(hipEventRecord(e1, st));
   HIP_CHECK(hipGetLastError());
@@ -670,11 +708,13 @@ void precond_launch(stf_ctx c, const Mf& mf, RhsSet r, T* vec, T* u, bool timed,
   const T* lpk = mf.lpk.as<T>();
   for (int d = mf.max_depth; d >= 0; --d) {
     Timed t(tc, K_SWEEP_FWD);
-    launch_sweep_fwd<T>(st, mf.level_args(d, nullptr, pact), lpk, mf.piv.as<int>(), vec, r);
+    const LevelArgs la = mf.level_args(d, nullptr, pact);
+    launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, r, tuned_sweep(c, la, true, sizeof(T), r.nr));
   }
   for (int d = 0; d <= mf.max_depth; ++d) {
     Timed t(tc, K_SWEEP_BWD);
-    launch_sweep_bwd<T>(st, mf.level_args(d, nullptr, pact), mf.upk.as<T>(), vec, u, r);
+    const LevelArgs la = mf.level_args(d, nullptr, pact);
+    launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, r, tuned_sweep(c, la, false, sizeof(T), r.nr));
   }
   Timed t(tc, K_SCATTER);
   launch_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.cover_x.as<int4>(), mf.cover_y.as<int4>(),
@@ -812,7 +852,7 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
       la.flist = sp.flist.as<int>();
       la.first = sp.lv[t][d].off;
       la.nlevel = sp.lv[t][d].n;
-      launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, rr);
+      launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, rr, tuned_sweep(c, la, true, sizeof(T), rr.nr));
     }
     for (int d = 0; d <= mf.max_depth; ++d) {
       if (sp.lv[t][d].n == 0) continue;
@@ -821,13 +861,186 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
       la.flist = sp.flist.as<int>();
       la.first = sp.lv[t][d].off;
       la.nlevel = sp.lv[t][d].n;
-      launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, rr);
+      launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, rr, tuned_sweep(c, la, false, sizeof(T), rr.nr));
     }
     Timed tm(tc, K_SCATTER);
     launch_stage_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.scat.as<ScatDev>(), mf.cover_x.as<int4>(),
                             mf.cover_y.as<int4>(), sl, sf, sc, mf.max_oxl, mf.max_oyl,
                             sp.inst.as<int>() + (size_t)t * mf.nsub, pact, r);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Autotuner: every candidate launch shape of every level is timed with HIP
+// events over `reps` passes (the fastest pass per shape counts, so the first
+// launch of a variant, which loads its code, does not), and the fastest shape
+// per level signature is kept in the context.  The factorisation trials run
+// whole factorisations (each re-assembles every front from keps, so passes
+// do not depend on each other); the sweep trials run the forward and backward
+// sweeps of whole rounds on zero right-hand sides (a round is a pure function
+// of its input).  Levels with fewer candidates repeat their last one.
+// ---------------------------------------------------------------------------
+struct EventSet {
+  std::vector<hipEvent_t> e;
+  explicit EventSet(size_t n) : e(n, nullptr) {
+    for (hipEvent_t& x : e) HIP_CHECK(hipEventCreate(&x));
+  }
+  ~EventSet() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+  double ms(size_t i, size_t j) const {
+    float v = 0.f;
+    HIP_CHECK(hipEventElapsedTime(&v, e[i], e[j]));
+    return v;
+  }
+};
+
+struct TuneTally {
+  int levels = 0, changed = 0;
+  double ms_default = 0.0, ms_tuned = 0.0;
+};
+
+// Keeps the fastest of `times` (one per candidate, candidate 0 = built-in).
+template <typename S>
+void tune_keep(stf_ctx c, const TuneKey& key, const std::vector<S>& cand, const std::vector<double>& times,
+               TuneTally& tally, TuneEntry (*enc)(const S&)) {
+  size_t best = 0;
+  for (size_t k = 1; k < cand.size(); ++k)
+    if (times[k] < times[best]) best = k;
+  TuneEntry e = enc(cand[best]);
+  e.ms = times[best];
+  e.ms_default = times[0];
+  c->tune[key] = e;
+  tally.levels += 1;
+  tally.changed += best != 0;
+  tally.ms_default += times[0];
+  tally.ms_tuned += times[best];
+}
+
+TuneEntry enc_factor(const FactorShape& s) { return TuneEntry{s.kind, s.nb, s.ntf, 0, 0.0, 0.0}; }
+TuneEntry enc_sweep(const SweepShape& s) { return TuneEntry{s.kind, s.kp, s.ntl, s.parts, 0.0, 0.0}; }
+
+template <typename T>
+void tune_factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, int reps, TuneTally& tally) {
+  hipStream_t st = c->stream;
+  const int L = mf.max_depth + 1;
+  std::vector<std::vector<FactorShape>> cand(L);
+  std::vector<std::vector<double>> best(L);
+  size_t ntr = 1;
+  for (int d = 0; d < L; ++d) {
+    cand[d] = factor_candidates(mf.level_args(d, keps), sizeof(T));
+    best[d].assign(cand[d].size(), 1e300);
+    ntr = std::max(ntr, cand[d].size());
+  }
+  const double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
+  EventSet ev((size_t)L + 1);
+  for (int rep = 0; rep < reps; ++rep)
+    for (size_t t = 0; t < ntr; ++t) {
+      HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
+      HIP_CHECK(hipEventRecord(ev.e[0], st));
+      for (int d = mf.max_depth, i = 1; d >= 0; --d, ++i) {
+        const size_t k = std::min(t, cand[d].size() - 1);
+        launch_front_factor<T>(st, mf.level_args(d, keps), mf.fac.as<T>(), mf.lpk.as<T>(), mf.upk.as<T>(),
+                               mf.piv.as<int>(), flag, tau, cand[d][k]);
+        HIP_CHECK(hipEventRecord(ev.e[i], st));
+      }
+      HIP_CHECK(hipEventSynchronize(ev.e[L]));
+      for (int d = mf.max_depth, i = 1; d >= 0; --d, ++i)
+        if (t < cand[d].size()) best[d][t] = std::min(best[d][t], ev.ms(i - 1, i));
+    }
+  for (int d = 0; d < L; ++d) {
+    const LevelArgs a = mf.level_args(d, keps);
+    tune_keep(c, TuneKey{0, (int)sizeof(T), 0, a.nlevel, a.max_m, a.max_p}, cand[d], best[d], tally,
+              enc_factor);
+  }
+}
+
+template <typename T>
+void tune_sweeps_mf(stf_ctx c, Mf& mf, int nr, long long ntot, int reps, TuneTally& tally) {
+  hipStream_t st = c->stream;
+  if (mf.ws_nr < nr) {
+    mf.vec.alloc((size_t)mf.vec_elems * sizeof(T) * nr);
+    mf.u.alloc((size_t)mf.u_elems * sizeof(T) * nr);
+    mf.ws_nr = nr;
+  }
+  DBuf v0;
+  v0.alloc((size_t)ntot * nr * sizeof(double2));
+  launch_zero(st, v0.as<double2>(), ntot * nr);
+  RhsSet r;
+  r.nr = nr;
+  r.vec_stride = mf.vec_elems;
+  r.u_stride = mf.u_elems;
+  for (int s = 0; s < nr; ++s) r.v[s] = v0.as<double2>() + (size_t)s * ntot;
+  const int L = mf.max_depth + 1;
+  std::vector<std::vector<SweepShape>> cand[2];
+  std::vector<std::vector<double>> best[2];
+  size_t ntr = 1;
+  for (int w = 0; w < 2; ++w) {
+    cand[w].resize(L);
+    best[w].resize(L);
+    for (int d = 0; d < L; ++d) {
+      cand[w][d] = sweep_candidates(mf.level_args(d, nullptr), w == 0, sizeof(T), nr);
+      best[w][d].assign(cand[w][d].size(), 1e300);
+      ntr = std::max(ntr, cand[w][d].size());
+    }
+  }
+  EventSet ev(2 * (size_t)L + 1);
+  T* vec = mf.vec.as<T>();
+  T* u = mf.u.as<T>();
+  for (int rep = 0; rep < reps; ++rep)
+    for (size_t t = 0; t < ntr; ++t) {
+      HIP_CHECK(hipEventRecord(ev.e[0], st));
+      int i = 1;
+      for (int d = mf.max_depth; d >= 0; --d, ++i) {
+        const size_t k = std::min(t, cand[0][d].size() - 1);
+        launch_sweep_fwd<T>(st, mf.level_args(d, nullptr), mf.lpk.as<T>(), mf.piv.as<int>(), vec, r,
+                            cand[0][d][k]);
+        HIP_CHECK(hipEventRecord(ev.e[i], st));
+      }
+      for (int d = 0; d <= mf.max_depth; ++d, ++i) {
+        const size_t k = std::min(t, cand[1][d].size() - 1);
+        launch_sweep_bwd<T>(st, mf.level_args(d, nullptr), mf.upk.as<T>(), vec, u, r, cand[1][d][k]);
+        HIP_CHECK(hipEventRecord(ev.e[i], st));
+      }
+      HIP_CHECK(hipEventSynchronize(ev.e[2 * L]));
+      i = 1;
+      for (int d = mf.max_depth; d >= 0; --d, ++i)
+        if (t < cand[0][d].size()) best[0][d][t] = std::min(best[0][d][t], ev.ms(i - 1, i));
+      for (int d = 0; d <= mf.max_depth; ++d, ++i)
+        if (t < cand[1][d].size()) best[1][d][t] = std::min(best[1][d][t], ev.ms(i - 1, i));
+    }
+  HIP_CHECK(hipStreamSynchronize(st));
+  for (int w = 0; w < 2; ++w)
+    for (int d = 0; d < L; ++d) {
+      const LevelArgs a = mf.level_args(d, nullptr);
+      tune_keep(c, TuneKey{w == 0 ? 1 : 2, (int)sizeof(T), nr, a.nlevel, a.max_m, a.max_p}, cand[w][d],
+                best[w][d], tally, enc_sweep);
+    }
+}
+
+// Sets every level's entry of a set to candidate `index` (clamped per level);
+// returns the largest candidate count.
+template <typename T>
+int tune_pick_mf(stf_ctx c, Mf& mf, const double2* keps, int nr, int what, int index) {
+  int most = 0;
+  for (int d = 0; d <= mf.max_depth; ++d) {
+    const LevelArgs a = mf.level_args(d, keps);
+    if (what & 1) {
+      const auto cand = factor_candidates(a, sizeof(T));
+      most = std::max(most, (int)cand.size());
+      TuneEntry e = enc_factor(cand[std::min<size_t>(index, cand.size() - 1)]);
+      c->tune[TuneKey{0, (int)sizeof(T), 0, a.nlevel, a.max_m, a.max_p}] = e;
+    }
+    if (what & 2)
+      for (int w = 0; w < 2; ++w) {
+        const auto cand = sweep_candidates(a, w == 0, sizeof(T), nr);
+        most = std::max(most, (int)cand.size());
+        TuneEntry e = enc_sweep(cand[std::min<size_t>(index, cand.size() - 1)]);
+        c->tune[TuneKey{w == 0 ? 1 : 2, (int)sizeof(T), nr, a.nlevel, a.max_m, a.max_p}] = e;
+      }
+  }
+  return most;
 }
 
 // Entries of the front vectors and of the local fields of one right-hand side
@@ -2035,6 +2248,10 @@ stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
       HIP_CHECK(hipEventCreateWithFlags(&c->iter_ev[e], hipEventDisableTiming));
     HIP_CHECK(hipEventCreateWithFlags(&c->cycle_ev, hipEventDisableTiming));
     c->scratch = scratch_address(device);
+    hipDeviceProp_t prop;
+    HIP_CHECK(hipGetDeviceProperties(&prop, device));
+    c->arch = prop.gcnArchName;
+    c->arch = c->arch.substr(0, c->arch.find(':'));     // gfx950, without feature flags
   });
   if (s != STF_OK) {
     g_noctx_error = c->last_error;
@@ -2102,6 +2319,48 @@ stf_status stf_plan_query(const stf_params* prm, stf_plan_info* out) {
   try {
     Plan pl = build_plan(*prm, nullptr);
     *out = plan_info(pl);
+    return STF_OK;
+  } catch (const Error& e) {
+    return e.code;
+  } catch (...) {
+    return STF_EINVAL;
+  }
+}
+
+stf_status stf_debug_level_shapes(const stf_params* prm, int32_t nrhs, int32_t* nlevels,
+                                  int32_t* ncandidates, int32_t* invalid) {
+  if (!prm || nrhs < 1 || nrhs > MAX_RHS) return STF_EINVAL;
+  try {
+    Plan pl = build_plan(*prm, nullptr);
+    std::vector<LevelArgs> lv;
+    for (const SubDesc& s : pl.subs)
+      for (const SymFront& f : pl.shapes[s.shape]->fronts) {
+        if ((int)lv.size() <= f.depth) lv.resize(f.depth + 1, LevelArgs{});
+        LevelArgs& a = lv[f.depth];
+        a.nlevel += 1;
+        a.max_m = std::max(a.max_m, f.p + f.q);
+        a.max_p = std::max(a.max_p, f.p);
+        a.max_pm = std::max(a.max_pm, f.p * (f.p + f.q));
+      }
+    int cands = 0, bad = 0;
+    const size_t elem = prm->front_prec == STF_C64 ? 8 : 16;
+    for (const LevelArgs& a : lv) {
+      bad += !factor_shape_ok(a, elem, factor_default(a, elem));
+      for (const FactorShape& f : factor_candidates(a, elem)) {
+        ++cands;
+        bad += !factor_shape_ok(a, elem, f);
+      }
+      for (int w = 0; w < 2; ++w) {
+        bad += !sweep_shape_ok(a, w == 0, elem, nrhs, sweep_default(a, w == 0, elem));
+        for (const SweepShape& sh : sweep_candidates(a, w == 0, elem, nrhs)) {
+          ++cands;
+          bad += !sweep_shape_ok(a, w == 0, elem, nrhs, sh);
+        }
+      }
+    }
+    if (nlevels) *nlevels = (int32_t)lv.size();
+    if (ncandidates) *ncandidates = cands;
+    if (invalid) *invalid = bad;
     return STF_OK;
   } catch (const Error& e) {
     return e.code;
@@ -2596,6 +2855,168 @@ stf_status stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,
     return STF_EPIVOT;
   }
   return worst;
+}
+
+stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
+                        int32_t what, int32_t reps, stf_tune_report* report) {
+  if (!ctx) return STF_EINVAL;
+  if (report) *report = stf_tune_report{0, 0, 0.0, 0.0};
+  return guard(ctx, [&] {
+    STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
+    STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
+    STF_REQUIRE(what >= 1 && what <= 3, "what: 1 factorisation, 2 sweeps, 3 both");
+    STF_REQUIRE(reps >= 1 && reps <= 100, "reps must be 1..100");
+    for (int p = 0; p < nprob; ++p) {
+      STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
+      if (!probs[p]->assembled) throw Error(STF_ESTATE, "autotune before assemble");
+      STF_REQUIRE(probs[p]->prec == probs[0]->prec, "all problems need one front precision");
+      for (int q = 0; q < p; ++q) STF_REQUIRE(probs[q] != probs[p], "a problem appears twice");
+    }
+    const bool c64 = probs[0]->prec == STF_C64;
+    TuneTally tally;
+    auto run = [&](Mf& mf, const double2* keps, int* flag, long long ntot) {
+      if (c64) {
+        if (what & 1) tune_factor_mf<float2>(ctx, mf, keps, flag, reps, tally);
+        factor_mf<float2>(ctx, mf, keps, flag, false, nullptr, nullptr);
+        if (what & 2) tune_sweeps_mf<float2>(ctx, mf, nrhs, ntot, reps, tally);
+      } else {
+        if (what & 1) tune_factor_mf<double2>(ctx, mf, keps, flag, reps, tally);
+        factor_mf<double2>(ctx, mf, keps, flag, false, nullptr, nullptr);
+        if (what & 2) tune_sweeps_mf<double2>(ctx, mf, nrhs, ntot, reps, tally);
+      }
+    };
+    if (nprob == 1) {
+      stf_problem pb = probs[0];
+      run(pb->ensure_mf(), pb->keps.as<double2>(), pb->flag.as<int>(), pb->N);
+      pb->factored = true;
+      pb->fac_timed = false;
+    } else {
+      BatchState& bs = batch_state(ctx, nprob, probs);
+      run(bs.mf, bs.keps.as<double2>(), bs.flag.as<int>(), bs.ntot);
+    }
+    // a captured batch cycle holds the shapes of its capture
+    if (ctx->batch) ctx->batch->release_graph();
+    HIP_CHECK(hipStreamSynchronize(ctx->stream));
+    if (report) *report = stf_tune_report{tally.levels, tally.changed, tally.ms_default, tally.ms_tuned};
+  });
+}
+
+
+stf_status stf_tune_pick(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
+                         int32_t what, int32_t index, int32_t* max_candidates) {
+  if (!ctx) return STF_EINVAL;
+  return guard(ctx, [&] {
+    STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
+    STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
+    STF_REQUIRE(what >= 1 && what <= 3, "what: 1 factorisation, 2 sweeps, 3 both");
+    STF_REQUIRE(index >= 0, "candidate index must be >= 0");
+    for (int p = 0; p < nprob; ++p) {
+      STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
+      if (!probs[p]->assembled) throw Error(STF_ESTATE, "tune_pick before assemble");
+      STF_REQUIRE(probs[p]->prec == probs[0]->prec, "all problems need one front precision");
+    }
+    Mf* mf = nullptr;
+    const double2* keps = nullptr;
+    if (nprob == 1) {
+      mf = &probs[0]->ensure_mf();
+      keps = probs[0]->keps.as<double2>();
+    } else {
+      BatchState& bs = batch_state(ctx, nprob, probs);
+      mf = &bs.mf;
+      keps = bs.keps.as<double2>();
+    }
+    const int most = probs[0]->prec == STF_C64 ? tune_pick_mf<float2>(ctx, *mf, keps, nrhs, what, index)
+                                               : tune_pick_mf<double2>(ctx, *mf, keps, nrhs, what, index);
+    if (ctx->batch) ctx->batch->release_graph();
+    if (max_candidates) *max_candidates = most;
+  });
+}
+
+stf_status stf_tune_save(stf_ctx ctx, const char* path) {
+  if (!ctx) return STF_EINVAL;
+  return guard(ctx, [&] {
+    STF_REQUIRE(path != nullptr, "null path");
+    FILE* f = std::fopen(path, "w");
+    STF_REQUIRE(f != nullptr, "cannot open the tune file for writing");
+    bool ok = std::fprintf(f, "stfdfd-tune 1 %s %zu\n", ctx->arch.c_str(), ctx->tune.size()) > 0;
+    for (const auto& kv : ctx->tune) {
+      const TuneKey& k = kv.first;
+      const TuneEntry& e = kv.second;
+      ok = ok && std::fprintf(f, "%d %d %d %d %d %d %d %d %d %d %.9g %.9g\n", k.op, k.elem, k.nr, k.nlevel,
+                              k.max_m, k.max_p, e.kind, e.a, e.b, e.c, e.ms, e.ms_default) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    STF_REQUIRE(ok, "writing the tune file failed");
+  });
+}
+
+stf_status stf_tune_load(stf_ctx ctx, const char* path) {
+  if (!ctx) return STF_EINVAL;
+  return guard(ctx, [&] {
+    STF_REQUIRE(path != nullptr, "null path");
+    FILE* f = std::fopen(path, "r");
+    STF_REQUIRE(f != nullptr, "cannot open the tune file");
+    std::map<TuneKey, TuneEntry> got;
+    char magic[32] = {0}, arch[128] = {0};
+    int version = 0;
+    long long count = -1;
+    bool ok = std::fscanf(f, "%31s %d %127s %lld", magic, &version, arch, &count) == 4 &&
+              std::string(magic) == "stfdfd-tune" && version == 1 && count >= 0 && count <= 1000000;
+    std::string why = ok ? "" : "not a tune file (bad header)";
+    if (ok && ctx->arch != arch) {
+      ok = false;
+      why = std::string("tune file is for ") + arch + ", this device is " + ctx->arch;
+    }
+    for (long long i = 0; ok && i < count; ++i) {
+      TuneKey k{};
+      TuneEntry e{};
+      ok = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf %lf", &k.op, &k.elem, &k.nr, &k.nlevel,
+                       &k.max_m, &k.max_p, &e.kind, &e.a, &e.b, &e.c, &e.ms, &e.ms_default) == 12;
+      ok = ok && k.op >= 0 && k.op <= 2 && (k.elem == 8 || k.elem == 16) &&
+           (k.op == 0 ? k.nr == 0 : (k.nr >= 1 && k.nr <= MAX_RHS)) && k.nlevel >= 1 && k.max_m >= 1 &&
+           k.max_p >= 0 && k.max_p <= k.max_m && e.kind >= 1 && e.kind <= 2 && std::isfinite(e.ms) &&
+           std::isfinite(e.ms_default);
+      if (ok) got[k] = e;
+      else why = "malformed tune file entry";
+    }
+    std::fclose(f);
+    STF_REQUIRE(ok, why);
+    for (const auto& kv : got) ctx->tune[kv.first] = kv.second;
+    if (ctx->batch) ctx->batch->release_graph();
+  });
+}
+
+stf_status stf_tune_clear(stf_ctx ctx) {
+  if (!ctx) return STF_EINVAL;
+  return guard(ctx, [&] {
+    ctx->tune.clear();
+    if (ctx->batch) ctx->batch->release_graph();
+  });
+}
+
+int32_t stf_tune_count(stf_ctx ctx) { return ctx ? (int32_t)ctx->tune.size() : -1; }
+
+stf_status stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms) {
+  if (!ctx) return STF_EINVAL;
+  return guard(ctx, [&] {
+    STF_REQUIRE(i >= 0 && i < (int32_t)ctx->tune.size(), "tune entry index out of range");
+    auto it = ctx->tune.begin();
+    std::advance(it, i);
+    const TuneKey& k = it->first;
+    const TuneEntry& e = it->second;
+    if (key) {
+      const int32_t v[6] = {k.op, k.elem, k.nr, k.nlevel, k.max_m, k.max_p};
+      std::copy(v, v + 6, key);
+    }
+    if (shape) {
+      const int32_t v[4] = {e.kind, e.a, e.b, e.c};
+      std::copy(v, v + 4, shape);
+    }
+    if (ms) {
+      ms[0] = e.ms;
+      ms[1] = e.ms_default;
+    }
+  });
 }
 
 stf_status stf_problem_info(stf_problem pb, stf_plan_info* out) {

@@ -883,16 +883,16 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
 // the bulk of the front's traffic instead of preceding it.
 // ---------------------------------------------------------------------------
 
-// sum over c = c0, c0+step, ... < c1 with c >= cmin of A[ad(c)] * x[c], with
-// the global loads issued in predicated batches of LB, so that every batch
-// (the last, partial one included) costs one memory round trip.  The column
-// sequence does not depend on the row, so the lanes of a wavefront read the
-// same column (contiguous rows) at every step.
-template <typename T, typename Addr>
-__device__ inline T gather_dot(const T* __restrict__ A, Addr ad, int c0, int cmin, int c1, int step,
-                               const T* x) {
+// sum over k = c0, c0 + step, ... < c1 with k >= cmin of A[ad(k)] x_s[k] for
+// NR vectors x_s = x + s xs at once, added to acc[s]: the global loads are
+// issued in predicated batches of LB, so that every batch (the last, partial
+// one included) costs one memory round trip, and each term is loaded once for
+// all right-hand sides.  The column sequence does not depend on the row, so the
+// lanes of a wavefront read the same column (contiguous rows) at every step.
+template <typename T, int NR, typename Addr>
+__device__ inline void gather_dot_nr(const T* __restrict__ A, Addr ad, int c0, int cmin, int c1,
+                                     int step, const T* x, int xs, T (&acc)[NR]) {
   constexpr int LB = 8;
-  T acc0 = czero<T>(), acc1 = czero<T>();
   for (int c = c0; c < c1; c += LB * step) {
     T av[LB];
 #pragma unroll
@@ -901,17 +901,19 @@ __device__ inline T gather_dot(const T* __restrict__ A, Addr ad, int c0, int cmi
       av[t] = (k >= cmin && k < c1) ? A[ad(k)] : czero<T>();
     }
 #pragma unroll
-    for (int t = 0; t < LB; t += 2) {
+    for (int t = 0; t < LB; ++t) {
       const int k = c + t * step;
-      if (k >= cmin && k < c1) acc0 = cfma(av[t], x[k], acc0);
-      if (k + step >= cmin && k + step < c1) acc1 = cfma(av[t + 1], x[k + step], acc1);
+      if (k >= cmin && k < c1)
+#pragma unroll
+        for (int s = 0; s < NR; ++s) acc[s] = cfma(av[t], x[s * xs + k], acc[s]);
     }
   }
-  return cadd(acc0, acc1);
 }
 
 // The first KP terms of a strided dot product, A[ad(k0 + G t)] for t < KP and
-// kmin <= k0 + G t < kend, held in registers; dot() adds the rest from memory.
+// kmin <= k0 + G t < kend, held in registers; dot_nr() forms the whole sum for
+// NR right-hand sides, taking the terms beyond the first KP from memory (once
+// for all of them).
 template <typename T, int KP>
 struct ColPrefetch {
   T av[KP];
@@ -923,20 +925,21 @@ struct ColPrefetch {
       av[t] = (k >= kmin && k < kend) ? A[ad(k)] : czero<T>();
     }
   }
-  // sum over k = k0, k0 + G, ... < kend with k >= kmin of A[ad(k)] x[k]
-  template <typename Addr>
-  __device__ inline T dot(const T* __restrict__ A, Addr ad, int k0, int kmin, int kend, int G,
-                          const T* x) const {
-    T acc0 = czero<T>(), acc1 = czero<T>();
+  // acc[s] = sum over k = k0, k0 + G, ... < kend with k >= kmin of A[ad(k)] x_s[k]
+  template <int NR, typename Addr>
+  __device__ inline void dot_nr(const T* __restrict__ A, Addr ad, int k0, int kmin, int kend, int G,
+                                const T* x, int xs, T (&acc)[NR]) const {
 #pragma unroll
-    for (int t = 0; t < KP; t += 2) {
+    for (int s = 0; s < NR; ++s) acc[s] = czero<T>();
+#pragma unroll
+    for (int t = 0; t < KP; ++t) {
       const int k = k0 + G * t;
-      if (k >= kmin && k < kend) acc0 = cfma(av[t], x[k], acc0);
-      if (k + G >= kmin && k + G < kend) acc1 = cfma(av[t + 1], x[k + G], acc1);
+      if (k >= kmin && k < kend)
+#pragma unroll
+        for (int s = 0; s < NR; ++s) acc[s] = cfma(av[t], x[s * xs + k], acc[s]);
     }
     const int kt = k0 + G * KP;
-    if (kt < kend) acc0 = cadd(acc0, gather_dot(A, ad, kt, kmin, kend, G, x));
-    return cadd(acc0, acc1);
+    if (kt < kend) gather_dot_nr<T, NR>(A, ad, kt, kmin, kend, G, x, xs, acc);
   }
 };
 
@@ -1029,12 +1032,13 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   for (int i = 0; i < RPL; ++i) {
     const int r = rl + 64 * i;
     const int kend = r < m ? min(r, p) : 0;
+    T acc[NR];
+    pf[i].template dot_nr<NR>(L, LowerAt{m, r}, g, 0, kend, G, &sh[wv][0][0], MW, acc);
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
-      T acc = pf[i].dot(L, LowerAt{m, r}, g, 0, kend, G, sh[wv][s]);
       if (RPL == 1)
-        for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-      if (g == 0 && r < m) vec[s * rs.vec_stride + f.vec_off + r] = cadd(sh[wv][s][r], acc);
+        for (int o = W; o < 64; o <<= 1) acc[s] = cadd(acc[s], shfl_xor_c(acc[s], o));
+      if (g == 0 && r < m) vec[s * rs.vec_stride + f.vec_off + r] = cadd(sh[wv][s][r], acc[s]);
     }
   }
 }
@@ -1089,12 +1093,10 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
   wave_sync();
   const long long uo = a.subs[f.sub].u_off;
   T xp[NR];
+  pf.template dot_nr<NR>(U, UpperAt{p, r}, g, r, r < p ? m : 0, G, &sh[wv][0][0], 128, xp);
 #pragma unroll
-  for (int s = 0; s < NR; ++s) {
-    T acc = pf.dot(U, UpperAt{p, r}, g, r, r < p ? m : 0, G, sh[wv][s]);
-    for (int o = W; o < 64; o <<= 1) acc = cadd(acc, shfl_xor_c(acc, o));
-    xp[s] = acc;
-  }
+  for (int s = 0; s < NR; ++s)
+    for (int o = W; o < 64; o <<= 1) xp[s] = cadd(xp[s], shfl_xor_c(xp[s], o));
   wave_sync();
 #pragma unroll
   for (int s = 0; s < NR; ++s)
@@ -1244,15 +1246,18 @@ __global__ __launch_bounds__(NTL) void k_fwd_large(LevelArgs a, const T* __restr
     for (int s = 0; s < NR; ++s) vl[s * mm + i] = tmp[s * mm + i];
   __syncthreads();
   T acc[NR];
-#pragma unroll
-  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(L, LowerAt{m, rr}, g, 0, min(rr, p), G, vl + s * mm) : czero<T>();
+  pf.template dot_nr<NR>(L, LowerAt{m, rr}, g, 0, act ? min(rr, p) : 0, G, vl, mm, acc);
   if (G == 1) {
+    if (act)
 #pragma unroll
-    for (int s = 0; s < NR; ++s) {
-      T* out = vec + s * rs.vec_stride + f.vec_off;
-      if (act) out[rr] = cadd(vl[s * mm + rr], acc[s]);
-      for (int r = rr + NTL; r < r1; r += NTL)
-        out[r] = cadd(vl[s * mm + r], gather_dot(L, LowerAt{m, r}, 0, 0, min(r, p), 1, vl + s * mm));
+      for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.vec_off + rr] = cadd(vl[s * mm + rr], acc[s]);
+    for (int r = rr + NTL; r < r1; r += NTL) {
+      T ext[NR];
+#pragma unroll
+      for (int s = 0; s < NR; ++s) ext[s] = czero<T>();
+      gather_dot_nr<T, NR>(L, LowerAt{m, r}, 0, 0, min(r, p), 1, vl, mm, ext);
+#pragma unroll
+      for (int s = 0; s < NR; ++s) vec[s * rs.vec_stride + f.vec_off + r] = cadd(vl[s * mm + r], ext[s]);
     }
   } else {
 #pragma unroll
@@ -1319,17 +1324,21 @@ __global__ __launch_bounds__(NTL) void k_bwd_large(LevelArgs a, const T* __restr
   __syncthreads();
   const long long uo = a.subs[f.sub].u_off;
   T acc[NR];
-#pragma unroll
-  for (int s = 0; s < NR; ++s) acc[s] = act ? pf.dot(U, UpperAt{p, rr}, g, rr, m, G, vl + s * mm) : czero<T>();
+  pf.template dot_nr<NR>(U, UpperAt{p, rr}, g, rr, act ? m : 0, G, vl, mm, acc);
   if (G == 1) {
     // rows beyond NTL (p > NTL): written to the front vector now, read back below
-    for (int r = rr + NTL; r < r1; r += NTL)
+    for (int r = rr + NTL; r < r1; r += NTL) {
+      T x[NR];
+#pragma unroll
+      for (int s = 0; s < NR; ++s) x[s] = czero<T>();
+      gather_dot_nr<T, NR>(U, UpperAt{p, r}, 0, r, m, 1, vl, mm, x);
+      const int vr = vars[r];
 #pragma unroll
       for (int s = 0; s < NR; ++s) {
-        const T x = gather_dot(U, UpperAt{p, r}, 0, r, m, 1, vl + s * mm);
-        vec[s * rs.vec_stride + f.vec_off + r] = x;
-        u[s * rs.u_stride + uo + vars[r]] = x;
+        vec[s * rs.vec_stride + f.vec_off + r] = x[s];
+        u[s * rs.u_stride + uo + vr] = x[s];
       }
+    }
   } else {
 #pragma unroll
     for (int s = 0; s < NR; ++s) scr[s * NTL + tid] = acc[s];
@@ -1554,20 +1563,42 @@ int max_lds() {
         v > 0)
       g_max_lds = v;
     else
-      g_max_lds = 65536;
+      g_max_lds = 163840;          // gfx950: 160 KiB of LDS per workgroup (no device: host checks)
   }
   return g_max_lds;
 }
 
+// LDS bytes of the panel kernel with NB-column panels on a level.
+size_t panel_lds(const LevelArgs& a, size_t elem, int nb) {
+  return std::max((size_t)a.max_m * nb, (size_t)DIB * DIB + 2 * DIB + (size_t)CR * DIB) * elem;
+}
+// Static LDS of the panel kernel besides the dynamic panel (staged U chunk,
+// pivot and reduction arrays), bounded.
+size_t panel_static_lds(size_t elem) { return (size_t)UC * 33 * elem + 512; }
+
 template <typename T, int NB, int NTF = NT>
 void large_launch(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
                   double tau) {
-  size_t lds = std::max((size_t)a.max_m * NB, (size_t)DIB * DIB + 2 * DIB + (size_t)CR * DIB) * sizeof(T);
+  const size_t lds = panel_lds(a, sizeof(T), NB);
   hipLaunchKernelGGL((k_factor_large<T, NB, NTF>), dim3(a.nlevel), dim3(NTF), lds, st, a, fac, lpk,
                      upk, piv, flag, tau);
 }
 
 }  // namespace
+
+int g_num_cus = 0;
+int num_cus() {
+  if (g_num_cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        v > 0)
+      g_num_cus = v;
+    else
+      g_num_cus = 256;
+  }
+  return g_num_cus;
+}
 
 int small_factor_limit(size_t elem) {
   // Largest front order whose m x m block (plus two 64-entry buffers) fits
@@ -1577,27 +1608,21 @@ int small_factor_limit(size_t elem) {
   return std::min(lim, 64);
 }
 
-template <typename T>
-void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
-                         double tau) {
-  if (a.max_m <= small_factor_limit(sizeof(T))) {
-    size_t lds = ((size_t)a.max_m * a.max_m + 128) * sizeof(T);
-    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, lpk, upk, piv, flag,
-                       tau);
-    return;
-  }
+// The built-in choice for a level.
+FactorShape factor_default(const LevelArgs& a, size_t elem) {
+  if (a.max_m <= small_factor_limit(elem)) return FactorShape{1, 0, 64};
   // Panel width: as wide as the LDS allows for the largest front of the level
   // (the staged U chunk and small arrays take the rest).
-  const size_t budget = (size_t)max_lds() - (size_t)UC * 33 * sizeof(T) - 512;
-  const size_t per_col = (size_t)a.max_m * sizeof(T);
+  const size_t budget = (size_t)max_lds() - panel_static_lds(elem);
+  const size_t per_col = (size_t)a.max_m * elem;
   // Fronts of order <= 256: panels as wide as the separator where that fits,
   // so that the Schur complement is updated in fewer passes, except for
   // complex64 fronts of order <= 128, whose levels hold thousands of fronts
   // and keep 8-column panels (fewer registers, more workgroups per CU).
-  int nb_max = sizeof(T) == 16 ? 16 : 32;
+  int nb_max = elem == 16 ? 16 : 32;
   int one = 1;
   while (one < a.max_p) one *= 2;
-  if (a.max_m <= 128 && sizeof(T) == 8) nb_max = 8;
+  if (a.max_m <= 128 && elem == 8) nb_max = 8;
   else if (a.max_m <= 256) nb_max = std::min(nb_max, one);
   int nb = 1;
   while (nb * 2 <= nb_max && per_col * nb * 2 <= budget) nb *= 2;
@@ -1605,12 +1630,66 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* 
   // Levels with at most one front per CU: four times the threads per front
   // (the serial chain of a front is the level's time), with 16-column panels
   // (8 in FP64) so that a thread fits in 128 registers.
-  constexpr int NB1K = sizeof(T) == 8 ? 16 : 8;
-  if (a.nlevel <= 256 && nb >= NB1K) {
+  const int nb1k = elem == 8 ? 16 : 8;
+  if (a.nlevel <= 256 && nb >= nb1k) return FactorShape{2, nb1k, 1024};
+  return FactorShape{2, nb, NT};
+}
+
+bool factor_shape_ok(const LevelArgs& a, size_t elem, const FactorShape& s) {
+  if (s.kind == 0) return true;
+  if (s.kind == 1) return s.ntf == 64 && a.max_m <= small_factor_limit(elem);
+  if (s.kind != 2) return false;
+  const int nb1k = elem == 8 ? 16 : 8;
+  const bool inst = (s.ntf == NT && (s.nb == 1 || s.nb == 2 || s.nb == 4 || s.nb == 8 || s.nb == 16 ||
+                                     s.nb == 32)) ||
+                    (s.ntf == 1024 && s.nb == nb1k);
+  if (!inst) return false;
+  if (panel_lds(a, elem, s.nb) + panel_static_lds(elem) > (size_t)max_lds()) return false;
+  return true;
+}
+
+std::vector<FactorShape> factor_candidates(const LevelArgs& a, size_t elem) {
+  std::vector<FactorShape> out;
+  const FactorShape d = factor_default(a, elem);
+  out.push_back(d);
+  auto add = [&](FactorShape s) {
+    if (!factor_shape_ok(a, elem, s)) return;
+    for (const FactorShape& o : out)
+      if (o.kind == s.kind && o.nb == s.nb && o.ntf == s.ntf) return;
+    out.push_back(s);
+  };
+  if (a.max_m <= small_factor_limit(elem)) {
+    // the LDS kernel, or the panel kernel with narrow panels
+    add(FactorShape{2, 4, NT});
+    add(FactorShape{2, 8, NT});
+    return out;
+  }
+  const int nb1k = elem == 8 ? 16 : 8;
+  for (int nb : {8, 16, 32}) {
+    if (elem == 16 && nb > 16) continue;
+    add(FactorShape{2, nb, NT});
+  }
+  if (a.nlevel <= 4 * num_cus()) add(FactorShape{2, nb1k, 1024});
+  return out;
+}
+
+template <typename T>
+void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
+                         double tau, FactorShape sh) {
+  if (sh.kind == 0) sh = factor_default(a, sizeof(T));
+  if (!factor_shape_ok(a, sizeof(T), sh)) throw Error(STF_EINVAL, "factorisation launch shape not valid for the level");
+  if (sh.kind == 1) {
+    size_t lds = ((size_t)a.max_m * a.max_m + 128) * sizeof(T);
+    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, lpk, upk, piv, flag,
+                       tau);
+    return;
+  }
+  if (sh.ntf == 1024) {
+    constexpr int NB1K = sizeof(T) == 8 ? 16 : 8;
     large_launch<T, NB1K, 1024>(st, a, fac, lpk, upk, piv, flag, tau);
     return;
   }
-  switch (nb) {
+  switch (sh.nb) {
     case 32: large_launch<T, 32>(st, a, fac, lpk, upk, piv, flag, tau); break;
     case 16: large_launch<T, 16>(st, a, fac, lpk, upk, piv, flag, tau); break;
     case 8: large_launch<T, 8>(st, a, fac, lpk, upk, piv, flag, tau); break;
@@ -1632,19 +1711,6 @@ inline int prefetch_depth(int need, int cap) {
 // threads with which the level's nwg workgroups all fit in one round at
 // sixteen wavefronts per CU (the latency of one front is the level's time, so a
 // second round costs more than narrower workgroups do); at least 256.
-int g_num_cus = 0;
-int num_cus() {
-  if (g_num_cus == 0) {
-    int dev = 0, v = 0;
-    if (hipGetDevice(&dev) == hipSuccess &&
-        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        v > 0)
-      g_num_cus = v;
-    else
-      g_num_cus = 256;
-  }
-  return g_num_cus;
-}
 inline int large_threads(int nwg) {
   const long long budget = 16LL * num_cus();             // resident wavefronts
   int ntl = 256;
@@ -1738,68 +1804,141 @@ void check_rhs(const RhsSet& r) {
   if (r.nr < 1 || r.nr > MAX_RHS) throw Error(STF_EINVAL, "1 to 4 right-hand sides per sweep");
 }
 
-template <typename T>
-void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
-                      const RhsSet& r) {
-  check_rhs(r);
-  const int cap = sizeof(T) == 8 ? 32 : 16;      // registers per lane for the prefetch
-  if (a.max_m <= 128 && a.max_p <= 64) {
-    // Wavefront kernels: at most 16 prefetched terms per lane (about 60
-    // registers), so that eight wavefronts per SIMD hide the gather latency.
-    const int cap = 16;
-    // A lane row takes at most min(r, p) <= max_p columns.
-    const int rpl = a.max_m <= 64 ? 1 : 2;
-    const int kp = prefetch_depth(a.max_p, cap / rpl);
-    if (rpl == 1) {
-      if (kp == 8) fwd_wave_launch<T, 1, 8>(st, a, fac, piv, vec, r);
-      else if (kp == 16) fwd_wave_launch<T, 1, 16>(st, a, fac, piv, vec, r);
-      else fwd_wave_launch<T, 1, (sizeof(T) == 8 ? 32 : 16)>(st, a, fac, piv, vec, r);
-    } else {
-      if (kp == 8) fwd_wave_launch<T, 2, 8>(st, a, fac, piv, vec, r);
-      else fwd_wave_launch<T, 2, (sizeof(T) == 8 ? 16 : 8)>(st, a, fac, piv, vec, r);
-    }
-    return;
-  }
-  // The rows of each front in `parts` workgroups; a row takes at most p columns.
-  const int parts = sweep_parts(a.nlevel, a.max_m);
-  const int ntl = large_threads(a.nlevel * parts);
-  const int rows = (a.max_m + parts - 1) / parts;
-  const int g = std::max(1, ntl / rows);
-  // A level of more workgroups than one round at four wavefronts per SIMD holds
-  // sixteen terms per lane (about 70 registers, seven wavefronts per SIMD).
-  const bool many = (long long)a.nlevel * parts * (ntl / 64) > 16LL * num_cus();
-  const int kp = prefetch_depth((a.max_p + g - 1) / g, many ? 16 : cap);
-  if (ntl == 256) fwd_large_launch<T, 256>(st, a, parts, kp, fac, piv, vec, r);
-  else if (ntl == 512) fwd_large_launch<T, 512>(st, a, parts, kp, fac, piv, vec, r);
-  else fwd_large_launch<T, 1024>(st, a, parts, kp, fac, piv, vec, r);
+// Levels the one-wavefront sweep kernels take: m <= 128 (two rows per lane,
+// or a 128-entry vector per wavefront backwards) and p <= 64 (a pivot or
+// separator row per lane).
+bool wave_level(const LevelArgs& a) { return a.max_m <= 128 && a.max_p <= 64; }
+
+// Instantiated prefetch depths: wavefront kernels 8, 16, 32 (complex64) or
+// 8, 16 (complex128), halved for two rows per lane; workgroup kernels 16, 32
+// (complex64) or 16.
+int wave_kp_max(size_t elem, int rpl) { return (elem == 8 ? 32 : 16) / rpl; }
+int large_kp_max(size_t elem) { return elem == 8 ? 32 : 16; }
+
+size_t sweep_lds(const LevelArgs& a, bool fwd, size_t elem, int nr, int ntl) {
+  return ((size_t)nr * ntl + (fwd ? 2 : 1) * (size_t)nr * a.max_m) * elem;
 }
 
-template <typename T>
-void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
-                      const RhsSet& r) {
-  check_rhs(r);
-  const int cap = sizeof(T) == 8 ? 32 : 16;
-  if (a.max_m <= 128 && a.max_p <= 64) {
-    const int cap = 16;                          // as in the forward sweep
+SweepShape sweep_default(const LevelArgs& a, bool fwd, size_t elem) {
+  const int cap = elem == 8 ? 32 : 16;           // registers per lane for the prefetch
+  if (wave_level(a)) {
+    // Wavefront kernels: at most 16 prefetched terms per lane (about 60
+    // registers), so that eight wavefronts per SIMD hide the gather latency.
+    if (fwd) {
+      // A lane row takes at most min(r, p) <= max_p columns.
+      const int rpl = a.max_m <= 64 ? 1 : 2;
+      return SweepShape{1, prefetch_depth(a.max_p, 16 / rpl), 64, 1};
+    }
     // Row groups: W >= max_p lanes, so G >= 64 / W groups share a row's columns.
     int w = 4;
     while (w < a.max_p) w *= 2;
     const int g = 64 / w;
-    const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
-    if (kp == 8) bwd_wave_launch<T, 8>(st, a, upk, vec, u, r);
-    else if (kp == 16) bwd_wave_launch<T, 16>(st, a, upk, vec, u, r);
-    else bwd_wave_launch<T, (sizeof(T) == 8 ? 32 : 16)>(st, a, upk, vec, u, r);
-    return;
+    return SweepShape{1, prefetch_depth((a.max_m + g - 1) / g, 16), 64, 1};
+  }
+  if (fwd) {
+    // The rows of each front in `parts` workgroups; a row takes at most p columns.
+    const int parts = sweep_parts(a.nlevel, a.max_m);
+    const int ntl = large_threads(a.nlevel * parts);
+    const int rows = (a.max_m + parts - 1) / parts;
+    const int g = std::max(1, ntl / rows);
+    // A level of more workgroups than one round at four wavefronts per SIMD holds
+    // sixteen terms per lane (about 70 registers, seven wavefronts per SIMD).
+    const bool many = (long long)a.nlevel * parts * (ntl / 64) > 16LL * num_cus();
+    return SweepShape{2, std::max(16, prefetch_depth((a.max_p + g - 1) / g, many ? 16 : cap)), ntl, parts};
   }
   // The rows p of each front in `parts` workgroups; a row takes at most m columns.
   const int parts = sweep_parts(a.nlevel, a.max_p);
   const int ntl = large_threads(a.nlevel * parts);
   const int rows = (std::max(a.max_p, 1) + parts - 1) / parts;
   const int g = std::max(1, ntl / rows);
-  const int kp = prefetch_depth((a.max_m + g - 1) / g, cap);
-  if (ntl == 256) bwd_large_launch<T, 256>(st, a, parts, kp, upk, vec, u, r);
-  else if (ntl == 512) bwd_large_launch<T, 512>(st, a, parts, kp, upk, vec, u, r);
-  else bwd_large_launch<T, 1024>(st, a, parts, kp, upk, vec, u, r);
+  return SweepShape{2, std::max(16, prefetch_depth((a.max_m + g - 1) / g, cap)), ntl, parts};
+}
+
+bool sweep_shape_ok(const LevelArgs& a, bool fwd, size_t elem, int nr, const SweepShape& s) {
+  if (s.kind == 0) return true;
+  if (s.kind == 1) {
+    if (!wave_level(a) || s.ntl != 64 || s.parts != 1) return false;
+    const int rpl = fwd && a.max_m > 64 ? 2 : 1;
+    return (s.kp == 8 || s.kp == 16 || s.kp == 32) && s.kp <= wave_kp_max(elem, rpl);
+  }
+  if (s.kind != 2) return false;
+  if (s.ntl != 256 && s.ntl != 512 && s.ntl != 1024) return false;
+  if (s.parts != 1 && s.parts != 2 && s.parts != 4 && s.parts != 8) return false;
+  if (s.kp != 16 && s.kp != 32) return false;
+  if (s.kp > large_kp_max(elem)) return false;
+  if (sweep_lds(a, fwd, elem, nr, s.ntl) > (size_t)max_lds()) return false;
+  // Backwards, a part that is one of several never writes the front's own
+  // vector, which the other parts read: it must hold its rows in one pass.
+  if (!fwd && s.parts > 1 && (a.max_p + s.parts - 1) / s.parts > s.ntl) return false;
+  return true;
+}
+
+std::vector<SweepShape> sweep_candidates(const LevelArgs& a, bool fwd, size_t elem, int nr) {
+  std::vector<SweepShape> out;
+  out.push_back(sweep_default(a, fwd, elem));
+  auto add = [&](SweepShape s) {
+    if (!sweep_shape_ok(a, fwd, elem, nr, s)) return;
+    for (const SweepShape& o : out)
+      if (o.kind == s.kind && o.kp == s.kp && o.ntl == s.ntl && o.parts == s.parts) return;
+    out.push_back(s);
+  };
+  if (wave_level(a)) {
+    for (int kp : {8, 16, 32}) add(SweepShape{1, kp, 64, 1});
+    // one workgroup per front for the wider fronts of these levels
+    if (a.max_m > 64)
+      for (int kp : {16, 32}) add(SweepShape{2, kp, 256, 1});
+    return out;
+  }
+  const int rows = fwd ? a.max_m : std::max(a.max_p, 1);
+  for (int parts : {1, 2, 4, 8}) {
+    if (parts > 1 && (long long)a.nlevel * parts > 4LL * num_cus()) continue;   // already full
+    if (parts > 1 && rows / parts < 16) continue;
+    for (int ntl : {256, 512, 1024})
+      for (int kp : {16, 32}) add(SweepShape{2, kp, ntl, parts});
+  }
+  return out;
+}
+
+template <typename T>
+void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
+                      const RhsSet& r, SweepShape sh) {
+  check_rhs(r);
+  if (sh.kind == 0) sh = sweep_default(a, true, sizeof(T));
+  if (!sweep_shape_ok(a, true, sizeof(T), r.nr, sh)) throw Error(STF_EINVAL, "sweep launch shape not valid for the level");
+  if (sh.kind == 1) {
+    constexpr int K32 = sizeof(T) == 8 ? 32 : 16;
+    constexpr int K16R2 = sizeof(T) == 8 ? 16 : 8;
+    if (a.max_m <= 64) {
+      if (sh.kp == 8) fwd_wave_launch<T, 1, 8>(st, a, fac, piv, vec, r);
+      else if (sh.kp == 16) fwd_wave_launch<T, 1, 16>(st, a, fac, piv, vec, r);
+      else fwd_wave_launch<T, 1, K32>(st, a, fac, piv, vec, r);
+    } else {
+      if (sh.kp == 8) fwd_wave_launch<T, 2, 8>(st, a, fac, piv, vec, r);
+      else fwd_wave_launch<T, 2, K16R2>(st, a, fac, piv, vec, r);
+    }
+    return;
+  }
+  if (sh.ntl == 256) fwd_large_launch<T, 256>(st, a, sh.parts, sh.kp, fac, piv, vec, r);
+  else if (sh.ntl == 512) fwd_large_launch<T, 512>(st, a, sh.parts, sh.kp, fac, piv, vec, r);
+  else fwd_large_launch<T, 1024>(st, a, sh.parts, sh.kp, fac, piv, vec, r);
+}
+
+template <typename T>
+void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
+                      const RhsSet& r, SweepShape sh) {
+  check_rhs(r);
+  if (sh.kind == 0) sh = sweep_default(a, false, sizeof(T));
+  if (!sweep_shape_ok(a, false, sizeof(T), r.nr, sh)) throw Error(STF_EINVAL, "sweep launch shape not valid for the level");
+  if (sh.kind == 1) {
+    constexpr int K32 = sizeof(T) == 8 ? 32 : 16;
+    if (sh.kp == 8) bwd_wave_launch<T, 8>(st, a, upk, vec, u, r);
+    else if (sh.kp == 16) bwd_wave_launch<T, 16>(st, a, upk, vec, u, r);
+    else bwd_wave_launch<T, K32>(st, a, upk, vec, u, r);
+    return;
+  }
+  if (sh.ntl == 256) bwd_large_launch<T, 256>(st, a, sh.parts, sh.kp, upk, vec, u, r);
+  else if (sh.ntl == 512) bwd_large_launch<T, 512>(st, a, sh.parts, sh.kp, upk, vec, u, r);
+  else bwd_large_launch<T, 1024>(st, a, sh.parts, sh.kp, upk, vec, u, r);
 }
 
 template <typename T>
@@ -1858,11 +1997,12 @@ void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsu
 }
 
 #define STF_INST(T)                                                                             \
-  template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, T*, int*, int*, double); \
+  template void launch_front_factor<T>(hipStream_t, const LevelArgs&, T*, T*, T*, int*, int*, double, \
+                                       FactorShape);                                            \
   template void launch_sweep_fwd<T>(hipStream_t, const LevelArgs&, const T*, const int*, T*,    \
-                                    const RhsSet&);                                             \
+                                    const RhsSet&, SweepShape);                                 \
   template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*,            \
-                                    const RhsSet&);                                             \
+                                    const RhsSet&, SweepShape);                                 \
   template void launch_scatter<T>(hipStream_t, const T*, const SubDev*, const int4*,            \
                                   const int4*, const ScatDev*, int, int, int, const int*,       \
                                   const RhsSet&);                                               \

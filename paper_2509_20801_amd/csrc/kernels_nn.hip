@@ -31,8 +31,10 @@ __device__ inline float gelu_df(float x) {
 
 // ---------------------------------------------------------------------------
 // C[b] = alpha A[b] B[b] + beta C[b], A (M x K), B (K x N), arbitrary strides.
-// 64 x 64 output tile per 256-thread workgroup, 4 x 4 per thread, K staged in
-// LDS 16 at a time.
+// TM x TN output tile per 256-thread workgroup (64 x 64, or 128 x 32 for the
+// narrow products of the x transform), 4 x 4 per thread, K staged in LDS 16 at
+// a time.  Tiles are loaded along whichever index is contiguous in memory, so
+// that consecutive threads read consecutive addresses.
 // ---------------------------------------------------------------------------
 struct GemmArgs {
   const float* A;
@@ -43,23 +45,26 @@ struct GemmArgs {
   float alpha, beta;
 };
 
+template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
-  constexpr int TM = 64, TN = 64, TK = 16;
+  constexpr int TK = 16, RX = TN / 4, RY = TM / 4;         // threads per row / column of the tile
+  static_assert(RX * RY == 256, "4 x 4 outputs per thread");
   __shared__ float As[TK][TM + 4];
   __shared__ float Bs[TK][TN + 4];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, tx = tid % RX, ty = tid / RX;
   const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN, b = blockIdx.z;
   const float* A = g.A + b * g.sAb;
   const float* Bm = g.B + b * g.sBb;
+  const bool a_k_fast = g.sAk == 1, b_n_fast = g.sBn == 1;
   float acc[4][4] = {};
   for (int k0 = 0; k0 < g.K; k0 += TK) {
     for (int t = tid; t < TM * TK; t += 256) {
-      const int mm = t % TM, kk = t / TM;
+      const int mm = a_k_fast ? t / TK : t % TM, kk = a_k_fast ? t % TK : t / TM;
       const int m = m0 + mm, k = k0 + kk;
       As[kk][mm] = (m < g.M && k < g.K) ? A[m * g.sAm + k * g.sAk] : 0.0f;
     }
     for (int t = tid; t < TN * TK; t += 256) {
-      const int nn = t % TN, kk = t / TN;
+      const int nn = b_n_fast ? t % TN : t / TK, kk = b_n_fast ? t / TN : t % TK;
       const int n = n0 + nn, k = k0 + kk;
       Bs[kk][nn] = (n < g.N && k < g.K) ? Bm[k * g.sBk + n * g.sBn] : 0.0f;
     }
@@ -68,9 +73,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     for (int kk = 0; kk < TK; ++kk) {
       float a[4], bb[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + 16 * i];
+      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty + RY * i];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + 16 * j];
+      for (int j = 0; j < 4; ++j) bb[j] = Bs[kk][tx + RX * j];
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -81,11 +86,11 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   float* C = g.C + b * g.sCb;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const int m = m0 + ty + 16 * i;
+    const int m = m0 + ty + RY * i;
     if (m >= g.M) continue;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int n = n0 + tx + 16 * j;
+      const int n = n0 + tx + RX * j;
       if (n >= g.N) continue;
       float* c = C + m * g.sCm + n * g.sCn;
       *c = g.alpha * acc[i][j] + (g.beta != 0.0f ? g.beta * *c : 0.0f);
@@ -494,8 +499,13 @@ void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, lon
              long long sBn, float* C, long long sCb, long long sCm, long long sCn, float alpha,
              float beta) {
   GemmArgs g{A, B, C, M, N, K, sAb, sAm, sAk, sBb, sBk, sBn, sCb, sCm, sCn, alpha, beta};
-  dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
-  hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
+  if (N <= 32) {
+    dim3 grid((N + 31) / 32, (M + 127) / 128, batch);
+    hipLaunchKernelGGL((k_gemm<128, 32>), grid, dim3(256), 0, st, g);
+  } else {
+    dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+    hipLaunchKernelGGL((k_gemm<64, 64>), grid, dim3(256), 0, st, g);
+  }
 }
 
 void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int n, int M,

@@ -253,17 +253,40 @@ struct LevelArgs {
                                 // pivot column is zeroed on its fully summed rows after
                                 // assembly (-1 = none)
 };
+// Launch shape of one level's kernel: kind 0 = the built-in rule for the
+// level, else an explicit choice (the autotuner's).  Factorisation: kind 1 =
+// one wavefront per front with the front in LDS (small fronts), kind 2 = the
+// panel kernel with nb-column panels and ntf threads per front.
+struct FactorShape {
+  int kind = 0, nb = 0, ntf = 0;
+};
+// Sweeps: kind 1 = one wavefront per front (levels with m <= 128, p <= 64),
+// kind 2 = `parts` workgroups of ntl threads per front; kp = operator terms
+// per thread held in registers ahead of the right-hand side.
+struct SweepShape {
+  int kind = 0, kp = 0, ntl = 0, parts = 0;
+};
+// The built-in choices, whether a shape runs a level (instantiated variant,
+// LDS, the kernels' own limits), and the shapes the autotuner times for a
+// level (the built-in choice first).  elem = bytes per complex entry.
+FactorShape factor_default(const LevelArgs& a, size_t elem);
+bool factor_shape_ok(const LevelArgs& a, size_t elem, const FactorShape& s);
+std::vector<FactorShape> factor_candidates(const LevelArgs& a, size_t elem);
+SweepShape sweep_default(const LevelArgs& a, bool fwd, size_t elem);
+bool sweep_shape_ok(const LevelArgs& a, bool fwd, size_t elem, int nr, const SweepShape& s);
+std::vector<SweepShape> sweep_candidates(const LevelArgs& a, bool fwd, size_t elem, int nr);
 // Assembly (original entries + extend-add of the children) and partial LU of
-// every front of one level.
+// every front of one level.  A shape that does not run the level is an
+// STF_EINVAL error.
 template <typename T>
 void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
-                         double tau);
+                         double tau, FactorShape sh = {});
 template <typename T>
 void launch_sweep_fwd(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
-                      const RhsSet& r);
+                      const RhsSet& r, SweepShape sh = {});
 template <typename T>
 void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
-                      const RhsSet& r);
+                      const RhsSet& r, SweepShape sh = {});
 // z = sum_k P_k u_k for every problem of a set (ScatDev table of nprob entries,
 // grid sized by the largest nx, ny), skipping problems with pact[p] == 0.
 template <typename T>

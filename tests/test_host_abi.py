@@ -155,3 +155,24 @@ def test_public_header_is_plain_c(tmp_path):
     r = subprocess.run([cc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-fsyntax-only", "-I", inc,
                         str(src)], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
+
+
+@pytest.mark.parametrize("cfg", ["metasurface", "small", "waveguides", "disks_768", "single"])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_launch_shape_rules_hold_on_every_level(stf, cfg, prec):
+    """The built-in launch shape of every level, and every candidate the
+    autotuner would time, passes the library's own validity rules (instantiated
+    variant, LDS, the kernels' limits), for one and four right-hand sides."""
+    p = {
+        "metasurface": lambda: workloads.configs.metasurface_sheet().params(),
+        "small": lambda: workloads.configs.small_random(nx=71, ny=53, pml=5, px=3, py=2, overlap=3,
+                                                        local_pml=5, seed=4).params(),
+        "waveguides": lambda: dict(nx=4128, ny=4128, k0=0.08, pml=(16,) * 4, px=16, py=16,
+                                   overlap=8, local_pml=16),
+        "disks_768": lambda: dict(nx=800, ny=800, k0=0.2, pml=(16,) * 4, px=6, py=6, overlap=8,
+                                  local_pml=16),
+        "single": lambda: dict(nx=200, ny=180, k0=0.3, pml=(12,) * 4, px=1, py=1),
+    }[cfg]()
+    for nr in (1, 4):
+        levels, cands, bad = stf.debug_level_shapes(dict(p, front_prec=prec), nrhs=nr)
+        assert levels >= 3 and cands >= 3 * levels and bad == 0, (levels, cands, bad)
