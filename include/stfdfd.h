@@ -394,7 +394,7 @@ typedef struct stf_nn_s* stf_nn;
 typedef struct {
   int32_t n;          /* tile side in nodes (2M <= n) */
   int32_t width;      /* W: 4, 8, 16 or 32 */
-  int32_t modes;      /* M */
+  int32_t modes;      /* M (1 <= M <= 22, 2M <= n) */
   int32_t layers;     /* L >= 1 */
   int32_t cin;        /* input features: 3 */
   int32_t max_batch;  /* largest number of tiles per call */

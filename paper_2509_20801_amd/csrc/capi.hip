@@ -1178,7 +1178,8 @@ long long nn_param_count(const stf_nn_config& c) {
 
 void nn_validate(const stf_nn_config& c) {
   STF_REQUIRE(c.n >= 4 && c.n <= 1024, "nn: tile side out of range");
-  STF_REQUIRE(c.modes >= 1 && 2 * c.modes <= c.n, "nn: modes out of range (2M <= n)");
+  STF_REQUIRE(c.modes >= 1 && 2 * c.modes <= c.n && c.modes <= 22,
+              "nn: modes out of range (2M <= n, M <= 22)");
   STF_REQUIRE(c.layers >= 1 && c.layers <= 16, "nn: layers out of range");
   STF_REQUIRE(c.cin == 3, "nn: three input features");
   STF_REQUIRE(nn_width_supported(c.cin, c.width) && nn_width_supported(c.width, c.width) &&
@@ -1267,8 +1268,8 @@ void nn_ensure(stf_nn nn, int B) {
   nn->cap = B;
 }
 
-// y = network(f); activations kept for nn_backward.
-void nn_forward(stf_nn nn, int B, const float* f, float* y) {
+// y = network(f); with keep, the pre-activations are kept for nn_backward.
+void nn_forward(stf_nn nn, int B, const float* f, float* y, bool keep = true) {
   const stf_nn_config& c = nn->cfg;
   hipStream_t st = nn->ctx->stream;
   Timed t(nn->ctx, K_NN);
@@ -1295,7 +1296,7 @@ void nn_forward(stf_nn nn, int B, const float* f, float* y) {
             nn->g.as<float>(), npix, n, 1, 1.0f / ((float)n * (float)n), 0.0f);
     const float* Wl = P + nn->offW[l];
     nn_pw_fwd(st, W, W, l < L - 1, hl, Wl, Wl + W * W, nn->g.as<float>(), npix, B,
-              nn->pre[l].as<float>(), nn->h[l + 1].as<float>());
+              keep ? nn->pre[l].as<float>() : nullptr, nn->h[l + 1].as<float>());
   }
   nn_pw_fwd(st, W, 2, false, nn->h[L].as<float>(), P + nn->offQ, P + nn->offQ + 2 * W, nullptr,
             npix, B, nullptr, y);
@@ -1403,7 +1404,7 @@ void nn_initial_guess(stf_problem pb, stf_nn nn, const double2* b, double2* x0) 
   for (int t0 = 0; t0 < nt; t0 += bmax) {
     const int B = std::min(bmax, nt - t0);
     nn_forward(nn, B, nn->tf.as<float>() + (long long)t0 * 3 * per,
-               nn->tpred.as<float>() + (long long)t0 * 2 * per);
+               nn->tpred.as<float>() + (long long)t0 * 2 * per, false);
   }
   Timed t(pb->ctx, K_NN);
   nn_blend(st, nn->tpred.as<float>(), nn->oy.as<int>(), nty, nn->ox.as<int>(), ntx, n, p.pml[0],

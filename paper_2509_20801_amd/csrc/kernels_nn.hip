@@ -99,6 +99,155 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
+// The x transform of every row: a tall A (M x K, rows contiguous, K <= 256)
+// times a narrow B (K x N, N <= 32).  B is held whole in LDS; each workgroup
+// streams 64 rows of A through LDS 64 columns at a time with 16-byte loads
+// along the rows (VEC: every row start 16-byte aligned), and each thread forms
+// 8 outputs of one row.
+// ---------------------------------------------------------------------------
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_gemm_tall(GemmArgs g) {
+  __shared__ float Bs[256][33];
+  __shared__ float As[64][65];
+  const int tid = threadIdx.x, b = blockIdx.z;
+  const float* A = g.A + b * g.sAb;
+  const float* Bm = g.B + b * g.sBb;
+  // B whole: 32 entries per thread, loaded in batches of 16 (all loads of a
+  // batch in flight before any is stored)
+  for (int t0 = 0; t0 < g.K * 32; t0 += 16 * 256) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = t0 + u * 256 + tid, k = t >> 5, n = t & 31;
+      v[u] = (k < g.K && n < g.N) ? Bm[k * g.sBk + n * g.sBn] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = t0 + u * 256 + tid, k = t >> 5, n = t & 31;
+      if (k < g.K) Bs[k][n] = v[u];
+    }
+  }
+  const int m0 = blockIdx.x * 64;
+  const int r = tid >> 2, cg = tid & 3;
+  float acc[8] = {};
+  for (int k0 = 0; k0 < g.K; k0 += 64) {
+    __syncthreads();
+    // 64 x 64 chunk of A: four 4-entry pieces per thread, all in flight at once
+    float v[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = u * 256 + tid, rr = t >> 4, c4 = (t & 15) * 4;
+      const int m = m0 + rr, k = k0 + c4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[u][e] = 0.0f;
+      if (m < g.M) {
+        const float* src = A + m * g.sAm + (long long)k * g.sAk;
+        if (VEC && k + 3 < g.K) {
+          const float4 x = *reinterpret_cast<const float4*>(src);
+          v[u][0] = x.x; v[u][1] = x.y; v[u][2] = x.z; v[u][3] = x.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[u][e] = k + e < g.K ? src[e * g.sAk] : 0.0f;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = u * 256 + tid, rr = t >> 4, c4 = (t & 15) * 4;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) As[rr][c4 + e] = v[u][e];
+    }
+    __syncthreads();
+    const int kw = min(64, g.K - k0);
+    for (int kk = 0; kk < kw; ++kk) {
+      const float a = As[r][kk];
+      const float* bk = &Bs[k0 + kk][cg * 8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) acc[j] = fmaf(a, bk[j], acc[j]);
+    }
+  }
+  const int m = m0 + r;
+  if (m >= g.M) return;
+  float* C = g.C + b * g.sCb + m * g.sCm;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int n = cg * 8 + j;
+    if (n < g.N) {
+      float* c = C + n * g.sCn;
+      *c = g.alpha * acc[j] + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The inverse x transform: C (M x N) = alpha A (M x K) B (K x N) + beta C per
+// batch entry for K <= 64 on the FP32 matrix cores: a 64 x 64 tile of C per
+// workgroup, 32 x 32 per wavefront as 2 x 2 16x16x4 products, K staged in LDS
+// whole.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; output
+// (i, j) of a 16 x 16 tile is in lane j + 16 (i / 4), register i % 4.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  __shared__ float As[64][65];          // [k][m]
+  __shared__ float Bs[64][65];          // [k][n]
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64, b = blockIdx.z;
+  const float* A = g.A + b * g.sAb;
+  const float* Bm = g.B + b * g.sBb;
+  // A along k when its rows are contiguous, else along m; B along n when its
+  // rows are contiguous, else along k; sixteen entries of each per thread, all
+  // in flight before any is stored.
+  const bool ak = g.sAk == 1, bn = g.sBn == 1;
+  float va[16], vb[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = u * 256 + tid;
+    const int mm = ak ? t >> 6 : t & 63, kk = ak ? t & 63 : t >> 6;
+    const int m = m0 + mm;
+    va[u] = (m < g.M && kk < g.K) ? A[m * g.sAm + kk * g.sAk] : 0.0f;
+    const int nn = bn ? t & 63 : t >> 6, kb = bn ? t >> 6 : t & 63;
+    const int n = n0 + nn;
+    vb[u] = (n < g.N && kb < g.K) ? Bm[kb * g.sBk + n * g.sBn] : 0.0f;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int t = u * 256 + tid;
+    As[ak ? t & 63 : t >> 6][ak ? t >> 6 : t & 63] = va[u];
+    Bs[bn ? t >> 6 : t & 63][bn ? t & 63 : t >> 6] = vb[u];
+  }
+  __syncthreads();
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  const int l16 = lane & 15, lk = lane >> 4;
+  V4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int k0 = 0; k0 < g.K; k0 += 4) {
+    const int k = k0 + lk;
+    const float a0 = As[k][wm + l16], a1 = As[k][wm + 16 + l16];
+    const float b0 = Bs[k][wn + l16], b1 = Bs[k][wn + 16 + l16];
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a1, b1, acc[1][1], 0, 0, 0);
+  }
+  float* C = g.C + b * g.sCb;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int m = m0 + wm + 16 * i + 4 * lk + v, n = n0 + wn + 16 * j + l16;
+        if (m < g.M && n < g.N) {
+          float* c = C + m * g.sCm + n * g.sCn;
+          *c = g.alpha * acc[i][j][v] + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+        }
+      }
+}
+
+// ---------------------------------------------------------------------------
 // Truncated DFT along y of one plane: H[a, k] = s_k sum_y Ey[a, y] T[y, k],
 // T row y = [Re (M) | Im (M)] of the x transform, Ey = exp(-2 pi i ky(a) y / n).
 // s_k = 1 (forward) or w_k / n^2 (gradient through the inverse transform).
@@ -109,22 +258,64 @@ __global__ __launch_bounds__(NNT) void k_dft_y(const float* __restrict__ T,
   extern __shared__ float Ts[];                  // n x 2M
   const int plane = blockIdx.x;
   const float* Tp = T + (long long)plane * n * 2 * M;
-  for (int t = threadIdx.x; t < n * 2 * M; t += NNT) Ts[t] = Tp[t];
+  // the plane into LDS, sixteen loads per thread in flight at a time
+  for (int t0 = 0; t0 < n * 2 * M; t0 += 16 * NNT) {
+    float v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = t0 + u * NNT + threadIdx.x;
+      v[u] = t < n * 2 * M ? Tp[t] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int t = t0 + u * NNT + threadIdx.x;
+      if (t < n * 2 * M) Ts[t] = v[u];
+    }
+  }
   __syncthreads();
   const float inv = 1.0f / ((float)n * (float)n);
-  for (int o = threadIdx.x; o < 2 * M * M; o += NNT) {
-    const int a = o / M, k = o - a * M;
-    const float2* e = ey + (long long)a * n;
-    float re = 0.0f, im = 0.0f;
-    for (int y = 0; y < n; ++y) {
-      const float2 w = e[y];
-      const float tr = Ts[y * 2 * M + k], ti = Ts[y * 2 * M + M + k];
-      re = fmaf(w.x, tr, fmaf(-w.y, ti, re));
-      im = fmaf(w.x, ti, fmaf(w.y, tr, im));
+  // Twiddles ey[a][y] staged in LDS YC columns at a time (after the plane).
+  constexpr int YC = 64;
+  float2* Es = reinterpret_cast<float2*>(Ts + n * 2 * M);   // 2M x YC
+  constexpr int OPT = 4;                                       // outputs per thread (2M M <= OPT NNT)
+  float re[OPT] = {}, im[OPT] = {};
+  for (int y0 = 0; y0 < n; y0 += YC) {
+    const int yc = min(YC, n - y0);
+    __syncthreads();
+    for (int t0 = 0; t0 < 2 * M * YC; t0 += 8 * NNT) {
+      float2 v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * NNT + threadIdx.x, a = t / YC, y = t - a * YC;
+        v[u] = (a < 2 * M && y < yc) ? ey[(long long)a * n + y0 + y] : make_float2(0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u * NNT + threadIdx.x;
+        if (t < 2 * M * YC) Es[t] = v[u];
+      }
     }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < OPT; ++j) {
+      const int o = threadIdx.x + j * NNT;
+      if (o >= 2 * M * M) continue;
+      const int a = o / M, k = o - a * M;
+      for (int y = 0; y < yc; ++y) {
+        const float2 w = Es[a * YC + y];
+        const float tr = Ts[(y0 + y) * 2 * M + k], ti = Ts[(y0 + y) * 2 * M + M + k];
+        re[j] = fmaf(w.x, tr, fmaf(-w.y, ti, re[j]));
+        im[j] = fmaf(w.x, ti, fmaf(w.y, tr, im[j]));
+      }
+    }
+  }
+  for (int j = 0; j < OPT; ++j) {
+    const int o = threadIdx.x + j * NNT;
+    if (o >= 2 * M * M) continue;
+    const int k = o % M;
     float s = 1.0f;
     if (grad_scale) s = (k == 0 ? 1.0f : 2.0f) * inv;
-    H[(long long)plane * 2 * M * M + o] = make_float2(s * re, s * im);
+    H[(long long)plane * 2 * M * M + o] = make_float2(s * re[j], s * im[j]);
   }
 }
 
@@ -143,12 +334,21 @@ __global__ __launch_bounds__(NNT) void k_dft_x_inv(const float2* __restrict__ G,
   if (o >= 2 * M * n) return;
   const int a = o / n, x = o - a * n;
   float re = 0.0f, im = 0.0f;
-  for (int k = 0; k < M; ++k) {
-    const float2 w = ex[(long long)k * n + x];   // exp(+2 pi i k x / n)
-    float2 gv = Gs[a * M + k];
-    if (weighted && k > 0) gv = make_float2(2.0f * gv.x, 2.0f * gv.y);
-    re = fmaf(gv.x, w.x, fmaf(-gv.y, w.y, re));
-    im = fmaf(gv.x, w.y, fmaf(gv.y, w.x, im));
+  for (int k0 = 0; k0 < M; k0 += 8) {
+    float2 w[8];                                 // exp(+2 pi i k x / n), eight per round trip
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      w[u] = k0 + u < M ? ex[(long long)(k0 + u) * n + x] : make_float2(0.0f, 0.0f);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int k = k0 + u;
+      if (k < M) {
+        float2 gv = Gs[a * M + k];
+        if (weighted && k > 0) gv = make_float2(2.0f * gv.x, 2.0f * gv.y);
+        re = fmaf(gv.x, w[u].x, fmaf(-gv.y, w[u].y, re));
+        im = fmaf(gv.x, w[u].y, fmaf(gv.y, w[u].x, im));
+      }
+    }
   }
   float* Sp = S + (long long)plane * 4 * M * n;
   Sp[(long long)a * n + x] = re;
@@ -243,7 +443,7 @@ __global__ __launch_bounds__(NNT) void k_pw_fwd(const float* __restrict__ in,
     const long long oi = (b * CO + o) * npix + p;
     if (add) s += add[oi];
     if (ACT) {
-      pre[oi] = s;
+      if (pre) pre[oi] = s;          // kept for the backward pass only
       out[oi] = gelu_f(s);
     } else {
       out[oi] = s;
@@ -499,6 +699,20 @@ void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, lon
              long long sBn, float* C, long long sCb, long long sCm, long long sCn, float alpha,
              float beta) {
   GemmArgs g{A, B, C, M, N, K, sAb, sAm, sAk, sBb, sBk, sBn, sCb, sCm, sCn, alpha, beta};
+  if (N <= 32 && K <= 256) {
+    // 16-byte loads along the rows of A when every row start is 16-byte aligned
+    const bool vec = sAk == 1 && sAm % 4 == 0 && sAb % 4 == 0 &&
+                     (reinterpret_cast<uintptr_t>(A) & 15) == 0;
+    dim3 grid((M + 63) / 64, 1, batch);
+    if (vec) hipLaunchKernelGGL((k_gemm_tall<true>), grid, dim3(256), 0, st, g);
+    else hipLaunchKernelGGL((k_gemm_tall<false>), grid, dim3(256), 0, st, g);
+    return;
+  }
+  if (K <= 64) {
+    dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
+    hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, st, g);
+    return;
+  }
   if (N <= 32) {
     dim3 grid((N + 31) / 32, (M + 127) / 128, batch);
     hipLaunchKernelGGL((k_gemm<128, 32>), grid, dim3(256), 0, st, g);
@@ -510,8 +724,9 @@ void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, lon
 
 void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int n, int M,
               bool grad_scale, float2* H) {
-  hipLaunchKernelGGL(k_dft_y, dim3(planes), dim3(NNT), (size_t)n * 2 * M * sizeof(float), st, T, ey,
-                     n, M, grad_scale ? 1 : 0, H);
+  if (2 * M * M > 4 * NNT) throw Error(STF_EINVAL, "too many modes for the y transform");
+  const size_t lds = (size_t)n * 2 * M * sizeof(float) + (size_t)2 * M * 64 * sizeof(float2);
+  hipLaunchKernelGGL(k_dft_y, dim3(planes), dim3(NNT), lds, st, T, ey, n, M, grad_scale ? 1 : 0, H);
 }
 
 void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
