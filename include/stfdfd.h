@@ -335,21 +335,32 @@ void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
  * the built-in rule.  Needs assembled problems of this context with one front
  * precision (STF_ESTATE otherwise); leaves them factored (the factorisation
  * is run again with the chosen shapes; a perturbed pivot is not reported
- * here).  Contents of the round's workspaces are overwritten.  report: NULL or
- * filled with the levels timed, how many changed from the built-in shape and
- * the summed level times with the built-in and with the chosen shapes (ms). */
+ * here).  Contents of the round's workspaces are overwritten.  With the
+ * sweeps, it then times whole rounds' sweeps level by level against subtree
+ * sweeps (the deep levels swept one subtree per workgroup, each root depth
+ * that fits) and keeps the fastest for the set's signature (operation 3 in
+ * the entries below).  report: NULL or filled with the levels timed, how many
+ * changed from the built-in shape, the summed level times with the built-in
+ * and with the chosen shapes (ms), the chosen subtree root depth (-1: level
+ * by level, or no sweeps tuned) and the sweeps' time with the built-in and
+ * with the chosen subtree choice (ms). */
 typedef struct {
   int32_t levels;
   int32_t changed;
   double  ms_default;
   double  ms_tuned;
+  int32_t fuse_depth;
+  double  ms_round_default;
+  double  ms_round_tuned;
 } stf_tune_report;
 stf_status  stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
                          int32_t what, int32_t reps, stf_tune_report* report);
 /* Test hook: sets, without timing, the entry of every level of the given
  * problems (as stf_autotune selects them) to the level's candidate shape
  * `index` (>= 0; the last candidate where a level has fewer; 0 is the
- * built-in shape).  *max_candidates (may be NULL) receives the largest
+ * built-in shape), and with the sweeps the subtree choice of the set to its
+ * option `index` (0 level by level, the built-in choice, then each root
+ * depth that fits).  *max_candidates (may be NULL) receives the largest
  * candidate count over the levels, so that index = 0 .. max - 1 visits every
  * candidate; every one must give the same results to rounding. */
 stf_status  stf_tune_pick(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
@@ -374,7 +385,9 @@ stf_status  stf_tune_clear(stf_ctx ctx);
  * order): key = {op (0 factorisation, 1 forward sweep, 2 backward sweep),
  * bytes per complex entry, nrhs (0 for the factorisation), fronts in the
  * level, max m, max p}; shape = {kind, nb or kp, ntf or ntl, parts};
- * ms = {chosen, built-in}.  Any output pointer may be NULL. */
+ * ms = {chosen, built-in}.  Operation 3 (the subtree choice of a set): key =
+ * {3, bytes, nrhs, fronts of the set, deepest level, subdomains}, shape =
+ * {1, root depth or -1, 0, 0}.  Any output pointer may be NULL. */
 int32_t     stf_tune_count(stf_ctx ctx);
 stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms);
 

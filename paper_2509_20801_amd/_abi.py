@@ -47,7 +47,8 @@ class NNConfig(C.Structure):
 
 class TuneReport(C.Structure):
     _fields_ = [("levels", C.c_int32), ("changed", C.c_int32), ("ms_default", C.c_double),
-                ("ms_tuned", C.c_double)]
+                ("ms_tuned", C.c_double), ("fuse_depth", C.c_int32), ("ms_round_default", C.c_double),
+                ("ms_round_tuned", C.c_double)]
 
 
 class PlanInfo(C.Structure):

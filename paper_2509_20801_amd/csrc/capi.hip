@@ -204,6 +204,12 @@ struct SweepPlan {
   DBuf slist, flist, inst;                    // members, front instances, membership flags
 };
 
+// Subtree sweeps of a set for roots at depth D (see FuseArgs).
+struct FusePlan {
+  FuseArgs args;                // device pointers into lev / fl
+  DBuf lev, fl;
+};
+
 struct Mf {
   int prec = STF_C128;
   int nprob = 0, nsub = 0, max_depth = -1, max_nx = 0, max_ny = 0;
@@ -214,6 +220,9 @@ struct Mf {
   int64_t n_fronts = 0, fac_elems = 0, lpk_elems = 0, upk_elems = 0, vec_elems = 0,
           piv_elems = 0, u_elems = 0;
   std::vector<Level> levels;     // by depth
+  std::vector<FrontDev> h_fronts;  // host copies of the front instances and children
+  std::vector<int> h_children;
+  std::map<int, std::unique_ptr<FusePlan>> fuse;   // subtree sweeps by root depth
   DBuf lcoef, subs, fronts, vars, cmap, ents, children, cover_x, cover_y, scat;
   DBuf fac, lpk, upk, piv, vec, u;
   int ws_nr = 0;                 // right-hand sides the vec / u workspaces hold
@@ -241,7 +250,68 @@ struct Mf {
                          &cover_y, &scat, &fac, &lpk, &upk, &piv, &vec, &u};
     int64_t t = 0;
     for (const DBuf* d : all) t += (int64_t)d->bytes;
+    for (const auto& kv : fuse) t += (int64_t)(kv.second->lev.bytes + kv.second->fl.bytes);
     return t;
+  }
+  // Shallowest root depth D of subtree sweeps: every level from D down is one
+  // the wavefront kernels take, and a subtree spans two levels or more; -1 if
+  // there is none.
+  int fuse_min_depth() const {
+    int d = max_depth;
+    if (d < 1 || levels[d].max_m > 128 || levels[d].max_p > 64) return -1;
+    while (d - 1 >= 0 && levels[d - 1].max_m <= 128 && levels[d - 1].max_p <= 64) --d;
+    return d <= max_depth - 1 ? d : -1;
+  }
+  // The subtree sweep tables for roots at depth D (built once, kept).
+  const FusePlan& fuse_plan(int D, hipStream_t st) {
+    auto it = fuse.find(D);
+    if (it != fuse.end()) return *it->second;
+    STF_REQUIRE(D >= 0 && D < max_depth, "internal: subtree root depth out of range");
+    std::unique_ptr<FusePlan> fp(new FusePlan());
+    FuseArgs& z = fp->args;
+    z.K = max_depth - D + 1;
+    z.ntrees = levels[D].n;
+    for (int d = D; d <= max_depth; ++d) {
+      z.max_m = std::max(z.max_m, levels[d].max_m);
+      z.max_p = std::max(z.max_p, levels[d].max_p);
+    }
+    std::vector<int> lev;
+    std::vector<int4> fl;
+    std::vector<int> slot(h_fronts.size(), -1);
+    std::vector<std::vector<int>> byl(z.K);
+    for (int t = 0; t < z.ntrees; ++t) {
+      for (auto& v : byl) v.clear();
+      byl[0].push_back(levels[D].off + t);
+      for (int j = 1; j < z.K; ++j)
+        for (int f : byl[j - 1])
+          for (int c = 0; c < h_fronts[f].nchild; ++c) byl[j].push_back(h_children[h_fronts[f].child_off + c]);
+      int q = 0;
+      for (int j = z.K - 1; j >= 1; --j)
+        for (int f : byl[j]) {
+          slot[f] = q;
+          q += h_fronts[f].q;
+        }
+      z.slot_q = std::max(z.slot_q, q);
+      for (int j = 0; j < z.K; ++j) {
+        lev.push_back((int)fl.size());
+        for (int f : byl[j]) {
+          const FrontDev& d = h_fronts[f];
+          const int c0 = d.nchild > 0 ? h_children[d.child_off] : -1;
+          const int c1 = d.nchild > 1 ? h_children[d.child_off + 1] : -1;
+          fl.push_back(make_int4(f, j == 0 ? -1 : slot[f], c0 >= 0 ? slot[c0] : -1, c1 >= 0 ? slot[c1] : -1));
+        }
+      }
+      lev.push_back((int)fl.size());
+    }
+    STF_REQUIRE(fl.size() < (1ULL << 31), "internal: subtree tables too large");
+    upload(fp->lev, lev, st);
+    upload(fp->fl, fl, st);
+    z.lev = fp->lev.as<int>();
+    z.fl = fp->fl.as<int4>();
+    HIP_CHECK(hipStreamSynchronize(st));
+    FusePlan& ref = *fp;
+    fuse[D] = std::move(fp);
+    return ref;
   }
 };
 
@@ -454,6 +524,9 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
   mf.max_depth = (int)mf.levels.size() - 1;
   upload(mf.fronts, fr, st);
   upload(mf.children, kids, st);
+  mf.fuse.clear();
+  mf.h_fronts = std::move(fr);
+  mf.h_children = std::move(kids);
 
   const size_t es = prec == STF_C64 ? sizeof(float2) : sizeof(double2);
   mf.fac.alloc((size_t)mf.fac_elems * es);
@@ -681,6 +754,8 @@ int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hip
   return h;
 }
 
+void fuse_prepare(stf_ctx c, Mf& mf);
+
 int factor_problem(stf_problem pb, bool fault = false) {
   Mf& mf = pb->ensure_mf();
   const double2* keps = pb->keps.as<double2>();
@@ -689,7 +764,52 @@ int factor_problem(stf_problem pb, bool fault = false) {
                     ? factor_mf<float2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1])
                     : factor_mf<double2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1]);
   pb->fac_timed = true;
+  fuse_prepare(pb->ctx, mf);
   return h;
+}
+
+// Root depth of the subtree sweeps of a set for nr right-hand sides: the
+// autotuned choice when the context has one for the set's signature, else
+// -1 (level by level: on the 1064^2 metasurface at 8 x 8 subdomains the
+// subtree sweeps measure slower, 1.04 against 0.65 ms for a round's sweeps
+// with four right-hand sides, since a workgroup takes its subtree's fronts
+// one level after another with few subtrees resident per CU).
+TuneKey fuse_key(const Mf& mf, size_t elem, int nr) {
+  return TuneKey{3, (int)elem, nr, (int)std::min<int64_t>(mf.n_fronts, INT32_MAX), mf.max_depth, mf.nsub};
+}
+
+// With build = false, only tables already built count (no allocation).
+int fuse_depth_for(stf_ctx c, Mf& mf, size_t elem, int nr, bool build = true) {
+  auto usable = [&](int D) {
+    if (!build && !mf.fuse.count(D)) return false;
+    return subtree_ok(mf.fuse_plan(D, c->stream).args, elem, nr);
+  };
+  auto it = c->tune.find(fuse_key(mf, elem, nr));
+  const int dmin = mf.fuse_min_depth();
+  if (it != c->tune.end()) {
+    const int D = it->second.a;
+    if (D < 0 || dmin < 0 || D < dmin || D >= mf.max_depth) return -1;
+    return usable(D) ? D : -1;
+  }
+  return -1;
+}
+
+// Builds the subtree tables the rounds of a set will use (outside graph
+// captures and allocation-free calls).
+void fuse_prepare(stf_ctx c, Mf& mf) {
+  const size_t elem = mf.prec == STF_C64 ? sizeof(float2) : sizeof(double2);
+  for (int nr = 1; nr <= MAX_RHS; ++nr) (void)fuse_depth_for(c, mf, elem, nr, true);
+}
+
+// Subtree-sweep choices for a set: the built-in one (level by level) first,
+// then every root depth whose subtrees fit.
+std::vector<int> fuse_options(stf_ctx c, Mf& mf, size_t elem, int nr) {
+  std::vector<int> out{-1};
+  const int dmin = mf.fuse_min_depth();
+  if (dmin >= 0)
+    for (int D = dmin; D < mf.max_depth; ++D)
+      if (subtree_ok(mf.fuse_plan(D, c->stream).args, elem, nr)) out.push_back(D);
+  return out;
 }
 
 // z_s = sum_k P_k A_k^{-1} R_k^I v_s (one source-transfer round) for the
@@ -698,24 +818,46 @@ int factor_problem(stf_problem pb, bool fault = false) {
 // vectors `vec` and local fields `u` (vec_elems and u_elems entries per
 // right-hand side).  With timed = false no event is recorded (the
 // allocation-free entry point).
+// The forward and backward sweeps of a round: the deep levels (depth >= D)
+// as subtree sweeps when D >= 0, the rest level by level.  r: strides set.
 template <typename T>
-void precond_launch(stf_ctx c, const Mf& mf, RhsSet r, T* vec, T* u, bool timed,
-                    const int* pact = nullptr) {
+void sweeps_launch(stf_ctx c, Mf& mf, const RhsSet& r, T* vec, T* u, stf_ctx tc, const int* pact, int D) {
   hipStream_t st = c->stream;
-  stf_ctx tc = timed ? c : nullptr;
-  r.vec_stride = mf.vec_elems;
-  r.u_stride = mf.u_elems;
   const T* lpk = mf.lpk.as<T>();
-  for (int d = mf.max_depth; d >= 0; --d) {
+  const int top = D >= 0 ? D : mf.max_depth + 1;
+  if (D >= 0) {
+    Timed t(tc, K_SWEEP_FWD);
+    launch_fwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), mf.fuse_plan(D, st).args, lpk,
+                          mf.piv.as<int>(), vec, r);
+  }
+  for (int d = top - 1; d >= 0; --d) {
     Timed t(tc, K_SWEEP_FWD);
     const LevelArgs la = mf.level_args(d, nullptr, pact);
     launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, r, tuned_sweep(c, la, true, sizeof(T), r.nr));
   }
-  for (int d = 0; d <= mf.max_depth; ++d) {
+  for (int d = 0; d < top; ++d) {
     Timed t(tc, K_SWEEP_BWD);
     const LevelArgs la = mf.level_args(d, nullptr, pact);
     launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, r, tuned_sweep(c, la, false, sizeof(T), r.nr));
   }
+  if (D >= 0) {
+    Timed t(tc, K_SWEEP_BWD);
+    launch_bwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), mf.fuse_plan(D, st).args,
+                          mf.upk.as<T>(), vec, u, r);
+  }
+}
+
+// fuse: 0 level by level only, 1 subtree sweeps whose tables exist, 2 also
+// building the tables.
+template <typename T>
+void precond_launch(stf_ctx c, Mf& mf, RhsSet r, T* vec, T* u, bool timed,
+                    const int* pact = nullptr, int fuse = 2) {
+  hipStream_t st = c->stream;
+  stf_ctx tc = timed ? c : nullptr;
+  r.vec_stride = mf.vec_elems;
+  r.u_stride = mf.u_elems;
+  const int D = fuse > 0 ? fuse_depth_for(c, mf, sizeof(T), r.nr, fuse == 2) : -1;
+  sweeps_launch<T>(c, mf, r, vec, u, tc, pact, D);
   Timed t(tc, K_SCATTER);
   launch_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.cover_x.as<int4>(), mf.cover_y.as<int4>(),
                     mf.scat.as<ScatDev>(), mf.nprob, mf.max_nx, mf.max_ny, pact, r);
@@ -899,7 +1041,11 @@ struct EventSet {
 struct TuneTally {
   int levels = 0, changed = 0;
   double ms_default = 0.0, ms_tuned = 0.0;
+  int fuse_depth = -1;                              // chosen subtree root depth (-1: none)
+  double ms_round_default = 0.0, ms_round_tuned = 0.0;
 };
+
+
 
 // Keeps the fastest of `times` (one per candidate, candidate 0 = built-in).
 template <typename S>
@@ -1017,6 +1163,28 @@ void tune_sweeps_mf(stf_ctx c, Mf& mf, int nr, long long ntot, int reps, TuneTal
       tune_keep(c, TuneKey{w == 0 ? 1 : 2, (int)sizeof(T), nr, a.nlevel, a.max_m, a.max_p}, cand[w][d],
                 best[w][d], tally, enc_sweep);
     }
+  // Then the subtree sweeps: whole rounds' sweeps (with the shapes just chosen)
+  // for each root depth D that fits, against level by level (D = -1).
+  const TuneKey fk = fuse_key(mf, sizeof(T), nr);
+  c->tune.erase(fk);
+  const std::vector<int> opts = fuse_options(c, mf, sizeof(T), nr);
+  std::vector<double> tf(opts.size(), 1e300);
+  EventSet fe(2);
+  for (int rep = 0; rep < reps; ++rep)
+    for (size_t k = 0; k < opts.size(); ++k) {
+      HIP_CHECK(hipEventRecord(fe.e[0], st));
+      sweeps_launch<T>(c, mf, r, vec, u, nullptr, nullptr, opts[k]);
+      HIP_CHECK(hipEventRecord(fe.e[1], st));
+      HIP_CHECK(hipEventSynchronize(fe.e[1]));
+      tf[k] = std::min(tf[k], fe.ms(0, 1));
+    }
+  size_t bk = 0;
+  for (size_t k = 1; k < opts.size(); ++k)
+    if (tf[k] < tf[bk]) bk = k;
+  c->tune[fk] = TuneEntry{1, opts[bk], 0, 0, tf[bk], tf[0]};
+  tally.fuse_depth = opts[bk];
+  tally.ms_round_default = tf[0];
+  tally.ms_round_tuned = tf[bk];
 }
 
 // Sets every level's entry of a set to candidate `index` (clamped per level);
@@ -1039,6 +1207,13 @@ int tune_pick_mf(stf_ctx c, Mf& mf, const double2* keps, int nr, int what, int i
         TuneEntry e = enc_sweep(cand[std::min<size_t>(index, cand.size() - 1)]);
         c->tune[TuneKey{w == 0 ? 1 : 2, (int)sizeof(T), nr, a.nlevel, a.max_m, a.max_p}] = e;
       }
+  }
+  if (what & 2) {
+    const TuneKey fk = fuse_key(mf, sizeof(T), nr);
+    c->tune.erase(fk);
+    const std::vector<int> opts = fuse_options(c, mf, sizeof(T), nr);
+    most = std::max(most, (int)opts.size());
+    c->tune[fk] = TuneEntry{1, opts[std::min<size_t>(index, opts.size() - 1)], 0, 0, 0.0, 0.0};
   }
   return most;
 }
@@ -1962,7 +2137,7 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order) 
       rs.z[k] = Z + (long long)j * Tn + (long long)k * b.ntot;
     }
     if (order == STF_ORDER_ADDITIVE) {
-      precond_launch<T>(c, b.mf, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), false, b.pact.as<int>());
+      precond_launch<T>(c, b.mf, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), false, b.pact.as<int>(), 1);
     } else {
       const SweepPlan& sp = sweep_plan(b.mf, order, st);
       sweep_launch<T>(c, b.mf, sp, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), b.keps.as<double2>(),
@@ -2005,6 +2180,7 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order) 
 template <typename T>
 void batch_run_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order, bool use_graph) {
   if (order != STF_ORDER_ADDITIVE) sweep_plan(b.mf, order, c->stream);   // built outside a capture
+  else fuse_prepare(c, b.mf);
   if (!use_graph) {
     batch_cycle<T>(c, b, tol, max_iter, order);
     return;
@@ -2505,7 +2681,7 @@ stf_status stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z)
                                   " bytes of round workspace; the allocation-free round holds at most " +
                                   std::to_string(SCRATCH_BYTES));
     if (!pb->factored || !pb->mf) throw Error(STF_ESTATE, "precond before factor");
-    const Mf& mf = *pb->mf;
+    Mf& mf = *pb->mf;
     int64_t ve = 0, ue = 0;
     round_workspace_elems(pb->plan, ve, ue);
     STF_REQUIRE(ve == mf.vec_elems && ue == mf.u_elems, "internal: workspace size mismatch");
@@ -2518,10 +2694,10 @@ stf_status stf_precond_apply_noalloc(stf_problem pb, const double* v, double* z)
     r.z[0] = reinterpret_cast<double2*>(z);
     if (pb->prec == STF_C64)
       precond_launch<float2>(pb->ctx, mf, r, reinterpret_cast<float2*>(base),
-                             reinterpret_cast<float2*>(base + voff), false);
+                             reinterpret_cast<float2*>(base + voff), false, nullptr, 1);
     else
       precond_launch<double2>(pb->ctx, mf, r, reinterpret_cast<double2*>(base),
-                              reinterpret_cast<double2*>(base + voff), false);
+                              reinterpret_cast<double2*>(base + voff), false, nullptr, 1);
     HIP_CHECK(hipGetLastError());
   });
 }
@@ -2861,7 +3037,7 @@ stf_status stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,
 stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
                         int32_t what, int32_t reps, stf_tune_report* report) {
   if (!ctx) return STF_EINVAL;
-  if (report) *report = stf_tune_report{0, 0, 0.0, 0.0};
+  if (report) *report = stf_tune_report{0, 0, 0.0, 0.0, -1, 0.0, 0.0};
   return guard(ctx, [&] {
     STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
     STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
@@ -2898,7 +3074,10 @@ stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, in
     // a captured batch cycle holds the shapes of its capture
     if (ctx->batch) ctx->batch->release_graph();
     HIP_CHECK(hipStreamSynchronize(ctx->stream));
-    if (report) *report = stf_tune_report{tally.levels, tally.changed, tally.ms_default, tally.ms_tuned};
+    if (report)
+      *report = stf_tune_report{tally.levels,     tally.changed,          tally.ms_default,
+                                tally.ms_tuned,   tally.fuse_depth,       tally.ms_round_default,
+                                tally.ms_round_tuned};
   });
 }
 
@@ -2973,10 +3152,13 @@ stf_status stf_tune_load(stf_ctx ctx, const char* path) {
       TuneEntry e{};
       ok = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf %lf", &k.op, &k.elem, &k.nr, &k.nlevel,
                        &k.max_m, &k.max_p, &e.kind, &e.a, &e.b, &e.c, &e.ms, &e.ms_default) == 12;
-      ok = ok && k.op >= 0 && k.op <= 2 && (k.elem == 8 || k.elem == 16) &&
-           (k.op == 0 ? k.nr == 0 : (k.nr >= 1 && k.nr <= MAX_RHS)) && k.nlevel >= 1 && k.max_m >= 1 &&
-           k.max_p >= 0 && k.max_p <= k.max_m && e.kind >= 1 && e.kind <= 2 && std::isfinite(e.ms) &&
-           std::isfinite(e.ms_default);
+      ok = ok && k.op >= 0 && k.op <= 3 && (k.elem == 8 || k.elem == 16) &&
+           (k.op == 0 ? k.nr == 0 : (k.nr >= 1 && k.nr <= MAX_RHS)) && k.nlevel >= 1 &&
+           std::isfinite(e.ms) && std::isfinite(e.ms_default);
+      if (k.op <= 2)   // a level: its largest front and separator, a launch shape
+        ok = ok && k.max_m >= 1 && k.max_p >= 0 && k.max_p <= k.max_m && e.kind >= 1 && e.kind <= 2;
+      else             // subtree sweeps of a set (max_m: deepest level, max_p: subdomains)
+        ok = ok && k.max_m >= 0 && k.max_p >= 1 && e.kind == 1 && e.a >= -1 && e.a < k.max_m;
       if (ok) got[k] = e;
       else why = "malformed tune file entry";
     }

@@ -943,23 +943,23 @@ struct ColPrefetch {
   }
 };
 
-// Forward sweep for levels with m <= 64 RPL and p <= 64: four fronts per
-// workgroup, one wavefront per front, no workgroup barriers.  Lane rows
-// r = lane + 64 i (i < RPL); with RPL = 1 and m <= 32, G = 64 / W lanes share a
-// row (columns k = g, g + G, ...) and a fixed butterfly adds their sums.  The
-// NR right-hand sides share the operator registers and the index loads.
-template <typename T, int RPL, int KP, int NR>
-__global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restrict__ lpk,
-                                                 const int* __restrict__ piv, T* __restrict__ vec,
-                                                 RhsSet rs) {
+// Forward sweep of one front on one wavefront, for fronts with m <= 64 RPL and
+// p <= 64.  Lane rows r = lane + 64 i (i < RPL); with RPL = 1 and m <= 32,
+// G = 64 / W lanes share a row (columns k = g, g + G, ...) and a fixed
+// butterfly adds their sums.  The NR right-hand sides share the operator
+// registers and the index loads.  sh: this wavefront's LDS scratch.
+// FUSED (subtree sweeps): the children's update vectors come from the LDS
+// slots sl.z, sl.w of the subtree (NR x q_child entries each) and the front's
+// own update part goes to its slot sl.y, or to its global front vector when
+// sl.y < 0 (the subtree's root); the separator part y_p always goes to the
+// global front vector (the backward sweep reads it).
+template <typename T, int RPL, int KP, int NR, bool FUSED>
+__device__ inline void fwd_front(const LevelArgs& a, const FrontDev& f, const T* __restrict__ lpk,
+                                 const int* __restrict__ piv, T* __restrict__ vec, const RhsSet& rs,
+                                 T (&sh)[NR][64 * RPL], T* __restrict__ slots, int4 sl) {
   constexpr int MW = 64 * RPL;
-  __shared__ T sh[4][NR][MW];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
-  if (fi >= a.nlevel) return;                          // whole wavefront
-  const FrontDev f = a.fronts[a.flist ? a.flist[a.first + fi] : a.first + fi];
-  if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
-  const int m = f.p + f.q, p = f.p;
+  const int lane = threadIdx.x & 63;
+  const int m = f.p + f.q, p = f.p, q = f.q;
   const T* L = lpk + f.lpk_off;
   const int W = RPL > 1 ? 64 : (m <= 16 ? 16 : (m <= 32 ? 32 : 64));
   const int G = 64 / W, g = lane / W, rl = lane - g * W;
@@ -994,8 +994,13 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
       const int idx = lane + 64 * i;
       // predicated on the position, not on the loaded index: the value load
       // does not wait for the child map
-      c0[s][i] = (f.nchild > 0 && idx < f.cq[0]) ? vs[f.cvec[0] + idx] : czero<T>();
-      c1[s][i] = (f.nchild > 1 && idx < f.cq[1]) ? vs[f.cvec[1] + idx] : czero<T>();
+      if (FUSED) {
+        c0[s][i] = (f.nchild > 0 && idx < f.cq[0]) ? slots[sl.z * NR + s * f.cq[0] + idx] : czero<T>();
+        c1[s][i] = (f.nchild > 1 && idx < f.cq[1]) ? slots[sl.w * NR + s * f.cq[1] + idx] : czero<T>();
+      } else {
+        c0[s][i] = (f.nchild > 0 && idx < f.cq[0]) ? vs[f.cvec[0] + idx] : czero<T>();
+        c1[s][i] = (f.nchild > 1 && idx < f.cq[1]) ? vs[f.cvec[1] + idx] : czero<T>();
+      }
     }
   }
   // R^I v last: its conversion to T waits for every load issued before it.
@@ -1003,59 +1008,77 @@ __global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restric
   for (int s = 0; s < NR; ++s) val[s] = gidx >= 0 ? from_d2<T>(rs.v[s][gidx]) : czero<T>();
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
-    sh[wv][s][lane] = val[s];
+    sh[s][lane] = val[s];
 #pragma unroll
-    for (int i = 1; i < RPL; ++i) sh[wv][s][lane + 64 * i] = czero<T>();
+    for (int i = 1; i < RPL; ++i) sh[s][lane + 64 * i] = czero<T>();
   }
   wave_sync();
 #pragma unroll
   for (int s = 0; s < NR; ++s)
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
-      if (d0[i] >= 0) sh[wv][s][d0[i]] = cadd(sh[wv][s][d0[i]], c0[s][i]);
+      if (d0[i] >= 0) sh[s][d0[i]] = cadd(sh[s][d0[i]], c0[s][i]);
   wave_sync();
 #pragma unroll
   for (int s = 0; s < NR; ++s)
 #pragma unroll
     for (int i = 0; i < RPL; ++i)
-      if (d1[i] >= 0) sh[wv][s][d1[i]] = cadd(sh[wv][s][d1[i]], c1[s][i]);
+      if (d1[i] >= 0) sh[s][d1[i]] = cadd(sh[s][d1[i]], c1[s][i]);
   wave_sync();
   // (P b)_r = b[perm[r]] on the separator rows (p <= 64).
   T pb[NR];
 #pragma unroll
-  for (int s = 0; s < NR; ++s) pb[s] = sh[wv][s][pv];
+  for (int s = 0; s < NR; ++s) pb[s] = sh[s][pv];
   wave_sync();
 #pragma unroll
-  for (int s = 0; s < NR; ++s) sh[wv][s][lane] = pb[s];
+  for (int s = 0; s < NR; ++s) sh[s][lane] = pb[s];
   wave_sync();
 #pragma unroll
   for (int i = 0; i < RPL; ++i) {
     const int r = rl + 64 * i;
     const int kend = r < m ? min(r, p) : 0;
     T acc[NR];
-    pf[i].template dot_nr<NR>(L, LowerAt{m, r}, g, 0, kend, G, &sh[wv][0][0], MW, acc);
+    pf[i].template dot_nr<NR>(L, LowerAt{m, r}, g, 0, kend, G, &sh[0][0], MW, acc);
 #pragma unroll
     for (int s = 0; s < NR; ++s) {
       if (RPL == 1)
         for (int o = W; o < 64; o <<= 1) acc[s] = cadd(acc[s], shfl_xor_c(acc[s], o));
-      if (g == 0 && r < m) vec[s * rs.vec_stride + f.vec_off + r] = cadd(sh[wv][s][r], acc[s]);
+      if (g == 0 && r < m) {
+        const T y = cadd(sh[s][r], acc[s]);
+        if (!FUSED || r < p || sl.y < 0) vec[s * rs.vec_stride + f.vec_off + r] = y;
+        else slots[sl.y * NR + s * q + (r - p)] = y;
+      }
     }
   }
 }
 
-// Backward sweep for levels with m <= 128 and p <= 64: four fronts per
-// workgroup, one wavefront per front.  Row r < p is shared by G = 64 / W lanes
-// (W >= p), which take columns c = r + g, r + g + G, ... of the packed operator
-// [U11^{-1} V'] (ld p); a fixed butterfly adds their sums.
-template <typename T, int KP, int NR>
-__global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restrict__ upk,
-                                                 T* __restrict__ vec, T* __restrict__ u, RhsSet rs) {
-  __shared__ T sh[4][NR][128];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// Forward sweep for levels with m <= 64 RPL and p <= 64: four fronts per
+// workgroup, one wavefront per front, no workgroup barriers.
+template <typename T, int RPL, int KP, int NR>
+__global__ __launch_bounds__(NT) void k_fwd_wave(LevelArgs a, const T* __restrict__ lpk,
+                                                 const int* __restrict__ piv, T* __restrict__ vec,
+                                                 RhsSet rs) {
+  __shared__ T sh[4][NR][64 * RPL];
+  const int wv = threadIdx.x >> 6;
   const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
-  if (fi >= a.nlevel) return;
+  if (fi >= a.nlevel) return;                          // whole wavefront
   const FrontDev f = a.fronts[a.flist ? a.flist[a.first + fi] : a.first + fi];
   if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
+  fwd_front<T, RPL, KP, NR, false>(a, f, lpk, piv, vec, rs, sh[wv], nullptr, int4{-1, -1, -1, -1});
+}
+
+// Backward sweep of one front on one wavefront, for fronts with m <= 128 and
+// p <= 64.  Row r < p is shared by G = 64 / W lanes (W >= p), which take
+// columns c = r + g, r + g + G, ... of the packed operator [U11^{-1} V'] (ld
+// p); a fixed butterfly adds their sums.  FUSED: x_q comes from the front's
+// LDS slot sl.y (global front vector when sl.y < 0, the subtree's root) and
+// the children's x_q go to their slots sl.z, sl.w instead of their global
+// front vectors.
+template <typename T, int KP, int NR, bool FUSED>
+__device__ inline void bwd_front(const LevelArgs& a, const FrontDev& f, const T* __restrict__ upk,
+                                 T* __restrict__ vec, T* __restrict__ u, const RhsSet& rs,
+                                 T (&sh)[NR][128], T* __restrict__ slots, int4 sl) {
+  const int lane = threadIdx.x & 63;
   const int m = f.p + f.q, p = f.p, q = f.q;
   const T* U = upk + f.upk_off;
   const int W = p <= 4 ? 4 : (p <= 8 ? 8 : (p <= 16 ? 16 : (p <= 32 ? 32 : 64)));
@@ -1073,27 +1096,32 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
       const int idx = lane + 64 * i;
       cm[c][i] = (c < f.nchild && idx < f.cq[c]) ? a.cmap[f.ccmap[c] + idx] : -1;
     }
-  // [y_p ; x_q], both from this front's own vector: y_p from the forward sweep,
-  // x_q put there by the parent's backward sweep.
+  // [y_p ; x_q]: y_p from the forward sweep, x_q put there by the parent's
+  // backward sweep.
+  const bool xq_lds = FUSED && sl.y >= 0;
   T y[NR], xq[NR][2];
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
     const T* vs = vec + s * rs.vec_stride + f.vec_off;
     y[s] = lane < p ? vs[lane] : czero<T>();
 #pragma unroll
-    for (int i = 0; i < 2; ++i) xq[s][i] = lane + 64 * i < q ? vs[p + lane + 64 * i] : czero<T>();
+    for (int i = 0; i < 2; ++i) {
+      const int idx = lane + 64 * i;
+      if (xq_lds) xq[s][i] = idx < q ? slots[sl.y * NR + s * q + idx] : czero<T>();
+      else xq[s][i] = idx < q ? vs[p + idx] : czero<T>();
+    }
   }
 #pragma unroll
   for (int s = 0; s < NR; ++s) {
-    if (lane < p) sh[wv][s][lane] = y[s];
+    if (lane < p) sh[s][lane] = y[s];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
-      if (lane + 64 * i < q) sh[wv][s][p + lane + 64 * i] = xq[s][i];
+      if (lane + 64 * i < q) sh[s][p + lane + 64 * i] = xq[s][i];
   }
   wave_sync();
   const long long uo = a.subs[f.sub].u_off;
   T xp[NR];
-  pf.template dot_nr<NR>(U, UpperAt{p, r}, g, r, r < p ? m : 0, G, &sh[wv][0][0], 128, xp);
+  pf.template dot_nr<NR>(U, UpperAt{p, r}, g, r, r < p ? m : 0, G, &sh[0][0], 128, xp);
 #pragma unroll
   for (int s = 0; s < NR; ++s)
     for (int o = W; o < 64; o <<= 1) xp[s] = cadd(xp[s], shfl_xor_c(xp[s], o));
@@ -1101,7 +1129,7 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
 #pragma unroll
   for (int s = 0; s < NR; ++s)
     if (lane < p) {                        // lane < p <= W: g = 0, r = lane
-      sh[wv][s][lane] = xp[s];
+      sh[s][lane] = xp[s];
       u[s * rs.u_stride + uo + var] = xp[s];
     }
   wave_sync();
@@ -1112,7 +1140,79 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
     for (int c = 0; c < 2; ++c)
 #pragma unroll
       for (int i = 0; i < 2; ++i)
-        if (cm[c][i] >= 0) vec[s * rs.vec_stride + f.cvec[c] + lane + 64 * i] = sh[wv][s][cm[c][i]];
+        if (cm[c][i] >= 0) {
+          const T x = sh[s][cm[c][i]];
+          if (FUSED) slots[(c == 0 ? sl.z : sl.w) * NR + s * f.cq[c] + lane + 64 * i] = x;
+          else vec[s * rs.vec_stride + f.cvec[c] + lane + 64 * i] = x;
+        }
+}
+
+// Backward sweep for levels with m <= 128 and p <= 64: four fronts per
+// workgroup, one wavefront per front.
+template <typename T, int KP, int NR>
+__global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restrict__ upk,
+                                                 T* __restrict__ vec, T* __restrict__ u, RhsSet rs) {
+  __shared__ T sh[4][NR][128];
+  const int wv = threadIdx.x >> 6;
+  const int fi = __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + wv);   // uniform per wavefront
+  if (fi >= a.nlevel) return;
+  const FrontDev f = a.fronts[a.flist ? a.flist[a.first + fi] : a.first + fi];
+  if (a.pact && a.pact[f.prob] == 0) return;           // problem converged (whole wavefront)
+  bwd_front<T, KP, NR, false>(a, f, upk, vec, u, rs, sh[wv], nullptr, int4{-1, -1, -1, -1});
+}
+
+// ---------------------------------------------------------------------------
+// Subtree sweeps: one workgroup (four wavefronts) per subtree of the deep
+// levels, i.e. a front at depth D with all its descendants (every level of
+// which the wavefront kernels take).  The fronts are swept level by level
+// inside the workgroup (bottom-up forward, top-down backward, a wavefront per
+// front, a workgroup barrier between levels), and the update vectors passed
+// between them stay in LDS: only the separator parts y_p, the local fields
+// and the root's update vector go through global memory.  lev: per subtree,
+// K + 1 offsets into fl (relative level j = depth - D); fl: {front, its slot,
+// child 0's slot, child 1's slot}, slots in units of q entries (x NR).
+// ---------------------------------------------------------------------------
+template <typename T, int RPL, int KP, int NR>
+__global__ __launch_bounds__(NT) void k_fwd_subtree(LevelArgs a, FuseArgs z, const T* __restrict__ lpk,
+                                                    const int* __restrict__ piv, T* __restrict__ vec,
+                                                    RhsSet rs) {
+  __shared__ T sh[4][NR][64 * RPL];
+  extern __shared__ unsigned char smem_raw[];
+  T* slots = reinterpret_cast<T*>(smem_raw);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* lev = z.lev + (long long)blockIdx.x * (z.K + 1);
+  if (a.pact && a.pact[a.fronts[z.fl[lev[0]].x].prob] == 0) return;   // whole workgroup
+  for (int j = z.K - 1; j >= 0; --j) {
+    const int e1 = lev[j + 1];
+    for (int e = lev[j] + wv; e < e1; e += 4) {
+      const int4 sl = z.fl[e];
+      const FrontDev f = a.fronts[sl.x];
+      fwd_front<T, RPL, KP, NR, true>(a, f, lpk, piv, vec, rs, sh[wv], slots, sl);
+      wave_sync();
+    }
+    __syncthreads();
+  }
+}
+
+template <typename T, int KP, int NR>
+__global__ __launch_bounds__(NT) void k_bwd_subtree(LevelArgs a, FuseArgs z, const T* __restrict__ upk,
+                                                    T* __restrict__ vec, T* __restrict__ u, RhsSet rs) {
+  __shared__ T sh[4][NR][128];
+  extern __shared__ unsigned char smem_raw[];
+  T* slots = reinterpret_cast<T*>(smem_raw);
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int* lev = z.lev + (long long)blockIdx.x * (z.K + 1);
+  if (a.pact && a.pact[a.fronts[z.fl[lev[0]].x].prob] == 0) return;   // whole workgroup
+  for (int j = 0; j < z.K; ++j) {
+    const int e1 = lev[j + 1];
+    for (int e = lev[j] + wv; e < e1; e += 4) {
+      const int4 sl = z.fl[e];
+      const FrontDev f = a.fronts[sl.x];
+      bwd_front<T, KP, NR, true>(a, f, upk, vec, u, rs, sh[wv], slots, sl);
+      wave_sync();
+    }
+    __syncthreads();
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1941,6 +2041,61 @@ void launch_sweep_bwd(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, 
   else bwd_large_launch<T, 1024>(st, a, sh.parts, sh.kp, upk, vec, u, r);
 }
 
+// LDS of the subtree sweeps besides the slots: the wavefronts' scratch.
+size_t subtree_scratch(size_t elem, int nr, int rpl, bool fwd) {
+  return (size_t)4 * nr * (fwd ? 64 * rpl : 128) * elem;
+}
+
+bool subtree_ok(const FuseArgs& z, size_t elem, int nr) {
+  if (z.K < 1 || z.ntrees < 1 || z.max_m > 128 || z.max_p > 64 || z.slot_q < 0) return false;
+  const int rpl = z.max_m <= 64 ? 1 : 2;
+  const size_t dyn = (size_t)z.slot_q * nr * elem;
+  return dyn + subtree_scratch(elem, nr, rpl, true) <= (size_t)max_lds() &&
+         dyn + subtree_scratch(elem, nr, 1, false) <= (size_t)max_lds();
+}
+
+template <typename T>
+void launch_fwd_subtree(hipStream_t st, const LevelArgs& a, const FuseArgs& z, const T* lpk, const int* piv,
+                        T* vec, const RhsSet& r) {
+  check_rhs(r);
+  if (!subtree_ok(z, sizeof(T), r.nr)) throw Error(STF_EINVAL, "subtree sweep does not fit the levels");
+  const size_t lds = (size_t)z.slot_q * r.nr * sizeof(T);
+  const int rpl = z.max_m <= 64 ? 1 : 2;
+  const int kp = prefetch_depth(z.max_p, 16 / rpl);
+#define STF_CALL(NR)                                                                                  \
+  if (rpl == 2)                                                                                       \
+    hipLaunchKernelGGL((k_fwd_subtree<T, 2, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
+                       vec, r);                                                                       \
+  else if (kp == 8)                                                                                   \
+    hipLaunchKernelGGL((k_fwd_subtree<T, 1, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
+                       vec, r);                                                                       \
+  else                                                                                                \
+    hipLaunchKernelGGL((k_fwd_subtree<T, 1, 16, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
+                       vec, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
+template <typename T>
+void launch_bwd_subtree(hipStream_t st, const LevelArgs& a, const FuseArgs& z, const T* upk, T* vec, T* u,
+                        const RhsSet& r) {
+  check_rhs(r);
+  if (!subtree_ok(z, sizeof(T), r.nr)) throw Error(STF_EINVAL, "subtree sweep does not fit the levels");
+  const size_t lds = (size_t)z.slot_q * r.nr * sizeof(T);
+  // Row groups as in the level kernels: W >= max_p lanes, G = 64 / W per row.
+  int w = 4;
+  while (w < z.max_p) w *= 2;
+  const int g = 64 / w;
+  const int kp = prefetch_depth((z.max_m + g - 1) / g, 16);
+#define STF_CALL(NR)                                                                                   \
+  if (kp == 8)                                                                                         \
+    hipLaunchKernelGGL((k_bwd_subtree<T, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, upk, vec, u, r); \
+  else                                                                                                 \
+    hipLaunchKernelGGL((k_bwd_subtree<T, 16, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, upk, vec, u, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
+}
+
 template <typename T>
 void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
                     const int4* cover_y, const ScatDev* probs, int nprob, int max_nx, int max_ny,
@@ -2003,6 +2158,10 @@ void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsu
                                     const RhsSet&, SweepShape);                                 \
   template void launch_sweep_bwd<T>(hipStream_t, const LevelArgs&, const T*, T*, T*,            \
                                     const RhsSet&, SweepShape);                                 \
+  template void launch_fwd_subtree<T>(hipStream_t, const LevelArgs&, const FuseArgs&, const T*, \
+                                      const int*, T*, const RhsSet&);                           \
+  template void launch_bwd_subtree<T>(hipStream_t, const LevelArgs&, const FuseArgs&, const T*, \
+                                      T*, T*, const RhsSet&);                                   \
   template void launch_scatter<T>(hipStream_t, const T*, const SubDev*, const int4*,            \
                                   const int4*, const ScatDev*, int, int, int, const int*,       \
                                   const RhsSet&);                                               \

@@ -253,6 +253,28 @@ struct LevelArgs {
                                 // pivot column is zeroed on its fully summed rows after
                                 // assembly (-1 = none)
 };
+// Subtree sweeps of the deep levels: one workgroup per subtree (a front at
+// depth D with all its descendants), the update vectors between its fronts in
+// LDS.  Every fused level must be one the wavefront kernels take (m <= 128,
+// p <= 64).
+struct FuseArgs {
+  const int* lev = nullptr;     // per subtree: K + 1 offsets into fl (relative level j = depth - D)
+  const int4* fl = nullptr;     // {front, its slot, child 0's slot, child 1's slot} (-1: none / root)
+  int K = 0;                    // levels per subtree
+  int ntrees = 0;               // subtrees (fronts at depth D)
+  int slot_q = 0;               // largest summed q over a subtree's slots
+  int max_m = 0, max_p = 0;     // over the fused levels
+};
+// Whether the subtree sweeps run these levels with nr right-hand sides (the
+// wavefront kernels' limits and the LDS of the slots).
+bool subtree_ok(const FuseArgs& z, size_t elem, int nr);
+template <typename T>
+void launch_fwd_subtree(hipStream_t st, const LevelArgs& a, const FuseArgs& z, const T* lpk, const int* piv,
+                        T* vec, const RhsSet& r);
+template <typename T>
+void launch_bwd_subtree(hipStream_t st, const LevelArgs& a, const FuseArgs& z, const T* upk, T* vec, T* u,
+                        const RhsSet& r);
+
 // Launch shape of one level's kernel: kind 0 = the built-in rule for the
 // level, else an explicit choice (the autotuner's).  Factorisation: kind 1 =
 // one wavefront per front with the front in LDS (small fronts), kind 2 = the

@@ -1,10 +1,12 @@
 """Autotuner for the per-level launch shapes of the factorisation and of the
 round's sweeps, through the C ABI.
 
-* Every candidate shape of every level gives the same round: the GPU round
-  after forcing candidate i on every level (stf_tune_pick) against the
-  oracle's round (oracle.ddm.SourceTransfer.apply), 1e-12 relative with
-  complex128 fronts and 2e-4 with complex64 fronts, as for the built-in shapes.
+* Every candidate shape of every level, and every subtree-sweep choice (level
+  by level, or the deep levels one subtree per workgroup from each root depth
+  that fits), gives the same round: the GPU round after forcing candidate i
+  on every level (stf_tune_pick) against the oracle's round
+  (oracle.ddm.SourceTransfer.apply), 1e-12 relative with complex128 fronts
+  and 2e-4 with complex64 fronts, as for the built-in shapes.
 * After stf_autotune a solve still meets its tolerance and matches the direct
   solve (oracle.fdfd.solve_direct): 1e-10 relative L2 at rel-res 1e-12
   (complex128), 1e-8 at rel-res 1e-10 (complex64); a batched solve after
@@ -90,9 +92,13 @@ def test_autotune_then_solve_matches_direct(stf, ctx, prec, tol, bar):
         levels = stf.plan_query(dict(p, front_prec=prec))["max_depth"] + 1
         print("autotune report", rep, flush=True)
         assert rep["levels"] == 3 * levels               # factorisation, forward and backward sweeps
-        assert len(ctx.tune_entries()) == 3 * levels
+        ent = ctx.tune_entries()
+        assert len([e for e in ent if e[0][0] <= 2]) == 3 * levels
+        fuse = [e for e in ent if e[0][0] == 3]             # the subtree choice of the problem
+        assert len(fuse) == 1 and fuse[0][1][1] == rep["fuse_depth"]
         assert 0.0 < rep["ms_tuned"] <= rep["ms_default"]
-        for key, shape, ms in ctx.tune_entries():
+        assert 0.0 < rep["ms_round_tuned"] <= rep["ms_round_default"]
+        for key, shape, ms in ent:
             assert key[1] == (8 if prec else 16) and shape[0] in (1, 2) and ms[0] <= ms[1]
         x, info = pb.solve(w.b[0], tol=tol, restart=30, max_iter=400)
         assert info[0]["status"] == 0 and info[0]["relres_true"] <= tol
