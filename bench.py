@@ -160,10 +160,12 @@ def stationary_form(stf, torch, ctx, w, prec, tol, max_rounds):
 CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "front_lu"),
             ("k_stencil", "stencil"), ("k_scatter", "scatter"), ("k_mdot", "arnoldi"),
             ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi"),
-            ("k_gs", "arnoldi")]
+            ("k_gs", "arnoldi"), ("k_gemm", "nn"), ("k_pw_", "nn"), ("k_dft_", "nn"),
+            ("k_mix_", "nn"), ("k_nn_", "nn")]
 SOURCE_OF = {"sweep_fwd": "kernels_front.hip", "sweep_bwd": "kernels_front.hip",
              "front_lu": "kernels_front.hip", "scatter": "kernels_front.hip",
-             "stencil": "kernels_stencil.hip", "arnoldi": "kernels_krylov.hip"}
+             "stencil": "kernels_stencil.hip", "arnoldi": "kernels_krylov.hip",
+             "nn": "kernels_nn.hip"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_metasurface_1064.md")
 COPY_BYTES = 1 << 29          # the calibration copy: 512 MiB read and 512 MiB written
 
@@ -242,6 +244,95 @@ def pmc_summary(fetch_dir, write_dir, copy_fetch_dir, copy_write_dir):
     print("\n".join(lines))
     print()
     print("traffic_json: " + json.dumps(out))
+
+
+def _short_name(name):
+    """Kernel name without namespaces, argument list and template arguments
+    beyond the first (the scalar type)."""
+    import re
+    n = name.replace("stf::(anonymous namespace)::", "").replace("void ", "")
+    n = n.replace("HIP_vector_type<float, 2u>", "c64").replace("HIP_vector_type<double, 2u>", "c128")
+    n = re.sub(r"\(.*", "", n)
+    return n
+
+
+def trace_summary(trace_dir):
+    """Markdown tables from a rocprofv3 --kernel-trace run: time per kernel
+    class and per kernel (template arguments kept), and each sweep launch shape
+    by level (grid size) with its mean duration."""
+    import csv
+    import collections
+    import glob
+    rows = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])))
+    per_k = collections.defaultdict(lambda: [0, 0.0])
+    per_c = collections.defaultdict(lambda: [0, 0.0])
+    per_l = collections.defaultdict(lambda: [0, 0.0])
+    total = 0.0
+    for r in rows:
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-3
+        n = _short_name(r["Kernel_Name"])
+        cls = next((c for pfx, c in CLASS_OF if pfx in r["Kernel_Name"]), "other")
+        total += d
+        for tab, key in ((per_k, n), (per_c, cls)):
+            tab[key][0] += 1
+            tab[key][1] += d
+        if cls in ("sweep_fwd", "sweep_bwd", "front_lu"):
+            wg = int(r["Workgroup_Size_X"])
+            key = (cls, n, int(r["Grid_Size_X"]) // wg, int(r["Grid_Size_Y"]), wg)
+            per_l[key][0] += 1
+            per_l[key][1] += d
+    out = ["Per kernel class (all dispatches of the run):", "",
+           "| class | launches | total ms | mean us | % |", "|---|---|---|---|---|"]
+    for k, (n, t) in sorted(per_c.items(), key=lambda kv: -kv[1][1]):
+        out.append("| %s | %d | %.3f | %.2f | %.1f |" % (k, n, t / 1e3, t / n, 100 * t / total))
+    out += ["", "Per kernel (template arguments: scalar type, then shape parameters):", "",
+            "| kernel | launches | total ms | mean us | % |", "|---|---|---|---|---|"]
+    for k, (n, t) in sorted(per_k.items(), key=lambda kv: -kv[1][1])[:40]:
+        out.append("| %s | %d | %.3f | %.2f | %.1f |" % (k.replace("|", "/"), n, t / 1e3, t / n,
+                                                         100 * t / total))
+    out += ["", "Sweeps and factorisation by launch (kernel, workgroups x parts, threads):", "",
+            "| class | kernel | workgroups | parts | threads | launches | mean us |",
+            "|---|---|---|---|---|---|---|"]
+    for k, (n, t) in sorted(per_l.items(), key=lambda kv: (kv[0][0], -kv[1][1] / kv[1][0])):
+        out.append("| %s | %s | %d | %d | %d | %d | %.2f |" % (k[0], k[1], k[2], k[3], k[4], n, t / n))
+    print("\n".join(out))
+
+
+def mfma_summary(mfma_dir, trace_dir):
+    """Per factorisation launch: matrix-core FP32 operations
+    (SQ_INSTS_VALU_MFMA_MOPS_F32 x 512 = executed MFMA flops), matrix-core busy
+    cycles (SQ_VALU_MFMA_BUSY_CYCLES) and GRBM_GUI_ACTIVE, with the duration of
+    the same launch in the kernel trace."""
+    import csv
+    import collections
+    import glob
+    rows = list(csv.DictReader(open(glob.glob(os.path.join(mfma_dir, "*counter_collection.csv"))[0])))
+    disp = collections.OrderedDict()
+    for r in rows:
+        if "k_factor_" not in r["Kernel_Name"]:
+            continue
+        d = disp.setdefault(r["Dispatch_Id"], {"name": _short_name(r["Kernel_Name"]),
+                                               "grid": int(r["Grid_Size"]) // int(r["Workgroup_Size"]),
+                                               "threads": int(r["Workgroup_Size"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    trows = list(csv.DictReader(open(glob.glob(os.path.join(trace_dir, "*kernel_trace.csv"))[0])))
+    durs = [(int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9 for r in trows
+            if "k_factor_" in r["Kernel_Name"]]
+    out = ["| launch | kernel | workgroups | threads | MFMA FP32 GFLOP | MFMA busy cycles | "
+           "GRBM_GUI_ACTIVE | trace ms | MFMA TFLOP/s |", "|---|---|---|---|---|---|---|---|---|"]
+    tot_f, tot_t = 0.0, 0.0
+    for i, d in enumerate(disp.values()):
+        fl = d.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) * 512
+        t = durs[i] if i < len(durs) else float("nan")
+        tot_f += fl
+        tot_t += t
+        out.append("| %d | %s | %d | %d | %.3f | %.4g | %.4g | %.3f | %.2f |" % (
+            i, d["name"], d["grid"], d["threads"], fl / 1e9, d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0),
+            d.get("GRBM_GUI_ACTIVE", 0.0), t * 1e3, fl / t / 1e12 if t > 0 else 0.0))
+    out.append("")
+    out.append("factorisation: %.2f GFLOP on the matrix cores in %.3f ms (%.2f TFLOP/s executed)"
+               % (tot_f / 1e9, tot_t * 1e3, tot_f / tot_t / 1e12 if tot_t > 0 else 0.0))
+    print("\n".join(out))
 
 
 def roofline(stf, w, prec, stats, steps, levels):
@@ -538,9 +629,19 @@ def main():
                     help="skip the 48-problem batch and the 17M-DoF waveguide problem")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only the PMC calibration copy (512 MiB)")
+    ap.add_argument("--trace-summary", metavar="TRACE_DIR",
+                    help="print tables from a rocprofv3 --kernel-trace output directory and exit")
+    ap.add_argument("--mfma-summary", nargs=2, metavar=("MFMA_DIR", "TRACE_DIR"),
+                    help="print the factorisation's matrix-core counters and exit")
     ap.add_argument("--pmc-summary", nargs=4, metavar=("FETCH", "WRITE", "COPY_FETCH", "COPY_WRITE"),
                     help="summarise rocprofv3 --pmc output directories and exit")
     args = ap.parse_args()
+    if args.trace_summary:
+        trace_summary(args.trace_summary)
+        return
+    if args.mfma_summary:
+        mfma_summary(*args.mfma_summary)
+        return
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
@@ -566,7 +667,7 @@ def main():
     if args.tune_file and os.path.exists(args.tune_file) and not args.no_tune:
         ctx.tune_load(args.tune_file)
         ctx._tune_loaded = True
-    net = learned.load_network(stf, ctx)
+    net = learned.load_network(stf, ctx, max_batch=64)   # the 49 tiles of a 1024^2 grid in one call
     if net is None:
         raise RuntimeError("the trained network (paper_2509_20801_amd/data) is missing")
     ctx.set_nn(net)
