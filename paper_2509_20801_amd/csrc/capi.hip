@@ -1464,11 +1464,16 @@ void nn_forward(stf_nn nn, int B, const float* f, float* y, bool keep = true) {
     nn_dft_y(st, T, nn->ey.as<float2>(), B * W, n, M, false, Hl);
     const float* Rre = P + nn->offR[l];
     nn_mix_fwd(st, Hl, Rre, Rre + (long long)W * W * NM, B, W, NM, nn->G.as<float2>());
-    float* S = nn->S.as<float>();
-    nn_dft_x_inv(st, nn->G.as<float2>(), nn->exi.as<float2>(), B * W, n, M, true, S);
     // g_plane = n^-2 [cos | -sin] (n x 4M) [Re S; Im S] (4M x n)
-    nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1,
-            nn->g.as<float>(), npix, n, 1, 1.0f / ((float)n * (float)n), 0.0f);
+    if (nn_spec_inv_ok(n, M)) {
+      nn_spec_inv(st, nn->G.as<float2>(), nn->exi.as<float2>(), B * W, n, M, true, nn->ainv.as<float>(),
+                  1.0f / ((float)n * (float)n), 0.0f, nn->g.as<float>(), npix);
+    } else {
+      float* S = nn->S.as<float>();
+      nn_dft_x_inv(st, nn->G.as<float2>(), nn->exi.as<float2>(), B * W, n, M, true, S);
+      nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1,
+              nn->g.as<float>(), npix, n, 1, 1.0f / ((float)n * (float)n), 0.0f);
+    }
     const float* Wl = P + nn->offW[l];
     nn_pw_fwd(st, W, W, l < L - 1, hl, Wl, Wl + W * W, nn->g.as<float>(), npix, B,
               keep ? nn->pre[l].as<float>() : nullptr, nn->h[l + 1].as<float>());
@@ -1504,10 +1509,15 @@ void nn_backward(stf_nn nn, int B, const float* f, const float* dy) {
     const long long rs = (long long)W * W * NM;
     nn_mix_bwd(st, nn->H[l].as<float2>(), nn->dG.as<float2>(), Rre, Rre + rs, B, W, NM,
                nn->dH.as<float2>(), Gd + nn->offR[l], Gd + nn->offR[l] + rs);
-    float* S = nn->S.as<float>();
-    nn_dft_x_inv(st, nn->dH.as<float2>(), nn->exi.as<float2>(), B * W, n, M, false, S);
-    nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1, dh2,
-            npix, n, 1, 1.0f, 1.0f);
+    if (nn_spec_inv_ok(n, M)) {
+      nn_spec_inv(st, nn->dH.as<float2>(), nn->exi.as<float2>(), B * W, n, M, false, nn->ainv.as<float>(),
+                  1.0f, 1.0f, dh2, npix);
+    } else {
+      float* S = nn->S.as<float>();
+      nn_dft_x_inv(st, nn->dH.as<float2>(), nn->exi.as<float2>(), B * W, n, M, false, S);
+      nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1, dh2,
+              npix, n, 1, 1.0f, 1.0f);
+    }
     std::swap(dh, dh2);
   }
   nn_pw_bwd(st, c.cin, W, false, dh, nullptr, f, P + nn->offP, npix, B, nullptr, nullptr, part,

@@ -99,22 +99,26 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 }
 
 // ---------------------------------------------------------------------------
-// The x transform of every row: a tall A (M x K, rows contiguous, K <= 256)
-// times a narrow B (K x N, N <= 32).  B is held whole in LDS; each workgroup
-// streams 64 rows of A through LDS 64 columns at a time with 16-byte loads
-// along the rows (VEC: every row start 16-byte aligned), and each thread forms
-// 8 outputs of one row.
+// The x transform of every row: a tall A (M x K, K <= 256) times a narrow B
+// (K x N, N <= 32) on the FP32 matrix cores.  B is held whole in LDS; each
+// workgroup streams 64 rows of A through LDS 64 columns at a time (16-byte
+// loads along the rows when VEC: every row start 16-byte aligned, K % 4 = 0),
+// and each wavefront forms a 16 x 32 block of C as two 16x16x4 products per
+// step of 4 in K.  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16];
+// output (i, j) of a 16 x 16 tile is in lane j + 16 (i / 4), register i % 4.
 // ---------------------------------------------------------------------------
 template <bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_tall(GemmArgs g) {
+  typedef float V4 __attribute__((ext_vector_type(4)));
   __shared__ float Bs[256][33];
   __shared__ float As[64][65];
-  const int tid = threadIdx.x, b = blockIdx.z;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, b = blockIdx.z;
   const float* A = g.A + b * g.sAb;
   const float* Bm = g.B + b * g.sBb;
-  // B whole: 32 entries per thread, loaded in batches of 16 (all loads of a
-  // batch in flight before any is stored)
-  for (int t0 = 0; t0 < g.K * 32; t0 += 16 * 256) {
+  // B whole (rows beyond K zero, read by the last step of 4): 32 entries per
+  // thread, loaded in batches of 16 (all loads of a batch in flight before
+  // any is stored)
+  for (int t0 = 0; t0 < 256 * 32; t0 += 16 * 256) {
     float v[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
@@ -123,13 +127,14 @@ __global__ __launch_bounds__(256) void k_gemm_tall(GemmArgs g) {
     }
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
-      const int t = t0 + u * 256 + tid, k = t >> 5, n = t & 31;
-      if (k < g.K) Bs[k][n] = v[u];
+      const int t = t0 + u * 256 + tid;
+      Bs[t >> 5][t & 31] = v[u];
     }
   }
   const int m0 = blockIdx.x * 64;
-  const int r = tid >> 2, cg = tid & 3;
-  float acc[8] = {};
+  const int l16 = lane & 15, lk = lane >> 4, wr = wv * 16;
+  V4 acc0 = {0.0f, 0.0f, 0.0f, 0.0f}, acc1 = {0.0f, 0.0f, 0.0f, 0.0f};
+  V4 acc2 = {0.0f, 0.0f, 0.0f, 0.0f}, acc3 = {0.0f, 0.0f, 0.0f, 0.0f};
   for (int k0 = 0; k0 < g.K; k0 += 64) {
     __syncthreads();
     // 64 x 64 chunk of A: four 4-entry pieces per thread, all in flight at once
@@ -158,25 +163,36 @@ __global__ __launch_bounds__(256) void k_gemm_tall(GemmArgs g) {
       for (int e = 0; e < 4; ++e) As[rr][c4 + e] = v[u][e];
     }
     __syncthreads();
-    const int kw = min(64, g.K - k0);
-    for (int kk = 0; kk < kw; ++kk) {
-      const float a = As[r][kk];
-      const float* bk = &Bs[k0 + kk][cg * 8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) acc[j] = fmaf(a, bk[j], acc[j]);
+    const int kw = min(64, g.K - k0);             // columns beyond K were stored as zeros
+    // two steps of 4 at a time into separate accumulators: four independent chains
+    for (int kk = 0; kk < kw; kk += 8) {
+      const float a = As[wr + l16][kk + lk], a2 = As[wr + l16][kk + 4 + lk];
+      const float b0 = Bs[k0 + kk + lk][l16], b1 = Bs[k0 + kk + lk][16 + l16];
+      const float b2 = Bs[k0 + kk + 4 + lk][l16], b3 = Bs[k0 + kk + 4 + lk][16 + l16];
+      // transposed products (B^T A^T): lane (l16, lk) receives
+      // C[wr + l16][16 j + 4 lk + v], four consecutive columns per lane
+      acc0 = __builtin_amdgcn_mfma_f32_16x16x4f32(b0, a, acc0, 0, 0, 0);
+      acc1 = __builtin_amdgcn_mfma_f32_16x16x4f32(b1, a, acc1, 0, 0, 0);
+      acc2 = __builtin_amdgcn_mfma_f32_16x16x4f32(b2, a2, acc2, 0, 0, 0);
+      acc3 = __builtin_amdgcn_mfma_f32_16x16x4f32(b3, a2, acc3, 0, 0, 0);
     }
   }
-  const int m = m0 + r;
+  acc0 += acc2;
+  acc1 += acc3;
+  float* C = g.C + b * g.sCb;
+  const int m = m0 + wr + l16;
   if (m >= g.M) return;
-  float* C = g.C + b * g.sCb + m * g.sCm;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) {
-    const int n = cg * 8 + j;
-    if (n < g.N) {
-      float* c = C + n * g.sCn;
-      *c = g.alpha * acc[j] + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int n = 16 * j + 4 * lk + v;
+      if (n < g.N) {
+        float* c = C + m * g.sCm + n * g.sCn;
+        const float x = j == 0 ? acc0[v] : acc1[v];
+        *c = g.alpha * x + (g.beta != 0.0f ? g.beta * *c : 0.0f);
+      }
     }
-  }
 }
 
 // ---------------------------------------------------------------------------
@@ -245,6 +261,169 @@ __global__ __launch_bounds__(256) void k_gemm_mfma(GemmArgs g) {
           *c = g.alpha * acc[i][j][v] + (g.beta != 0.0f ? g.beta * *c : 0.0f);
         }
       }
+}
+
+// ---------------------------------------------------------------------------
+// The inverse transform of one plane in one pass: the x inverse
+// S[a][x] = sum_k w_k G[a][k] exp(+2 pi i k x / n) (w_k = 1, 2, 2, ... when
+// weighted) formed in LDS as rows [Re S; Im S] (4M x n), then the y inverse
+// out = alpha Ainv S + beta out (Ainv: n x 4M, rows contiguous) on the FP32
+// matrix cores, 16 x 16 tiles of out, a wavefront per 16-row block at a time
+// with its rows of Ainv held in registers across the column blocks.  n is a
+// multiple of 16 (at most 1024), 4M <= 88; out 16-byte aligned with npix a
+// multiple of 4.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_spec_inv(const float2* __restrict__ G,
+                                                  const float2* __restrict__ ex, int n, int M,
+                                                  int weighted, const float* __restrict__ ainv,
+                                                  float alpha, float beta, float* __restrict__ out,
+                                                  long long npix) {
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  extern __shared__ float Ss[];                  // 4M x (n + 16): rows 16 banks apart
+  __shared__ float2 Gs[2 * 22 * 22];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int plane = blockIdx.x, ld = n + 16, K = 4 * M;
+  const float2* Gp = G + (long long)plane * 2 * M * M;
+  for (int t = tid; t < 2 * M * M; t += 256) {
+    float2 v = Gp[t];
+    if (weighted && t % M > 0) v = make_float2(2.0f * v.x, 2.0f * v.y);
+    Gs[t] = v;
+  }
+  __syncthreads();
+  // S: thread per column x, its M twiddles in registers
+  for (int x = tid; x < n; x += 256) {
+    float2 w[22];
+#pragma unroll
+    for (int k = 0; k < 22; ++k) w[k] = k < M ? ex[(long long)k * n + x] : make_float2(0.0f, 0.0f);
+    for (int a = 0; a < 2 * M; ++a) {
+      float re = 0.0f, im = 0.0f;
+#pragma unroll
+      for (int k = 0; k < 22; ++k)
+        if (k < M) {
+          const float2 gv = Gs[a * M + k];
+          re = fmaf(gv.x, w[k].x, fmaf(-gv.y, w[k].y, re));
+          im = fmaf(gv.x, w[k].y, fmaf(gv.y, w[k].x, im));
+        }
+      Ss[a * ld + x] = re;
+      Ss[(2 * M + a) * ld + x] = im;
+    }
+  }
+  __syncthreads();
+  const int l16 = lane & 15, lk = lane >> 4, nb = n / 16;
+  float* op = out + (long long)plane * npix;
+  for (int yb = wv; yb < nb; yb += 4) {
+    float av[22];                                // Ainv[yb*16 + l16][4 s + lk], s < K / 4
+#pragma unroll
+    for (int s4 = 0; s4 < 22; ++s4)
+      av[s4] = 4 * s4 < K ? ainv[(long long)(yb * 16 + l16) * K + 4 * s4 + lk] : 0.0f;
+    // four column blocks at a time: four independent accumulation chains
+    for (int xb0 = 0; xb0 < nb; xb0 += 4) {
+      V4 acc[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = V4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s4 = 0; s4 < 22; ++s4)
+        if (4 * s4 < K) {
+          float bv[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            bv[j] = xb0 + j < nb ? Ss[(4 * s4 + lk) * ld + (xb0 + j) * 16 + l16] : 0.0f;
+          // the transposed product (S^T Ainv^T): lane (l16, lk) receives
+          // out[yb*16 + l16][x0 + 4 lk + v], four consecutive x per lane
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j], av[s4], acc[j], 0, 0, 0);
+        }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (xb0 + j >= nb) continue;
+        float4* c = reinterpret_cast<float4*>(op + (long long)(yb * 16 + l16) * n + (xb0 + j) * 16 + 4 * lk);
+        float4 r = make_float4(alpha * acc[j][0], alpha * acc[j][1], alpha * acc[j][2], alpha * acc[j][3]);
+        if (beta != 0.0f) {
+          const float4 o = *c;
+          r.x += beta * o.x; r.y += beta * o.y; r.z += beta * o.z; r.w += beta * o.w;
+        }
+        *c = r;
+      }
+    }
+  }
+}
+
+// The same for the compiled tile side NN and mode count MM (the trained
+// network's n = 256, M = 16): every LDS offset an immediate, loops unrolled.
+template <int NN, int MM>
+__global__ __launch_bounds__(256) void k_spec_inv_t(const float2* __restrict__ G,
+                                                    const float2* __restrict__ ex, int weighted,
+                                                    const float* __restrict__ ainv, float alpha,
+                                                    float beta, float* __restrict__ out, long long npix) {
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  constexpr int LD = NN + 16, K = 4 * MM, NB = NN / 16;
+  static_assert(NN % 64 == 0 && NN <= 256, "a column per thread, four column blocks per group");
+  extern __shared__ float Ss[];                  // K x LD
+  __shared__ float2 Gs[2 * MM * MM];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int plane = blockIdx.x;
+  const float2* Gp = G + (long long)plane * 2 * MM * MM;
+  for (int t = tid; t < 2 * MM * MM; t += 256) {
+    float2 v = Gp[t];
+    if (weighted && t % MM > 0) v = make_float2(2.0f * v.x, 2.0f * v.y);
+    Gs[t] = v;
+  }
+  __syncthreads();
+  if (tid < NN) {
+    const int x = tid;
+    float2 w[MM];
+#pragma unroll
+    for (int k = 0; k < MM; ++k) w[k] = ex[k * NN + x];
+#pragma unroll 4
+    for (int a = 0; a < 2 * MM; ++a) {
+      float re = 0.0f, im = 0.0f;
+#pragma unroll
+      for (int k = 0; k < MM; ++k) {
+        const float2 gv = Gs[a * MM + k];
+        re = fmaf(gv.x, w[k].x, fmaf(-gv.y, w[k].y, re));
+        im = fmaf(gv.x, w[k].y, fmaf(gv.y, w[k].x, im));
+      }
+      Ss[a * LD + x] = re;
+      Ss[(2 * MM + a) * LD + x] = im;
+    }
+  }
+  __syncthreads();
+  const int l16 = lane & 15, lk = lane >> 4;
+  float* op = out + (long long)plane * npix;
+  const float* sb = Ss + lk * LD + l16;
+  for (int yb = wv; yb < NB; yb += 4) {
+    float av[K / 4];
+    const float* ar = ainv + (yb * 16 + l16) * K + lk;
+#pragma unroll
+    for (int s4 = 0; s4 < K / 4; ++s4) av[s4] = ar[4 * s4];
+    float* orow = op + (long long)(yb * 16 + l16) * NN + 4 * lk;
+    for (int xb0 = 0; xb0 < NB; xb0 += 4) {
+      V4 acc[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[j] = V4{0.0f, 0.0f, 0.0f, 0.0f};
+      const float* sx = sb + xb0 * 16;
+#pragma unroll
+      for (int s4 = 0; s4 < K / 4; ++s4) {
+        float bv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = sx[4 * s4 * LD + j * 16];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[j], av[s4], acc[j], 0, 0, 0);
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        float4* c = reinterpret_cast<float4*>(orow + (xb0 + j) * 16);
+        float4 r = make_float4(alpha * acc[j][0], alpha * acc[j][1], alpha * acc[j][2], alpha * acc[j][3]);
+        if (beta != 0.0f) {
+          const float4 o = *c;
+          r.x += beta * o.x; r.y += beta * o.y; r.z += beta * o.z; r.w += beta * o.w;
+        }
+        *c = r;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -727,6 +906,26 @@ void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int 
   if (2 * M * M > 4 * NNT) throw Error(STF_EINVAL, "too many modes for the y transform");
   const size_t lds = (size_t)n * 2 * M * sizeof(float) + (size_t)2 * M * 64 * sizeof(float2);
   hipLaunchKernelGGL(k_dft_y, dim3(planes), dim3(NNT), lds, st, T, ey, n, M, grad_scale ? 1 : 0, H);
+}
+
+bool nn_spec_inv_ok(int n, int M) { return n % 16 == 0 && n <= 1024 && M >= 1 && M <= 22; }
+// the float4 stores of k_spec_inv: 16-byte aligned planes
+bool nn_spec_inv_out_ok(const float* out, long long npix) {
+  return (reinterpret_cast<uintptr_t>(out) & 15) == 0 && npix % 4 == 0;
+}
+
+void nn_spec_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
+                 bool weighted, const float* ainv, float alpha, float beta, float* out, long long npix) {
+  if (!nn_spec_inv_ok(n, M) || !nn_spec_inv_out_ok(out, npix))
+    throw Error(STF_EINVAL, "nn: inverse transform shape or alignment");
+  const size_t lds = (size_t)4 * M * (n + 16) * sizeof(float);
+  if (n == 256 && M == 16) {
+    hipLaunchKernelGGL((k_spec_inv_t<256, 16>), dim3(planes), dim3(256), lds, st, G, ex, weighted ? 1 : 0,
+                       ainv, alpha, beta, out, npix);
+    return;
+  }
+  hipLaunchKernelGGL(k_spec_inv, dim3(planes), dim3(256), lds, st, G, ex, n, M, weighted ? 1 : 0, ainv,
+                     alpha, beta, out, npix);
 }
 
 void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,

@@ -442,6 +442,11 @@ void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, lon
              float beta);
 void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int n, int M,
               bool grad_scale, float2* H);
+// out (per plane, n x n) = alpha Ainv S + beta out with S the x inverse of G
+// (as nn_dft_x_inv), in one pass per plane (n % 16 == 0, n <= 1024, M <= 22).
+bool nn_spec_inv_ok(int n, int M);
+void nn_spec_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
+                 bool weighted, const float* ainv, float alpha, float beta, float* out, long long npix);
 void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
                   bool weighted, float* S);
 void nn_mix_fwd(hipStream_t st, const float2* H, const float* Rre, const float* Rim, int B, int W,

@@ -19,6 +19,9 @@ from workloads import learned
 pytestmark = pytest.mark.gpu
 
 CFG = nn.NNConfig(n=32, width=8, modes=4, layers=3, cin=3)
+# the deployed architecture (256^2 tiles, 16 channels, 16 modes, 4 layers),
+# whose transforms run the kernels compiled for that shape
+DEPLOY = nn.NNConfig(n=256, width=16, modes=16, layers=4, cin=3)
 
 
 @pytest.fixture(scope="module")
@@ -55,30 +58,32 @@ def test_param_count_matches_reference(stf):
         assert stf.nn_param_count(c.n, c.width, c.modes, c.layers, c.cin) == c.nparams()
 
 
-def test_forward_matches_reference(stf, ctx):
+@pytest.mark.parametrize("cfg,batch", [(CFG, 3), (DEPLOY, 2)], ids=["small", "deployed"])
+def test_forward_matches_reference(stf, ctx, cfg, batch):
     import torch
-    flat = _flat(CFG, 1)
-    net = _net(stf, ctx, CFG, flat)
-    f, _ = _inputs(CFG, 3, 2)
+    flat = _flat(cfg, 1)
+    net = _net(stf, ctx, cfg, flat)
+    f, _ = _inputs(cfg, batch, 2)
     y = net.forward(torch.from_numpy(f).cuda()).cpu().numpy()
-    yr, _ = nn.forward(CFG, nn.unflatten(CFG, flat), f.astype(np.float64))
+    yr, _ = nn.forward(cfg, nn.unflatten(cfg, flat), f.astype(np.float64))
     assert np.abs(y - yr).max() <= 1e-4 * np.abs(yr).max()
     net.close()
 
 
-def test_gradient_matches_reference(stf, ctx):
+@pytest.mark.parametrize("cfg,batch", [(CFG, 3), (DEPLOY, 1)], ids=["small", "deployed"])
+def test_gradient_matches_reference(stf, ctx, cfg, batch):
     import torch
-    flat = _flat(CFG, 4)
-    net = _net(stf, ctx, CFG, flat)
-    f, t = _inputs(CFG, 3, 5)
+    flat = _flat(cfg, 4)
+    net = _net(stf, ctx, cfg, flat)
+    f, t = _inputs(cfg, batch, 5)
     loss, g = net.loss_grad(torch.from_numpy(f).cuda(), torch.from_numpy(t).cuda())
-    p = nn.unflatten(CFG, flat)
-    y, cache = nn.forward(CFG, p, f.astype(np.float64))
+    p = nn.unflatten(cfg, flat)
+    y, cache = nn.forward(cfg, p, f.astype(np.float64))
     lr_, dy = nn.loss_and_grad(y, t.astype(np.float64))
-    gr, _ = nn.backward(CFG, p, cache, dy)
+    gr, _ = nn.backward(cfg, p, cache, dy)
     assert abs(loss - lr_) <= 1e-5 * lr_
-    gg = nn.unflatten(CFG, g.astype(np.float64))
-    for name, _ in CFG.shapes():
+    gg = nn.unflatten(cfg, g.astype(np.float64))
+    for name, _ in cfg.shapes():
         num = np.linalg.norm(gg[name] - gr[name])
         assert num <= 2e-3 * np.linalg.norm(gr[name]) + 1e-7, (name, num, np.linalg.norm(gr[name]))
     net.close()
