@@ -333,31 +333,29 @@ __global__ __launch_bounds__(64) void k_factor_small(LevelArgs a, T* __restrict_
       G[(k + 1) * m + r] = cfms(G[k * m + r], G[(k + 1) * m + k], G[(k + 1) * m + r]);
     wave_sync();
     pivot_step(k + 1);
-    // Row k+1 past column k+1 still lacks step k's update: u2 = row k+1 - l u1.
+    // Row k+1 past column k+1 still lacks step k's update: u2 = row k+1 - l u1,
+    // formed once (a lane per column) before the rank-2 update reads it.
     const T lk1 = G[k * m + k + 1];
+    for (int c = k + 2 + lane; c < m; c += 64) G[c * m + k + 1] = cfms(lk1, G[c * m + k], G[c * m + k + 1]);
+    wave_sync();
     for (int r = k + 2 + lane; r < m; r += 64) {
       const T l1 = G[k * m + r], l2 = G[(k + 1) * m + r];
       // four columns per round trip: all reads of a batch before its writes
       constexpr int CB = 4;
       for (int c0 = k + 2; c0 < m; c0 += CB) {
-        T u1[CB], a2[CB], x[CB];
+        T u1[CB], u2[CB], x[CB];
 #pragma unroll
         for (int e = 0; e < CB; ++e) {
-          const int c = min(c0 + e, m - 1);
-          u1[e] = G[c * m + k];
-          a2[e] = G[c * m + k + 1];
-          x[e] = G[c * m + r];
+          const T* gc = G + min(c0 + e, m - 1) * m;
+          u1[e] = gc[k];
+          u2[e] = gc[k + 1];
+          x[e] = gc[r];
         }
 #pragma unroll
         for (int e = 0; e < CB; ++e)
-          if (c0 + e < m) {
-            const T u2 = cfms(lk1, u1[e], a2[e]);
-            G[(c0 + e) * m + r] = cfms(l2, u2, cfms(l1, u1[e], x[e]));
-          }
+          if (c0 + e < m) G[(c0 + e) * m + r] = cfms(l2, u2[e], cfms(l1, u1[e], x[e]));
       }
     }
-    wave_sync();
-    for (int c = k + 2 + lane; c < m; c += 64) G[c * m + k + 1] = cfms(lk1, G[c * m + k], G[c * m + k + 1]);
     wave_sync();
   }
   if (k < p) {                      // odd p: a last single step
