@@ -161,7 +161,7 @@ CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "fro
             ("k_stencil", "stencil"), ("k_scatter", "scatter"), ("k_mdot", "arnoldi"),
             ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi"),
             ("k_gs", "arnoldi"), ("k_gemm", "nn"), ("k_pw_", "nn"), ("k_dft_", "nn"),
-            ("k_mix_", "nn"), ("k_nn_", "nn")]
+            ("k_mix_", "nn"), ("k_nn_", "nn"), ("k_spec_", "nn")]
 SOURCE_OF = {"sweep_fwd": "kernels_front.hip", "sweep_bwd": "kernels_front.hip",
              "front_lu": "kernels_front.hip", "scatter": "kernels_front.hip",
              "stencil": "kernels_stencil.hip", "arnoldi": "kernels_krylov.hip",
