@@ -187,16 +187,19 @@ def test_learned_solve_converges_and_falls_back(stf, ctx):
     net.close()
 
 
-def test_trained_network_gain_on_the_1024_grid(stf, ctx):
-    """What the committed trained network gains on a 1024 x 1024 metasurface
-    (seed 5001, not a training tile): both solves converge to the same field;
-    when the fallback rejects the guess the run is the zero-guess run."""
+@pytest.mark.parametrize("interior,parts,seed", [(1024, 8, 5001), (2048, 16, 5002)],
+                         ids=["1024", "2048"])
+def test_trained_network_gain_on_the_deploy_grids(stf, ctx, interior, parts, seed):
+    """What the committed trained network gains on the deploy metasurfaces
+    (1024^2 at 8 x 8 subdomains, seed 5001; 2048^2 at 16 x 16, seed 5002; not
+    training tiles): both solves converge to the same field; when the fallback
+    rejects the guess the run is the zero-guess run."""
     import json
     from paper_2509_20801_amd import learned as L
-    net = L.load_network(stf, ctx)
+    net = L.load_network(stf, ctx, max_batch=64)
     if net is None:
         pytest.skip("no trained weights in the package")
-    w = workloads.configs.metasurface_sheet(seed=5001)
+    w = workloads.configs.metasurface_sheet(interior=interior, parts=parts, seed=seed)
     out = L.evaluate(stf, ctx, net, w, log=lambda s: print(s))
     z, l = out["zero"], out["learned"]
     assert z["relres_true"] <= 1e-8 and l["relres_true"] <= 1e-8
