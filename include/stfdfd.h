@@ -337,9 +337,9 @@ void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
  * is run again with the chosen shapes; a perturbed pivot is not reported
  * here).  Contents of the round's workspaces are overwritten.  With the
  * sweeps, it then times whole rounds' sweeps level by level against subtree
- * sweeps (the deep levels swept one subtree per workgroup, each root depth
- * that fits) and keeps the fastest for the set's signature (operation 3 in
- * the entries below).  report: NULL or filled with the levels timed, how many
+ * sweeps (the deep levels swept 1, 2, 4 or 8 subtrees per workgroup, each
+ * root depth that fits) and keeps the fastest for the set's signature
+ * (operation 3 in the entries below).  report: NULL or filled with the levels timed, how many
  * changed from the built-in shape, the summed level times with the built-in
  * and with the chosen shapes (ms), the chosen subtree root depth (-1: level
  * by level, or no sweeps tuned) and the sweeps' time with the built-in and
@@ -387,7 +387,8 @@ stf_status  stf_tune_clear(stf_ctx ctx);
  * level, max m, max p}; shape = {kind, nb or kp, ntf or ntl, parts};
  * ms = {chosen, built-in}.  Operation 3 (the subtree choice of a set): key =
  * {3, bytes, nrhs, fronts of the set, deepest level, subdomains}, shape =
- * {1, root depth or -1, 0, 0}.  Any output pointer may be NULL. */
+ * {1, root depth or -1 (level by level), subtrees per workgroup (1, 2, 4, 8),
+ * 0}.  Any output pointer may be NULL. */
 int32_t     stf_tune_count(stf_ctx ctx);
 stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms);
 

@@ -222,7 +222,7 @@ struct Mf {
   std::vector<Level> levels;     // by depth
   std::vector<FrontDev> h_fronts;  // host copies of the front instances and children
   std::vector<int> h_children;
-  std::map<int, std::unique_ptr<FusePlan>> fuse;   // subtree sweeps by root depth
+  std::map<int, std::unique_ptr<FusePlan>> fuse;   // subtree sweeps by choice (fuse_code)
   DBuf lcoef, subs, fronts, vars, cmap, ents, children, cover_x, cover_y, scat;
   DBuf fac, lpk, upk, piv, vec, u;
   int ws_nr = 0;                 // right-hand sides the vec / u workspaces hold
@@ -262,15 +262,17 @@ struct Mf {
     while (d - 1 >= 0 && levels[d - 1].max_m <= 128 && levels[d - 1].max_p <= 64) --d;
     return d <= max_depth - 1 ? d : -1;
   }
-  // The subtree sweep tables for roots at depth D (built once, kept).
-  const FusePlan& fuse_plan(int D, hipStream_t st) {
-    auto it = fuse.find(D);
+  // The subtree sweep tables for `code` = 16 D + T: roots at depth D, T
+  // subtrees (consecutive roots of the level) per workgroup (built once, kept).
+  const FusePlan& fuse_plan(int code, hipStream_t st) {
+    auto it = fuse.find(code);
     if (it != fuse.end()) return *it->second;
-    STF_REQUIRE(D >= 0 && D < max_depth, "internal: subtree root depth out of range");
+    const int D = code / 16, T = code % 16;
+    STF_REQUIRE(D >= 0 && D < max_depth && T >= 1, "internal: subtree choice out of range");
     std::unique_ptr<FusePlan> fp(new FusePlan());
     FuseArgs& z = fp->args;
     z.K = max_depth - D + 1;
-    z.ntrees = levels[D].n;
+    z.ntrees = (levels[D].n + T - 1) / T;
     for (int d = D; d <= max_depth; ++d) {
       z.max_m = std::max(z.max_m, levels[d].max_m);
       z.max_p = std::max(z.max_p, levels[d].max_p);
@@ -281,7 +283,7 @@ struct Mf {
     std::vector<std::vector<int>> byl(z.K);
     for (int t = 0; t < z.ntrees; ++t) {
       for (auto& v : byl) v.clear();
-      byl[0].push_back(levels[D].off + t);
+      for (int i = t * T; i < std::min(levels[D].n, (t + 1) * T); ++i) byl[0].push_back(levels[D].off + i);
       for (int j = 1; j < z.K; ++j)
         for (int f : byl[j - 1])
           for (int c = 0; c < h_fronts[f].nchild; ++c) byl[j].push_back(h_children[h_fronts[f].child_off + c]);
@@ -310,7 +312,7 @@ struct Mf {
     z.fl = fp->fl.as<int4>();
     HIP_CHECK(hipStreamSynchronize(st));
     FusePlan& ref = *fp;
-    fuse[D] = std::move(fp);
+    fuse[code] = std::move(fp);
     return ref;
   }
 };
@@ -768,30 +770,26 @@ int factor_problem(stf_problem pb, bool fault = false) {
   return h;
 }
 
-// Root depth of the subtree sweeps of a set for nr right-hand sides: the
+// Subtree sweeps of a set for nr right-hand sides, as a code 16 D + T (roots
+// at depth D, T subtrees per workgroup) or -1 (level by level): the
 // autotuned choice when the context has one for the set's signature, else
-// -1 (level by level: on the 1064^2 metasurface at 8 x 8 subdomains the
-// subtree sweeps measure slower, 1.04 against 0.65 ms for a round's sweeps
-// with four right-hand sides, since a workgroup takes its subtree's fronts
-// one level after another with few subtrees resident per CU).
+// -1 (on the 1064^2 metasurface at 8 x 8 subdomains the subtree sweeps
+// measure slower, since a workgroup takes its subtrees' fronts one level
+// after another).
 TuneKey fuse_key(const Mf& mf, size_t elem, int nr) {
   return TuneKey{3, (int)elem, nr, (int)std::min<int64_t>(mf.n_fronts, INT32_MAX), mf.max_depth, mf.nsub};
 }
 
 // With build = false, only tables already built count (no allocation).
 int fuse_depth_for(stf_ctx c, Mf& mf, size_t elem, int nr, bool build = true) {
-  auto usable = [&](int D) {
-    if (!build && !mf.fuse.count(D)) return false;
-    return subtree_ok(mf.fuse_plan(D, c->stream).args, elem, nr);
-  };
   auto it = c->tune.find(fuse_key(mf, elem, nr));
   const int dmin = mf.fuse_min_depth();
-  if (it != c->tune.end()) {
-    const int D = it->second.a;
-    if (D < 0 || dmin < 0 || D < dmin || D >= mf.max_depth) return -1;
-    return usable(D) ? D : -1;
-  }
-  return -1;
+  if (it == c->tune.end()) return -1;
+  const int D = it->second.a, T = it->second.b;
+  if (D < 0 || dmin < 0 || D < dmin || D >= mf.max_depth || T < 1 || T > 8) return -1;
+  const int code = 16 * D + T;
+  if (!build && !mf.fuse.count(code)) return -1;
+  return subtree_ok(mf.fuse_plan(code, c->stream).args, elem, nr) ? code : -1;
 }
 
 // Builds the subtree tables the rounds of a set will use (outside graph
@@ -801,14 +799,16 @@ void fuse_prepare(stf_ctx c, Mf& mf) {
   for (int nr = 1; nr <= MAX_RHS; ++nr) (void)fuse_depth_for(c, mf, elem, nr, true);
 }
 
-// Subtree-sweep choices for a set: the built-in one (level by level) first,
-// then every root depth whose subtrees fit.
+// Subtree-sweep choices for a set: the built-in one (level by level, -1)
+// first, then every root depth and subtrees per workgroup (1, 2, 4, 8) that
+// fit, as codes 16 D + T.
 std::vector<int> fuse_options(stf_ctx c, Mf& mf, size_t elem, int nr) {
   std::vector<int> out{-1};
   const int dmin = mf.fuse_min_depth();
   if (dmin >= 0)
     for (int D = dmin; D < mf.max_depth; ++D)
-      if (subtree_ok(mf.fuse_plan(D, c->stream).args, elem, nr)) out.push_back(D);
+      for (int T : {1, 2, 4, 8})
+        if (subtree_ok(mf.fuse_plan(16 * D + T, c->stream).args, elem, nr)) out.push_back(16 * D + T);
   return out;
 }
 
@@ -818,16 +818,18 @@ std::vector<int> fuse_options(stf_ctx c, Mf& mf, size_t elem, int nr) {
 // vectors `vec` and local fields `u` (vec_elems and u_elems entries per
 // right-hand side).  With timed = false no event is recorded (the
 // allocation-free entry point).
-// The forward and backward sweeps of a round: the deep levels (depth >= D)
-// as subtree sweeps when D >= 0, the rest level by level.  r: strides set.
+// The forward and backward sweeps of a round: with a subtree choice
+// (code = 16 D + T >= 0) the deep levels (depth >= D) as subtree sweeps, the
+// rest level by level.  r: strides set.
 template <typename T>
-void sweeps_launch(stf_ctx c, Mf& mf, const RhsSet& r, T* vec, T* u, stf_ctx tc, const int* pact, int D) {
+void sweeps_launch(stf_ctx c, Mf& mf, const RhsSet& r, T* vec, T* u, stf_ctx tc, const int* pact, int code) {
   hipStream_t st = c->stream;
   const T* lpk = mf.lpk.as<T>();
+  const int D = code >= 0 ? code / 16 : -1;
   const int top = D >= 0 ? D : mf.max_depth + 1;
   if (D >= 0) {
     Timed t(tc, K_SWEEP_FWD);
-    launch_fwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), mf.fuse_plan(D, st).args, lpk,
+    launch_fwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), mf.fuse_plan(code, st).args, lpk,
                           mf.piv.as<int>(), vec, r);
   }
   for (int d = top - 1; d >= 0; --d) {
@@ -842,7 +844,7 @@ void sweeps_launch(stf_ctx c, Mf& mf, const RhsSet& r, T* vec, T* u, stf_ctx tc,
   }
   if (D >= 0) {
     Timed t(tc, K_SWEEP_BWD);
-    launch_bwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), mf.fuse_plan(D, st).args,
+    launch_bwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), mf.fuse_plan(code, st).args,
                           mf.upk.as<T>(), vec, u, r);
   }
 }
@@ -1181,8 +1183,9 @@ void tune_sweeps_mf(stf_ctx c, Mf& mf, int nr, long long ntot, int reps, TuneTal
   size_t bk = 0;
   for (size_t k = 1; k < opts.size(); ++k)
     if (tf[k] < tf[bk]) bk = k;
-  c->tune[fk] = TuneEntry{1, opts[bk], 0, 0, tf[bk], tf[0]};
-  tally.fuse_depth = opts[bk];
+  c->tune[fk] = opts[bk] < 0 ? TuneEntry{1, -1, 1, 0, tf[bk], tf[0]}
+                             : TuneEntry{1, opts[bk] / 16, opts[bk] % 16, 0, tf[bk], tf[0]};
+  tally.fuse_depth = opts[bk] < 0 ? -1 : opts[bk] / 16;
   tally.ms_round_default = tf[0];
   tally.ms_round_tuned = tf[bk];
 }
@@ -1213,7 +1216,8 @@ int tune_pick_mf(stf_ctx c, Mf& mf, const double2* keps, int nr, int what, int i
     c->tune.erase(fk);
     const std::vector<int> opts = fuse_options(c, mf, sizeof(T), nr);
     most = std::max(most, (int)opts.size());
-    c->tune[fk] = TuneEntry{1, opts[std::min<size_t>(index, opts.size() - 1)], 0, 0, 0.0, 0.0};
+    const int o = opts[std::min<size_t>(index, opts.size() - 1)];
+    c->tune[fk] = o < 0 ? TuneEntry{1, -1, 1, 0, 0.0, 0.0} : TuneEntry{1, o / 16, o % 16, 0, 0.0, 0.0};
   }
   return most;
 }
@@ -3168,7 +3172,8 @@ stf_status stf_tune_load(stf_ctx ctx, const char* path) {
       if (k.op <= 2)   // a level: its largest front and separator, a launch shape
         ok = ok && k.max_m >= 1 && k.max_p >= 0 && k.max_p <= k.max_m && e.kind >= 1 && e.kind <= 2;
       else             // subtree sweeps of a set (max_m: deepest level, max_p: subdomains)
-        ok = ok && k.max_m >= 0 && k.max_p >= 1 && e.kind == 1 && e.a >= -1 && e.a < k.max_m;
+        ok = ok && k.max_m >= 0 && k.max_p >= 1 && e.kind == 1 && e.a >= -1 && e.a < k.max_m &&
+             e.b >= 1 && e.b <= 8;
       if (ok) got[k] = e;
       else why = "malformed tune file entry";
     }

@@ -1160,9 +1160,9 @@ __global__ __launch_bounds__(NT) void k_bwd_wave(LevelArgs a, const T* __restric
 }
 
 // ---------------------------------------------------------------------------
-// Subtree sweeps: one workgroup (four wavefronts) per subtree of the deep
-// levels, i.e. a front at depth D with all its descendants (every level of
-// which the wavefront kernels take).  The fronts are swept level by level
+// Subtree sweeps: one workgroup (four wavefronts) per group of subtrees of
+// the deep levels (a subtree: a front at depth D with all its descendants,
+// every level of which the wavefront kernels take).  The fronts are swept level by level
 // inside the workgroup (bottom-up forward, top-down backward, a wavefront per
 // front, a workgroup barrier between levels), and the update vectors passed
 // between them stay in LDS: only the separator parts y_p, the local fields
@@ -1179,12 +1179,13 @@ __global__ __launch_bounds__(NT) void k_fwd_subtree(LevelArgs a, FuseArgs z, con
   T* slots = reinterpret_cast<T*>(smem_raw);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int* lev = z.lev + (long long)blockIdx.x * (z.K + 1);
-  if (a.pact && a.pact[a.fronts[z.fl[lev[0]].x].prob] == 0) return;   // whole workgroup
   for (int j = z.K - 1; j >= 0; --j) {
     const int e1 = lev[j + 1];
     for (int e = lev[j] + wv; e < e1; e += 4) {
       const int4 sl = z.fl[e];
       const FrontDev f = a.fronts[sl.x];
+      // a converged problem's fronts are skipped (a subtree is one problem's)
+      if (a.pact && a.pact[f.prob] == 0) continue;
       fwd_front<T, RPL, KP, NR, true>(a, f, lpk, piv, vec, rs, sh[wv], slots, sl);
       wave_sync();
     }
@@ -1200,12 +1201,12 @@ __global__ __launch_bounds__(NT) void k_bwd_subtree(LevelArgs a, FuseArgs z, con
   T* slots = reinterpret_cast<T*>(smem_raw);
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int* lev = z.lev + (long long)blockIdx.x * (z.K + 1);
-  if (a.pact && a.pact[a.fronts[z.fl[lev[0]].x].prob] == 0) return;   // whole workgroup
   for (int j = 0; j < z.K; ++j) {
     const int e1 = lev[j + 1];
     for (int e = lev[j] + wv; e < e1; e += 4) {
       const int4 sl = z.fl[e];
       const FrontDev f = a.fronts[sl.x];
+      if (a.pact && a.pact[f.prob] == 0) continue;    // converged problem
       bwd_front<T, KP, NR, true>(a, f, upk, vec, u, rs, sh[wv], slots, sl);
       wave_sync();
     }
