@@ -530,11 +530,14 @@ def subdomain_study(stf, torch, ctx, tol=1e-3, fgmres_tol=1e-8):
             "stationary_tol": tol, "fgmres_tol": fgmres_tol, "rows": rows}
 
 
-def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order="diagonal"):
+def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order="diagonal",
+                     tune=True):
     """The large single problem: the 4128 x 4128 waveguide layout (17.0M DoF,
     16 x 16 subdomains, complex64 fronts, fundamental-mode source) to FP64 true
     rel-res 1e-10; one warm-up and one timed step (assembly, factorisation,
-    solve), in the four-diagonal order and in the additive one."""
+    solve), in the four-diagonal order and in the additive one.  The autotuner
+    (outside the timed steps) covers the factorisation levels, the additive
+    round's sweeps and the subtree choice of the diagonal stages."""
     import workloads
     w = workloads.configs.waveguides()
     eps = torch.from_numpy(w.eps_cells).cuda()
@@ -543,6 +546,16 @@ def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order
     x = torch.empty_like(b)
     out = {"workload": "waveguides 4128x4128 (4096^2 + 16-cell PML), h = 20 nm, lambda = 1.55 um, "
                        "16x16 subdomains", "ndof": w.ndof, "tol": tol}
+    if tune and not getattr(ctx, "_tune_loaded", False):
+        t0 = time.perf_counter()
+        orders = () if order == "additive" else (order,)
+        rep = ctx.autotune(pb, nrhs=1, reps=2, orders=orders)
+        rep["wall_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
+        nf = pb.info()["nfronts"]
+        # (root depth or -1, subtrees per workgroup, ms chosen, ms level by level)
+        rep["staged"] = [(e[1][1], e[1][2], round(e[2][0], 3), round(e[2][1], 3))
+                         for e in ctx.tune_entries() if e[0][0] >= 4 and e[0][3] == nf]
+        out["autotune"] = rep
     for od in (order, "additive"):
         def step():
             pb.assemble(eps)
@@ -580,7 +593,8 @@ def batched_disks(stf, torch, ctx, steps, tol, restart, max_iter, order="diagona
     if tune:
         t0 = time.perf_counter()
         tuned = None if getattr(ctx, "_tune_loaded", False) else \
-            ctx.autotune(pbs, nrhs=4, sweeps=order == "additive", reps=2)
+            ctx.autotune(pbs, nrhs=4, sweeps=order == "additive", reps=2,
+                         orders=() if order == "additive" else (order,))
         if tuned is not None:
             tuned["wall_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
 

@@ -327,9 +327,11 @@ void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
  * stf_autotune times every candidate shape of every level (HIP events, `reps`
  * passes of 1..100, the fastest pass counting) for the problems given: one
  * problem (its own fronts), or nprob > 1 problems as the set that
- * stf_batch_solve builds for the same problems in the same order.  what: 1 the
- * factorisation, 2 the additive round's sweeps with nrhs (1..4) right-hand
- * sides, 3 both.  The fastest shape per level signature is kept in the context
+ * stf_batch_solve builds for the same problems in the same order.  what: a
+ * sum of 1 (the factorisation), 2 (the additive round's sweeps with nrhs
+ * (1..4) right-hand sides), 4, 8, 16 (the subtree choice of the staged
+ * orders rows, rows + columns, diagonal: whole applications timed level by
+ * level and with subtree sweeps in every stage, operation 3 + order below).  The fastest shape per level signature is kept in the context
  * and used by every later factorisation and round on it whose levels have
  * that signature (solo, batched, staged or allocation-free); other levels keep
  * the built-in rule.  Needs assembled problems of this context with one front
@@ -358,9 +360,10 @@ stf_status  stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, i
 /* Test hook: sets, without timing, the entry of every level of the given
  * problems (as stf_autotune selects them) to the level's candidate shape
  * `index` (>= 0; the last candidate where a level has fewer; 0 is the
- * built-in shape), and with the sweeps the subtree choice of the set to its
- * option `index` (0 level by level, the built-in choice, then each root
- * depth that fits).  *max_candidates (may be NULL) receives the largest
+ * built-in shape), and with the sweeps (what & 2, and the staged orders'
+ * bits 4, 8, 16) the subtree choice of the set to its option `index` (0 level
+ * by level, the built-in choice, then each root depth and subtrees per
+ * workgroup that fit).  *max_candidates (may be NULL) receives the largest
  * candidate count over the levels, so that index = 0 .. max - 1 visits every
  * candidate; every one must give the same results to rounding. */
 stf_status  stf_tune_pick(stf_ctx ctx, int32_t nprob, const stf_problem* probs, int32_t nrhs,
@@ -388,7 +391,8 @@ stf_status  stf_tune_clear(stf_ctx ctx);
  * ms = {chosen, built-in}.  Operation 3 (the subtree choice of a set): key =
  * {3, bytes, nrhs, fronts of the set, deepest level, subdomains}, shape =
  * {1, root depth or -1 (level by level), subtrees per workgroup (1, 2, 4, 8),
- * 0}.  Any output pointer may be NULL. */
+ * 0}; operations 4, 5, 6: the same for the stages of the orders rows, rows +
+ * columns, diagonal.  Any output pointer may be NULL. */
 int32_t     stf_tune_count(stf_ctx ctx);
 stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms);
 

@@ -132,6 +132,15 @@ def _close_all():
         c.close()
 
 
+def _what(factor, sweeps, orders):
+    what = (1 if factor else 0) | (2 if sweeps else 0)
+    for o in orders:
+        if o not in _abi.ORDERS or o == "additive":
+            raise ValueError("staged orders: rows, rows_cols, diagonal")
+        what |= 2 << _abi.ORDERS[o]
+    return what
+
+
 class Context:
     """Device context.  stream: a hipStream_t handle (int) or a torch stream; by
     default the current torch stream of `device` (so torch and library work are
@@ -190,27 +199,29 @@ class Context:
                 mask |= 1 << (KERNEL_CLASSES.index(c) if isinstance(c, str) else int(c))
         _check(self.handle, self._lib.stf_ctx_set_timing_mask(self.handle, mask))
 
-    def autotune(self, problems, nrhs=4, factor=True, sweeps=True, reps=3):
+    def autotune(self, problems, nrhs=4, factor=True, sweeps=True, reps=3, orders=()):
         """Time every candidate launch shape of each tree level (factorisation
         and/or the round's sweeps with `nrhs` right-hand sides) of one problem, or
         of the set a batched solve builds for `problems`, and keep the fastest per
-        level signature on this context.  Leaves the problems factored.  Returns
-        the report as a dict."""
+        level signature on this context; `orders` (names of staged orders) adds
+        the subtree choice of their stages.  Leaves the problems factored.
+        Returns the report as a dict."""
         if isinstance(problems, Problem):
             problems = [problems]
-        what = (1 if factor else 0) | (2 if sweeps else 0)
+        what = _what(factor, sweeps, orders)
         arr = (C.c_void_p * len(problems))(*[p.handle.value for p in problems])
         rep = _abi.TuneReport()
         _check(self.handle, self._lib.stf_autotune(self.handle, len(problems), arr, int(nrhs), what,
                                                    int(reps), C.byref(rep)))
         return {f: getattr(rep, f) for f, _ in _abi.TuneReport._fields_}
 
-    def tune_pick(self, problems, index, nrhs=4, factor=True, sweeps=True):
-        """Test hook: every level's shape set to its candidate `index` (clamped);
-        returns the largest candidate count over the levels."""
+    def tune_pick(self, problems, index, nrhs=4, factor=True, sweeps=True, orders=()):
+        """Test hook: every level's shape (and the subtree choices of the
+        additive round and of `orders`) set to candidate `index` (clamped);
+        returns the largest candidate count."""
         if isinstance(problems, Problem):
             problems = [problems]
-        what = (1 if factor else 0) | (2 if sweeps else 0)
+        what = _what(factor, sweeps, orders)
         arr = (C.c_void_p * len(problems))(*[p.handle.value for p in problems])
         most = C.c_int32()
         _check(self.handle, self._lib.stf_tune_pick(self.handle, len(problems), arr, int(nrhs), what,

@@ -197,17 +197,21 @@ struct Timed {
 // level (largest first within a level), so one launch per level serves them all.
 // Stages of a sweeping order over a set: stage t holds, for every problem,
 // that problem's stage t (problems with fewer stages contribute nothing).
+// Subtree sweeps of a set over subtrees of the deep levels (see FuseArgs).
+struct FusePlan {
+  FuseArgs args;                // device pointers into lev / fl
+  DBuf lev, fl;
+};
+
 struct SweepPlan {
   int nstage = 0;
   std::vector<int> s_first, s_count;          // per stage: its members in slist
   std::vector<std::vector<Level>> lv;         // per stage and depth: range in flist
   DBuf slist, flist, inst;                    // members, front instances, membership flags
-};
-
-// Subtree sweeps of a set for roots at depth D (see FuseArgs).
-struct FusePlan {
-  FuseArgs args;                // device pointers into lev / fl
-  DBuf lev, fl;
+  std::vector<int> h_flist;                   // host copy of flist
+  // subtree sweeps per choice (16 D + T): per stage, the tables over the
+  // stage's fronts at depth D (null where the stage has none)
+  std::map<int, std::vector<std::unique_ptr<FusePlan>>> fuse;
 };
 
 struct Mf {
@@ -262,17 +266,15 @@ struct Mf {
     while (d - 1 >= 0 && levels[d - 1].max_m <= 128 && levels[d - 1].max_p <= 64) --d;
     return d <= max_depth - 1 ? d : -1;
   }
-  // The subtree sweep tables for `code` = 16 D + T: roots at depth D, T
-  // subtrees (consecutive roots of the level) per workgroup (built once, kept).
-  const FusePlan& fuse_plan(int code, hipStream_t st) {
-    auto it = fuse.find(code);
-    if (it != fuse.end()) return *it->second;
-    const int D = code / 16, T = code % 16;
+  // Subtree sweep tables for the given roots (fronts at depth D), T subtrees
+  // (consecutive roots) per workgroup.
+  std::unique_ptr<FusePlan> build_fuse(const std::vector<int>& roots, int D, int T, hipStream_t st) const {
     STF_REQUIRE(D >= 0 && D < max_depth && T >= 1, "internal: subtree choice out of range");
     std::unique_ptr<FusePlan> fp(new FusePlan());
     FuseArgs& z = fp->args;
     z.K = max_depth - D + 1;
-    z.ntrees = (levels[D].n + T - 1) / T;
+    const int nr = (int)roots.size();
+    z.ntrees = (nr + T - 1) / T;
     for (int d = D; d <= max_depth; ++d) {
       z.max_m = std::max(z.max_m, levels[d].max_m);
       z.max_p = std::max(z.max_p, levels[d].max_p);
@@ -283,7 +285,7 @@ struct Mf {
     std::vector<std::vector<int>> byl(z.K);
     for (int t = 0; t < z.ntrees; ++t) {
       for (auto& v : byl) v.clear();
-      for (int i = t * T; i < std::min(levels[D].n, (t + 1) * T); ++i) byl[0].push_back(levels[D].off + i);
+      for (int i = t * T; i < std::min(nr, (t + 1) * T); ++i) byl[0].push_back(roots[i]);
       for (int j = 1; j < z.K; ++j)
         for (int f : byl[j - 1])
           for (int c = 0; c < h_fronts[f].nchild; ++c) byl[j].push_back(h_children[h_fronts[f].child_off + c]);
@@ -311,6 +313,18 @@ struct Mf {
     z.lev = fp->lev.as<int>();
     z.fl = fp->fl.as<int4>();
     HIP_CHECK(hipStreamSynchronize(st));
+    return fp;
+  }
+  // The subtree sweep tables for `code` = 16 D + T over every front at depth
+  // D (built once, kept).
+  const FusePlan& fuse_plan(int code, hipStream_t st) {
+    auto it = fuse.find(code);
+    if (it != fuse.end()) return *it->second;
+    const int D = code / 16, T = code % 16;
+    STF_REQUIRE(D >= 0 && D < max_depth, "internal: subtree root depth out of range");
+    std::vector<int> roots(levels[D].n);
+    std::iota(roots.begin(), roots.end(), levels[D].off);
+    std::unique_ptr<FusePlan> fp = build_fuse(roots, D, T, st);
     FusePlan& ref = *fp;
     fuse[code] = std::move(fp);
     return ref;
@@ -958,10 +972,50 @@ const SweepPlan& sweep_plan(Mf& mf, int order, hipStream_t st) {
   upload(sp->slist, slist, st);
   upload(sp->flist, flist, st);
   upload(sp->inst, inst, st);
+  sp->h_flist = flist;
   HIP_CHECK(hipStreamSynchronize(st));
   const SweepPlan& ref = *sp;
   mf.sweeps[order] = std::move(sp);
   return ref;
+}
+
+// The per-stage subtree tables of a staged order for choice `code`
+// (16 D + T), built on first use.
+const std::vector<std::unique_ptr<FusePlan>>& stage_fuse(const Mf& mf, const SweepPlan& spc, int code,
+                                                          hipStream_t st) {
+  SweepPlan& sp = const_cast<SweepPlan&>(spc);
+  auto it = sp.fuse.find(code);
+  if (it != sp.fuse.end()) return it->second;
+  const int D = code / 16, T = code % 16;
+  std::vector<std::unique_ptr<FusePlan>> per(sp.nstage);
+  for (int t = 0; t < sp.nstage; ++t) {
+    const Level& L = sp.lv[t][D];
+    if (L.n == 0) continue;
+    std::vector<int> roots(sp.h_flist.begin() + L.off, sp.h_flist.begin() + L.off + L.n);
+    per[t] = mf.build_fuse(roots, D, T, st);
+  }
+  return sp.fuse[code] = std::move(per);
+}
+
+// Subtree choice (16 D + T) for the stages of `order` on a set with nr
+// right-hand sides: the autotuned one (operation 3 + order) or -1 (level by
+// level).  With build = false only tables already built count.
+TuneKey staged_fuse_key(const Mf& mf, size_t elem, int nr, int order) {
+  return TuneKey{3 + order, (int)elem, nr, (int)std::min<int64_t>(mf.n_fronts, INT32_MAX), mf.max_depth,
+                 mf.nsub};
+}
+
+int staged_fuse_for(stf_ctx c, Mf& mf, const SweepPlan& sp, size_t elem, int nr, int order, bool build) {
+  auto it = c->tune.find(staged_fuse_key(mf, elem, nr, order));
+  const int dmin = mf.fuse_min_depth();
+  if (it == c->tune.end()) return -1;
+  const int D = it->second.a, T = it->second.b;
+  if (D < 0 || dmin < 0 || D < dmin || D >= mf.max_depth || T < 1 || T > 8) return -1;
+  const int code = 16 * D + T;
+  if (!build && !sp.fuse.count(code)) return -1;
+  for (const auto& f : stage_fuse(mf, sp, code, c->stream))
+    if (f && !subtree_ok(f->args, elem, nr)) return -1;
+  return code;
 }
 
 // One application of the staged order for the right-hand sides of r:
@@ -969,10 +1023,13 @@ const SweepPlan& sweep_plan(Mf& mf, int order, hipStream_t st) {
 // the first stage, where z = 0), its sweeps, z_s += its full local fields.
 // keps / gc: the set's concatenated node permittivity and coupling arrays;
 // rbuf: one global vector per slot (rstride apart) for the stage residuals.
+// code: subtree choice (16 D + T) for the deep levels of every stage, or -1
+// (level by level); its tables must exist (stage_fuse) when the call is
+// captured into a graph.
 template <typename T>
 void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u,
                   const double2* keps, const double2* gc, double2* rbuf, long long rstride,
-                  long long zlen, bool timed, const int* pact = nullptr) {
+                  long long zlen, bool timed, const int* pact = nullptr, int code = -1) {
   hipStream_t st = c->stream;
   stf_ctx tc = timed ? c : nullptr;
   r.vec_stride = mf.vec_elems;
@@ -980,7 +1037,11 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
   for (int s = 0; s < r.nr; ++s) launch_zero(st, r.z[s], zlen);
   const T* lpk = mf.lpk.as<T>();
   const int* sl = sp.slist.as<int>();
+  const std::vector<std::unique_ptr<FusePlan>>* sfz = code >= 0 ? &stage_fuse(mf, sp, code, st) : nullptr;
+  const int Dz = code >= 0 ? code / 16 : mf.max_depth + 1;
   for (int t = 0; t < sp.nstage; ++t) {
+    const FusePlan* fz = sfz ? (*sfz)[t].get() : nullptr;
+    const int top = fz ? Dz : mf.max_depth + 1;
     const int sf = sp.s_first[t], sc = sp.s_count[t];
     RhsSet rr = r;
     if (t > 0) {
@@ -989,7 +1050,12 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
                             mf.max_ixl, mf.max_iyl, pact, r, rbuf, rstride);
       for (int s = 0; s < r.nr; ++s) rr.v[s] = rbuf + s * rstride;
     }
-    for (int d = mf.max_depth; d >= 0; --d) {
+    if (fz) {
+      Timed tm(tc, K_SWEEP_FWD);
+      launch_fwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), fz->args, lpk, mf.piv.as<int>(),
+                            vec, rr);
+    }
+    for (int d = top - 1; d >= 0; --d) {
       if (sp.lv[t][d].n == 0) continue;
       Timed tm(tc, K_SWEEP_FWD);
       LevelArgs la = mf.level_args(d, nullptr, pact);
@@ -998,7 +1064,7 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
       la.nlevel = sp.lv[t][d].n;
       launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, rr, tuned_sweep(c, la, true, sizeof(T), rr.nr));
     }
-    for (int d = 0; d <= mf.max_depth; ++d) {
+    for (int d = 0; d < top; ++d) {
       if (sp.lv[t][d].n == 0) continue;
       Timed tm(tc, K_SWEEP_BWD);
       LevelArgs la = mf.level_args(d, nullptr, pact);
@@ -1006,6 +1072,11 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
       la.first = sp.lv[t][d].off;
       la.nlevel = sp.lv[t][d].n;
       launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, rr, tuned_sweep(c, la, false, sizeof(T), rr.nr));
+    }
+    if (fz) {
+      Timed tm(tc, K_SWEEP_BWD);
+      launch_bwd_subtree<T>(st, mf.level_args(mf.max_depth, nullptr, pact), fz->args, mf.upk.as<T>(), vec,
+                            u, rr);
     }
     Timed tm(tc, K_SCATTER);
     launch_stage_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.scat.as<ScatDev>(), mf.cover_x.as<int4>(),
@@ -1190,6 +1261,58 @@ void tune_sweeps_mf(stf_ctx c, Mf& mf, int nr, long long ntot, int reps, TuneTal
   tally.ms_round_tuned = tf[bk];
 }
 
+// Staged orders: whole applications of `order` (with the per-level shapes
+// chosen so far) for each subtree choice, level by level first; keeps the
+// fastest for the set's signature (operation 3 + order).
+template <typename T>
+void tune_staged_mf(stf_ctx c, Mf& mf, int nr, long long ntot, const double2* keps, const double2* gc,
+                    int order, int reps) {
+  hipStream_t st = c->stream;
+  if (mf.ws_nr < nr) {
+    mf.vec.alloc((size_t)mf.vec_elems * sizeof(T) * nr);
+    mf.u.alloc((size_t)mf.u_elems * sizeof(T) * nr);
+    mf.ws_nr = nr;
+  }
+  DBuf v0, z, rb;
+  v0.alloc((size_t)ntot * nr * sizeof(double2));
+  z.alloc((size_t)ntot * nr * sizeof(double2));
+  rb.alloc((size_t)ntot * nr * sizeof(double2));
+  launch_zero(st, v0.as<double2>(), ntot * nr);
+  RhsSet r;
+  r.nr = nr;
+  for (int s = 0; s < nr; ++s) {
+    r.v[s] = v0.as<double2>() + (size_t)s * ntot;
+    r.z[s] = z.as<double2>() + (size_t)s * ntot;
+  }
+  const SweepPlan& sp = sweep_plan(mf, order, st);
+  const TuneKey key = staged_fuse_key(mf, sizeof(T), nr, order);
+  c->tune.erase(key);
+  const std::vector<int> opts = fuse_options(c, mf, sizeof(T), nr);
+  std::vector<double> tf(opts.size(), 1e300);
+  EventSet fe(2);
+  for (int rep = 0; rep < reps; ++rep)
+    for (size_t k = 0; k < opts.size(); ++k) {
+      if (opts[k] >= 0) {
+        bool ok = true;
+        for (const auto& f : stage_fuse(mf, sp, opts[k], st))
+          if (f && !subtree_ok(f->args, sizeof(T), nr)) ok = false;
+        if (!ok) continue;
+      }
+      HIP_CHECK(hipEventRecord(fe.e[0], st));
+      sweep_launch<T>(c, mf, sp, r, mf.vec.as<T>(), mf.u.as<T>(), keps, gc, rb.as<double2>(), ntot, ntot, false,
+                      nullptr, opts[k]);
+      HIP_CHECK(hipEventRecord(fe.e[1], st));
+      HIP_CHECK(hipEventSynchronize(fe.e[1]));
+      tf[k] = std::min(tf[k], fe.ms(0, 1));
+    }
+  size_t bk = 0;
+  for (size_t k = 1; k < opts.size(); ++k)
+    if (tf[k] < tf[bk]) bk = k;
+  c->tune[key] = opts[bk] < 0 ? TuneEntry{1, -1, 1, 0, tf[bk], tf[0]}
+                              : TuneEntry{1, opts[bk] / 16, opts[bk] % 16, 0, tf[bk], tf[0]};
+  HIP_CHECK(hipStreamSynchronize(st));
+}
+
 // Sets every level's entry of a set to candidate `index` (clamped per level);
 // returns the largest candidate count.
 template <typename T>
@@ -1211,8 +1334,10 @@ int tune_pick_mf(stf_ctx c, Mf& mf, const double2* keps, int nr, int what, int i
         c->tune[TuneKey{w == 0 ? 1 : 2, (int)sizeof(T), nr, a.nlevel, a.max_m, a.max_p}] = e;
       }
   }
-  if (what & 2) {
-    const TuneKey fk = fuse_key(mf, sizeof(T), nr);
+  for (int order = 0; order <= STF_ORDER_DIAGONAL; ++order) {
+    const int bit = order == 0 ? 2 : (2 << order);
+    if (!(what & bit)) continue;
+    const TuneKey fk = order == 0 ? fuse_key(mf, sizeof(T), nr) : staged_fuse_key(mf, sizeof(T), nr, order);
     c->tune.erase(fk);
     const std::vector<int> opts = fuse_options(c, mf, sizeof(T), nr);
     most = std::max(most, (int)opts.size());
@@ -1251,8 +1376,9 @@ void sweep_problem(stf_problem pb, const RhsSet& r, int order) {
     mf.ws_nr = r.nr;
   }
   pb->ksr.alloc((size_t)pb->N * sizeof(double2) * r.nr);
+  const int code = staged_fuse_for(pb->ctx, mf, sp, sizeof(T), r.nr, order, true);
   sweep_launch<T>(pb->ctx, mf, sp, r, mf.vec.as<T>(), mf.u.as<T>(), pb->keps.as<double2>(),
-                  pb->gcoef.as<double2>(), pb->ksr.as<double2>(), pb->N, pb->N, true);
+                  pb->gcoef.as<double2>(), pb->ksr.as<double2>(), pb->N, pb->N, true, nullptr, code);
 }
 
 // One preconditioner application for the right-hand sides of r in `order`.
@@ -2154,8 +2280,9 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order) 
       precond_launch<T>(c, b.mf, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), false, b.pact.as<int>(), 1);
     } else {
       const SweepPlan& sp = sweep_plan(b.mf, order, st);
+      const int code = staged_fuse_for(c, b.mf, sp, sizeof(T), rs.nr, order, false);
       sweep_launch<T>(c, b.mf, sp, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), b.keps.as<double2>(),
-                      b.gc.as<double2>(), b.RS.as<double2>(), b.ntot, b.ntot, false, b.pact.as<int>());
+                      b.gc.as<double2>(), b.RS.as<double2>(), b.ntot, b.ntot, false, b.pact.as<int>(), code);
     }
     launch_bstencil(st, 0, Z + (long long)j * Tn, nullptr, W, b.keps.as<double2>(), b.gc.as<double2>(),
                     sys, b.tsys.as<int>(), b.ntiles, act, nullptr);
@@ -2193,8 +2320,12 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order) 
 // context stream); rebuilt when the systems, m, tol or max_iter change.
 template <typename T>
 void batch_run_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order, bool use_graph) {
-  if (order != STF_ORDER_ADDITIVE) sweep_plan(b.mf, order, c->stream);   // built outside a capture
-  else fuse_prepare(c, b.mf);
+  if (order != STF_ORDER_ADDITIVE) {                  // tables built outside a capture
+    const SweepPlan& sp = sweep_plan(b.mf, order, c->stream);
+    (void)staged_fuse_for(c, b.mf, sp, sizeof(T), b.nslot, order, true);
+  } else {
+    fuse_prepare(c, b.mf);
+  }
   if (!use_graph) {
     batch_cycle<T>(c, b, tol, max_iter, order);
     return;
@@ -3055,7 +3186,7 @@ stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, in
   return guard(ctx, [&] {
     STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
     STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
-    STF_REQUIRE(what >= 1 && what <= 3, "what: 1 factorisation, 2 sweeps, 3 both");
+    STF_REQUIRE(what >= 1 && what <= 31, "what: bits 1 factorisation, 2 additive sweeps, 4 / 8 / 16 staged orders");
     STF_REQUIRE(reps >= 1 && reps <= 100, "reps must be 1..100");
     for (int p = 0; p < nprob; ++p) {
       STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
@@ -3065,25 +3196,29 @@ stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, in
     }
     const bool c64 = probs[0]->prec == STF_C64;
     TuneTally tally;
-    auto run = [&](Mf& mf, const double2* keps, int* flag, long long ntot) {
+    auto run = [&](Mf& mf, const double2* keps, const double2* gc, int* flag, long long ntot) {
       if (c64) {
         if (what & 1) tune_factor_mf<float2>(ctx, mf, keps, flag, reps, tally);
         factor_mf<float2>(ctx, mf, keps, flag, false, nullptr, nullptr);
         if (what & 2) tune_sweeps_mf<float2>(ctx, mf, nrhs, ntot, reps, tally);
+        for (int order = 1; order <= STF_ORDER_DIAGONAL; ++order)
+          if (what & (2 << order)) tune_staged_mf<float2>(ctx, mf, nrhs, ntot, keps, gc, order, reps);
       } else {
         if (what & 1) tune_factor_mf<double2>(ctx, mf, keps, flag, reps, tally);
         factor_mf<double2>(ctx, mf, keps, flag, false, nullptr, nullptr);
         if (what & 2) tune_sweeps_mf<double2>(ctx, mf, nrhs, ntot, reps, tally);
+        for (int order = 1; order <= STF_ORDER_DIAGONAL; ++order)
+          if (what & (2 << order)) tune_staged_mf<double2>(ctx, mf, nrhs, ntot, keps, gc, order, reps);
       }
     };
     if (nprob == 1) {
       stf_problem pb = probs[0];
-      run(pb->ensure_mf(), pb->keps.as<double2>(), pb->flag.as<int>(), pb->N);
+      run(pb->ensure_mf(), pb->keps.as<double2>(), pb->gcoef.as<double2>(), pb->flag.as<int>(), pb->N);
       pb->factored = true;
       pb->fac_timed = false;
     } else {
       BatchState& bs = batch_state(ctx, nprob, probs);
-      run(bs.mf, bs.keps.as<double2>(), bs.flag.as<int>(), bs.ntot);
+      run(bs.mf, bs.keps.as<double2>(), bs.gc.as<double2>(), bs.flag.as<int>(), bs.ntot);
     }
     // a captured batch cycle holds the shapes of its capture
     if (ctx->batch) ctx->batch->release_graph();
@@ -3102,7 +3237,7 @@ stf_status stf_tune_pick(stf_ctx ctx, int32_t nprob, const stf_problem* probs, i
   return guard(ctx, [&] {
     STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
     STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
-    STF_REQUIRE(what >= 1 && what <= 3, "what: 1 factorisation, 2 sweeps, 3 both");
+    STF_REQUIRE(what >= 1 && what <= 31, "what: bits 1 factorisation, 2 additive sweeps, 4 / 8 / 16 staged orders");
     STF_REQUIRE(index >= 0, "candidate index must be >= 0");
     for (int p = 0; p < nprob; ++p) {
       STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
@@ -3166,12 +3301,13 @@ stf_status stf_tune_load(stf_ctx ctx, const char* path) {
       TuneEntry e{};
       ok = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf %lf", &k.op, &k.elem, &k.nr, &k.nlevel,
                        &k.max_m, &k.max_p, &e.kind, &e.a, &e.b, &e.c, &e.ms, &e.ms_default) == 12;
-      ok = ok && k.op >= 0 && k.op <= 3 && (k.elem == 8 || k.elem == 16) &&
+      ok = ok && k.op >= 0 && k.op <= 3 + STF_ORDER_DIAGONAL && (k.elem == 8 || k.elem == 16) &&
            (k.op == 0 ? k.nr == 0 : (k.nr >= 1 && k.nr <= MAX_RHS)) && k.nlevel >= 1 &&
            std::isfinite(e.ms) && std::isfinite(e.ms_default);
       if (k.op <= 2)   // a level: its largest front and separator, a launch shape
         ok = ok && k.max_m >= 1 && k.max_p >= 0 && k.max_p <= k.max_m && e.kind >= 1 && e.kind <= 2;
-      else             // subtree sweeps of a set (max_m: deepest level, max_p: subdomains)
+      else             // subtree sweeps of a set, additive or staged order (max_m: deepest
+                       // level, max_p: subdomains)
         ok = ok && k.max_m >= 0 && k.max_p >= 1 && e.kind == 1 && e.a >= -1 && e.a < k.max_m &&
              e.b >= 1 && e.b <= 8;
       if (ok) got[k] = e;

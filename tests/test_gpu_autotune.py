@@ -7,6 +7,11 @@ round's sweeps, through the C ABI.
   on every level (stf_tune_pick) against the oracle's round
   (oracle.ddm.SourceTransfer.apply), 1e-12 relative with complex128 fronts
   and 2e-4 with complex64 fronts, as for the built-in shapes.
+* Every subtree choice of the stages of a staged order (rows, rows + columns,
+  diagonal) gives the same sweep application: the GPU sweep after forcing
+  choice i against the oracle's (oracle.ddm.sweep_apply), 1e-12 / 2e-4 as
+  above; a batched diagonal solve after tuning its stages matches the direct
+  solve.
 * After stf_autotune a solve still meets its tolerance and matches the direct
   solve (oracle.fdfd.solve_direct): 1e-10 relative L2 at rel-res 1e-12
   (complex128), 1e-8 at rel-res 1e-10 (complex64); a batched solve after
@@ -77,6 +82,58 @@ def test_every_candidate_shape_gives_the_same_round(stf, ctx, case, prec, bar):
     finally:
         ctx.tune_clear()
         pb.close()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("order", ["rows", "rows_cols", "diagonal"])
+@pytest.mark.parametrize("prec,bar", [(0, 1e-12), (1, 2e-4)])
+def test_every_staged_subtree_choice_gives_the_same_sweep(stf, ctx, case, order, prec, bar):
+    w = CASES[case]()
+    p = w.params()
+    A = fdfd.global_matrix(p, w.eps_cells)
+    B = ddm.SourceTransfer(p, w.eps_cells)
+    v = workloads.sources.random_field(w.nx, w.ny, 23)
+    ref = ddm.sweep_apply(B, A, v.ravel(), ddm.sweep_stages(B.subs, p["px"], p["py"], order))
+    pb = stf.Problem(ctx, dict(p, front_prec=prec), w.eps_cells)
+    try:
+        pb.factor()
+        ctx.tune_clear()
+        most = ctx.tune_pick(pb, 0, nrhs=1, factor=False, sweeps=False, orders=(order,))
+        assert most >= 2
+        for idx in range(most):
+            print("case %s order %s prec %d choice %d of %d" % (case, order, prec, idx, most),
+                  flush=True)
+            ctx.tune_pick(pb, idx, nrhs=1, factor=False, sweeps=False, orders=(order,))
+            assert [e[0][0] for e in ctx.tune_entries()] == [3 + stf._abi.ORDERS[order]]
+            assert _rel(pb.sweep(v, order), ref) < bar, idx
+    finally:
+        ctx.tune_clear()
+        pb.close()
+
+
+def test_autotune_staged_then_batched_diagonal_solve(stf, ctx):
+    import torch
+    ws = [workloads.configs.disks_problem(k, sides=(64, 96, 128), pml=10, block=32, overlap=4,
+                                          local_pml=8, nrhs=2, seed0=911) for k in range(3)]
+    pbs = [stf.Problem(ctx, dict(w.params(), front_prec=1), w.eps_cells) for w in ws]
+    try:
+        ctx.tune_clear()
+        rep = ctx.autotune(pbs, nrhs=2, reps=2, factor=True, sweeps=False, orders=("diagonal",))
+        print("autotune report", rep, flush=True)
+        ent = ctx.tune_entries()
+        st = [e for e in ent if e[0][0] == 3 + stf._abi.ORDERS["diagonal"]]
+        assert len(st) == 1 and st[0][0][2] == 2 and st[0][2][0] <= st[0][2][1]
+        xs, infos = stf.batch_solve(ctx, pbs, [torch.from_numpy(w.b).cuda() for w in ws], tol=1e-10,
+                                    restart=12, max_iter=400, order="diagonal")
+        for p, w in enumerate(ws):
+            A = fdfd.global_matrix(w.params(), w.eps_cells)
+            for r in range(w.b.shape[0]):
+                assert infos[p][r]["status"] == 0 and infos[p][r]["relres_true"] <= 1e-10
+                assert _rel(xs[p][r].cpu().numpy(), fdfd.solve_direct(A, w.b[r].ravel())) < 1e-8
+    finally:
+        ctx.tune_clear()
+        for pb in pbs:
+            pb.close()
 
 
 @pytest.mark.parametrize("prec,tol,bar", [(0, 1e-12, 1e-10), (1, 1e-10, 1e-8)])
