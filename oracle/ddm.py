@@ -198,10 +198,13 @@ def stationary(A, B, b, rounds):
 # the Jacobi round above.  Orders: "rows" (subdomain rows up, then back down),
 # "rows_cols" (rows up and down, then columns right and back), "diagonal"
 # (anti-diagonals kx + ky rising and falling, then the diagonals
-# kx + (py - 1 - ky) rising and falling: four corner-to-corner directions).
+# kx + (py - 1 - ky) rising and falling: four corner-to-corner directions),
+# "checker" (two colours: the subdomains with kx + ky even, then those with
+# kx + ky odd, so that no stage holds two edge neighbours; the multiplicative
+# Schwarz form with the fewest stages).
 # ---------------------------------------------------------------------------
 
-ORDERS = ("additive", "rows", "rows_cols", "diagonal")
+ORDERS = ("additive", "rows", "rows_cols", "diagonal", "checker")
 
 
 def sweep_stages(subs, px, py, order):
@@ -219,6 +222,9 @@ def sweep_stages(subs, px, py, order):
         d1 = [[s.k for s in subs if s.kx + s.ky == d] for d in range(nd)]
         d2 = [[s.k for s in subs if s.kx + (py - 1 - s.ky) == d] for d in range(nd)]
         return d1 + d1[-2::-1] + d2 + d2[-2::-1]
+    if order == "checker":
+        colours = [[s.k for s in subs if (s.kx + s.ky) % 2 == c] for c in (0, 1)]
+        return [c for c in colours if c]
     raise ValueError("unknown order %r" % (order,))
 
 

@@ -191,6 +191,13 @@ def test_sweep_stages_cover_every_subdomain():
     assert len(ddm.sweep_stages(subs, 3, 2, "rows")) == 3
     assert len(ddm.sweep_stages(subs, 3, 2, "rows_cols")) == 3 + 5
     assert len(ddm.sweep_stages(subs, 3, 2, "diagonal")) == 4 * 4 - 2
+    # two colours, no two edge neighbours in one stage
+    assert ddm.sweep_stages(subs, 3, 2, "checker") == [[0, 2, 4], [1, 3, 5]]
+    for stg in ddm.sweep_stages(subs, 3, 2, "checker"):
+        for a in stg:
+            for b in stg:
+                sa, sb = subs[a], subs[b]
+                assert abs(sa.kx - sb.kx) + abs(sa.ky - sb.ky) != 1
     # additive = the Jacobi round
     B = ddm.SourceTransfer(w.params(), w.eps_cells)
     A = fdfd.global_matrix(w.params(), w.eps_cells)
@@ -212,9 +219,11 @@ def test_one_column_sweep_carries_a_wave_through_both_subdomains():
     assert fdfd.relres(A, B.apply(b), b) > 1e-2
     # the full symmetric order only improves on that
     assert fdfd.relres(A, ddm.sweep_apply(B, A, b, stages), b) < 1e-4
+    # the two-colour order of two subdomains is that one-way sweep
+    assert ddm.sweep_stages(B.subs, 2, 1, "checker") == [[0], [1]]
 
 
-@pytest.mark.parametrize("order", ["rows", "rows_cols", "diagonal"])
+@pytest.mark.parametrize("order", ["rows", "rows_cols", "diagonal", "checker"])
 def test_fgmres_with_sweeps_matches_direct_in_fewer_iterations(order):
     """Any staged order is a fixed linear preconditioner: FGMRES converges to the
     direct solve, in fewer iterations than with the Jacobi round here."""
