@@ -59,14 +59,15 @@ def params_of(w, prec, leaf=0):
                 local_pml_R=p["local_pml_R"], front_prec=prec, leaf_size=leaf)
 
 
-def autotune(ctx, problems, nrhs, tune):
+def autotune(ctx, problems, nrhs, tune, order="additive"):
     """The launch-shape autotuner for these problems' level signatures (a
     one-time set-up per device and shape, like the symbolic plan: outside the
-    timed steps); its report and wall time, or None when tuning is off."""
+    timed steps), with the subtree choice of a staged order's stages; its
+    report and wall time, or None when tuning is off."""
     if not tune or getattr(ctx, "_tune_loaded", False):
         return None
     t0 = time.perf_counter()
-    rep = ctx.autotune(problems, nrhs=nrhs, reps=3)
+    rep = ctx.autotune(problems, nrhs=nrhs, reps=3, orders=() if order == "additive" else (order,))
     rep["wall_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
     rep["ms_default"], rep["ms_tuned"] = round(rep["ms_default"], 4), round(rep["ms_tuned"], 4)
     return rep
@@ -78,7 +79,7 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     b = torch.from_numpy(w.b[0] if nrhs == 1 else w.b[:nrhs]).cuda()
     x = torch.empty_like(b)
     pb = stf.Problem(ctx, params_of(w, prec, leaf), eps)
-    tuned = autotune(ctx, pb, nrhs, tune)
+    tuned = autotune(ctx, pb, nrhs, tune, order)
     infos = []
 
     def step():
@@ -335,18 +336,26 @@ def mfma_summary(mfma_dir, trace_dir):
     print("\n".join(out))
 
 
-def roofline(stf, w, prec, stats, steps, levels):
+def order_stages(order, px, py):
+    """Number of stages of a preconditioner order on px x py subdomains."""
+    return {"additive": 1, "checker": 1 if px * py == 1 else 2, "rows": 2 * py - 1,
+            "rows_cols": 2 * py - 1 + 2 * px - 1,
+            "diagonal": 2 * (2 * (px + py - 1) - 1)}[order]
+
+
+def roofline(stf, w, prec, stats, steps, levels, stages=1):
     """Roofline of the kernel class with the largest summed time: its algorithmic
     work (fine nested-dissection reference counts) over its measured launch
     time, against the published peak of the bound it is priced on.  A sweep
-    class launches once per tree level (`levels`) and preconditioner
-    application; an application reads half the reference factor entries per
-    direction once, whatever the number of right-hand sides swept with it."""
+    class launches once per tree level (`levels`) and stage (`stages`) in a
+    preconditioner application; an additive or two-colour application reads
+    half the reference factor entries per direction once (each subdomain in
+    one stage), whatever the number of right-hand sides swept with it."""
     ref = stf.plan_query(params_of(w, prec, leaf=4))     # fine nested dissection reference
     es = 8 if prec == stf.STF_C64 else 16
     dom = next(iter(stats))
     ms, launches = stats[dom]
-    apps = launches / levels
+    apps = launches / (levels * stages)
     units = {
         # algorithmic work over the timed steps
         "front_lu": ("mfma", ref["lu_flops"] * steps / 1e12),                # TFLOP
@@ -397,28 +406,36 @@ def _worker_loop(conn):
             return
 
 
-def cpu_baseline_sample(w, workers, restart):
+def cpu_baseline_sample(w, workers, restart, order="additive"):
     """The oracle (NumPy/SciPy) on `workers` host processes, started before the
     GPU is touched: SuperLU factorisations of all 64 subdomains spread over the
     workers (each keeps its group's factors), then three FGMRES iterations of
-    the oracle's own algorithm (oracle.krylov.fgmres) whose source-transfer
-    round sends each subdomain's restricted source to the worker holding its
-    factors.  Returns the measured times; cpu_baseline() extrapolates them."""
+    the oracle's own algorithm (oracle.krylov.fgmres) whose preconditioner (the
+    stages of `order`, oracle.ddm.sweep_stages / sweep_apply) sends each
+    subdomain's restricted source to the worker holding its factors.  Returns
+    the measured times; cpu_baseline() extrapolates them."""
     from oracle import ddm, fdfd
     p = w.params()
     t0 = time.perf_counter()
     A = fdfd.global_matrix(p, w.eps_cells)
     subs = ddm.partition(p)
     t_asm = time.perf_counter() - t0
-    return _cpu_rounds(w, p, A, subs, workers, restart, t_asm)
+    stages = ddm.sweep_stages(subs, p["px"], p["py"], order)
+    return _cpu_rounds(w, p, A, subs, workers, restart, t_asm, stages)
 
 
-def _cpu_rounds(w, p, A, subs, workers, restart, t_asm):
+def _cpu_rounds(w, p, A, subs, workers, restart, t_asm, stages):
     import multiprocessing as mp
     import numpy as np
     from oracle import krylov
     ctx = mp.get_context("fork")
-    groups = [list(range(i, len(subs), workers)) for i in range(workers)]
+    # every stage's subdomains dealt round-robin over the workers
+    groups = [[] for _ in range(workers)]
+    seen = set()
+    for stage in stages:
+        for i, k in enumerate(x for x in stage if x not in seen):
+            groups[i % workers].append(k)
+            seen.add(k)
     procs, conns = [], []
     for _ in groups:                 # every fork before any thread or GPU use
         a, b = ctx.Pipe()
@@ -442,15 +459,19 @@ def _cpu_rounds(w, p, A, subs, workers, restart, t_asm):
             return r.ravel()
 
         def round_(v):
-            V = np.asarray(v).reshape(ny, nx)
-            for c, g in zip(conns, groups):
-                c.send(("solve", [(k, restrict(V, subs[k])) for k in g]))
+            v = np.asarray(v)
             z = np.zeros((ny, nx), dtype=np.complex128)
-            for c in conns:
-                for k, u in c.recv():
-                    s = subs[k]
-                    z[s.oy[0]:s.oy[1], s.ox[0]:s.ox[1]] += u.reshape(s.oy[1] - s.oy[0],
-                                                                     s.ox[1] - s.ox[0])
+            for t, stage in enumerate(stages):
+                # z += sum over the stage of P_k A_k^{-1} R_k^I (v - A z)
+                V = (v if t == 0 else v - A @ z.ravel()).reshape(ny, nx)
+                mem = set(stage)
+                for c, g in zip(conns, groups):
+                    c.send(("solve", [(k, restrict(V, subs[k])) for k in g if k in mem]))
+                for c in conns:
+                    for k, u in c.recv():
+                        s = subs[k]
+                        z[s.oy[0]:s.oy[1], s.ox[0]:s.ox[1]] += u.reshape(s.oy[1] - s.oy[0],
+                                                                         s.ox[1] - s.ox[0])
             return z.ravel()
 
         k = 3
@@ -468,7 +489,7 @@ def _cpu_rounds(w, p, A, subs, workers, restart, t_asm):
             pr.join(timeout=10)
             if pr.is_alive():
                 pr.terminate()
-    return dict(t_asm=t_asm, t_fac=t_fac, t_it=t_it, workers=workers)
+    return dict(t_asm=t_asm, t_fac=t_fac, t_it=t_it, workers=workers, stages=len(stages))
 
 
 def cpu_model():
@@ -486,10 +507,11 @@ def cpu_baseline(w, sample, gpu_iters):
     return {"value": round(w.nx * w.ny / total, 1), "unit": "DoF/s", "cores": sample["workers"],
             "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "sample": "oracle on a pool of %d host processes: SuperLU factors of all 64 "
-                      "subdomains (%.1f s), 3 FGMRES iterations with the pooled round "
-                      "(%.2f s each), extrapolated to the GPU run's %d iterations "
-                      "(%.1f s est., one right-hand side)" % (sample["workers"], sample["t_fac"],
-                                                             sample["t_it"], gpu_iters, total)}
+                      "subdomains (%.1f s), 3 FGMRES iterations with the pooled "
+                      "preconditioner (%d stage(s), %.2f s each), extrapolated to the GPU "
+                      "run's %d iterations (%.1f s est., one right-hand side)"
+                      % (sample["workers"], sample["t_fac"], sample.get("stages", 1),
+                         sample["t_it"], gpu_iters, total)}
 
 
 STUDY_PARTS = [(2, 1), (2, 2), (4, 2), (4, 4), (8, 4), (8, 8)]     # N = 2 ... 64 as in Table 1
@@ -633,6 +655,11 @@ def main():
     # a long basis to resolve), while the Gram-Schmidt work grows with the
     # basis; 3 measured fastest for both forms.
     ap.add_argument("--restart", type=int, default=3)
+    # Order of the source transfer in the preconditioner of the headline, plain
+    # and mixed forms.  The two-colour order (kx + ky even, then odd) reads every
+    # factor once per application, like the Jacobi round, and on this workload
+    # needs 31 FGMRES iterations against 51.
+    ap.add_argument("--order", default="checker", choices=["additive", "checker"])
     ap.add_argument("--max-iter", type=int, default=400)
     ap.add_argument("--no-timing", action="store_true", help="skip per-kernel HIP event timing")
     ap.add_argument("--no-tune", action="store_true",
@@ -676,7 +703,7 @@ def main():
     sample = None
     if not args.no_cpu_baseline:
         # Before anything touches the GPU: the pool forks from this process.
-        sample = cpu_baseline_sample(w, min(16, os.cpu_count() or 1), args.restart)
+        sample = cpu_baseline_sample(w, min(16, os.cpu_count() or 1), args.restart, args.order)
     import torch
     import paper_2509_20801_amd as stf
     from paper_2509_20801_amd import learned
@@ -695,7 +722,7 @@ def main():
     t_h, inf_h, stats, info, profile = run_form(stf, torch, ctx, w4, stf.STF_C64, args.steps,
                                                 args.warmup, args.tol, args.restart, args.max_iter,
                                                 not args.no_timing, nrhs=4, x0="learned",
-                                                tune=not args.no_tune)
+                                                order=args.order, tune=not args.no_tune)
     last = inf_h[-1]
     ok = all(i["status"] == 0 and i["relres_true"] <= args.tol for i in last)
     out = {"metric": METRIC, "value": round(4 * N / t_h, 1), "unit": "DoF*RHS/s", "n_gpus": 1,
@@ -707,7 +734,8 @@ def main():
                       "ndof": N, "nrhs": 4,
                       "form": "mixed+batched+learned: complex64 fronts, 4 right-hand sides per "
                               "sweep, network guess with zero-guess fallback, FP64 FGMRES",
-                      "restart": args.restart, "tol": args.tol, "parallelism": "1 GPU"},
+                      "order": args.order, "restart": args.restart, "tol": args.tol,
+                      "parallelism": "1 GPU"},
            "iters": [i["iters"] for i in last], "relres_true": max(i["relres_true"] for i in last),
            "learned_guess_kept": [i["used_learned"] for i in last],
            "relres_guess": [round(i["relres_x0"], 4) for i in last],
@@ -715,28 +743,45 @@ def main():
            "converged": ok, "power": {k: round(v, 6) for k, v in info["power"].items()},
            "autotune": info["autotune"]}
     if stats:
-        dom, rl = roofline(stf, w, stf.STF_C64, stats, args.steps, info["max_depth"] + 1)
+        dom, rl = roofline(stf, w, stf.STF_C64, stats, args.steps, info["max_depth"] + 1,
+                           order_stages(args.order, w.px, w.py))
         out["roofline"] = rl
         out["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in profile.items()}
     if not args.no_plain:
         t_p, inf_p, _, _, _ = run_form(stf, torch, ctx, w, stf.STF_C128, args.steps, args.warmup,
                                        args.tol, args.restart, args.max_iter, False,
-                                       tune=not args.no_tune)
+                                       order=args.order, tune=not args.no_tune)
         out["plain_fp64"] = {"value": round(N / t_p, 1), "unit": "DoF/s",
                              "ms_per_step": round(t_p * 1e3, 3), "iters": inf_p[-1]["iters"],
-                             "form": "complex128 fronts, one right-hand side, zero guess"}
+                             "form": "complex128 fronts, one right-hand side, zero guess, "
+                                     "same order"}
         out["speedup_vs_plain"] = round((4 * N / t_h) / (N / t_p), 3)
     if not args.no_side:
         t_m, inf_m, _, _, _ = run_form(stf, torch, ctx, w, stf.STF_C64, args.steps, args.warmup,
                                        args.tol, args.restart, args.max_iter, False,
-                                       tune=not args.no_tune)
+                                       order=args.order, tune=not args.no_tune)
         out["mixed_1rhs"] = {"value": round(N / t_m, 1), "unit": "DoF/s",
                              "ms_per_step": round(t_m * 1e3, 3), "iters": inf_m[-1]["iters"]}
         t_b, inf_b, _, _, _ = run_form(stf, torch, ctx, w4, stf.STF_C64, args.steps, args.warmup,
-                                       args.tol, args.restart, args.max_iter, False, nrhs=4)
+                                       args.tol, args.restart, args.max_iter, False, nrhs=4,
+                                       order=args.order)
         out["mixed_batched_4rhs"] = {"value": round(4 * N / t_b, 1), "unit": "DoF*RHS/s",
                                      "ms_per_step": round(t_b * 1e3, 3),
                                      "iters": [i["iters"] for i in inf_b[-1]]}
+        # The headline form and the plain form in the other order.
+        other = "additive" if args.order != "additive" else "checker"
+        t_o, inf_o, _, _, _ = run_form(stf, torch, ctx, w4, stf.STF_C64, args.steps, args.warmup,
+                                       args.tol, args.restart, args.max_iter, False, nrhs=4,
+                                       x0="learned", order=other, tune=not args.no_tune)
+        t_op, inf_op, _, _, _ = run_form(stf, torch, ctx, w, stf.STF_C128, args.steps,
+                                         args.warmup, args.tol, args.restart, args.max_iter, False,
+                                         order=other, tune=not args.no_tune)
+        out["order_" + other] = {"value": round(4 * N / t_o, 1), "unit": "DoF*RHS/s",
+                                 "ms_per_step": round(t_o * 1e3, 3),
+                                 "iters": [i["iters"] for i in inf_o[-1]],
+                                 "plain_fp64": {"value": round(N / t_op, 1), "unit": "DoF/s",
+                                                "ms_per_step": round(t_op * 1e3, 3),
+                                                "iters": inf_op[-1]["iters"]}}
         out["stationary"] = stationary_form(stf, torch, ctx, w, stf.STF_C64, args.tol, 200)
         out["subdomain_study"] = subdomain_study(stf, torch, ctx)
     if not args.no_batched:

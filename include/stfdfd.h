@@ -71,11 +71,16 @@ enum { STF_X0_ZERO = 0, STF_X0_USER = 1, STF_X0_LEARNED = 2 };
  *   STF_ORDER_ROWS_COLS  rows up and down, then columns kx = 0 .. px-1 and back;
  *   STF_ORDER_DIAGONAL   the anti-diagonals kx + ky rising and falling, then the
  *                        diagonals kx + (py-1-ky) rising and falling (four
- *                        corner-to-corner directions).
- * A staged application reads the factors once per stage a subdomain belongs
- * to (2-4 times) but carries waves across many subdomains, so FGMRES needs far
- * fewer iterations where waves cross many subdomains. */
-enum { STF_ORDER_ADDITIVE = 0, STF_ORDER_ROWS = 1, STF_ORDER_ROWS_COLS = 2, STF_ORDER_DIAGONAL = 3 };
+ *                        corner-to-corner directions);
+ *   STF_ORDER_CHECKER    two colours: the subdomains with kx + ky even, then
+ *                        those with kx + ky odd (no stage holds two edge
+ *                        neighbours).
+ * The sweeping orders read the factors once per stage a subdomain belongs to
+ * (2-4 times) but carry waves across many subdomains, so FGMRES needs far
+ * fewer iterations where waves cross many subdomains.  The two-colour order
+ * reads every factor once, like the Jacobi round, in two half-size stages. */
+enum { STF_ORDER_ADDITIVE = 0, STF_ORDER_ROWS = 1, STF_ORDER_ROWS_COLS = 2, STF_ORDER_DIAGONAL = 3,
+       STF_ORDER_CHECKER = 4 };
 
 /* Problem description (Sec. 2.1-2.3).  Global PML sides are ordered x-, x+, y-, y+.
  * The interior [pml[0], nx-pml[1]) x [pml[2], ny-pml[3]) is split into px x py
@@ -329,9 +334,10 @@ void        stf_problem_destroy(stf_problem pb);          /* NULL-safe */
  * problem (its own fronts), or nprob > 1 problems as the set that
  * stf_batch_solve builds for the same problems in the same order.  what: a
  * sum of 1 (the factorisation), 2 (the additive round's sweeps with nrhs
- * (1..4) right-hand sides), 4, 8, 16 (the subtree choice of the staged
- * orders rows, rows + columns, diagonal: whole applications timed level by
- * level and with subtree sweeps in every stage, operation 3 + order below).  The fastest shape per level signature is kept in the context
+ * (1..4) right-hand sides), 4, 8, 16, 32 (the subtree choice of the staged
+ * orders rows, rows + columns, diagonal, two colours: whole applications timed
+ * level by level and with subtree sweeps in every stage, operation 3 + order
+ * below).  The fastest shape per level signature is kept in the context
  * and used by every later factorisation and round on it whose levels have
  * that signature (solo, batched, staged or allocation-free); other levels keep
  * the built-in rule.  Needs assembled problems of this context with one front
@@ -361,7 +367,7 @@ stf_status  stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, i
  * problems (as stf_autotune selects them) to the level's candidate shape
  * `index` (>= 0; the last candidate where a level has fewer; 0 is the
  * built-in shape), and with the sweeps (what & 2, and the staged orders'
- * bits 4, 8, 16) the subtree choice of the set to its option `index` (0 level
+ * bits 4, 8, 16, 32) the subtree choice of the set to its option `index` (0 level
  * by level, the built-in choice, then each root depth and subtrees per
  * workgroup that fit).  *max_candidates (may be NULL) receives the largest
  * candidate count over the levels, so that index = 0 .. max - 1 visits every
@@ -391,8 +397,8 @@ stf_status  stf_tune_clear(stf_ctx ctx);
  * ms = {chosen, built-in}.  Operation 3 (the subtree choice of a set): key =
  * {3, bytes, nrhs, fronts of the set, deepest level, subdomains}, shape =
  * {1, root depth or -1 (level by level), subtrees per workgroup (1, 2, 4, 8),
- * 0}; operations 4, 5, 6: the same for the stages of the orders rows, rows +
- * columns, diagonal.  Any output pointer may be NULL. */
+ * 0}; operations 4, 5, 6, 7: the same for the stages of the orders rows,
+ * rows + columns, diagonal, two colours.  Any output pointer may be NULL. */
 int32_t     stf_tune_count(stf_ctx ctx);
 stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms);
 

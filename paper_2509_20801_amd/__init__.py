@@ -136,7 +136,7 @@ def _what(factor, sweeps, orders):
     what = (1 if factor else 0) | (2 if sweeps else 0)
     for o in orders:
         if o not in _abi.ORDERS or o == "additive":
-            raise ValueError("staged orders: rows, rows_cols, diagonal")
+            raise ValueError("staged orders: rows, rows_cols, diagonal, checker")
         what |= 2 << _abi.ORDERS[o]
     return what
 
@@ -331,7 +331,7 @@ class Problem:
 
     def sweep(self, v, order, z=None):
         """One preconditioner application in a staged order ("rows", "rows_cols",
-        "diagonal"; "additive" is the round of precond())."""
+        "diagonal", "checker"; "additive" is the round of precond())."""
         n = self.ndof
         pv, dev, kv = _ptr(v, n, "v")
         z = self._out_like(v, tuple(v.shape)) if z is None else z

@@ -12,7 +12,7 @@ STATUS_NAMES = {0: "STF_OK", 1: "STF_EINVAL", 2: "STF_ENOMEM", 3: "STF_EDEVICE",
                 5: "STF_EPIVOT", 6: "STF_ENOCONV", 7: "STF_ENAN"}
 STF_C128, STF_C64 = 0, 1
 STF_X0_ZERO, STF_X0_USER, STF_X0_LEARNED = 0, 1, 2
-ORDERS = {"additive": 0, "rows": 1, "rows_cols": 2, "diagonal": 3}
+ORDERS = {"additive": 0, "rows": 1, "rows_cols": 2, "diagonal": 3, "checker": 4}
 KERNEL_CLASSES = ["assemble", "stencil", "front_asm", "front_lu", "sweep_fwd", "sweep_bwd",
                   "scatter", "arnoldi", "update", "nn"]
 

@@ -892,9 +892,10 @@ void precond_mf(stf_ctx c, Mf& mf, const RhsSet& r, const int* pact = nullptr) {
 }
 
 // Stages of problem p (subdomain k = ky * px + kx of that problem) for a
-// sweeping order: 1 symmetric rows, 2 symmetric rows then symmetric columns,
+// staged order: 1 symmetric rows, 2 symmetric rows then symmetric columns,
 // 3 four diagonal sweeps (kx + ky rising and falling, then kx + (py-1-ky)
-// rising and falling).
+// rising and falling), 4 two colours (kx + ky even, then odd; a single
+// subdomain has one stage).
 std::vector<std::vector<int>> order_stages(int order, int px, int py) {
   std::vector<std::vector<int>> rows(py), cols(px), out;
   for (int ky = 0; ky < py; ++ky)
@@ -921,6 +922,14 @@ std::vector<std::vector<int>> order_stages(int order, int px, int py) {
       }
     there_and_back(d1);
     there_and_back(d2);
+  } else if (order == STF_ORDER_CHECKER) {
+    for (int c = 0; c < 2; ++c) {
+      std::vector<int> st;
+      for (int ky = 0; ky < py; ++ky)
+        for (int kx = 0; kx < px; ++kx)
+          if ((kx + ky) % 2 == c) st.push_back(ky * px + kx);
+      if (!st.empty()) out.push_back(st);
+    }
   } else {
     throw Error(STF_EINVAL, "unknown sweeping order");
   }
@@ -1018,6 +1027,16 @@ int staged_fuse_for(stf_ctx c, Mf& mf, const SweepPlan& sp, size_t elem, int nr,
   return code;
 }
 
+// Level d of stage t as launch arguments: the stage's fronts of that level
+// (through the stage front list), the level's largest orders.
+LevelArgs stage_level_args(const Mf& mf, const SweepPlan& sp, int t, int d, const int* pact) {
+  LevelArgs la = mf.level_args(d, nullptr, pact);
+  la.flist = sp.flist.as<int>();
+  la.first = sp.lv[t][d].off;
+  la.nlevel = sp.lv[t][d].n;
+  return la;
+}
+
 // One application of the staged order for the right-hand sides of r:
 // z_s = 0, then for every stage r_s = v_s - A z_s on its own boxes (skipped for
 // the first stage, where z = 0), its sweeps, z_s += its full local fields.
@@ -1058,19 +1077,13 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
     for (int d = top - 1; d >= 0; --d) {
       if (sp.lv[t][d].n == 0) continue;
       Timed tm(tc, K_SWEEP_FWD);
-      LevelArgs la = mf.level_args(d, nullptr, pact);
-      la.flist = sp.flist.as<int>();
-      la.first = sp.lv[t][d].off;
-      la.nlevel = sp.lv[t][d].n;
+      const LevelArgs la = stage_level_args(mf, sp, t, d, pact);
       launch_sweep_fwd<T>(st, la, lpk, mf.piv.as<int>(), vec, rr, tuned_sweep(c, la, true, sizeof(T), rr.nr));
     }
     for (int d = 0; d < top; ++d) {
       if (sp.lv[t][d].n == 0) continue;
       Timed tm(tc, K_SWEEP_BWD);
-      LevelArgs la = mf.level_args(d, nullptr, pact);
-      la.flist = sp.flist.as<int>();
-      la.first = sp.lv[t][d].off;
-      la.nlevel = sp.lv[t][d].n;
+      const LevelArgs la = stage_level_args(mf, sp, t, d, pact);
       launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), vec, u, rr, tuned_sweep(c, la, false, sizeof(T), rr.nr));
     }
     if (fz) {
@@ -1261,12 +1274,28 @@ void tune_sweeps_mf(stf_ctx c, Mf& mf, int nr, long long ntot, int reps, TuneTal
   tally.ms_round_tuned = tf[bk];
 }
 
-// Staged orders: whole applications of `order` (with the per-level shapes
-// chosen so far) for each subtree choice, level by level first; keeps the
-// fastest for the set's signature (operation 3 + order).
+// Stage levels of a staged order grouped by launch signature (direction w:
+// 0 forward, 1 backward), each with the (stage, depth) pairs that have it.
+std::map<TuneKey, std::vector<std::pair<int, int>>> stage_level_groups(const Mf& mf, const SweepPlan& sp,
+                                                                        size_t elem, int nr, int w) {
+  std::map<TuneKey, std::vector<std::pair<int, int>>> g;
+  for (int t = 0; t < sp.nstage; ++t)
+    for (int d = 0; d <= mf.max_depth; ++d) {
+      if (sp.lv[t][d].n == 0) continue;
+      const LevelArgs la = stage_level_args(mf, sp, t, d, nullptr);
+      g[TuneKey{w == 0 ? 1 : 2, (int)elem, nr, la.nlevel, la.max_m, la.max_p}].push_back({t, d});
+    }
+  return g;
+}
+
+// Staged orders: first the launch shape of every stage-level signature (every
+// candidate timed over all the stage levels that have the signature, on zero
+// right-hand sides), then whole applications of `order` for each subtree
+// choice, level by level first; keeps the fastest for the set's signature
+// (operation 3 + order).
 template <typename T>
 void tune_staged_mf(stf_ctx c, Mf& mf, int nr, long long ntot, const double2* keps, const double2* gc,
-                    int order, int reps) {
+                    int order, int reps, TuneTally& tally) {
   hipStream_t st = c->stream;
   if (mf.ws_nr < nr) {
     mf.vec.alloc((size_t)mf.vec_elems * sizeof(T) * nr);
@@ -1285,6 +1314,34 @@ void tune_staged_mf(stf_ctx c, Mf& mf, int nr, long long ntot, const double2* ke
     r.z[s] = z.as<double2>() + (size_t)s * ntot;
   }
   const SweepPlan& sp = sweep_plan(mf, order, st);
+  {
+    RhsSet rz = r;
+    rz.vec_stride = mf.vec_elems;
+    rz.u_stride = mf.u_elems;
+    EventSet ev(2);
+    for (int w = 0; w < 2; ++w)
+      for (const auto& kv : stage_level_groups(mf, sp, sizeof(T), nr, w)) {
+        const auto& members = kv.second;
+        const LevelArgs a0 = stage_level_args(mf, sp, members[0].first, members[0].second, nullptr);
+        const std::vector<SweepShape> cand = sweep_candidates(a0, w == 0, sizeof(T), nr);
+        std::vector<double> times(cand.size(), 1e300);
+        for (int rep = 0; rep < reps; ++rep)
+          for (size_t k = 0; k < cand.size(); ++k) {
+            HIP_CHECK(hipEventRecord(ev.e[0], st));
+            for (const auto& td : members) {
+              const LevelArgs la = stage_level_args(mf, sp, td.first, td.second, nullptr);
+              if (w == 0)
+                launch_sweep_fwd<T>(st, la, mf.lpk.as<T>(), mf.piv.as<int>(), mf.vec.as<T>(), rz, cand[k]);
+              else
+                launch_sweep_bwd<T>(st, la, mf.upk.as<T>(), mf.vec.as<T>(), mf.u.as<T>(), rz, cand[k]);
+            }
+            HIP_CHECK(hipEventRecord(ev.e[1], st));
+            HIP_CHECK(hipEventSynchronize(ev.e[1]));
+            times[k] = std::min(times[k], ev.ms(0, 1));
+          }
+        tune_keep(c, kv.first, cand, times, tally, enc_sweep);
+      }
+  }
   const TuneKey key = staged_fuse_key(mf, sizeof(T), nr, order);
   c->tune.erase(key);
   const std::vector<int> opts = fuse_options(c, mf, sizeof(T), nr);
@@ -1334,7 +1391,18 @@ int tune_pick_mf(stf_ctx c, Mf& mf, const double2* keps, int nr, int what, int i
         c->tune[TuneKey{w == 0 ? 1 : 2, (int)sizeof(T), nr, a.nlevel, a.max_m, a.max_p}] = e;
       }
   }
-  for (int order = 0; order <= STF_ORDER_DIAGONAL; ++order) {
+  for (int order = 1; order <= STF_ORDER_CHECKER; ++order) {
+    if (!(what & (2 << order))) continue;
+    const SweepPlan& sp = sweep_plan(mf, order, c->stream);
+    for (int w = 0; w < 2; ++w)
+      for (const auto& kv : stage_level_groups(mf, sp, sizeof(T), nr, w)) {
+        const LevelArgs a0 = stage_level_args(mf, sp, kv.second[0].first, kv.second[0].second, nullptr);
+        const auto cand = sweep_candidates(a0, w == 0, sizeof(T), nr);
+        most = std::max(most, (int)cand.size());
+        c->tune[kv.first] = enc_sweep(cand[std::min<size_t>(index, cand.size() - 1)]);
+      }
+  }
+  for (int order = 0; order <= STF_ORDER_CHECKER; ++order) {
     const int bit = order == 0 ? 2 : (2 << order);
     if (!(what & bit)) continue;
     const TuneKey fk = order == 0 ? fuse_key(mf, sizeof(T), nr) : staged_fuse_key(mf, sizeof(T), nr, order);
@@ -3038,7 +3106,7 @@ stf_status stf_sweep_apply(stf_problem pb, int32_t order, const double* v, doubl
   if (!pb) return STF_EINVAL;
   return guard(pb->ctx, [&] {
     STF_REQUIRE(v && z, "null argument");
-    STF_REQUIRE(order >= STF_ORDER_ADDITIVE && order <= STF_ORDER_DIAGONAL,
+    STF_REQUIRE(order >= STF_ORDER_ADDITIVE && order <= STF_ORDER_CHECKER,
                 "unknown source-transfer order");
     if (!pb->factored) throw Error(STF_ESTATE, "precond before factor");
     hipStream_t st = pb->ctx->stream;
@@ -3080,7 +3148,7 @@ stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, i
                 "x0_mode invalid");
     STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
     STF_REQUIRE(opts->debug_fault == 0 || opts->debug_fault == 1, "debug_fault must be 0 or 1");
-    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_DIAGONAL,
+    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_CHECKER,
                 "unknown source-transfer order");
     STF_REQUIRE(opts->rounds <= 1 || opts->order == STF_ORDER_ADDITIVE,
                 "several rounds per application need the additive order");
@@ -3152,7 +3220,7 @@ stf_status stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,
                 "x0_mode invalid");
     STF_REQUIRE(opts->rounds <= 1, "a batched solve takes one source-transfer round per application");
     STF_REQUIRE(opts->debug_fault == 0, "debug_fault is not available in a batched solve");
-    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_DIAGONAL,
+    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_CHECKER,
                 "unknown source-transfer order");
     for (int p = 0; p < nprob; ++p) {
       STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
@@ -3186,7 +3254,7 @@ stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, in
   return guard(ctx, [&] {
     STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
     STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
-    STF_REQUIRE(what >= 1 && what <= 31, "what: bits 1 factorisation, 2 additive sweeps, 4 / 8 / 16 staged orders");
+    STF_REQUIRE(what >= 1 && what <= 63, "what: bits 1 factorisation, 2 additive sweeps, 4 / 8 / 16 / 32 staged orders");
     STF_REQUIRE(reps >= 1 && reps <= 100, "reps must be 1..100");
     for (int p = 0; p < nprob; ++p) {
       STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
@@ -3201,14 +3269,14 @@ stf_status stf_autotune(stf_ctx ctx, int32_t nprob, const stf_problem* probs, in
         if (what & 1) tune_factor_mf<float2>(ctx, mf, keps, flag, reps, tally);
         factor_mf<float2>(ctx, mf, keps, flag, false, nullptr, nullptr);
         if (what & 2) tune_sweeps_mf<float2>(ctx, mf, nrhs, ntot, reps, tally);
-        for (int order = 1; order <= STF_ORDER_DIAGONAL; ++order)
-          if (what & (2 << order)) tune_staged_mf<float2>(ctx, mf, nrhs, ntot, keps, gc, order, reps);
+        for (int order = 1; order <= STF_ORDER_CHECKER; ++order)
+          if (what & (2 << order)) tune_staged_mf<float2>(ctx, mf, nrhs, ntot, keps, gc, order, reps, tally);
       } else {
         if (what & 1) tune_factor_mf<double2>(ctx, mf, keps, flag, reps, tally);
         factor_mf<double2>(ctx, mf, keps, flag, false, nullptr, nullptr);
         if (what & 2) tune_sweeps_mf<double2>(ctx, mf, nrhs, ntot, reps, tally);
-        for (int order = 1; order <= STF_ORDER_DIAGONAL; ++order)
-          if (what & (2 << order)) tune_staged_mf<double2>(ctx, mf, nrhs, ntot, keps, gc, order, reps);
+        for (int order = 1; order <= STF_ORDER_CHECKER; ++order)
+          if (what & (2 << order)) tune_staged_mf<double2>(ctx, mf, nrhs, ntot, keps, gc, order, reps, tally);
       }
     };
     if (nprob == 1) {
@@ -3237,7 +3305,7 @@ stf_status stf_tune_pick(stf_ctx ctx, int32_t nprob, const stf_problem* probs, i
   return guard(ctx, [&] {
     STF_REQUIRE(nprob >= 1 && probs, "need at least one problem");
     STF_REQUIRE(nrhs >= 1 && nrhs <= MAX_RHS, "1 to 4 right-hand sides per sweep");
-    STF_REQUIRE(what >= 1 && what <= 31, "what: bits 1 factorisation, 2 additive sweeps, 4 / 8 / 16 staged orders");
+    STF_REQUIRE(what >= 1 && what <= 63, "what: bits 1 factorisation, 2 additive sweeps, 4 / 8 / 16 / 32 staged orders");
     STF_REQUIRE(index >= 0, "candidate index must be >= 0");
     for (int p = 0; p < nprob; ++p) {
       STF_REQUIRE(probs[p] && probs[p]->ctx == ctx, "problem missing or on another context");
@@ -3301,7 +3369,7 @@ stf_status stf_tune_load(stf_ctx ctx, const char* path) {
       TuneEntry e{};
       ok = std::fscanf(f, "%d %d %d %d %d %d %d %d %d %d %lf %lf", &k.op, &k.elem, &k.nr, &k.nlevel,
                        &k.max_m, &k.max_p, &e.kind, &e.a, &e.b, &e.c, &e.ms, &e.ms_default) == 12;
-      ok = ok && k.op >= 0 && k.op <= 3 + STF_ORDER_DIAGONAL && (k.elem == 8 || k.elem == 16) &&
+      ok = ok && k.op >= 0 && k.op <= 3 + STF_ORDER_CHECKER && (k.elem == 8 || k.elem == 16) &&
            (k.op == 0 ? k.nr == 0 : (k.nr >= 1 && k.nr <= MAX_RHS)) && k.nlevel >= 1 &&
            std::isfinite(e.ms) && std::isfinite(e.ms_default);
       if (k.op <= 2)   // a level: its largest front and separator, a launch shape

@@ -7,10 +7,10 @@ round's sweeps, through the C ABI.
   on every level (stf_tune_pick) against the oracle's round
   (oracle.ddm.SourceTransfer.apply), 1e-12 relative with complex128 fronts
   and 2e-4 with complex64 fronts, as for the built-in shapes.
-* Every subtree choice of the stages of a staged order (rows, rows + columns,
-  diagonal) gives the same sweep application: the GPU sweep after forcing
-  choice i against the oracle's (oracle.ddm.sweep_apply), 1e-12 / 2e-4 as
-  above; a batched diagonal solve after tuning its stages matches the direct
+* Every subtree choice and every launch shape of the stage levels of a staged
+  order (rows, rows + columns, diagonal, two colours) gives the same sweep
+  application: the GPU sweep after forcing choice i against the oracle's
+  (oracle.ddm.sweep_apply), 1e-12 / 2e-4 as above; a batched diagonal solve after tuning its stages matches the direct
   solve.
 * After stf_autotune a solve still meets its tolerance and matches the direct
   solve (oracle.fdfd.solve_direct): 1e-10 relative L2 at rel-res 1e-12
@@ -85,7 +85,7 @@ def test_every_candidate_shape_gives_the_same_round(stf, ctx, case, prec, bar):
 
 
 @pytest.mark.parametrize("case", list(CASES))
-@pytest.mark.parametrize("order", ["rows", "rows_cols", "diagonal"])
+@pytest.mark.parametrize("order", ["rows", "rows_cols", "diagonal", "checker"])
 @pytest.mark.parametrize("prec,bar", [(0, 1e-12), (1, 2e-4)])
 def test_every_staged_subtree_choice_gives_the_same_sweep(stf, ctx, case, order, prec, bar):
     w = CASES[case]()
@@ -104,7 +104,10 @@ def test_every_staged_subtree_choice_gives_the_same_sweep(stf, ctx, case, order,
             print("case %s order %s prec %d choice %d of %d" % (case, order, prec, idx, most),
                   flush=True)
             ctx.tune_pick(pb, idx, nrhs=1, factor=False, sweeps=False, orders=(order,))
-            assert [e[0][0] for e in ctx.tune_entries()] == [3 + stf._abi.ORDERS[order]]
+            ops = [e[0][0] for e in ctx.tune_entries()]
+            # the stage levels' shapes (operations 1, 2) and the stages' subtree choice
+            assert [o for o in ops if o >= 3] == [3 + stf._abi.ORDERS[order]]
+            assert set(ops) - {3 + stf._abi.ORDERS[order]} <= {1, 2}
             assert _rel(pb.sweep(v, order), ref) < bar, idx
     finally:
         ctx.tune_clear()

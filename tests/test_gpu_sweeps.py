@@ -11,7 +11,7 @@ from oracle import ddm, fdfd
 
 pytestmark = pytest.mark.gpu
 
-ORDERS = ["rows", "rows_cols", "diagonal"]
+ORDERS = ["rows", "rows_cols", "diagonal", "checker"]
 
 
 @pytest.fixture(scope="module")
