@@ -83,10 +83,11 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     infos = []
 
     def step():
+        # assembly, factorisation (with the network's guesses beside it on a
+        # second stream when x0 is learned) and the FGMRES solve
         pb.assemble(eps)
-        pb.factor()
-        _, inf = pb.solve(b, x=x, tol=tol, restart=restart, max_iter=max_iter, rounds=rounds,
-                          x0=x0, order=order)
+        _, inf = pb.factor_solve(b, x=x, tol=tol, restart=restart, max_iter=max_iter,
+                                 rounds=rounds, x0=x0, order=order)
         infos.append(inf[0] if nrhs == 1 else inf)
 
     for _ in range(warmup):
@@ -557,9 +558,9 @@ def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order
     """The large single problem: the 4128 x 4128 waveguide layout (17.0M DoF,
     16 x 16 subdomains, complex64 fronts, fundamental-mode source) to FP64 true
     rel-res 1e-10; one warm-up and one timed step (assembly, factorisation,
-    solve), in the four-diagonal order and in the additive one.  The autotuner
-    (outside the timed steps) covers the factorisation levels, the additive
-    round's sweeps and the subtree choice of the diagonal stages."""
+    solve), in the four-diagonal, two-colour and additive orders.  The
+    autotuner (outside the timed steps) covers the factorisation levels, the
+    additive round's sweeps and the stage levels of the staged orders."""
     import workloads
     w = workloads.configs.waveguides()
     eps = torch.from_numpy(w.eps_cells).cuda()
@@ -570,15 +571,14 @@ def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order
                        "16x16 subdomains", "ndof": w.ndof, "tol": tol}
     if tune and not getattr(ctx, "_tune_loaded", False):
         t0 = time.perf_counter()
-        orders = () if order == "additive" else (order,)
-        rep = ctx.autotune(pb, nrhs=1, reps=2, orders=orders)
+        rep = ctx.autotune(pb, nrhs=1, reps=2, orders=(order, "checker"))
         rep["wall_ms"] = round((time.perf_counter() - t0) * 1e3, 1)
         nf = pb.info()["nfronts"]
         # (root depth or -1, subtrees per workgroup, ms chosen, ms level by level)
         rep["staged"] = [(e[1][1], e[1][2], round(e[2][0], 3), round(e[2][1], 3))
                          for e in ctx.tune_entries() if e[0][0] >= 4 and e[0][3] == nf]
         out["autotune"] = rep
-    for od in (order, "additive"):
+    for od in (order, "checker", "additive"):
         def step():
             pb.assemble(eps)
             pb.factor()

@@ -218,6 +218,16 @@ stf_status  stf_factor(stf_problem pb);
  * info: array of nrhs (may be NULL).  Returns the worst per-RHS status. */
 stf_status  stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                       const stf_solve_opts* opts, stf_solve_info* info);
+/* stf_factor then stf_solve in one call (Eq. (22), then the solve phase), with
+ * the same arguments as stf_solve.  With STF_X0_LEARNED and device arrays the
+ * network's guesses (which need only the permittivity and b) are computed on a
+ * second stream of the context while the factorisation runs, and the solve
+ * waits for them: the network fills the GPU that the few large fronts of the
+ * top tree levels leave idle.  The results equal those of the two separate
+ * calls.  Returns STF_EPIVOT if a pivot was perturbed and the solve itself
+ * succeeded, else the solve's status. */
+stf_status  stf_factor_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
+                             const stf_solve_opts* opts, stf_solve_info* info);
 /* Stop rules of the stationary iteration: the FP64 true relative residual
  * |b - A x| / |b| <= tol, or Eq. (20): the summed 2-norms of the subdomains'
  * local fields on their overlapping regions (Omega_k outside I_k, the fields

@@ -404,6 +404,18 @@ class Problem:
         x0: None (zero guess), an array (user guess) or "learned" (the context's network).
         debug_fault=1 re-factors with one planted zero pivot column first (test hook of the
         tiny-pivot path); the call then reports STF_EPIVOT as info["epivot"]."""
+        return self._solve(self._lib.stf_solve, b, x, tol, restart, max_iter, x0, history_cap,
+                           raise_on_noconv, rounds, debug_fault, order)
+
+    def factor_solve(self, b, x=None, tol=1e-10, restart=30, max_iter=500, x0=None,
+                     history_cap=4096, raise_on_noconv=False, rounds=1, order="additive"):
+        """factor() then solve() in one call (stf_factor_solve); with x0="learned" and
+        device arrays the network's guesses run during the factorisation."""
+        return self._solve(self._lib.stf_factor_solve, b, x, tol, restart, max_iter, x0,
+                           history_cap, raise_on_noconv, rounds, 0, order)
+
+    def _solve(self, fn, b, x, tol, restart, max_iter, x0, history_cap, raise_on_noconv, rounds,
+               debug_fault, order):
         shape = tuple(b.shape)
         nrhs = 1 if len(shape) == 2 else int(shape[0])
         n = self.ndof
@@ -435,8 +447,8 @@ class Problem:
             infos[i].history = hist[i].ctypes.data_as(C.POINTER(C.c_double))
             infos[i].history_cap = history_cap
         allow = (_abi.STF_EPIVOT,) if raise_on_noconv else (_abi.STF_ENOCONV, _abi.STF_EPIVOT)
-        st = _check(self.ctx.handle, self._lib.stf_solve(self.handle, nrhs, pb_, pxx, dev,
-                                                         C.byref(opts), infos), allow=allow)
+        st = _check(self.ctx.handle, fn(self.handle, nrhs, pb_, pxx, dev, C.byref(opts), infos),
+                    allow=allow)
         out = []
         for i in range(nrhs):
             inf = infos[i]

@@ -76,6 +76,8 @@ EXPORTS = {
     "stf_factor": (C.c_int, [C.c_void_p]),
     "stf_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int,
                             C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
+    "stf_factor_solve": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_int,
+                                   C.POINTER(SolveOpts), C.POINTER(SolveInfo)]),
     "stf_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_precond_apply": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
     "stf_precond_apply_noalloc": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <functional>
 #include <mutex>
 #include <numeric>
 
@@ -121,6 +122,12 @@ struct stf_ctx_s {
   BatchState* batch = nullptr;  // state of the last stf_batch_solve (owned)
   std::map<TuneKey, TuneEntry> tune;   // autotuned launch shapes (this device)
   std::string arch;             // the device's architecture name (tune files)
+  // Second stream (default priority) for work that overlaps the main stream's
+  // (the network's guesses during a factorisation), and the two events that
+  // order it against the main stream.
+  hipStream_t side = nullptr;
+  hipEvent_t side_ev[2] = {nullptr, nullptr};
+  int cus = 0;                  // compute units of the device (0 until queried)
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -748,7 +755,7 @@ SweepShape tuned_sweep(stf_ctx c, const LevelArgs& a, bool fwd, size_t elem, int
 // launches.  Returns the perturbation flag (synchronises the stream).
 template <typename T>
 int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hipEvent_t e0,
-              hipEvent_t e1) {
+              hipEvent_t e1, const std::function<void(int)>* before_level = nullptr) {
   STF_REQUIRE(!fault || mf.max_depth >= 1, "the planted fault needs a tree of two levels or more");
   hipStream_t st = c->stream;
   T* fac = mf.fac.as<T>();
@@ -756,6 +763,7 @@ int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hip
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
   if (e0) HIP_CHECK(hipEventRecord(e0, st));
   for (int d = mf.max_depth; d >= 0; --d) {
+    if (before_level) (*before_level)(d);
     Timed t(c, K_FRONT_LU);
     LevelArgs la = mf.level_args(d, keps);
     if (fault && d == 1) la.fault = la.first;
@@ -772,13 +780,14 @@ int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hip
 
 void fuse_prepare(stf_ctx c, Mf& mf);
 
-int factor_problem(stf_problem pb, bool fault = false) {
+int factor_problem(stf_problem pb, bool fault = false,
+                   const std::function<void(int)>* before_level = nullptr) {
   Mf& mf = pb->ensure_mf();
   const double2* keps = pb->keps.as<double2>();
   int* flag = pb->flag.as<int>();
   const int h = mf.prec == STF_C64
-                    ? factor_mf<float2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1])
-                    : factor_mf<double2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1]);
+                    ? factor_mf<float2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1], before_level)
+                    : factor_mf<double2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1], before_level);
   pb->fac_timed = true;
   fuse_prepare(pb->ctx, mf);
   return h;
@@ -1824,7 +1833,7 @@ struct RhsRun {
 // side keeps its own Krylov basis and stops on its own residual; the
 // arithmetic of each equals that of a solo solve.
 stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2* const* x,
-                        const stf_solve_opts& o, stf_solve_info* info) {
+                        const stf_solve_opts& o, stf_solve_info* info, bool guess_ready = false) {
   stf_ctx c = pb->ctx;
   hipStream_t st = c->stream;
   const long long N = pb->N;
@@ -1860,7 +1869,7 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
   for (int s = 0; s < nr; ++s) {
     RhsRun& q = R[s];
     if (o.x0_mode == STF_X0_ZERO) HIP_CHECK(hipMemsetAsync(q.x, 0, N * sizeof(double2), st));
-    if (o.x0_mode == STF_X0_LEARNED) {
+    if (o.x0_mode == STF_X0_LEARNED && !guess_ready) {
       STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
       HIP_CHECK(hipEventRecord(pb->ev[4 + 2 * s], st));
       nn_initial_guess(pb, c->nn, q.b, q.x);
@@ -2606,6 +2615,173 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
 // Exported entry points
 // ---------------------------------------------------------------------------
 
+namespace {
+
+// Runs f with the context's (and the network's context's) launches on the
+// side stream, which first waits for everything already on the main stream;
+// the main stream then waits for the side stream's work at the point of the
+// join() call.
+struct SideStream {
+  stf_ctx c, nc;
+  hipStream_t main;
+  SideStream(stf_ctx c_, stf_ctx nc_) : c(c_), nc(nc_), main(c_->stream) {
+    if (!c->side) HIP_CHECK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    for (int e = 0; e < 2; ++e)
+      if (!c->side_ev[e]) HIP_CHECK(hipEventCreateWithFlags(&c->side_ev[e], hipEventDisableTiming));
+  }
+  // The side stream's next work waits for what the main stream holds so far.
+  void fork() {
+    HIP_CHECK(hipEventRecord(c->side_ev[0], main));
+    HIP_CHECK(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
+  }
+  template <typename F>
+  void run(F&& f) {
+    c->stream = c->side;
+    if (nc) nc->stream = c->side;
+    try {
+      f();
+    } catch (...) {
+      c->stream = main;
+      if (nc) nc->stream = main;
+      throw;
+    }
+    c->stream = main;
+    if (nc) nc->stream = main;
+  }
+  void join() {
+    HIP_CHECK(hipEventRecord(c->side_ev[1], c->side));
+    HIP_CHECK(hipStreamWaitEvent(main, c->side_ev[1], 0));
+  }
+};
+
+}  // namespace
+
+static stf_status solve_impl(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
+                      const stf_solve_opts* opts, stf_solve_info* info, bool refactor) {
+  if (!pb) return STF_EINVAL;
+  stf_status worst = STF_OK;
+  bool perturbed = false;
+  stf_status s = guard(pb->ctx, [&] {
+    STF_REQUIRE(b && x && opts, "null argument");
+    STF_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
+    STF_REQUIRE(opts->restart >= 1 && opts->restart <= 200, "restart out of range");
+    STF_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
+    STF_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be finite and >= 0");
+    STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER ||
+                    opts->x0_mode == STF_X0_LEARNED,
+                "x0_mode invalid");
+    STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
+    STF_REQUIRE(opts->debug_fault == 0 || opts->debug_fault == 1, "debug_fault must be 0 or 1");
+    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_CHECKER,
+                "unknown source-transfer order");
+    STF_REQUIRE(opts->rounds <= 1 || opts->order == STF_ORDER_ADDITIVE,
+                "several rounds per application need the additive order");
+    if (refactor) {
+      if (!pb->assembled) throw Error(STF_ESTATE, "factor before assemble");
+      const size_t per = (size_t)pb->N * 2;
+      require_finite(pb, b, per * nrhs, on_device, "b");
+      stf_ctx c = pb->ctx;
+      // The network's guesses on the side stream during the factorisation
+      // (device arrays, at most MAX_RHS right-hand sides in one group).
+      const bool overlap = opts->x0_mode == STF_X0_LEARNED && on_device && nrhs <= MAX_RHS &&
+                           opts->rounds <= 1 && opts->debug_fault == 0;
+      if (overlap) {
+        STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+        SideStream side(c, c->nn->ctx != c ? c->nn->ctx : nullptr);
+        // The guesses start with the first level of at most four fronts per
+        // compute unit: the deep levels fill the GPU by themselves, the top
+        // ones leave most of it idle.
+        Mf& mf = pb->ensure_mf();
+        if (c->cus == 0) HIP_CHECK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount,
+                                                         c->device));
+        int start = 0;
+        for (int d = mf.max_depth; d >= 0; --d)
+          if (mf.levels[d].n <= 4 * c->cus) {
+            start = d;
+            break;
+          }
+        const std::function<void(int)> hook = [&](int d) {
+          if (d != start) return;
+          side.fork();
+          side.run([&] {
+            for (int i = 0; i < nrhs; ++i) {
+              HIP_CHECK(hipEventRecord(pb->ev[4 + 2 * i], c->stream));
+              nn_initial_guess(pb, c->nn, reinterpret_cast<const double2*>(b) + (size_t)i * pb->N,
+                               reinterpret_cast<double2*>(x) + (size_t)i * pb->N);
+              HIP_CHECK(hipEventRecord(pb->ev[5 + 2 * i], c->stream));
+            }
+          });
+        };
+        pb->factored = false;
+        perturbed = factor_problem(pb, false, &hook) != 0;
+        pb->factored = true;
+        side.join();
+        const double2* bd[MAX_RHS];
+        double2* xd[MAX_RHS];
+        for (int i = 0; i < nrhs; ++i) {
+          bd[i] = reinterpret_cast<const double2*>(b) + (size_t)i * pb->N;
+          xd[i] = reinterpret_cast<double2*>(x) + (size_t)i * pb->N;
+        }
+        worst = fgmres_multi(pb, nrhs, bd, xd, *opts, info, true);
+        HIP_CHECK(hipGetLastError());
+        return;
+      }
+      pb->factored = false;
+      perturbed = factor_problem(pb) != 0;
+      pb->factored = true;
+    }
+    if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
+    if (opts->debug_fault == 1) {
+      perturbed = factor_problem(pb, true) != 0;
+      STF_REQUIRE(perturbed, "internal: the planted fault did not reach the pivot perturbation");
+    }
+    const size_t per = (size_t)pb->N * 2;
+    require_finite(pb, b, per * nrhs, on_device, "b");
+    if (opts->x0_mode == STF_X0_USER) require_finite(pb, x, per * nrhs, on_device, "x0");
+    hipStream_t st = pb->ctx->stream;
+    const size_t vb = (size_t)pb->N * sizeof(double2);
+    // Right-hand sides go through in groups of up to MAX_RHS (one with
+    // several source-transfer rounds per application: those are not batched).
+    const int gmax = (opts->rounds > 1) ? 1 : MAX_RHS;
+    for (int r0 = 0; r0 < nrhs; r0 += gmax) {
+      const int g = std::min(gmax, nrhs - r0);
+      const double2* bd[MAX_RHS];
+      double2* xd[MAX_RHS];
+      if (!on_device) {
+        pb->hb.alloc(vb * g);
+        pb->hx.alloc(vb * g);
+        HIP_CHECK(hipMemcpyAsync(pb->hb.p, b + r0 * per, vb * g, hipMemcpyHostToDevice, st));
+        if (opts->x0_mode == STF_X0_USER)
+          HIP_CHECK(hipMemcpyAsync(pb->hx.p, x + r0 * per, vb * g, hipMemcpyHostToDevice, st));
+      }
+      for (int i = 0; i < g; ++i) {
+        if (on_device) {
+          bd[i] = reinterpret_cast<const double2*>(b) + (size_t)(r0 + i) * pb->N;
+          xd[i] = reinterpret_cast<double2*>(x) + (size_t)(r0 + i) * pb->N;
+        } else {
+          bd[i] = pb->hb.as<double2>() + (size_t)i * pb->N;
+          xd[i] = pb->hx.as<double2>() + (size_t)i * pb->N;
+        }
+      }
+      stf_status r = fgmres_multi(pb, g, bd, xd, *opts, info ? info + r0 : nullptr);
+      if (!on_device) {
+        HIP_CHECK(hipMemcpyAsync(x + r0 * per, pb->hx.p, vb * g, hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+      }
+      if (r != STF_OK && worst == STF_OK) worst = r;
+    }
+    HIP_CHECK(hipGetLastError());
+  });
+  if (s != STF_OK) return s;
+  if (worst == STF_ENOCONV) pb->ctx->last_error = "FGMRES reached max_iter above tol";
+  if (worst == STF_OK && perturbed) {
+    pb->ctx->last_error = opts->debug_fault == 1 ? "tiny pivot perturbed during factorisation (planted fault)"
+                                                 : "tiny pivot perturbed during factorisation";
+    return STF_EPIVOT;
+  }
+  return worst;
+}
+
 extern "C" {
 
 stf_status stf_ctx_create(int device, void* hip_stream, stf_ctx* out) {
@@ -2666,6 +2842,12 @@ void stf_ctx_destroy(stf_ctx c) {
   for (int e = 0; e < 2; ++e)
     if (c->iter_ev[e]) (void)hipEventDestroy(c->iter_ev[e]);
   if (c->cycle_ev) (void)hipEventDestroy(c->cycle_ev);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
+  for (int e = 0; e < 2; ++e)
+    if (c->side_ev[e]) (void)hipEventDestroy(c->side_ev[e]);
   if (c->pinned) (void)hipHostFree(c->pinned);
   destroy_batch(c->batch);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -3134,73 +3316,12 @@ stf_status stf_sweep_apply(stf_problem pb, int32_t order, const double* v, doubl
 
 stf_status stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                      const stf_solve_opts* opts, stf_solve_info* info) {
-  if (!pb) return STF_EINVAL;
-  stf_status worst = STF_OK;
-  bool perturbed = false;
-  stf_status s = guard(pb->ctx, [&] {
-    STF_REQUIRE(b && x && opts, "null argument");
-    STF_REQUIRE(nrhs >= 1, "nrhs must be >= 1");
-    STF_REQUIRE(opts->restart >= 1 && opts->restart <= 200, "restart out of range");
-    STF_REQUIRE(opts->max_iter >= 1, "max_iter must be >= 1");
-    STF_REQUIRE(std::isfinite(opts->tol) && opts->tol >= 0, "tol must be finite and >= 0");
-    STF_REQUIRE(opts->x0_mode == STF_X0_ZERO || opts->x0_mode == STF_X0_USER ||
-                    opts->x0_mode == STF_X0_LEARNED,
-                "x0_mode invalid");
-    STF_REQUIRE(opts->rounds >= 0 && opts->rounds <= 8, "rounds out of range");
-    STF_REQUIRE(opts->debug_fault == 0 || opts->debug_fault == 1, "debug_fault must be 0 or 1");
-    STF_REQUIRE(opts->order >= STF_ORDER_ADDITIVE && opts->order <= STF_ORDER_CHECKER,
-                "unknown source-transfer order");
-    STF_REQUIRE(opts->rounds <= 1 || opts->order == STF_ORDER_ADDITIVE,
-                "several rounds per application need the additive order");
-    if (!pb->factored) throw Error(STF_ESTATE, "solve before factor");
-    if (opts->debug_fault == 1) {
-      perturbed = factor_problem(pb, true) != 0;
-      STF_REQUIRE(perturbed, "internal: the planted fault did not reach the pivot perturbation");
-    }
-    const size_t per = (size_t)pb->N * 2;
-    require_finite(pb, b, per * nrhs, on_device, "b");
-    if (opts->x0_mode == STF_X0_USER) require_finite(pb, x, per * nrhs, on_device, "x0");
-    hipStream_t st = pb->ctx->stream;
-    const size_t vb = (size_t)pb->N * sizeof(double2);
-    // Right-hand sides go through in groups of up to MAX_RHS (one with
-    // several source-transfer rounds per application: those are not batched).
-    const int gmax = (opts->rounds > 1) ? 1 : MAX_RHS;
-    for (int r0 = 0; r0 < nrhs; r0 += gmax) {
-      const int g = std::min(gmax, nrhs - r0);
-      const double2* bd[MAX_RHS];
-      double2* xd[MAX_RHS];
-      if (!on_device) {
-        pb->hb.alloc(vb * g);
-        pb->hx.alloc(vb * g);
-        HIP_CHECK(hipMemcpyAsync(pb->hb.p, b + r0 * per, vb * g, hipMemcpyHostToDevice, st));
-        if (opts->x0_mode == STF_X0_USER)
-          HIP_CHECK(hipMemcpyAsync(pb->hx.p, x + r0 * per, vb * g, hipMemcpyHostToDevice, st));
-      }
-      for (int i = 0; i < g; ++i) {
-        if (on_device) {
-          bd[i] = reinterpret_cast<const double2*>(b) + (size_t)(r0 + i) * pb->N;
-          xd[i] = reinterpret_cast<double2*>(x) + (size_t)(r0 + i) * pb->N;
-        } else {
-          bd[i] = pb->hb.as<double2>() + (size_t)i * pb->N;
-          xd[i] = pb->hx.as<double2>() + (size_t)i * pb->N;
-        }
-      }
-      stf_status r = fgmres_multi(pb, g, bd, xd, *opts, info ? info + r0 : nullptr);
-      if (!on_device) {
-        HIP_CHECK(hipMemcpyAsync(x + r0 * per, pb->hx.p, vb * g, hipMemcpyDeviceToHost, st));
-        HIP_CHECK(hipStreamSynchronize(st));
-      }
-      if (r != STF_OK && worst == STF_OK) worst = r;
-    }
-    HIP_CHECK(hipGetLastError());
-  });
-  if (s != STF_OK) return s;
-  if (worst == STF_ENOCONV) pb->ctx->last_error = "FGMRES reached max_iter above tol";
-  if (worst == STF_OK && perturbed) {
-    pb->ctx->last_error = "tiny pivot perturbed during factorisation (planted fault)";
-    return STF_EPIVOT;
-  }
-  return worst;
+  return solve_impl(pb, nrhs, b, x, on_device, opts, info, false);
+}
+
+stf_status stf_factor_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
+                            const stf_solve_opts* opts, stf_solve_info* info) {
+  return solve_impl(pb, nrhs, b, x, on_device, opts, info, true);
 }
 
 stf_status stf_batch_solve(stf_ctx ctx, int32_t nprob, const stf_problem* probs,

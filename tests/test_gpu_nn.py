@@ -187,6 +187,46 @@ def test_learned_solve_converges_and_falls_back(stf, ctx):
     net.close()
 
 
+def test_factor_solve_runs_the_guess_beside_the_factorisation(stf, ctx):
+    """stf_factor_solve (the network on a second stream during the
+    factorisation, device arrays) gives the same fields, bit for bit, and the
+    same iterations and guess residuals as stf_factor followed by stf_solve, for
+    two right-hand sides; with host arrays (no overlap) as well."""
+    import torch
+    flat = _flat(CFG, 12, noise=0.0)
+    net = _net(stf, ctx, CFG, flat)
+    ctx.set_nn(net)
+    w = _small_problem(seed=1)
+    b2 = np.stack([w.b[0], 0.5j * w.b[0] + 0.1])
+    pb = stf.Problem(ctx, _prm(w), w.eps_cells)
+    try:
+        for dev in (True, False):
+            b = torch.from_numpy(b2).cuda() if dev else b2
+            pb.assemble(w.eps_cells)
+            pb.factor()
+            x1, inf1 = pb.solve(b, tol=1e-10, x0="learned")
+            pb.assemble(w.eps_cells)
+            x2, inf2 = pb.factor_solve(b, tol=1e-10, x0="learned")
+            if dev:
+                x1, x2 = x1.cpu().numpy(), x2.cpu().numpy()
+            assert np.array_equal(x1, x2)
+            for a, c in zip(inf1, inf2):
+                assert a["status"] == 0 and c["status"] == 0
+                assert (a["iters"], a["used_learned"], a["relres_x0"]) == \
+                    (c["iters"], c["used_learned"], c["relres_x0"])
+                assert c["t_factor_ms"] > 0.0 and c["t_nn_ms"] > 0.0
+        # solve before factor is still refused; factor_solve factors itself
+        pb.assemble(w.eps_cells)
+        with pytest.raises(stf.StfError):
+            pb.solve(b2, tol=1e-10)
+        x3, inf3 = pb.factor_solve(b2, tol=1e-10)
+        assert inf3[0]["status"] == 0 and inf3[0]["relres_true"] <= 1e-10
+    finally:
+        ctx.set_nn(None)
+        pb.close()
+        net.close()
+
+
 @pytest.mark.parametrize("interior,parts,seed", [(1024, 8, 5001), (2048, 16, 5002)],
                          ids=["1024", "2048"])
 def test_trained_network_gain_on_the_deploy_grids(stf, ctx, interior, parts, seed):
