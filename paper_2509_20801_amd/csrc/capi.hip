@@ -778,6 +778,44 @@ int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hip
   return h;
 }
 
+// The context's second stream: fork() makes its next work wait for what the
+// main stream holds so far, run(f) issues f's launches (those of the context
+// and of the network's context) on it, join() makes the main stream wait for
+// everything issued on it.
+struct SideStream {
+  stf_ctx c, nc;
+  hipStream_t main;
+  SideStream(stf_ctx c_, stf_ctx nc_) : c(c_), nc(nc_), main(c_->stream) {
+    if (!c->side) HIP_CHECK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    for (int e = 0; e < 2; ++e)
+      if (!c->side_ev[e]) HIP_CHECK(hipEventCreateWithFlags(&c->side_ev[e], hipEventDisableTiming));
+  }
+  // The side stream's next work waits for what the main stream holds so far.
+  void fork() {
+    HIP_CHECK(hipEventRecord(c->side_ev[0], main));
+    HIP_CHECK(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
+  }
+  template <typename F>
+  void run(F&& f) {
+    c->stream = c->side;
+    if (nc) nc->stream = c->side;
+    try {
+      f();
+    } catch (...) {
+      c->stream = main;
+      if (nc) nc->stream = main;
+      throw;
+    }
+    c->stream = main;
+    if (nc) nc->stream = main;
+  }
+  void join() {
+    HIP_CHECK(hipEventRecord(c->side_ev[1], c->side));
+    HIP_CHECK(hipStreamWaitEvent(main, c->side_ev[1], 0));
+  }
+};
+
+
 void fuse_prepare(stf_ctx c, Mf& mf);
 
 int factor_problem(stf_problem pb, bool fault = false,
@@ -2444,13 +2482,6 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
                          const stf_solve_opts& o, stf_solve_info* const* info, bool& perturbed) {
   hipStream_t st = c->stream;
   BatchState& bs = batch_state(c, nprob, probs);
-  // Factorisation of every problem, one launch per tree level over all fronts.
-  perturbed = factor_mf<T>(c, bs.mf, bs.keps.as<double2>(), bs.flag.as<int>(), false, bs.ev[0],
-                           bs.ev[1]) != 0;
-  const double t_fac = [&] {
-    float ms = 0.f;
-    return hipEventElapsedTime(&ms, bs.ev[0], bs.ev[1]) == hipSuccess ? (double)ms : 0.0;
-  }();
   int maxr = 0;
   for (int p = 0; p < nprob; ++p) maxr = std::max(maxr, (int)nrhs[p]);
   const int m = o.restart;
@@ -2459,10 +2490,9 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
     if (info && info[p])
       for (int r = 0; r < nrhs[p]; ++r) hcap = std::max(hcap, info[p][r].history_cap);
   hcap = std::min(hcap, o.max_iter + 1);
-  stf_status worst = STF_OK;
-  const bool graph = batch_use_graph();
-  for (int slot0 = 0; slot0 < maxr; slot0 += MAX_RHS) {
-    const int nslot = std::min(MAX_RHS, maxr - slot0);
+  // A slot group's systems, workspaces, right-hand sides and initial guesses
+  // (zero or the user's) in the batch vectors.
+  auto prepare = [&](int slot0, int nslot) {
     batch_systems(bs, nrhs, slot0, nslot, m, hcap, st);
     if (bs.mf.ws_nr < nslot) {
       const size_t es = sizeof(T);
@@ -2470,10 +2500,7 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
       bs.mf.u.alloc((size_t)bs.mf.u_elems * es * nslot);
       bs.mf.ws_nr = nslot;
     }
-    const int nsys = bs.nsys;
     const size_t vb = (size_t)bs.T * sizeof(double2);
-    HIP_CHECK(hipEventRecord(bs.ev[2], st));
-    // Right-hand sides and initial guesses into the batch vectors.
     HIP_CHECK(hipMemsetAsync(bs.B.p, 0, vb, st));
     HIP_CHECK(hipMemsetAsync(bs.X.p, 0, vb, st));
     const hipMemcpyKind hk = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
@@ -2489,22 +2516,59 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
           HIP_CHECK(hipMemcpyAsync(bs.X.as<double2>() + off, x_out[p] + 2 * n * r,
                                    n * sizeof(double2), hk, st));
       }
-    std::vector<double> t_nn(nsys, 0.0);
-    if (o.x0_mode == STF_X0_LEARNED) {
-      STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
-      for (int s = 0; s < nsys; ++s) {
-        if (!bs.hsys[s].present) continue;
-        const int p = s % nprob;
-        hipEvent_t e0 = probs[p]->ev[4], e1 = probs[p]->ev[5];
-        HIP_CHECK(hipEventRecord(e0, st));
-        nn_initial_guess(probs[p], c->nn, bs.B.as<double2>() + bs.hsys[s].off,
-                         bs.X.as<double2>() + bs.hsys[s].off);
-        HIP_CHECK(hipEventRecord(e1, st));
-        HIP_CHECK(hipEventSynchronize(e1));
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess) t_nn[s] = ms;
-      }
+  };
+  // The network's guesses of a slot group (system s of problem s % nprob in
+  // slot s / nprob), bracketed by that problem's events of the slot.
+  auto guesses = [&] {
+    for (int s = 0; s < bs.nsys; ++s) {
+      if (!bs.hsys[s].present) continue;
+      const int p = s % nprob, k = s / nprob;
+      HIP_CHECK(hipEventRecord(probs[p]->ev[4 + 2 * k], c->stream));
+      nn_initial_guess(probs[p], c->nn, bs.B.as<double2>() + bs.hsys[s].off,
+                       bs.X.as<double2>() + bs.hsys[s].off);
+      HIP_CHECK(hipEventRecord(probs[p]->ev[5 + 2 * k], c->stream));
     }
+  };
+  if (o.x0_mode == STF_X0_LEARNED) STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+  // With one slot group, its guesses run on the side stream during the
+  // factorisation, from the first level of at most four fronts per compute
+  // unit on (the deep levels fill the GPU by themselves).
+  const bool overlap = o.x0_mode == STF_X0_LEARNED && maxr <= MAX_RHS;
+  std::unique_ptr<SideStream> side;
+  std::function<void(int)> hook;
+  if (overlap) {
+    prepare(0, maxr);
+    side.reset(new SideStream(c, c->nn->ctx != c ? c->nn->ctx : nullptr));
+    if (c->cus == 0) HIP_CHECK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
+    int start = 0;
+    for (int d = bs.mf.max_depth; d >= 0; --d)
+      if (bs.mf.levels[d].n <= 4 * c->cus) {
+        start = d;
+        break;
+      }
+    hook = [&, start](int d) {
+      if (d != start) return;
+      side->fork();
+      side->run(guesses);
+    };
+  }
+  // Factorisation of every problem, one launch per tree level over all fronts.
+  perturbed = factor_mf<T>(c, bs.mf, bs.keps.as<double2>(), bs.flag.as<int>(), false, bs.ev[0],
+                           bs.ev[1], overlap ? &hook : nullptr) != 0;
+  if (overlap) side->join();
+  const double t_fac = [&] {
+    float ms = 0.f;
+    return hipEventElapsedTime(&ms, bs.ev[0], bs.ev[1]) == hipSuccess ? (double)ms : 0.0;
+  }();
+  stf_status worst = STF_OK;
+  const bool graph = batch_use_graph();
+  for (int slot0 = 0; slot0 < maxr; slot0 += MAX_RHS) {
+    const int nslot = std::min(MAX_RHS, maxr - slot0);
+    if (!overlap) prepare(slot0, nslot);
+    const int nsys = bs.nsys;
+    HIP_CHECK(hipEventRecord(bs.ev[2], st));
+    if (o.x0_mode == STF_X0_LEARNED && !overlap) guesses();
+    // (the guesses' times are read once the stream has been synchronised below)
     // |b|^2, initial residuals, cleared flags and counters.
     HIP_CHECK(hipMemsetAsync(bs.sc.p, 0, bs.sc.bytes, st));
     HIP_CHECK(hipMemsetAsync(bs.it.p, 0, bs.it.bytes, st));
@@ -2515,6 +2579,15 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
     std::vector<double> sch(16 * (size_t)nsys);
     HIP_CHECK(hipMemcpyAsync(sch.data(), bs.sc.p, sizeof(double) * 16 * nsys, hipMemcpyDeviceToHost, st));
     HIP_CHECK(hipStreamSynchronize(st));
+    std::vector<double> t_nn(nsys, 0.0);
+    if (o.x0_mode == STF_X0_LEARNED)
+      for (int s = 0; s < nsys; ++s) {
+        if (!bs.hsys[s].present) continue;
+        const int p = s % nprob, k = s / nprob;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, probs[p]->ev[4 + 2 * k], probs[p]->ev[5 + 2 * k]) == hipSuccess)
+          t_nn[s] = ms;
+      }
     std::vector<double> bnorm(nsys), rx0(nsys);
     std::vector<int> used(nsys, 0);
     bool refresh = false;
@@ -2615,46 +2688,6 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
 // Exported entry points
 // ---------------------------------------------------------------------------
 
-namespace {
-
-// Runs f with the context's (and the network's context's) launches on the
-// side stream, which first waits for everything already on the main stream;
-// the main stream then waits for the side stream's work at the point of the
-// join() call.
-struct SideStream {
-  stf_ctx c, nc;
-  hipStream_t main;
-  SideStream(stf_ctx c_, stf_ctx nc_) : c(c_), nc(nc_), main(c_->stream) {
-    if (!c->side) HIP_CHECK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    for (int e = 0; e < 2; ++e)
-      if (!c->side_ev[e]) HIP_CHECK(hipEventCreateWithFlags(&c->side_ev[e], hipEventDisableTiming));
-  }
-  // The side stream's next work waits for what the main stream holds so far.
-  void fork() {
-    HIP_CHECK(hipEventRecord(c->side_ev[0], main));
-    HIP_CHECK(hipStreamWaitEvent(c->side, c->side_ev[0], 0));
-  }
-  template <typename F>
-  void run(F&& f) {
-    c->stream = c->side;
-    if (nc) nc->stream = c->side;
-    try {
-      f();
-    } catch (...) {
-      c->stream = main;
-      if (nc) nc->stream = main;
-      throw;
-    }
-    c->stream = main;
-    if (nc) nc->stream = main;
-  }
-  void join() {
-    HIP_CHECK(hipEventRecord(c->side_ev[1], c->side));
-    HIP_CHECK(hipStreamWaitEvent(main, c->side_ev[1], 0));
-  }
-};
-
-}  // namespace
 
 static stf_status solve_impl(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,
                       const stf_solve_opts* opts, stf_solve_info* info, bool refactor) {

@@ -227,6 +227,42 @@ def test_factor_solve_runs_the_guess_beside_the_factorisation(stf, ctx):
         net.close()
 
 
+@pytest.mark.parametrize("nr", [2, 5])
+def test_batched_learned_guess_matches_the_solo_guess(stf, ctx, nr):
+    """stf_batch_solve with the learned guess: the guesses (computed on the
+    side stream during the factorisation when every problem has at most four
+    right-hand sides, after it otherwise) have the residuals of the solo
+    solve's guesses, the fallback takes the same decisions, and the fields
+    converge to the solo fields (1e-8 relative at rel-res 1e-10)."""
+    import torch
+    flat = _flat(CFG, 12, noise=0.0)
+    net = _net(stf, ctx, CFG, flat)
+    ctx.set_nn(net)
+    ws = [_small_problem(seed=1), _small_problem(nx=72, seed=2)]
+    bs = [np.stack([(1.0 + 0.3j * r) * w.b[0] + 0.05 * r for r in range(nr if k == 0 else 2)])
+          for k, w in enumerate(ws)]
+    pbs = [stf.Problem(ctx, _prm(w), w.eps_cells) for w in ws]
+    try:
+        xs, infos = stf.batch_solve(ctx, pbs, [torch.from_numpy(b).cuda() for b in bs], tol=1e-10,
+                                    restart=12, max_iter=400, x0="learned")
+        for p, (pb, b) in enumerate(zip(pbs, bs)):
+            pb.factor()
+            xsolo, isolo = pb.solve(b, tol=1e-10, restart=12, max_iter=400, x0="learned")
+            for r in range(b.shape[0]):
+                got, ref = infos[p][r], isolo[r]
+                assert got["status"] == 0 and got["relres_true"] <= 1e-10
+                assert got["used_learned"] == ref["used_learned"]
+                assert abs(got["relres_x0"] - ref["relres_x0"]) <= 1e-12 * max(1.0, ref["relres_x0"])
+                assert got["t_nn_ms"] > 0.0
+                x = xs[p][r].cpu().numpy()
+                assert np.linalg.norm(x - xsolo[r]) <= 1e-8 * np.linalg.norm(xsolo[r])
+    finally:
+        ctx.set_nn(None)
+        for pb in pbs:
+            pb.close()
+        net.close()
+
+
 @pytest.mark.parametrize("interior,parts,seed", [(1024, 8, 5001), (2048, 16, 5002)],
                          ids=["1024", "2048"])
 def test_trained_network_gain_on_the_deploy_grids(stf, ctx, interior, parts, seed):
