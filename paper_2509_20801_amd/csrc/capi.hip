@@ -580,6 +580,8 @@ struct stf_problem_s {
   DBuf ksr;                        // stage residuals of a staged order (one vector per slot)
   DBuf hb, hx, cells;              // staging for host inputs
   int krylov_m = 0, krylov_nr = 0;
+  long long kpart_stride = 0;   // double2 entries of one right-hand side's Gram-Schmidt partials
+  long long knpart_stride = 0;  // doubles of one right-hand side's norm partials
   // Phase timers: [0, 1] the last factorisation, [2, 3] a solve group, [4 + 2 s, 5 + 2 s]
   // the network's guess of right-hand side s of the group.
   hipEvent_t ev[4 + 2 * MAX_RHS] = {};
@@ -703,7 +705,7 @@ void build_device_state(stf_problem pb) {
   for (auto& v : pl.g.cy.e) gc.push_back(make_double2(v.real(), v.imag()));
   upload(pb->gcoef, gc, st);
   pb->keps.alloc((size_t)pb->N * sizeof(double2));
-  pb->flag.alloc(sizeof(int) * 4);
+  pb->flag.alloc(sizeof(int) * (4 + MAX_RHS));   // [0] pivot / finite flag, [4 + s] Gram-Schmidt gates
   pb->scal.alloc(sizeof(double) * 64);
   int nblk = std::max(stencil_partial_blocks(p.nx, p.ny), krylov_blocks(pb->N));
   pb->partial.alloc((size_t)nblk * sizeof(double2) * 4);
@@ -1100,7 +1102,7 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
   stf_ctx tc = timed ? c : nullptr;
   r.vec_stride = mf.vec_elems;
   r.u_stride = mf.u_elems;
-  for (int s = 0; s < r.nr; ++s) launch_zero(st, r.z[s], zlen);
+  launch_zero_set(st, r, zlen);
   const T* lpk = mf.lpk.as<T>();
   const int* sl = sp.slist.as<int>();
   const std::vector<std::unique_ptr<FusePlan>>* sfz = code >= 0 ? &stage_fuse(mf, sp, code, st) : nullptr;
@@ -1569,21 +1571,26 @@ void ensure_krylov(stf_problem pb, int m, int nr) {
   size_t vb = (size_t)pb->N * sizeof(double2);
   pb->kV.alloc(vb * (m + 1) * nr);
   pb->kZ.alloc(vb * m * nr);
-  pb->kw.alloc(vb);
+  pb->kw.alloc(vb * nr);
   pb->kr.alloc(vb * nr);
   pb->kH.alloc(sizeof(double2) * (m + 1) * m * nr);
   pb->kcs.alloc(sizeof(double) * m * nr);
   pb->ksn.alloc(sizeof(double2) * m * nr);
   pb->kg.alloc(sizeof(double2) * (m + 1) * nr);
   pb->ky.alloc(sizeof(double2) * (m + 1) * nr);
-  pb->kh1.alloc(sizeof(double2) * (m + 1));
-  pb->kh2.alloc(sizeof(double2) * (m + 1));
+  pb->kh1.alloc(sizeof(double2) * (m + 1) * nr);
+  pb->kh2.alloc(sizeof(double2) * (m + 1) * nr);
   pb->scal.alloc(sizeof(double) * 16 * (nr + 1));
+  // Gram-Schmidt partials and norm partials, one region per right-hand side.
   int nblk = krylov_blocks(pb->N);
   size_t need = (size_t)nblk * (m + 1) * sizeof(double2);
   const int stride = gs_stride(std::min(m + 1, 32));
   need = std::max(need, (size_t)gs_blocks(pb->N, 32) * stride * sizeof(double2));
-  pb->partial.alloc(std::max<size_t>(pb->partial.bytes, need));
+  need = (need + 255) & ~size_t(255);
+  pb->kpart_stride = (long long)(need / sizeof(double2));
+  pb->partial.alloc(std::max<size_t>(pb->partial.bytes, need * nr));
+  pb->knpart_stride = std::max(krylov_blocks(pb->N), gs_blocks(pb->N, 32));
+  pb->npartial.alloc(std::max<size_t>(pb->npartial.bytes, sizeof(double) * pb->knpart_stride * nr));
   pb->krylov_m = m;
   pb->krylov_nr = nr;
 }
@@ -1966,56 +1973,109 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
       for (int s : cur)
         precond_rounds(pb, R[s].V + (long long)j * N, R[s].Z + (long long)j * N, rounds);
     }
-    for (int s : cur) {
-      RhsRun& q = R[s];
-      apply_A(pb, q.Z + (long long)j * N, w);
-      // Classical Gram-Schmidt with re-orthogonalisation: h1 = V^H w with
-      // |w|^2, w -= V h1 with the new |w|^2; a second pass (gated on the
-      // device) when more than half of |w|^2 cancelled.
-      {
-        Timed t(c, K_ARNOLDI);
-        double2* part = pb->partial.as<double2>();
-        double* npart = pb->npartial.as<double>();
-        int* gate = pb->flag.as<int>() + 1;
-        double2* h1 = pb->kh1.as<double2>();
-        double2* h2 = pb->kh2.as<double2>();
-        const int nv = j + 1, stride = gs_stride(nv);
-        if (stride > 0) {
-          // The first pass's update and the second pass's products share one
-          // read of the basis (the products are discarded when the gate stays
-          // closed).
-          const int gb = gs_blocks(N, nv);
-          launch_gs(st, GS_DOT, q.V, N, nv, nullptr, w, N, part, npart, nullptr);
-          launch_gs_reduce(st, part, gb, stride, nv, h1, npart, q.sc + 6, nullptr, nullptr);
-          launch_gs(st, GS_UPDATE_DOT, q.V, N, nv, h1, w, N, part, npart, nullptr);
-          launch_gs_reduce(st, part, gb, stride, nv, h2, npart, q.sc + 3, q.sc + 6, gate);
-          // The second update writes v_{j+1} itself, normalised by
-          // |w|^2 = |w1|^2 - |h2|^2 (kept in sc[8]); the Givens step adds h2 to
-          // the column.  With the gate closed, the scale below makes v_{j+1}.
-          launch_gs(st, GS_UPDATE_NORMALIZE, q.V, N, nv, h2, w, N, part, npart, gate,
-                    q.V + (long long)(j + 1) * N, q.sc + 3, q.sc + 8);
-        } else {
-          launch_mdot(st, q.V, N, nv, w, N, part, npart, nullptr);
+    // A z_j, then classical Gram-Schmidt with re-orthogonalisation: h1 = V^H w
+    // with |w|^2, w -= V h1 with the new |w|^2; a second pass (gated on the
+    // device) when more than half of |w|^2 cancelled.  Every right-hand side
+    // has its own w, partials, coefficients and gate; with a basis of at most
+    // 32 vectors each pass is one launch for all of them.
+    const int nv = j + 1, stride = gs_stride(nv);
+    auto wof = [&](int s) { return w + (long long)s * N; };
+    auto partof = [&](int s) { return pb->partial.as<double2>() + (long long)s * pb->kpart_stride; };
+    auto npartof = [&](int s) { return pb->npartial.as<double>() + (long long)s * pb->knpart_stride; };
+    auto gateof = [&](int s) { return pb->flag.as<int>() + 4 + s; };
+    auto h1of = [&](int s) { return pb->kh1.as<double2>() + (long long)s * (m + 1); };
+    auto h2of = [&](int s) { return pb->kh2.as<double2>() + (long long)s * (m + 1); };
+    for (int s : cur) apply_A(pb, R[s].Z + (long long)j * N, wof(s));
+    const int nc = (int)cur.size();
+    {
+      Timed t(c, K_ARNOLDI);
+      if (stride > 0) {
+        // The first pass's update and the second pass's products share one
+        // read of the basis (the products are discarded when the gate stays
+        // closed).  The second update writes v_{j+1} itself, normalised by
+        // |w|^2 = |w1|^2 - |h2|^2 (kept in sc[8]); the Givens step adds h2 to
+        // the column.  With the gate closed, the scale below makes v_{j+1}.
+        const int gb = gs_blocks(N, nv);
+        GsSet ga;
+        GsRedSet ra;
+        for (int i = 0; i < nc; ++i) {
+          const int s = cur[i];
+          ga.V[i] = R[s].V;
+          ga.w[i] = wof(s);
+          ga.partial[i] = partof(s);
+          ga.npart[i] = npartof(s);
+          ra.partial[i] = partof(s);
+          ra.npart[i] = npartof(s);
+        }
+        launch_gs_set(st, GS_DOT, nc, ga, N, nv, N);
+        for (int i = 0; i < nc; ++i) {
+          ra.h[i] = h1of(cur[i]);
+          ra.out[i] = R[cur[i]].sc + 6;
+        }
+        launch_gs_reduce_set(st, nc, ra, gb, stride, nv);
+        for (int i = 0; i < nc; ++i) ga.h[i] = h1of(cur[i]);
+        launch_gs_set(st, GS_UPDATE_DOT, nc, ga, N, nv, N);
+        for (int i = 0; i < nc; ++i) {
+          const int s = cur[i];
+          ra.h[i] = h2of(s);
+          ra.out[i] = R[s].sc + 3;
+          ra.ref[i] = R[s].sc + 6;
+          ra.gate[i] = gateof(s);
+        }
+        launch_gs_reduce_set(st, nc, ra, gb, stride, nv);
+        for (int i = 0; i < nc; ++i) {
+          const int s = cur[i];
+          ga.h[i] = h2of(s);
+          ga.gate[i] = gateof(s);
+          ga.vout[i] = R[s].V + (long long)(j + 1) * N;
+          ga.nrm_in[i] = R[s].sc + 3;
+          ga.nrm_out[i] = R[s].sc + 8;
+        }
+        launch_gs_set(st, GS_UPDATE_NORMALIZE, nc, ga, N, nv, N);
+      } else {
+        for (int s : cur) {
+          RhsRun& q = R[s];
+          double2* part = partof(s);
+          double* npart = npartof(s);
+          int* gate = gateof(s);
+          double2* h1 = h1of(s);
+          double2* h2 = h2of(s);
+          double2* ws = wof(s);
+          launch_mdot(st, q.V, N, nv, ws, N, part, npart, nullptr);
           launch_mdot_reduce(st, part, nblk, nv, h1, nullptr);
           launch_norm_reduce(st, npart, nblk, q.sc + 6, nullptr, nullptr, 0);
-          launch_mupdate(st, q.V, N, nv, h1, w, N, npart, nullptr);
+          launch_mupdate(st, q.V, N, nv, h1, ws, N, npart, nullptr);
           launch_norm_reduce(st, npart, nblk, q.sc + 3, q.sc + 6, gate, 1);
-          launch_mdot(st, q.V, N, nv, w, N, part, nullptr, gate);
+          launch_mdot(st, q.V, N, nv, ws, N, part, nullptr, gate);
           launch_mdot_reduce(st, part, nblk, nv, h2, gate);
-          launch_mupdate(st, q.V, N, nv, h2, w, N, npart, gate);
+          launch_mupdate(st, q.V, N, nv, h2, ws, N, npart, gate);
           launch_norm_reduce(st, npart, nblk, q.sc + 3, nullptr, gate, 0);
           launch_hacc(st, h1, h2, nv, gate);
         }
       }
-      {
-        Timed t(c, K_UPDATE);
-        const bool reg = gs_stride(j + 1) > 0;
-        int* gate = pb->flag.as<int>() + 1;
-        launch_scale_givens(st, w, q.V + (long long)(j + 1) * N, N, q.H, pb->kh1.as<double2>(),
-                            q.sc + 3, q.cs, q.sn, q.g, j, m + 1, q.sc + 4,
-                            reg ? pb->kh2.as<double2>() : nullptr, reg ? gate : nullptr,
-                            reg ? q.sc + 8 : nullptr, q.hpd + 16 + 2 * (j & 1));
+    }
+    {
+      Timed t(c, K_UPDATE);
+      const bool reg = stride > 0;
+      GivensSet gv;
+      for (int i = 0; i < nc; ++i) {
+        const int s = cur[i];
+        RhsRun& q = R[s];
+        gv.w[i] = wof(s);
+        gv.v[i] = q.V + (long long)(j + 1) * N;
+        gv.H[i] = q.H;
+        gv.h[i] = h1of(s);
+        gv.wnorm2[i] = q.sc + 3;
+        gv.cs[i] = q.cs;
+        gv.sn[i] = q.sn;
+        gv.g[i] = q.g;
+        gv.est[i] = q.sc + 4;
+        gv.h2[i] = reg ? h2of(s) : nullptr;
+        gv.gate[i] = reg ? gateof(s) : nullptr;
+        gv.wnorm2_alt[i] = reg ? q.sc + 8 : nullptr;
+        gv.host_out[i] = q.hpd + 16 + 2 * (j & 1);
       }
+      launch_scale_givens_set(st, nc, gv, N, j, m + 1);
     }
     HIP_CHECK(hipEventRecord(c->iter_ev[j & 1], st));
   };

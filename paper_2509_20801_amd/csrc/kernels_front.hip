@@ -1621,6 +1621,13 @@ __global__ __launch_bounds__(256) void k_zero(double2* __restrict__ p, long long
     p[t] = make_double2(0.0, 0.0);
 }
 
+// z_s = 0 for the right-hand sides of rs (blockIdx.y = s).
+__global__ __launch_bounds__(256) void k_zero_set(RhsSet rs, long long n) {
+  double2* p = rs.z[blockIdx.y];
+  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256)
+    p[t] = make_double2(0.0, 0.0);
+}
+
 // The quantity of Eq. (20): per subdomain (block), the 2-norm of its local
 // field on Omega_k outside I_k (the overlapping region), then (one block) the
 // sum of those norms over the subdomains in index order.
@@ -2134,6 +2141,14 @@ void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const 
                      slist, sfirst, inst, pact, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
+}
+
+void launch_zero_set(hipStream_t st, const RhsSet& r, long long n) {
+  check_rhs(r);
+  long long g = (n + 255) / 256;
+  if (g > 8192 / r.nr) g = 8192 / r.nr;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_zero_set, dim3((unsigned)g, r.nr), dim3(256), 0, st, r, n);
 }
 
 void launch_zero(hipStream_t st, double2* p, long long n) {

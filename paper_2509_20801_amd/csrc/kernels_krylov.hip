@@ -191,16 +191,20 @@ template <int K> __device__ inline double wave_fold(double (&a)[K], int lane) {
 // final; instead of w it writes v = w / |w| to vout, with |w|^2 taken as
 // nrm_in[0] - |h|^2 (the new w is orthogonal to the basis, so the norm removed
 // is that of the coefficients), which block 0 also stores in nrm_out[0].
+// One launch serves the right-hand sides of a GsSet: blockIdx.y selects the
+// pointers, the pass over each vector is that of a single launch.
 template <int NVM, bool UPD, bool DOT, bool NRM>
-__global__ __launch_bounds__(KT) void k_gs(const double2* __restrict__ V, long long ld, int nv,
-                                           const double2* __restrict__ h,
-                                           double2* __restrict__ w, long long n,
-                                           double* __restrict__ partial,
-                                           double* __restrict__ norm_partial,
-                                           const int* __restrict__ gate,
-                                           double2* __restrict__ vout,
-                                           const double* __restrict__ nrm_in,
-                                           double* __restrict__ nrm_out) {
+__global__ __launch_bounds__(KT) void k_gs(GsSet S, long long ld, int nv, long long n) {
+  const int sy = blockIdx.y;
+  const double2* __restrict__ V = S.V[sy];
+  const double2* __restrict__ h = S.h[sy];
+  double2* __restrict__ w = S.w[sy];
+  double* __restrict__ partial = reinterpret_cast<double*>(S.partial[sy]);
+  double* __restrict__ norm_partial = S.npart[sy];
+  const int* __restrict__ gate = S.gate[sy];
+  double2* __restrict__ vout = S.vout[sy];
+  const double* __restrict__ nrm_in = S.nrm_in[sy];
+  double* __restrict__ nrm_out = S.nrm_out[sy];
   constexpr int K = 2 * NVM;
   constexpr int EPT = 32 / NVM;                          // entries per thread
   __shared__ double2 hs[NVM];
@@ -325,12 +329,14 @@ struct Cd {
 // Blocks 0..nv-1: h[i] = sum_b partial[b * stride + i] in a fixed order;
 // block nv: out[0] = sum of the nblk norm partials and, with ref, the
 // re-orthogonalisation gate (out < ref/2).
-__global__ __launch_bounds__(KT) void k_gs_reduce(const double2* __restrict__ partial, int nblk,
-                                                  int stride, int nv, double2* __restrict__ h,
-                                                  const double* __restrict__ npart,
-                                                  double* __restrict__ out,
-                                                  const double* __restrict__ ref,
-                                                  int* __restrict__ gate) {
+__global__ __launch_bounds__(KT) void k_gs_reduce(GsRedSet S, int nblk, int stride, int nv) {
+  const int sy = blockIdx.y;
+  const double2* __restrict__ partial = S.partial[sy];
+  double2* __restrict__ h = S.h[sy];
+  const double* __restrict__ npart = S.npart[sy];
+  double* __restrict__ out = S.out[sy];
+  const double* __restrict__ ref = S.ref[sy];
+  int* __restrict__ gate = S.gate[sy];
   __shared__ double red[4];
   const int i = blockIdx.x;
   if (i < nv) {
@@ -480,23 +486,13 @@ __device__ inline void givens_body(double2* __restrict__ H, const double2* __res
 // second Gram-Schmidt update wrote it).  The Givens step writes |w| only when
 // the gate is set, the scale reads it only when it is not, so the blocks do
 // not race.
-__global__ __launch_bounds__(KT) void k_scale_givens(const double2* __restrict__ w,
-                                                     double2* __restrict__ v, long long n,
-                                                     double2* __restrict__ H,
-                                                     const double2* __restrict__ h,
-                                                     double* __restrict__ wnorm2,
-                                                     double* __restrict__ cs,
-                                                     double2* __restrict__ sn,
-                                                     double2* __restrict__ g, int j, int ldh,
-                                                     double* __restrict__ est,
-                                                     const double2* __restrict__ h2,
-                                                     const int* __restrict__ gate,
-                                                     const double* __restrict__ wnorm2_alt,
-                                                     double* __restrict__ host_out) {
+__global__ __launch_bounds__(KT) void k_scale_givens(GivensSet S, long long n, int j, int ldh) {
+  const int sy = blockIdx.y;
   if (blockIdx.x == 0)
-    givens_body(H, h, wnorm2, cs, sn, g, j, ldh, est, h2, gate, wnorm2_alt, host_out);
+    givens_body(S.H[sy], S.h[sy], S.wnorm2[sy], S.cs[sy], S.sn[sy], S.g[sy], j, ldh, S.est[sy],
+                S.h2[sy], S.gate[sy], S.wnorm2_alt[sy], S.host_out[sy]);
   else
-    scale_body(w, wnorm2, v, n, gate, blockIdx.x - 1, gridDim.x - 1);
+    scale_body(S.w[sy], S.wnorm2[sy], S.v[sy], n, S.gate[sy], blockIdx.x - 1, gridDim.x - 1);
 }
 
 // y = R^{-1} g by back substitution on one thread.  For k <= TSL the upper
@@ -584,42 +580,64 @@ int gs_blocks(long long n, int nv) {
 }
 
 
-void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
-                      double2* h, const double* npart, double* out, const double* ref, int* gate) {
-  hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1), dim3(KT), 0, st, partial, nblk, stride, nv, h,
-                     npart, out, ref, gate);
+void launch_gs_reduce_set(hipStream_t st, int nr, const GsRedSet& S, int nblk, int stride, int nv) {
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
+  hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1, nr), dim3(KT), 0, st, S, nblk, stride, nv);
 }
 
-void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
-               double2* w, long long n, double2* partial, double* norm_partial, const int* gate,
-               double2* vout, const double* nrm_in, double* nrm_out) {
+void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
+                      double2* h, const double* npart, double* out, const double* ref, int* gate) {
+  GsRedSet S;
+  S.partial[0] = partial;
+  S.h[0] = h;
+  S.npart[0] = npart;
+  S.out[0] = out;
+  S.ref[0] = ref;
+  S.gate[0] = gate;
+  launch_gs_reduce_set(st, 1, S, nblk, stride, nv);
+}
+
+void launch_gs_set(hipStream_t st, int mode, int nr, const GsSet& S, long long ld, int nv, long long n) {
   const int nvm = gs_stride(nv);
   STF_REQUIRE(nvm > 0 && nv >= 1, "register Gram-Schmidt pass takes 1..32 basis vectors");
   STF_REQUIRE(mode >= GS_DOT && mode <= GS_UPDATE_NORMALIZE, "unknown Gram-Schmidt pass");
-  STF_REQUIRE(mode != GS_UPDATE_NORMALIZE || (vout && nrm_in && nrm_out),
-              "normalising pass needs its output vector and norms");
-  double* pd = reinterpret_cast<double*>(partial);
-  const dim3 g(gs_blocks(n, nv)), b(KT);
-#define STF_GS_CASE(M)                                                                         \
-  if (nvm == M) {                                                                              \
-    if (mode == GS_DOT)                                                                        \
-      hipLaunchKernelGGL((k_gs<M, false, true, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,   \
-                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
-    else if (mode == GS_UPDATE_DOT)                                                            \
-      hipLaunchKernelGGL((k_gs<M, true, true, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,    \
-                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
-    else if (mode == GS_UPDATE)                                                                \
-      hipLaunchKernelGGL((k_gs<M, true, false, false>), g, b, 0, st, V, ld, nv, h, w, n, pd,   \
-                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
-    else                                                                                       \
-      hipLaunchKernelGGL((k_gs<M, true, false, true>), g, b, 0, st, V, ld, nv, h, w, n, pd,    \
-                         norm_partial, gate, vout, nrm_in, nrm_out);                           \
-    return;                                                                                    \
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
+  for (int s = 0; s < nr; ++s)
+    STF_REQUIRE(mode != GS_UPDATE_NORMALIZE || (S.vout[s] && S.nrm_in[s] && S.nrm_out[s]),
+                "normalising pass needs its output vector and norms");
+  const dim3 g(gs_blocks(n, nv), nr), b(KT);
+#define STF_GS_CASE(M)                                                                        \
+  if (nvm == M) {                                                                             \
+    if (mode == GS_DOT)                                                                       \
+      hipLaunchKernelGGL((k_gs<M, false, true, false>), g, b, 0, st, S, ld, nv, n);           \
+    else if (mode == GS_UPDATE_DOT)                                                           \
+      hipLaunchKernelGGL((k_gs<M, true, true, false>), g, b, 0, st, S, ld, nv, n);            \
+    else if (mode == GS_UPDATE)                                                               \
+      hipLaunchKernelGGL((k_gs<M, true, false, false>), g, b, 0, st, S, ld, nv, n);           \
+    else                                                                                      \
+      hipLaunchKernelGGL((k_gs<M, true, false, true>), g, b, 0, st, S, ld, nv, n);            \
+    return;                                                                                   \
   }
   STF_GS_CASE(8)
   STF_GS_CASE(16)
   STF_GS_CASE(32)
 #undef STF_GS_CASE
+}
+
+void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
+               double2* w, long long n, double2* partial, double* norm_partial, const int* gate,
+               double2* vout, const double* nrm_in, double* nrm_out) {
+  GsSet S;
+  S.V[0] = V;
+  S.h[0] = h;
+  S.w[0] = w;
+  S.partial[0] = partial;
+  S.npart[0] = norm_partial;
+  S.gate[0] = gate;
+  S.vout[0] = vout;
+  S.nrm_in[0] = nrm_in;
+  S.nrm_out[0] = nrm_out;
+  launch_gs_set(st, mode, 1, S, ld, nv, n);
 }
 
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
@@ -647,13 +665,31 @@ void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2*
   hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n, skip);
 }
 
+void launch_scale_givens_set(hipStream_t st, int nr, const GivensSet& S, long long n, int j, int ldh) {
+  STF_REQUIRE(j >= 0 && j < GV, "Givens step beyond the staged column");
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
+  hipLaunchKernelGGL(k_scale_givens, dim3(grid_for(n) + 1, nr), dim3(KT), 0, st, S, n, j, ldh);
+}
+
 void launch_scale_givens(hipStream_t st, const double2* w, double2* v, long long n, double2* H,
                          const double2* h, double* wnorm2, double* cs, double2* sn, double2* g,
                          int j, int ldh, double* est_out, const double2* h2, const int* gate,
                          const double* wnorm2_alt, double* host_out) {
-  STF_REQUIRE(j >= 0 && j < GV, "Givens step beyond the staged column");
-  hipLaunchKernelGGL(k_scale_givens, dim3(grid_for(n) + 1), dim3(KT), 0, st, w, v, n, H, h, wnorm2,
-                     cs, sn, g, j, ldh, est_out, h2, gate, wnorm2_alt, host_out);
+  GivensSet S;
+  S.w[0] = w;
+  S.v[0] = v;
+  S.H[0] = H;
+  S.h[0] = h;
+  S.wnorm2[0] = wnorm2;
+  S.cs[0] = cs;
+  S.sn[0] = sn;
+  S.g[0] = g;
+  S.est[0] = est_out;
+  S.h2[0] = h2;
+  S.gate[0] = gate;
+  S.wnorm2_alt[0] = wnorm2_alt;
+  S.host_out[0] = host_out;
+  launch_scale_givens_set(st, 1, S, n, j, ldh);
 }
 
 void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n) {

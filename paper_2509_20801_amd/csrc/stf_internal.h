@@ -331,6 +331,7 @@ void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const 
                           int scount, int maxw, int maxh, const int* inst, const int* pact,
                           const RhsSet& r);
 void launch_zero(hipStream_t st, double2* p, long long n);
+void launch_zero_set(hipStream_t st, const RhsSet& r, long long n);   // every r.z[s]
 // Eq. (20): per_sub[k] = |u_k| on Omega_k outside I_k (nsub subdomains), out[0] = their sum.
 template <typename T>
 void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsub, double* per_sub,
@@ -359,10 +360,34 @@ int gs_stride(int nv);    // 8, 16 or 32; 0 when nv > 32 (use launch_mdot / laun
 void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv, const double2* h,
                double2* w, long long n, double2* partial, double* norm_partial, const int* gate,
                double2* vout = nullptr, const double* nrm_in = nullptr, double* nrm_out = nullptr);
+// The same pass for nr (<= MAX_RHS) independent right-hand sides in one
+// launch (blockIdx.y = s); every pointer of launch_gs per right-hand side,
+// basis length nv, leading dimension ld and vector length n shared.
+struct GsSet {
+  const double2* V[MAX_RHS] = {};
+  const double2* h[MAX_RHS] = {};
+  double2* w[MAX_RHS] = {};
+  double2* partial[MAX_RHS] = {};
+  double* npart[MAX_RHS] = {};
+  const int* gate[MAX_RHS] = {};
+  double2* vout[MAX_RHS] = {};
+  const double* nrm_in[MAX_RHS] = {};
+  double* nrm_out[MAX_RHS] = {};
+};
+void launch_gs_set(hipStream_t st, int mode, int nr, const GsSet& S, long long ld, int nv, long long n);
 // Between the passes: h[i] = sum_b partial[b * stride + i] (i < nv) and
 // out = sum of the nblk norm partials, with ref also gate = (out < ref/2).
 void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
                       double2* h, const double* npart, double* out, const double* ref, int* gate);
+struct GsRedSet {
+  const double2* partial[MAX_RHS] = {};
+  double2* h[MAX_RHS] = {};
+  const double* npart[MAX_RHS] = {};
+  double* out[MAX_RHS] = {};
+  const double* ref[MAX_RHS] = {};
+  int* gate[MAX_RHS] = {};
+};
+void launch_gs_reduce_set(hipStream_t st, int nr, const GsRedSet& S, int nblk, int stride, int nv);
 // w -= V h (+ |w|^2 partials).
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
                     double2* w, long long n, double* norm_partial, const int* gate);
@@ -386,6 +411,22 @@ void launch_scale_givens(hipStream_t st, const double2* w, double2* v, long long
                          const double2* h, double* wnorm2, double* cs, double2* sn, double2* g,
                          int j, int ldh, double* est_out, const double2* h2, const int* gate,
                          const double* wnorm2_alt, double* host_out);
+struct GivensSet {
+  const double2* w[MAX_RHS] = {};
+  double2* v[MAX_RHS] = {};
+  double2* H[MAX_RHS] = {};
+  const double2* h[MAX_RHS] = {};
+  double* wnorm2[MAX_RHS] = {};
+  double* cs[MAX_RHS] = {};
+  double2* sn[MAX_RHS] = {};
+  double2* g[MAX_RHS] = {};
+  double* est[MAX_RHS] = {};
+  const double2* h2[MAX_RHS] = {};
+  const int* gate[MAX_RHS] = {};
+  const double* wnorm2_alt[MAX_RHS] = {};
+  double* host_out[MAX_RHS] = {};
+};
+void launch_scale_givens_set(hipStream_t st, int nr, const GivensSet& S, long long n, int j, int ldh);
 // y = R^{-1} g (k x k upper triangular, column-major ldh).
 void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
                      int ldh);
