@@ -1985,8 +1985,17 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
     auto gateof = [&](int s) { return pb->flag.as<int>() + 4 + s; };
     auto h1of = [&](int s) { return pb->kh1.as<double2>() + (long long)s * (m + 1); };
     auto h2of = [&](int s) { return pb->kh2.as<double2>() + (long long)s * (m + 1); };
-    for (int s : cur) apply_A(pb, R[s].Z + (long long)j * N, wof(s));
     const int nc = (int)cur.size();
+    {
+      StencilSet sa;
+      for (int i = 0; i < nc; ++i) {
+        sa.x[i] = R[cur[i]].Z + (long long)j * N;
+        sa.y[i] = wof(cur[i]);
+      }
+      Timed t(c, K_STENCIL);
+      launch_stencil_set(st, nc, sa, pb->keps.as<double2>(), pb->cxw(), pb->cxe(), pb->cyw(), pb->cye(),
+                         pb->prm.nx, pb->prm.ny);
+    }
     {
       Timed t(c, K_ARNOLDI);
       if (stride > 0) {

@@ -73,6 +73,35 @@ __global__ __launch_bounds__(256) void k_stencil(const double2* __restrict__ x,
   }
 }
 
+// y_s = A x_s for NR vectors (blockIdx.z-free: every thread applies its
+// node's coefficients, loaded once, to all of them; the arithmetic per vector
+// is that of k_stencil<0>).
+template <int NR>
+__global__ __launch_bounds__(256) void k_stencil_set(StencilSet S, const double2* __restrict__ keps,
+                                                     const double2* __restrict__ cxw,
+                                                     const double2* __restrict__ cxe,
+                                                     const double2* __restrict__ cyw,
+                                                     const double2* __restrict__ cye, int nx, int ny) {
+  int i = blockIdx.x * SBX + threadIdx.x;
+  int j = blockIdx.y * SBY + threadIdx.y;
+  if (i >= nx || j >= ny) return;
+  long long n = (long long)j * nx + i;
+  double2 aw = cxw[i], ae = cxe[i], as = cyw[j], an = cye[j];
+  double2 ke = keps[n];
+  double2 dg = make_double2(ke.x - ((aw.x + ae.x) + (as.x + an.x)),
+                            ke.y - ((aw.y + ae.y) + (as.y + an.y)));
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    const double2* __restrict__ x = S.x[s];
+    double2 acc = cmul(dg, x[n]);
+    if (i > 0) acc = cfma(aw, x[n - 1], acc);
+    if (i < nx - 1) acc = cfma(ae, x[n + 1], acc);
+    if (j > 0) acc = cfma(as, x[n - nx], acc);
+    if (j < ny - 1) acc = cfma(an, x[n + nx], acc);
+    S.y[s][n] = acc;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ partial, int n,
                                                     double* __restrict__ out) {
   __shared__ double red[4];
@@ -193,6 +222,20 @@ void launch_node_keps(hipStream_t st, const double2* cells, double2* keps, int n
 
 int stencil_partial_blocks(int nx, int ny) {
   return ((nx + SBX - 1) / SBX) * ((ny + SBY - 1) / SBY);
+}
+
+void launch_stencil_set(hipStream_t st, int nr, const StencilSet& S, const double2* keps,
+                        const double2* cxw, const double2* cxe, const double2* cyw,
+                        const double2* cye, int nx, int ny) {
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 vectors per stencil launch");
+  dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_stencil_set<NR>), grd, blk, 0, st, S, keps, cxw, cxe, cyw, cye, nx, ny)
+  if (nr == 1) STF_CALL(1);
+  else if (nr == 2) STF_CALL(2);
+  else if (nr == 3) STF_CALL(3);
+  else STF_CALL(4);
+#undef STF_CALL
 }
 
 void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b, double2* y,

@@ -209,6 +209,15 @@ enum KClass {
 // node k0^2 * eps_bar from the cell map (Eq. (3)).
 void launch_node_keps(hipStream_t st, const double2* cells, double2* keps, int nx, int ny,
                       double k0sq);
+// y_s = A x_s for nr (<= MAX_RHS) vectors in one launch (the coefficients
+// read once per node for all of them).
+struct StencilSet {
+  const double2* x[MAX_RHS] = {};
+  double2* y[MAX_RHS] = {};
+};
+void launch_stencil_set(hipStream_t st, int nr, const StencilSet& S, const double2* keps,
+                        const double2* cxw, const double2* cxe, const double2* cyw,
+                        const double2* cye, int nx, int ny);
 // y = A x  (mode 0) or r = b - A x with per-block partial |r|^2 (mode 1).
 void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b, double2* y,
                     const double2* keps, const double2* cxw, const double2* cxe,
