@@ -726,30 +726,51 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
           Us[c][k] = (k < nb) ? F[(long long)(c0 + c) * m + kb + k] : czero<T>();
         }
         __syncthreads();
-        const int ntc = (cw + 15) / 16;
-        for (int tt = wv; tt < ntr * ntc; tt += NTF / 64) {
-          const int rb = n0 + 16 * (tt / ntc), cb = 16 * (tt % ntc);
-          typename M::V accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
-          const int ra = rb + l16, cbb = cb + l16;
-          for (int k0 = 0; k0 < nb; k0 += 4) {
-            const int kk = k0 + lk;
-            const T av = (kk < nb && ra < m) ? P[kk * ldp + (ra - kb)] : czero<T>();
-            const T bv = (kk < nb && cbb < cw) ? Us[cbb][kk] : czero<T>();
-            accr = M::mma((MR)av.x, (MR)bv.x, accr);
-            accr = M::mma((MR)-av.y, (MR)bv.y, accr);
-            acci = M::mma((MR)av.x, (MR)bv.y, acci);
-            acci = M::mma((MR)av.y, (MR)bv.x, acci);
-          }
-          if (cbb < cw) {
-            T* Fc = F + (long long)(c0 + cbb) * m;
+        const int ntc = (cw + 15) / 16, nt = ntr * ntc;
+        // TU tiles per wavefront at a time: the loads of their F22 entries are
+        // issued together before the products, so that the memory round trips
+        // of the read-modify-writes overlap instead of following each other.
+        constexpr int TU = (NTF >= 1024 || NB <= 8) ? 2 : 4, NWV = NTF / 64;
+        for (int t0 = wv; t0 < nt; t0 += TU * NWV) {
+          T cv[TU][4];
+#pragma unroll
+          for (int u = 0; u < TU; ++u) {
+            const int tt = t0 + u * NWV;
+            const int rb = n0 + 16 * (tt / ntc), cbb = 16 * (tt % ntc) + l16;
+            const T* Fc = F + (long long)(c0 + cbb) * m;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
               const int r = rb + M::row(lane, v);
-              if (r < m) {
-                T x = Fc[r];
-                x.x -= accr[v];
-                x.y -= acci[v];
-                Fc[r] = x;
+              cv[u][v] = (tt < nt && cbb < cw && r < m) ? Fc[r] : czero<T>();
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < TU; ++u) {
+            const int tt = t0 + u * NWV;
+            if (tt >= nt) break;
+            const int rb = n0 + 16 * (tt / ntc), cb = 16 * (tt % ntc);
+            typename M::V accr = {0, 0, 0, 0}, acci = {0, 0, 0, 0};
+            const int ra = rb + l16, cbb = cb + l16;
+            for (int k0 = 0; k0 < nb; k0 += 4) {
+              const int kk = k0 + lk;
+              const T av = (kk < nb && ra < m) ? P[kk * ldp + (ra - kb)] : czero<T>();
+              const T bv = (kk < nb && cbb < cw) ? Us[cbb][kk] : czero<T>();
+              accr = M::mma((MR)av.x, (MR)bv.x, accr);
+              accr = M::mma((MR)-av.y, (MR)bv.y, accr);
+              acci = M::mma((MR)av.x, (MR)bv.y, acci);
+              acci = M::mma((MR)av.y, (MR)bv.x, acci);
+            }
+            if (cbb < cw) {
+              T* Fc = F + (long long)(c0 + cbb) * m;
+#pragma unroll
+              for (int v = 0; v < 4; ++v) {
+                const int r = rb + M::row(lane, v);
+                if (r < m) {
+                  T x = cv[u][v];
+                  x.x -= accr[v];
+                  x.y -= acci[v];
+                  Fc[r] = x;
+                }
               }
             }
           }
