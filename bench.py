@@ -160,7 +160,8 @@ def stationary_form(stf, torch, ctx, w, prec, tol, max_rounds):
 # Kernel classes of the library's kernels (by kernel name) and the source file
 # that holds them (a PMC summary is valid only for the source it was taken on).
 CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "front_lu"),
-            ("k_stencil", "stencil"), ("k_scatter", "scatter"), ("k_mdot", "arnoldi"),
+            ("k_stencil", "stencil"), ("k_stage_residual", "stencil"), ("k_scatter", "scatter"),
+            ("k_stage_scatter", "scatter"), ("k_zero", "scatter"), ("k_mdot", "arnoldi"),
             ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi"),
             ("k_gs", "arnoldi"), ("k_gemm", "nn"), ("k_pw_", "nn"), ("k_dft_", "nn"),
             ("k_mix_", "nn"), ("k_nn_", "nn"), ("k_spec_", "nn")]
