@@ -215,6 +215,7 @@ struct SweepPlan {
   std::vector<int> s_first, s_count;          // per stage: its members in slist
   std::vector<std::vector<Level>> lv;         // per stage and depth: range in flist
   DBuf slist, flist, inst;                    // members, front instances, membership flags
+  DBuf fdev;                                  // the descriptors of flist's fronts, in its order
   std::vector<int> h_flist;                   // host copy of flist
   // subtree sweeps per choice (16 D + T): per stage, the tables over the
   // stage's fronts at depth D (null where the stage has none)
@@ -1030,6 +1031,11 @@ const SweepPlan& sweep_plan(Mf& mf, int order, hipStream_t st) {
   upload(sp->slist, slist, st);
   upload(sp->flist, flist, st);
   upload(sp->inst, inst, st);
+  // A stage level's launch reads its fronts' descriptors from this copy
+  // directly (one dependent load per workgroup instead of two).
+  std::vector<FrontDev> fd(flist.size());
+  for (size_t i = 0; i < flist.size(); ++i) fd[i] = mf.h_fronts[flist[i]];
+  upload(sp->fdev, fd, st);
   sp->h_flist = flist;
   HIP_CHECK(hipStreamSynchronize(st));
   const SweepPlan& ref = *sp;
@@ -1077,10 +1083,11 @@ int staged_fuse_for(stf_ctx c, Mf& mf, const SweepPlan& sp, size_t elem, int nr,
 }
 
 // Level d of stage t as launch arguments: the stage's fronts of that level
-// (through the stage front list), the level's largest orders.
+// (their descriptors from the stage plan's copy), the level's largest orders.
 LevelArgs stage_level_args(const Mf& mf, const SweepPlan& sp, int t, int d, const int* pact) {
   LevelArgs la = mf.level_args(d, nullptr, pact);
-  la.flist = sp.flist.as<int>();
+  la.fronts = sp.fdev.as<FrontDev>();
+  la.flist = nullptr;
   la.first = sp.lv[t][d].off;
   la.nlevel = sp.lv[t][d].n;
   return la;
