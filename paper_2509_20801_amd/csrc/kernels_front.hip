@@ -40,6 +40,9 @@ constexpr int NT = 256;        // threads of a large-front workgroup
 constexpr int UC = 32;         // columns of U staged in LDS per trailing-update chunk
 constexpr int DIB = 64;        // inverted diagonal blocks of L11 and U11
 constexpr int CR = 32;         // rows (or columns) staged per chunk by the inversion tail
+// Leading dimension of the inversion tail's diagonal blocks for a level whose
+// separators are at most max_p wide.
+__host__ __device__ constexpr int inv_ld(int max_p) { return max_p <= 32 ? 32 : DIB; }
 
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -783,22 +786,26 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
   // L11 (wavefront 0) and U11 (wavefront 1), one block at a time in LDS.
   if (tid == 0) pivots_to_perm(ip, reinterpret_cast<int*>(P), p);
   __syncthreads();
-  T* Db = P;                                    // DIB x DIB block, then two column buffers
+  // Diagonal blocks with leading dimension LDB (32 when every separator of the
+  // level fits, so that levels of small separators keep their LDS small), two
+  // 64-entry column buffers, then a CR x LDB staging chunk.
+  const int LDB = inv_ld(a.max_p);
+  T* Db = P;
   for (int j0 = 0; j0 < p; j0 += DIB) {
     const int nbk = min(DIB, p - j0);
     for (int t = tid; t < nbk * nbk; t += NTF) {
       int c = t / nbk, r = t - c * nbk;
-      Db[c * DIB + r] = F[(long long)(j0 + c) * m + j0 + r];
+      Db[c * LDB + r] = F[(long long)(j0 + c) * m + j0 + r];
     }
     __syncthreads();
-    if (wv == 0) invert_lower_unit(Db, DIB, nbk, Db + DIB * DIB, lane);
-    if (wv == 1) invert_upper(Db, DIB, nbk, Db + DIB * DIB + DIB, lane);
+    if (wv == 0) invert_lower_unit(Db, LDB, nbk, Db + LDB * LDB, lane);
+    if (wv == 1) invert_upper(Db, LDB, nbk, Db + LDB * LDB + 64, lane);
     __syncthreads();
     for (int t = tid; t < nbk * nbk; t += NTF) {
       int c = t / nbk, r = t - c * nbk;
-      F[(long long)(j0 + c) * m + j0 + r] = Db[c * DIB + r];
+      F[(long long)(j0 + c) * m + j0 + r] = Db[c * LDB + r];
     }
-    T* Cb = Db + DIB * DIB + 2 * DIB;           // CR x DIB staging chunk
+    T* Cb = Db + LDB * LDB + 128;
     // M'_J = -L[j1:m, J] Linv_J, 64 rows at a time.
     const int j1 = j0 + nbk;
     for (int r0 = j1; r0 < m; r0 += CR) {
@@ -813,7 +820,7 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
       mma_neg_product<T>(
           rows, nbk, nbk, [&](int r, int k) { return Cb[k * CR + r]; },
           [&](int k, int c) {
-            return k == c ? T{(R)1, (R)0} : (k > c ? Db[c * DIB + k] : czero<T>());
+            return k == c ? T{(R)1, (R)0} : (k > c ? Db[c * LDB + k] : czero<T>());
           },
           [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NTF / 64, lane);
     }
@@ -829,7 +836,7 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
       // [rows x nbk] = -C Uinv_J
       mma_neg_product<T>(
           rows, nbk, nbk, [&](int r, int k) { return Cb[k * CR + r]; },
-          [&](int k, int c) { return k <= c ? Db[c * DIB + k] : czero<T>(); },
+          [&](int k, int c) { return k <= c ? Db[c * LDB + k] : czero<T>(); },
           [&](int r, int c, T v) { F[(long long)(j0 + c) * m + r0 + r] = v; }, wv, NTF / 64, lane);
     }
     // A single-block front also gets V' = -U11^{-1} U12 (64 columns at a time).
@@ -839,13 +846,13 @@ __global__ __launch_bounds__(NTF) void k_factor_large(LevelArgs a, T* __restrict
         __syncthreads();
         for (int t = tid; t < cols * p; t += NTF) {
           int c = t / p, r = t - c * p;
-          Cb[c * DIB + r] = F[(long long)(c0 + c) * m + r];
+          Cb[c * LDB + r] = F[(long long)(c0 + c) * m + r];
         }
         __syncthreads();
         // [p x cols] = -Uinv U12
         mma_neg_product<T>(
-            p, cols, p, [&](int r, int k) { return k >= r ? Db[k * DIB + r] : czero<T>(); },
-            [&](int k, int c) { return Cb[c * DIB + k]; },
+            p, cols, p, [&](int r, int k) { return k >= r ? Db[k * LDB + r] : czero<T>(); },
+            [&](int k, int c) { return Cb[c * LDB + k]; },
             [&](int r, int c, T v) { F[(long long)(c0 + c) * m + r] = v; }, wv, NTF / 64, lane);
       }
     }
@@ -1697,7 +1704,8 @@ int max_lds() {
 
 // LDS bytes of the panel kernel with NB-column panels on a level.
 size_t panel_lds(const LevelArgs& a, size_t elem, int nb) {
-  return std::max((size_t)a.max_m * nb, (size_t)DIB * DIB + 2 * DIB + (size_t)CR * DIB) * elem;
+  const size_t ld = inv_ld(a.max_p);
+  return std::max((size_t)a.max_m * nb, ld * ld + 128 + (size_t)CR * ld) * elem;
 }
 // Static LDS of the panel kernel besides the dynamic panel (staged U chunk,
 // pivot and reduction arrays), bounded.
