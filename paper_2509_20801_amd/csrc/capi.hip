@@ -2120,16 +2120,27 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
       }
     }
     if (active.empty()) break;
-    for (int s : active) {
-      RhsRun& q = R[s];
-      if (!q.started) {
-        Timed t(c, K_UPDATE);
-        launch_cycle_start(st, q.r, q.sc + 2, q.V, N, q.g, m + 1);   // v_0 = r / |r|, g = |r| e_1
+    {
+      CycleSet cs;                               // v_0 = r / |r|, g = |r| e_1
+      int ns = 0;
+      for (int s : active) {
+        RhsRun& q = R[s];
+        if (!q.started) {
+          cs.r[ns] = q.r;
+          cs.nrm2[ns] = q.sc + 2;
+          cs.v[ns] = q.V;
+          cs.gs[ns] = q.g;
+          ++ns;
+        }
+        q.started = false;
+        q.stop = false;
+        q.k = 0;
+        q.launched = 0;
       }
-      q.started = false;
-      q.stop = false;
-      q.k = 0;
-      q.launched = 0;
+      if (ns > 0) {
+        Timed t(c, K_UPDATE);
+        launch_cycle_start_set(st, ns, cs, N, m + 1);
+      }
     }
     // Iteration j+1 is enqueued before the host waits for iteration j's
     // estimates, so the GPU queue does not drain between iterations.  A right-
@@ -2169,26 +2180,55 @@ stf_status fgmres_multi(stf_problem pb, int nr, const double2* const* b, double2
     // The cycle's length k is fixed by the checks above (the last iteration's
     // own estimate only adds to the history), so the update and the true
     // residual are enqueued before the host waits for that estimate.
-    for (int s : active) {
-      RhsRun& q = R[s];
-      if (!q.stop) q.k = q.launched;
+    // One launch each for every right-hand side of the cycle: y = R^{-1} g,
+    // x += Z y, r = b - A x with |r|^2 on the device and in the pinned host
+    // staging (written by the reduction itself).
+    {
+      CycleSet cs;
+      ResidualSet rs;
+      const int na = (int)active.size();
+      for (int i = 0; i < na; ++i) {
+        RhsRun& q = R[active[i]];
+        if (!q.stop) q.k = q.launched;
+        cs.H[i] = q.H;
+        cs.g[i] = q.g;
+        cs.y[i] = q.y;
+        cs.k[i] = q.k;
+        cs.Z[i] = q.Z;
+        cs.x[i] = q.x;
+        rs.x[i] = q.x;
+        rs.b[i] = q.b;
+        rs.r[i] = q.r;
+        rs.partial[i] = reinterpret_cast<double*>(pb->partial.as<double2>() + (long long)active[i] * pb->kpart_stride);
+        rs.out[i] = q.sc + 2;
+        rs.host_out[i] = q.hpd + 2;
+      }
       {
         Timed t(c, K_UPDATE);
-        launch_trisolve(st, q.H, q.g, q.y, q.k, m + 1);
-        launch_xupdate(st, q.Z, N, q.k, q.y, q.x, N);
+        launch_trisolve_set(st, na, cs, m + 1);
+        launch_xupdate_set(st, na, cs, N, N);
       }
-      residual(pb, q.x, q.b, q.r, q.sc + 2);
-      HIP_CHECK(hipMemcpyAsync(q.hp + 2, q.sc + 2, sizeof(double), hipMemcpyDeviceToHost, st));
+      Timed t(c, K_STENCIL);
+      launch_residual_set(st, na, rs, pb->keps.as<double2>(), pb->cxw(), pb->cxe(), pb->cyw(), pb->cye(),
+                          pb->prm.nx, pb->prm.ny);
     }
     HIP_CHECK(hipEventRecord(c->cycle_ev, st));
     // The next cycle's start needs only device values: enqueued now, it runs
     // while the host reads the true residuals; a right-hand side that has
     // converged or run out of iterations ignores it (it writes v_0 and g only).
-    for (int s : active) {
-      RhsRun& q = R[s];
+    {
+      CycleSet cs;
+      const int na = (int)active.size();
+      for (int i = 0; i < na; ++i) {
+        RhsRun& q = R[active[i]];
+        cs.r[i] = q.r;
+        cs.nrm2[i] = q.sc + 2;
+        cs.v[i] = q.V;
+        cs.gs[i] = q.g;
+        q.started = true;
+      }
       Timed t(c, K_UPDATE);
-      launch_cycle_start(st, q.r, q.sc + 2, q.V, N, q.g, m + 1);
-      q.started = true;
+      launch_cycle_start_set(st, na, cs, N, m + 1);
     }
     if (last >= 0) {
       HIP_CHECK(hipEventSynchronize(c->iter_ev[last & 1]));

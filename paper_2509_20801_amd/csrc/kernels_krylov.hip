@@ -391,10 +391,12 @@ __global__ __launch_bounds__(KT) void k_scale(const double2* __restrict__ w,
 
 // The start of an FGMRES cycle: v_0 = r / |r| (|r|^2 in nrm2[0]), and block 0
 // also sets g = (|r|, 0, ..., 0) (glen entries), all from device values.
-__global__ __launch_bounds__(KT) void k_cycle_start(const double2* __restrict__ r,
-                                                    const double* __restrict__ nrm2,
-                                                    double2* __restrict__ v, long long n,
-                                                    double2* __restrict__ g, int glen) {
+__global__ __launch_bounds__(KT) void k_cycle_start(CycleSet S, long long n, int glen) {
+  const int sy = blockIdx.y;
+  const double2* __restrict__ r = S.r[sy];
+  const double* __restrict__ nrm2 = S.nrm2[sy];
+  double2* __restrict__ v = S.v[sy];
+  double2* __restrict__ g = S.gs[sy];
   if (blockIdx.x == 0)
     for (int i = threadIdx.x; i < glen; i += KT)
       g[i] = make_double2(i == 0 ? sqrt(nrm2[0]) : 0.0, 0.0);
@@ -499,8 +501,8 @@ __global__ __launch_bounds__(KT) void k_scale_givens(GivensSet S, long long n, i
 // triangle of R and g are first staged in LDS by the whole block, so that the
 // serial chain waits on no memory round trips; larger k reads them directly.
 constexpr int TSL = 40;
-__global__ void k_trisolve(const double2* __restrict__ H, const double2* __restrict__ g,
-                           double2* __restrict__ y, int k, int ldh) {
+__device__ inline void trisolve_body(const double2* __restrict__ H, const double2* __restrict__ g,
+                                     double2* __restrict__ y, int k, int ldh) {
   __shared__ double2 R[TSL * TSL];
   __shared__ double2 gs[TSL], ys[TSL];
   if (k <= TSL) {
@@ -527,9 +529,18 @@ __global__ void k_trisolve(const double2* __restrict__ H, const double2* __restr
   }
 }
 
-__global__ __launch_bounds__(KT) void k_xupdate(const double2* __restrict__ Z, long long ld, int k,
-                                                const double2* __restrict__ y,
-                                                double2* __restrict__ x, long long n) {
+// One block per right-hand side (blockIdx.x = s).
+__global__ void k_trisolve(CycleSet S, int ldh) {
+  const int s = blockIdx.x;
+  trisolve_body(S.H[s], S.g[s], S.y[s], S.k[s], ldh);
+}
+
+__global__ __launch_bounds__(KT) void k_xupdate(CycleSet S, long long ld, long long n) {
+  const int sy = blockIdx.y;
+  const double2* __restrict__ Z = S.Z[sy];
+  const int k = S.k[sy];
+  const double2* __restrict__ y = S.y[sy];
+  double2* __restrict__ x = S.x[sy];
   __shared__ double2 ys[256];
   if ((int)threadIdx.x < k) ys[threadIdx.x] = y[threadIdx.x];
   __syncthreads();
@@ -655,10 +666,11 @@ void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const i
   hipLaunchKernelGGL(k_hacc, dim3(1), dim3(256), 0, st, h1, h2, nv, gate);
 }
 
-void launch_cycle_start(hipStream_t st, const double2* r, const double* nrm2, double2* v,
-                        long long n, double2* g, int glen) {
-  hipLaunchKernelGGL(k_cycle_start, dim3(grid_for(n)), dim3(KT), 0, st, r, nrm2, v, n, g, glen);
+void launch_cycle_start_set(hipStream_t st, int nr, const CycleSet& S, long long n, int glen) {
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
+  hipLaunchKernelGGL(k_cycle_start, dim3(grid_for(n), nr), dim3(KT), 0, st, S, n, glen);
 }
+
 
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n,
                   const int* skip) {
@@ -696,14 +708,14 @@ void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n) {
   hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(KT), 0, st, y, x, n);
 }
 
-void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
-                     int ldh) {
-  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, st, H, g, y, k, ldh);
+void launch_trisolve_set(hipStream_t st, int nr, const CycleSet& S, int ldh) {
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
+  hipLaunchKernelGGL(k_trisolve, dim3(nr), dim3(64), 0, st, S, ldh);
 }
 
-void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
-                    double2* x, long long n) {
-  hipLaunchKernelGGL(k_xupdate, dim3(grid_for(n)), dim3(KT), 0, st, Z, ld, k, y, x, n);
+void launch_xupdate_set(hipStream_t st, int nr, const CycleSet& S, long long ld, long long n) {
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
+  hipLaunchKernelGGL(k_xupdate, dim3(grid_for(n), nr), dim3(KT), 0, st, S, ld, n);
 }
 
 }  // namespace stf

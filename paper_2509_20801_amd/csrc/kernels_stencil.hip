@@ -102,6 +102,69 @@ __global__ __launch_bounds__(256) void k_stencil_set(StencilSet S, const double2
   }
 }
 
+// r_s = b_s - A x_s for NR right-hand sides with per-block partial |r_s|^2,
+// each node's coefficients loaded once (per vector the arithmetic and the
+// block sums of k_stencil<1>).
+template <int NR>
+__global__ __launch_bounds__(256) void k_residual_set(ResidualSet S, const double2* __restrict__ keps,
+                                                      const double2* __restrict__ cxw,
+                                                      const double2* __restrict__ cxe,
+                                                      const double2* __restrict__ cyw,
+                                                      const double2* __restrict__ cye, int nx, int ny) {
+  int i = blockIdx.x * SBX + threadIdx.x;
+  int j = blockIdx.y * SBY + threadIdx.y;
+  double loc[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) loc[s] = 0.0;
+  if (i < nx && j < ny) {
+    long long n = (long long)j * nx + i;
+    double2 aw = cxw[i], ae = cxe[i], as = cyw[j], an = cye[j];
+    double2 ke = keps[n];
+    double2 dg = make_double2(ke.x - ((aw.x + ae.x) + (as.x + an.x)),
+                              ke.y - ((aw.y + ae.y) + (as.y + an.y)));
+#pragma unroll
+    for (int s = 0; s < NR; ++s) {
+      const double2* __restrict__ x = S.x[s];
+      double2 acc = cmul(dg, x[n]);
+      if (i > 0) acc = cfma(aw, x[n - 1], acc);
+      if (i < nx - 1) acc = cfma(ae, x[n + 1], acc);
+      if (j > 0) acc = cfma(as, x[n - nx], acc);
+      if (j < ny - 1) acc = cfma(an, x[n + nx], acc);
+      double2 r = csub(S.b[s][n], acc);
+      S.r[s][n] = r;
+      loc[s] = r.x * r.x + r.y * r.y;
+    }
+  }
+  __shared__ double red[NR][4];
+  int tid = threadIdx.y * SBX + threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) {
+    double v = wave_sum(loc[s]);
+    if ((tid & 63) == 0) red[s][tid >> 6] = v;
+  }
+  __syncthreads();
+  if (tid < NR)
+    S.partial[tid][blockIdx.y * gridDim.x + blockIdx.x] = (red[tid][0] + red[tid][1]) + (red[tid][2] + red[tid][3]);
+}
+
+// out_s[0] = the sum of the n partials of right-hand side s (blockIdx.x = s),
+// also written to host_out_s[0] when given (device-visible host memory).
+__global__ __launch_bounds__(256) void k_reduce_sum_set(ResidualSet S, int n) {
+  __shared__ double red[4];
+  const int sy = blockIdx.x;
+  const double* __restrict__ partial = S.partial[sy];
+  double s = 0.0;
+  for (int t = threadIdx.x; t < n; t += 256) s += partial[t];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double v = (red[0] + red[1]) + (red[2] + red[3]);
+    S.out[sy][0] = v;
+    if (S.host_out[sy]) S.host_out[sy][0] = v;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_reduce_sum(const double* __restrict__ partial, int n,
                                                     double* __restrict__ out) {
   __shared__ double red[4];
@@ -265,6 +328,21 @@ void launch_far_field(hipStream_t st, const double2* e, int nx, int i0, int i1, 
                       double dx, double dy, double k0, const double* phis, int nang, double2* F) {
   hipLaunchKernelGGL(k_far_field, dim3(nang), dim3(256), 0, st, e, nx, i0, i1, j0, j1, dx, dy, k0,
                      phis, F);
+}
+
+void launch_residual_set(hipStream_t st, int nr, const ResidualSet& S, const double2* keps,
+                         const double2* cxw, const double2* cxe, const double2* cyw,
+                         const double2* cye, int nx, int ny) {
+  STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 vectors per residual launch");
+  dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
+#define STF_CALL(NR) \
+  hipLaunchKernelGGL((k_residual_set<NR>), grd, blk, 0, st, S, keps, cxw, cxe, cyw, cye, nx, ny)
+  if (nr == 1) STF_CALL(1);
+  else if (nr == 2) STF_CALL(2);
+  else if (nr == 3) STF_CALL(3);
+  else STF_CALL(4);
+#undef STF_CALL
+  hipLaunchKernelGGL(k_reduce_sum_set, dim3(nr), dim3(256), 0, st, S, (int)(grd.x * grd.y));
 }
 
 void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out) {

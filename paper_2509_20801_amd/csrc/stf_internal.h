@@ -218,6 +218,20 @@ struct StencilSet {
 void launch_stencil_set(hipStream_t st, int nr, const StencilSet& S, const double2* keps,
                         const double2* cxw, const double2* cxe, const double2* cyw,
                         const double2* cye, int nx, int ny);
+// r_s = b_s - A x_s for nr (<= MAX_RHS) vectors, then out_s[0] = |r_s|^2 (and
+// host_out_s[0] when given: device-visible host memory) from per-block
+// partials (partial_s: one double per 256-node block); two launches in all.
+struct ResidualSet {
+  const double2* x[MAX_RHS] = {};
+  const double2* b[MAX_RHS] = {};
+  double2* r[MAX_RHS] = {};
+  double* partial[MAX_RHS] = {};
+  double* out[MAX_RHS] = {};
+  double* host_out[MAX_RHS] = {};
+};
+void launch_residual_set(hipStream_t st, int nr, const ResidualSet& S, const double2* keps,
+                         const double2* cxw, const double2* cxe, const double2* cyw,
+                         const double2* cye, int nx, int ny);
 // y = A x  (mode 0) or r = b - A x with per-block partial |r|^2 (mode 1).
 void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b, double2* y,
                     const double2* keps, const double2* cxw, const double2* cxe,
@@ -404,10 +418,6 @@ void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, cons
 void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* out,
                         const double* ref, int* gate, int decide);
 void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate);
-// Start of an FGMRES cycle: v = r / sqrt(nrm2), g = (sqrt(nrm2), 0, ...) of glen
-// entries, from device values only.
-void launch_cycle_start(hipStream_t st, const double2* r, const double* nrm2, double2* v,
-                        long long n, double2* g, int glen);
 // v = w / sqrt(nrm2) (skipped when skip and skip[0] != 0)
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v,
                   long long n, const int* skip = nullptr);
@@ -436,14 +446,27 @@ struct GivensSet {
   double* host_out[MAX_RHS] = {};
 };
 void launch_scale_givens_set(hipStream_t st, int nr, const GivensSet& S, long long n, int j, int ldh);
-// y = R^{-1} g (k x k upper triangular, column-major ldh).
-void launch_trisolve(hipStream_t st, const double2* H, const double2* g, double2* y, int k,
-                     int ldh);
+// The end and start of FGMRES cycles for nr (<= MAX_RHS) right-hand sides in
+// one launch each (blockIdx selects s): y_s = R_s^{-1} g_s over k_s columns
+// (H, g, y, k), x_s += Z_s y_s (Z, k, y, x), v_s = r_s / sqrt(nrm2_s) with
+// gs_s = (sqrt(nrm2_s), 0, ...) (r, nrm2, v, gs).
+struct CycleSet {
+  const double2* H[MAX_RHS] = {};
+  const double2* g[MAX_RHS] = {};
+  double2* y[MAX_RHS] = {};
+  int k[MAX_RHS] = {};
+  const double2* Z[MAX_RHS] = {};
+  double2* x[MAX_RHS] = {};
+  const double2* r[MAX_RHS] = {};
+  const double* nrm2[MAX_RHS] = {};
+  double2* v[MAX_RHS] = {};
+  double2* gs[MAX_RHS] = {};
+};
+void launch_trisolve_set(hipStream_t st, int nr, const CycleSet& S, int ldh);
+void launch_xupdate_set(hipStream_t st, int nr, const CycleSet& S, long long ld, long long n);
+void launch_cycle_start_set(hipStream_t st, int nr, const CycleSet& S, long long n, int glen);
 // y += x
 void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n);
-// x += Z y
-void launch_xupdate(hipStream_t st, const double2* Z, long long ld, int k, const double2* y,
-                    double2* x, long long n);
 
 // ---------------------------------------------------------------------------
 // Batched FGMRES (kernels_batch.hip): every launch covers all systems; sc holds
