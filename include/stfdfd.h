@@ -222,8 +222,8 @@ stf_status  stf_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, 
  * the same arguments as stf_solve.  With STF_X0_LEARNED and device arrays the
  * network's guesses (which need only the permittivity and b) are computed on a
  * second stream of the context while the factorisation runs, and the solve
- * waits for them: the network fills the GPU that the few large fronts of the
- * top tree levels leave idle.  The results equal those of the two separate
+ * waits for them: the network's memory-bound kernels share the GPU with the
+ * factorisation's leaf levels and fill what its top tree levels leave idle.  The results equal those of the two separate
  * calls.  Returns STF_EPIVOT if a pivot was perturbed and the solve itself
  * succeeded, else the solve's status. */
 stf_status  stf_factor_solve(stf_problem pb, int32_t nrhs, const double* b, double* x, int on_device,

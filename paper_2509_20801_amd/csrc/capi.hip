@@ -8,7 +8,6 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
-#include <functional>
 #include <mutex>
 #include <numeric>
 
@@ -127,7 +126,6 @@ struct stf_ctx_s {
   // order it against the main stream.
   hipStream_t side = nullptr;
   hipEvent_t side_ev[2] = {nullptr, nullptr};
-  int cus = 0;                  // compute units of the device (0 until queried)
 
   hipEvent_t get_event() {
     if (!pool.empty()) {
@@ -758,7 +756,7 @@ SweepShape tuned_sweep(stf_ctx c, const LevelArgs& a, bool fwd, size_t elem, int
 // launches.  Returns the perturbation flag (synchronises the stream).
 template <typename T>
 int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hipEvent_t e0,
-              hipEvent_t e1, const std::function<void(int)>* before_level = nullptr) {
+              hipEvent_t e1) {
   STF_REQUIRE(!fault || mf.max_depth >= 1, "the planted fault needs a tree of two levels or more");
   hipStream_t st = c->stream;
   T* fac = mf.fac.as<T>();
@@ -766,7 +764,6 @@ int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hip
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
   if (e0) HIP_CHECK(hipEventRecord(e0, st));
   for (int d = mf.max_depth; d >= 0; --d) {
-    if (before_level) (*before_level)(d);
     Timed t(c, K_FRONT_LU);
     LevelArgs la = mf.level_args(d, keps);
     if (fault && d == 1) la.fault = la.first;
@@ -821,14 +818,13 @@ struct SideStream {
 
 void fuse_prepare(stf_ctx c, Mf& mf);
 
-int factor_problem(stf_problem pb, bool fault = false,
-                   const std::function<void(int)>* before_level = nullptr) {
+int factor_problem(stf_problem pb, bool fault = false) {
   Mf& mf = pb->ensure_mf();
   const double2* keps = pb->keps.as<double2>();
   int* flag = pb->flag.as<int>();
   const int h = mf.prec == STF_C64
-                    ? factor_mf<float2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1], before_level)
-                    : factor_mf<double2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1], before_level);
+                    ? factor_mf<float2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1])
+                    : factor_mf<double2>(pb->ctx, mf, keps, flag, fault, pb->ev[0], pb->ev[1]);
   pb->fac_timed = true;
   fuse_prepare(pb->ctx, mf);
   return h;
@@ -2646,31 +2642,19 @@ stf_status batch_solve_t(stf_ctx c, int nprob, const stf_problem* probs, const i
     }
   };
   if (o.x0_mode == STF_X0_LEARNED) STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
-  // With one slot group, its guesses run on the side stream during the
-  // factorisation, from the first level of at most four fronts per compute
-  // unit on (the deep levels fill the GPU by themselves).
+  // With one slot group, its guesses run on the side stream beside the whole
+  // factorisation.
   const bool overlap = o.x0_mode == STF_X0_LEARNED && maxr <= MAX_RHS;
   std::unique_ptr<SideStream> side;
-  std::function<void(int)> hook;
   if (overlap) {
     prepare(0, maxr);
     side.reset(new SideStream(c, c->nn->ctx != c ? c->nn->ctx : nullptr));
-    if (c->cus == 0) HIP_CHECK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount, c->device));
-    int start = 0;
-    for (int d = bs.mf.max_depth; d >= 0; --d)
-      if (bs.mf.levels[d].n <= 4 * c->cus) {
-        start = d;
-        break;
-      }
-    hook = [&, start](int d) {
-      if (d != start) return;
-      side->fork();
-      side->run(guesses);
-    };
+    side->fork();
+    side->run(guesses);
   }
   // Factorisation of every problem, one launch per tree level over all fronts.
   perturbed = factor_mf<T>(c, bs.mf, bs.keps.as<double2>(), bs.flag.as<int>(), false, bs.ev[0],
-                           bs.ev[1], overlap ? &hook : nullptr) != 0;
+                           bs.ev[1]) != 0;
   if (overlap) side->join();
   const double t_fac = [&] {
     float ms = 0.f;
@@ -2836,33 +2820,21 @@ static stf_status solve_impl(stf_problem pb, int32_t nrhs, const double* b, doub
                            opts->rounds <= 1 && opts->debug_fault == 0;
       if (overlap) {
         STF_REQUIRE(c->nn, "STF_X0_LEARNED needs a network (stf_ctx_set_nn)");
+        // The guesses run beside the whole factorisation: its network kernels
+        // (memory-bound) share the GPU with the leaf levels (bound by their
+        // vector instructions and LDS) and fill what the top levels leave idle.
         SideStream side(c, c->nn->ctx != c ? c->nn->ctx : nullptr);
-        // The guesses start with the first level of at most four fronts per
-        // compute unit: the deep levels fill the GPU by themselves, the top
-        // ones leave most of it idle.
-        Mf& mf = pb->ensure_mf();
-        if (c->cus == 0) HIP_CHECK(hipDeviceGetAttribute(&c->cus, hipDeviceAttributeMultiprocessorCount,
-                                                         c->device));
-        int start = 0;
-        for (int d = mf.max_depth; d >= 0; --d)
-          if (mf.levels[d].n <= 4 * c->cus) {
-            start = d;
-            break;
+        side.fork();
+        side.run([&] {
+          for (int i = 0; i < nrhs; ++i) {
+            HIP_CHECK(hipEventRecord(pb->ev[4 + 2 * i], c->stream));
+            nn_initial_guess(pb, c->nn, reinterpret_cast<const double2*>(b) + (size_t)i * pb->N,
+                             reinterpret_cast<double2*>(x) + (size_t)i * pb->N);
+            HIP_CHECK(hipEventRecord(pb->ev[5 + 2 * i], c->stream));
           }
-        const std::function<void(int)> hook = [&](int d) {
-          if (d != start) return;
-          side.fork();
-          side.run([&] {
-            for (int i = 0; i < nrhs; ++i) {
-              HIP_CHECK(hipEventRecord(pb->ev[4 + 2 * i], c->stream));
-              nn_initial_guess(pb, c->nn, reinterpret_cast<const double2*>(b) + (size_t)i * pb->N,
-                               reinterpret_cast<double2*>(x) + (size_t)i * pb->N);
-              HIP_CHECK(hipEventRecord(pb->ev[5 + 2 * i], c->stream));
-            }
-          });
-        };
+        });
         pb->factored = false;
-        perturbed = factor_problem(pb, false, &hook) != 0;
+        perturbed = factor_problem(pb) != 0;
         pb->factored = true;
         side.join();
         const double2* bd[MAX_RHS];
