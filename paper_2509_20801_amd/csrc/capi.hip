@@ -1719,6 +1719,16 @@ void nn_forward(stf_nn nn, int B, const float* f, float* y, bool keep = true) {
     nn_dft_y(st, T, nn->ey.as<float2>(), B * W, n, M, false, Hl);
     const float* Rre = P + nn->offR[l];
     nn_mix_fwd(st, Hl, Rre, Rre + (long long)W * W * NM, B, W, NM, nn->G.as<float2>());
+    const float* Wl = P + nn->offW[l];
+    if (!keep && nn_spec_pw_ok(n, M, W)) {
+      // Inference: the x-inverse rows, then the y inverse transform fused with
+      // the pointwise part (the spectral branch is not stored).
+      float* S = nn->S.as<float>();
+      nn_spec_rows(st, nn->G.as<float2>(), nn->exi.as<float2>(), B * W, n, M, S);
+      nn_spec_pw(st, S, nn->ainv.as<float>(), 1.0f / ((float)n * (float)n), hl, Wl, Wl + W * W, npix, B, n,
+                 M, W, l < L - 1, nn->h[l + 1].as<float>());
+      continue;
+    }
     // g_plane = n^-2 [cos | -sin] (n x 4M) [Re S; Im S] (4M x n)
     if (nn_spec_inv_ok(n, M)) {
       nn_spec_inv(st, nn->G.as<float2>(), nn->exi.as<float2>(), B * W, n, M, true, nn->ainv.as<float>(),
@@ -1729,7 +1739,6 @@ void nn_forward(stf_nn nn, int B, const float* f, float* y, bool keep = true) {
       nn_gemm(st, B * W, n, n, 4 * M, nn->ainv.as<float>(), 0, 4 * M, 1, S, 4LL * M * n, n, 1,
               nn->g.as<float>(), npix, n, 1, 1.0f / ((float)n * (float)n), 0.0f);
     }
-    const float* Wl = P + nn->offW[l];
     nn_pw_fwd(st, W, W, l < L - 1, hl, Wl, Wl + W * W, nn->g.as<float>(), npix, B,
               keep ? nn->pre[l].as<float>() : nullptr, nn->h[l + 1].as<float>());
   }
@@ -3755,7 +3764,7 @@ stf_status stf_nn_forward(stf_nn nn, int32_t batch, const float* f, float* y) {
   return guard(nn->ctx, [&] {
     STF_REQUIRE(f && y, "null argument");
     nn_ensure(nn, batch);
-    nn_forward(nn, batch, f, y);
+    nn_forward(nn, batch, f, y, false);          // inference: no pre-activations kept
     HIP_CHECK(hipGetLastError());
   });
 }

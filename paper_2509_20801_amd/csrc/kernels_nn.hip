@@ -597,6 +597,102 @@ __global__ __launch_bounds__(NNT) void k_mix_bwd_r(const float2* __restrict__ H,
   dRim[t] = im;
 }
 
+// The x-inverse rows S (4M x NN per plane: Re rows, then Im rows) of the
+// compiled shape, a thread per column that loads its twiddles once for all 2M
+// rows (the first phase of k_spec_inv_t, written to memory).
+template <int NN, int MM>
+__global__ __launch_bounds__(NN) void k_spec_rows_t(const float2* __restrict__ G,
+                                                    const float2* __restrict__ ex,
+                                                    float* __restrict__ S) {
+  __shared__ float2 Gs[2 * MM * MM];
+  const int x = threadIdx.x, plane = blockIdx.x;
+  const float2* Gp = G + (long long)plane * 2 * MM * MM;
+  for (int t = x; t < 2 * MM * MM; t += NN) {
+    float2 v = Gp[t];
+    if (t % MM > 0) v = make_float2(2.0f * v.x, 2.0f * v.y);
+    Gs[t] = v;
+  }
+  __syncthreads();
+  float2 w[MM];
+#pragma unroll
+  for (int k = 0; k < MM; ++k) w[k] = ex[k * NN + x];
+  float* Sp = S + (long long)plane * 4 * MM * NN;
+#pragma unroll 4
+  for (int a = 0; a < 2 * MM; ++a) {
+    float re = 0.0f, im = 0.0f;
+#pragma unroll
+    for (int k = 0; k < MM; ++k) {
+      const float2 gv = Gs[a * MM + k];
+      re = fmaf(gv.x, w[k].x, fmaf(-gv.y, w[k].y, re));
+      im = fmaf(gv.x, w[k].y, fmaf(gv.y, w[k].x, im));
+    }
+    Sp[a * NN + x] = re;
+    Sp[(2 * MM + a) * NN + x] = im;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inference of a layer of the compiled shape (n = NN, M = MM, width WD) with
+// the spectral branch and the pointwise part in one pass: for a 16 x 16 pixel
+// block of one tile, every output channel o gets g_o = alpha Ainv S_o (the y
+// inverse transform of the rows S_o that k_dft_x_inv wrote, on the FP32 matrix
+// cores with the operand layout and summation order of k_spec_inv_t), then
+// out_o = act(bias_o + sum_i W[o, i] h_i + g_o) in the order of k_pw_fwd; g
+// never goes to memory.  Workgroup: 16 rows of one tile, four 16-column blocks
+// (a wavefront each); each lane ends with 4 consecutive pixels of one row.
+// ---------------------------------------------------------------------------
+template <int NN, int MM, int WD, bool ACT>
+__global__ __launch_bounds__(256) void k_spec_pw_t(const float* __restrict__ S,
+                                                   const float* __restrict__ ainv, float alpha,
+                                                   const float* __restrict__ hin,
+                                                   const float* __restrict__ Wm,
+                                                   const float* __restrict__ bias, long long npix,
+                                                   float* __restrict__ out) {
+  typedef float V4 __attribute__((ext_vector_type(4)));
+  constexpr int K = 4 * MM;
+  static_assert(NN % 64 == 0 && K % 4 == 0, "four 16-column blocks per workgroup");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int b = blockIdx.z, yb = blockIdx.y, xb = blockIdx.x * 4 + wv;
+  // the input channels of this lane's four pixels first: their loads overlap
+  // the products below
+  const long long pix = (long long)(yb * 16 + l16) * NN + xb * 16 + 4 * lk;
+  float4 hv[WD];
+#pragma unroll
+  for (int i = 0; i < WD; ++i) hv[i] = *reinterpret_cast<const float4*>(hin + ((long long)b * WD + i) * npix + pix);
+  float av[K / 4];
+  const float* ar = ainv + (yb * 16 + l16) * K + lk;
+#pragma unroll
+  for (int s4 = 0; s4 < K / 4; ++s4) av[s4] = ar[4 * s4];
+  V4 acc[WD];
+#pragma unroll
+  for (int o = 0; o < WD; ++o) {
+    const float* sp = S + ((long long)b * WD + o) * K * NN + (long long)lk * NN + xb * 16 + l16;
+    float bv[K / 4];
+#pragma unroll
+    for (int s4 = 0; s4 < K / 4; ++s4) bv[s4] = sp[(long long)4 * s4 * NN];
+    acc[o] = V4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s4 = 0; s4 < K / 4; ++s4) acc[o] = __builtin_amdgcn_mfma_f32_16x16x4f32(bv[s4], av[s4], acc[o], 0, 0, 0);
+  }
+#pragma unroll
+  for (int o = 0; o < WD; ++o) {
+    float r[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      float sacc = bias[o];
+#pragma unroll
+      for (int i = 0; i < WD; ++i) {
+        const float hi = v == 0 ? hv[i].x : v == 1 ? hv[i].y : v == 2 ? hv[i].z : hv[i].w;
+        sacc = fmaf(Wm[o * WD + i], hi, sacc);
+      }
+      sacc += alpha * acc[o][v];
+      r[v] = ACT ? gelu_f(sacc) : sacc;
+    }
+    *reinterpret_cast<float4*>(out + ((long long)b * WD + o) * npix + pix) = make_float4(r[0], r[1], r[2], r[3]);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Pointwise channel mixing, one thread per pixel:
 //   pre[o] = sum_i Wm[o, i] in[i] + bias[o] (+ add[o]);  out = ACT ? gelu(pre) : pre.
@@ -926,6 +1022,28 @@ void nn_spec_inv(hipStream_t st, const float2* G, const float2* ex, int planes, 
   }
   hipLaunchKernelGGL(k_spec_inv, dim3(planes), dim3(256), lds, st, G, ex, n, M, weighted ? 1 : 0, ainv,
                      alpha, beta, out, npix);
+}
+
+bool nn_spec_pw_ok(int n, int M, int W) { return n == 256 && M == 16 && W == 16; }
+
+void nn_spec_rows(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M, float* S) {
+  if (n != 256 || M != 16) throw Error(STF_EINVAL, "nn: x-inverse rows of the compiled shape only");
+  hipLaunchKernelGGL((k_spec_rows_t<256, 16>), dim3(planes), dim3(256), 0, st, G, ex, S);
+}
+
+void nn_spec_pw(hipStream_t st, const float* S, const float* ainv, float alpha, const float* hin,
+                const float* Wm, const float* bias, long long npix, int B, int n, int M, int W, bool act,
+                float* out) {
+  if (!nn_spec_pw_ok(n, M, W) || npix != (long long)n * n ||
+      (reinterpret_cast<uintptr_t>(hin) & 15) != 0 || (reinterpret_cast<uintptr_t>(out) & 15) != 0)
+    throw Error(STF_EINVAL, "nn: fused spectral + pointwise layer shape or alignment");
+  const dim3 grid(256 / 64, 256 / 16, B);
+  if (act)
+    hipLaunchKernelGGL((k_spec_pw_t<256, 16, 16, true>), grid, dim3(256), 0, st, S, ainv, alpha, hin, Wm,
+                       bias, npix, out);
+  else
+    hipLaunchKernelGGL((k_spec_pw_t<256, 16, 16, false>), grid, dim3(256), 0, st, S, ainv, alpha, hin, Wm,
+                       bias, npix, out);
 }
 
 void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,

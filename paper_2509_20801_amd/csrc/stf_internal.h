@@ -529,6 +529,15 @@ void nn_mix_bwd(hipStream_t st, const float2* H, const float2* dG, const float* 
 bool nn_width_supported(int cin, int w);
 void nn_pw_fwd(hipStream_t st, int ci, int co, bool act, const float* in, const float* Wm,
                const float* bias, const float* add, long long npix, int B, float* pre, float* out);
+// Inference of one layer of the compiled shape (n = 256, M = 16, width 16):
+// out = act(W h + bias + alpha Ainv S) per plane, S the rows k_dft_x_inv wrote
+// (4M x n per plane), without storing the spectral branch.
+bool nn_spec_pw_ok(int n, int M, int W);
+// The weighted x-inverse rows (4M x n per plane) of the compiled shape.
+void nn_spec_rows(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M, float* S);
+void nn_spec_pw(hipStream_t st, const float* S, const float* ainv, float alpha, const float* hin,
+                const float* Wm, const float* bias, long long npix, int B, int n, int M, int W, bool act,
+                float* out);
 int nn_pw_bwd_blocks();
 void nn_pw_bwd(hipStream_t st, int ci, int co, bool act, const float* dout, const float* pre,
                const float* in, const float* Wm, long long npix, int B, float* dpre, float* din,
