@@ -161,13 +161,16 @@ def stationary_form(stf, torch, ctx, w, prec, tol, max_rounds):
 # that holds them (a PMC summary is valid only for the source it was taken on).
 CLASS_OF = [("k_fwd_", "sweep_fwd"), ("k_bwd_", "sweep_bwd"), ("k_factor_", "front_lu"),
             ("k_stencil", "stencil"), ("k_stage_residual", "stencil"), ("k_scatter", "scatter"),
-            ("k_stage_scatter", "scatter"), ("k_zero", "scatter"), ("k_mdot", "arnoldi"),
+            ("k_stage_scatter", "scatter"), ("k_zero", "scatter"), ("k_residual_set", "stencil"),
+            ("k_reduce_sum_set", "stencil"), ("k_xupdate", "update"), ("k_trisolve", "update"),
+            ("k_cycle_start", "update"), ("k_scale_givens", "update"), ("k_mdot", "arnoldi"),
             ("k_mupdate", "arnoldi"), ("k_norm_reduce", "arnoldi"), ("k_hacc", "arnoldi"),
             ("k_gs", "arnoldi"), ("k_gemm", "nn"), ("k_pw_", "nn"), ("k_dft_", "nn"),
             ("k_mix_", "nn"), ("k_nn_", "nn"), ("k_spec_", "nn")]
 SOURCE_OF = {"sweep_fwd": "kernels_front.hip", "sweep_bwd": "kernels_front.hip",
              "front_lu": "kernels_front.hip", "scatter": "kernels_front.hip",
              "stencil": "kernels_stencil.hip", "arnoldi": "kernels_krylov.hip",
+             "update": "kernels_krylov.hip",
              "nn": "kernels_nn.hip"}
 PMC_SUMMARY = os.path.join(ROOT, "profiles", "pmc_traffic_metasurface_1064.md")
 COPY_BYTES = 1 << 29          # the calibration copy: 512 MiB read and 512 MiB written
