@@ -754,21 +754,47 @@ SweepShape tuned_sweep(stf_ctx c, const LevelArgs& a, bool fwd, size_t elem, int
 // column carries fill in the update rows after assembly, so the perturbation
 // has a nonzero column maximum to scale.  e0 / e1 (may be null) bracket the
 // launches.  Returns the perturbation flag (synchronises the stream).
+// Launches level d of the factorisation with shape sh.  A level on the
+// one-wavefront LDS kernel goes in runs of fronts of similar order (instances
+// are stored largest first within a level; a run ends where the order falls
+// below 85% of its first), each run with LDS for its own largest front, so
+// that the smaller fronts fit more workgroups per CU.
+template <typename T>
+void factor_level(hipStream_t st, const Mf& mf, int d, const double2* keps, int* flag, double tau, bool fault,
+                  FactorShape sh) {
+  LevelArgs la = mf.level_args(d, keps);
+  if (fault && d == 1) la.fault = la.first;
+  const FactorShape s = sh.kind == 0 ? factor_default(la, sizeof(T)) : sh;
+  T* fac = mf.fac.as<T>();
+  if (s.kind != 1) {
+    launch_front_factor<T>(st, la, fac, mf.lpk.as<T>(), mf.upk.as<T>(), mf.piv.as<int>(), flag, tau, s);
+    return;
+  }
+  const int off = mf.levels[d].off, n = mf.levels[d].n;
+  for (int i = 0; i < n;) {
+    const int m0 = mf.h_fronts[off + i].p + mf.h_fronts[off + i].q;
+    int j = i + 1;
+    while (j < n && 20 * (mf.h_fronts[off + j].p + mf.h_fronts[off + j].q) >= 17 * m0) ++j;
+    LevelArgs run = la;
+    run.first = off + i;
+    run.nlevel = j - i;
+    run.max_m = m0;
+    launch_front_factor<T>(st, run, fac, mf.lpk.as<T>(), mf.upk.as<T>(), mf.piv.as<int>(), flag, tau, s);
+    i = j;
+  }
+}
+
 template <typename T>
 int factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, bool fault, hipEvent_t e0,
               hipEvent_t e1) {
   STF_REQUIRE(!fault || mf.max_depth >= 1, "the planted fault needs a tree of two levels or more");
   hipStream_t st = c->stream;
-  T* fac = mf.fac.as<T>();
   HIP_CHECK(hipMemsetAsync(flag, 0, sizeof(int), st));
   double tau = sizeof(T) == 16 ? 1e-10 : 1e-5;
   if (e0) HIP_CHECK(hipEventRecord(e0, st));
   for (int d = mf.max_depth; d >= 0; --d) {
     Timed t(c, K_FRONT_LU);
-    LevelArgs la = mf.level_args(d, keps);
-    if (fault && d == 1) la.fault = la.first;
-    launch_front_factor<T>(st, la, fac, mf.lpk.as<T>(), mf.upk.as<T>(), mf.piv.as<int>(), flag, tau,
-                           tuned_factor(c, la, sizeof(T)));
+    factor_level<T>(st, mf, d, keps, flag, tau, fault, tuned_factor(c, mf.level_args(d, keps), sizeof(T)));
   }
   if (e1) HIP_CHECK(hipEventRecord(e1, st));
   HIP_CHECK(hipGetLastError());
@@ -1225,8 +1251,7 @@ void tune_factor_mf(stf_ctx c, Mf& mf, const double2* keps, int* flag, int reps,
       HIP_CHECK(hipEventRecord(ev.e[0], st));
       for (int d = mf.max_depth, i = 1; d >= 0; --d, ++i) {
         const size_t k = std::min(t, cand[d].size() - 1);
-        launch_front_factor<T>(st, mf.level_args(d, keps), mf.fac.as<T>(), mf.lpk.as<T>(), mf.upk.as<T>(),
-                               mf.piv.as<int>(), flag, tau, cand[d][k]);
+        factor_level<T>(st, mf, d, keps, flag, tau, false, cand[d][k]);
         HIP_CHECK(hipEventRecord(ev.e[i], st));
       }
       HIP_CHECK(hipEventSynchronize(ev.e[L]));
