@@ -1115,9 +1115,10 @@ LevelArgs stage_level_args(const Mf& mf, const SweepPlan& sp, int t, int d, cons
   return la;
 }
 
-// One application of the staged order for the right-hand sides of r:
-// z_s = 0, then for every stage r_s = v_s - A z_s on its own boxes (skipped for
-// the first stage, where z = 0), its sweeps, z_s += its full local fields.
+// One application of the staged order for the right-hand sides of r: for
+// every stage r_s = v_s - A z_s on its own boxes (skipped for the first stage,
+// where z = 0), its sweeps, z_s += its full local fields (the first stage's
+// sum writes every node of z_s, so no zero fill comes first).
 // keps / gc: the set's concatenated node permittivity and coupling arrays;
 // rbuf: one global vector per slot (rstride apart) for the stage residuals.
 // code: subtree choice (16 D + T) for the deep levels of every stage, or -1
@@ -1126,12 +1127,11 @@ LevelArgs stage_level_args(const Mf& mf, const SweepPlan& sp, int t, int d, cons
 template <typename T>
 void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u,
                   const double2* keps, const double2* gc, double2* rbuf, long long rstride,
-                  long long zlen, bool timed, const int* pact = nullptr, int code = -1) {
+                  bool timed, const int* pact = nullptr, int code = -1) {
   hipStream_t st = c->stream;
   stf_ctx tc = timed ? c : nullptr;
   r.vec_stride = mf.vec_elems;
   r.u_stride = mf.u_elems;
-  launch_zero_set(st, r, zlen);
   const T* lpk = mf.lpk.as<T>();
   const int* sl = sp.slist.as<int>();
   const std::vector<std::unique_ptr<FusePlan>>* sfz = code >= 0 ? &stage_fuse(mf, sp, code, st) : nullptr;
@@ -1170,9 +1170,14 @@ void sweep_launch(stf_ctx c, Mf& mf, const SweepPlan& sp, RhsSet r, T* vec, T* u
                             u, rr);
     }
     Timed tm(tc, K_SCATTER);
-    launch_stage_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.scat.as<ScatDev>(), mf.cover_x.as<int4>(),
-                            mf.cover_y.as<int4>(), sl, sf, sc, mf.max_oxl, mf.max_oyl,
-                            sp.inst.as<int>() + (size_t)t * mf.nsub, pact, r);
+    if (t == 0)
+      launch_stage_scatter_first<T>(st, u, mf.subs.as<SubDev>(), mf.cover_x.as<int4>(), mf.cover_y.as<int4>(),
+                                    mf.scat.as<ScatDev>(), mf.nprob, mf.max_nx, mf.max_ny,
+                                    sp.inst.as<int>(), pact, r);
+    else
+      launch_stage_scatter<T>(st, u, mf.subs.as<SubDev>(), mf.scat.as<ScatDev>(), mf.cover_x.as<int4>(),
+                              mf.cover_y.as<int4>(), sl, sf, sc, mf.max_oxl, mf.max_oyl,
+                              sp.inst.as<int>() + (size_t)t * mf.nsub, pact, r);
   }
 }
 
@@ -1433,7 +1438,7 @@ void tune_staged_mf(stf_ctx c, Mf& mf, int nr, long long ntot, const double2* ke
         if (!ok) continue;
       }
       HIP_CHECK(hipEventRecord(fe.e[0], st));
-      sweep_launch<T>(c, mf, sp, r, mf.vec.as<T>(), mf.u.as<T>(), keps, gc, rb.as<double2>(), ntot, ntot, false,
+      sweep_launch<T>(c, mf, sp, r, mf.vec.as<T>(), mf.u.as<T>(), keps, gc, rb.as<double2>(), ntot, false,
                       nullptr, opts[k]);
       HIP_CHECK(hipEventRecord(fe.e[1], st));
       HIP_CHECK(hipEventSynchronize(fe.e[1]));
@@ -1523,7 +1528,7 @@ void sweep_problem(stf_problem pb, const RhsSet& r, int order) {
   pb->ksr.alloc((size_t)pb->N * sizeof(double2) * r.nr);
   const int code = staged_fuse_for(pb->ctx, mf, sp, sizeof(T), r.nr, order, true);
   sweep_launch<T>(pb->ctx, mf, sp, r, mf.vec.as<T>(), mf.u.as<T>(), pb->keps.as<double2>(),
-                  pb->gcoef.as<double2>(), pb->ksr.as<double2>(), pb->N, pb->N, true, nullptr, code);
+                  pb->gcoef.as<double2>(), pb->ksr.as<double2>(), pb->N, true, nullptr, code);
 }
 
 // One preconditioner application for the right-hand sides of r in `order`.
@@ -2543,7 +2548,7 @@ void batch_cycle(stf_ctx c, BatchState& b, double tol, int max_iter, int order) 
       const SweepPlan& sp = sweep_plan(b.mf, order, st);
       const int code = staged_fuse_for(c, b.mf, sp, sizeof(T), rs.nr, order, false);
       sweep_launch<T>(c, b.mf, sp, rs, b.mf.vec.as<T>(), b.mf.u.as<T>(), b.keps.as<double2>(),
-                      b.gc.as<double2>(), b.RS.as<double2>(), b.ntot, b.ntot, false, b.pact.as<int>(), code);
+                      b.gc.as<double2>(), b.RS.as<double2>(), b.ntot, false, b.pact.as<int>(), code);
     }
     launch_bstencil(st, 0, Z + (long long)j * Tn, nullptr, W, b.keps.as<double2>(), b.gc.as<double2>(),
                     sys, b.tsys.as<int>(), b.ntiles, act, nullptr);

@@ -1644,14 +1644,51 @@ __global__ __launch_bounds__(256) void k_stage_scatter(const T* __restrict__ u,
   }
 }
 
-__global__ __launch_bounds__(256) void k_zero(double2* __restrict__ p, long long n) {
-  for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256)
-    p[t] = make_double2(0.0, 0.0);
+// The first stage's sum over the whole grid (blockIdx.z = problem): z_s =
+// the sum of the local fields of the stage's members covering the node, in
+// the fixed order of k_stage_scatter (0 where none covers it), so that z needs
+// no zero fill before the application.
+template <typename T, int NR>
+__global__ __launch_bounds__(256) void k_stage_scatter_first(const T* __restrict__ u,
+                                                             const SubDev* __restrict__ subs,
+                                                             const int4* __restrict__ cover_x,
+                                                             const int4* __restrict__ cover_y,
+                                                             const ScatDev* __restrict__ probs,
+                                                             const int* __restrict__ inst,
+                                                             const int* __restrict__ pact, RhsSet rs) {
+  const ScatDev P = probs[blockIdx.z];
+  const int gx = blockIdx.x * 64 + threadIdx.x;
+  const int gy = blockIdx.y * 4 + threadIdx.y;
+  if (gx >= P.nx || gy >= P.ny) return;
+  const int4 cx = cover_x[P.cx_off + gx], cy = cover_y[P.cy_off + gy];
+  const int kys[2] = {cy.x, cy.z}, uys[2] = {cy.y, cy.w};
+  const int kxs[2] = {cx.x, cx.z}, txs[2] = {cx.y, cx.w};
+  double2 acc[NR];
+#pragma unroll
+  for (int s = 0; s < NR; ++s) acc[s] = make_double2(0.0, 0.0);
+  const bool active = !pact || pact[blockIdx.z] != 0;   // a converged problem's z stays 0
+#pragma unroll
+  for (int b = 0; b < 2 && active; ++b)
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      if (kys[b] < 0 || kxs[c] < 0) continue;
+      const int kk = P.sub0 + kys[b] * P.px + kxs[c];
+      if (inst[kk] == 0) continue;
+      const SubDev& Q = subs[kk];
+      const long long o = Q.u_off + (long long)uys[b] * Q.nxl + txs[c];
+#pragma unroll
+      for (int s = 0; s < NR; ++s) {
+        const double2 v = to_d2(u[s * rs.u_stride + o]);
+        acc[s].x += v.x;
+        acc[s].y += v.y;
+      }
+    }
+  const long long n = P.gbase + (long long)gy * P.nx + gx;
+#pragma unroll
+  for (int s = 0; s < NR; ++s) rs.z[s][n] = acc[s];
 }
 
-// z_s = 0 for the right-hand sides of rs (blockIdx.y = s).
-__global__ __launch_bounds__(256) void k_zero_set(RhsSet rs, long long n) {
-  double2* p = rs.z[blockIdx.y];
+__global__ __launch_bounds__(256) void k_zero(double2* __restrict__ p, long long n) {
   for (long long t = (long long)blockIdx.x * 256 + threadIdx.x; t < n; t += (long long)gridDim.x * 256)
     p[t] = make_double2(0.0, 0.0);
 }
@@ -2172,12 +2209,17 @@ void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const 
 #undef STF_CALL
 }
 
-void launch_zero_set(hipStream_t st, const RhsSet& r, long long n) {
+template <typename T>
+void launch_stage_scatter_first(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
+                                const int4* cover_y, const ScatDev* probs, int nprob, int max_nx,
+                                int max_ny, const int* inst, const int* pact, const RhsSet& r) {
   check_rhs(r);
-  long long g = (n + 255) / 256;
-  if (g > 8192 / r.nr) g = 8192 / r.nr;
-  if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_zero_set, dim3((unsigned)g, r.nr), dim3(256), 0, st, r, n);
+  dim3 blk(64, 4), grd((max_nx + 63) / 64, (max_ny + 3) / 4, nprob);
+#define STF_CALL(NR)                                                                              \
+  hipLaunchKernelGGL((k_stage_scatter_first<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, probs, \
+                     inst, pact, r)
+  STF_NR_DISPATCH(r.nr, STF_CALL)
+#undef STF_CALL
 }
 
 void launch_zero(hipStream_t st, double2* p, long long n) {
@@ -2212,7 +2254,10 @@ void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsu
                                        double*);                                                \
   template void launch_stage_scatter<T>(hipStream_t, const T*, const SubDev*, const ScatDev*,   \
                                         const int4*, const int4*, const int*, int, int, int, int,\
-                                        const int*, const int*, const RhsSet&);
+                                        const int*, const int*, const RhsSet&);                 \
+  template void launch_stage_scatter_first<T>(hipStream_t, const T*, const SubDev*, const int4*, \
+                                              const int4*, const ScatDev*, int, int, int,        \
+                                              const int*, const int*, const RhsSet&);
 STF_INST(double2)
 STF_INST(float2)
 

@@ -353,8 +353,14 @@ void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const 
                           const int4* cover_x, const int4* cover_y, const int* slist, int sfirst,
                           int scount, int maxw, int maxh, const int* inst, const int* pact,
                           const RhsSet& r);
+// The first stage's sum written over every node of every problem (members by
+// inst, as launch_stage_scatter adds them; 0 where none covers a node): no
+// zero fill of z is needed before it.
+template <typename T>
+void launch_stage_scatter_first(hipStream_t st, const T* u, const SubDev* subs, const int4* cover_x,
+                                const int4* cover_y, const ScatDev* probs, int nprob, int max_nx,
+                                int max_ny, const int* inst, const int* pact, const RhsSet& r);
 void launch_zero(hipStream_t st, double2* p, long long n);
-void launch_zero_set(hipStream_t st, const RhsSet& r, long long n);   // every r.z[s]
 // Eq. (20): per_sub[k] = |u_k| on Omega_k outside I_k (nsub subdomains), out[0] = their sum.
 template <typename T>
 void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsub, double* per_sub,
