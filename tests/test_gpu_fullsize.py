@@ -8,6 +8,13 @@ the configuration-1 physics check against the Mie series.
   residual is recomputed on the CPU with the oracle's operator.
   Bars: complex64 fronts at FGMRES rel-res 1e-10 -> 1e-8 relative L2 over the samples;
   complex128 fronts at rel-res 1e-12 -> 1e-10.
+* The same grid with the benchmark's four current sheets, element by element over the
+  whole field: the oracle's direct FP64 solution of all four (one SuperLU
+  factorisation, about 40 s on the host) against the headline form (complex64
+  fronts, the four right-hand sides swept together in the two-colour order, restart
+  3, rel-res 1e-10 -> 1e-8 relative L2 per right-hand side, and every node within
+  1e-8 of the field's largest magnitude) and the plain form (complex128 fronts, one
+  right-hand side, rel-res 1e-12 -> 1e-10).
 * Configuration 1 (cylinder, TF/SF, 2 x 2): the GPU field equals the oracle to 1e-10 and
   is within the discretisation error of the Mie series (13% at 20 points per
   wavelength, 10 inside the eps = 4 cylinder; second order pinned in
@@ -80,6 +87,36 @@ def test_metasurface_full_size_matches_direct_solve(stf, ctx, metasurface, prec,
     err = np.linalg.norm(xh[idx] - xr) / np.linalg.norm(xr)
     assert err <= bar, err
     assert abs(np.linalg.norm(xh) / ref["norm"] - 1) <= bar
+    pb.close()
+
+
+@pytest.fixture(scope="module")
+def metasurface4():
+    w = workloads.configs.metasurface_sheet(nrhs=4)
+    A = fdfd.global_matrix(w.params(), w.eps_cells)
+    B = w.b.reshape(w.b.shape[0], -1).T
+    X = fdfd.solve_direct(A, B).T.reshape(w.b.shape)
+    return w, A, X
+
+
+@pytest.mark.parametrize("form", ["headline", "plain"])
+def test_metasurface_whole_field_matches_direct_solve(stf, ctx, metasurface4, form):
+    import torch
+    w, A, X = metasurface4
+    eps = torch.from_numpy(w.eps_cells).cuda()
+    if form == "headline":
+        prec, tol, bar, nr, kw = 1, 1e-10, 1e-8, 4, dict(restart=3, order="checker")
+    else:
+        prec, tol, bar, nr, kw = 0, 1e-12, 1e-10, 1, dict(restart=3, order="checker")
+    pb = stf.Problem(ctx, _prm(w, front_prec=prec), eps)
+    b = torch.from_numpy(np.ascontiguousarray(w.b[:nr])).cuda()
+    x, info = pb.factor_solve(b, tol=tol, max_iter=600, **kw)
+    xh = x.cpu().numpy()
+    for r in range(nr):
+        assert info[r]["status"] == 0 and info[r]["relres_true"] <= tol
+        assert fdfd.relres(A, xh[r].ravel(), w.b[r].ravel()) <= 1.5 * tol
+        assert fdfd.rel_l2(xh[r], X[r]) <= bar, (r, fdfd.rel_l2(xh[r], X[r]))
+        assert np.abs(xh[r] - X[r]).max() <= bar * np.abs(X[r]).max()
     pb.close()
 
 
