@@ -17,7 +17,10 @@ Network (hyper-parameters in NNConfig; n x n tiles, W channels, M modes):
     Finv    g[y, x] = n^-2 Re sum_{a,k} w_k G[a, k] exp(+2 pi i (ky(a) y + k x) / n),
             w_0 = 1, w_k = 2 (k >= 1): the real field of the truncated
             Hermitian half-spectrum, equal to numpy.fft.irfft2 of it.
-Loss: mean over samples of |y - t|^2 / |t|^2.  Optimiser: Adam.
+Loss: mean over samples of |y - t|^2 / |t|^2.  Optimiser: Adam on an FP32 master
+copy of the parameters; the network computes with that copy rounded to BF16
+(quantize_bf16), so its forward and gradients are evaluated at the rounded
+weights (the callers pass them to forward/backward).
 
 Gradients use the convention grad = dL/dRe + i dL/dIm for complex quantities:
   through Finv:   dG = w_k n^-2 Ftrunc(dg)
@@ -164,6 +167,18 @@ def backward(cfg, p, cache, dy):
     g["P_b"] = dh.sum(axis=(0, 2, 3))
     df = np.einsum("oi,boyx->biyx", p["P_w"], dh)
     return g, df
+
+
+def quantize_bf16(flat):
+    """The weights the network computes with: every parameter rounded to FP32
+    (the master copy's format), then to BF16, the upper 16 bits of an IEEE
+    binary32 (8 exponent bits, 7 fraction bits), by round to nearest with ties
+    to even; returned as float64 (exactly representable).  Finite inputs only."""
+    u = np.ascontiguousarray(np.asarray(flat, dtype=np.float64).astype(np.float32)).view(np.uint32)
+    u = u.astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    r = ((u + np.uint64(0x7FFF) + lsb) & np.uint64(0xFFFF0000)).astype(np.uint32)
+    return r.view(np.float32).astype(np.float64)
 
 
 def adam(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):

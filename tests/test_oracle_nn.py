@@ -8,7 +8,10 @@
 * GELU: odd-part identity gelu(x) - gelu(-x) = x and its derivative by
   finite differences; with one layer and no activation the network is affine;
 * Adam: the first step moves every parameter by lr * sign(grad) (closed form);
-* blending: constant tile predictions give that constant on the interior.
+* blending: constant tile predictions give that constant on the interior;
+* BF16 rounding: values with 8 significant bits are fixed points, exact ties go to
+  the even neighbour (hand-computed cases), every result is within 2^-8 relative,
+  and the rounding equals torch's FP32 -> bfloat16 conversion (library).
 """
 import numpy as np
 import pytest
@@ -128,3 +131,23 @@ def test_training_tile_shape():
     assert abs(w.eps_cells[20 + r, 150].real - 2.13) < 1e-12
     w2 = learned.tile_workload(50000, subcells=4)
     assert np.array_equal(w.eps_cells, w2.eps_cells) and np.array_equal(w.b, w2.b)
+
+
+def test_bf16_rounding():
+    exact = np.array([0.0, 1.0, -2.5, 0.15625, 3.0 * 2.0 ** -20, 255.0, -1.0 / 128])
+    assert np.array_equal(nn.quantize_bf16(exact), exact)
+    one = 1.0
+    # halfway between 1 and 1 + 2^-7: the even neighbour is 1
+    assert nn.quantize_bf16([one + 2.0 ** -8])[0] == one
+    # halfway between 1 + 2^-7 (odd last bit) and 1 + 2^-6: the even one is 1 + 2^-6
+    assert nn.quantize_bf16([one + 3 * 2.0 ** -8])[0] == one + 2.0 ** -6
+    # just above the half: rounds up; just below: down
+    assert nn.quantize_bf16([one + 2.0 ** -8 + 2.0 ** -20])[0] == one + 2.0 ** -7
+    assert nn.quantize_bf16([one + 2.0 ** -8 - 2.0 ** -20])[0] == one
+    assert nn.quantize_bf16([-(one + 3 * 2.0 ** -8)])[0] == -(one + 2.0 ** -6)
+    x = np.random.default_rng(3).standard_normal(20000) * np.exp(np.random.default_rng(4).uniform(-20, 20, 20000))
+    q = nn.quantize_bf16(x)
+    assert np.all(np.abs(q - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-6))   # unit roundoff, 8 bits
+    torch = pytest.importorskip("torch")
+    ref = torch.from_numpy(x.astype(np.float32)).to(torch.bfloat16).to(torch.float64).numpy()
+    assert np.array_equal(q, ref)
