@@ -413,7 +413,7 @@ int32_t     stf_tune_count(stf_ctx ctx);
 stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape, double* ms);
 
 /* ---- learned warm start -------------------------------------------------
- * A spectral neural operator on n x n tiles (FP32): pointwise lift of the cin
+ * A spectral neural operator on n x n tiles: pointwise lift of the cin
  * input features to W channels, L layers h <- act(K h + W_l h + c_l) with the
  * spectral convolution K h = Finv(R . Ftrunc(h)) over the modes kx in [0, M),
  * ky in [-M, M) (complex weights R per mode and channel pair), GELU (tanh
@@ -421,8 +421,13 @@ stf_status  stf_tune_entry(stf_ctx ctx, int32_t i, int32_t* key, int32_t* shape,
  * real and imaginary part of the field.  Features of a tile:
  * ((Re eps_node - 1) / 4, Re b, Im b).  Parameters form one flat FP32 vector:
  * P_w (W, cin), P_b (W), per layer Re R (W, W, 2M, M), Im R, W_l (W, W),
- * c_l (W), then Q_w (2, W), Q_b (2).  Training minimises the mean over tiles
- * of |y - t|^2 / |t|^2 with Adam (beta1 0.9, beta2 0.999, eps 1e-8).
+ * c_l (W), then Q_w (2, W), Q_b (2).  The library keeps that vector as an FP32
+ * master copy (get/set_params, the Adam step) and computes with the master
+ * copy rounded to BF16 (round to nearest, ties to even: the weights), refreshed
+ * after every change; activations, transforms and every sum are FP32 (the
+ * transforms on the FP32 matrix cores), and gradients are taken at the BF16
+ * weights.  Training minimises the mean over tiles of |y - t|^2 / |t|^2 with
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8) on the master copy.
  * Tensors are planar [tile][channel][y][x], x fastest. */
 typedef struct stf_nn_s* stf_nn;
 typedef struct {

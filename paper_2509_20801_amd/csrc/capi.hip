@@ -633,6 +633,7 @@ struct stf_nn_s {
   long long offP = 0, offQ = 0;
   std::vector<long long> offR, offW;   // per layer: Re R (Im R follows), W_l (c_l follows)
   DBuf par, grad, am, av;
+  DBuf wq;                             // par rounded to BF16: the weights the kernels read
   DBuf exT;      // (n, 2M) floats: [cos | -sin](2 pi k x / n), the forward x transform
   DBuf ey;       // (2M, n) float2: exp(-2 pi i ky(a) y / n)
   DBuf exi;      // (M, n) float2: exp(+2 pi i k x / n)
@@ -1665,6 +1666,7 @@ void nn_setup(stf_nn nn) {
   nn->offQ = o;
   const size_t pb = (size_t)nn->np * sizeof(float);
   nn->par.alloc(pb);
+  nn->wq.alloc(pb);
   nn->grad.alloc(pb);
   nn->am.alloc(pb);
   nn->av.alloc(pb);
@@ -1735,7 +1737,7 @@ void nn_forward(stf_nn nn, int B, const float* f, float* y, bool keep = true) {
   Timed t(nn->ctx, K_NN);
   const int n = c.n, W = c.width, M = c.modes, L = c.layers, NM = nn->NM();
   const long long npix = nn->npix();
-  const float* P = nn->par.as<float>();
+  const float* P = nn->wq.as<float>();              // the BF16 weights
   float* h0 = nn->h[0].as<float>();
   nn_pw_fwd(st, c.cin, W, false, f, P + nn->offP, P + nn->offP + W * c.cin, nullptr, npix, B,
             nullptr, h0);
@@ -1783,7 +1785,7 @@ void nn_backward(stf_nn nn, int B, const float* f, const float* dy) {
   Timed t(nn->ctx, K_NN);
   const int n = c.n, W = c.width, M = c.modes, L = c.layers, NM = nn->NM();
   const long long npix = nn->npix();
-  const float* P = nn->par.as<float>();
+  const float* P = nn->wq.as<float>();              // gradients at the BF16 weights
   float* Gd = nn->grad.as<float>();
   float* part = nn->pwpart.as<float>();
   float* dh = nn->dh.as<float>();
@@ -3743,6 +3745,7 @@ stf_status stf_nn_create(stf_ctx ctx, const stf_nn_config* cfg, const float* par
     for (long long i = 0; i < nn->np; ++i)
       STF_REQUIRE(std::isfinite(params[i]), "nn: non-finite parameter");
     HIP_CHECK(hipMemcpyAsync(nn->par.p, params, pb, hipMemcpyHostToDevice, ctx->stream));
+    nn_quantize_bf16(ctx->stream, nn->par.as<float>(), nn->wq.as<float>(), nn->np);
     HIP_CHECK(hipMemsetAsync(nn->am.p, 0, pb, ctx->stream));
     HIP_CHECK(hipMemsetAsync(nn->av.p, 0, pb, ctx->stream));
     HIP_CHECK(hipMemsetAsync(nn->grad.p, 0, pb, ctx->stream));
@@ -3783,6 +3786,7 @@ stf_status stf_nn_set_params(stf_nn nn, const float* params) {
     const size_t pb = (size_t)nn->np * sizeof(float);
     hipStream_t st = nn->ctx->stream;
     HIP_CHECK(hipMemcpyAsync(nn->par.p, params, pb, hipMemcpyHostToDevice, st));
+    nn_quantize_bf16(st, nn->par.as<float>(), nn->wq.as<float>(), nn->np);
     HIP_CHECK(hipMemsetAsync(nn->am.p, 0, pb, st));
     HIP_CHECK(hipMemsetAsync(nn->av.p, 0, pb, st));
     HIP_CHECK(hipStreamSynchronize(st));
@@ -3825,7 +3829,7 @@ stf_status stf_nn_train_step(stf_nn nn, int32_t batch, const float* f, const flo
     STF_REQUIRE(std::isfinite(*loss), "nn: non-finite loss");
     Timed tm(nn->ctx, K_NN);
     nn_adam(nn->ctx->stream, nn->par.as<float>(), nn->grad.as<float>(), nn->am.as<float>(),
-            nn->av.as<float>(), nn->np, lr, step, 0.9, 0.999, 1e-8);
+            nn->av.as<float>(), nn->np, lr, step, 0.9, 0.999, 1e-8, nn->wq.as<float>());
     HIP_CHECK(hipGetLastError());
   });
 }

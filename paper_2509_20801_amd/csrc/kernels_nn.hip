@@ -870,11 +870,27 @@ __global__ __launch_bounds__(NNT) void k_loss_grad(const float* __restrict__ y,
   dy[i] = (float)(2.0 * ((double)y[i] - (double)t[i]) / ((double)B * den[b]));
 }
 
-// Adam (Kingma & Ba 2015): bc1 = 1 - beta1^step, bc2 = 1 - beta2^step.
+// The BF16 value of a finite FP32 x (its upper 16 bits after round to nearest,
+// ties to even), returned as the FP32 number it represents.
+__device__ inline float bf16_round(float x) {
+  const unsigned u = __float_as_uint(x);
+  return __uint_as_float((u + 0x7FFFu + ((u >> 16) & 1u)) & 0xFFFF0000u);
+}
+
+// q = the BF16 rounding of the master parameters p (the weights the network
+// computes with).
+__global__ __launch_bounds__(NNT) void k_quantize_bf16(const float* __restrict__ p,
+                                                       float* __restrict__ q, long long n) {
+  const long long i = (long long)blockIdx.x * NNT + threadIdx.x;
+  if (i < n) q[i] = bf16_round(p[i]);
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master parameters p: bc1 = 1 - beta1^step,
+// bc2 = 1 - beta2^step; q gets the updated parameters rounded to BF16.
 __global__ __launch_bounds__(NNT) void k_adam(float* __restrict__ p, const float* __restrict__ g,
                                               float* __restrict__ m, float* __restrict__ v,
                                               long long n, float lr, float beta1, float beta2,
-                                              float bc1, float bc2, float eps) {
+                                              float bc1, float bc2, float eps, float* __restrict__ q) {
   const long long i = (long long)blockIdx.x * NNT + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -882,7 +898,9 @@ __global__ __launch_bounds__(NNT) void k_adam(float* __restrict__ p, const float
   const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+  p[i] = pi;
+  q[i] = bf16_round(pi);
 }
 
 // ---------------------------------------------------------------------------
@@ -1135,11 +1153,15 @@ void nn_loss(hipStream_t st, const float* y, const float* t, long long per, int 
 }
 
 void nn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, long long n, double lr,
-             int step, double beta1, double beta2, double eps) {
+             int step, double beta1, double beta2, double eps, float* q) {
   const float bc1 = (float)(1.0 - std::pow(beta1, step));
   const float bc2 = (float)(1.0 - std::pow(beta2, step));
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, g, m, v, n,
-                     (float)lr, (float)beta1, (float)beta2, bc1, bc2, (float)eps);
+                     (float)lr, (float)beta1, (float)beta2, bc1, bc2, (float)eps, q);
+}
+
+void nn_quantize_bf16(hipStream_t st, const float* p, float* q, long long n) {
+  hipLaunchKernelGGL(k_quantize_bf16, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, q, n);
 }
 
 void nn_features(hipStream_t st, const double2* keps, const double2* b, double k0sq, int nx,

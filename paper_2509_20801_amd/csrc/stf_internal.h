@@ -551,8 +551,11 @@ void nn_pw_bwd(hipStream_t st, int ci, int co, bool act, const float* dout, cons
 int nn_loss_blocks();
 void nn_loss(hipStream_t st, const float* y, const float* t, long long per, int B, double* partial,
              double* den, double* loss, float* dy);
+// Adam on the FP32 master parameters p; q gets them rounded to BF16.
 void nn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, long long n, double lr,
-             int step, double beta1, double beta2, double eps);
+             int step, double beta1, double beta2, double eps, float* q);
+// q = p rounded to BF16 (round to nearest, ties to even), held as FP32 values.
+void nn_quantize_bf16(hipStream_t st, const float* p, float* q, long long n);
 void nn_features(hipStream_t st, const double2* keps, const double2* b, double k0sq, int nx,
                  int pml_x, int pml_y, const int2* org, int ntiles, int n, float* f);
 void nn_fields(hipStream_t st, const double2* x, int nx, int pml_x, int pml_y, const int2* org,

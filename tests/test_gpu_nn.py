@@ -65,7 +65,7 @@ def test_forward_matches_reference(stf, ctx, cfg, batch):
     net = _net(stf, ctx, cfg, flat)
     f, _ = _inputs(cfg, batch, 2)
     y = net.forward(torch.from_numpy(f).cuda()).cpu().numpy()
-    yr, _ = nn.forward(cfg, nn.unflatten(cfg, flat), f.astype(np.float64))
+    yr, _ = nn.forward(cfg, nn.unflatten(cfg, nn.quantize_bf16(flat)), f.astype(np.float64))
     assert np.abs(y - yr).max() <= 1e-4 * np.abs(yr).max()
     net.close()
 
@@ -77,7 +77,7 @@ def test_gradient_matches_reference(stf, ctx, cfg, batch):
     net = _net(stf, ctx, cfg, flat)
     f, t = _inputs(cfg, batch, 5)
     loss, g = net.loss_grad(torch.from_numpy(f).cuda(), torch.from_numpy(t).cuda())
-    p = nn.unflatten(cfg, flat)
+    p = nn.unflatten(cfg, nn.quantize_bf16(flat))          # gradients at the BF16 weights
     y, cache = nn.forward(cfg, p, f.astype(np.float64))
     lr_, dy = nn.loss_and_grad(y, t.astype(np.float64))
     gr, _ = nn.backward(cfg, p, cache, dy)
@@ -103,6 +103,31 @@ def test_adam_step_matches_reference(stf, ctx):
     ref, _, _ = nn.adam(flat, g.astype(np.float64), z, z, 1, 1e-3)
     assert np.abs(p1 - ref).max() <= 1e-6
     net.close()
+
+
+def test_weights_are_rounded_to_bf16(stf, ctx):
+    """The network computes with its parameters rounded to BF16 exactly as the
+    oracle rounds them: the same outputs, bit for bit, from the FP32 parameters
+    and from their BF16 rounding, at creation, after set_params and after an
+    Adam step (whose rounding is fused into the update); get_params returns the
+    FP32 master copy."""
+    import torch
+    flat = _flat(CFG, 11)
+    q = nn.quantize_bf16(flat)
+    assert np.count_nonzero(q != flat) > 0.9 * flat.size
+    f, t = _inputs(CFG, 2, 12)
+    fd, td = torch.from_numpy(f).cuda(), torch.from_numpy(t).cuda()
+    a, b = _net(stf, ctx, CFG, flat), _net(stf, ctx, CFG, q)
+    assert torch.equal(a.forward(fd), b.forward(fd))
+    assert np.array_equal(a.get_params().astype(np.float64), flat)
+    b.set_params(flat)
+    assert torch.equal(a.forward(fd), b.forward(fd))
+    a.train_step(fd, td, 1e-3, 1)
+    p1 = a.get_params().astype(np.float64)
+    b.set_params(nn.quantize_bf16(p1))
+    assert torch.equal(a.forward(fd), b.forward(fd))
+    a.close()
+    b.close()
 
 
 def test_training_reduces_the_loss(stf, ctx):
@@ -143,7 +168,7 @@ def test_initial_guess_and_tile_data_match_reference(stf, ctx):
     pml, n, interior = 8, CFG.n, w.nx - 16
     org = learned.tile_origins(interior, n, n // 2)
     eps_node = fdfd.node_eps(w.eps_cells)
-    p = nn.unflatten(CFG, flat)
+    p = nn.unflatten(CFG, nn.quantize_bf16(flat))
     feats = np.stack([nn.features(eps_node, b, pml + oy, pml + ox, n) for oy in org for ox in org])
     y, _ = nn.forward(CFG, p, feats)
     pred = [[y[a * len(org) + c] for c in range(len(org))] for a in range(len(org))]
