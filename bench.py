@@ -113,7 +113,7 @@ def run_form(stf, torch, ctx, w, prec, steps, warmup, tol, restart, max_iter, ti
     stats = {}
     if timing:
         # The same number of steps again with the dominant class's launches
-        # bracketed by HIP events on the library's stream: its per-launch time.
+        # timed by events that each kernel's dispatch records: its per-launch time.
         timed_infos = list(infos)
         ctx.set_timing(True, classes=[dom])
         for _ in range(steps):

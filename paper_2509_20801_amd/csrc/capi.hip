@@ -16,6 +16,8 @@
 
 using namespace stf;
 
+thread_local KernelTimer* stf::t_kernel_timer = nullptr;
+
 namespace {
 
 struct DBuf {
@@ -139,6 +141,7 @@ struct stf_ctx_s {
   }
   void fold() {
     HIP_CHECK(hipStreamSynchronize(stream));
+    if (side) HIP_CHECK(hipStreamSynchronize(side));   // kernels timed on the second stream
     for (int c = 0; c < STF_K_COUNT; ++c) {
       for (auto& pr : pending[c]) {
         float ms = 0.f;
@@ -163,34 +166,35 @@ namespace {
 // Message of the last failure that happened without a context (stf_ctx_create).
 thread_local std::string g_noctx_error;
 
-// Brackets one kernel launch with events when timing is on.
-struct Timed {
+// While in scope (and timing is on for its class), every kernel launched on
+// this thread is timed on its own: the start and stop events are recorded by
+// its dispatch, and the pair is added to the class.  Nested scopes time their
+// kernels in the innermost class.  Kernels captured into a graph are not timed.
+struct Timed final : KernelTimer {
   stf_ctx c;
   int cls;
-  hipEvent_t b = nullptr;
+  KernelTimer* prev = nullptr;
+  bool on = false;
   Timed(stf_ctx c_, int cls_) : c(c_), cls(cls_) {
     if (c && c->timing && (c->timing_mask >> cls & 1u)) {
-      if (c->npending() > 16384) c->fold();
-      b = c->get_event();
-      HIP_CHECK(hipEventRecord(b, c->stream));
+      on = true;
+      prev = t_kernel_timer;
+      t_kernel_timer = this;
     }
   }
+  Timed(const Timed&) = delete;
+  Timed& operator=(const Timed&) = delete;
+  bool events(hipStream_t st, hipEvent_t* start, hipEvent_t* stop) override {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return false;
+    if (c->npending() > 16384) c->fold();
+    *start = c->get_event();
+    *stop = c->get_event();
+    c->pending[cls].push_back({*start, *stop});
+    return true;
+  }
   ~Timed() {
-    if (!b) return;
-    hipEvent_t e = nullptr;
-    if (!c->pool.empty()) {
-      e = c->pool.back();
-      c->pool.pop_back();
-    } else if (hipEventCreate(&e) != hipSuccess) {
-      c->pool.push_back(b);
-      return;
-    }
-    if (hipEventRecord(e, c->stream) != hipSuccess) {
-      c->pool.push_back(b);
-      c->pool.push_back(e);
-      return;
-    }
-    c->pending[cls].push_back({b, e});
+    if (on) t_kernel_timer = prev;
   }
 };
 

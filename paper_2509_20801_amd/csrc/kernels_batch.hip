@@ -539,21 +539,21 @@ void launch_bstencil(hipStream_t st, int mode, const double2* x, const double2* 
   if (ntiles <= 0) return;
   const dim3 blk(64, 4);
   if (mode == 0)
-    hipLaunchKernelGGL(k_bstencil<0>, dim3(ntiles), blk, 0, st, x, b, y, keps, gc, sys, tsys, gate,
+    STF_LAUNCH(k_bstencil<0>, dim3(ntiles), blk, 0, st, x, b, y, keps, gc, sys, tsys, gate,
                        partial);
   else
-    hipLaunchKernelGGL(k_bstencil<1>, dim3(ntiles), blk, 0, st, x, b, y, keps, gc, sys, tsys, gate,
+    STF_LAUNCH(k_bstencil<1>, dim3(ntiles), blk, 0, st, x, b, y, keps, gc, sys, tsys, gate,
                        partial);
 }
 
 void launch_bnorm2(hipStream_t st, const double2* v, const SysDev* sys, const int* bsys, int nblk,
                    double* npart) {
-  if (nblk > 0) hipLaunchKernelGGL(k_bnorm2, dim3(nblk), dim3(BT), 0, st, v, sys, bsys, npart);
+  if (nblk > 0) STF_LAUNCH(k_bnorm2, dim3(nblk), dim3(BT), 0, st, v, sys, bsys, npart);
 }
 
 void launch_bsum(hipStream_t st, const double* partial, const SysDev* sys, int nsys, int ci,
                  const int* gate, double* sc, int out) {
-  hipLaunchKernelGGL(k_bsum, dim3(nsys), dim3(BT), 0, st, partial, sys, ci, gate, sc, out);
+  STF_LAUNCH(k_bsum, dim3(nsys), dim3(BT), 0, st, partial, sys, ci, gate, sc, out);
 }
 
 int bgs_class(int nv) { return nv <= 8 ? 2 : nv <= 16 ? 1 : nv <= 32 ? 0 : -1; }
@@ -569,13 +569,13 @@ void launch_bgs(hipStream_t st, int mode, const double2* V, long long ld, int nv
 #define STF_BGS_CASE(M)                                                                          \
   if (M == (32 >> ci)) {                                                                         \
     if (mode == GS_DOT)                                                                          \
-      hipLaunchKernelGGL((k_bgs<M, false, true, false>), g, b, 0, st, V, ld, nv, h, hs, w, sys,  \
+      STF_LAUNCH((k_bgs<M, false, true, false>), g, b, 0, st, V, ld, nv, h, hs, w, sys,  \
                          bsys, ci, act, rgate, partial, npart, vout, sc, nin, nout);             \
     else if (mode == GS_UPDATE_DOT)                                                              \
-      hipLaunchKernelGGL((k_bgs<M, true, true, false>), g, b, 0, st, V, ld, nv, h, hs, w, sys,   \
+      STF_LAUNCH((k_bgs<M, true, true, false>), g, b, 0, st, V, ld, nv, h, hs, w, sys,   \
                          bsys, ci, act, rgate, partial, npart, vout, sc, nin, nout);             \
     else                                                                                         \
-      hipLaunchKernelGGL((k_bgs<M, true, false, true>), g, b, 0, st, V, ld, nv, h, hs, w, sys,   \
+      STF_LAUNCH((k_bgs<M, true, false, true>), g, b, 0, st, V, ld, nv, h, hs, w, sys,   \
                          bsys, ci, act, rgate, partial, npart, vout, sc, nin, nout);             \
     return;                                                                                      \
   }
@@ -590,7 +590,7 @@ void launch_bgs_reduce(hipStream_t st, const double* partial, int nv, const SysD
                        double* sc, int out, int ref, int* rgate_out) {
   const int ci = bgs_class(nv);
   const int K = 2 * (ci == 2 ? 8 : ci == 1 ? 16 : 32);
-  hipLaunchKernelGGL(k_bgs_reduce, dim3(nv + 1, nsys), dim3(BT), 0, st, partial, K, nv, sys, ci, act,
+  STF_LAUNCH(k_bgs_reduce, dim3(nv + 1, nsys), dim3(BT), 0, st, partial, K, nv, sys, ci, act,
                      rgate_in, h, hs, npart, sc, out, ref, rgate_out);
 }
 
@@ -600,37 +600,37 @@ void launch_bgivens_scale(hipStream_t st, const double2* w, double2* v, const Sy
                           int j, int* act, const int* rgate, int* kcol, int* it, double* hist,
                           int hcap, double tol, int max_iter) {
   STF_REQUIRE(m <= BGV && j < m, "batched Givens step beyond the staged column");
-  hipLaunchKernelGGL(k_bgivens_scale, dim3(nsys + nblk), dim3(BT), 0, st, w, v, sys, bsys, nsys, H,
+  STF_LAUNCH(k_bgivens_scale, dim3(nsys + nblk), dim3(BT), 0, st, w, v, sys, bsys, nsys, H,
                      h1, h2, m, sc, cs, sn, g, j, act, rgate, kcol, it, hist, hcap, tol, max_iter);
 }
 
 void launch_bpact(hipStream_t st, const int* act, int nslot, int nprob, int* pact) {
-  hipLaunchKernelGGL(k_bpact, dim3(1), dim3(BT), 0, st, act, nslot, nprob, pact);
+  STF_LAUNCH(k_bpact, dim3(1), dim3(BT), 0, st, act, nslot, nprob, pact);
 }
 
 void launch_bcycle_start(hipStream_t st, const double2* r, double2* v, const SysDev* sys,
                          const int* bsys, int nblk, int nsys, const double* sc, double2* g, int glen,
                          int* act, int* cyc, int* kcol, const int* it, double tol, int max_iter) {
-  hipLaunchKernelGGL(k_bcycle_start, dim3(nsys + nblk), dim3(BT), 0, st, r, v, sys, bsys, nsys, sc, g,
+  STF_LAUNCH(k_bcycle_start, dim3(nsys + nblk), dim3(BT), 0, st, r, v, sys, bsys, nsys, sc, g,
                      glen, act, cyc, kcol, it, tol, max_iter);
 }
 
 void launch_btrisolve(hipStream_t st, const double2* H, int m, const double2* g, double2* y,
                       const int* kcol, const int* cyc, int nsys) {
   STF_REQUIRE(m <= BGV, "batched triangular solve beyond the staged size");
-  hipLaunchKernelGGL(k_btrisolve, dim3(nsys), dim3(64), 0, st, H, m, g, y, kcol, cyc);
+  STF_LAUNCH(k_btrisolve, dim3(nsys), dim3(64), 0, st, H, m, g, y, kcol, cyc);
 }
 
 void launch_bxupdate(hipStream_t st, const double2* Z, long long ld, const double2* y, int hs,
                      double2* x, const SysDev* sys, const int* bsys, int nblk, const int* kcol,
                      const int* cyc) {
   if (nblk > 0)
-    hipLaunchKernelGGL(k_bxupdate, dim3(nblk), dim3(BT), 0, st, Z, ld, y, hs, x, sys, bsys, kcol, cyc);
+    STF_LAUNCH(k_bxupdate, dim3(nblk), dim3(BT), 0, st, Z, ld, y, hs, x, sys, bsys, kcol, cyc);
 }
 
 void launch_bstatus(hipStream_t st, const double* sc, const int* it, const int* cyc, int nsys,
                     double* host_out) {
-  hipLaunchKernelGGL(k_bstatus, dim3(1), dim3(BT), 0, st, sc, it, cyc, nsys, host_out);
+  STF_LAUNCH(k_bstatus, dim3(1), dim3(BT), 0, st, sc, it, cyc, nsys, host_out);
 }
 
 }  // namespace stf

@@ -1752,7 +1752,7 @@ template <typename T, int NB, int NTF = NT>
 void large_launch(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* upk, int* piv, int* flag,
                   double tau) {
   const size_t lds = panel_lds(a, sizeof(T), NB);
-  hipLaunchKernelGGL((k_factor_large<T, NB, NTF>), dim3(a.nlevel), dim3(NTF), lds, st, a, fac, lpk,
+  STF_LAUNCH((k_factor_large<T, NB, NTF>), dim3(a.nlevel), dim3(NTF), lds, st, a, fac, lpk,
                      upk, piv, flag, tau);
 }
 
@@ -1852,7 +1852,7 @@ void launch_front_factor(hipStream_t st, const LevelArgs& a, T* fac, T* lpk, T* 
   if (!factor_shape_ok(a, sizeof(T), sh)) throw Error(STF_EINVAL, "factorisation launch shape not valid for the level");
   if (sh.kind == 1) {
     size_t lds = ((size_t)a.max_m * a.max_m + 128) * sizeof(T);
-    hipLaunchKernelGGL(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, lpk, upk, piv, flag,
+    STF_LAUNCH(k_factor_small<T>, dim3(a.nlevel), dim3(64), lds, st, a, fac, lpk, upk, piv, flag,
                        tau);
     return;
   }
@@ -1918,7 +1918,7 @@ template <typename T, int RPL, int KP>
 void fwd_wave_launch(hipStream_t st, const LevelArgs& a, const T* fac, const int* piv, T* vec,
                      const RhsSet& r) {
 #define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_fwd_wave<T, RPL, KP, NR>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, piv, vec, r)
+  STF_LAUNCH((k_fwd_wave<T, RPL, KP, NR>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, fac, piv, vec, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
@@ -1927,7 +1927,7 @@ template <typename T, int KP>
 void bwd_wave_launch(hipStream_t st, const LevelArgs& a, const T* upk, T* vec, T* u,
                      const RhsSet& r) {
 #define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_bwd_wave<T, KP, NR>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u, r)
+  STF_LAUNCH((k_bwd_wave<T, KP, NR>), dim3((a.nlevel + 3) / 4), dim3(NT), 0, st, a, upk, vec, u, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
@@ -1937,7 +1937,7 @@ void fwd_large_nr(hipStream_t st, const LevelArgs& a, int parts, const T* fac, c
                   T* vec, const RhsSet& r) {
   const size_t lds = ((size_t)r.nr * NTL + 2 * (size_t)r.nr * a.max_m) * sizeof(T);
 #define STF_CALL(NR)                                                                         \
-  hipLaunchKernelGGL((k_fwd_large<T, NTL, KP, NR>), dim3(a.nlevel, parts), dim3(NTL), lds, st, a, \
+  STF_LAUNCH((k_fwd_large<T, NTL, KP, NR>), dim3(a.nlevel, parts), dim3(NTL), lds, st, a, \
                      fac, piv, vec, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
@@ -1948,7 +1948,7 @@ void bwd_large_nr(hipStream_t st, const LevelArgs& a, int parts, const T* upk, T
                   const RhsSet& r) {
   const size_t lds = ((size_t)r.nr * NTL + (size_t)r.nr * a.max_m) * sizeof(T);
 #define STF_CALL(NR)                                                                         \
-  hipLaunchKernelGGL((k_bwd_large<T, NTL, KP, NR>), dim3(a.nlevel, parts), dim3(NTL), lds, st, a, \
+  STF_LAUNCH((k_bwd_large<T, NTL, KP, NR>), dim3(a.nlevel, parts), dim3(NTL), lds, st, a, \
                      upk, vec, u, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
@@ -2136,13 +2136,13 @@ void launch_fwd_subtree(hipStream_t st, const LevelArgs& a, const FuseArgs& z, c
   const int kp = prefetch_depth(z.max_p, 16 / rpl);
 #define STF_CALL(NR)                                                                                  \
   if (rpl == 2)                                                                                       \
-    hipLaunchKernelGGL((k_fwd_subtree<T, 2, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
+    STF_LAUNCH((k_fwd_subtree<T, 2, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
                        vec, r);                                                                       \
   else if (kp == 8)                                                                                   \
-    hipLaunchKernelGGL((k_fwd_subtree<T, 1, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
+    STF_LAUNCH((k_fwd_subtree<T, 1, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
                        vec, r);                                                                       \
   else                                                                                                \
-    hipLaunchKernelGGL((k_fwd_subtree<T, 1, 16, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
+    STF_LAUNCH((k_fwd_subtree<T, 1, 16, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, lpk, piv, \
                        vec, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
@@ -2161,9 +2161,9 @@ void launch_bwd_subtree(hipStream_t st, const LevelArgs& a, const FuseArgs& z, c
   const int kp = prefetch_depth((z.max_m + g - 1) / g, 16);
 #define STF_CALL(NR)                                                                                   \
   if (kp == 8)                                                                                         \
-    hipLaunchKernelGGL((k_bwd_subtree<T, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, upk, vec, u, r); \
+    STF_LAUNCH((k_bwd_subtree<T, 8, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, upk, vec, u, r); \
   else                                                                                                 \
-    hipLaunchKernelGGL((k_bwd_subtree<T, 16, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, upk, vec, u, r)
+    STF_LAUNCH((k_bwd_subtree<T, 16, NR>), dim3(z.ntrees), dim3(NT), lds, st, a, z, upk, vec, u, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
@@ -2175,7 +2175,7 @@ void launch_scatter(hipStream_t st, const T* u, const SubDev* subs, const int4* 
   check_rhs(r);
   dim3 blk(64, 4), grd((max_nx + 63) / 64, (max_ny + 3) / 4, nprob);
 #define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_scatter<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, probs, pact, r)
+  STF_LAUNCH((k_scatter<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, probs, pact, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
 }
@@ -2188,7 +2188,7 @@ void launch_stage_residual(hipStream_t st, const double2* keps, const double2* g
   if (scount <= 0) return;
   dim3 blk(64, 4), grd((maxw + 63) / 64, (maxh + 3) / 4, scount);
 #define STF_CALL(NR)                                                                            \
-  hipLaunchKernelGGL((k_stage_residual<NR>), grd, blk, 0, st, keps, gc, subs, probs, slist, sfirst, \
+  STF_LAUNCH((k_stage_residual<NR>), grd, blk, 0, st, keps, gc, subs, probs, slist, sfirst, \
                      pact, r, rbuf, rstride)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
@@ -2203,7 +2203,7 @@ void launch_stage_scatter(hipStream_t st, const T* u, const SubDev* subs, const 
   if (scount <= 0) return;
   dim3 blk(64, 4), grd((maxw + 63) / 64, (maxh + 3) / 4, scount);
 #define STF_CALL(NR)                                                                            \
-  hipLaunchKernelGGL((k_stage_scatter<T, NR>), grd, blk, 0, st, u, subs, probs, cover_x, cover_y, \
+  STF_LAUNCH((k_stage_scatter<T, NR>), grd, blk, 0, st, u, subs, probs, cover_x, cover_y, \
                      slist, sfirst, inst, pact, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
@@ -2216,7 +2216,7 @@ void launch_stage_scatter_first(hipStream_t st, const T* u, const SubDev* subs, 
   check_rhs(r);
   dim3 blk(64, 4), grd((max_nx + 63) / 64, (max_ny + 3) / 4, nprob);
 #define STF_CALL(NR)                                                                              \
-  hipLaunchKernelGGL((k_stage_scatter_first<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, probs, \
+  STF_LAUNCH((k_stage_scatter_first<T, NR>), grd, blk, 0, st, u, subs, cover_x, cover_y, probs, \
                      inst, pact, r)
   STF_NR_DISPATCH(r.nr, STF_CALL)
 #undef STF_CALL
@@ -2226,14 +2226,14 @@ void launch_zero(hipStream_t st, double2* p, long long n) {
   long long g = (n + 255) / 256;
   if (g > 8192) g = 8192;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)g), dim3(256), 0, st, p, n);
+  STF_LAUNCH(k_zero, dim3((unsigned)g), dim3(256), 0, st, p, n);
 }
 
 template <typename T>
 void launch_overlap_norm(hipStream_t st, const T* u, const SubDev* subs, int nsub, double* per_sub,
                          double* out) {
-  hipLaunchKernelGGL((k_overlap_norm<T>), dim3(nsub), dim3(256), 0, st, u, subs, per_sub);
-  hipLaunchKernelGGL(k_sum_ordered, dim3(1), dim3(64), 0, st, per_sub, nsub, out);
+  STF_LAUNCH((k_overlap_norm<T>), dim3(nsub), dim3(256), 0, st, u, subs, per_sub);
+  STF_LAUNCH(k_sum_ordered, dim3(1), dim3(64), 0, st, per_sub, nsub, out);
 }
 
 #define STF_INST(T)                                                                             \

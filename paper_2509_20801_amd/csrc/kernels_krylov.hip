@@ -572,13 +572,13 @@ int krylov_blocks(long long n) { return (int)((n + CHUNK - 1) / CHUNK); }
 
 void launch_mdot(hipStream_t st, const double2* V, long long ld, int nv, const double2* w,
                  long long n, double2* partial, double* norm_partial, const int* gate) {
-  hipLaunchKernelGGL(k_mdot, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, w, n, partial,
+  STF_LAUNCH(k_mdot, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, w, n, partial,
                      norm_partial, gate);
 }
 
 void launch_mdot_reduce(hipStream_t st, const double2* partial, int nblk, int nv, double2* h,
                         const int* gate, int stride) {
-  hipLaunchKernelGGL(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk,
+  STF_LAUNCH(k_mdot_reduce, dim3(nv), dim3(KT), 0, st, partial, nblk,
                      stride > 0 ? stride : nv, h, gate);
 }
 
@@ -593,7 +593,7 @@ int gs_blocks(long long n, int nv) {
 
 void launch_gs_reduce_set(hipStream_t st, int nr, const GsRedSet& S, int nblk, int stride, int nv) {
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
-  hipLaunchKernelGGL(k_gs_reduce, dim3(nv + 1, nr), dim3(KT), 0, st, S, nblk, stride, nv);
+  STF_LAUNCH(k_gs_reduce, dim3(nv + 1, nr), dim3(KT), 0, st, S, nblk, stride, nv);
 }
 
 void launch_gs_reduce(hipStream_t st, const double2* partial, int nblk, int stride, int nv,
@@ -620,13 +620,13 @@ void launch_gs_set(hipStream_t st, int mode, int nr, const GsSet& S, long long l
 #define STF_GS_CASE(M)                                                                        \
   if (nvm == M) {                                                                             \
     if (mode == GS_DOT)                                                                       \
-      hipLaunchKernelGGL((k_gs<M, false, true, false>), g, b, 0, st, S, ld, nv, n);           \
+      STF_LAUNCH((k_gs<M, false, true, false>), g, b, 0, st, S, ld, nv, n);           \
     else if (mode == GS_UPDATE_DOT)                                                           \
-      hipLaunchKernelGGL((k_gs<M, true, true, false>), g, b, 0, st, S, ld, nv, n);            \
+      STF_LAUNCH((k_gs<M, true, true, false>), g, b, 0, st, S, ld, nv, n);            \
     else if (mode == GS_UPDATE)                                                               \
-      hipLaunchKernelGGL((k_gs<M, true, false, false>), g, b, 0, st, S, ld, nv, n);           \
+      STF_LAUNCH((k_gs<M, true, false, false>), g, b, 0, st, S, ld, nv, n);           \
     else                                                                                      \
-      hipLaunchKernelGGL((k_gs<M, true, false, true>), g, b, 0, st, S, ld, nv, n);            \
+      STF_LAUNCH((k_gs<M, true, false, true>), g, b, 0, st, S, ld, nv, n);            \
     return;                                                                                   \
   }
   STF_GS_CASE(8)
@@ -653,34 +653,34 @@ void launch_gs(hipStream_t st, int mode, const double2* V, long long ld, int nv,
 
 void launch_mupdate(hipStream_t st, const double2* V, long long ld, int nv, const double2* h,
                     double2* w, long long n, double* norm_partial, const int* gate) {
-  hipLaunchKernelGGL(k_mupdate, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, h, w, n,
+  STF_LAUNCH(k_mupdate, dim3(krylov_blocks(n)), dim3(KT), 0, st, V, ld, nv, h, w, n,
                      norm_partial, gate);
 }
 
 void launch_norm_reduce(hipStream_t st, const double* partial, int n, double* out,
                         const double* ref, int* gate, int decide) {
-  hipLaunchKernelGGL(k_norm_reduce, dim3(1), dim3(KT), 0, st, partial, n, out, ref, gate, decide);
+  STF_LAUNCH(k_norm_reduce, dim3(1), dim3(KT), 0, st, partial, n, out, ref, gate, decide);
 }
 
 void launch_hacc(hipStream_t st, double2* h1, const double2* h2, int nv, const int* gate) {
-  hipLaunchKernelGGL(k_hacc, dim3(1), dim3(256), 0, st, h1, h2, nv, gate);
+  STF_LAUNCH(k_hacc, dim3(1), dim3(256), 0, st, h1, h2, nv, gate);
 }
 
 void launch_cycle_start_set(hipStream_t st, int nr, const CycleSet& S, long long n, int glen) {
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
-  hipLaunchKernelGGL(k_cycle_start, dim3(grid_for(n), nr), dim3(KT), 0, st, S, n, glen);
+  STF_LAUNCH(k_cycle_start, dim3(grid_for(n), nr), dim3(KT), 0, st, S, n, glen);
 }
 
 
 void launch_scale(hipStream_t st, const double2* w, const double* nrm2, double2* v, long long n,
                   const int* skip) {
-  hipLaunchKernelGGL(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n, skip);
+  STF_LAUNCH(k_scale, dim3(grid_for(n)), dim3(KT), 0, st, w, nrm2, v, n, skip);
 }
 
 void launch_scale_givens_set(hipStream_t st, int nr, const GivensSet& S, long long n, int j, int ldh) {
   STF_REQUIRE(j >= 0 && j < GV, "Givens step beyond the staged column");
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
-  hipLaunchKernelGGL(k_scale_givens, dim3(grid_for(n) + 1, nr), dim3(KT), 0, st, S, n, j, ldh);
+  STF_LAUNCH(k_scale_givens, dim3(grid_for(n) + 1, nr), dim3(KT), 0, st, S, n, j, ldh);
 }
 
 void launch_scale_givens(hipStream_t st, const double2* w, double2* v, long long n, double2* H,
@@ -705,17 +705,17 @@ void launch_scale_givens(hipStream_t st, const double2* w, double2* v, long long
 }
 
 void launch_axpy(hipStream_t st, double2* y, const double2* x, long long n) {
-  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(KT), 0, st, y, x, n);
+  STF_LAUNCH(k_axpy, dim3(grid_for(n)), dim3(KT), 0, st, y, x, n);
 }
 
 void launch_trisolve_set(hipStream_t st, int nr, const CycleSet& S, int ldh) {
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
-  hipLaunchKernelGGL(k_trisolve, dim3(nr), dim3(64), 0, st, S, ldh);
+  STF_LAUNCH(k_trisolve, dim3(nr), dim3(64), 0, st, S, ldh);
 }
 
 void launch_xupdate_set(hipStream_t st, int nr, const CycleSet& S, long long ld, long long n) {
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 right-hand sides per launch");
-  hipLaunchKernelGGL(k_xupdate, dim3(grid_for(n), nr), dim3(KT), 0, st, S, ld, n);
+  STF_LAUNCH(k_xupdate, dim3(grid_for(n), nr), dim3(KT), 0, st, S, ld, n);
 }
 
 }  // namespace stf

@@ -997,21 +997,21 @@ void nn_gemm(hipStream_t st, int batch, int M, int N, int K, const float* A, lon
     const bool vec = sAk == 1 && sAm % 4 == 0 && sAb % 4 == 0 &&
                      (reinterpret_cast<uintptr_t>(A) & 15) == 0;
     dim3 grid((M + 63) / 64, 1, batch);
-    if (vec) hipLaunchKernelGGL((k_gemm_tall<true>), grid, dim3(256), 0, st, g);
-    else hipLaunchKernelGGL((k_gemm_tall<false>), grid, dim3(256), 0, st, g);
+    if (vec) STF_LAUNCH((k_gemm_tall<true>), grid, dim3(256), 0, st, g);
+    else STF_LAUNCH((k_gemm_tall<false>), grid, dim3(256), 0, st, g);
     return;
   }
   if (K <= 64) {
     dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
-    hipLaunchKernelGGL(k_gemm_mfma, grid, dim3(256), 0, st, g);
+    STF_LAUNCH(k_gemm_mfma, grid, dim3(256), 0, st, g);
     return;
   }
   if (N <= 32) {
     dim3 grid((N + 31) / 32, (M + 127) / 128, batch);
-    hipLaunchKernelGGL((k_gemm<128, 32>), grid, dim3(256), 0, st, g);
+    STF_LAUNCH((k_gemm<128, 32>), grid, dim3(256), 0, st, g);
   } else {
     dim3 grid((N + 63) / 64, (M + 63) / 64, batch);
-    hipLaunchKernelGGL((k_gemm<64, 64>), grid, dim3(256), 0, st, g);
+    STF_LAUNCH((k_gemm<64, 64>), grid, dim3(256), 0, st, g);
   }
 }
 
@@ -1019,7 +1019,7 @@ void nn_dft_y(hipStream_t st, const float* T, const float2* ey, int planes, int 
               bool grad_scale, float2* H) {
   if (2 * M * M > 4 * NNT) throw Error(STF_EINVAL, "too many modes for the y transform");
   const size_t lds = (size_t)n * 2 * M * sizeof(float) + (size_t)2 * M * 64 * sizeof(float2);
-  hipLaunchKernelGGL(k_dft_y, dim3(planes), dim3(NNT), lds, st, T, ey, n, M, grad_scale ? 1 : 0, H);
+  STF_LAUNCH(k_dft_y, dim3(planes), dim3(NNT), lds, st, T, ey, n, M, grad_scale ? 1 : 0, H);
 }
 
 bool nn_spec_inv_ok(int n, int M) { return n % 16 == 0 && n <= 1024 && M >= 1 && M <= 22; }
@@ -1034,11 +1034,11 @@ void nn_spec_inv(hipStream_t st, const float2* G, const float2* ex, int planes, 
     throw Error(STF_EINVAL, "nn: inverse transform shape or alignment");
   const size_t lds = (size_t)4 * M * (n + 16) * sizeof(float);
   if (n == 256 && M == 16) {
-    hipLaunchKernelGGL((k_spec_inv_t<256, 16>), dim3(planes), dim3(256), lds, st, G, ex, weighted ? 1 : 0,
+    STF_LAUNCH((k_spec_inv_t<256, 16>), dim3(planes), dim3(256), lds, st, G, ex, weighted ? 1 : 0,
                        ainv, alpha, beta, out, npix);
     return;
   }
-  hipLaunchKernelGGL(k_spec_inv, dim3(planes), dim3(256), lds, st, G, ex, n, M, weighted ? 1 : 0, ainv,
+  STF_LAUNCH(k_spec_inv, dim3(planes), dim3(256), lds, st, G, ex, n, M, weighted ? 1 : 0, ainv,
                      alpha, beta, out, npix);
 }
 
@@ -1046,7 +1046,7 @@ bool nn_spec_pw_ok(int n, int M, int W) { return n == 256 && M == 16 && W == 16;
 
 void nn_spec_rows(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M, float* S) {
   if (n != 256 || M != 16) throw Error(STF_EINVAL, "nn: x-inverse rows of the compiled shape only");
-  hipLaunchKernelGGL((k_spec_rows_t<256, 16>), dim3(planes), dim3(256), 0, st, G, ex, S);
+  STF_LAUNCH((k_spec_rows_t<256, 16>), dim3(planes), dim3(256), 0, st, G, ex, S);
 }
 
 void nn_spec_pw(hipStream_t st, const float* S, const float* ainv, float alpha, const float* hin,
@@ -1057,34 +1057,34 @@ void nn_spec_pw(hipStream_t st, const float* S, const float* ainv, float alpha, 
     throw Error(STF_EINVAL, "nn: fused spectral + pointwise layer shape or alignment");
   const dim3 grid(256 / 64, 256 / 16, B);
   if (act)
-    hipLaunchKernelGGL((k_spec_pw_t<256, 16, 16, true>), grid, dim3(256), 0, st, S, ainv, alpha, hin, Wm,
+    STF_LAUNCH((k_spec_pw_t<256, 16, 16, true>), grid, dim3(256), 0, st, S, ainv, alpha, hin, Wm,
                        bias, npix, out);
   else
-    hipLaunchKernelGGL((k_spec_pw_t<256, 16, 16, false>), grid, dim3(256), 0, st, S, ainv, alpha, hin, Wm,
+    STF_LAUNCH((k_spec_pw_t<256, 16, 16, false>), grid, dim3(256), 0, st, S, ainv, alpha, hin, Wm,
                        bias, npix, out);
 }
 
 void nn_dft_x_inv(hipStream_t st, const float2* G, const float2* ex, int planes, int n, int M,
                   bool weighted, float* S) {
   dim3 grid((2 * M * n + NNT - 1) / NNT, planes);
-  hipLaunchKernelGGL(k_dft_x_inv, grid, dim3(NNT), (size_t)2 * M * M * sizeof(float2), st, G, ex,
+  STF_LAUNCH(k_dft_x_inv, grid, dim3(NNT), (size_t)2 * M * M * sizeof(float2), st, G, ex,
                      n, M, weighted ? 1 : 0, S);
 }
 
 void nn_mix_fwd(hipStream_t st, const float2* H, const float* Rre, const float* Rim, int B, int W,
                 int NM, float2* G) {
   long long tot = (long long)B * W * NM;
-  hipLaunchKernelGGL(k_mix_fwd, dim3((unsigned)((tot + NNT - 1) / NNT)), dim3(NNT), 0, st, H, Rre,
+  STF_LAUNCH(k_mix_fwd, dim3((unsigned)((tot + NNT - 1) / NNT)), dim3(NNT), 0, st, H, Rre,
                      Rim, B, W, NM, G);
 }
 
 void nn_mix_bwd(hipStream_t st, const float2* H, const float2* dG, const float* Rre,
                 const float* Rim, int B, int W, int NM, float2* dH, float* dRre, float* dRim) {
   long long tot = (long long)B * W * NM;
-  hipLaunchKernelGGL(k_mix_bwd_h, dim3((unsigned)((tot + NNT - 1) / NNT)), dim3(NNT), 0, st, dG,
+  STF_LAUNCH(k_mix_bwd_h, dim3((unsigned)((tot + NNT - 1) / NNT)), dim3(NNT), 0, st, dG,
                      Rre, Rim, B, W, NM, dH);
   long long tr = (long long)W * W * NM;
-  hipLaunchKernelGGL(k_mix_bwd_r, dim3((unsigned)((tr + NNT - 1) / NNT)), dim3(NNT), 0, st, H, dG,
+  STF_LAUNCH(k_mix_bwd_r, dim3((unsigned)((tr + NNT - 1) / NNT)), dim3(NNT), 0, st, H, dG,
                      B, W, NM, dRre, dRim);
 }
 
@@ -1104,10 +1104,10 @@ void nn_pw_fwd(hipStream_t st, int ci, int co, bool act, const float* in, const 
 #define NN_CASE(a, b)                                                                            \
   if (ci == a && co == b) {                                                                      \
     if (act)                                                                                     \
-      hipLaunchKernelGGL((k_pw_fwd<a, b, true>), dim3(grid), dim3(NNT), 0, st, in, Wm, bias, add, \
+      STF_LAUNCH((k_pw_fwd<a, b, true>), dim3(grid), dim3(NNT), 0, st, in, Wm, bias, add, \
                          npix, B, pre, out);                                                     \
     else                                                                                         \
-      hipLaunchKernelGGL((k_pw_fwd<a, b, false>), dim3(grid), dim3(NNT), 0, st, in, Wm, bias,    \
+      STF_LAUNCH((k_pw_fwd<a, b, false>), dim3(grid), dim3(NNT), 0, st, in, Wm, bias,    \
                          add, npix, B, pre, out);                                                \
     return;                                                                                      \
   }
@@ -1125,13 +1125,13 @@ void nn_pw_bwd(hipStream_t st, int ci, int co, bool act, const float* dout, cons
 #define NN_CASE(a, b)                                                                            \
   if (ci == a && co == b) {                                                                      \
     if (act)                                                                                     \
-      hipLaunchKernelGGL((k_pw_bwd<a, b, true>), dim3(nblk), dim3(NNT), 0, st, dout, pre, in, Wm, \
+      STF_LAUNCH((k_pw_bwd<a, b, true>), dim3(nblk), dim3(NNT), 0, st, dout, pre, in, Wm, \
                          npix, B, dpre, din, partial);                                           \
     else                                                                                         \
-      hipLaunchKernelGGL((k_pw_bwd<a, b, false>), dim3(nblk), dim3(NNT), 0, st, dout, pre, in,   \
+      STF_LAUNCH((k_pw_bwd<a, b, false>), dim3(nblk), dim3(NNT), 0, st, dout, pre, in,   \
                          Wm, npix, B, dpre, din, partial);                                       \
     const int cnt = a * b + b;                                                                   \
-    hipLaunchKernelGGL(k_sum_partials, dim3((cnt + NNT - 1) / NNT), dim3(NNT), 0, st, partial,   \
+    STF_LAUNCH(k_sum_partials, dim3((cnt + NNT - 1) / NNT), dim3(NNT), 0, st, partial,   \
                        nblk, cnt, cnt, grad_w);                                                  \
     return;                                                                                      \
   }
@@ -1145,10 +1145,10 @@ int nn_loss_blocks() { return 64; }
 void nn_loss(hipStream_t st, const float* y, const float* t, long long per, int B, double* partial,
              double* den, double* loss, float* dy) {
   const int nblk = nn_loss_blocks();
-  hipLaunchKernelGGL(k_loss_partial, dim3(nblk, B), dim3(NNT), 0, st, y, t, per, nblk, partial);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, partial, B, nblk, den, loss);
+  STF_LAUNCH(k_loss_partial, dim3(nblk, B), dim3(NNT), 0, st, y, t, per, nblk, partial);
+  STF_LAUNCH(k_loss_final, dim3(1), dim3(64), 0, st, partial, B, nblk, den, loss);
   if (dy)
-    hipLaunchKernelGGL(k_loss_grad, dim3((unsigned)((per * B + NNT - 1) / NNT)), dim3(NNT), 0, st, y,
+    STF_LAUNCH(k_loss_grad, dim3((unsigned)((per * B + NNT - 1) / NNT)), dim3(NNT), 0, st, y,
                        t, den, per, B, dy);
 }
 
@@ -1156,31 +1156,31 @@ void nn_adam(hipStream_t st, float* p, const float* g, float* m, float* v, long 
              int step, double beta1, double beta2, double eps, float* q) {
   const float bc1 = (float)(1.0 - std::pow(beta1, step));
   const float bc2 = (float)(1.0 - std::pow(beta2, step));
-  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, g, m, v, n,
+  STF_LAUNCH(k_adam, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, g, m, v, n,
                      (float)lr, (float)beta1, (float)beta2, bc1, bc2, (float)eps, q);
 }
 
 void nn_quantize_bf16(hipStream_t st, const float* p, float* q, long long n) {
-  hipLaunchKernelGGL(k_quantize_bf16, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, q, n);
+  STF_LAUNCH(k_quantize_bf16, dim3((unsigned)((n + NNT - 1) / NNT)), dim3(NNT), 0, st, p, q, n);
 }
 
 void nn_features(hipStream_t st, const double2* keps, const double2* b, double k0sq, int nx,
                  int pml_x, int pml_y, const int2* org, int ntiles, int n, float* f) {
   dim3 grid((unsigned)(((long long)n * n + NNT - 1) / NNT), ntiles);
-  hipLaunchKernelGGL(k_nn_features, grid, dim3(NNT), 0, st, keps, b, k0sq, nx, pml_x, pml_y, org, n,
+  STF_LAUNCH(k_nn_features, grid, dim3(NNT), 0, st, keps, b, k0sq, nx, pml_x, pml_y, org, n,
                      f);
 }
 
 void nn_fields(hipStream_t st, const double2* x, int nx, int pml_x, int pml_y, const int2* org,
                int ntiles, int n, float* t) {
   dim3 grid((unsigned)(((long long)n * n + NNT - 1) / NNT), ntiles);
-  hipLaunchKernelGGL(k_nn_fields, grid, dim3(NNT), 0, st, x, nx, pml_x, pml_y, org, n, t);
+  STF_LAUNCH(k_nn_fields, grid, dim3(NNT), 0, st, x, nx, pml_x, pml_y, org, n, t);
 }
 
 void nn_blend(hipStream_t st, const float* pred, const int* oy, int nty, const int* ox, int ntx,
               int n, int pml_x, int pml_y, int inx, int iny, int nx, int ny, double2* x0) {
   const long long N = (long long)nx * ny;
-  hipLaunchKernelGGL(k_nn_blend, dim3((unsigned)((N + NNT - 1) / NNT)), dim3(NNT), 0, st, pred, oy,
+  STF_LAUNCH(k_nn_blend, dim3((unsigned)((N + NNT - 1) / NNT)), dim3(NNT), 0, st, pred, oy,
                      nty, ox, ntx, n, pml_x, pml_y, inx, iny, nx, ny, x0);
 }
 

@@ -280,7 +280,7 @@ __global__ __launch_bounds__(256) void k_check_finite(const double* __restrict__
 void launch_node_keps(hipStream_t st, const double2* cells, double2* keps, int nx, int ny,
                       double k0sq) {
   dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
-  hipLaunchKernelGGL(k_node_keps, grd, blk, 0, st, cells, keps, nx, ny, k0sq);
+  STF_LAUNCH(k_node_keps, grd, blk, 0, st, cells, keps, nx, ny, k0sq);
 }
 
 int stencil_partial_blocks(int nx, int ny) {
@@ -293,7 +293,7 @@ void launch_stencil_set(hipStream_t st, int nr, const StencilSet& S, const doubl
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 vectors per stencil launch");
   dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
 #define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_stencil_set<NR>), grd, blk, 0, st, S, keps, cxw, cxe, cyw, cye, nx, ny)
+  STF_LAUNCH((k_stencil_set<NR>), grd, blk, 0, st, S, keps, cxw, cxe, cyw, cye, nx, ny)
   if (nr == 1) STF_CALL(1);
   else if (nr == 2) STF_CALL(2);
   else if (nr == 3) STF_CALL(3);
@@ -307,10 +307,10 @@ void launch_stencil(hipStream_t st, int mode, const double2* x, const double2* b
                     int* nblocks_out) {
   dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
   if (mode == 0)
-    hipLaunchKernelGGL(k_stencil<0>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
+    STF_LAUNCH(k_stencil<0>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
                        partial);
   else
-    hipLaunchKernelGGL(k_stencil<1>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
+    STF_LAUNCH(k_stencil<1>, grd, blk, 0, st, x, b, y, keps, cxw, cxe, cyw, cye, nx, ny,
                        partial);
   if (nblocks_out) *nblocks_out = grd.x * grd.y;
 }
@@ -320,13 +320,13 @@ void launch_line_flux(hipStream_t st, const double2* e, int nx, int axis, int in
   const long long base = axis == 1 ? (long long)index * nx + lo : (long long)lo * nx + index;
   const long long st_t = axis == 1 ? 1 : nx, st_n = axis == 1 ? nx : 1;
   const double d = axis == 1 ? dy : dx, dl = axis == 1 ? dx : dy;
-  hipLaunchKernelGGL(k_line_flux, dim3(1), dim3(256), 0, st, e, base, st_t, st_n, hi - lo,
+  STF_LAUNCH(k_line_flux, dim3(1), dim3(256), 0, st, e, base, st_t, st_n, hi - lo,
                      1.0 / (k0 * d), 0.5 * dl, out);
 }
 
 void launch_far_field(hipStream_t st, const double2* e, int nx, int i0, int i1, int j0, int j1,
                       double dx, double dy, double k0, const double* phis, int nang, double2* F) {
-  hipLaunchKernelGGL(k_far_field, dim3(nang), dim3(256), 0, st, e, nx, i0, i1, j0, j1, dx, dy, k0,
+  STF_LAUNCH(k_far_field, dim3(nang), dim3(256), 0, st, e, nx, i0, i1, j0, j1, dx, dy, k0,
                      phis, F);
 }
 
@@ -336,24 +336,24 @@ void launch_residual_set(hipStream_t st, int nr, const ResidualSet& S, const dou
   STF_REQUIRE(nr >= 1 && nr <= MAX_RHS, "1 to 4 vectors per residual launch");
   dim3 blk(SBX, SBY), grd((nx + SBX - 1) / SBX, (ny + SBY - 1) / SBY);
 #define STF_CALL(NR) \
-  hipLaunchKernelGGL((k_residual_set<NR>), grd, blk, 0, st, S, keps, cxw, cxe, cyw, cye, nx, ny)
+  STF_LAUNCH((k_residual_set<NR>), grd, blk, 0, st, S, keps, cxw, cxe, cyw, cye, nx, ny)
   if (nr == 1) STF_CALL(1);
   else if (nr == 2) STF_CALL(2);
   else if (nr == 3) STF_CALL(3);
   else STF_CALL(4);
 #undef STF_CALL
-  hipLaunchKernelGGL(k_reduce_sum_set, dim3(nr), dim3(256), 0, st, S, (int)(grd.x * grd.y));
+  STF_LAUNCH(k_reduce_sum_set, dim3(nr), dim3(256), 0, st, S, (int)(grd.x * grd.y));
 }
 
 void launch_reduce_sum(hipStream_t st, const double* partial, int n, double* out) {
-  hipLaunchKernelGGL(k_reduce_sum, dim3(1), dim3(256), 0, st, partial, n, out);
+  STF_LAUNCH(k_reduce_sum, dim3(1), dim3(256), 0, st, partial, n, out);
 }
 
 void launch_check_finite(hipStream_t st, const double* a, long long n, int* flag) {
   long long g = (n + 255) / 256;
   if (g > 2048) g = 2048;
   if (g < 1) g = 1;
-  hipLaunchKernelGGL(k_check_finite, dim3((unsigned)g), dim3(256), 0, st, a, n, flag);
+  STF_LAUNCH(k_check_finite, dim3((unsigned)g), dim3(256), 0, st, a, n, flag);
 }
 
 }  // namespace stf

@@ -1,6 +1,7 @@
 // Internal declarations of the stfdfd library (host plans, device layouts, launchers).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <complex>
@@ -34,6 +35,29 @@ struct Error : std::runtime_error {
     if (e_ != hipSuccess)                                                                  \
       throw ::stf::Error(e_ == hipErrorOutOfMemory ? STF_ENOMEM : STF_EDEVICE,             \
                          std::string(#expr) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+// Per-kernel timing.  While a timer is installed on the calling thread, every
+// launch through STF_LAUNCH asks it for a start and a stop event, which the
+// runtime records as part of that kernel's own dispatch (hipExtLaunchKernelGGL),
+// so that their interval is the kernel's execution alone, as in a kernel trace;
+// without a timer (or when the timer declines, e.g. during graph capture) the
+// launch is a plain one.
+struct KernelTimer {
+  virtual bool events(hipStream_t st, hipEvent_t* start, hipEvent_t* stop) = 0;
+
+ protected:
+  ~KernelTimer() = default;
+};
+extern thread_local KernelTimer* t_kernel_timer;
+
+#define STF_LAUNCH(K, GRID, BLOCK, SHMEM, STREAM, ...)                                       \
+  do {                                                                                     \
+    hipEvent_t stf_t0_ = nullptr, stf_t1_ = nullptr;                                       \
+    if (::stf::t_kernel_timer && ::stf::t_kernel_timer->events((STREAM), &stf_t0_, &stf_t1_)) \
+      hipExtLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, stf_t0_, stf_t1_, 0u, __VA_ARGS__); \
+    else                                                                                   \
+      hipLaunchKernelGGL(K, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);                      \
   } while (0)
 
 // ---------------------------------------------------------------------------
