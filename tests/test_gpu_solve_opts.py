@@ -1,6 +1,7 @@
 """GPU checks of the solve options through the C ABI: several source-transfer
 rounds per preconditioner application (rounds > 1), the planted tiny-pivot
-fault (debug_fault), and the phase timers of stf_solve_info.
+fault (debug_fault), the phase timers of stf_solve_info, and the per-kernel
+timing of the context (events recorded by each kernel's own dispatch).
 
 Tolerances as in test_gpu_parity.py: FGMRES solutions 1e-10 relative L2 at
 rel-res 1e-12 (complex128 fronts) and 1e-8 at rel-res 1e-10 (complex64 fronts).
@@ -116,4 +117,37 @@ def test_phase_timers(stf, ctx):
     _, info = pb.solve(w.b[0], tol=1e-10)
     assert info[0]["t_factor_ms"] > 0.0 and info[0]["t_solve_ms"] > 0.0
     assert info[0]["t_nn_ms"] == 0.0
+    pb.close()
+
+
+def test_per_kernel_timing_leaves_results_unchanged(stf, ctx):
+    """With timing on, every kernel is launched with events its dispatch records:
+    the preconditioner and a whole solve give the same results, bit for bit, as
+    with timing off; each class counts one launch per kernel (one sweep kernel
+    per tree level and direction in an additive round) with a positive time."""
+    import torch
+    w = _case()
+    pb = stf.Problem(ctx, _prm(w, front_prec=1), w.eps_cells)
+    pb.factor()
+    levels = pb.info()["max_depth"] + 1
+    v = torch.from_numpy(np.ascontiguousarray(w.b[0])).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(w.b)).cuda()
+    z0 = pb.precond(v)
+    x0, i0 = pb.solve(b, tol=1e-10)
+    before = {c: ctx.kernel_stats(c) for c in ("sweep_fwd", "sweep_bwd", "arnoldi", "stencil")}
+    ctx.set_timing(True)
+    try:
+        z1 = pb.precond(v)
+        mid = {c: ctx.kernel_stats(c) for c in before}
+        x1, i1 = pb.solve(b, tol=1e-10)
+        after = {c: ctx.kernel_stats(c) for c in before}
+    finally:
+        ctx.set_timing(False)
+    assert torch.equal(z0, z1) and torch.equal(x0, x1)
+    assert [i["iters"] for i in i0] == [i["iters"] for i in i1]
+    for c in ("sweep_fwd", "sweep_bwd"):
+        assert mid[c][1] - before[c][1] == levels
+        assert mid[c][0] > before[c][0]
+    for c in before:
+        assert after[c][1] > mid[c][1] and after[c][0] > mid[c][0]
     pb.close()
