@@ -157,7 +157,9 @@ typedef struct {
   int32_t max_front;        /* largest front order m = p + q */
   int32_t max_depth;        /* deepest tree level (root = 0) */
   int64_t factor_entries;   /* sum over fronts of p*p + 2*p*q (entries the sweeps read) */
-  int64_t front_entries;    /* sum over fronts of m*m (stored) */
+  int64_t front_entries;    /* sum over fronts of m*m (the working blocks; the library keeps
+                               only two tree levels' worth, the even depths in one arena and
+                               the odd in another, each sized for its largest level) */
   double  lu_flops;         /* real flops of the partial LUs: 8 * sum_k (m-k)^2, k = 1..p */
   int64_t device_bytes;     /* device memory held by the problem (0 from stf_plan_query) */
 } stf_plan_info;

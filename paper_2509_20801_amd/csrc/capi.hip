@@ -459,10 +459,19 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
   for (size_t t = 0; t < order.size(); ++t) inst[order[t]] = (int)t;
   std::vector<FrontDev> fr(recs.size());
   std::vector<int> kids;
+  // Working blocks: a front's block is read after its own level only by its
+  // parent's assembly, one level up, so the levels share two arenas, the even
+  // depths one and the odd depths the other, each sized for its largest level
+  // (offsets within a level here, the odd arena's base added below).
   long long fac_off = 0, lpk_off = 0, upk_off = 0;
   long long vec_off = 0, piv_off = 0;
+  std::vector<long long> lvl_fac;          // working-block entries per depth
   for (size_t t = 0; t < order.size(); ++t) {
     const Rec& rc = recs[order[t]];
+    if ((int)lvl_fac.size() <= rc.depth) {
+      lvl_fac.resize(rc.depth + 1, 0);
+      fac_off = 0;
+    }
     const SubDev& s = sd[rc.sub];
     const SymShape& sh = *rc.sh;
     const int sid = shape_id[rc.sh];
@@ -498,6 +507,7 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
     for (int c = 0; c < f.nchild; ++c)
       kids.push_back(inst[sub_base[rc.sub] + sh.children[f.child_off + c]]);
     fac_off += (long long)m * m;
+    lvl_fac[rc.depth] = fac_off;
     // Packed sweep operators: the strictly lower trapezoid of the first p
     // columns (forward) and the upper trapezoid of the first p rows (backward).
     lpk_off += (long long)f.p * f.q + (long long)f.p * (f.p - 1) / 2;
@@ -531,7 +541,11 @@ void build_mf(Mf& mf, const std::vector<const Plan*>& plans, const std::vector<l
     mf.front_sub[t] = recs[order[t]].sub;
     mf.front_depth[t] = recs[order[t]].depth;
   }
-  mf.fac_elems = fac_off;
+  long long arena[2] = {0, 0};
+  for (size_t dd = 0; dd < lvl_fac.size(); ++dd) arena[dd & 1] = std::max(arena[dd & 1], lvl_fac[dd]);
+  for (size_t t = 0; t < order.size(); ++t)
+    if (recs[order[t]].depth & 1) fr[t].fac_off += arena[0];
+  mf.fac_elems = arena[0] + arena[1];
   mf.vec_elems = vec_off;
   mf.piv_elems = piv_off;
   mf.levels.clear();
