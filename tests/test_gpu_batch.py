@@ -98,6 +98,35 @@ def test_batch_graph_replays_equal_eager_launches(stf, ctx, batch, monkeypatch):
         pb.close()
 
 
+def test_batch_with_kernel_timing_on(stf, ctx, batch, monkeypatch):
+    """Per-kernel timing on during a batched solve: the kernels the cycle's
+    graph captures are launched plainly (a timer declines during capture), the
+    eager launches carry their dispatch events, and both runs equal the untimed
+    ones bit for bit; the factorisation's kernels are timed."""
+    import torch
+    ws, refs = batch
+    pbs = [stf.Problem(ctx, dict(w.params(), front_prec=1), w.eps_cells) for w in ws]
+    bs = [torch.from_numpy(w.b).cuda() for w in ws]
+    monkeypatch.delenv("STF_BATCH_EAGER", raising=False)
+    x0, i0 = stf.batch_solve(ctx, pbs, bs, tol=1e-10, restart=4, max_iter=400)
+    lu0 = ctx.kernel_stats("front_lu")
+    ctx.set_timing(True)
+    try:
+        xg, ig = stf.batch_solve(ctx, pbs, bs, tol=1e-10, restart=4, max_iter=400)
+        lu1 = ctx.kernel_stats("front_lu")
+        monkeypatch.setenv("STF_BATCH_EAGER", "1")
+        xe, ie = stf.batch_solve(ctx, pbs, bs, tol=1e-10, restart=4, max_iter=400)
+    finally:
+        ctx.set_timing(False)
+        monkeypatch.delenv("STF_BATCH_EAGER", raising=False)
+    assert lu1[1] > lu0[1] and lu1[0] > lu0[0]
+    for p in range(len(ws)):
+        assert torch.equal(xg[p], x0[p]) and torch.equal(xe[p], x0[p]), p
+        assert [i["iters"] for i in ig[p]] == [i["iters"] for i in i0[p]]
+    for pb in pbs:
+        pb.close()
+
+
 def test_batch_host_buffers_and_user_guess(stf, ctx, batch):
     ws, refs = batch
     ws, refs = ws[:3], refs[:3]
