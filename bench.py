@@ -558,7 +558,7 @@ def subdomain_study(stf, torch, ctx, tol=1e-3, fgmres_tol=1e-8):
 
 
 def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order="diagonal",
-                     tune=True):
+                     tune=True, orders=None):
     """The large single problem: the 4128 x 4128 waveguide layout (17.0M DoF,
     16 x 16 subdomains, complex64 fronts, fundamental-mode source) to FP64 true
     rel-res 1e-10; one warm-up and one timed step (assembly, factorisation,
@@ -582,7 +582,7 @@ def large_waveguides(stf, torch, ctx, tol=1e-10, restart=20, max_iter=600, order
         rep["staged"] = [(e[1][1], e[1][2], round(e[2][0], 3), round(e[2][1], 3))
                          for e in ctx.tune_entries() if e[0][0] >= 4 and e[0][3] == nf]
         out["autotune"] = rep
-    for od in (order, "checker", "additive"):
+    for od in orders or (order, "checker", "additive"):
         def step():
             pb.assemble(eps)
             pb.factor()
@@ -677,6 +677,9 @@ def main():
                     help="skip the side forms (mixed without the network, stationary)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 48-problem batch and the 17M-DoF waveguide problem")
+    ap.add_argument("--waveguides-only", action="store_true",
+                    help="run only the 17M-DoF waveguide problem in the four-diagonal order "
+                         "(a warm-up and a timed step; for kernel traces) and print its record")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run only the PMC calibration copy (512 MiB)")
     ap.add_argument("--trace-summary", metavar="TRACE_DIR",
@@ -705,7 +708,7 @@ def main():
     w4 = workloads_batched()
     w = workload()
     sample = None
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.waveguides_only:
         # Before anything touches the GPU: the pool forks from this process.
         sample = cpu_baseline_sample(w, min(16, os.cpu_count() or 1), args.restart, args.order)
     import torch
@@ -717,6 +720,13 @@ def main():
     if args.tune_file and os.path.exists(args.tune_file) and not args.no_tune:
         ctx.tune_load(args.tune_file)
         ctx._tune_loaded = True
+    if args.waveguides_only:
+        rec = large_waveguides(stf, torch, ctx, tune=not args.no_tune, orders=("diagonal",))
+        if args.tune_file and not args.no_tune and not ctx._tune_loaded:
+            ctx.tune_save(args.tune_file)
+        print(json.dumps(rec), flush=True)
+        ctx.close()
+        return
     net = learned.load_network(stf, ctx, max_batch=64)   # the 49 tiles of a 1024^2 grid in one call
     if net is None:
         raise RuntimeError("the trained network (paper_2509_20801_amd/data) is missing")
